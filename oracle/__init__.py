@@ -1,0 +1,168 @@
+"""pcol oracle -- TEST INFRASTRUCTURE ONLY.
+
+A plain FP64 CPU statement of the deterministic hard-sphere collision step
+(``pcol_oracle.c``; every function there cites the paper passage it follows).
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU library neither calls nor links
+it, and the two share no code.
+
+Pins of this oracle against the paper and the mathematics are in
+``tests/test_oracle_pins.py``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRCS = [os.path.join(_HERE, "pcol_oracle.c")]
+_LIB = os.path.join(_HERE, "libpcol_oracle.so")
+_lib = None
+
+OK, E_INVALID, E_BOX, E_NOMEM, E_SWEEPS = 0, 1, 2, 3, 5
+
+_FLAGS = ["-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-shared", "-fPIC"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (FMA contraction off, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", *_FLAGS, *_SRCS, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("n_pairs", ctypes.c_int64), ("n_sweeps", ctypes.c_int64),
+                ("pair_tests", ctypes.c_int64), ("reach", ctypes.c_double)]
+
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I64 = ctypes.POINTER(ctypes.c_int64)
+_I32 = ctypes.POINTER(ctypes.c_int32)
+_U8 = ctypes.POINTER(ctypes.c_uint8)
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        lib.orc_pair_time.argtypes = [_D, _D, ctypes.c_double, _D, _D, ctypes.c_double, _D,
+                                      ctypes.c_double, _D]
+        lib.orc_pair_time.restype = ctypes.c_int
+        lib.orc_earliest.argtypes = [ctypes.c_int64] + [_D] * 7 + [_D, ctypes.c_double, _U8,
+                                                                  ctypes.c_int, ctypes.c_double,
+                                                                  _I64, _D, _I64]
+        lib.orc_earliest.restype = ctypes.c_int
+        lib.orc_resolve_pair.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_double] + [_D] * 8 + \
+            [_D, ctypes.c_double, ctypes.c_double] + [_D] * 6
+        lib.orc_resolve_pair.restype = None
+        lib.orc_step.argtypes = [ctypes.c_int64] + [_D] * 8 + [_D, ctypes.c_double, ctypes.c_double,
+                                                              ctypes.c_int, ctypes.c_double,
+                                                              ctypes.c_int] + [_D] * 6 + \
+            [_I64, _D, _I32, ctypes.POINTER(_Stats)]
+        lib.orc_step.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(_D)
+
+
+def _c64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int):
+        super().__init__(f"oracle status {code}")
+        self.code = code
+
+
+def pair_time(xi, vi, ri, xj, vj, rj, L, dt):
+    """Contact time of one pair within [0, dt] or None (eq. detect1/detect2)."""
+    a = [_c64(v) for v in (xi, vi, xj, vj, L)]
+    t = ctypes.c_double(0.0)
+    hit = _load().orc_pair_time(_d(a[0]), _d(a[1]), float(ri), _d(a[2]), _d(a[3]), float(rj),
+                                _d(a[4]), float(dt), ctypes.byref(t))
+    return t.value if hit else None
+
+
+def earliest(box, active=None, *, grid: bool = True, cell_mult: float = 1.0):
+    """Earliest partner (index or -1) and its contact time for every active sphere."""
+    n = box.n
+    partner = np.empty(n, dtype=np.int64)
+    tmin = np.empty(n, dtype=np.float64)
+    tests = ctypes.c_int64(0)
+    arrs = [_c64(a) for a in (box.x, box.y, box.z, box.vx, box.vy, box.vz, box.r)]
+    act = None
+    if active is not None:
+        act = np.ascontiguousarray(active, dtype=np.uint8)
+    L = _c64(box.L)
+    rc = _load().orc_earliest(n, *[_d(a) for a in arrs], _d(L), float(box.dt),
+                              act.ctypes.data_as(_U8) if act is not None else None, int(grid),
+                              float(cell_mult), partner.ctypes.data_as(_I64), _d(tmin),
+                              ctypes.byref(tests))
+    if rc:
+        raise OracleError(rc)
+    return partner, tmin, tests.value
+
+
+@dataclass
+class StepResult:
+    x: np.ndarray
+    y: np.ndarray
+    z: np.ndarray
+    vx: np.ndarray
+    vy: np.ndarray
+    vz: np.ndarray
+    partner: np.ndarray   # int64, -1 = no collision
+    tcoll: np.ndarray     # contact time within the step, NaN = none
+    sweep: np.ndarray     # int32 sweep index of the collision, -1 = none
+    n_pairs: int
+    n_sweeps: int
+    pair_tests: int
+    reach: float
+
+
+def step(box, *, e: float | None = None, grid: bool = True, cell_mult: float = 1.0,
+         max_sweeps: int = 0) -> StepResult:
+    """One collision step of ``box`` (a workloads.Box); inputs are not modified."""
+    n = box.n
+    arrs = [_c64(a) for a in (box.x, box.y, box.z, box.vx, box.vy, box.vz, box.r, box.m)]
+    outs = [np.empty(n) for _ in range(6)]
+    partner = np.empty(n, dtype=np.int64)
+    tcoll = np.empty(n)
+    sweep = np.empty(n, dtype=np.int32)
+    st = _Stats()
+    L = _c64(box.L)
+    rc = _load().orc_step(n, *[_d(a) for a in arrs], _d(L), float(box.dt),
+                          float(box.e if e is None else e), int(grid), float(cell_mult),
+                          int(max_sweeps), *[_d(o) for o in outs], partner.ctypes.data_as(_I64),
+                          _d(tcoll), sweep.ctypes.data_as(_I32), ctypes.byref(st))
+    if rc:
+        raise OracleError(rc)
+    return StepResult(*outs, partner, tcoll, sweep, st.n_pairs, st.n_sweeps, st.pair_tests,
+                      st.reach)
+
+
+def resolve_pair(box, i: int, j: int, t: float, *, e: float | None = None):
+    """New (x, v) of spheres i and j after their collision at time t (arrays of shape (2, 3))."""
+    n = box.n
+    arrs = [_c64(a) for a in (box.x, box.y, box.z, box.vx, box.vy, box.vz, box.r, box.m)]
+    outs = [np.zeros(n) for _ in range(6)]
+    L = _c64(box.L)
+    _load().orc_resolve_pair(int(i), int(j), float(t), *[_d(a) for a in arrs], _d(L),
+                             float(box.dt), float(box.e if e is None else e),
+                             *[_d(o) for o in outs])
+    xs = np.array([[outs[k][i] for k in range(3)], [outs[k][j] for k in range(3)]])
+    vs = np.array([[outs[k][i] for k in range(3, 6)], [outs[k][j] for k in range(3, 6)]])
+    return xs, vs

@@ -1,0 +1,459 @@
+/*
+ * pcol oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, FP64 CPU statement of one deterministic hard-sphere
+ * collision step, written from the paper (Schwarz, Kopper, de Staercke, Beck,
+ * "Efficient computation of particle-fluid and particle-particle interactions
+ * in compressible flow", arXiv 2501.05340).  Only the tests, the smoke check
+ * and the benchmark's CPU-baseline leg may call it; the GPU library never does,
+ * and the two share no code.
+ *
+ * Build: gcc -O2 -std=c11 -fopenmp -ffp-contract=off (no fast-math: every
+ * floating-point operation below is one IEEE-754 binary64 operation, rounded
+ * to nearest, in the order written).
+ *
+ * What is computed (one step of length dt, periodic box [0,L0)x[0,L1)x[0,L2)):
+ *
+ *  pair time   Sec. "Particle Collisions", eq. (detect1/detect2): two spheres
+ *              moving on straight lines touch when |dx + t dv|^2 = (r_i+r_j)^2.
+ *              A collision exists when the quadratic has two positive roots,
+ *              the lower one is <= dt, and the spheres approach each other.
+ *              orc_pair_time() spells out the operation order used.
+ *  earliest    each active sphere's partner is the active sphere with the
+ *              smallest contact time, exact ties going to the smaller index
+ *              (the paper only asks for a deterministic order; this is the
+ *              order-free rule that a parallel sweep can reproduce).
+ *  sweeps      Sec. "Collision Operator": one collision per sphere per step;
+ *              spheres that collided leave the eligible set.  Every sweep
+ *              resolves all mutual earliest pairs at once, removes them, and
+ *              recomputes partners over the rest from start-of-step data,
+ *              until a sweep finds no mutual pair.
+ *  resolve     Sec. "Inter-Particle Collisions", momentum jump relations with
+ *              the normal impulse J_n = -m_r (1+e) (v_r . n_p), friction
+ *              coefficient 0 (no tangential impulse, no spin), followed by
+ *              eq. (update_vel1/update_vel2) and eq. (update_rho): move to the
+ *              contact point, then fly the rest of the step with the new
+ *              velocity.
+ *  free flight spheres without a collision move x + dt v; every position is
+ *              wrapped back into [0, L).
+ *
+ * Every function below cites the passage it follows.  Pins: tests/test_oracle_*.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#pragma STDC FP_CONTRACT OFF
+
+enum {
+  ORC_OK = 0,
+  ORC_E_INVALID = 1, /* bad argument or non-finite / non-positive data */
+  ORC_E_BOX = 2,     /* box side <= 2 * reach on some axis */
+  ORC_E_NOMEM = 3,
+  ORC_E_SWEEPS = 5   /* sweep cap reached with mutual pairs still found */
+};
+
+/* minimum-image component: the separation along one periodic axis is mapped
+ * into [-L/2, L/2] by one subtraction or addition of L */
+static double orc_wrap_sep(double d, double len) {
+  if (d > 0.5 * len) {
+    d = d - len;
+  } else if (d < -0.5 * len) {
+    d = d + len;
+  }
+  return d;
+}
+
+/*
+ * Contact time of spheres i and j within [0, dt], Sec. "Particle Collisions",
+ * eq. (detect1/detect2).  With d = x_j - x_i (minimum image) and u = v_j - v_i
+ * the contact condition |d + t u|^2 = s^2, s = r_i + r_j, is the quadratic
+ *     a t^2 + 2 b t + c = 0,  a = u.u,  b = d.u,  c = d.d - s^2.
+ * Two positive roots exist iff a > 0, b < 0 (the spheres approach), c > 0
+ * (they are apart now) and D = b^2 - a c >= 0 (a tangent contact counts: "at
+ * least one solution").  The lower root is evaluated in the cancellation-free
+ * form t = c / (-b + sqrt(D)); the collision is kept iff t <= dt.
+ * Sums are accumulated left to right: ((p0 + p1) + p2).
+ * Returns 1 and stores t on a collision, else 0.
+ */
+int orc_pair_time(const double xi[3], const double vi[3], double ri, const double xj[3],
+                  const double vj[3], double rj, const double L[3], double dt, double *t_out) {
+  double d[3], u[3];
+  for (int k = 0; k < 3; ++k) {
+    d[k] = orc_wrap_sep(xj[k] - xi[k], L[k]);
+    u[k] = vj[k] - vi[k];
+  }
+  const double s = ri + rj;
+  const double a = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
+  const double b = (d[0] * u[0] + d[1] * u[1]) + d[2] * u[2];
+  const double c = ((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]) - s * s;
+  if (!(a > 0.0) || !(b < 0.0) || !(c > 0.0)) return 0;
+  const double D = b * b - a * c;
+  if (!(D >= 0.0)) return 0;
+  const double t = c / (-b + sqrt(D));
+  if (!(t <= dt)) return 0;
+  *t_out = t;
+  return 1;
+}
+
+/* the lexicographic order on (t, index) used to pick the earliest partner */
+static int orc_before(double t1, int64_t j1, double t2, int64_t j2) {
+  return t1 < t2 || (t1 == t2 && j1 < j2);
+}
+
+/* reach = 2 r_max + 2 |v|_max dt: the largest centre distance at step start of
+ * any pair that can touch within dt (Sec. "Collision Operator": the halo grows
+ * with the distance the fastest particle travels; both spheres move) */
+static double orc_reach(int64_t n, const double *vx, const double *vy, const double *vz,
+                        const double *r, double dt) {
+  double v2 = 0.0, rm = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    const double w = (vx[i] * vx[i] + vy[i] * vy[i]) + vz[i] * vz[i];
+    if (w > v2) v2 = w;
+    if (r[i] > rm) rm = r[i];
+  }
+  return 2.0 * rm + 2.0 * sqrt(v2) * dt;
+}
+
+/* a plain uniform cell grid with cell side >= reach * cell_mult (Sec. "Collision
+ * Operator": particles are bucketed by host element, and only elements within the
+ * halo distance hold candidates) */
+typedef struct {
+  int nc[3];
+  double h[3];
+  int64_t *start; /* ncell + 1 */
+  int64_t *item;  /* particle indices bucketed by cell */
+  int nb[3];      /* number of distinct neighbour offsets per axis */
+  int off[3][3];  /* the distinct offsets */
+} orc_grid;
+
+static int orc_cell_of(double x, double h, int nc) {
+  int c = (int)floor(x / h);
+  if (c < 0) c = 0;
+  if (c > nc - 1) c = nc - 1;
+  return c;
+}
+
+static int orc_grid_build(orc_grid *G, int64_t n, const double *x, const double *y,
+                          const double *z, const double L[3], double cell) {
+  const double *p[3] = {x, y, z};
+  for (int a = 0; a < 3; ++a) {
+    int nc = (int)floor(L[a] / (cell * (1.0 + 1e-9)));
+    if (nc < 1) nc = 1;
+    if (nc > 2048) nc = 2048;
+    G->nc[a] = nc;
+    G->h[a] = L[a] / nc;
+    /* distinct cells among c-1, c, c+1 (periodic); fewer than three cells
+     * per axis would otherwise visit a cell twice */
+    if (nc >= 3) {
+      G->nb[a] = 3;
+      G->off[a][0] = -1;
+      G->off[a][1] = 0;
+      G->off[a][2] = 1;
+    } else if (nc == 2) {
+      G->nb[a] = 2;
+      G->off[a][0] = 0;
+      G->off[a][1] = 1;
+    } else {
+      G->nb[a] = 1;
+      G->off[a][0] = 0;
+    }
+  }
+  const int64_t ncell = (int64_t)G->nc[0] * G->nc[1] * G->nc[2];
+  G->start = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
+  G->item = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+  int64_t *cid = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+  if (!G->start || !G->item || !cid) {
+    free(G->start);
+    free(G->item);
+    free(cid);
+    return ORC_E_NOMEM;
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    int c[3];
+    for (int a = 0; a < 3; ++a) c[a] = orc_cell_of(p[a][i], G->h[a], G->nc[a]);
+    cid[i] = ((int64_t)c[2] * G->nc[1] + c[1]) * G->nc[0] + c[0];
+    G->start[cid[i] + 1] += 1;
+  }
+  for (int64_t k = 0; k < ncell; ++k) G->start[k + 1] += G->start[k];
+  int64_t *fill = (int64_t *)malloc((size_t)(ncell > 0 ? ncell : 1) * sizeof(int64_t));
+  if (!fill) {
+    free(G->start);
+    free(G->item);
+    free(cid);
+    return ORC_E_NOMEM;
+  }
+  memcpy(fill, G->start, (size_t)ncell * sizeof(int64_t));
+  for (int64_t i = 0; i < n; ++i) G->item[fill[cid[i]]++] = i;
+  free(fill);
+  free(cid);
+  return ORC_OK;
+}
+
+static void orc_grid_free(orc_grid *G) {
+  free(G->start);
+  free(G->item);
+}
+
+static int orc_check_inputs(int64_t n, const double *x, const double *y, const double *z,
+                            const double *vx, const double *vy, const double *vz,
+                            const double *r, const double *m, const double L[3], double dt) {
+  if (n < 0 || !(dt > 0.0) || !isfinite(dt)) return ORC_E_INVALID;
+  for (int a = 0; a < 3; ++a)
+    if (!(L[a] > 0.0) || !isfinite(L[a])) return ORC_E_INVALID;
+  const double *p[3] = {x, y, z};
+  for (int64_t i = 0; i < n; ++i) {
+    for (int a = 0; a < 3; ++a)
+      if (!(p[a][i] >= 0.0 && p[a][i] < L[a])) return ORC_E_INVALID;
+    if (!isfinite(vx[i]) || !isfinite(vy[i]) || !isfinite(vz[i])) return ORC_E_INVALID;
+    if (!(r[i] > 0.0) || !isfinite(r[i])) return ORC_E_INVALID;
+    if (m && (!(m[i] > 0.0) || !isfinite(m[i]))) return ORC_E_INVALID;
+  }
+  return ORC_OK;
+}
+
+/*
+ * Earliest partner of every active sphere over the active set (the rule stated
+ * in the file header).  partner[i] = index or -1, tmin[i] = its contact time
+ * (or +inf).  Inactive spheres get partner -1.
+ *   use_grid = 0: all pairs, O(N^2) (the brute-force definition).
+ *   use_grid = 1: candidates from the 27 surrounding cells of a grid with cell
+ *                 side >= reach * cell_mult (cell_mult >= 1).
+ * pair_tests (nullable) receives the number of unordered active candidate pairs.
+ */
+int orc_earliest(int64_t n, const double *x, const double *y, const double *z, const double *vx,
+                 const double *vy, const double *vz, const double *r, const double L[3], double dt,
+                 const uint8_t *active, int use_grid, double cell_mult, int64_t *partner,
+                 double *tmin, int64_t *pair_tests) {
+  int rc = orc_check_inputs(n, x, y, z, vx, vy, vz, r, NULL, L, dt);
+  if (rc) return rc;
+  const double reach = orc_reach(n, vx, vy, vz, r, dt);
+  for (int a = 0; a < 3; ++a)
+    if (!(L[a] > 2.0 * reach)) return ORC_E_BOX;
+  if (cell_mult < 1.0) cell_mult = 1.0;
+  int64_t tests2 = 0; /* ordered candidate count */
+  if (!use_grid) {
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : tests2)
+    for (int64_t i = 0; i < n; ++i) {
+      partner[i] = -1;
+      tmin[i] = INFINITY;
+      if (active && !active[i]) continue;
+      const double xi[3] = {x[i], y[i], z[i]}, vi[3] = {vx[i], vy[i], vz[i]};
+      for (int64_t j = 0; j < n; ++j) {
+        if (j == i || (active && !active[j])) continue;
+        ++tests2;
+        const double xj[3] = {x[j], y[j], z[j]}, vj[3] = {vx[j], vy[j], vz[j]};
+        double t;
+        if (orc_pair_time(xi, vi, r[i], xj, vj, r[j], L, dt, &t) &&
+            orc_before(t, j, tmin[i], partner[i] < 0 ? INT64_MAX : partner[i])) {
+          tmin[i] = t;
+          partner[i] = j;
+        }
+      }
+    }
+  } else {
+    orc_grid G;
+    rc = orc_grid_build(&G, n, x, y, z, L, reach * cell_mult);
+    if (rc) return rc;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : tests2)
+    for (int64_t i = 0; i < n; ++i) {
+      partner[i] = -1;
+      tmin[i] = INFINITY;
+      if (active && !active[i]) continue;
+      const double xi[3] = {x[i], y[i], z[i]}, vi[3] = {vx[i], vy[i], vz[i]};
+      const int c0 = orc_cell_of(x[i], G.h[0], G.nc[0]);
+      const int c1 = orc_cell_of(y[i], G.h[1], G.nc[1]);
+      const int c2 = orc_cell_of(z[i], G.h[2], G.nc[2]);
+      for (int a2 = 0; a2 < G.nb[2]; ++a2)
+        for (int a1 = 0; a1 < G.nb[1]; ++a1)
+          for (int a0 = 0; a0 < G.nb[0]; ++a0) {
+            const int q0 = (c0 + G.off[0][a0] + G.nc[0]) % G.nc[0];
+            const int q1 = (c1 + G.off[1][a1] + G.nc[1]) % G.nc[1];
+            const int q2 = (c2 + G.off[2][a2] + G.nc[2]) % G.nc[2];
+            const int64_t q = ((int64_t)q2 * G.nc[1] + q1) * G.nc[0] + q0;
+            for (int64_t k = G.start[q]; k < G.start[q + 1]; ++k) {
+              const int64_t j = G.item[k];
+              if (j == i || (active && !active[j])) continue;
+              ++tests2;
+              const double xj[3] = {x[j], y[j], z[j]}, vj[3] = {vx[j], vy[j], vz[j]};
+              double t;
+              if (orc_pair_time(xi, vi, r[i], xj, vj, r[j], L, dt, &t) &&
+                  orc_before(t, j, tmin[i], partner[i] < 0 ? INT64_MAX : partner[i])) {
+                tmin[i] = t;
+                partner[i] = j;
+              }
+            }
+          }
+    }
+    orc_grid_free(&G);
+  }
+  if (pair_tests) *pair_tests = tests2 / 2;
+  return ORC_OK;
+}
+
+/* wrap one coordinate of a final position back into [0, L) (C5: one shift by L
+ * suffices because no sphere moves more than L/2 in a step; a result that
+ * rounds to L itself is mapped to 0) */
+static double orc_wrap_pos(double p, double len) {
+  if (p >= len) {
+    p = p - len;
+  } else if (p < 0.0) {
+    p = p + len;
+  }
+  if (p >= len) p = 0.0;
+  return p;
+}
+
+/*
+ * Resolve the binary collision of spheres i and j at time t of the step,
+ * Sec. "Inter-Particle Collisions" with friction 0 and eq. (update_vel1),
+ * (update_vel2), (update_rho):
+ *   contact separation  w = d + t u         (d, u as in orc_pair_time)
+ *   unit normal i->j    n = w / s           (|w| = s at contact)
+ *   normal closing rate g = u . n  (< 0)
+ *   reduced mass        m_r = m_i m_j / (m_i + m_j)
+ *   impulse on i        J n with J = m_r (1 + e) g, which is the paper's
+ *                       J_n = -m_r (1+e) (v_r . n_p), v_r = v_i - v_j = -u
+ *   velocities          v_i' = v_i + (J/m_i) n,  v_j' = v_j - (J/m_j) n
+ *   positions           x' = (x + t v) + (dt - t) v'   (moved to the contact
+ *                       point, then the rest of the step with v'), wrapped.
+ * Reads the start-of-step state (x*, v*), writes the new state to (xo*, vo*).
+ */
+void orc_resolve_pair(int64_t i, int64_t j, double t, const double *x, const double *y,
+                      const double *z, const double *vx, const double *vy, const double *vz,
+                      const double *r, const double *m, const double L[3], double dt, double e,
+                      double *xo, double *yo, double *zo, double *vxo, double *vyo, double *vzo) {
+  const double xi[3] = {x[i], y[i], z[i]}, xj[3] = {x[j], y[j], z[j]};
+  const double vi[3] = {vx[i], vy[i], vz[i]}, vj[3] = {vx[j], vy[j], vz[j]};
+  double d[3], u[3], n[3];
+  for (int k = 0; k < 3; ++k) {
+    d[k] = orc_wrap_sep(xj[k] - xi[k], L[k]);
+    u[k] = vj[k] - vi[k];
+  }
+  const double s = r[i] + r[j];
+  for (int k = 0; k < 3; ++k) {
+    const double w = d[k] + t * u[k];
+    n[k] = w / s;
+  }
+  const double g = (u[0] * n[0] + u[1] * n[1]) + u[2] * n[2];
+  const double mr = (m[i] * m[j]) / (m[i] + m[j]);
+  const double J = (mr * (1.0 + e)) * g;
+  const double ai = J / m[i], aj = J / m[j];
+  double vin[3], vjn[3];
+  for (int k = 0; k < 3; ++k) {
+    vin[k] = vi[k] + ai * n[k];
+    vjn[k] = vj[k] - aj * n[k];
+  }
+  const double rest = dt - t;
+  double *xout[3] = {xo, yo, zo}, *vout[3] = {vxo, vyo, vzo};
+  for (int k = 0; k < 3; ++k) {
+    xout[k][i] = orc_wrap_pos((xi[k] + t * vi[k]) + rest * vin[k], L[k]);
+    xout[k][j] = orc_wrap_pos((xj[k] + t * vj[k]) + rest * vjn[k], L[k]);
+    vout[k][i] = vin[k];
+    vout[k][j] = vjn[k];
+  }
+}
+
+typedef struct {
+  int64_t n_pairs;    /* collisions resolved in the step */
+  int64_t n_sweeps;   /* sweeps run, including the final one that found none */
+  int64_t pair_tests; /* unordered active candidate pairs, summed over sweeps */
+  double reach;
+} orc_stats;
+
+/*
+ * One full collision step (the sweeps described in the file header), Sec.
+ * "Collision Operator": detect over the eligible set, resolve mutual earliest
+ * pairs, remove them from the eligible set, repeat; then free flight and wrap.
+ * Inputs (x*, v*, r, m) are the start-of-step state and are not modified; the
+ * new state goes to (xo*, vo*).  partner[i] = the sphere i collided with or -1;
+ * tcoll[i] = contact time within the step (NaN if none); sweep_of[i] = sweep
+ * (0-based) in which i collided, or -1.  Any of the three may be NULL.
+ */
+int orc_step(int64_t n, const double *x, const double *y, const double *z, const double *vx,
+             const double *vy, const double *vz, const double *r, const double *m,
+             const double L[3], double dt, double e, int use_grid, double cell_mult, int max_sweeps,
+             double *xo, double *yo, double *zo, double *vxo, double *vyo, double *vzo,
+             int64_t *partner, double *tcoll, int32_t *sweep_of, orc_stats *st) {
+  int rc = orc_check_inputs(n, x, y, z, vx, vy, vz, r, m, L, dt);
+  if (rc) return rc;
+  if (!(e >= 0.0 && e <= 1.0)) return ORC_E_INVALID;
+  const double reach = orc_reach(n, vx, vy, vz, r, dt);
+  for (int a = 0; a < 3; ++a)
+    if (!(L[a] > 2.0 * reach)) return ORC_E_BOX;
+  const size_t nn = (size_t)(n > 0 ? n : 1);
+  uint8_t *active = (uint8_t *)malloc(nn);
+  uint8_t *hit = (uint8_t *)malloc(nn);
+  int64_t *pj = (int64_t *)malloc(nn * sizeof(int64_t));
+  double *pt = (double *)malloc(nn * sizeof(double));
+  if (!active || !hit || !pj || !pt) {
+    free(active);
+    free(hit);
+    free(pj);
+    free(pt);
+    return ORC_E_NOMEM;
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    active[i] = 1;
+    hit[i] = 0;
+    if (partner) partner[i] = -1;
+    if (tcoll) tcoll[i] = NAN;
+    if (sweep_of) sweep_of[i] = -1;
+  }
+  int64_t pairs = 0, tests = 0, sweeps = 0;
+  for (;;) {
+    int64_t tk = 0;
+    rc = orc_earliest(n, x, y, z, vx, vy, vz, r, L, dt, active, use_grid, cell_mult, pj, pt, &tk);
+    if (rc) break;
+    tests += tk;
+    ++sweeps;
+    int64_t found = 0;
+#pragma omp parallel for schedule(static) reduction(+ : found)
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t j = pj[i];
+      if (j > i && pj[j] == i) {
+        orc_resolve_pair(i, j, pt[i], x, y, z, vx, vy, vz, r, m, L, dt, e, xo, yo, zo, vxo, vyo,
+                         vzo);
+        hit[i] = hit[j] = 1;
+        if (partner) {
+          partner[i] = j;
+          partner[j] = i;
+        }
+        if (tcoll) tcoll[i] = tcoll[j] = pt[i];
+        if (sweep_of) sweep_of[i] = sweep_of[j] = (int32_t)(sweeps - 1);
+        ++found;
+      }
+    }
+    if (found == 0) break;
+    pairs += found;
+    for (int64_t i = 0; i < n; ++i)
+      if (hit[i]) active[i] = 0;
+    if (max_sweeps > 0 && sweeps >= max_sweeps) {
+      rc = ORC_E_SWEEPS;
+      break;
+    }
+  }
+  if (rc == ORC_OK) {
+    const double *p[3] = {x, y, z}, *v[3] = {vx, vy, vz};
+    double *po[3] = {xo, yo, zo}, *vo[3] = {vxo, vyo, vzo};
+    for (int64_t i = 0; i < n; ++i) {
+      if (hit[i]) continue;
+      for (int k = 0; k < 3; ++k) {
+        po[k][i] = orc_wrap_pos(p[k][i] + dt * v[k][i], L[k]);
+        vo[k][i] = v[k][i];
+      }
+    }
+  }
+  if (st) {
+    st->n_pairs = pairs;
+    st->n_sweeps = sweeps;
+    st->pair_tests = tests;
+    st->reach = reach;
+  }
+  free(active);
+  free(hit);
+  free(pj);
+  free(pt);
+  return rc;
+}
