@@ -1,0 +1,193 @@
+/*
+ * pcol.h -- deterministic hard-sphere binary collision step on one AMD MI355X
+ * (gfx950).  C ABI over hand-written HIP kernels.
+ *
+ * The operation is the hard-sphere collision operator of Schwarz, Kopper,
+ * de Staercke and Beck, "Efficient computation of particle-fluid and
+ * particle-particle interactions in compressible flow" (arXiv 2501.05340):
+ *
+ *   - Sec. "Particle Collisions", eq. (detect1/detect2): within a step of
+ *     length dt two spheres moving on straight lines collide at the lower of
+ *     the two positive roots t of |dx + t dv|^2 = (r_i + r_j)^2 if it is <= dt
+ *     and the spheres approach each other.
+ *   - Sec. "Inter-Particle Collisions": momentum jump relations with the normal
+ *     impulse J_n = -m_r (1 + e) (v_r . n_p), v_r = v_1 - v_2, n_p the unit
+ *     vector from sphere 1 to sphere 2, m_r = m_1 m_2 / (m_1 + m_2); friction
+ *     coefficient 0, so no tangential impulse and no spin.
+ *   - eq. (update_vel1/update_vel2/update_rho): new velocities v + J/m, and the
+ *     sphere is moved to the contact point and flies the rest of the step with
+ *     its new velocity.
+ *   - Sec. "Collision Operator": one collision per sphere per step; spheres
+ *     that collided leave the set of eligible partners.
+ *
+ * THE ORDERING RULE (the paper asks only for a deterministic order; this is
+ * the order-independent rule every entry point computes):
+ *   1. The contact time of an active pair (i, j) is computed in IEEE-754
+ *      binary64, round to nearest, without FMA contraction, in exactly this
+ *      order:  d_k = x_j,k - x_i,k, then if d_k > L_k/2: d_k -= L_k, else if
+ *      d_k < -L_k/2: d_k += L_k;  u_k = v_j,k - v_i,k;  s = r_i + r_j;
+ *      a = (u0 u0 + u1 u1) + u2 u2;  b = (d0 u0 + d1 u1) + d2 u2;
+ *      c = ((d0 d0 + d1 d1) + d2 d2) - s s;  a collision exists iff
+ *      a > 0, b < 0, c > 0 and D = b b - a c >= 0; then t = c / (-b + sqrt(D))
+ *      and the collision is kept iff t <= dt.  (t_ij == t_ji bitwise.)
+ *   2. partner(i) = the active j != i minimising (t_ij, j) lexicographically:
+ *      exact binary64 comparison of t, exact ties to the smaller caller index.
+ *   3. A sweep resolves every pair with partner(i) = j and partner(j) = i, all
+ *      at once, using start-of-step positions and velocities, and removes both
+ *      spheres from the active set.  Sweeps repeat until one finds no mutual
+ *      pair (the globally earliest pair is always mutual, so each sweep with a
+ *      remaining contact resolves at least one pair).
+ *   4. Resolve of i with partner j at time t (same d, u, s as in 1):
+ *      n_k = (d_k + t u_k) / s;  g = (u0 n0 + u1 n1) + u2 n2;
+ *      m_r = (m_i m_j) / (m_i + m_j);  J = (m_r (1 + e)) g;
+ *      v_i,k' = v_i,k + (J / m_i) n_k;  x_i,k' = (x_i,k + t v_i,k) + (dt - t) v_i,k'.
+ *      (For j the same with the roles swapped; the result is bitwise
+ *      independent of which sphere is called i.)
+ *   5. Spheres without a collision: x' = x + dt v.  Every final coordinate is
+ *      wrapped: if x' >= L: x' -= L, else if x' < 0: x' += L; a result equal to
+ *      L becomes 0.
+ *
+ * Data: structure-of-arrays, binary64, N <= 2^31 - 1 spheres.  All array
+ * pointers are DEVICE pointers owned by the caller; the library owns only the
+ * scratch inside pcol_ctx.  Calls enqueue work on the context's HIP stream.
+ * Entry points that validate data on the device read back a few bytes and so
+ * synchronise with that stream; they say so below.  Errors in arguments or
+ * data are reported before any kernel writes caller memory (caller arrays are
+ * then unchanged), except PCOL_E_SWEEPS, see pcol_step.  No C++ exception
+ * crosses this interface.
+ */
+#ifndef PCOL_H
+#define PCOL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pcol_ctx pcol_ctx;
+
+typedef enum {
+  PCOL_OK = 0,
+  PCOL_E_INVALID = 1, /* bad argument, or data that is non-finite, r <= 0, m <= 0, or a
+                         position outside [0, L) */
+  PCOL_E_BOX = 2,     /* some box side L_k <= 2 * reach, reach = 2 max r + 2 max|v| dt:
+                         the minimum image would no longer be unique */
+  PCOL_E_NOMEM = 3,   /* device allocation failed */
+  PCOL_E_HIP = 4,     /* a HIP runtime call failed; see pcol_last_error */
+  PCOL_E_SWEEPS = 5,  /* opts.max_sweeps sweeps ran and the last still resolved pairs */
+  PCOL_E_STATE = 6    /* call order: pcol_detect / pcol_resolve before pcol_bin, or for a
+                         different particle count than the last pcol_bin */
+} pcol_status;
+
+/* The spheres.  x, y, z in [0, len_k); r > 0 (radius: the paper's diameter is 2r);
+ * m > 0.  Positions and velocities are updated in place by pcol_resolve,
+ * pcol_advance and pcol_step. */
+typedef struct {
+  int64_t n;
+  double *x, *y, *z;
+  double *vx, *vy, *vz;
+  const double *r;
+  const double *m;
+} pcol_particles;
+
+/* periodic box [0, len0) x [0, len1) x [0, len2) */
+typedef struct {
+  double len[3];
+} pcol_box;
+
+typedef struct {
+  double cell_mult;   /* grid cell side >= reach * cell_mult, cell_mult >= 1 (default 1) */
+  int max_sweeps;     /* 0: no cap (a step needs at most n/2 + 1 sweeps) */
+  int home_cells;     /* home cells per workgroup along x in the sweep-1 detect; 0 = auto */
+  int contact_slots;  /* contacts kept per sphere from the sweep-1 detect; spheres with more
+                         fall back to an exact neighbourhood search (default 12) */
+  int fp32_filter;    /* 1: FP32 pair filter with FP64 recheck (same results) */
+  double band_rel;    /* FP32 filter safety band, relative to r_i + r_j (default 1e-4) */
+  int timing;         /* 1: time kernels with HIP events; times land in pcol_stats */
+} pcol_opts;
+
+typedef struct {
+  int64_t n_pairs;       /* collisions resolved */
+  int64_t n_sweeps;      /* sweeps run, including the last one that resolved nothing */
+  int64_t pair_tests;    /* unordered candidate pairs tested geometrically */
+  int64_t contacts;      /* unordered pairs with a contact within dt (sweep 1) */
+  int64_t n_overflow;    /* spheres whose contacts exceeded contact_slots */
+  int64_t n_recheck;     /* FP32 filter survivors rechecked in FP64 (fp32_filter only) */
+  int32_t nc[3];         /* grid cells per axis */
+  int32_t home_cells;    /* home cells per workgroup used */
+  int32_t max_cell;      /* largest cell occupancy */
+  double h[3];           /* grid cell side per axis */
+  double reach;          /* 2 max r + 2 max|v| dt */
+  double ms_bin;         /* with opts.timing only: validation, reach, binning */
+  double ms_detect;      /*   the sweep-1 pair-test kernel alone */
+  double ms_sweeps;      /*   partner selection and all resolve sweeps */
+  double ms_advance;     /*   free flight and wrap */
+} pcol_stats;
+
+/* Fill *opts with the defaults listed above. */
+void pcol_default_opts(pcol_opts *opts);
+
+/* Create a context for up to n_max spheres on the current HIP device.
+ * hip_stream: a hipStream_t (NULL = the default stream).  opts: nullable.
+ * Allocates O(n_max) device scratch; returns PCOL_E_NOMEM if that fails. */
+pcol_status pcol_create(pcol_ctx **out, int64_t n_max, void *hip_stream, const pcol_opts *opts);
+
+/* Release the context and its device scratch (NULL is ignored). */
+void pcol_destroy(pcol_ctx *ctx);
+
+/* Text of the last error reported on this context (never NULL). */
+const char *pcol_last_error(const pcol_ctx *ctx);
+
+/* Change the stream later calls enqueue on. */
+pcol_status pcol_set_stream(pcol_ctx *ctx, void *hip_stream);
+
+/* Bin the spheres (Sec. "Collision Operator": particles are sorted by host
+ * cell and counted per cell): validates the data, computes
+ * reach = 2 max r + 2 max|v| dt and a uniform grid of cell side >= reach *
+ * cell_mult per axis, and keeps a cell-sorted copy of the start-of-step state
+ * in the context.  Reads only.  Synchronises (reads back the reach and the
+ * largest cell). */
+pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box, double dt);
+
+/* Earliest partner of every active sphere over the active set (rule 1-2),
+ * from the state kept by the last pcol_bin (p must be the binned set).
+ * active: device uint8[n], nonzero = active; NULL = all active.
+ * key_out: device uint64[n]:  (bits of (float)t_min) << 32 | partner index,
+ *          or UINT64_MAX when no active sphere collides with i (or i inactive).
+ * tmin_out: device double[n] (nullable): the exact binary64 t_min, +inf if none.
+ * Indices are caller indices.  Asynchronous. */
+pcol_status pcol_detect(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box, double dt,
+                        const uint8_t *active, uint64_t *key_out, double *tmin_out);
+
+/* One sweep of rule 3-4 from keys made by pcol_detect: for every active i whose
+ * partner j has i as its partner, sphere i gets its post-collision velocity and
+ * end-of-step position (written into p), active[i] = 0, partner[i] = j,
+ * tcoll[i] = t.  Start-of-step data come from the last pcol_bin, so p may
+ * already hold results of earlier sweeps.  n_pairs_dev: device int64 scalar,
+ * incremented by the number of pairs resolved (nullable).  Spheres not in a
+ * mutual pair are untouched.  Asynchronous. */
+pcol_status pcol_resolve(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, double dt,
+                         double e, const uint64_t *key, uint8_t *active, int32_t *partner,
+                         double *tcoll, int64_t *n_pairs_dev);
+
+/* Free flight (rule 5) of every sphere with partner[i] < 0, in place, from the
+ * positions and velocities currently in p.  Asynchronous. */
+pcol_status pcol_advance(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, double dt,
+                         const int32_t *partner);
+
+/* The whole step (rules 1-5): bin, sweeps until none resolves a pair, free
+ * flight and wrap; p is updated in place.  partner (device int32[n], nullable):
+ * the caller index of the sphere i collided with, or -1.  tcoll (device
+ * double[n], nullable): contact time within the step, NaN if none.
+ * stats (host, nullable).  Synchronises once after validation, once after
+ * binning and once per sweep.  On PCOL_E_SWEEPS the pairs resolved so far
+ * have been written to p and the free flight has not run. */
+pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, double dt, double e,
+                      int32_t *partner, double *tcoll, pcol_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCOL_H */

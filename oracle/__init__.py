@@ -61,6 +61,9 @@ def _load():
                                                                   ctypes.c_int, ctypes.c_double,
                                                                   _I64, _D, _I64]
         lib.orc_earliest.restype = ctypes.c_int
+        lib.orc_earliest_subset.argtypes = [ctypes.c_int64] + [_D] * 7 + [_D, ctypes.c_double, _U8,
+                                                                         ctypes.c_int64, _I64, _I64, _D]
+        lib.orc_earliest_subset.restype = ctypes.c_int
         lib.orc_resolve_pair.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_double] + [_D] * 8 + \
             [_D, ctypes.c_double, ctypes.c_double] + [_D] * 6
         lib.orc_resolve_pair.restype = None
@@ -114,6 +117,23 @@ def earliest(box, active=None, *, grid: bool = True, cell_mult: float = 1.0):
     if rc:
         raise OracleError(rc)
     return partner, tmin, tests.value
+
+
+def earliest_subset(box, idx, active=None):
+    """Earliest partner and time of the spheres idx only (same rule as earliest)."""
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    partner = np.empty(idx.shape[0], dtype=np.int64)
+    tmin = np.empty(idx.shape[0], dtype=np.float64)
+    arrs = [_c64(a) for a in (box.x, box.y, box.z, box.vx, box.vy, box.vz, box.r)]
+    act = None if active is None else np.ascontiguousarray(active, dtype=np.uint8)
+    L = _c64(box.L)
+    rc = _load().orc_earliest_subset(box.n, *[_d(a) for a in arrs], _d(L), float(box.dt),
+                                     act.ctypes.data_as(_U8) if act is not None else None,
+                                     idx.shape[0], idx.ctypes.data_as(_I64),
+                                     partner.ctypes.data_as(_I64), _d(tmin))
+    if rc:
+        raise OracleError(rc)
+    return partner, tmin
 
 
 @dataclass

@@ -292,6 +292,57 @@ int orc_earliest(int64_t n, const double *x, const double *y, const double *z, c
   return ORC_OK;
 }
 
+/*
+ * The same earliest-partner rule as orc_earliest, evaluated only for the
+ * spheres listed in idx[0..nsub) (over all active candidates, grid search).
+ * Used to check large inputs at sampled spheres.
+ */
+int orc_earliest_subset(int64_t n, const double *x, const double *y, const double *z,
+                        const double *vx, const double *vy, const double *vz, const double *r,
+                        const double L[3], double dt, const uint8_t *active, int64_t nsub,
+                        const int64_t *idx, int64_t *partner, double *tmin) {
+  int rc = orc_check_inputs(n, x, y, z, vx, vy, vz, r, NULL, L, dt);
+  if (rc) return rc;
+  const double reach = orc_reach(n, vx, vy, vz, r, dt);
+  for (int a = 0; a < 3; ++a)
+    if (!(L[a] > 2.0 * reach)) return ORC_E_BOX;
+  orc_grid G;
+  rc = orc_grid_build(&G, n, x, y, z, L, reach);
+  if (rc) return rc;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t s = 0; s < nsub; ++s) {
+    const int64_t i = idx[s];
+    partner[s] = -1;
+    tmin[s] = INFINITY;
+    if (i < 0 || i >= n || (active && !active[i])) continue;
+    const double xi[3] = {x[i], y[i], z[i]}, vi[3] = {vx[i], vy[i], vz[i]};
+    const int c0 = orc_cell_of(x[i], G.h[0], G.nc[0]);
+    const int c1 = orc_cell_of(y[i], G.h[1], G.nc[1]);
+    const int c2 = orc_cell_of(z[i], G.h[2], G.nc[2]);
+    for (int a2 = 0; a2 < G.nb[2]; ++a2)
+      for (int a1 = 0; a1 < G.nb[1]; ++a1)
+        for (int a0 = 0; a0 < G.nb[0]; ++a0) {
+          const int q0 = (c0 + G.off[0][a0] + G.nc[0]) % G.nc[0];
+          const int q1 = (c1 + G.off[1][a1] + G.nc[1]) % G.nc[1];
+          const int q2 = (c2 + G.off[2][a2] + G.nc[2]) % G.nc[2];
+          const int64_t q = ((int64_t)q2 * G.nc[1] + q1) * G.nc[0] + q0;
+          for (int64_t k = G.start[q]; k < G.start[q + 1]; ++k) {
+            const int64_t j = G.item[k];
+            if (j == i || (active && !active[j])) continue;
+            const double xj[3] = {x[j], y[j], z[j]}, vj[3] = {vx[j], vy[j], vz[j]};
+            double t;
+            if (orc_pair_time(xi, vi, r[i], xj, vj, r[j], L, dt, &t) &&
+                orc_before(t, j, tmin[s], partner[s] < 0 ? INT64_MAX : partner[s])) {
+              tmin[s] = t;
+              partner[s] = j;
+            }
+          }
+        }
+  }
+  orc_grid_free(&G);
+  return ORC_OK;
+}
+
 /* wrap one coordinate of a final position back into [0, L) (C5: one shift by L
  * suffices because no sphere moves more than L/2 in a step; a result that
  * rounds to L itself is mapped to 0) */

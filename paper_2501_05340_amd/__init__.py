@@ -1,0 +1,277 @@
+"""pcol: a deterministic hard-sphere binary collision step on one AMD MI355X.
+
+Thin Python binding of ``libpcol.so`` (C ABI declared in ``include/pcol.h``):
+argument marshalling only.  Every step of the method runs in the library's HIP
+kernels; PyTorch supplies device memory and the current stream.  There is no
+CPU path: importing this package without the built library raises.
+
+The entry points keep the C names (``pcol_create``, ``pcol_bin``,
+``pcol_detect``, ``pcol_resolve``, ``pcol_advance``, ``pcol_step``).  Arrays are
+torch tensors on the GPU: float64 for positions, velocities, radii, masses and
+times, uint8 for active masks, int32 for partners, int64 for keys (the uint64
+key bits reinterpreted).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpcol.so")
+
+PCOL_OK, PCOL_E_INVALID, PCOL_E_BOX, PCOL_E_NOMEM, PCOL_E_HIP, PCOL_E_SWEEPS, PCOL_E_STATE = range(7)
+STATUS_NAMES = {0: "PCOL_OK", 1: "PCOL_E_INVALID", 2: "PCOL_E_BOX", 3: "PCOL_E_NOMEM",
+                4: "PCOL_E_HIP", 5: "PCOL_E_SWEEPS", 6: "PCOL_E_STATE"}
+NO_KEY = -1  # UINT64_MAX seen as int64
+
+
+class pcol_particles(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64)] + [(k, ctypes.c_void_p) for k in
+                                          ("x", "y", "z", "vx", "vy", "vz", "r", "m")]
+
+
+class pcol_box(ctypes.Structure):
+    _fields_ = [("len", ctypes.c_double * 3)]
+
+
+class pcol_opts(ctypes.Structure):
+    _fields_ = [("cell_mult", ctypes.c_double), ("max_sweeps", ctypes.c_int),
+                ("home_cells", ctypes.c_int), ("contact_slots", ctypes.c_int),
+                ("fp32_filter", ctypes.c_int), ("band_rel", ctypes.c_double),
+                ("timing", ctypes.c_int)]
+
+
+class pcol_stats(ctypes.Structure):
+    _fields_ = [("n_pairs", ctypes.c_int64), ("n_sweeps", ctypes.c_int64),
+                ("pair_tests", ctypes.c_int64), ("contacts", ctypes.c_int64),
+                ("n_overflow", ctypes.c_int64), ("n_recheck", ctypes.c_int64),
+                ("nc", ctypes.c_int32 * 3), ("home_cells", ctypes.c_int32),
+                ("max_cell", ctypes.c_int32), ("h", ctypes.c_double * 3),
+                ("reach", ctypes.c_double), ("ms_bin", ctypes.c_double),
+                ("ms_detect", ctypes.c_double), ("ms_sweeps", ctypes.c_double),
+                ("ms_advance", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            out[name] = list(v) if hasattr(v, "__len__") else v
+        return out
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(hipcc, gfx950). There is no CPU fallback.")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, V = ctypes.POINTER, ctypes.c_void_p
+    ctx_p = ctypes.c_void_p
+    lib.pcol_default_opts.argtypes = [P(pcol_opts)]
+    lib.pcol_default_opts.restype = None
+    lib.pcol_create.argtypes = [P(ctx_p), ctypes.c_int64, V, P(pcol_opts)]
+    lib.pcol_create.restype = ctypes.c_int
+    lib.pcol_destroy.argtypes = [ctx_p]
+    lib.pcol_destroy.restype = None
+    lib.pcol_last_error.argtypes = [ctx_p]
+    lib.pcol_last_error.restype = ctypes.c_char_p
+    lib.pcol_set_stream.argtypes = [ctx_p, V]
+    lib.pcol_set_stream.restype = ctypes.c_int
+    lib.pcol_bin.argtypes = [ctx_p, P(pcol_particles), P(pcol_box), ctypes.c_double]
+    lib.pcol_bin.restype = ctypes.c_int
+    lib.pcol_detect.argtypes = [ctx_p, P(pcol_particles), P(pcol_box), ctypes.c_double, V, V, V]
+    lib.pcol_detect.restype = ctypes.c_int
+    lib.pcol_resolve.argtypes = [ctx_p, P(pcol_particles), P(pcol_box), ctypes.c_double,
+                                 ctypes.c_double, V, V, V, V, V]
+    lib.pcol_resolve.restype = ctypes.c_int
+    lib.pcol_advance.argtypes = [ctx_p, P(pcol_particles), P(pcol_box), ctypes.c_double, V]
+    lib.pcol_advance.restype = ctypes.c_int
+    lib.pcol_step.argtypes = [ctx_p, P(pcol_particles), P(pcol_box), ctypes.c_double,
+                              ctypes.c_double, V, V, P(pcol_stats)]
+    lib.pcol_step.restype = ctypes.c_int
+    return lib
+
+
+lib = _load()
+
+EXPORTED = ["pcol_default_opts", "pcol_create", "pcol_destroy", "pcol_last_error",
+            "pcol_set_stream", "pcol_bin", "pcol_detect", "pcol_resolve", "pcol_advance",
+            "pcol_step"]
+
+
+class PcolError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+@dataclass
+class Particles:
+    """SoA sphere state on the GPU (float64, contiguous, length n)."""
+    x: torch.Tensor
+    y: torch.Tensor
+    z: torch.Tensor
+    vx: torch.Tensor
+    vy: torch.Tensor
+    vz: torch.Tensor
+    r: torch.Tensor
+    m: torch.Tensor
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+    @staticmethod
+    def from_box(box, device="cuda") -> "Particles":
+        f = lambda a: torch.as_tensor(a, dtype=torch.float64).to(device).contiguous()
+        return Particles(f(box.x), f(box.y), f(box.z), f(box.vx), f(box.vy), f(box.vz), f(box.r),
+                         f(box.m))
+
+    def clone(self) -> "Particles":
+        return Particles(*[t.clone() for t in self.tensors()])
+
+    def tensors(self):
+        return [self.x, self.y, self.z, self.vx, self.vy, self.vz, self.r, self.m]
+
+    def struct(self) -> pcol_particles:
+        n = self.n
+        for t in self.tensors():
+            if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.shape != (n,):
+                raise ValueError("particle arrays must be contiguous float64 CUDA tensors of equal length")
+        return pcol_particles(n, *[t.data_ptr() for t in self.tensors()])
+
+
+def _box(L) -> pcol_box:
+    b = pcol_box()
+    for a in range(3):
+        b.len[a] = float(L[a])
+    return b
+
+
+def _ptr(t, dtype=None, n=None):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous() or (dtype is not None and t.dtype != dtype):
+        raise ValueError(f"expected a contiguous CUDA tensor of {dtype}")
+    if n is not None and t.shape[0] != n:
+        raise ValueError("array length differs from the particle count")
+    return t.data_ptr()
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def pcol_default_opts(**kw) -> pcol_opts:
+    o = pcol_opts()
+    lib.pcol_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class Context:
+    """Owns a pcol_ctx; destroyed with the object."""
+
+    def __init__(self, n_max: int, opts: pcol_opts | None = None):
+        self._h = ctypes.c_void_p()
+        st = lib.pcol_create(ctypes.byref(self._h), int(n_max), ctypes.c_void_p(_stream()),
+                             ctypes.byref(opts) if opts is not None else None)
+        if st != PCOL_OK:
+            raise PcolError(st, "pcol_create failed")
+        self.n_max = int(n_max)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def check(self, st: int):
+        if st != PCOL_OK:
+            raise PcolError(st, lib.pcol_last_error(self._h).decode())
+
+    def sync_stream(self):
+        lib.pcol_set_stream(self._h, ctypes.c_void_p(_stream()))
+
+    def close(self):
+        if self._h:
+            lib.pcol_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pcol_create(n_max: int, opts: pcol_opts | None = None) -> Context:
+    return Context(n_max, opts)
+
+
+def pcol_destroy(ctx: Context) -> None:
+    ctx.close()
+
+
+def pcol_last_error(ctx: Context) -> str:
+    return lib.pcol_last_error(ctx.handle).decode()
+
+
+def pcol_set_stream(ctx: Context, stream=None) -> None:
+    """Point the context at a stream (default: torch's current stream)."""
+    h = stream.cuda_stream if stream is not None else _stream()
+    ctx.check(lib.pcol_set_stream(ctx.handle, ctypes.c_void_p(h)))
+
+
+def pcol_bin(ctx: Context, p: Particles, L, dt: float) -> None:
+    ctx.sync_stream()
+    ps = p.struct()
+    ctx.check(lib.pcol_bin(ctx.handle, ctypes.byref(ps), ctypes.byref(_box(L)), float(dt)))
+
+
+def pcol_detect(ctx: Context, p: Particles, L, dt: float, active=None, key_out=None,
+                tmin_out=None):
+    """Returns (key, tmin) tensors (allocated if not given)."""
+    n = p.n
+    if key_out is None:
+        key_out = torch.empty(n, dtype=torch.int64, device=p.x.device)
+    if tmin_out is None:
+        tmin_out = torch.empty(n, dtype=torch.float64, device=p.x.device)
+    ctx.sync_stream()
+    ps = p.struct()
+    ctx.check(lib.pcol_detect(ctx.handle, ctypes.byref(ps), ctypes.byref(_box(L)), float(dt),
+                              _ptr(active, torch.uint8, n), _ptr(key_out, torch.int64, n),
+                              _ptr(tmin_out, torch.float64, n)))
+    return key_out, tmin_out
+
+
+def pcol_resolve(ctx: Context, p: Particles, L, dt: float, e: float, key, active, partner=None,
+                 tcoll=None, n_pairs=None) -> None:
+    n = p.n
+    ctx.sync_stream()
+    ps = p.struct()
+    ctx.check(lib.pcol_resolve(ctx.handle, ctypes.byref(ps), ctypes.byref(_box(L)), float(dt),
+                               float(e), _ptr(key, torch.int64, n), _ptr(active, torch.uint8, n),
+                               _ptr(partner, torch.int32, n), _ptr(tcoll, torch.float64, n),
+                               _ptr(n_pairs, torch.int64)))
+
+
+def pcol_advance(ctx: Context, p: Particles, L, dt: float, partner) -> None:
+    ctx.sync_stream()
+    ps = p.struct()
+    ctx.check(lib.pcol_advance(ctx.handle, ctypes.byref(ps), ctypes.byref(_box(L)), float(dt),
+                               _ptr(partner, torch.int32, p.n)))
+
+
+def pcol_step(ctx: Context, p: Particles, L, dt: float, e: float, partner=None, tcoll=None,
+              stats: bool = True):
+    """One full step in place; returns a dict of pcol_stats (or None)."""
+    n = p.n
+    st = pcol_stats() if stats else None
+    ctx.sync_stream()
+    ps = p.struct()
+    ctx.check(lib.pcol_step(ctx.handle, ctypes.byref(ps), ctypes.byref(_box(L)), float(dt),
+                            float(e), _ptr(partner, torch.int32, n), _ptr(tcoll, torch.float64, n),
+                            ctypes.byref(st) if st is not None else None))
+    return st.as_dict() if st is not None else None

@@ -1,0 +1,192 @@
+// Internal declarations of the pcol HIP library: device helpers shared by the
+// kernels and the launch wrappers the C-ABI layer calls.  gfx950 only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#pragma clang fp contract(off)
+
+namespace pcol {
+
+// Cell-sorted start-of-step record of one sphere (64 B, one HBM burst).
+struct alignas(16) Rec {
+  double x, y, z, r;
+  double vx, vy, vz, m;
+};
+
+// Sphere status during a step.
+enum : uint8_t { ST_ACTIVE = 0, ST_FREE = 1, ST_COLLIDED = 2 };
+
+// Uniform grid over the periodic box.  Cells are numbered (cz * nc1 + cy) * nc0 + cx,
+// so the cells of one x-row are consecutive and so are their spheres after sorting.
+struct Grid {
+  int nc[3];
+  int ncell;
+  double inv_h[3];  // nc / L, for cell assignment only
+  double L[3];
+  double halfL[3];  // 0.5 * L, the minimum-image threshold
+};
+
+// Values the reach kernel reduces (non-negative doubles compared as bit patterns).
+struct ReachOut {
+  unsigned long long v2max;  // max over spheres of (vx^2 + vy^2) + vz^2
+  unsigned long long rmax;
+  unsigned int bad;          // bit 0: non-finite / r <= 0 / m <= 0; bit 1: position outside [0, L)
+  unsigned int maxcell;      // filled by the scan
+};
+
+// Per-sweep counters the host reads back.
+struct SweepCounters {
+  unsigned long long pairs;       // pairs resolved this sweep
+  unsigned long long pair_tests;  // unordered pairs tested geometrically
+  unsigned long long contacts;    // unordered contacts found
+  unsigned long long recheck;     // FP32 filter survivors rechecked in FP64
+  unsigned int n_next;            // spheres still waiting for a partner
+  unsigned int n_dirty;           // spheres whose partner collided with another sphere
+  unsigned int n_overflow;        // spheres with more contacts than slots
+  unsigned int pad;
+};
+
+// ---------------------------------------------------------------- the rule
+
+// Contact time of a pair from its minimum-image separation d = x_j - x_i and
+// relative velocity u = v_j - v_i (rule 1 of pcol.h; eq. detect1/detect2).
+__device__ __forceinline__ bool contact_time(double d0, double d1, double d2, double u0, double u1,
+                                             double u2, double s, double dt, double &t) {
+  const double a = (u0 * u0 + u1 * u1) + u2 * u2;
+  const double b = (d0 * u0 + d1 * u1) + d2 * u2;
+  const double c = ((d0 * d0 + d1 * d1) + d2 * d2) - s * s;
+  if (!(a > 0.0) || !(b < 0.0) || !(c > 0.0)) return false;
+  const double D = b * b - a * c;
+  if (!(D >= 0.0)) return false;
+  t = c / (-b + __builtin_sqrt(D));
+  return t <= dt;
+}
+
+// Minimum-image separation along one axis (rule 1).
+__device__ __forceinline__ double wrap_sep(double d, double L, double halfL) {
+  if (d > halfL) {
+    d = d - L;
+  } else if (d < -halfL) {
+    d = d + L;
+  }
+  return d;
+}
+
+// Final coordinate back into [0, L) (rule 5).
+__device__ __forceinline__ double wrap_pos(double p, double L) {
+  if (p >= L) {
+    p = p - L;
+  } else if (p < 0.0) {
+    p = p + L;
+  }
+  if (p >= L) p = 0.0;
+  return p;
+}
+
+// Exact contact time of two records with the canonical minimum image.
+__device__ __forceinline__ bool pair_time(const Rec &a, const Rec &b, const Grid &G, double dt,
+                                          double &t) {
+  const double d0 = wrap_sep(b.x - a.x, G.L[0], G.halfL[0]);
+  const double d1 = wrap_sep(b.y - a.y, G.L[1], G.halfL[1]);
+  const double d2 = wrap_sep(b.z - a.z, G.L[2], G.halfL[2]);
+  return contact_time(d0, d1, d2, b.vx - a.vx, b.vy - a.vy, b.vz - a.vz, a.r + b.r, dt, t);
+}
+
+// Post-collision state of sphere `a` colliding with `b` at time t (rule 4,
+// Sec. "Inter-Particle Collisions" with friction 0, eq. update_vel/update_rho).
+// Bitwise independent of which of the two is `a`.
+__device__ __forceinline__ void resolve_one(const Rec &a, const Rec &b, const Grid &G, double t,
+                                            double dt, double e, double out_x[3],
+                                            double out_v[3]) {
+  const double d0 = wrap_sep(b.x - a.x, G.L[0], G.halfL[0]);
+  const double d1 = wrap_sep(b.y - a.y, G.L[1], G.halfL[1]);
+  const double d2 = wrap_sep(b.z - a.z, G.L[2], G.halfL[2]);
+  const double u0 = b.vx - a.vx, u1 = b.vy - a.vy, u2 = b.vz - a.vz;
+  const double s = a.r + b.r;
+  const double n0 = (d0 + t * u0) / s;
+  const double n1 = (d1 + t * u1) / s;
+  const double n2 = (d2 + t * u2) / s;
+  const double g = (u0 * n0 + u1 * n1) + u2 * n2;
+  const double mr = (a.m * b.m) / (a.m + b.m);
+  const double J = (mr * (1.0 + e)) * g;
+  const double ai = J / a.m;
+  out_v[0] = a.vx + ai * n0;
+  out_v[1] = a.vy + ai * n1;
+  out_v[2] = a.vz + ai * n2;
+  const double rest = dt - t;
+  out_x[0] = wrap_pos((a.x + t * a.vx) + rest * out_v[0], G.L[0]);
+  out_x[1] = wrap_pos((a.y + t * a.vy) + rest * out_v[1], G.L[1]);
+  out_x[2] = wrap_pos((a.z + t * a.vz) + rest * out_v[2], G.L[2]);
+}
+
+__device__ __forceinline__ int cell_coord(double x, double inv_h, int nc) {
+  int c = (int)(x * inv_h);
+  c = c < 0 ? 0 : c;
+  return c > nc - 1 ? nc - 1 : c;
+}
+
+// ---------------------------------------------------------------- launches
+
+struct Particles {
+  int64_t n;
+  double *x, *y, *z, *vx, *vy, *vz;
+  const double *r, *m;
+};
+
+// Everything the sweep-1 detect needs.
+struct DetectArgs {
+  const Rec *rec;
+  const int *start;   // ncell + 1
+  int *cnt;           // per sorted sphere: contacts found
+  double *slot_t;     // [n * K]
+  int *slot_j;        // [n * K]
+  SweepCounters *ctr;
+  Grid G;
+  double dt;
+  double dt2;         // 2 dt (1 + 2^-20): conservative bound for the cheap reject
+  int K;
+  int fp32;           // FP32 filter + FP64 recheck
+  float band;         // FP32 filter band relative to s
+};
+
+hipError_t launch_fill_u32(hipStream_t s, unsigned int *p, unsigned int v, int64_t n);
+hipError_t launch_fill_u8(hipStream_t s, uint8_t *p, uint8_t v, int64_t n);
+hipError_t launch_fill_f64(hipStream_t s, double *p, double v, int64_t n);
+hipError_t launch_fill_i32(hipStream_t s, int *p, int v, int64_t n);
+hipError_t launch_reach(hipStream_t s, const Particles &P, const double L[3], ReachOut *out);
+hipError_t launch_cell_hist(hipStream_t s, const Particles &P, const Grid &G, int *cid, int *slot,
+                            int *count);
+hipError_t launch_scan(hipStream_t s, const int *count, int ncell, int *start, int *blocksum,
+                       ReachOut *out);
+hipError_t launch_scatter(hipStream_t s, const Particles &P, const int *cid, const int *slot,
+                          const int *start, Rec *rec, int *perm, int *rank);
+hipError_t launch_detect_half(hipStream_t s, const DetectArgs &A);
+hipError_t launch_count_pairs(hipStream_t s, const int *start, const Grid &G,
+                              unsigned long long *out);
+hipError_t launch_slot_min(hipStream_t s, const int *list, int nlist, const int *cnt,
+                           const double *slot_t, const int *slot_j, int K, const uint8_t *status,
+                           const int *perm, int *key_j, double *key_t, int *ovf_list,
+                           SweepCounters *ctr);
+hipError_t launch_gather_exact(hipStream_t s, const int *list, int nlist, const Rec *rec,
+                               const int *start, const Grid &G, double dt, const uint8_t *status,
+                               const int *perm, int *key_j, double *key_t, const unsigned int *nlist_dev);
+hipError_t launch_resolve_sweep(hipStream_t s, const int *list, int nlist, const Rec *rec,
+                                const Grid &G, double dt, double e, const int *key_j,
+                                const double *key_t, uint8_t *status, const int *perm,
+                                const Particles &P, int *partner_out, double *tcoll_out,
+                                int *next_list, int *dirty_list, SweepCounters *ctr);
+hipError_t launch_advance(hipStream_t s, const Particles &P, const int *partner, double dt,
+                          const double L[3]);
+hipError_t launch_status_from_active(hipStream_t s, const uint8_t *active, const int *perm, int n,
+                                     uint8_t *status, int *list, unsigned int *nlist);
+hipError_t launch_export_keys(hipStream_t s, int n, const int *perm, const int *key_j,
+                              const double *key_t, const uint8_t *status, uint64_t *key_out,
+                              double *tmin_out);
+hipError_t launch_resolve_public(hipStream_t s, int n, const Rec *rec, const int *rank,
+                                 const Grid &G, double dt, double e, const uint64_t *key,
+                                 const Particles &P, uint8_t *active, int *partner, double *tcoll,
+                                 long long *npairs);
+
+}  // namespace pcol

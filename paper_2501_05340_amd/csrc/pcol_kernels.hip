@@ -1,0 +1,876 @@
+// HIP kernels of the pcol collision step (gfx950, wave64).  Each kernel states
+// the step of the method it implements; the rule numbers refer to the header
+// comment of include/pcol.h.
+#include "pcol_internal.h"
+
+#include <math.h>
+
+namespace pcol {
+
+namespace {
+
+constexpr int WAVE = 64;
+
+__device__ __forceinline__ unsigned long long dbits(double v) {
+  return (unsigned long long)__double_as_longlong(v);
+}
+
+// Exclusive position of this lane among the lanes of the wave for which `pred`
+// holds, and one atomic per wave on `counter` for all of them.  Returns the
+// slot of this lane (valid only where pred).
+__device__ __forceinline__ unsigned int wave_append(bool pred, unsigned int *counter) {
+  const unsigned long long mask = __ballot(pred);
+  if (mask == 0ull) return 0u;
+  const unsigned int lane = __lane_id();
+  const unsigned int below = __popcll(mask & ((1ull << lane) - 1ull));
+  const int leader = __ffsll((long long)mask) - 1;
+  unsigned int base = 0u;
+  if ((int)lane == leader) base = atomicAdd(counter, (unsigned int)__popcll(mask));
+  base = __shfl(base, leader);
+  return base + below;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// blockIdx -> logical block so that each of the 8 XCDs (which receive
+// workgroups round-robin) walks one contiguous range of logical blocks: spatial
+// neighbours then share that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+  const int q = nblocks / 8, r = nblocks % 8;
+  const int x = bid % 8;
+  return x * q + (x < r ? x : r) + bid / 8;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- fills
+
+__global__ void k_fill_u32(unsigned int *p, unsigned int v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_fill_u8(uint8_t *p, uint8_t v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_fill_f64(double *p, double v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+static int fill_grid(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  return g < 1 ? 1 : (int)g;
+}
+
+hipError_t launch_fill_u32(hipStream_t s, unsigned int *p, unsigned int v, int64_t n) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid(n)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill_i32(hipStream_t s, int *p, int v, int64_t n) {
+  return launch_fill_u32(s, (unsigned int *)p, (unsigned int)v, n);
+}
+hipError_t launch_fill_u8(hipStream_t s, uint8_t *p, uint8_t v, int64_t n) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u8, dim3(fill_grid(n)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill_f64(hipStream_t s, double *p, double v, int64_t n) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f64, dim3(fill_grid(n)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- a1: reach + validation
+
+// max (vx^2 + vy^2) + vz^2, max r, and data validity (Sec. "Collision Operator":
+// the halo must cover the distance the fastest sphere travels).  Reads 64 B per
+// sphere, coalesced.
+__global__ __launch_bounds__(256) void k_reach(Particles P, double L0, double L1, double L2,
+                                               ReachOut *out) {
+  double v2 = 0.0, rm = 0.0;
+  unsigned int bad = 0u;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < P.n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double x = P.x[i], y = P.y[i], z = P.z[i];
+    const double vx = P.vx[i], vy = P.vy[i], vz = P.vz[i];
+    const double r = P.r[i], m = P.m[i];
+    const double w = (vx * vx + vy * vy) + vz * vz;
+    const bool fin = isfinite(x) && isfinite(y) && isfinite(z) && isfinite(w) && isfinite(r) &&
+                     isfinite(m);
+    if (!fin || !(r > 0.0) || !(m > 0.0)) bad |= 1u;
+    if (!(x >= 0.0 && x < L0) || !(y >= 0.0 && y < L1) || !(z >= 0.0 && z < L2)) bad |= 2u;
+    if (fin) {
+      v2 = w > v2 ? w : v2;
+      rm = r > rm ? r : rm;
+    }
+  }
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    const double a = __shfl_xor(v2, o), b = __shfl_xor(rm, o);
+    v2 = a > v2 ? a : v2;
+    rm = b > rm ? b : rm;
+    bad |= __shfl_xor(bad, o);
+  }
+  if (__lane_id() == 0) {
+    atomicMax(&out->v2max, dbits(v2));
+    atomicMax(&out->rmax, dbits(rm));
+    if (bad) atomicOr(&out->bad, bad);
+  }
+}
+
+hipError_t launch_reach(hipStream_t s, const Particles &P, const double L[3], ReachOut *out) {
+  int64_t g = (P.n + 255) / 256;
+  if (g > 2048) g = 2048;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_reach, dim3((int)g), dim3(256), 0, s, P, L[0], L[1], L[2], out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- a2: cell id + histogram
+
+// cell of each sphere and its rank within the cell (the counting-sort slot);
+// Sec. "Collision Operator": particles are sorted by host cell and counted.
+__global__ __launch_bounds__(256) void k_cell_hist(Particles P, Grid G, int *cid, int *slot,
+                                                   int *count) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= P.n) return;
+  const int cx = cell_coord(P.x[i], G.inv_h[0], G.nc[0]);
+  const int cy = cell_coord(P.y[i], G.inv_h[1], G.nc[1]);
+  const int cz = cell_coord(P.z[i], G.inv_h[2], G.nc[2]);
+  const int c = (cz * G.nc[1] + cy) * G.nc[0] + cx;
+  cid[i] = c;
+  slot[i] = atomicAdd(&count[c], 1);
+}
+
+hipError_t launch_cell_hist(hipStream_t s, const Particles &P, const Grid &G, int *cid, int *slot,
+                            int *count) {
+  if (P.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cell_hist, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, s, P, G,
+                     cid, slot, count);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- a3: exclusive scan
+
+constexpr int SCAN_T = 1024;   // threads per scan block
+constexpr int SCAN_E = 4;      // elements per thread
+constexpr int SCAN_B = SCAN_T * SCAN_E;
+
+// block-wide exclusive scan of one int per thread
+__device__ void block_exclusive_scan(int v, int &excl) {
+  __shared__ int wsum[SCAN_T / WAVE];
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  int inc = v;
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const int t = __shfl_up(inc, o);
+    if (lane >= o) inc += t;
+  }
+  if (lane == WAVE - 1) wsum[w] = inc;
+  __syncthreads();
+  if (w == 0) {
+    int s = lane < SCAN_T / WAVE ? wsum[lane] : 0;
+    int si = s;
+    for (int o = 1; o < WAVE; o <<= 1) {
+      const int t = __shfl_up(si, o);
+      if (lane >= o) si += t;
+    }
+    if (lane < SCAN_T / WAVE) wsum[lane] = si - s;
+  }
+  __syncthreads();
+  excl = wsum[w] + inc - v;
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_blocks(const int *count, int n, int *start,
+                                                         int *blocksum, ReachOut *out) {
+  const int base = blockIdx.x * SCAN_B + threadIdx.x * SCAN_E;
+  int v[SCAN_E];
+  int sum = 0, mx = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_E; ++k) {
+    v[k] = base + k < n ? count[base + k] : 0;
+    sum += v[k];
+    mx = v[k] > mx ? v[k] : mx;
+  }
+  int excl;
+  block_exclusive_scan(sum, excl);
+  int run = excl;
+#pragma unroll
+  for (int k = 0; k < SCAN_E; ++k) {
+    if (base + k < n) start[base + k] = run;
+    run += v[k];
+  }
+  // block total: the last thread's running end
+  if (threadIdx.x == SCAN_T - 1) blocksum[blockIdx.x] = run;
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    const int t = __shfl_xor(mx, o);
+    mx = t > mx ? t : mx;
+  }
+  if (__lane_id() == 0) atomicMax(&out->maxcell, (unsigned int)mx);
+}
+
+// exclusive scan of the block sums in place (one block, chunks of SCAN_T)
+__global__ __launch_bounds__(SCAN_T) void k_scan_sums(int *blocksum, int nb) {
+  __shared__ int carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < nb; c0 += SCAN_T) {
+    const int i = c0 + threadIdx.x;
+    const int v = i < nb ? blocksum[i] : 0;
+    int excl;
+    block_exclusive_scan(v, excl);
+    const int c = carry;
+    if (i < nb) blocksum[i] = c + excl;
+    __syncthreads();
+    if (threadIdx.x == SCAN_T - 1) carry = c + excl + v;
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scan_add(int *start, const int *count, int n,
+                                                  const int *blocksum) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int v = start[i] + blocksum[i / SCAN_B];
+  start[i] = v;
+  if (i == n - 1) start[n] = v + count[i];
+}
+
+hipError_t launch_scan(hipStream_t s, const int *count, int ncell, int *start, int *blocksum,
+                       ReachOut *out) {
+  const int nb = (ncell + SCAN_B - 1) / SCAN_B;
+  hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(SCAN_T), 0, s, count, ncell, start, blocksum,
+                     out);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_T), 0, s, blocksum, nb);
+  hipLaunchKernelGGL(k_scan_add, dim3((ncell + 255) / 256), dim3(256), 0, s, start, count, ncell,
+                     blocksum);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- a4: scatter
+
+// cell-sorted 64-B records of the start-of-step state; reads the caller's SoA
+// arrays coalesced and writes one record per sphere.
+__global__ __launch_bounds__(256) void k_scatter(Particles P, const int *cid, const int *slot,
+                                                 const int *start, Rec *rec, int *perm,
+                                                 int *rank) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= P.n) return;
+  const int pos = start[cid[i]] + slot[i];
+  Rec q;
+  q.x = P.x[i];
+  q.y = P.y[i];
+  q.z = P.z[i];
+  q.r = P.r[i];
+  q.vx = P.vx[i];
+  q.vy = P.vy[i];
+  q.vz = P.vz[i];
+  q.m = P.m[i];
+  rec[pos] = q;
+  perm[pos] = (int)i;
+  rank[i] = pos;
+}
+
+hipError_t launch_scatter(hipStream_t s, const Particles &P, const int *cid, const int *slot,
+                          const int *start, Rec *rec, int *perm, int *rank) {
+  if (P.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, s, P, cid,
+                     slot, start, rec, perm, rank);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- a5: sweep-1 detect
+
+// All contacts within dt among all spheres (rule 1; eq. detect1/detect2), each
+// unordered pair of spheres in neighbouring cells tested exactly once (the
+// half stencil: own cell with j after i, and the 13 forward neighbour cells).
+// Every contact (i, j, t) is appended to the contact slots of both spheres.
+//
+// One wave per home cell.  The wave's candidate list is the concatenation of
+// up to 10 contiguous runs of the cell-sorted records (4 rows of 3 cells, the
+// own cell and the next cell; a periodic wrap along x splits a row in two).
+// Lanes hold candidates j (one 64-B record each, loaded once per chunk of 64);
+// the home spheres i are wave-uniform and loop inside, so each pair costs the
+// arithmetic only.  A run carries the periodic image shift of its cells; for a
+// pair that can touch, the shifted separation equals the minimum image of rule
+// 1 bitwise (the grid has >= 3 cells per axis and cell side >= reach).
+//
+// Cheap reject before the square root: any root t <= dt has
+// c <= 2 |b| dt (1 + 6 eps), so c > -b * dt2 (dt2 = 2 dt (1 + 2^-20)) means no
+// contact.  Spheres that pass go through the full rule.
+constexpr int MAXRUN = 10;
+
+// records seen through the constant address space: wave-uniform reads of the
+// home spheres become scalar loads (the records are never written during the
+// detect)
+typedef __attribute__((address_space(4))) const Rec *crec_ptr;
+
+template <bool SHIFT>
+__device__ __forceinline__ void detect_chunk(const DetectArgs &A, int h0, int h1, int g, bool ok,
+                                             bool own, double sx, double sy, double sz) {
+  const crec_ptr hrec = (crec_ptr)A.rec;
+  Rec b;
+  if (ok) {
+    b = A.rec[g];
+  } else {
+    b.x = b.y = b.z = 0.0;
+    b.vx = b.vy = b.vz = 0.0;
+    b.r = 0.0;
+    b.m = 1.0;
+  }
+  const double dt = A.dt, dt2 = A.dt2;
+  // home record i+1 is requested while pair (i, j) is computed
+  double nx = hrec[h0].x, ny = hrec[h0].y, nz = hrec[h0].z, nr = hrec[h0].r;
+  double nvx = hrec[h0].vx, nvy = hrec[h0].vy, nvz = hrec[h0].vz;
+  for (int i = h0; i < h1; ++i) {
+    const double xi = nx, yi = ny, zi = nz, ri = nr, vxi = nvx, vyi = nvy, vzi = nvz;
+    const int in = i + 1 < h1 ? i + 1 : i;
+    nx = hrec[in].x;
+    ny = hrec[in].y;
+    nz = hrec[in].z;
+    nr = hrec[in].r;
+    nvx = hrec[in].vx;
+    nvy = hrec[in].vy;
+    nvz = hrec[in].vz;
+    double d0 = b.x - xi, d1 = b.y - yi, d2 = b.z - zi;
+    if (SHIFT) {
+      d0 = d0 + sx;
+      d1 = d1 + sy;
+      d2 = d2 + sz;
+    }
+    const double u0 = b.vx - vxi, u1 = b.vy - vyi, u2 = b.vz - vzi;
+    const double s = ri + b.r;
+    const double bb = (d0 * u0 + d1 * u1) + d2 * u2;
+    const double cc = ((d0 * d0 + d1 * d1) + d2 * d2) - s * s;
+    const bool valid = ok && (!own || g > i);
+    if (valid && bb < 0.0 && cc > 0.0 && cc <= -bb * dt2) {
+      const double aa = (u0 * u0 + u1 * u1) + u2 * u2;
+      const double D = bb * bb - aa * cc;
+      if (aa > 0.0 && D >= 0.0) {
+        const double t = cc / (-bb + __builtin_sqrt(D));
+        if (t <= dt) {
+          const int K = A.K;
+          const int k1 = atomicAdd(&A.cnt[i], 1);
+          if (k1 < K) {
+            A.slot_t[(size_t)i * K + k1] = t;
+            A.slot_j[(size_t)i * K + k1] = g;
+          }
+          const int k2 = atomicAdd(&A.cnt[g], 1);
+          if (k2 < K) {
+            A.slot_t[(size_t)g * K + k2] = t;
+            A.slot_j[(size_t)g * K + k2] = i;
+          }
+        }
+      }
+    }
+  }
+}
+
+// shift code of a run: per axis 0 = -L, 1 = none, 2 = +L (2 bits each), bit 6 = own cell
+__device__ __forceinline__ int run_code(int sx, int sy, int sz, int own) {
+  return (sx + 1) | ((sy + 1) << 2) | ((sz + 1) << 4) | (own << 6);
+}
+
+__device__ __forceinline__ double code_shift(int c, double L) {
+  return c == 0 ? -L : (c == 2 ? L : 0.0);
+}
+
+__global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
+  const Grid &G = A.G;
+  const int cell = xcd_remap(blockIdx.x, gridDim.x);
+  const int nc0 = G.nc[0], nc1 = G.nc[1], nc2 = G.nc[2];
+  const int cx = cell % nc0, cy = (cell / nc0) % nc1, cz = cell / (nc0 * nc1);
+  const int h0 = A.start[cell], h1 = A.start[cell + 1];
+  if (h1 <= h0) return;
+
+  // runs of consecutive sorted records: global start, length, shift code
+  int rg[MAXRUN], rl[MAXRUN], rc[MAXRUN];
+#pragma unroll
+  for (int k = 0; k < MAXRUN; ++k) {
+    rg[k] = 0;
+    rl[k] = 0;
+    rc[k] = run_code(0, 0, 0, 0);
+  }
+  bool any_shift = false;
+  const int dys[4] = {1, -1, 0, 1}, dzs[4] = {0, 1, 1, 1};
+#pragma unroll
+  for (int row = 0; row < 4; ++row) {
+    int y = cy + dys[row], z = cz + dzs[row];
+    int sy = 0, sz = 0;
+    if (y >= nc1) {
+      y -= nc1;
+      sy = 1;
+    } else if (y < 0) {
+      y += nc1;
+      sy = -1;
+    }
+    if (z >= nc2) {
+      z -= nc2;
+      sz = 1;
+    }
+    const int rowbase = (z * nc1 + y) * nc0;
+    const int k0 = 2 * row, k1 = 2 * row + 1;
+    if (cx - 1 < 0) {  // the wrapped left cell, then cells 0..1
+      rg[k0] = A.start[rowbase + nc0 - 1];
+      rl[k0] = A.start[rowbase + nc0] - rg[k0];
+      rc[k0] = run_code(-1, sy, sz, 0);
+      rg[k1] = A.start[rowbase];
+      rl[k1] = A.start[rowbase + 2] - rg[k1];
+      rc[k1] = run_code(0, sy, sz, 0);
+      any_shift = true;
+    } else if (cx + 1 >= nc0) {  // cells cx-1..cx, then the wrapped right cell 0
+      rg[k0] = A.start[rowbase + cx - 1];
+      rl[k0] = A.start[rowbase + cx + 1] - rg[k0];
+      rc[k0] = run_code(0, sy, sz, 0);
+      rg[k1] = A.start[rowbase];
+      rl[k1] = A.start[rowbase + 1] - rg[k1];
+      rc[k1] = run_code(1, sy, sz, 0);
+      any_shift = true;
+    } else {
+      rg[k0] = A.start[rowbase + cx - 1];
+      rl[k0] = A.start[rowbase + cx + 2] - rg[k0];
+      rc[k0] = run_code(0, sy, sz, 0);
+    }
+    if (sy != 0 || sz != 0) any_shift = true;
+  }
+  // own cell (pairs with j after i) and the next cell along x
+  rg[8] = h0;
+  rl[8] = h1 - h0;
+  rc[8] = run_code(0, 0, 0, 1);
+  if (cx + 1 >= nc0) {
+    const int rowbase = (cz * nc1 + cy) * nc0;
+    rg[9] = A.start[rowbase];
+    rl[9] = A.start[rowbase + 1] - rg[9];
+    rc[9] = run_code(1, 0, 0, 0);
+    any_shift = true;
+  } else {
+    rg[9] = h1;
+    rl[9] = A.start[cell + 2] - h1;
+  }
+  int total = 0;
+  int pre[MAXRUN];
+#pragma unroll
+  for (int k = 0; k < MAXRUN; ++k) {
+    pre[k] = total;
+    total += rl[k];
+  }
+
+  const int lane = threadIdx.x;
+  for (int base = 0; base < total; base += WAVE) {
+    const int v = base + lane;
+    int g = 0, code = run_code(0, 0, 0, 0);
+    bool ok = false;
+#pragma unroll
+    for (int k = 0; k < MAXRUN; ++k) {
+      if (v >= pre[k] && v < pre[k] + rl[k]) {
+        g = rg[k] + (v - pre[k]);
+        code = rc[k];
+        ok = true;
+      }
+    }
+    const bool own = (code >> 6) & 1;
+    if (any_shift) {
+      detect_chunk<true>(A, h0, h1, g, ok, own, code_shift(code & 3, G.L[0]),
+                         code_shift((code >> 2) & 3, G.L[1]), code_shift((code >> 4) & 3, G.L[2]));
+    } else {
+      detect_chunk<false>(A, h0, h1, g, ok, own, 0.0, 0.0, 0.0);
+    }
+  }
+}
+
+hipError_t launch_detect_half(hipStream_t s, const DetectArgs &A) {
+  if (A.G.ncell <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_detect_half, dim3(A.G.ncell), dim3(WAVE), 0, s, A);
+  return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------- unordered pair count
+
+// unordered candidate pairs the half stencil tests: per cell n(n-1)/2 plus n
+// times the occupancy of its 13 forward neighbour cells
+__global__ __launch_bounds__(256) void k_count_pairs(const int *start, Grid G,
+                                                     unsigned long long *out) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  unsigned long long acc = 0ull;
+  if (c < G.ncell) {
+    const int nc0 = G.nc[0], nc1 = G.nc[1], nc2 = G.nc[2];
+    const int cx = c % nc0, cy = (c / nc0) % nc1, cz = c / (nc0 * nc1);
+    const long long n = start[c + 1] - start[c];
+    acc = (unsigned long long)(n * (n - 1) / 2);
+    const int off[13][3] = {{1, 0, 0},  {-1, 1, 0}, {0, 1, 0},  {1, 1, 0},  {-1, -1, 1},
+                            {0, -1, 1}, {1, -1, 1}, {-1, 0, 1}, {0, 0, 1},  {1, 0, 1},
+                            {-1, 1, 1}, {0, 1, 1},  {1, 1, 1}};
+    for (int k = 0; k < 13; ++k) {
+      const int x = (cx + off[k][0] + nc0) % nc0, y = (cy + off[k][1] + nc1) % nc1,
+                z = (cz + off[k][2] + nc2) % nc2;
+      const int q = (z * nc1 + y) * nc0 + x;
+      acc += (unsigned long long)(n * (start[q + 1] - start[q]));
+    }
+  }
+  acc = wave_sum(acc);
+  if (__lane_id() == 0 && acc) atomicAdd(out, acc);
+}
+
+hipError_t launch_count_pairs(hipStream_t s, const int *start, const Grid &G,
+                              unsigned long long *out) {
+  hipLaunchKernelGGL(k_count_pairs, dim3((G.ncell + 255) / 256), dim3(256), 0, s, start, G, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- a5/a7: partner from contact slots
+
+// Earliest partner of each listed sphere among its recorded contacts whose
+// partner has not collided (rule 2: exact binary64 t, ties to the smaller caller
+// index).  The contact set of a sphere only shrinks over the sweeps of a step,
+// so the slots from the sweep-1 detect are complete for every later sweep.
+// Spheres with more contacts than slots are queued for the exact search.
+__global__ __launch_bounds__(256) void k_slot_min(const int *list, int nlist, const int *cnt,
+                                                  const double *slot_t, const int *slot_j, int K,
+                                                  const uint8_t *status, const int *perm,
+                                                  int *key_j, double *key_t, int *ovf_list,
+                                                  SweepCounters *ctr) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  bool ovf = false;
+  int i = -1;
+  unsigned long long nc = 0ull;
+  if (idx < nlist) {
+    i = list ? list[idx] : idx;
+    const int c = cnt[i];
+    nc = (unsigned long long)c;
+    if (c > K) {
+      ovf = true;
+      key_j[i] = -1;
+      key_t[i] = INFINITY;
+    } else {
+      double bt = INFINITY;
+      int bj = -1;
+      for (int k = 0; k < c; ++k) {
+        const int j = slot_j[(size_t)i * K + k];
+        if (status && status[j] == ST_COLLIDED) continue;
+        const double t = slot_t[(size_t)i * K + k];
+        if (t < bt || (bj >= 0 && t == bt && perm[j] < perm[bj])) {
+          bt = t;
+          bj = j;
+        }
+      }
+      key_j[i] = bj;
+      key_t[i] = bt;
+    }
+  }
+  const unsigned int k = wave_append(ovf, &ctr->n_overflow);
+  if (ovf) ovf_list[k] = i;
+  if (!list) {  // the sweep-1 pass also counts the contacts (each stored twice)
+    nc = wave_sum(nc);
+    if (__lane_id() == 0 && nc) atomicAdd(&ctr->contacts, nc);
+  }
+}
+
+hipError_t launch_slot_min(hipStream_t s, const int *list, int nlist, const int *cnt,
+                           const double *slot_t, const int *slot_j, int K, const uint8_t *status,
+                           const int *perm, int *key_j, double *key_t, int *ovf_list,
+                           SweepCounters *ctr) {
+  if (nlist <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_slot_min, dim3((nlist + 255) / 256), dim3(256), 0, s, list, nlist, cnt,
+                     slot_t, slot_j, K, status, perm, key_j, key_t, ovf_list, ctr);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- exact neighbourhood search
+
+// Earliest partner (rule 2) of listed spheres by an exact search of the 27
+// surrounding cells (distinct cells only when an axis has fewer than 3),
+// minimum image by rule 1.  One wave per sphere; lanes over candidates; the
+// wave reduces (t, caller index) exactly.  Used for spheres whose contacts
+// overflowed the slots, for pcol_detect with an active mask, and for boxes
+// with fewer than 3 cells along some axis.  `status` (nullable) excludes
+// collided spheres.  The list length is read from nlist_dev when given.
+__global__ __launch_bounds__(256) void k_gather_exact(const int *list, int nlist,
+                                                      const unsigned int *nlist_dev,
+                                                      const Rec *rec, const int *start, Grid G,
+                                                      double dt, const uint8_t *status,
+                                                      const int *perm, int *key_j,
+                                                      double *key_t) {
+  const int lane = __lane_id();
+  const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int nw = (gridDim.x * blockDim.x) / WAVE;
+  const int count = nlist_dev ? (int)*nlist_dev : nlist;
+  int nb[3], off[3][3];
+  for (int a = 0; a < 3; ++a) {
+    if (G.nc[a] >= 3) {
+      nb[a] = 3;
+      off[a][0] = -1;
+      off[a][1] = 0;
+      off[a][2] = 1;
+    } else if (G.nc[a] == 2) {
+      nb[a] = 2;
+      off[a][0] = 0;
+      off[a][1] = 1;
+      off[a][2] = 0;
+    } else {
+      nb[a] = 1;
+      off[a][0] = off[a][1] = off[a][2] = 0;
+    }
+  }
+  for (int w = wid; w < count; w += nw) {
+    const int i = list ? list[w] : w;
+    const Rec a = rec[i];
+    const int cx = cell_coord(a.x, G.inv_h[0], G.nc[0]);
+    const int cy = cell_coord(a.y, G.inv_h[1], G.nc[1]);
+    const int cz = cell_coord(a.z, G.inv_h[2], G.nc[2]);
+    double bt = INFINITY;
+    int bo = 0x7fffffff, bj = -1;
+    for (int kz = 0; kz < nb[2]; ++kz)
+      for (int ky = 0; ky < nb[1]; ++ky)
+        for (int kx = 0; kx < nb[0]; ++kx) {
+          const int x = (cx + off[0][kx] + G.nc[0]) % G.nc[0];
+          const int y = (cy + off[1][ky] + G.nc[1]) % G.nc[1];
+          const int z = (cz + off[2][kz] + G.nc[2]) % G.nc[2];
+          const int q = (z * G.nc[1] + y) * G.nc[0] + x;
+          const int s0 = start[q], s1 = start[q + 1];
+          for (int j = s0 + lane; j < s1; j += WAVE) {
+            if (j == i) continue;
+            if (status && status[j] == ST_COLLIDED) continue;
+            const Rec b = rec[j];
+            double t;
+            if (pair_time(a, b, G, dt, t)) {
+              const int o = perm[j];
+              if (t < bt || (t == bt && o < bo)) {
+                bt = t;
+                bo = o;
+                bj = j;
+              }
+            }
+          }
+        }
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+      const double t2 = __shfl_xor(bt, o);
+      const int o2 = __shfl_xor(bo, o);
+      const int j2 = __shfl_xor(bj, o);
+      if (t2 < bt || (t2 == bt && o2 < bo)) {
+        bt = t2;
+        bo = o2;
+        bj = j2;
+      }
+    }
+    if (lane == 0) {
+      key_j[i] = bj;
+      key_t[i] = bt;
+    }
+  }
+}
+
+hipError_t launch_gather_exact(hipStream_t s, const int *list, int nlist, const Rec *rec,
+                               const int *start, const Grid &G, double dt, const uint8_t *status,
+                               const int *perm, int *key_j, double *key_t,
+                               const unsigned int *nlist_dev) {
+  int64_t waves = nlist_dev ? 8192 : nlist;
+  if (waves <= 0) return hipSuccess;
+  if (waves > 8192) waves = 8192;
+  const int blocks = (int)((waves + 3) / 4);
+  hipLaunchKernelGGL(k_gather_exact, dim3(blocks), dim3(256), 0, s, list, nlist, nlist_dev, rec,
+                     start, G, dt, status, perm, key_j, key_t);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- a6: mutual resolve
+
+// One sweep of rule 3-4 over the listed sorted spheres (all when list is NULL).
+// A sphere whose partner has it as partner resolves its own side of the pair
+// from the start-of-step records and writes its end-of-step state to the
+// caller's arrays (Sec. "Inter-Particle Collisions"; eq. update_vel, update_rho).
+// Others stay active; those whose partner collides this sweep are queued for a
+// new partner search.  Spheres without a partner become free for the step.
+__global__ __launch_bounds__(256) void k_resolve_sweep(const int *list, int nlist,
+                                                       const Rec *rec, Grid G, double dt,
+                                                       double e, const int *key_j,
+                                                       const double *key_t, uint8_t *status,
+                                                       const int *perm, Particles P,
+                                                       int *partner_out, double *tcoll_out,
+                                                       int *next_list, int *dirty_list,
+                                                       SweepCounters *ctr) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  bool wait = false, dirty = false;
+  unsigned long long npair = 0ull;
+  int i = -1;
+  if (idx < nlist) {
+    i = list ? list[idx] : idx;
+    if (status[i] == ST_ACTIVE) {
+      const int p = key_j[i];
+      if (p < 0) {
+        status[i] = ST_FREE;
+      } else {
+        const int q = key_j[p];
+        if (q == i) {
+          const Rec a = rec[i], b = rec[p];
+          const double t = key_t[i];
+          double xo[3], vo[3];
+          resolve_one(a, b, G, t, dt, e, xo, vo);
+          const int o = perm[i];
+          P.x[o] = xo[0];
+          P.y[o] = xo[1];
+          P.z[o] = xo[2];
+          P.vx[o] = vo[0];
+          P.vy[o] = vo[1];
+          P.vz[o] = vo[2];
+          partner_out[o] = perm[p];
+          tcoll_out[o] = t;
+          status[i] = ST_COLLIDED;
+          if (i < p) npair = 1ull;
+        } else {
+          wait = true;
+          dirty = q >= 0 && key_j[q] == p;  // p pairs with q this sweep
+        }
+      }
+    }
+  }
+  const unsigned int kn = wave_append(wait, &ctr->n_next);
+  if (wait) next_list[kn] = i;
+  const unsigned int kd = wave_append(dirty, &ctr->n_dirty);
+  if (dirty) dirty_list[kd] = i;
+  npair = wave_sum(npair);
+  if (__lane_id() == 0 && npair) atomicAdd(&ctr->pairs, npair);
+}
+
+hipError_t launch_resolve_sweep(hipStream_t s, const int *list, int nlist, const Rec *rec,
+                                const Grid &G, double dt, double e, const int *key_j,
+                                const double *key_t, uint8_t *status, const int *perm,
+                                const Particles &P, int *partner_out, double *tcoll_out,
+                                int *next_list, int *dirty_list, SweepCounters *ctr) {
+  if (nlist <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_resolve_sweep, dim3((nlist + 255) / 256), dim3(256), 0, s, list, nlist,
+                     rec, G, dt, e, key_j, key_t, status, perm, P, partner_out, tcoll_out,
+                     next_list, dirty_list, ctr);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- a8: free flight + wrap
+
+// rule 5: spheres that did not collide fly the whole step; coalesced over the
+// caller's order.
+__global__ __launch_bounds__(256) void k_advance(Particles P, const int *partner, double dt,
+                                                 double L0, double L1, double L2) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= P.n || partner[i] >= 0) return;
+  P.x[i] = wrap_pos(P.x[i] + dt * P.vx[i], L0);
+  P.y[i] = wrap_pos(P.y[i] + dt * P.vy[i], L1);
+  P.z[i] = wrap_pos(P.z[i] + dt * P.vz[i], L2);
+}
+
+hipError_t launch_advance(hipStream_t s, const Particles &P, const int *partner, double dt,
+                          const double L[3]) {
+  if (P.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_advance, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, s, P, partner,
+                     dt, L[0], L[1], L[2]);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- public single-sweep API
+
+// caller active mask -> sorted status (inactive = excluded like collided) and
+// the list of active sorted spheres
+__global__ __launch_bounds__(256) void k_status_from_active(const uint8_t *active,
+                                                            const int *perm, int n,
+                                                            uint8_t *status, int *list,
+                                                            unsigned int *nlist) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  bool act = false;
+  if (i < n) {
+    act = active ? active[perm[i]] != 0 : true;
+    status[i] = act ? ST_ACTIVE : ST_COLLIDED;
+  }
+  const unsigned int k = wave_append(act, nlist);
+  if (act) list[k] = i;
+}
+
+hipError_t launch_status_from_active(hipStream_t s, const uint8_t *active, const int *perm, int n,
+                                     uint8_t *status, int *list, unsigned int *nlist) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_status_from_active, dim3((n + 255) / 256), dim3(256), 0, s, active, perm,
+                     n, status, list, nlist);
+  return hipGetLastError();
+}
+
+// keys in the caller's order: (bits of (float)t) << 32 | caller index of the partner
+__global__ __launch_bounds__(256) void k_export_keys(int n, const int *perm, const int *key_j,
+                                                     const double *key_t, const uint8_t *status,
+                                                     uint64_t *key_out, double *tmin_out) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int o = perm[i];
+  const int j = key_j[i];
+  const bool has = j >= 0 && (!status || status[i] == ST_ACTIVE);
+  uint64_t key = ~0ull;
+  double t = INFINITY;
+  if (has) {
+    t = key_t[i];
+    const float tf = (float)t;
+    key = ((uint64_t)__float_as_uint(tf) << 32) | (uint64_t)(uint32_t)perm[j];
+  }
+  key_out[o] = key;
+  if (tmin_out) tmin_out[o] = t;
+}
+
+hipError_t launch_export_keys(hipStream_t s, int n, const int *perm, const int *key_j,
+                              const double *key_t, const uint8_t *status, uint64_t *key_out,
+                              double *tmin_out) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_export_keys, dim3((n + 255) / 256), dim3(256), 0, s, n, perm, key_j, key_t,
+                     status, key_out, tmin_out);
+  return hipGetLastError();
+}
+
+// rule 3-4 from caller-order keys; start-of-step data from the binned records
+__global__ __launch_bounds__(256) void k_resolve_public(int n, const Rec *rec, const int *rank,
+                                                        Grid G, double dt, double e,
+                                                        const uint64_t *key, Particles P,
+                                                        uint8_t *active, int *partner,
+                                                        double *tcoll, long long *npairs) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  unsigned long long np = 0ull;
+  if (i < n && active[i] != 0 && key[i] != ~0ull) {
+    const int p = (int)(uint32_t)(key[i] & 0xffffffffull);
+    if (p >= 0 && p < n && p != i && key[p] != ~0ull &&
+        (int)(uint32_t)(key[p] & 0xffffffffull) == i) {
+      const Rec a = rec[rank[i]], b = rec[rank[p]];
+      double t;
+      if (pair_time(a, b, G, dt, t)) {
+        double xo[3], vo[3];
+        resolve_one(a, b, G, t, dt, e, xo, vo);
+        P.x[i] = xo[0];
+        P.y[i] = xo[1];
+        P.z[i] = xo[2];
+        P.vx[i] = vo[0];
+        P.vy[i] = vo[1];
+        P.vz[i] = vo[2];
+        active[i] = 0;
+        if (partner) partner[i] = p;
+        if (tcoll) tcoll[i] = t;
+        if (i < p) np = 1ull;
+      }
+    }
+  }
+  np = wave_sum(np);
+  if (__lane_id() == 0 && np && npairs) atomicAdd((unsigned long long *)npairs, np);
+}
+
+hipError_t launch_resolve_public(hipStream_t s, int n, const Rec *rec, const int *rank,
+                                 const Grid &G, double dt, double e, const uint64_t *key,
+                                 const Particles &P, uint8_t *active, int *partner, double *tcoll,
+                                 long long *npairs) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_resolve_public, dim3((n + 255) / 256), dim3(256), 0, s, n, rec, rank, G,
+                     dt, e, key, P, active, partner, tcoll, npairs);
+  return hipGetLastError();
+}
+
+}  // namespace pcol

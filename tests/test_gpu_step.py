@@ -1,0 +1,250 @@
+"""GPU parity of the HIP collision step against the FP64 oracle (needs an MI355X).
+
+Bar: pair sets (partner per sphere) bit-exact, contact times bitwise equal, and
+post-collision positions and velocities within 1e-12 relative; the rule fixes
+every binary64 operation, so the states are expected to agree bitwise as well
+and a dedicated test asserts that.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from tests.gpu_helpers import FIELDS, box_slice, compare_step, gpu_step
+
+pytestmark = pytest.mark.gpu
+
+pc = pytest.importorskip("paper_2501_05340_amd")
+
+
+def _announce(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def cfg2():
+    return workloads.config(2)
+
+
+@pytest.fixture(scope="module")
+def poly20k():
+    # the 16M recipe (lognormal radii, phi 0.3, e 0.8) at 20k spheres: 8^3 cells
+    return workloads.make_box(20000, seed=13, phi=0.3, lognormal=(1.0, 0.25, 0.5, 2.0), e=0.8)
+
+
+def test_step_config1_bitwise():
+    box = workloads.config(1)
+    _announce(f"config1 n={box.n}")
+    gpu = gpu_step(box)
+    orc = oracle.step(box)
+    assert orc.n_pairs > 50
+    assert compare_step(box, gpu, orc) == 0
+    st = gpu[3]
+    assert st["n_pairs"] == orc.n_pairs and st["n_sweeps"] == orc.n_sweeps
+
+
+def test_step_config2_1M(cfg2):
+    _announce(f"config2 n={cfg2.n}")
+    gpu = gpu_step(cfg2)
+    orc = oracle.step(cfg2)
+    nonbit = compare_step(cfg2, gpu, orc)
+    assert nonbit == 0
+    st = gpu[3]
+    assert st["n_pairs"] == orc.n_pairs and st["n_sweeps"] == orc.n_sweeps
+    assert st["pair_tests"] > 0 and st["contacts"] >= orc.n_pairs
+
+
+@pytest.mark.parametrize("n", [20000, 19963, 4097, 65])
+def test_step_polydisperse_tiles_and_ragged(poly20k, n):
+    box = box_slice(poly20k, n)
+    _announce(f"poly n={n}")
+    gpu = gpu_step(box)
+    orc = oracle.step(box)
+    assert compare_step(box, gpu, orc) == 0
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4])
+@pytest.mark.parametrize("mono", [True, False])
+def test_step_small_box_fewer_than_three_cells(seed, mono):
+    if mono:
+        box = workloads.make_box(250, seed=seed, phi=0.3, radius=0.5, e=0.85, dt=0.25)
+    else:
+        box = workloads.make_box(250, seed=seed, phi=0.3, lognormal=(0.5, 0.3, 0.25, 1.0), e=0.85,
+                                 dt=0.2)
+    _announce(f"small box seed={seed} mono={mono}")
+    gpu = gpu_step(box)
+    assert min(gpu[3]["nc"]) < 3
+    orc = oracle.step(box)
+    assert orc.n_sweeps >= 3
+    assert compare_step(box, gpu, orc) == 0
+
+
+@pytest.mark.parametrize("e", [0.0, 1.0])
+def test_step_restitution_limits(poly20k, e):
+    box = box_slice(poly20k, 8000)
+    box.e = e
+    gpu = gpu_step(box)
+    orc = oracle.step(box)
+    assert compare_step(box, gpu, orc) == 0
+
+
+@pytest.mark.parametrize("n", [0, 1, 2])
+def test_step_degenerate_sizes(n):
+    base = workloads.Box(np.array([1.0, 4.0]), np.array([2.0, 2.0]), np.array([2.0, 2.0]),
+                         np.array([0.5, -0.5]), np.zeros(2), np.zeros(2), np.array([0.5, 0.5]),
+                         np.ones(2), (10.0, 10.0, 10.0), 3.0, 0.7)
+    box = box_slice(base, n)
+    gpu = gpu_step(box)
+    orc = oracle.step(box)
+    assert compare_step(box, gpu, orc) == 0
+    if n == 2:
+        assert gpu[1].tolist() == [1, 0] and gpu[2][0] == 2.0
+
+
+def test_two_sphere_periodic_case_multistep():
+    """The paper's two-sphere validation inputs, stepped on the GPU and the oracle in
+    lockstep; the contact happens through the periodic y boundary in step 40."""
+    L = (2.2, 2.2, 2.2)
+    box = workloads.Box(np.array([1.08, 1.117]), np.array([0.6, 1.6]), np.array([1.1, 1.1]),
+                        np.array([0.0, 0.0]), np.array([-15.0, 15.0]), np.zeros(2),
+                        np.array([0.02, 0.02]), np.ones(2), L, 1e-3, 1.0)
+    hit = None
+    for k in range(45):
+        gpu = gpu_step(box)
+        orc = oracle.step(box)
+        assert compare_step(box, gpu, orc) == 0
+        if orc.n_pairs and hit is None:
+            hit = k
+        out = gpu[0]
+        box = workloads.Box(out["x"], out["y"], out["z"], out["vx"], out["vy"], out["vz"], box.r,
+                            box.m, L, box.dt, 1.0)
+    assert hit == 39
+
+
+def test_detect_keys_all_active_and_masked(poly20k):
+    box = poly20k
+    p = pc.Particles.from_box(box)
+    ctx = pc.Context(box.n)
+    pc.pcol_bin(ctx, p, box.L, box.dt)
+    key, tmin = pc.pcol_detect(ctx, p, box.L, box.dt)
+    torch.cuda.synchronize()
+    key = key.cpu().numpy().view(np.uint64)
+    tmin = tmin.cpu().numpy()
+    op, ot, _ = oracle.earliest(box)
+    has = op >= 0
+    assert np.array_equal(key == np.uint64(2 ** 64 - 1), ~has)
+    assert np.array_equal((key[has] & np.uint64(0xFFFFFFFF)).astype(np.int64), op[has])
+    f32 = ot[has].astype(np.float32).view(np.uint32).astype(np.uint64)
+    assert np.array_equal(key[has] >> np.uint64(32), f32)
+    assert np.array_equal(tmin, ot)
+    # a random active mask (exact neighbourhood search path)
+    act = (np.random.default_rng(3).random(box.n) < 0.6).astype(np.uint8)
+    key2, tmin2 = pc.pcol_detect(ctx, p, box.L, box.dt, active=torch.from_numpy(act).cuda())
+    torch.cuda.synchronize()
+    op2, ot2, _ = oracle.earliest(box, active=act)
+    key2 = key2.cpu().numpy().view(np.uint64)
+    has2 = op2 >= 0
+    assert np.array_equal((key2[has2] & np.uint64(0xFFFFFFFF)).astype(np.int64), op2[has2])
+    assert np.all(key2[~has2] == np.uint64(2 ** 64 - 1))
+    assert np.array_equal(tmin2.cpu().numpy(), ot2)
+
+
+def test_composed_entry_points_equal_step(poly20k):
+    """pcol_bin, then pcol_detect + pcol_resolve per sweep, then pcol_advance, gives the
+    same result as pcol_step."""
+    box = box_slice(poly20k, 12000)
+    ref = gpu_step(box)
+    p = pc.Particles.from_box(box)
+    ctx = pc.Context(box.n)
+    n = box.n
+    pc.pcol_bin(ctx, p, box.L, box.dt)
+    active = torch.ones(n, dtype=torch.uint8, device="cuda")
+    partner = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    tcoll = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+    npairs = torch.zeros(1, dtype=torch.int64, device="cuda")
+    sweeps = 0
+    while True:
+        key, _ = pc.pcol_detect(ctx, p, box.L, box.dt, active=active)
+        before = int(npairs.item())
+        pc.pcol_resolve(ctx, p, box.L, box.dt, box.e, key, active, partner, tcoll, npairs)
+        sweeps += 1
+        if int(npairs.item()) == before:
+            break
+    pc.pcol_advance(ctx, p, box.L, box.dt, partner)
+    torch.cuda.synchronize()
+    out = {f: getattr(p, f).cpu().numpy() for f in FIELDS}
+    for f in FIELDS:
+        assert np.array_equal(out[f], ref[0][f])
+    assert np.array_equal(partner.cpu().numpy(), ref[1])
+    assert np.array_equal(tcoll.cpu().numpy(), ref[2], equal_nan=True)
+    assert sweeps == ref[3]["n_sweeps"]
+
+
+def test_invariance_cell_size_slots_and_permutation(poly20k):
+    box = box_slice(poly20k, 15000)
+    ref = gpu_step(box)
+    for opts in ({"cell_mult": 1.7}, {"cell_mult": 2.5}, {"contact_slots": 1},
+                 {"contact_slots": 2}):
+        got = gpu_step(box, **opts)
+        for f in FIELDS:
+            assert np.array_equal(got[0][f], ref[0][f]), opts
+        assert np.array_equal(got[1], ref[1]) and np.array_equal(got[2], ref[2], equal_nan=True)
+    perm = np.random.default_rng(9).permutation(box.n)
+    pbox = workloads.Box(*[a[perm].copy() for a in box.arrays()], box.L, box.dt, box.e)
+    got = gpu_step(pbox)
+    inv = np.argsort(perm)
+    for f in FIELDS:
+        assert np.array_equal(got[0][f][inv], ref[0][f])
+    mapped = np.where(got[1] >= 0, perm[np.maximum(got[1], 0)], -1)[inv]
+    assert np.array_equal(mapped, ref[1])
+
+
+def test_determinism_rerun(cfg2):
+    a = gpu_step(cfg2)
+    b = gpu_step(cfg2)
+    for f in FIELDS:
+        assert np.array_equal(a[0][f].view(np.uint64), b[0][f].view(np.uint64))
+    assert np.array_equal(a[1], b[1])
+
+
+def test_error_codes_leave_inputs_unchanged():
+    box = workloads.config(1)
+    ctx = pc.Context(box.n)
+
+    def expect(code, mutate=None, dt=None, e=None, **kw):
+        b = box.copy()
+        if mutate:
+            mutate(b)
+        p = pc.Particles.from_box(b)
+        before = [t.clone() for t in p.tensors()]
+        with pytest.raises(pc.PcolError) as ei:
+            pc.pcol_step(ctx, p, b.L, b.dt if dt is None else dt, b.e if e is None else e)
+        assert ei.value.code == code
+        if code != pc.PCOL_E_SWEEPS:
+            for t0, t1 in zip(before, p.tensors()):
+                assert torch.equal(t0, t1)
+
+    expect(pc.PCOL_E_INVALID, lambda b: b.vx.__setitem__(3, np.nan))
+    expect(pc.PCOL_E_INVALID, lambda b: b.r.__setitem__(4, 0.0))
+    expect(pc.PCOL_E_INVALID, lambda b: b.m.__setitem__(5, -1.0))
+    expect(pc.PCOL_E_INVALID, lambda b: b.x.__setitem__(6, b.L[0]))
+    expect(pc.PCOL_E_INVALID, lambda b: b.z.__setitem__(7, -1e-300))
+    expect(pc.PCOL_E_INVALID, e=1.5)
+    expect(pc.PCOL_E_INVALID, dt=-1.0)
+    expect(pc.PCOL_E_BOX, dt=0.2)
+    ctx2 = pc.Context(box.n, pc.pcol_default_opts(max_sweeps=1))
+    p = pc.Particles.from_box(box)
+    with pytest.raises(pc.PcolError) as ei:
+        pc.pcol_step(ctx2, p, box.L, box.dt, box.e)
+    assert ei.value.code == pc.PCOL_E_SWEEPS
+    # detect before any bin, and n above n_max
+    ctx3 = pc.Context(box.n)
+    p = pc.Particles.from_box(box)
+    with pytest.raises(pc.PcolError) as ei:
+        pc.pcol_detect(ctx3, p, box.L, box.dt)
+    assert ei.value.code == pc.PCOL_E_STATE
+    small = pc.Context(10)
+    with pytest.raises(pc.PcolError) as ei:
+        pc.pcol_step(small, p, box.L, box.dt, box.e)
+    assert ei.value.code == pc.PCOL_E_INVALID
