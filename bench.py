@@ -5,8 +5,9 @@ log-sd 0.25, clamped to [0.5, 2], m = r^3) at volume fraction 0.3 in a periodic
 cube, N(0, 1) velocities, e = 0.8, dt = 0.4; seeded random sequential
 placement.  A step is the whole path: validation and reach, binning, the
 pair-test sweep, partner selection and resolve sweeps until none is left, free
-flight and wrap.  Steps run back to back on the evolving state (inputs resident
-in HBM).
+flight and wrap.  Every timed step starts from the configured input: the
+positions and velocities are restored from a device copy (inside the timed
+region) before each step, so each step processes the same batch.
 
 Prints one JSON line: particles stepped per second (value), pair tests per
 second of the detect kernel, the detect kernel's ALU roofline fraction, and the
@@ -91,14 +92,21 @@ def main():
     ctx = pc.Context(box.n, opts)
     partner = torch.empty(box.n, dtype=torch.int32, device="cuda")
     tcoll = torch.empty(box.n, dtype=torch.float64, device="cuda")
+    p0 = p.clone()
+
+    def restore():
+        for t, t0 in zip(p.tensors()[:6], p0.tensors()[:6]):
+            t.copy_(t0)
 
     for k in range(args.warmup):
+        restore()
         st = pc.pcol_step(ctx, p, box.L, box.dt, box.e, partner, tcoll)
         log(f"warmup {k}: {st['n_pairs']} pairs, {st['n_sweeps']} sweeps, detect {st['ms_detect']:.3f} ms")
     torch.cuda.synchronize()
     stats = []
     t0 = time.perf_counter()
     for k in range(args.steps):
+        restore()
         stats.append(pc.pcol_step(ctx, p, box.L, box.dt, box.e, partner, tcoll))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0

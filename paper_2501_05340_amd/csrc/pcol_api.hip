@@ -37,10 +37,8 @@ struct pcol_ctx {
   int *key_j = nullptr;
   double *key_t = nullptr;
   uint8_t *status = nullptr;
-  int *list_a = nullptr;
-  int *list_b = nullptr;
-  int *dirty = nullptr;
   int *ovf = nullptr;
+  OutRec *out = nullptr;
   int *partner_tmp = nullptr;
   double *tcoll_tmp = nullptr;
   ReachOut *reach_d = nullptr;
@@ -152,8 +150,8 @@ void pcol_destroy(pcol_ctx *ctx) {
   if (!ctx) return;
   void *dev[] = {ctx->rec,    ctx->perm,   ctx->rank,   ctx->cid,         ctx->slot,
                  ctx->count,  ctx->start,  ctx->blocksum, ctx->cnt,      ctx->slot_t,
-                 ctx->slot_j, ctx->key_j,  ctx->key_t,  ctx->status,      ctx->list_a,
-                 ctx->list_b, ctx->dirty,  ctx->ovf,    ctx->partner_tmp, ctx->tcoll_tmp,
+                 ctx->slot_j, ctx->key_j,  ctx->key_t,  ctx->status,      ctx->out,
+                 ctx->ovf,    ctx->partner_tmp, ctx->tcoll_tmp,
                  ctx->reach_d, ctx->ctr_d, ctx->tests_d};
   for (void *p : dev)
     if (p) (void)hipFree(p);
@@ -198,9 +196,7 @@ pcol_status pcol_create(pcol_ctx **out, int64_t n_max, void *hip_stream, const p
   A(dalloc(&ctx->key_j, n));
   A(dalloc(&ctx->key_t, n));
   A(dalloc(&ctx->status, n));
-  A(dalloc(&ctx->list_a, n));
-  A(dalloc(&ctx->list_b, n));
-  A(dalloc(&ctx->dirty, n));
+  A(dalloc(&ctx->out, n));
   A(dalloc(&ctx->ovf, n));
   A(dalloc(&ctx->partner_tmp, n));
   A(dalloc(&ctx->tcoll_tmp, n));
@@ -305,12 +301,11 @@ static pcol_status check_binned(pcol_ctx *ctx, const pcol_particles *p, const pc
   return PCOL_OK;
 }
 
-// keys of all spheres over the active set into ctx->key_j / key_t (sorted order);
-// status must describe the active set.  all_active selects the half-stencil path.
-static pcol_status detect_all(pcol_ctx *ctx, double dt, bool all_active, int nact) {
+// sweep 1: keys of all spheres (all active) into ctx->key_j / key_t (sorted order)
+static pcol_status detect_all(pcol_ctx *ctx, double dt) {
   hipStream_t s = ctx->stream;
   const int n = (int)ctx->binned_n;
-  if (all_active && !ctx->small) {
+  if (!ctx->small) {
     DetectArgs A{};
     A.rec = ctx->rec;
     A.start = ctx->start;
@@ -318,6 +313,7 @@ static pcol_status detect_all(pcol_ctx *ctx, double dt, bool all_active, int nac
     A.slot_t = ctx->slot_t;
     A.slot_j = ctx->slot_j;
     A.ctr = ctx->ctr_d;
+    A.n = n;
     A.G = ctx->G;
     A.dt = dt;
     A.dt2 = 2.0 * dt * (1.0 + 0x1.0p-20);
@@ -329,18 +325,25 @@ static pcol_status detect_all(pcol_ctx *ctx, double dt, bool all_active, int nac
     PCOL_HIP(launch_detect_half(s, A));
     if (ctx->opts.timing) PCOL_HIP(hipEventRecord(ctx->ev[6], s));
     ctx->detect_timed = true;
-    PCOL_HIP(launch_slot_min(s, nullptr, n, ctx->cnt, ctx->slot_t, ctx->slot_j, ctx->K, nullptr,
+    PCOL_HIP(launch_slot_min(s, n, 1, ctx->cnt, ctx->slot_t, ctx->slot_j, ctx->K, ctx->status,
                              ctx->perm, ctx->key_j, ctx->key_t, ctx->ovf, ctx->ctr_d));
-    PCOL_HIP(launch_gather_exact(s, ctx->ovf, 0, ctx->rec, ctx->start, ctx->G, dt, nullptr,
-                                 ctx->perm, ctx->key_j, ctx->key_t, &ctx->ctr_d->n_overflow));
+    PCOL_HIP(launch_gather_exact(s, ctx->ovf, 0, &ctx->ctr_d->n_overflow, -1, ctx->rec, ctx->start,
+                                 ctx->G, dt, ctx->status, ctx->perm, ctx->key_j, ctx->key_t));
   } else {
-    // exact search for every active sphere (lists built by the caller)
-    PCOL_HIP(launch_fill_i32(s, ctx->key_j, -1, n));
-    PCOL_HIP(launch_gather_exact(s, all_active ? nullptr : ctx->list_a, nact, ctx->rec, ctx->start,
-                                 ctx->G, dt, ctx->status, ctx->perm, ctx->key_j, ctx->key_t,
-                                 nullptr));
+    // fewer than 3 cells on some axis: exact search for every sphere
+    PCOL_HIP(launch_gather_exact(s, nullptr, n, nullptr, -1, ctx->rec, ctx->start, ctx->G, dt,
+                                 ctx->status, ctx->perm, ctx->key_j, ctx->key_t));
   }
   return PCOL_OK;
+}
+
+static void sum_counters(const SweepCounters &c, unsigned long long &pairs,
+                         unsigned long long &contacts) {
+  pairs = contacts = 0ull;
+  for (int k = 0; k < NSHARD; ++k) {
+    pairs += c.shard[k].pairs;
+    contacts += c.shard[k].contacts;
+  }
 }
 
 pcol_status pcol_detect(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box, double dt,
@@ -355,15 +358,12 @@ pcol_status pcol_detect(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *
   PCOL_HIP(hipMemsetAsync(ctx->ctr_d, 0, sizeof(SweepCounters), s));
   if (!active) {
     PCOL_HIP(launch_fill_u8(s, ctx->status, ST_ACTIVE, n));
-    if ((st = detect_all(ctx, dt, true, n)) != PCOL_OK) return st;
+    if ((st = detect_all(ctx, dt)) != PCOL_OK) return st;
   } else {
-    PCOL_HIP(launch_status_from_active(s, active, ctx->perm, n, ctx->status, ctx->list_a,
-                                       &ctx->ctr_d->n_next));
-    // the list length is only known on the device: search over the whole list
-    // buffer bound, idle waves exit on the device count
+    PCOL_HIP(launch_status_from_active(s, active, ctx->perm, n, ctx->status));
     PCOL_HIP(launch_fill_i32(s, ctx->key_j, -1, n));
-    PCOL_HIP(launch_gather_exact(s, ctx->list_a, 0, ctx->rec, ctx->start, ctx->G, dt, ctx->status,
-                                 ctx->perm, ctx->key_j, ctx->key_t, &ctx->ctr_d->n_next));
+    PCOL_HIP(launch_gather_exact(s, nullptr, n, nullptr, ST_ACTIVE, ctx->rec, ctx->start, ctx->G,
+                                 dt, ctx->status, ctx->perm, ctx->key_j, ctx->key_t));
   }
   PCOL_HIP(launch_export_keys(s, n, ctx->perm, ctx->key_j, ctx->key_t, ctx->status, key_out,
                               tmin_out));
@@ -410,54 +410,44 @@ pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, dou
   unsigned long long contacts = 0ull;
   double ms_detect = 0.0;
   if (n > 0) {
-    PCOL_HIP(launch_fill_i32(s, part, -1, n));
-    PCOL_HIP(launch_fill_f64(s, tc, NAN, n));
     PCOL_HIP(launch_fill_u8(s, ctx->status, ST_ACTIVE, n));
     PCOL_HIP(hipMemsetAsync(ctx->ctr_d, 0, sizeof(SweepCounters), s));
     // sweep 1: every contact within dt, then the earliest partner of each sphere
     ctx->detect_timed = false;
-    if ((st = detect_all(ctx, dt, true, n)) != PCOL_OK) return st;
+    if ((st = detect_all(ctx, dt)) != PCOL_OK) return st;
     if (timing) PCOL_HIP(hipEventRecord(ctx->ev[2], s));
-    int *act = ctx->list_a, *nxt = ctx->list_b;
-    int nact = n;
-    const int *cur_list = nullptr;  // sweep 1 visits every sphere
     for (;;) {
-      PCOL_HIP(launch_resolve_sweep(s, cur_list, nact, ctx->rec, ctx->G, dt, e, ctx->key_j,
-                                    ctx->key_t, ctx->status, ctx->perm, P, part, tc, nxt,
-                                    ctx->dirty, ctx->ctr_d));
+      PCOL_HIP(launch_resolve_sweep(s, n, ctx->rec, ctx->G, dt, e, ctx->key_j, ctx->key_t,
+                                    ctx->status, ctx->perm, ctx->out, ctx->ctr_d));
       PCOL_HIP(hipMemcpyAsync(ctx->ctr_h, ctx->ctr_d, sizeof(SweepCounters),
                               hipMemcpyDeviceToHost, s));
       PCOL_HIP(hipStreamSynchronize(s));
-      const SweepCounters c = *ctx->ctr_h;
-      if (sweeps == 0) contacts = c.contacts / 2ull;
-      ovf_total += c.n_overflow;
+      unsigned long long sp, sc;
+      sum_counters(*ctx->ctr_h, sp, sc);
+      if (sweeps == 0) contacts = sc / 2ull;
+      ovf_total += ctx->ctr_h->n_overflow;
       ++sweeps;
-      pairs += (int64_t)c.pairs;
-      if (c.pairs == 0ull) break;
+      pairs += (int64_t)sp;
+      if (sp == 0ull) break;
       if (ctx->opts.max_sweeps > 0 && sweeps >= ctx->opts.max_sweeps)
         return fail(ctx, PCOL_E_SWEEPS, "sweep cap reached with pairs still resolving");
-      // next sweep: new partners for spheres whose partner collided elsewhere
-      const int ndirty = (int)c.n_dirty;
-      nact = (int)c.n_next;
+      // next sweep: new partners for DIRTY spheres (partner collided elsewhere)
       PCOL_HIP(hipMemsetAsync(ctx->ctr_d, 0, sizeof(SweepCounters), s));
       if (!ctx->small) {
-        PCOL_HIP(launch_slot_min(s, ctx->dirty, ndirty, ctx->cnt, ctx->slot_t, ctx->slot_j, ctx->K,
-                                 ctx->status, ctx->perm, ctx->key_j, ctx->key_t, ctx->ovf,
-                                 ctx->ctr_d));
-        PCOL_HIP(launch_gather_exact(s, ctx->ovf, 0, ctx->rec, ctx->start, ctx->G, dt,
-                                     ctx->status, ctx->perm, ctx->key_j, ctx->key_t,
-                                     &ctx->ctr_d->n_overflow));
+        PCOL_HIP(launch_slot_min(s, n, 0, ctx->cnt, ctx->slot_t, ctx->slot_j, ctx->K, ctx->status,
+                                 ctx->perm, ctx->key_j, ctx->key_t, ctx->ovf, ctx->ctr_d));
+        PCOL_HIP(launch_gather_exact(s, ctx->ovf, 0, &ctx->ctr_d->n_overflow, -1, ctx->rec,
+                                     ctx->start, ctx->G, dt, ctx->status, ctx->perm, ctx->key_j,
+                                     ctx->key_t));
       } else {
-        PCOL_HIP(launch_gather_exact(s, ctx->dirty, ndirty, ctx->rec, ctx->start, ctx->G, dt,
-                                     ctx->status, ctx->perm, ctx->key_j, ctx->key_t, nullptr));
+        PCOL_HIP(launch_gather_exact(s, nullptr, n, nullptr, ST_DIRTY, ctx->rec, ctx->start,
+                                     ctx->G, dt, ctx->status, ctx->perm, ctx->key_j,
+                                     ctx->key_t));
       }
-      int *tmp = act;
-      act = nxt;
-      nxt = tmp;
-      cur_list = act;
     }
     if (timing) PCOL_HIP(hipEventRecord(ctx->ev[3], s));
-    PCOL_HIP(launch_advance(s, P, part, dt, box->len));
+    PCOL_HIP(launch_advance_sorted(s, n, ctx->rec, ctx->status, dt, ctx->G, ctx->out));
+    PCOL_HIP(launch_unpermute(s, P, ctx->rank, ctx->out, part, tc));
     if (timing) {
       PCOL_HIP(hipEventRecord(ctx->ev[4], s));
       PCOL_HIP(hipEventSynchronize(ctx->ev[4]));

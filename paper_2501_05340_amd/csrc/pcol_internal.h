@@ -15,8 +15,18 @@ struct alignas(16) Rec {
   double vx, vy, vz, m;
 };
 
-// Sphere status during a step.
-enum : uint8_t { ST_ACTIVE = 0, ST_FREE = 1, ST_COLLIDED = 2 };
+// Sphere status during a step: ACTIVE has a valid partner key (or none yet),
+// DIRTY is active but its partner collided with another sphere, so its key
+// must be recomputed; FREE has no contact left in the step; COLLIDED is done.
+enum : uint8_t { ST_ACTIVE = 0, ST_FREE = 1, ST_COLLIDED = 2, ST_DIRTY = 3 };
+
+// End-of-step state of one sphere in cell-sorted order (64 B), copied to the
+// caller's order by a final gather.
+struct alignas(16) OutRec {
+  double x, y, z, vx, vy, vz, t;
+  int partner;  // caller index, -1 = none
+  int pad;
+};
 
 // Uniform grid over the periodic box.  Cells are numbered (cz * nc1 + cy) * nc0 + cx,
 // so the cells of one x-row are consecutive and so are their spheres after sorting.
@@ -36,16 +46,21 @@ struct ReachOut {
   unsigned int maxcell;      // filled by the scan
 };
 
-// Per-sweep counters the host reads back.
+// Per-sweep counters the host reads back.  Sums are spread over NSHARD
+// counters on separate 128-B lines (one atomic per workgroup on shard
+// blockIdx % NSHARD), so no single address takes an atomic per wave.
+constexpr int NSHARD = 64;
+struct alignas(128) CounterShard {
+  unsigned long long pairs;     // pairs resolved this sweep
+  unsigned long long contacts;  // contacts found (each counted from both spheres)
+  unsigned long long recheck;   // FP32 filter survivors rechecked in FP64
+  unsigned long long pad[13];
+};
 struct SweepCounters {
-  unsigned long long pairs;       // pairs resolved this sweep
-  unsigned long long pair_tests;  // unordered pairs tested geometrically
-  unsigned long long contacts;    // unordered contacts found
-  unsigned long long recheck;     // FP32 filter survivors rechecked in FP64
-  unsigned int n_next;            // spheres still waiting for a partner
-  unsigned int n_dirty;           // spheres whose partner collided with another sphere
-  unsigned int n_overflow;        // spheres with more contacts than slots
-  unsigned int pad;
+  CounterShard shard[NSHARD];
+  unsigned int n_overflow;  // spheres with more contacts than slots (list length)
+  unsigned int n_list;      // length of a list built on the device (public detect)
+  unsigned int pad[30];
 };
 
 // ---------------------------------------------------------------- the rule
@@ -143,6 +158,7 @@ struct DetectArgs {
   double *slot_t;     // [n * K]
   int *slot_j;        // [n * K]
   SweepCounters *ctr;
+  int n;              // spheres (slot arrays are k-major: slot[k * n + i])
   Grid G;
   double dt;
   double dt2;         // 2 dt (1 + 2^-20): conservative bound for the cheap reject
@@ -165,22 +181,24 @@ hipError_t launch_scatter(hipStream_t s, const Particles &P, const int *cid, con
 hipError_t launch_detect_half(hipStream_t s, const DetectArgs &A);
 hipError_t launch_count_pairs(hipStream_t s, const int *start, const Grid &G,
                               unsigned long long *out);
-hipError_t launch_slot_min(hipStream_t s, const int *list, int nlist, const int *cnt,
-                           const double *slot_t, const int *slot_j, int K, const uint8_t *status,
-                           const int *perm, int *key_j, double *key_t, int *ovf_list,
-                           SweepCounters *ctr);
-hipError_t launch_gather_exact(hipStream_t s, const int *list, int nlist, const Rec *rec,
-                               const int *start, const Grid &G, double dt, const uint8_t *status,
-                               const int *perm, int *key_j, double *key_t, const unsigned int *nlist_dev);
-hipError_t launch_resolve_sweep(hipStream_t s, const int *list, int nlist, const Rec *rec,
-                                const Grid &G, double dt, double e, const int *key_j,
-                                const double *key_t, uint8_t *status, const int *perm,
-                                const Particles &P, int *partner_out, double *tcoll_out,
-                                int *next_list, int *dirty_list, SweepCounters *ctr);
+hipError_t launch_slot_min(hipStream_t s, int n, int first, const int *cnt, const double *slot_t,
+                           const int *slot_j, int K, uint8_t *status, const int *perm, int *key_j,
+                           double *key_t, int *ovf_list, SweepCounters *ctr);
+hipError_t launch_gather_exact(hipStream_t s, const int *list, int nlist, const unsigned int *nlist_dev,
+                               int select, const Rec *rec, const int *start, const Grid &G,
+                               double dt, uint8_t *status, const int *perm, int *key_j,
+                               double *key_t);
+hipError_t launch_resolve_sweep(hipStream_t s, int n, const Rec *rec, const Grid &G, double dt,
+                                double e, const int *key_j, const double *key_t, uint8_t *status,
+                                const int *perm, OutRec *out, SweepCounters *ctr);
+hipError_t launch_advance_sorted(hipStream_t s, int n, const Rec *rec, const uint8_t *status,
+                                 double dt, const Grid &G, OutRec *out);
+hipError_t launch_unpermute(hipStream_t s, const Particles &P, const int *rank, const OutRec *out,
+                            int *partner, double *tcoll);
 hipError_t launch_advance(hipStream_t s, const Particles &P, const int *partner, double dt,
                           const double L[3]);
 hipError_t launch_status_from_active(hipStream_t s, const uint8_t *active, const int *perm, int n,
-                                     uint8_t *status, int *list, unsigned int *nlist);
+                                     uint8_t *status);
 hipError_t launch_export_keys(hipStream_t s, int n, const int *perm, const int *key_j,
                               const double *key_t, const uint8_t *status, uint64_t *key_out,
                               double *tmin_out);

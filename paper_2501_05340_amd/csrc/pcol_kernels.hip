@@ -45,6 +45,26 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
   return x * q + (x < r ? x : r) + bid / 8;
 }
 
+// Sum of v over the workgroup added to *target by one atomic (blockDim a
+// multiple of the wave size, at most 1024 threads).
+__device__ __forceinline__ void block_add(unsigned long long v, unsigned long long *target) {
+  __shared__ unsigned long long part[1024 / WAVE];
+  v = wave_sum(v);
+  const int w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+  if (__lane_id() == 0) part[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long tot = 0ull;
+    for (int k = 0; k < nw; ++k) tot += part[k];
+    if (tot) atomicAdd(target, tot);
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ CounterShard &my_shard(SweepCounters *ctr) {
+  return ctr->shard[blockIdx.x % NSHARD];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- fills
@@ -304,9 +324,11 @@ hipError_t launch_scatter(hipStream_t s, const Particles &P, const int *cid, con
 // pair that can touch, the shifted separation equals the minimum image of rule
 // 1 bitwise (the grid has >= 3 cells per axis and cell side >= reach).
 //
-// Cheap reject before the square root: any root t <= dt has
-// c <= 2 |b| dt (1 + 6 eps), so c > -b * dt2 (dt2 = 2 dt (1 + 2^-20)) means no
-// contact.  Spheres that pass go through the full rule.
+// Cheap reject before the square root: t = c / (-b + sqrt(D)) >= c / (2|b|)
+// because sqrt(D) <= |b| when a, c > 0, and with the roundings of rule 1 any
+// kept t <= dt has c <= 2 |b| dt (1 + 6 eps); so c > -b * dt2 with
+// dt2 = 2 dt (1 + 2^-20) means no contact.  Pairs that pass go through the
+// full rule.
 constexpr int MAXRUN = 10;
 
 // records seen through the constant address space: wave-uniform reads of the
@@ -315,11 +337,11 @@ constexpr int MAXRUN = 10;
 typedef __attribute__((address_space(4))) const Rec *crec_ptr;
 
 template <bool SHIFT>
-__device__ __forceinline__ void detect_chunk(const DetectArgs &A, int h0, int h1, int g, bool ok,
-                                             bool own, double sx, double sy, double sz) {
+__device__ __forceinline__ void detect_chunk(const DetectArgs &A, int h0, int h1, int g, int thr,
+                                             double sx, double sy, double sz) {
   const crec_ptr hrec = (crec_ptr)A.rec;
   Rec b;
-  if (ok) {
+  if (thr >= 0) {
     b = A.rec[g];
   } else {
     b.x = b.y = b.z = 0.0;
@@ -351,23 +373,26 @@ __device__ __forceinline__ void detect_chunk(const DetectArgs &A, int h0, int h1
     const double s = ri + b.r;
     const double bb = (d0 * u0 + d1 * u1) + d2 * u2;
     const double cc = ((d0 * d0 + d1 * d1) + d2 * d2) - s * s;
-    const bool valid = ok && (!own || g > i);
-    if (valid && bb < 0.0 && cc > 0.0 && cc <= -bb * dt2) {
+    // lane holds a candidate for this i (thr: -1 none, j for the own cell where only
+    // j > i is tested, INT_MAX otherwise) and the cheap reject passes.  With c > 0,
+    // c <= -b dt2 implies b < 0.
+    if (i < thr && cc <= -bb * dt2) {
       const double aa = (u0 * u0 + u1 * u1) + u2 * u2;
       const double D = bb * bb - aa * cc;
-      if (aa > 0.0 && D >= 0.0) {
+      if (cc > 0.0 && aa > 0.0 && D >= 0.0) {
         const double t = cc / (-bb + __builtin_sqrt(D));
         if (t <= dt) {
           const int K = A.K;
+          const size_t n = (size_t)A.n;
           const int k1 = atomicAdd(&A.cnt[i], 1);
           if (k1 < K) {
-            A.slot_t[(size_t)i * K + k1] = t;
-            A.slot_j[(size_t)i * K + k1] = g;
+            A.slot_t[k1 * n + i] = t;
+            A.slot_j[k1 * n + i] = g;
           }
           const int k2 = atomicAdd(&A.cnt[g], 1);
           if (k2 < K) {
-            A.slot_t[(size_t)g * K + k2] = t;
-            A.slot_j[(size_t)g * K + k2] = i;
+            A.slot_t[k2 * n + g] = t;
+            A.slot_j[k2 * n + g] = i;
           }
         }
       }
@@ -478,11 +503,12 @@ __global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
       }
     }
     const bool own = (code >> 6) & 1;
+    const int thr = !ok ? -1 : (own ? g : 0x7fffffff);
     if (any_shift) {
-      detect_chunk<true>(A, h0, h1, g, ok, own, code_shift(code & 3, G.L[0]),
+      detect_chunk<true>(A, h0, h1, g, thr, code_shift(code & 3, G.L[0]),
                          code_shift((code >> 2) & 3, G.L[1]), code_shift((code >> 4) & 3, G.L[2]));
     } else {
-      detect_chunk<false>(A, h0, h1, g, ok, own, 0.0, 0.0, 0.0);
+      detect_chunk<false>(A, h0, h1, g, thr, 0.0, 0.0, 0.0);
     }
   }
 }
@@ -529,100 +555,92 @@ hipError_t launch_count_pairs(hipStream_t s, const int *start, const Grid &G,
 
 // ---------------------------------------------------------------- a5/a7: partner from contact slots
 
-// Earliest partner of each listed sphere among its recorded contacts whose
-// partner has not collided (rule 2: exact binary64 t, ties to the smaller caller
-// index).  The contact set of a sphere only shrinks over the sweeps of a step,
-// so the slots from the sweep-1 detect are complete for every later sweep.
-// Spheres with more contacts than slots are queued for the exact search.
-__global__ __launch_bounds__(256) void k_slot_min(const int *list, int nlist, const int *cnt,
+// Earliest partner (rule 2: exact binary64 t, ties to the smaller caller index)
+// of each sphere among its recorded contacts whose partner has not collided.
+// The contact set of a sphere only shrinks over the sweeps of a step, so the
+// slots written by the sweep-1 detect are complete for every later sweep.
+// first = 1: every sphere (sweep 1); first = 0: only DIRTY spheres, which
+// become ACTIVE again.  Spheres with more contacts than slots are queued for
+// the exact search (rare; one atomic per wave that has one).  Slots are
+// k-major, so the reads of a wave are coalesced.
+__global__ __launch_bounds__(256) void k_slot_min(int n, int first, const int *cnt,
                                                   const double *slot_t, const int *slot_j, int K,
-                                                  const uint8_t *status, const int *perm,
-                                                  int *key_j, double *key_t, int *ovf_list,
+                                                  uint8_t *status, const int *perm, int *key_j,
+                                                  double *key_t, int *ovf_list,
                                                   SweepCounters *ctr) {
-  const int idx = blockIdx.x * 256 + threadIdx.x;
+  const int i = blockIdx.x * 256 + threadIdx.x;
   bool ovf = false;
-  int i = -1;
   unsigned long long nc = 0ull;
-  if (idx < nlist) {
-    i = list ? list[idx] : idx;
-    const int c = cnt[i];
-    nc = (unsigned long long)c;
-    if (c > K) {
-      ovf = true;
-      key_j[i] = -1;
-      key_t[i] = INFINITY;
-    } else {
-      double bt = INFINITY;
-      int bj = -1;
-      for (int k = 0; k < c; ++k) {
-        const int j = slot_j[(size_t)i * K + k];
-        if (status && status[j] == ST_COLLIDED) continue;
-        const double t = slot_t[(size_t)i * K + k];
-        if (t < bt || (bj >= 0 && t == bt && perm[j] < perm[bj])) {
-          bt = t;
-          bj = j;
+  if (i < n) {
+    const uint8_t st = status[i];
+    if (first ? st == ST_ACTIVE : st == ST_DIRTY) {
+      const int c = cnt[i];
+      nc = (unsigned long long)c;
+      if (c > K) {
+        ovf = true;
+        key_j[i] = -1;
+        key_t[i] = INFINITY;
+      } else {
+        double bt = INFINITY;
+        int bj = -1;
+        for (int k = 0; k < c; ++k) {
+          const int j = slot_j[(size_t)k * n + i];
+          if (!first && status[j] == ST_COLLIDED) continue;
+          const double t = slot_t[(size_t)k * n + i];
+          if (t < bt || (bj >= 0 && t == bt && perm[j] < perm[bj])) {
+            bt = t;
+            bj = j;
+          }
         }
+        key_j[i] = bj;
+        key_t[i] = bt;
       }
-      key_j[i] = bj;
-      key_t[i] = bt;
+      if (!first) status[i] = ST_ACTIVE;
     }
   }
   const unsigned int k = wave_append(ovf, &ctr->n_overflow);
   if (ovf) ovf_list[k] = i;
-  if (!list) {  // the sweep-1 pass also counts the contacts (each stored twice)
-    nc = wave_sum(nc);
-    if (__lane_id() == 0 && nc) atomicAdd(&ctr->contacts, nc);
-  }
+  if (first) block_add(nc, &my_shard(ctr).contacts);
 }
 
-hipError_t launch_slot_min(hipStream_t s, const int *list, int nlist, const int *cnt,
-                           const double *slot_t, const int *slot_j, int K, const uint8_t *status,
-                           const int *perm, int *key_j, double *key_t, int *ovf_list,
-                           SweepCounters *ctr) {
-  if (nlist <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_slot_min, dim3((nlist + 255) / 256), dim3(256), 0, s, list, nlist, cnt,
-                     slot_t, slot_j, K, status, perm, key_j, key_t, ovf_list, ctr);
+hipError_t launch_slot_min(hipStream_t s, int n, int first, const int *cnt, const double *slot_t,
+                           const int *slot_j, int K, uint8_t *status, const int *perm, int *key_j,
+                           double *key_t, int *ovf_list, SweepCounters *ctr) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_slot_min, dim3((n + 255) / 256), dim3(256), 0, s, n, first, cnt, slot_t,
+                     slot_j, K, status, perm, key_j, key_t, ovf_list, ctr);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- exact neighbourhood search
 
-// Earliest partner (rule 2) of listed spheres by an exact search of the 27
-// surrounding cells (distinct cells only when an axis has fewer than 3),
-// minimum image by rule 1.  One wave per sphere; lanes over candidates; the
-// wave reduces (t, caller index) exactly.  Used for spheres whose contacts
-// overflowed the slots, for pcol_detect with an active mask, and for boxes
-// with fewer than 3 cells along some axis.  `status` (nullable) excludes
-// collided spheres.  The list length is read from nlist_dev when given.
+// Earliest partner (rule 2) by an exact search of the 27 surrounding cells
+// (distinct cells only when an axis has fewer than 3), minimum image by rule
+// 1.  One wave per sphere; lanes over candidates; the wave reduces
+// (t, caller index) exactly.  Spheres come from `list` (length nlist, or
+// *nlist_dev when given) or, with list NULL, are all i < nlist whose status is
+// `select` (select < 0: all); selected DIRTY spheres become ACTIVE.  Collided
+// spheres are never candidates.  Used for spheres whose contacts overflowed
+// the slots, for pcol_detect with an active mask, and for grids with fewer
+// than 3 cells along some axis.
 __global__ __launch_bounds__(256) void k_gather_exact(const int *list, int nlist,
-                                                      const unsigned int *nlist_dev,
+                                                      const unsigned int *nlist_dev, int select,
                                                       const Rec *rec, const int *start, Grid G,
-                                                      double dt, const uint8_t *status,
+                                                      double dt, uint8_t *status,
                                                       const int *perm, int *key_j,
                                                       double *key_t) {
   const int lane = __lane_id();
   const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   const int nw = (gridDim.x * blockDim.x) / WAVE;
   const int count = nlist_dev ? (int)*nlist_dev : nlist;
-  int nb[3], off[3][3];
+  int nb[3], lo[3];
   for (int a = 0; a < 3; ++a) {
-    if (G.nc[a] >= 3) {
-      nb[a] = 3;
-      off[a][0] = -1;
-      off[a][1] = 0;
-      off[a][2] = 1;
-    } else if (G.nc[a] == 2) {
-      nb[a] = 2;
-      off[a][0] = 0;
-      off[a][1] = 1;
-      off[a][2] = 0;
-    } else {
-      nb[a] = 1;
-      off[a][0] = off[a][1] = off[a][2] = 0;
-    }
+    nb[a] = G.nc[a] >= 3 ? 3 : G.nc[a];
+    lo[a] = G.nc[a] >= 3 ? -1 : 0;
   }
   for (int w = wid; w < count; w += nw) {
     const int i = list ? list[w] : w;
+    if (!list && select >= 0 && status[i] != (uint8_t)select) continue;
     const Rec a = rec[i];
     const int cx = cell_coord(a.x, G.inv_h[0], G.nc[0]);
     const int cy = cell_coord(a.y, G.inv_h[1], G.nc[1]);
@@ -632,14 +650,14 @@ __global__ __launch_bounds__(256) void k_gather_exact(const int *list, int nlist
     for (int kz = 0; kz < nb[2]; ++kz)
       for (int ky = 0; ky < nb[1]; ++ky)
         for (int kx = 0; kx < nb[0]; ++kx) {
-          const int x = (cx + off[0][kx] + G.nc[0]) % G.nc[0];
-          const int y = (cy + off[1][ky] + G.nc[1]) % G.nc[1];
-          const int z = (cz + off[2][kz] + G.nc[2]) % G.nc[2];
+          const int x = (cx + lo[0] + kx + G.nc[0]) % G.nc[0];
+          const int y = (cy + lo[1] + ky + G.nc[1]) % G.nc[1];
+          const int z = (cz + lo[2] + kz + G.nc[2]) % G.nc[2];
           const int q = (z * G.nc[1] + y) * G.nc[0] + x;
           const int s0 = start[q], s1 = start[q + 1];
           for (int j = s0 + lane; j < s1; j += WAVE) {
             if (j == i) continue;
-            if (status && status[j] == ST_COLLIDED) continue;
+            if (status[j] == ST_COLLIDED) continue;
             const Rec b = rec[j];
             double t;
             if (pair_time(a, b, G, dt, t)) {
@@ -665,91 +683,133 @@ __global__ __launch_bounds__(256) void k_gather_exact(const int *list, int nlist
     if (lane == 0) {
       key_j[i] = bj;
       key_t[i] = bt;
+      if (status[i] == ST_DIRTY) status[i] = ST_ACTIVE;
     }
   }
 }
 
-hipError_t launch_gather_exact(hipStream_t s, const int *list, int nlist, const Rec *rec,
-                               const int *start, const Grid &G, double dt, const uint8_t *status,
-                               const int *perm, int *key_j, double *key_t,
-                               const unsigned int *nlist_dev) {
+hipError_t launch_gather_exact(hipStream_t s, const int *list, int nlist, const unsigned int *nlist_dev,
+                               int select, const Rec *rec, const int *start, const Grid &G,
+                               double dt, uint8_t *status, const int *perm, int *key_j,
+                               double *key_t) {
   int64_t waves = nlist_dev ? 8192 : nlist;
   if (waves <= 0) return hipSuccess;
   if (waves > 8192) waves = 8192;
   const int blocks = (int)((waves + 3) / 4);
-  hipLaunchKernelGGL(k_gather_exact, dim3(blocks), dim3(256), 0, s, list, nlist, nlist_dev, rec,
-                     start, G, dt, status, perm, key_j, key_t);
+  hipLaunchKernelGGL(k_gather_exact, dim3(blocks), dim3(256), 0, s, list, nlist, nlist_dev, select,
+                     rec, start, G, dt, status, perm, key_j, key_t);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- a6: mutual resolve
 
-// One sweep of rule 3-4 over the listed sorted spheres (all when list is NULL).
-// A sphere whose partner has it as partner resolves its own side of the pair
-// from the start-of-step records and writes its end-of-step state to the
-// caller's arrays (Sec. "Inter-Particle Collisions"; eq. update_vel, update_rho).
-// Others stay active; those whose partner collides this sweep are queued for a
-// new partner search.  Spheres without a partner become free for the step.
-__global__ __launch_bounds__(256) void k_resolve_sweep(const int *list, int nlist,
-                                                       const Rec *rec, Grid G, double dt,
+// One sweep of rule 3-4 over every ACTIVE sphere (cell-sorted order).  A sphere
+// whose partner has it as partner resolves its own side of the pair from the
+// start-of-step records and writes its end-of-step state to its output record
+// (Sec. "Inter-Particle Collisions"; eq. update_vel, update_rho).  A sphere
+// whose partner pairs with a third sphere this sweep becomes DIRTY (new partner
+// search next sweep); one without a partner becomes FREE for the step.  Each
+// thread writes only its own status, and reads only keys, so the sweep is a
+// pure function of the keys.  Partners are spatial neighbours, so the partner
+// reads stay within a few cells of the sorted order.
+__global__ __launch_bounds__(256) void k_resolve_sweep(int n, const Rec *rec, Grid G, double dt,
                                                        double e, const int *key_j,
                                                        const double *key_t, uint8_t *status,
-                                                       const int *perm, Particles P,
-                                                       int *partner_out, double *tcoll_out,
-                                                       int *next_list, int *dirty_list,
+                                                       const int *perm, OutRec *out,
                                                        SweepCounters *ctr) {
-  const int idx = blockIdx.x * 256 + threadIdx.x;
-  bool wait = false, dirty = false;
+  const int i = blockIdx.x * 256 + threadIdx.x;
   unsigned long long npair = 0ull;
-  int i = -1;
-  if (idx < nlist) {
-    i = list ? list[idx] : idx;
-    if (status[i] == ST_ACTIVE) {
-      const int p = key_j[i];
-      if (p < 0) {
-        status[i] = ST_FREE;
-      } else {
-        const int q = key_j[p];
-        if (q == i) {
-          const Rec a = rec[i], b = rec[p];
-          const double t = key_t[i];
-          double xo[3], vo[3];
-          resolve_one(a, b, G, t, dt, e, xo, vo);
-          const int o = perm[i];
-          P.x[o] = xo[0];
-          P.y[o] = xo[1];
-          P.z[o] = xo[2];
-          P.vx[o] = vo[0];
-          P.vy[o] = vo[1];
-          P.vz[o] = vo[2];
-          partner_out[o] = perm[p];
-          tcoll_out[o] = t;
-          status[i] = ST_COLLIDED;
-          if (i < p) npair = 1ull;
-        } else {
-          wait = true;
-          dirty = q >= 0 && key_j[q] == p;  // p pairs with q this sweep
-        }
+  if (i < n && status[i] == ST_ACTIVE) {
+    const int p = key_j[i];
+    if (p < 0) {
+      status[i] = ST_FREE;
+    } else {
+      const int q = key_j[p];
+      if (q == i) {
+        const Rec a = rec[i], b = rec[p];
+        const double t = key_t[i];
+        double xo[3], vo[3];
+        resolve_one(a, b, G, t, dt, e, xo, vo);
+        OutRec o;
+        o.x = xo[0];
+        o.y = xo[1];
+        o.z = xo[2];
+        o.vx = vo[0];
+        o.vy = vo[1];
+        o.vz = vo[2];
+        o.t = t;
+        o.partner = perm[p];
+        o.pad = 0;
+        out[i] = o;
+        status[i] = ST_COLLIDED;
+        if (i < p) npair = 1ull;
+      } else if (q >= 0 && key_j[q] == p) {
+        status[i] = ST_DIRTY;  // p pairs with q this sweep
       }
     }
   }
-  const unsigned int kn = wave_append(wait, &ctr->n_next);
-  if (wait) next_list[kn] = i;
-  const unsigned int kd = wave_append(dirty, &ctr->n_dirty);
-  if (dirty) dirty_list[kd] = i;
-  npair = wave_sum(npair);
-  if (__lane_id() == 0 && npair) atomicAdd(&ctr->pairs, npair);
+  block_add(npair, &my_shard(ctr).pairs);
 }
 
-hipError_t launch_resolve_sweep(hipStream_t s, const int *list, int nlist, const Rec *rec,
-                                const Grid &G, double dt, double e, const int *key_j,
-                                const double *key_t, uint8_t *status, const int *perm,
-                                const Particles &P, int *partner_out, double *tcoll_out,
-                                int *next_list, int *dirty_list, SweepCounters *ctr) {
-  if (nlist <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_resolve_sweep, dim3((nlist + 255) / 256), dim3(256), 0, s, list, nlist,
-                     rec, G, dt, e, key_j, key_t, status, perm, P, partner_out, tcoll_out,
-                     next_list, dirty_list, ctr);
+hipError_t launch_resolve_sweep(hipStream_t s, int n, const Rec *rec, const Grid &G, double dt,
+                                double e, const int *key_j, const double *key_t, uint8_t *status,
+                                const int *perm, OutRec *out, SweepCounters *ctr) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_resolve_sweep, dim3((n + 255) / 256), dim3(256), 0, s, n, rec, G, dt, e,
+                     key_j, key_t, status, perm, out, ctr);
+  return hipGetLastError();
+}
+
+// rule 5 in cell-sorted order: spheres that did not collide fly the whole step
+__global__ __launch_bounds__(256) void k_advance_sorted(int n, const Rec *rec,
+                                                        const uint8_t *status, double dt, Grid G,
+                                                        OutRec *out) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n || status[i] == ST_COLLIDED) return;
+  const Rec a = rec[i];
+  OutRec o;
+  o.x = wrap_pos(a.x + dt * a.vx, G.L[0]);
+  o.y = wrap_pos(a.y + dt * a.vy, G.L[1]);
+  o.z = wrap_pos(a.z + dt * a.vz, G.L[2]);
+  o.vx = a.vx;
+  o.vy = a.vy;
+  o.vz = a.vz;
+  o.t = __longlong_as_double(0x7ff8000000000000LL);  // NaN: no collision
+  o.partner = -1;
+  o.pad = 0;
+  out[i] = o;
+}
+
+hipError_t launch_advance_sorted(hipStream_t s, int n, const Rec *rec, const uint8_t *status,
+                                 double dt, const Grid &G, OutRec *out) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_advance_sorted, dim3((n + 255) / 256), dim3(256), 0, s, n, rec, status, dt,
+                     G, out);
+  return hipGetLastError();
+}
+
+// end-of-step state back to the caller's order: one 64-B record gathered per
+// sphere, coalesced writes
+__global__ __launch_bounds__(256) void k_unpermute(Particles P, const int *rank, const OutRec *out,
+                                                   int *partner, double *tcoll) {
+  const int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (o >= P.n) return;
+  const OutRec q = out[rank[o]];
+  P.x[o] = q.x;
+  P.y[o] = q.y;
+  P.z[o] = q.z;
+  P.vx[o] = q.vx;
+  P.vy[o] = q.vy;
+  P.vz[o] = q.vz;
+  partner[o] = q.partner;
+  tcoll[o] = q.t;
+}
+
+hipError_t launch_unpermute(hipStream_t s, const Particles &P, const int *rank, const OutRec *out,
+                            int *partner, double *tcoll) {
+  if (P.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_unpermute, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, s, P, rank,
+                     out, partner, tcoll);
   return hipGetLastError();
 }
 
@@ -776,27 +836,21 @@ hipError_t launch_advance(hipStream_t s, const Particles &P, const int *partner,
 
 // ---------------------------------------------------------------- public single-sweep API
 
-// caller active mask -> sorted status (inactive = excluded like collided) and
-// the list of active sorted spheres
+// caller active mask -> sorted status (inactive spheres are excluded like
+// collided ones)
 __global__ __launch_bounds__(256) void k_status_from_active(const uint8_t *active,
                                                             const int *perm, int n,
-                                                            uint8_t *status, int *list,
-                                                            unsigned int *nlist) {
+                                                            uint8_t *status) {
   const int i = blockIdx.x * 256 + threadIdx.x;
-  bool act = false;
-  if (i < n) {
-    act = active ? active[perm[i]] != 0 : true;
-    status[i] = act ? ST_ACTIVE : ST_COLLIDED;
-  }
-  const unsigned int k = wave_append(act, nlist);
-  if (act) list[k] = i;
+  if (i >= n) return;
+  status[i] = (active ? active[perm[i]] != 0 : true) ? ST_ACTIVE : ST_COLLIDED;
 }
 
 hipError_t launch_status_from_active(hipStream_t s, const uint8_t *active, const int *perm, int n,
-                                     uint8_t *status, int *list, unsigned int *nlist) {
+                                     uint8_t *status) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_status_from_active, dim3((n + 255) / 256), dim3(256), 0, s, active, perm,
-                     n, status, list, nlist);
+                     n, status);
   return hipGetLastError();
 }
 
