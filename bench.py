@@ -74,7 +74,8 @@ def main():
     ap.add_argument("--n", type=int, default=0, help="override N (default 16M)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
-    ap.add_argument("--fp32", action="store_true", help="FP32 filter + FP64 recheck form")
+    ap.add_argument("--form", choices=["both", "fp64", "fp32"], default="both",
+                    help="plain FP64 path, FP32 filter + FP64 recheck, or both (value = fp64)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on one GPU only: the collision step is a single-GPU build; "
@@ -87,33 +88,49 @@ def main():
     t0 = time.perf_counter()
     box = make_workload(args)
     log(f"workload {box.n} spheres, L={box.L[0]:.3f}, generated in {time.perf_counter() - t0:.1f} s")
-    p = pc.Particles.from_box(box)
-    opts = pc.pcol_default_opts(timing=1, fp32_filter=int(args.fp32))
-    ctx = pc.Context(box.n, opts)
-    partner = torch.empty(box.n, dtype=torch.int32, device="cuda")
-    tcoll = torch.empty(box.n, dtype=torch.float64, device="cuda")
-    p0 = p.clone()
+    p0 = pc.Particles.from_box(box)
 
-    def restore():
-        for t, t0 in zip(p.tensors()[:6], p0.tensors()[:6]):
-            t.copy_(t0)
+    def run_form(fp32: int):
+        """K timed steps of one form, each from the configured input."""
+        p = p0.clone()
+        ctx = pc.Context(box.n, pc.pcol_default_opts(timing=1, fp32_filter=fp32))
+        partner = torch.empty(box.n, dtype=torch.int32, device="cuda")
+        tcoll = torch.empty(box.n, dtype=torch.float64, device="cuda")
 
-    for k in range(args.warmup):
-        restore()
-        st = pc.pcol_step(ctx, p, box.L, box.dt, box.e, partner, tcoll)
-        log(f"warmup {k}: {st['n_pairs']} pairs, {st['n_sweeps']} sweeps, detect {st['ms_detect']:.3f} ms")
-    torch.cuda.synchronize()
-    stats = []
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        restore()
-        stats.append(pc.pcol_step(ctx, p, box.L, box.dt, box.e, partner, tcoll))
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    for k, st in enumerate(stats):
-        log(f"step {k}: pairs {st['n_pairs']} sweeps {st['n_sweeps']} tests {st['pair_tests']} "
-            f"bin {st['ms_bin']:.3f} detect {st['ms_detect']:.3f} sweeps {st['ms_sweeps']:.3f} "
-            f"advance {st['ms_advance']:.3f} ms")
+        def restore():
+            for t, t_0 in zip(p.tensors()[:6], p0.tensors()[:6]):
+                t.copy_(t_0)
+
+        name = "fp32+recheck" if fp32 else "fp64"
+        for k in range(args.warmup):
+            restore()
+            st = pc.pcol_step(ctx, p, box.L, box.dt, box.e, partner, tcoll)
+            log(f"[{name}] warmup {k}: {st['n_pairs']} pairs, {st['n_sweeps']} sweeps, "
+                f"detect {st['ms_detect']:.3f} ms")
+        torch.cuda.synchronize()
+        stats = []
+        t_start = time.perf_counter()
+        for k in range(args.steps):
+            restore()
+            stats.append(pc.pcol_step(ctx, p, box.L, box.dt, box.e, partner, tcoll))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        for k, st in enumerate(stats):
+            log(f"[{name}] step {k}: pairs {st['n_pairs']} sweeps {st['n_sweeps']} tests "
+                f"{st['pair_tests']} rechecks {st['n_recheck']} bin {st['ms_bin']:.3f} detect "
+                f"{st['ms_detect']:.3f} sweeps {st['ms_sweeps']:.3f} advance {st['ms_advance']:.3f} ms")
+        out = {"p": p, "partner": partner, "stats": stats, "wall": wall}
+        ctx.close()
+        return out
+
+    forms = {}
+    if args.form in ("both", "fp64"):
+        forms["fp64"] = run_form(0)
+    if args.form in ("both", "fp32"):
+        forms["fp32"] = run_form(1)
+    main_form = "fp64" if "fp64" in forms else "fp32"
+    R = forms[main_form]
+    stats, wall = R["stats"], R["wall"]
     ms_step = wall * 1e3 / args.steps
     det_ms = [st["ms_detect"] for st in stats]
     tests = sum(st["pair_tests"] for st in stats)
@@ -130,11 +147,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if args.fp32 else "f64",
+        "dtype": "f64" if main_form == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"{box.name}: {box.n} polydisperse spheres, phi 0.3, e {box.e}, "
                                f"dt {box.dt}, periodic cube L={box.L[0]:.4f}",
-                   "n": box.n, "form": "fp32_filter+fp64_recheck" if args.fp32 else "plain_fp64"},
+                   "n": box.n, "form": "plain_fp64" if main_form == "fp64" else "fp32_filter+fp64_recheck"},
         "pair_tests_per_s": tests / det_total,
         "detect_ms_median": statistics.median(det_ms),
         "pairs_per_step": statistics.mean(st["n_pairs"] for st in stats),
@@ -144,6 +161,26 @@ def main():
                      "kernel": "k_detect_half",
                      "note": f"{OPS_PER_PAIR_TEST} non-FMA FP64 ops per unordered pair test"},
     }
+    if "fp64" in forms and "fp32" in forms:
+        A, B = forms["fp64"], forms["fp32"]
+        mismatch = int((A["partner"] != B["partner"]).sum().item())
+        errs = []
+        for f in ("vx", "vy", "vz"):
+            a, b = getattr(A["p"], f), getattr(B["p"], f)
+            errs.append(((a - b).abs() / a.abs().clamp_min(1e-300)).max().item())
+        sb = B["stats"]
+        dm32 = [st["ms_detect"] for st in sb]
+        out["fp32_form"] = {
+            "value": box.n * args.steps / B["wall"], "unit": "particles/s",
+            "ms_per_step": B["wall"] * 1e3 / args.steps,
+            "speedup_vs_fp64": A["wall"] / B["wall"],
+            "detect_ms_median": statistics.median(dm32),
+            "detect_speedup_vs_fp64": statistics.median(det_ms) / statistics.median(dm32),
+            "pair_set_mismatch": mismatch,
+            "max_rel_velocity_error": max(errs),
+            "band": sb[0]["band"],
+            "rechecks_per_step": statistics.mean(st["n_recheck"] for st in sb),
+        }
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on {args.cpu_sample} spheres")
         out["cpu_baseline"] = cpu_baseline(args)

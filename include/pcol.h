@@ -119,6 +119,7 @@ typedef struct {
   int32_t max_cell;      /* largest cell occupancy */
   double h[3];           /* grid cell side per axis */
   double reach;          /* 2 max r + 2 max|v| dt */
+  double band;           /* FP32 filter band in use (>= band_rel; 0 without the filter) */
   double ms_bin;         /* with opts.timing only: validation, reach, binning */
   double ms_detect;      /*   the sweep-1 pair-test kernel alone */
   double ms_sweeps;      /*   partner selection and all resolve sweeps */

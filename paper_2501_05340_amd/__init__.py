@@ -50,7 +50,8 @@ class pcol_stats(ctypes.Structure):
                 ("n_overflow", ctypes.c_int64), ("n_recheck", ctypes.c_int64),
                 ("nc", ctypes.c_int32 * 3), ("home_cells", ctypes.c_int32),
                 ("max_cell", ctypes.c_int32), ("h", ctypes.c_double * 3),
-                ("reach", ctypes.c_double), ("ms_bin", ctypes.c_double),
+                ("reach", ctypes.c_double), ("band", ctypes.c_double),
+                ("ms_bin", ctypes.c_double),
                 ("ms_detect", ctypes.c_double), ("ms_sweeps", ctypes.c_double),
                 ("ms_advance", ctypes.c_double)]
 

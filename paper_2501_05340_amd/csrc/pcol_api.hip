@@ -21,6 +21,7 @@ struct pcol_ctx {
 
   // cell-sorted state of the last pcol_bin
   Rec *rec = nullptr;
+  Rec32 *rec32 = nullptr;  // FP32 filter records (fp32_filter only)
   int *perm = nullptr;  // sorted position -> caller index
   int *rank = nullptr;  // caller index -> sorted position
   int *cid = nullptr;
@@ -54,6 +55,8 @@ struct pcol_ctx {
   const double *binned_x = nullptr;
   Grid G{};
   double reach = 0.0;
+  double vmax = 0.0, rmin = 0.0, rmax = 0.0;
+  double band = 0.0;   // FP32 filter band in use (relative to r_i + r_j)
   double h[3] = {0, 0, 0};
   int maxcell = 0;
   bool small = false;  // some axis has fewer than 3 cells
@@ -148,7 +151,7 @@ pcol_status pcol_set_stream(pcol_ctx *ctx, void *hip_stream) {
 
 void pcol_destroy(pcol_ctx *ctx) {
   if (!ctx) return;
-  void *dev[] = {ctx->rec,    ctx->perm,   ctx->rank,   ctx->cid,         ctx->slot,
+  void *dev[] = {ctx->rec,    ctx->rec32,  ctx->perm,   ctx->rank,   ctx->cid,         ctx->slot,
                  ctx->count,  ctx->start,  ctx->blocksum, ctx->cnt,      ctx->slot_t,
                  ctx->slot_j, ctx->key_j,  ctx->key_t,  ctx->status,      ctx->out,
                  ctx->ovf,    ctx->partner_tmp, ctx->tcoll_tmp,
@@ -186,6 +189,7 @@ pcol_status pcol_create(pcol_ctx **out, int64_t n_max, void *hip_stream, const p
     if (e == hipSuccess && r != hipSuccess) e = r;
   };
   A(dalloc(&ctx->rec, n));
+  if (ctx->opts.fp32_filter) A(dalloc(&ctx->rec32, n));
   A(dalloc(&ctx->perm, n));
   A(dalloc(&ctx->rank, n));
   A(dalloc(&ctx->cid, n));
@@ -224,15 +228,18 @@ pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box
   hipStream_t s = ctx->stream;
   // a1: reach and data validity (one read-back)
   PCOL_HIP(hipMemsetAsync(ctx->reach_d, 0, sizeof(ReachOut), s));
+  PCOL_HIP(launch_fill_u32(s, (unsigned int *)&ctx->reach_d->rmin, 0u, 1));
+  PCOL_HIP(launch_fill_u32(s, (unsigned int *)&ctx->reach_d->rmin + 1, 0x7ff00000u, 1));
   PCOL_HIP(launch_reach(s, P, box->len, ctx->reach_d));
   PCOL_HIP(hipMemcpyAsync(ctx->reach_h, ctx->reach_d, sizeof(ReachOut), hipMemcpyDeviceToHost, s));
   PCOL_HIP(hipStreamSynchronize(s));
   const ReachOut ro = *ctx->reach_h;
   if (ro.bad & 1u) return fail(ctx, PCOL_E_INVALID, "non-finite value, r <= 0 or m <= 0");
   if (ro.bad & 2u) return fail(ctx, PCOL_E_INVALID, "position outside [0, L)");
-  double v2, rmax;
+  double v2, rmax, rmin;
   memcpy(&v2, &ro.v2max, sizeof(double));
   memcpy(&rmax, &ro.rmax, sizeof(double));
+  memcpy(&rmin, &ro.rmin, sizeof(double));
   const double reach = 2.0 * rmax + 2.0 * sqrt(v2) * dt;
   for (int a = 0; a < 3; ++a)
     if (!(box->len[a] > 2.0 * reach))
@@ -261,7 +268,8 @@ pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box
     G.L[a] = box->len[a];
     G.halfL[a] = 0.5 * box->len[a];
     G.inv_h[a] = (double)G.nc[a] / box->len[a];
-    ctx->h[a] = box->len[a] / G.nc[a];
+    G.h[a] = box->len[a] / G.nc[a];
+    ctx->h[a] = G.h[a];
     if (G.nc[a] < 3) ctx->small = true;
   }
   if ((int64_t)G.ncell + 2 > ctx->cell_cap) {
@@ -281,12 +289,16 @@ pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box
   PCOL_HIP(launch_fill_i32(s, ctx->count, 0, G.ncell));
   PCOL_HIP(launch_cell_hist(s, P, G, ctx->cid, ctx->slot, ctx->count));
   PCOL_HIP(launch_scan(s, ctx->count, G.ncell, ctx->start, ctx->blocksum, ctx->reach_d));
-  PCOL_HIP(launch_scatter(s, P, ctx->cid, ctx->slot, ctx->start, ctx->rec, ctx->perm, ctx->rank));
+  PCOL_HIP(launch_scatter(s, P, G, ctx->cid, ctx->slot, ctx->start, ctx->rec,
+                          ctx->opts.fp32_filter ? ctx->rec32 : nullptr, ctx->perm, ctx->rank));
   PCOL_HIP(hipMemcpyAsync(ctx->reach_h, ctx->reach_d, sizeof(ReachOut), hipMemcpyDeviceToHost, s));
   PCOL_HIP(hipStreamSynchronize(s));
   ctx->maxcell = (int)ctx->reach_h->maxcell;
   ctx->G = G;
   ctx->reach = reach;
+  ctx->vmax = sqrt(v2);
+  ctx->rmin = rmin;
+  ctx->rmax = rmax;
   ctx->binned = true;
   ctx->binned_n = p->n;
   ctx->binned_x = p->x;
@@ -299,6 +311,30 @@ static pcol_status check_binned(pcol_ctx *ctx, const pcol_particles *p, const pc
   for (int a = 0; a < 3; ++a)
     if (box->len[a] != ctx->G.L[a]) return fail(ctx, PCOL_E_STATE, "box differs from pcol_bin");
   return PCOL_OK;
+}
+
+// Contact-distance factor of the FP32 filter.  Bounds (unit roundoff u = 2^-24)
+// on the FP32 errors of the filter quantities for any pair the binary64 rule
+// can keep (|d| <= reach, |u| <= 2 vmax, coordinates within 1.5 h of the home
+// cell centre):
+//   separation   Dd = (2 h + reach) u       relative velocity  Du = 4 vmax u
+//   c' = |d|^2 - (s k)^2:  2 sqrt3 reach Dd + 3 u reach^2 + 6 u (2 rmax k)^2
+//   b' dt2f = d.u dt2f:    (sqrt3 (reach Du + 2 vmax Dd) + 6 u reach vmax) 2 dt (1 + 2^-11)
+// The inflation (k^2 - 1) s_min^2 >= 2 (k - 1) s_min^2 must cover their sum; k
+// is chosen so that it covers twice the sum, and never below 1 + band_rel.
+static double fp32_band(const pcol_ctx *ctx, double dt) {  // returns the band
+  const double u = 0x1.0p-24;
+  double h = ctx->h[0];
+  for (int a = 1; a < 3; ++a) h = ctx->h[a] > h ? ctx->h[a] : h;
+  const double R = ctx->reach, V = ctx->vmax, smin = 2.0 * ctx->rmin;
+  const double k0 = 1.0 + ctx->opts.band_rel + 1e-3;  // generous k for the radius term
+  const double Dd = (2.0 * h + R) * u, Du = 4.0 * V * u;
+  const double ec = 2.0 * sqrt(3.0) * R * Dd + 3.0 * u * R * R +
+                    6.0 * u * (2.0 * ctx->rmax * k0) * (2.0 * ctx->rmax * k0);
+  const double eb = (sqrt(3.0) * (R * Du + 2.0 * V * Dd) + 6.0 * u * R * V) * 2.0 * dt *
+                    (1.0 + 0x1.0p-11);
+  const double need = 2.0 * (ec + eb) / (2.0 * smin * smin);
+  return ctx->opts.band_rel > need ? ctx->opts.band_rel : need;
 }
 
 // sweep 1: keys of all spheres (all active) into ctx->key_j / key_t (sorted order)
@@ -318,8 +354,14 @@ static pcol_status detect_all(pcol_ctx *ctx, double dt) {
     A.dt = dt;
     A.dt2 = 2.0 * dt * (1.0 + 0x1.0p-20);
     A.K = ctx->K;
+    A.rec32 = ctx->rec32;
     A.fp32 = ctx->opts.fp32_filter;
-    A.band = (float)ctx->opts.band_rel;
+    ctx->band = A.fp32 ? fp32_band(ctx, dt) : 0.0;
+    // round the factor up so the float never shrinks the inflation
+    const double kb = 1.0 + ctx->band;
+    A.kband = (float)kb;
+    if ((double)A.kband < kb) A.kband = nextafterf(A.kband, 2.0f);
+    A.dt2f = (float)(2.0 * dt * (1.0 + 0x1.0p-12));
     PCOL_HIP(launch_fill_i32(s, ctx->cnt, 0, n));
     if (ctx->opts.timing) PCOL_HIP(hipEventRecord(ctx->ev[5], s));
     PCOL_HIP(launch_detect_half(s, A));
@@ -407,7 +449,7 @@ pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, dou
   double *tc = tcoll ? tcoll : ctx->tcoll_tmp;
   const Particles P = to_dev(p);
   int64_t pairs = 0, sweeps = 0, ovf_total = 0;
-  unsigned long long contacts = 0ull;
+  unsigned long long contacts = 0ull, recheck = 0ull;
   double ms_detect = 0.0;
   if (n > 0) {
     PCOL_HIP(launch_fill_u8(s, ctx->status, ST_ACTIVE, n));
@@ -424,7 +466,10 @@ pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, dou
       PCOL_HIP(hipStreamSynchronize(s));
       unsigned long long sp, sc;
       sum_counters(*ctx->ctr_h, sp, sc);
-      if (sweeps == 0) contacts = sc / 2ull;
+      if (sweeps == 0) {
+        contacts = sc / 2ull;
+        for (int k = 0; k < NSHARD; ++k) recheck += ctx->ctr_h->shard[k].recheck;
+      }
       ovf_total += ctx->ctr_h->n_overflow;
       ++sweeps;
       pairs += (int64_t)sp;
@@ -461,6 +506,8 @@ pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, dou
     stats->n_sweeps = sweeps;
     stats->contacts = (int64_t)contacts;
     stats->n_overflow = ovf_total;
+    stats->n_recheck = (int64_t)recheck;
+    stats->band = ctx->band;
     for (int a = 0; a < 3; ++a) {
       stats->nc[a] = ctx->G.nc[a];
       stats->h[a] = ctx->h[a];

@@ -36,12 +36,21 @@ struct Grid {
   double inv_h[3];  // nc / L, for cell assignment only
   double L[3];
   double halfL[3];  // 0.5 * L, the minimum-image threshold
+  double h[3];      // L / nc, cell side
+};
+
+// FP32 copy of a record for the pair filter: position relative to the centre
+// of the sphere's own cell, radius, velocity (32 B).
+struct alignas(16) Rec32 {
+  float x, y, z, r;
+  float vx, vy, vz, pad;
 };
 
 // Values the reach kernel reduces (non-negative doubles compared as bit patterns).
 struct ReachOut {
   unsigned long long v2max;  // max over spheres of (vx^2 + vy^2) + vz^2
   unsigned long long rmax;
+  unsigned long long rmin;   // initialised to the bits of +inf
   unsigned int bad;          // bit 0: non-finite / r <= 0 / m <= 0; bit 1: position outside [0, L)
   unsigned int maxcell;      // filled by the scan
 };
@@ -53,7 +62,7 @@ constexpr int NSHARD = 64;
 struct alignas(128) CounterShard {
   unsigned long long pairs;     // pairs resolved this sweep
   unsigned long long contacts;  // contacts found (each counted from both spheres)
-  unsigned long long recheck;   // FP32 filter survivors rechecked in FP64
+  unsigned long long recheck;   // FP32 filter survivors rechecked in FP64 (counted per wave)
   unsigned long long pad[13];
 };
 struct SweepCounters {
@@ -153,6 +162,7 @@ struct Particles {
 // Everything the sweep-1 detect needs.
 struct DetectArgs {
   const Rec *rec;
+  const Rec32 *rec32; // FP32 filter records (fp32 form only)
   const int *start;   // ncell + 1
   int *cnt;           // per sorted sphere: contacts found
   double *slot_t;     // [n * K]
@@ -164,7 +174,8 @@ struct DetectArgs {
   double dt2;         // 2 dt (1 + 2^-20): conservative bound for the cheap reject
   int K;
   int fp32;           // FP32 filter + FP64 recheck
-  float band;         // FP32 filter band relative to s
+  float kband;        // FP32 filter: contact distance inflated to s * kband
+  float dt2f;         // FP32 filter: 2 dt (1 + 2^-12)
 };
 
 hipError_t launch_fill_u32(hipStream_t s, unsigned int *p, unsigned int v, int64_t n);
@@ -176,8 +187,9 @@ hipError_t launch_cell_hist(hipStream_t s, const Particles &P, const Grid &G, in
                             int *count);
 hipError_t launch_scan(hipStream_t s, const int *count, int ncell, int *start, int *blocksum,
                        ReachOut *out);
-hipError_t launch_scatter(hipStream_t s, const Particles &P, const int *cid, const int *slot,
-                          const int *start, Rec *rec, int *perm, int *rank);
+hipError_t launch_scatter(hipStream_t s, const Particles &P, const Grid &G, const int *cid,
+                          const int *slot, const int *start, Rec *rec, Rec32 *rec32, int *perm,
+                          int *rank);
 hipError_t launch_detect_half(hipStream_t s, const DetectArgs &A);
 hipError_t launch_count_pairs(hipStream_t s, const int *start, const Grid &G,
                               unsigned long long *out);

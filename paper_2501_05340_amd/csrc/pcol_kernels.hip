@@ -117,7 +117,7 @@ hipError_t launch_fill_f64(hipStream_t s, double *p, double v, int64_t n) {
 // sphere, coalesced.
 __global__ __launch_bounds__(256) void k_reach(Particles P, double L0, double L1, double L2,
                                                ReachOut *out) {
-  double v2 = 0.0, rm = 0.0;
+  double v2 = 0.0, rm = 0.0, rn = INFINITY;
   unsigned int bad = 0u;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < P.n;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -132,17 +132,20 @@ __global__ __launch_bounds__(256) void k_reach(Particles P, double L0, double L1
     if (fin) {
       v2 = w > v2 ? w : v2;
       rm = r > rm ? r : rm;
+      rn = r < rn ? r : rn;
     }
   }
   for (int o = WAVE / 2; o > 0; o >>= 1) {
-    const double a = __shfl_xor(v2, o), b = __shfl_xor(rm, o);
+    const double a = __shfl_xor(v2, o), b = __shfl_xor(rm, o), c = __shfl_xor(rn, o);
     v2 = a > v2 ? a : v2;
     rm = b > rm ? b : rm;
+    rn = c < rn ? c : rn;
     bad |= __shfl_xor(bad, o);
   }
   if (__lane_id() == 0) {
     atomicMax(&out->v2max, dbits(v2));
     atomicMax(&out->rmax, dbits(rm));
+    if (rn > 0.0) atomicMin(&out->rmin, dbits(rn));
     if (bad) atomicOr(&out->bad, bad);
   }
 }
@@ -279,13 +282,15 @@ hipError_t launch_scan(hipStream_t s, const int *count, int ncell, int *start, i
 // ---------------------------------------------------------------- a4: scatter
 
 // cell-sorted 64-B records of the start-of-step state; reads the caller's SoA
-// arrays coalesced and writes one record per sphere.
-__global__ __launch_bounds__(256) void k_scatter(Particles P, const int *cid, const int *slot,
-                                                 const int *start, Rec *rec, int *perm,
-                                                 int *rank) {
+// arrays coalesced and writes one record per sphere.  With rec32 given, also
+// the 32-B FP32 filter record (position relative to the cell centre).
+__global__ __launch_bounds__(256) void k_scatter(Particles P, Grid G, const int *cid,
+                                                 const int *slot, const int *start, Rec *rec,
+                                                 Rec32 *rec32, int *perm, int *rank) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= P.n) return;
-  const int pos = start[cid[i]] + slot[i];
+  const int c = cid[i];
+  const int pos = start[c] + slot[i];
   Rec q;
   q.x = P.x[i];
   q.y = P.y[i];
@@ -298,13 +303,27 @@ __global__ __launch_bounds__(256) void k_scatter(Particles P, const int *cid, co
   rec[pos] = q;
   perm[pos] = (int)i;
   rank[i] = pos;
+  if (rec32) {
+    const int cx = c % G.nc[0], cy = (c / G.nc[0]) % G.nc[1], cz = c / (G.nc[0] * G.nc[1]);
+    Rec32 f;
+    f.x = (float)(q.x - (cx + 0.5) * G.h[0]);
+    f.y = (float)(q.y - (cy + 0.5) * G.h[1]);
+    f.z = (float)(q.z - (cz + 0.5) * G.h[2]);
+    f.r = (float)q.r;
+    f.vx = (float)q.vx;
+    f.vy = (float)q.vy;
+    f.vz = (float)q.vz;
+    f.pad = 0.f;
+    rec32[pos] = f;
+  }
 }
 
-hipError_t launch_scatter(hipStream_t s, const Particles &P, const int *cid, const int *slot,
-                          const int *start, Rec *rec, int *perm, int *rank) {
+hipError_t launch_scatter(hipStream_t s, const Particles &P, const Grid &G, const int *cid,
+                          const int *slot, const int *start, Rec *rec, Rec32 *rec32, int *perm,
+                          int *rank) {
   if (P.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scatter, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, s, P, cid,
-                     slot, start, rec, perm, rank);
+  hipLaunchKernelGGL(k_scatter, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, s, P, G, cid,
+                     slot, start, rec, rec32, perm, rank);
   return hipGetLastError();
 }
 
@@ -336,7 +355,37 @@ constexpr int MAXRUN = 10;
 // detect)
 typedef __attribute__((address_space(4))) const Rec *crec_ptr;
 
-template <bool SHIFT>
+// shift code of a run: per axis 0 = -L, 1 = none, 2 = +L (2 bits each), bit 6 = own cell
+__device__ __forceinline__ int run_code(int sx, int sy, int sz, int own) {
+  return (sx + 1) | ((sy + 1) << 2) | ((sz + 1) << 4) | (own << 6);
+}
+
+__device__ __forceinline__ double code_shift(int c, double L) {
+  return c == 0 ? -L : (c == 2 ? L : 0.0);
+}
+
+// Candidate slots past the end of the list hold this far-away sphere: its
+// separation squares to +inf and b stays finite, so it never passes the reject.
+constexpr double FAR_AWAY = 1e300;
+
+// Append contact (i, j, t) to both spheres' slots.
+__device__ __forceinline__ void record_contact(const DetectArgs &A, int i, int g, double t) {
+  const int K = A.K;
+  const size_t n = (size_t)A.n;
+  const int k1 = atomicAdd(&A.cnt[i], 1);
+  if (k1 < K) {
+    A.slot_t[k1 * n + i] = t;
+    A.slot_j[k1 * n + i] = g;
+  }
+  const int k2 = atomicAdd(&A.cnt[g], 1);
+  if (k2 < K) {
+    A.slot_t[k2 * n + g] = t;
+    A.slot_j[k2 * n + g] = i;
+  }
+}
+
+
+template <bool SHIFT, bool MASK>
 __device__ __forceinline__ void detect_chunk(const DetectArgs &A, int h0, int h1, int g, int thr,
                                              double sx, double sy, double sz) {
   const crec_ptr hrec = (crec_ptr)A.rec;
@@ -344,7 +393,7 @@ __device__ __forceinline__ void detect_chunk(const DetectArgs &A, int h0, int h1
   if (thr >= 0) {
     b = A.rec[g];
   } else {
-    b.x = b.y = b.z = 0.0;
+    b.x = b.y = b.z = FAR_AWAY;
     b.vx = b.vy = b.vz = 0.0;
     b.r = 0.0;
     b.m = 1.0;
@@ -373,42 +422,96 @@ __device__ __forceinline__ void detect_chunk(const DetectArgs &A, int h0, int h1
     const double s = ri + b.r;
     const double bb = (d0 * u0 + d1 * u1) + d2 * u2;
     const double cc = ((d0 * d0 + d1 * d1) + d2 * d2) - s * s;
-    // lane holds a candidate for this i (thr: -1 none, j for the own cell where only
-    // j > i is tested, INT_MAX otherwise) and the cheap reject passes.  With c > 0,
-    // c <= -b dt2 implies b < 0.
-    if (i < thr && cc <= -bb * dt2) {
+    // the cheap reject (with c > 0, c <= -b dt2 implies b < 0); in own-cell chunks
+    // only j > i is a candidate (thr = j there, INT_MAX elsewhere)
+    if ((!MASK || i < thr) && cc <= -bb * dt2) {
       const double aa = (u0 * u0 + u1 * u1) + u2 * u2;
       const double D = bb * bb - aa * cc;
       if (cc > 0.0 && aa > 0.0 && D >= 0.0) {
         const double t = cc / (-bb + __builtin_sqrt(D));
-        if (t <= dt) {
-          const int K = A.K;
-          const size_t n = (size_t)A.n;
-          const int k1 = atomicAdd(&A.cnt[i], 1);
-          if (k1 < K) {
-            A.slot_t[k1 * n + i] = t;
-            A.slot_j[k1 * n + i] = g;
-          }
-          const int k2 = atomicAdd(&A.cnt[g], 1);
-          if (k2 < K) {
-            A.slot_t[k2 * n + g] = t;
-            A.slot_j[k2 * n + g] = i;
-          }
-        }
+        if (t <= dt) record_contact(A, i, g, t);
       }
     }
   }
 }
 
-// shift code of a run: per axis 0 = -L, 1 = none, 2 = +L (2 bits each), bit 6 = own cell
-__device__ __forceinline__ int run_code(int sx, int sy, int sz, int own) {
-  return (sx + 1) | ((sy + 1) << 2) | ((sz + 1) << 4) | (own << 6);
+typedef __attribute__((address_space(4))) const Rec32 *crec32_ptr;
+
+// FP32 form of detect_chunk: a conservative single-precision filter, then the
+// binary64 rule (identical to the plain path) for the pairs that pass.
+//
+// Coordinates are relative to the home cell centre (|x| <= 1.5 h for the
+// candidates), so each coordinate carries at most ulp32(1.5 h) / 2 of rounding.
+// The filter inflates the contact distance to s * kband and the step bound to
+// 2 dt (1 + 2^-12), and passes a pair iff  c' + b' * dt2f <= 0  with
+// c' = |d|^2 - (s kband)^2 and b' = d.u (explicit FMAs allowed: this is not the
+// rule's arithmetic).  Any pair the binary64 rule keeps has c <= 2|b| dt (1+6 eps);
+// the host picks kband so that 2 (kband - 1) s_min^2 exceeds twice a bound on the
+// FP32 errors of c' and b' dt2f over separations up to reach, so such a pair
+// always passes (pcol_api.hip, fp32_band).
+template <bool SHIFT, bool MASK>
+__device__ __forceinline__ void detect_chunk32(const DetectArgs &A, int h0, int h1, int g, int thr,
+                                               int code, double ox, double oy, double oz,
+                                               unsigned int *nrecheck) {
+  const crec_ptr hrec = (crec_ptr)A.rec;
+  const crec32_ptr hrec32 = (crec32_ptr)A.rec32;
+  const Grid &G = A.G;
+  float bx, by, bz, bvx, bvy, bvz, br;
+  if (thr >= 0) {
+    const Rec b = A.rec[g];
+    // candidate relative to the home cell centre (ox, oy, oz), image shift applied
+    bx = (float)((b.x + code_shift(code & 3, G.L[0])) - ox);
+    by = (float)((b.y + code_shift((code >> 2) & 3, G.L[1])) - oy);
+    bz = (float)((b.z + code_shift((code >> 4) & 3, G.L[2])) - oz);
+    bvx = (float)b.vx;
+    bvy = (float)b.vy;
+    bvz = (float)b.vz;
+    br = (float)b.r;
+  } else {
+    bx = by = bz = 1e18f;
+    bvx = bvy = bvz = 0.f;
+    br = 0.f;
+  }
+  const float kband = A.kband, dt2f = A.dt2f;
+  // home record i+1 (FP32) is requested while pair (i, j) is tested
+  float nx = hrec32[h0].x, ny = hrec32[h0].y, nz = hrec32[h0].z, nr = hrec32[h0].r;
+  float nvx = hrec32[h0].vx, nvy = hrec32[h0].vy, nvz = hrec32[h0].vz;
+  for (int i = h0; i < h1; ++i) {
+    const float ax = nx, ay = ny, az = nz, ar = nr, avx = nvx, avy = nvy, avz = nvz;
+    const int in = i + 1 < h1 ? i + 1 : i;
+    nx = hrec32[in].x;
+    ny = hrec32[in].y;
+    nz = hrec32[in].z;
+    nr = hrec32[in].r;
+    nvx = hrec32[in].vx;
+    nvy = hrec32[in].vy;
+    nvz = hrec32[in].vz;
+    const float d0 = bx - ax, d1 = by - ay, d2 = bz - az;
+    const float u0 = bvx - avx, u1 = bvy - avy, u2 = bvz - avz;
+    const float sb = (ar + br) * kband;
+    const float bb = __builtin_fmaf(d0, u0, __builtin_fmaf(d1, u1, d2 * u2));
+    const float q = __builtin_fmaf(d0, d0, __builtin_fmaf(d1, d1, d2 * d2));
+    const float cc = __builtin_fmaf(-sb, sb, q);
+    if ((!MASK || i < thr) && __builtin_fmaf(bb, dt2f, cc) <= 0.0f) {
+      ++*nrecheck;
+      // binary64 rule for the survivor, from the full records
+      const Rec b = A.rec[g];
+      const double xi = hrec[i].x, yi = hrec[i].y, zi = hrec[i].z, ri = hrec[i].r;
+      const double vxi = hrec[i].vx, vyi = hrec[i].vy, vzi = hrec[i].vz;
+      double e0 = b.x - xi, e1 = b.y - yi, e2 = b.z - zi;
+      if (SHIFT) {
+        e0 = e0 + code_shift(code & 3, G.L[0]);
+        e1 = e1 + code_shift((code >> 2) & 3, G.L[1]);
+        e2 = e2 + code_shift((code >> 4) & 3, G.L[2]);
+      }
+      double t;
+      if (contact_time(e0, e1, e2, b.vx - vxi, b.vy - vyi, b.vz - vzi, ri + b.r, A.dt, t))
+        record_contact(A, i, g, t);
+    }
+  }
 }
 
-__device__ __forceinline__ double code_shift(int c, double L) {
-  return c == 0 ? -L : (c == 2 ? L : 0.0);
-}
-
+template <bool FP32>
 __global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
   const Grid &G = A.G;
   const int cell = xcd_remap(blockIdx.x, gridDim.x);
@@ -426,6 +529,20 @@ __global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
     rc[k] = run_code(0, 0, 0, 0);
   }
   bool any_shift = false;
+  // own cell first (pairs with j after i), then the next cell along x
+  rg[0] = h0;
+  rl[0] = h1 - h0;
+  rc[0] = run_code(0, 0, 0, 1);
+  if (cx + 1 >= nc0) {
+    const int rowbase = (cz * nc1 + cy) * nc0;
+    rg[1] = A.start[rowbase];
+    rl[1] = A.start[rowbase + 1] - rg[1];
+    rc[1] = run_code(1, 0, 0, 0);
+    any_shift = true;
+  } else {
+    rg[1] = h1;
+    rl[1] = A.start[cell + 2] - h1;
+  }
   const int dys[4] = {1, -1, 0, 1}, dzs[4] = {0, 1, 1, 1};
 #pragma unroll
   for (int row = 0; row < 4; ++row) {
@@ -443,7 +560,7 @@ __global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
       sz = 1;
     }
     const int rowbase = (z * nc1 + y) * nc0;
-    const int k0 = 2 * row, k1 = 2 * row + 1;
+    const int k0 = 2 + 2 * row, k1 = 3 + 2 * row;
     if (cx - 1 < 0) {  // the wrapped left cell, then cells 0..1
       rg[k0] = A.start[rowbase + nc0 - 1];
       rl[k0] = A.start[rowbase + nc0] - rg[k0];
@@ -467,20 +584,6 @@ __global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
     }
     if (sy != 0 || sz != 0) any_shift = true;
   }
-  // own cell (pairs with j after i) and the next cell along x
-  rg[8] = h0;
-  rl[8] = h1 - h0;
-  rc[8] = run_code(0, 0, 0, 1);
-  if (cx + 1 >= nc0) {
-    const int rowbase = (cz * nc1 + cy) * nc0;
-    rg[9] = A.start[rowbase];
-    rl[9] = A.start[rowbase + 1] - rg[9];
-    rc[9] = run_code(1, 0, 0, 0);
-    any_shift = true;
-  } else {
-    rg[9] = h1;
-    rl[9] = A.start[cell + 2] - h1;
-  }
   int total = 0;
   int pre[MAXRUN];
 #pragma unroll
@@ -490,6 +593,7 @@ __global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
   }
 
   const int lane = threadIdx.x;
+  unsigned int nrc = 0u;
   for (int base = 0; base < total; base += WAVE) {
     const int v = base + lane;
     int g = 0, code = run_code(0, 0, 0, 0);
@@ -504,18 +608,47 @@ __global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
     }
     const bool own = (code >> 6) & 1;
     const int thr = !ok ? -1 : (own ? g : 0x7fffffff);
-    if (any_shift) {
-      detect_chunk<true>(A, h0, h1, g, thr, code_shift(code & 3, G.L[0]),
-                         code_shift((code >> 2) & 3, G.L[1]), code_shift((code >> 4) & 3, G.L[2]));
-    } else {
-      detect_chunk<false>(A, h0, h1, g, thr, 0.0, 0.0, 0.0);
+    const double sx = code_shift(code & 3, G.L[0]), sy = code_shift((code >> 2) & 3, G.L[1]),
+                 sz = code_shift((code >> 4) & 3, G.L[2]);
+    if (FP32) {
+      const double ox = (cx + 0.5) * G.h[0], oy = (cy + 0.5) * G.h[1], oz = (cz + 0.5) * G.h[2];
+      if (base < rl[0]) {
+        if (any_shift)
+          detect_chunk32<true, true>(A, h0, h1, g, thr, code, ox, oy, oz, &nrc);
+        else
+          detect_chunk32<false, true>(A, h0, h1, g, thr, code, ox, oy, oz, &nrc);
+      } else {
+        if (any_shift)
+          detect_chunk32<true, false>(A, h0, h1, g, thr, code, ox, oy, oz, &nrc);
+        else
+          detect_chunk32<false, false>(A, h0, h1, g, thr, code, ox, oy, oz, &nrc);
+      }
+      continue;
     }
+    if (base < rl[0]) {  // chunk holds own-cell candidates
+      if (any_shift)
+        detect_chunk<true, true>(A, h0, h1, g, thr, sx, sy, sz);
+      else
+        detect_chunk<false, true>(A, h0, h1, g, thr, 0.0, 0.0, 0.0);
+    } else {
+      if (any_shift)
+        detect_chunk<true, false>(A, h0, h1, g, thr, sx, sy, sz);
+      else
+        detect_chunk<false, false>(A, h0, h1, g, thr, 0.0, 0.0, 0.0);
+    }
+  }
+  if (FP32) {
+    const unsigned long long tot = wave_sum((unsigned long long)nrc);
+    if (lane == 0 && tot) atomicAdd(&A.ctr->shard[blockIdx.x % NSHARD].recheck, tot);
   }
 }
 
 hipError_t launch_detect_half(hipStream_t s, const DetectArgs &A) {
   if (A.G.ncell <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_detect_half, dim3(A.G.ncell), dim3(WAVE), 0, s, A);
+  if (A.fp32)
+    hipLaunchKernelGGL(k_detect_half<true>, dim3(A.G.ncell), dim3(WAVE), 0, s, A);
+  else
+    hipLaunchKernelGGL(k_detect_half<false>, dim3(A.G.ncell), dim3(WAVE), 0, s, A);
   return hipGetLastError();
 }
 

@@ -248,3 +248,37 @@ def test_error_codes_leave_inputs_unchanged():
     with pytest.raises(pc.PcolError) as ei:
         pc.pcol_step(small, p, box.L, box.dt, box.e)
     assert ei.value.code == pc.PCOL_E_INVALID
+
+
+# ---------------------------------------------------------------- FP32 filter + FP64 recheck form
+
+
+@pytest.mark.parametrize("which", ["config1", "config2", "poly20k", "small"])
+def test_fp32_filter_form_matches_oracle(which, cfg2, poly20k):
+    """The FP32 pair filter passes every pair the binary64 rule can keep and the
+    survivors are decided in binary64, so pair sets, times and states equal the
+    oracle's exactly."""
+    if which == "config1":
+        box = workloads.config(1)
+    elif which == "config2":
+        box = cfg2
+    elif which == "poly20k":
+        box = poly20k
+    else:
+        box = workloads.make_box(250, seed=5, phi=0.3, radius=0.5, e=0.85, dt=0.25)
+    _announce(f"fp32 form {which}")
+    gpu = gpu_step(box, fp32_filter=1)
+    orc = oracle.step(box)
+    assert compare_step(box, gpu, orc) == 0
+    st = gpu[3]
+    if min(st["nc"]) >= 3:
+        assert st["band"] >= 1e-4 and st["n_recheck"] >= orc.n_pairs
+
+
+def test_fp32_filter_form_equals_plain_form_bitwise(poly20k):
+    a = gpu_step(poly20k)
+    b = gpu_step(poly20k, fp32_filter=1)
+    for f in FIELDS:
+        assert np.array_equal(a[0][f].view(np.uint64), b[0][f].view(np.uint64))
+    assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2], equal_nan=True)
+    assert a[3]["contacts"] == b[3]["contacts"]
