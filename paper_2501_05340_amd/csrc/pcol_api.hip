@@ -353,9 +353,21 @@ static pcol_status detect_all(pcol_ctx *ctx, double dt) {
     A.G = ctx->G;
     A.dt = dt;
     A.dt2 = 2.0 * dt * (1.0 + 0x1.0p-20);
+    {
+      // 16 eps (reach^2 + (2 rmax)^2 + reach * 2 vmax * dt2): twice the bound on the
+      // differences between the filter's FMA values and the rule's b, c (pair64)
+      const double R = ctx->reach, smax = 2.0 * ctx->rmax;
+      A.tol = 16.0 * 0x1.0p-53 * (R * R + smax * smax + R * 2.0 * ctx->vmax * A.dt2);
+    }
     A.K = ctx->K;
     A.rec32 = ctx->rec32;
     A.fp32 = ctx->opts.fp32_filter;
+    // the FP32 filter reads its home records from an LDS copy of the home cell
+    // (when the largest cell fits in 20 KB); the FP64 filter reads them through
+    // the scalar cache, which measured faster for 64-B records
+    A.cap = A.fp32 && ctx->maxcell * (int)sizeof(Rec32) <= 20 * 1024
+                ? (ctx->maxcell > 0 ? ctx->maxcell : 1)
+                : 0;
     ctx->band = A.fp32 ? fp32_band(ctx, dt) : 0.0;
     // round the factor up so the float never shrinks the inflation
     const double kb = 1.0 + ctx->band;

@@ -171,8 +171,11 @@ struct DetectArgs {
   int n;              // spheres (slot arrays are k-major: slot[k * n + i])
   Grid G;
   double dt;
-  double dt2;         // 2 dt (1 + 2^-20): conservative bound for the cheap reject
+  double dt2;         // 2 dt (1 + 2^-20): step bound of the FP64 filter
+  double tol;         // FP64 filter tolerance (bound on FMA-vs-rule rounding differences)
   int K;
+  int cap;            // home spheres staged in LDS per cell (largest cell occupancy);
+                      // 0: read the home spheres through the scalar cache instead
   int fp32;           // FP32 filter + FP64 recheck
   float kband;        // FP32 filter: contact distance inflated to s * kband
   float dt2f;         // FP32 filter: 2 dt (1 + 2^-12)

@@ -343,17 +343,16 @@ hipError_t launch_scatter(hipStream_t s, const Particles &P, const Grid &G, cons
 // pair that can touch, the shifted separation equals the minimum image of rule
 // 1 bitwise (the grid has >= 3 cells per axis and cell side >= reach).
 //
-// Cheap reject before the square root: t = c / (-b + sqrt(D)) >= c / (2|b|)
-// because sqrt(D) <= |b| when a, c > 0, and with the roundings of rule 1 any
-// kept t <= dt has c <= 2 |b| dt (1 + 6 eps); so c > -b * dt2 with
-// dt2 = 2 dt (1 + 2^-20) means no contact.  Pairs that pass go through the
-// full rule.
+// A conservative filter (pair64, pair32) keeps the square root, the division
+// and the rule's exact operation order off the hot path; every pair it passes
+// is decided by the rule itself.
 constexpr int MAXRUN = 10;
 
 // records seen through the constant address space: wave-uniform reads of the
 // home spheres become scalar loads (the records are never written during the
 // detect)
 typedef __attribute__((address_space(4))) const Rec *crec_ptr;
+typedef __attribute__((address_space(4))) const Rec32 *crec32_ptr;
 
 // shift code of a run: per axis 0 = -L, 1 = none, 2 = +L (2 bits each), bit 6 = own cell
 __device__ __forceinline__ int run_code(int sx, int sy, int sz, int own) {
@@ -385,10 +384,47 @@ __device__ __forceinline__ void record_contact(const DetectArgs &A, int i, int g
 }
 
 
+// One home sphere (wave-uniform) against the lane's candidate.
+//
+// Filter: b' = d.u and c' = |d|^2 - s^2 by FMA chains (not the rule's operation
+// order), pass iff  c' + b' dt2 <= tol.  For a pair the rule keeps, c <= 2|b| dt
+// (1 + 6 eps) (the kept root is c / (-b + sqrt(D)) >= c / (2|b|)), and the FMA
+// values differ from the rule's b, c by at most 7 eps (|d|^2 + s^2) and
+// 7 eps |d| |u|; tol (set by the host from the reach, the largest radius and
+// speed) bounds those differences for |d| <= reach, so every kept pair passes.
+// Passing pairs are then decided by the rule itself (contact_time), so the
+// result is exactly the rule's.
 template <bool SHIFT, bool MASK>
-__device__ __forceinline__ void detect_chunk(const DetectArgs &A, int h0, int h1, int g, int thr,
-                                             double sx, double sy, double sz) {
-  const crec_ptr hrec = (crec_ptr)A.rec;
+__device__ __forceinline__ void pair64(const DetectArgs &A, const Rec &b, int g, int thr, double sx,
+                                       double sy, double sz, int i, double xi, double yi,
+                                       double zi, double ri, double vxi, double vyi, double vzi) {
+  double d0 = b.x - xi, d1 = b.y - yi, d2 = b.z - zi;
+  if (SHIFT) {
+    d0 = d0 + sx;
+    d1 = d1 + sy;
+    d2 = d2 + sz;
+  }
+  const double u0 = b.vx - vxi, u1 = b.vy - vyi, u2 = b.vz - vzi;
+  const double s = ri + b.r;
+  const double ss = s * s;
+  const double bf = __builtin_fma(d0, u0, __builtin_fma(d1, u1, d2 * u2));
+  const double cf = __builtin_fma(d0, d0, __builtin_fma(d1, d1, __builtin_fma(d2, d2, -ss)));
+  // in own-cell chunks only j > i is a candidate (thr = j there, INT_MAX elsewhere)
+  if ((!MASK || i < thr) && __builtin_fma(bf, A.dt2, cf) <= A.tol) {
+    double t;
+    if (contact_time(d0, d1, d2, u0, u1, u2, s, A.dt, t)) record_contact(A, i, g, t);
+  }
+}
+
+// The lane's candidate j against every home sphere i in [h0, h1).  The home
+// records come either from the wave's LDS copy of the home cell (broadcast
+// reads, HP = const Rec *) or through the constant address space (scalar loads,
+// HP = crec_ptr); the loop is unrolled by two and walks a pointer, so the
+// scalar instructions per pair stay few (the scalar pipe issues at the VALU's
+// rate).
+template <bool SHIFT, bool MASK, typename HP>
+__device__ __forceinline__ void detect_chunk(const DetectArgs &A, HP p, int h0, int h1, int g,
+                                             int thr, double sx, double sy, double sz) {
   Rec b;
   if (thr >= 0) {
     b = A.rec[g];
@@ -398,63 +434,54 @@ __device__ __forceinline__ void detect_chunk(const DetectArgs &A, int h0, int h1
     b.r = 0.0;
     b.m = 1.0;
   }
-  const double dt = A.dt, dt2 = A.dt2;
-  // home record i+1 is requested while pair (i, j) is computed
-  double nx = hrec[h0].x, ny = hrec[h0].y, nz = hrec[h0].z, nr = hrec[h0].r;
-  double nvx = hrec[h0].vx, nvy = hrec[h0].vy, nvz = hrec[h0].vz;
-  for (int i = h0; i < h1; ++i) {
-    const double xi = nx, yi = ny, zi = nz, ri = nr, vxi = nvx, vyi = nvy, vzi = nvz;
-    const int in = i + 1 < h1 ? i + 1 : i;
-    nx = hrec[in].x;
-    ny = hrec[in].y;
-    nz = hrec[in].z;
-    nr = hrec[in].r;
-    nvx = hrec[in].vx;
-    nvy = hrec[in].vy;
-    nvz = hrec[in].vz;
-    double d0 = b.x - xi, d1 = b.y - yi, d2 = b.z - zi;
+  int i = h0;
+  for (; i + 1 < h1; i += 2, p += 2) {
+    pair64<SHIFT, MASK>(A, b, g, thr, sx, sy, sz, i, p[0].x, p[0].y, p[0].z, p[0].r, p[0].vx,
+                        p[0].vy, p[0].vz);
+    pair64<SHIFT, MASK>(A, b, g, thr, sx, sy, sz, i + 1, p[1].x, p[1].y, p[1].z, p[1].r, p[1].vx,
+                        p[1].vy, p[1].vz);
+  }
+  if (i < h1)
+    pair64<SHIFT, MASK>(A, b, g, thr, sx, sy, sz, i, p[0].x, p[0].y, p[0].z, p[0].r, p[0].vx,
+                        p[0].vy, p[0].vz);
+}
+
+// One home sphere (FP32 record in scalar registers) against the lane's candidate.
+template <bool SHIFT, bool MASK>
+__device__ __forceinline__ void pair32(const DetectArgs &A, int g, int thr, int code, float bx,
+                                       float by, float bz, float br, float bvx, float bvy,
+                                       float bvz, int i, float ax, float ay, float az, float ar,
+                                       float avx, float avy, float avz, unsigned int *nrecheck) {
+  const float d0 = bx - ax, d1 = by - ay, d2 = bz - az;
+  const float u0 = bvx - avx, u1 = bvy - avy, u2 = bvz - avz;
+  const float sb = (ar + br) * A.kband;
+  const float bb = __builtin_fmaf(d0, u0, __builtin_fmaf(d1, u1, d2 * u2));
+  const float q = __builtin_fmaf(d0, d0, __builtin_fmaf(d1, d1, d2 * d2));
+  const float cc = __builtin_fmaf(-sb, sb, q);
+  if ((!MASK || i < thr) && __builtin_fmaf(bb, A.dt2f, cc) <= 0.0f) {
+    ++*nrecheck;
+    // binary64 rule for the survivor, from the full records
+    const Grid &G = A.G;
+    const crec_ptr hrec = (crec_ptr)A.rec;
+    const Rec b = A.rec[g];
+    const double xi = hrec[i].x, yi = hrec[i].y, zi = hrec[i].z, ri = hrec[i].r;
+    const double vxi = hrec[i].vx, vyi = hrec[i].vy, vzi = hrec[i].vz;
+    double e0 = b.x - xi, e1 = b.y - yi, e2 = b.z - zi;
     if (SHIFT) {
-      d0 = d0 + sx;
-      d1 = d1 + sy;
-      d2 = d2 + sz;
+      e0 = e0 + code_shift(code & 3, G.L[0]);
+      e1 = e1 + code_shift((code >> 2) & 3, G.L[1]);
+      e2 = e2 + code_shift((code >> 4) & 3, G.L[2]);
     }
-    const double u0 = b.vx - vxi, u1 = b.vy - vyi, u2 = b.vz - vzi;
-    const double s = ri + b.r;
-    const double bb = (d0 * u0 + d1 * u1) + d2 * u2;
-    const double cc = ((d0 * d0 + d1 * d1) + d2 * d2) - s * s;
-    // the cheap reject (with c > 0, c <= -b dt2 implies b < 0); in own-cell chunks
-    // only j > i is a candidate (thr = j there, INT_MAX elsewhere)
-    if ((!MASK || i < thr) && cc <= -bb * dt2) {
-      const double aa = (u0 * u0 + u1 * u1) + u2 * u2;
-      const double D = bb * bb - aa * cc;
-      if (cc > 0.0 && aa > 0.0 && D >= 0.0) {
-        const double t = cc / (-bb + __builtin_sqrt(D));
-        if (t <= dt) record_contact(A, i, g, t);
-      }
-    }
+    double t;
+    if (contact_time(e0, e1, e2, b.vx - vxi, b.vy - vyi, b.vz - vzi, ri + b.r, A.dt, t))
+      record_contact(A, i, g, t);
   }
 }
 
-typedef __attribute__((address_space(4))) const Rec32 *crec32_ptr;
-
-// FP32 form of detect_chunk: a conservative single-precision filter, then the
-// binary64 rule (identical to the plain path) for the pairs that pass.
-//
-// Coordinates are relative to the home cell centre (|x| <= 1.5 h for the
-// candidates), so each coordinate carries at most ulp32(1.5 h) / 2 of rounding.
-// The filter inflates the contact distance to s * kband and the step bound to
-// 2 dt (1 + 2^-12), and passes a pair iff  c' + b' * dt2f <= 0  with
-// c' = |d|^2 - (s kband)^2 and b' = d.u (explicit FMAs allowed: this is not the
-// rule's arithmetic).  Any pair the binary64 rule keeps has c <= 2|b| dt (1+6 eps);
-// the host picks kband so that 2 (kband - 1) s_min^2 exceeds twice a bound on the
-// FP32 errors of c' and b' dt2f over separations up to reach, so such a pair
-// always passes (pcol_api.hip, fp32_band).
-template <bool SHIFT, bool MASK>
-__device__ __forceinline__ void detect_chunk32(const DetectArgs &A, int h0, int h1, int g, int thr,
-                                               int code, double ox, double oy, double oz,
+template <bool SHIFT, bool MASK, typename HP>
+__device__ __forceinline__ void detect_chunk32(const DetectArgs &A, HP p, int h0, int h1, int g,
+                                               int thr, int code, double ox, double oy, double oz,
                                                unsigned int *nrecheck) {
-  const crec_ptr hrec = (crec_ptr)A.rec;
-  const crec32_ptr hrec32 = (crec32_ptr)A.rec32;
   const Grid &G = A.G;
   float bx, by, bz, bvx, bvy, bvz, br;
   if (thr >= 0) {
@@ -472,53 +499,36 @@ __device__ __forceinline__ void detect_chunk32(const DetectArgs &A, int h0, int 
     bvx = bvy = bvz = 0.f;
     br = 0.f;
   }
-  const float kband = A.kband, dt2f = A.dt2f;
-  // home record i+1 (FP32) is requested while pair (i, j) is tested
-  float nx = hrec32[h0].x, ny = hrec32[h0].y, nz = hrec32[h0].z, nr = hrec32[h0].r;
-  float nvx = hrec32[h0].vx, nvy = hrec32[h0].vy, nvz = hrec32[h0].vz;
-  for (int i = h0; i < h1; ++i) {
-    const float ax = nx, ay = ny, az = nz, ar = nr, avx = nvx, avy = nvy, avz = nvz;
-    const int in = i + 1 < h1 ? i + 1 : i;
-    nx = hrec32[in].x;
-    ny = hrec32[in].y;
-    nz = hrec32[in].z;
-    nr = hrec32[in].r;
-    nvx = hrec32[in].vx;
-    nvy = hrec32[in].vy;
-    nvz = hrec32[in].vz;
-    const float d0 = bx - ax, d1 = by - ay, d2 = bz - az;
-    const float u0 = bvx - avx, u1 = bvy - avy, u2 = bvz - avz;
-    const float sb = (ar + br) * kband;
-    const float bb = __builtin_fmaf(d0, u0, __builtin_fmaf(d1, u1, d2 * u2));
-    const float q = __builtin_fmaf(d0, d0, __builtin_fmaf(d1, d1, d2 * d2));
-    const float cc = __builtin_fmaf(-sb, sb, q);
-    if ((!MASK || i < thr) && __builtin_fmaf(bb, dt2f, cc) <= 0.0f) {
-      ++*nrecheck;
-      // binary64 rule for the survivor, from the full records
-      const Rec b = A.rec[g];
-      const double xi = hrec[i].x, yi = hrec[i].y, zi = hrec[i].z, ri = hrec[i].r;
-      const double vxi = hrec[i].vx, vyi = hrec[i].vy, vzi = hrec[i].vz;
-      double e0 = b.x - xi, e1 = b.y - yi, e2 = b.z - zi;
-      if (SHIFT) {
-        e0 = e0 + code_shift(code & 3, G.L[0]);
-        e1 = e1 + code_shift((code >> 2) & 3, G.L[1]);
-        e2 = e2 + code_shift((code >> 4) & 3, G.L[2]);
-      }
-      double t;
-      if (contact_time(e0, e1, e2, b.vx - vxi, b.vy - vyi, b.vz - vzi, ri + b.r, A.dt, t))
-        record_contact(A, i, g, t);
-    }
+  int i = h0;
+  for (; i + 1 < h1; i += 2, p += 2) {
+    pair32<SHIFT, MASK>(A, g, thr, code, bx, by, bz, br, bvx, bvy, bvz, i, p[0].x, p[0].y, p[0].z,
+                        p[0].r, p[0].vx, p[0].vy, p[0].vz, nrecheck);
+    pair32<SHIFT, MASK>(A, g, thr, code, bx, by, bz, br, bvx, bvy, bvz, i + 1, p[1].x, p[1].y,
+                        p[1].z, p[1].r, p[1].vx, p[1].vy, p[1].vz, nrecheck);
   }
+  if (i < h1)
+    pair32<SHIFT, MASK>(A, g, thr, code, bx, by, bz, br, bvx, bvy, bvz, i, p[0].x, p[0].y, p[0].z,
+                        p[0].r, p[0].vx, p[0].vy, p[0].vz, nrecheck);
 }
 
-template <bool FP32>
+template <bool FP32, bool LDSI>
 __global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
+  extern __shared__ double4 lds_raw[];  // LDSI: the home cell's records (Rec or Rec32)
   const Grid &G = A.G;
   const int cell = xcd_remap(blockIdx.x, gridDim.x);
   const int nc0 = G.nc[0], nc1 = G.nc[1], nc2 = G.nc[2];
   const int cx = cell % nc0, cy = (cell / nc0) % nc1, cz = cell / (nc0 * nc1);
   const int h0 = A.start[cell], h1 = A.start[cell + 1];
   if (h1 <= h0) return;
+  if (LDSI) {  // stage the home cell (cap >= occupancy of every cell)
+    for (int k = threadIdx.x; k < h1 - h0; k += WAVE) {
+      if (FP32)
+        ((Rec32 *)lds_raw)[k] = A.rec32[h0 + k];
+      else
+        ((Rec *)lds_raw)[k] = A.rec[h0 + k];
+    }
+    __syncthreads();
+  }
 
   // runs of consecutive sorted records: global start, length, shift code
   int rg[MAXRUN], rl[MAXRUN], rc[MAXRUN];
@@ -612,29 +622,61 @@ __global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
                  sz = code_shift((code >> 4) & 3, G.L[2]);
     if (FP32) {
       const double ox = (cx + 0.5) * G.h[0], oy = (cy + 0.5) * G.h[1], oz = (cz + 0.5) * G.h[2];
-      if (base < rl[0]) {
-        if (any_shift)
-          detect_chunk32<true, true>(A, h0, h1, g, thr, code, ox, oy, oz, &nrc);
-        else
-          detect_chunk32<false, true>(A, h0, h1, g, thr, code, ox, oy, oz, &nrc);
+      if (LDSI) {
+        const Rec32 *p = (const Rec32 *)lds_raw;
+        if (base < rl[0]) {
+          if (any_shift)
+            detect_chunk32<true, true>(A, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
+          else
+            detect_chunk32<false, true>(A, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
+        } else {
+          if (any_shift)
+            detect_chunk32<true, false>(A, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
+          else
+            detect_chunk32<false, false>(A, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
+        }
       } else {
-        if (any_shift)
-          detect_chunk32<true, false>(A, h0, h1, g, thr, code, ox, oy, oz, &nrc);
-        else
-          detect_chunk32<false, false>(A, h0, h1, g, thr, code, ox, oy, oz, &nrc);
+        const crec32_ptr p = (crec32_ptr)A.rec32 + h0;
+        if (base < rl[0]) {
+          if (any_shift)
+            detect_chunk32<true, true>(A, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
+          else
+            detect_chunk32<false, true>(A, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
+        } else {
+          if (any_shift)
+            detect_chunk32<true, false>(A, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
+          else
+            detect_chunk32<false, false>(A, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
+        }
       }
       continue;
     }
-    if (base < rl[0]) {  // chunk holds own-cell candidates
-      if (any_shift)
-        detect_chunk<true, true>(A, h0, h1, g, thr, sx, sy, sz);
-      else
-        detect_chunk<false, true>(A, h0, h1, g, thr, 0.0, 0.0, 0.0);
+    if (LDSI) {
+      const Rec *p = (const Rec *)lds_raw;
+      if (base < rl[0]) {  // chunk holds own-cell candidates
+        if (any_shift)
+          detect_chunk<true, true>(A, p, h0, h1, g, thr, sx, sy, sz);
+        else
+          detect_chunk<false, true>(A, p, h0, h1, g, thr, 0.0, 0.0, 0.0);
+      } else {
+        if (any_shift)
+          detect_chunk<true, false>(A, p, h0, h1, g, thr, sx, sy, sz);
+        else
+          detect_chunk<false, false>(A, p, h0, h1, g, thr, 0.0, 0.0, 0.0);
+      }
     } else {
-      if (any_shift)
-        detect_chunk<true, false>(A, h0, h1, g, thr, sx, sy, sz);
-      else
-        detect_chunk<false, false>(A, h0, h1, g, thr, 0.0, 0.0, 0.0);
+      const crec_ptr p = (crec_ptr)A.rec + h0;
+      if (base < rl[0]) {
+        if (any_shift)
+          detect_chunk<true, true>(A, p, h0, h1, g, thr, sx, sy, sz);
+        else
+          detect_chunk<false, true>(A, p, h0, h1, g, thr, 0.0, 0.0, 0.0);
+      } else {
+        if (any_shift)
+          detect_chunk<true, false>(A, p, h0, h1, g, thr, sx, sy, sz);
+        else
+          detect_chunk<false, false>(A, p, h0, h1, g, thr, 0.0, 0.0, 0.0);
+      }
     }
   }
   if (FP32) {
@@ -645,10 +687,18 @@ __global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
 
 hipError_t launch_detect_half(hipStream_t s, const DetectArgs &A) {
   if (A.G.ncell <= 0) return hipSuccess;
-  if (A.fp32)
-    hipLaunchKernelGGL(k_detect_half<true>, dim3(A.G.ncell), dim3(WAVE), 0, s, A);
-  else
-    hipLaunchKernelGGL(k_detect_half<false>, dim3(A.G.ncell), dim3(WAVE), 0, s, A);
+  const size_t lds = (size_t)A.cap * (A.fp32 ? sizeof(Rec32) : sizeof(Rec));
+  if (A.cap > 0) {
+    if (A.fp32)
+      hipLaunchKernelGGL((k_detect_half<true, true>), dim3(A.G.ncell), dim3(WAVE), lds, s, A);
+    else
+      hipLaunchKernelGGL((k_detect_half<false, true>), dim3(A.G.ncell), dim3(WAVE), lds, s, A);
+  } else {
+    if (A.fp32)
+      hipLaunchKernelGGL((k_detect_half<true, false>), dim3(A.G.ncell), dim3(WAVE), 0, s, A);
+    else
+      hipLaunchKernelGGL((k_detect_half<false, false>), dim3(A.G.ncell), dim3(WAVE), 0, s, A);
+  }
   return hipGetLastError();
 }
 
