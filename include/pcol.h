@@ -187,6 +187,32 @@ pcol_status pcol_advance(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, 
 pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, double dt, double e,
                       int32_t *partner, double *tcoll, pcol_stats *stats);
 
+/* Gradient of a scalar loss with respect to the positions and velocities of
+ * all spheres (device arrays, caller order, n each). */
+typedef struct {
+  double *x, *y, *z;
+  double *vx, *vy, *vz;
+} pcol_state_grad;
+
+/* Adjoint of one pcol_step with its pair set held fixed (reverse mode; the
+ * derivative of rule 4 and of the contact time of rule 1, which depends on the
+ * start positions and velocities through |d + t u| = r_i + r_j).  For a
+ * multi-step rollout call it once per step in reverse order; the checkpoint of
+ * a step is its start state and its pair record.
+ *   start:   the step's start-of-step state (x, y, z, vx, vy, vz, r, m), read only.
+ *   partner, tcoll: that step's outputs of pcol_step (device, caller order).
+ *   g_out:   gradient with respect to the step's end-of-step state (read only).
+ *   g_in:    receives the gradient with respect to the start state; its arrays
+ *            must not alias g_out's.
+ *   ge:      device double scalar; the gradient with respect to e is ADDED to it
+ *            (summed in a fixed order, so repeated runs agree bitwise).
+ * Positions are differentiated through the periodic wrap as the identity (the
+ * wrap shifts by a constant).  Uses context scratch for n_max spheres; no
+ * readback, asynchronous. */
+pcol_status pcol_step_backward(pcol_ctx *ctx, const pcol_particles *start, const pcol_box *box,
+                               double dt, double e, const int32_t *partner, const double *tcoll,
+                               const pcol_state_grad *g_out, pcol_state_grad *g_in, double *ge);
+
 #ifdef __cplusplus
 }
 #endif

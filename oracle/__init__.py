@@ -7,7 +7,8 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 it, and the two share no code.
 
 Pins of this oracle against the paper and the mathematics are in
-``tests/test_oracle_pins.py``.
+``tests/test_oracle_pins.py``; the forward-mode derivative ``step_jvp`` is
+pinned in ``tests/test_oracle_jvp.py``.
 """
 from __future__ import annotations
 
@@ -64,6 +65,10 @@ def _load():
         lib.orc_earliest_subset.argtypes = [ctypes.c_int64] + [_D] * 7 + [_D, ctypes.c_double, _U8,
                                                                          ctypes.c_int64, _I64, _I64, _D]
         lib.orc_earliest_subset.restype = ctypes.c_int
+        lib.orc_step_jvp.argtypes = [ctypes.c_int64] + [_D] * 8 + [_D, ctypes.c_double,
+                                                                  ctypes.c_double] + [_D] * 6 + \
+            [ctypes.c_double] + [_D] * 12 + [_I64]
+        lib.orc_step_jvp.restype = ctypes.c_int
         lib.orc_resolve_pair.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_double] + [_D] * 8 + \
             [_D, ctypes.c_double, ctypes.c_double] + [_D] * 6
         lib.orc_resolve_pair.restype = None
@@ -172,6 +177,26 @@ def step(box, *, e: float | None = None, grid: bool = True, cell_mult: float = 1
         raise OracleError(rc)
     return StepResult(*outs, partner, tcoll, sweep, st.n_pairs, st.n_sweeps, st.pair_tests,
                       st.reach)
+
+
+def step_jvp(box, dx, dv, de: float, *, e: float | None = None):
+    """One step and its forward-mode derivative along (dx, dv, de), pair set fixed.
+
+    dx, dv: arrays of shape (3, n).  Returns (StateTuple x, v as (3, n) arrays,
+    tangent tx, tv as (3, n) arrays, partner)."""
+    n = box.n
+    arrs = [_c64(a) for a in (box.x, box.y, box.z, box.vx, box.vy, box.vz, box.r, box.m)]
+    tin = [_c64(a) for a in (dx[0], dx[1], dx[2], dv[0], dv[1], dv[2])]
+    outs = [np.empty(n) for _ in range(12)]
+    partner = np.empty(n, dtype=np.int64)
+    L = _c64(box.L)
+    rc = _load().orc_step_jvp(n, *[_d(a) for a in arrs], _d(L), float(box.dt),
+                              float(box.e if e is None else e), *[_d(a) for a in tin], float(de),
+                              *[_d(o) for o in outs], partner.ctypes.data_as(_I64))
+    if rc:
+        raise OracleError(rc)
+    return (np.array(outs[0:3]), np.array(outs[3:6]), np.array(outs[6:9]), np.array(outs[9:12]),
+            partner)
 
 
 def resolve_pair(box, i: int, j: int, t: float, *, e: float | None = None):

@@ -508,3 +508,95 @@ int orc_step(int64_t n, const double *x, const double *y, const double *z, const
   free(pt);
   return rc;
 }
+
+/*
+ * Forward-mode derivative (Jacobian-vector product) of one step with the pair
+ * set held fixed at the primal's: the same sweeps pick the pairs, then every
+ * quantity of the resolve carries a tangent (Sec. "Inter-Particle Collisions"
+ * and eq. update_vel/update_rho differentiated by hand).
+ *
+ * For a pair (i, j) with d = x_j - x_i, u = v_j - v_i, contact time t, w = d + t u,
+ * n = w / s, g = u . n, c = m_r (1 + e), J = c g:
+ *   the contact condition |w|^2 = s^2 gives  t' = -(n . d' + t n . u') / g,
+ *   w' = d' + t u' + t' u,  n' = w' / s,  g' = u' . n + u . n',
+ *   J' = c g' + m_r g e',
+ *   v_i' -> v_i' + (J'/m_i) n + (J/m_i) n',   v_j' -> v_j' - (J'/m_j) n - (J/m_j) n',
+ *   x_i' -> x_i' + t' (v_i - v_i_new) + t v_i' + (dt - t) v_i_new'.
+ * Spheres without a collision: x' = x + dt v'  (tangent), v' unchanged.
+ * Periodic wraps shift by constants and do not enter the tangents.
+ * Tangent inputs dx, dy, dz, dvx, dvy, dvz (arrays) and de; tangent outputs
+ * tx.., tv... Also writes the primal like orc_step.
+ */
+int orc_step_jvp(int64_t n, const double *x, const double *y, const double *z, const double *vx,
+                 const double *vy, const double *vz, const double *r, const double *m,
+                 const double L[3], double dt, double e, const double *dx, const double *dy,
+                 const double *dz, const double *dvx, const double *dvy, const double *dvz,
+                 double de, double *xo, double *yo, double *zo, double *vxo, double *vyo,
+                 double *vzo, double *txo, double *tyo, double *tzo, double *tvxo, double *tvyo,
+                 double *tvzo, int64_t *partner) {
+  const size_t nn = (size_t)(n > 0 ? n : 1);
+  double *tc = (double *)malloc(nn * sizeof(double));
+  int64_t *pp = partner ? partner : (int64_t *)malloc(nn * sizeof(int64_t));
+  if (!tc || !pp) {
+    free(tc);
+    if (!partner) free(pp);
+    return ORC_E_NOMEM;
+  }
+  int rc = orc_step(n, x, y, z, vx, vy, vz, r, m, L, dt, e, 1, 1.0, 0, xo, yo, zo, vxo, vyo, vzo,
+                    pp, tc, NULL, NULL);
+  if (rc == ORC_OK) {
+    const double *X[3] = {x, y, z}, *V[3] = {vx, vy, vz};
+    const double *DX[3] = {dx, dy, dz}, *DV[3] = {dvx, dvy, dvz};
+    double *TX[3] = {txo, tyo, tzo}, *TV[3] = {tvxo, tvyo, tvzo};
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t j = pp[i];
+      if (j < 0) {
+        for (int k = 0; k < 3; ++k) {
+          TX[k][i] = DX[k][i] + dt * DV[k][i];
+          TV[k][i] = DV[k][i];
+        }
+        continue;
+      }
+      /* primal of the pair from i's side (n points from i to j) */
+      const double t = tc[i];
+      double d[3], u[3], w[3], nv[3];
+      for (int k = 0; k < 3; ++k) {
+        d[k] = orc_wrap_sep(X[k][j] - X[k][i], L[k]);
+        u[k] = V[k][j] - V[k][i];
+      }
+      const double s = r[i] + r[j];
+      for (int k = 0; k < 3; ++k) {
+        w[k] = d[k] + t * u[k];
+        nv[k] = w[k] / s;
+      }
+      const double g = (u[0] * nv[0] + u[1] * nv[1]) + u[2] * nv[2];
+      const double mr = (m[i] * m[j]) / (m[i] + m[j]);
+      const double c = mr * (1.0 + e);
+      const double J = c * g;
+      /* tangents */
+      double dd[3], du[3];
+      for (int k = 0; k < 3; ++k) {
+        dd[k] = DX[k][j] - DX[k][i];
+        du[k] = DV[k][j] - DV[k][i];
+      }
+      const double nd = nv[0] * dd[0] + nv[1] * dd[1] + nv[2] * dd[2];
+      const double nu = nv[0] * du[0] + nv[1] * du[1] + nv[2] * du[2];
+      const double tt = -(nd + t * nu) / g;
+      double dn[3];
+      for (int k = 0; k < 3; ++k) dn[k] = (dd[k] + t * du[k] + tt * u[k]) / s;
+      const double dg = (du[0] * nv[0] + du[1] * nv[1] + du[2] * nv[2]) +
+                        (u[0] * dn[0] + u[1] * dn[1] + u[2] * dn[2]);
+      const double dJ = c * dg + mr * g * de;
+      for (int k = 0; k < 3; ++k) {
+        const double vnew = V[k][i] + (J / m[i]) * nv[k];
+        const double dvnew = DV[k][i] + (dJ / m[i]) * nv[k] + (J / m[i]) * dn[k];
+        TV[k][i] = dvnew;
+        TX[k][i] = DX[k][i] + tt * (V[k][i] - vnew) + t * DV[k][i] + (dt - t) * dvnew;
+      }
+    }
+  }
+  free(tc);
+  if (!partner) free(pp);
+  return rc;
+}

@@ -63,6 +63,10 @@ class pcol_stats(ctypes.Structure):
         return out
 
 
+class pcol_state_grad(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("x", "y", "z", "vx", "vy", "vz")]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
@@ -92,6 +96,10 @@ def _load():
     lib.pcol_step.argtypes = [ctx_p, P(pcol_particles), P(pcol_box), ctypes.c_double,
                               ctypes.c_double, V, V, P(pcol_stats)]
     lib.pcol_step.restype = ctypes.c_int
+    lib.pcol_step_backward.argtypes = [ctx_p, P(pcol_particles), P(pcol_box), ctypes.c_double,
+                                       ctypes.c_double, V, V, P(pcol_state_grad),
+                                       P(pcol_state_grad), V]
+    lib.pcol_step_backward.restype = ctypes.c_int
     return lib
 
 
@@ -99,7 +107,7 @@ lib = _load()
 
 EXPORTED = ["pcol_default_opts", "pcol_create", "pcol_destroy", "pcol_last_error",
             "pcol_set_stream", "pcol_bin", "pcol_detect", "pcol_resolve", "pcol_advance",
-            "pcol_step"]
+            "pcol_step", "pcol_step_backward"]
 
 
 class PcolError(RuntimeError):
@@ -276,3 +284,83 @@ def pcol_step(ctx: Context, p: Particles, L, dt: float, e: float, partner=None, 
                             float(e), _ptr(partner, torch.int32, n), _ptr(tcoll, torch.float64, n),
                             ctypes.byref(st) if st is not None else None))
     return st.as_dict() if st is not None else None
+
+
+def _grad_struct(ts, n):
+    return pcol_state_grad(*[_ptr(t, torch.float64, n) for t in ts])
+
+
+def pcol_step_backward(ctx: Context, start: Particles, L, dt: float, e: float, partner, tcoll,
+                       g_out, g_in, ge) -> None:
+    """Adjoint of one step (pair set fixed).  g_out, g_in: sequences of six float64
+    tensors (x, y, z, vx, vy, vz); ge: float64 scalar tensor, accumulated."""
+    n = start.n
+    ctx.sync_stream()
+    ps = start.struct()
+    go = _grad_struct(g_out, n)
+    gi = _grad_struct(g_in, n)
+    ctx.check(lib.pcol_step_backward(ctx.handle, ctypes.byref(ps), ctypes.byref(_box(L)),
+                                     float(dt), float(e), _ptr(partner, torch.int32, n),
+                                     _ptr(tcoll, torch.float64, n), ctypes.byref(go),
+                                     ctypes.byref(gi), _ptr(ge, torch.float64)))
+
+
+class Rollout(torch.autograd.Function):
+    """``nsteps`` collision steps as a differentiable function of the initial
+    positions, velocities and the restitution coefficient e (pair sets held fixed
+    at those of the forward pass).  Every ``checkpoint_every``-th start state is
+    kept together with every step's pair record (partner, contact time); the
+    backward pass recomputes the other start states by stepping forward from the
+    nearest checkpoint (the step is deterministic, so the pair sets repeat
+    bitwise), then applies pcol_step_backward step by step in reverse."""
+
+    @staticmethod
+    def forward(fctx, x, y, z, vx, vy, vz, e, r, m, L, dt, nsteps, pctx, checkpoint_every=1):
+        n = x.shape[0]
+        p = Particles(x.detach().clone(), y.detach().clone(), z.detach().clone(),
+                      vx.detach().clone(), vy.detach().clone(), vz.detach().clone(), r, m)
+        ev = float(e)
+        ckpt, records = {}, []
+        for k in range(nsteps):
+            if k % checkpoint_every == 0:
+                ckpt[k] = [t.clone() for t in p.tensors()[:6]]
+            partner = torch.empty(n, dtype=torch.int32, device=x.device)
+            tcoll = torch.empty(n, dtype=torch.float64, device=x.device)
+            pcol_step(pctx, p, L, dt, ev, partner, tcoll, stats=False)
+            records.append((partner, tcoll))
+        fctx.ckpt, fctx.records = ckpt, records
+        fctx.meta = (L, dt, ev, nsteps, pctx, checkpoint_every, r, m)
+        return p.x, p.y, p.z, p.vx, p.vy, p.vz
+
+    @staticmethod
+    def backward(fctx, *grads):
+        L, dt, ev, nsteps, pctx, every, r, m = fctx.meta
+        n = r.shape[0]
+        g = [gr.contiguous() if gr is not None else torch.zeros(n, dtype=torch.float64, device=r.device)
+             for gr in grads]
+        ge = torch.zeros((), dtype=torch.float64, device=r.device)
+        cache = {}
+        for k in reversed(range(nsteps)):
+            if k not in cache:  # recompute the start states of this checkpoint segment
+                base = (k // every) * every
+                s = [t.clone() for t in fctx.ckpt[base]]
+                cache = {base: [t.clone() for t in s]}
+                p = Particles(*s, r, m)
+                for q in range(base, k):
+                    partner = torch.empty(n, dtype=torch.int32, device=r.device)
+                    tcoll = torch.empty(n, dtype=torch.float64, device=r.device)
+                    pcol_step(pctx, p, L, dt, ev, partner, tcoll, stats=False)
+                    cache[q + 1] = [t.clone() for t in p.tensors()[:6]]
+            start = Particles(*cache[k], r, m)
+            partner, tcoll = fctx.records[k]
+            gin = [torch.empty_like(t) for t in g]
+            pcol_step_backward(pctx, start, L, dt, ev, partner, tcoll, g, gin, ge)
+            g = gin
+        return (*g, ge, None, None, None, None, None, None, None)
+
+
+def rollout(p: Particles, e, L, dt: float, nsteps: int, ctx: Context, checkpoint_every: int = 1):
+    """Differentiable multi-step rollout; returns the final (x, y, z, vx, vy, vz).
+    e: float64 0-d tensor (requires_grad for its gradient)."""
+    return Rollout.apply(p.x, p.y, p.z, p.vx, p.vy, p.vz, e, p.r, p.m, L, dt, nsteps, ctx,
+                         checkpoint_every)

@@ -545,4 +545,27 @@ pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, dou
   return PCOL_OK;
 }
 
+pcol_status pcol_step_backward(pcol_ctx *ctx, const pcol_particles *start, const pcol_box *box,
+                               double dt, double e, const int32_t *partner, const double *tcoll,
+                               const pcol_state_grad *g_out, pcol_state_grad *g_in, double *ge) {
+  pcol_status st = check_common(ctx, start, box, dt);
+  if (st != PCOL_OK) return st;
+  if (!(e >= 0.0 && e <= 1.0)) return fail(ctx, PCOL_E_INVALID, "e outside [0, 1]");
+  if (!g_out || !g_in || !ge) return fail(ctx, PCOL_E_INVALID, "null gradient argument");
+  if (start->n > 0 && (!partner || !tcoll || !g_out->x || !g_out->y || !g_out->z || !g_out->vx ||
+                       !g_out->vy || !g_out->vz || !g_in->x || !g_in->y || !g_in->z ||
+                       !g_in->vx || !g_in->vy || !g_in->vz))
+    return fail(ctx, PCOL_E_INVALID, "null array");
+  Grid G{};
+  for (int a = 0; a < 3; ++a) {
+    G.L[a] = box->len[a];
+    G.halfL[a] = 0.5 * box->len[a];
+  }
+  StateGrad go{g_out->x, g_out->y, g_out->z, g_out->vx, g_out->vy, g_out->vz};
+  StateGrad gi{g_in->x, g_in->y, g_in->z, g_in->vx, g_in->vy, g_in->vz};
+  PCOL_HIP(launch_step_backward(ctx->stream, to_dev(start), G, dt, e, partner, tcoll, go, gi,
+                                ctx->key_t, ge));
+  return PCOL_OK;
+}
+
 }  // extern "C"

@@ -159,6 +159,11 @@ struct Particles {
   const double *r, *m;
 };
 
+// gradient with respect to a step's positions and velocities (SoA)
+struct StateGrad {
+  double *x, *y, *z, *vx, *vy, *vz;
+};
+
 // Everything the sweep-1 detect needs.
 struct DetectArgs {
   const Rec *rec;
@@ -217,6 +222,10 @@ hipError_t launch_status_from_active(hipStream_t s, const uint8_t *active, const
 hipError_t launch_export_keys(hipStream_t s, int n, const int *perm, const int *key_j,
                               const double *key_t, const uint8_t *status, uint64_t *key_out,
                               double *tmin_out);
+hipError_t launch_step_backward(hipStream_t s, const Particles &P, const Grid &G, double dt,
+                                double e, const int *partner, const double *tcoll,
+                                const StateGrad &gout, const StateGrad &gin, double *ebuf,
+                                double *ge);
 hipError_t launch_resolve_public(hipStream_t s, int n, const Rec *rec, const int *rank,
                                  const Grid &G, double dt, double e, const uint64_t *key,
                                  const Particles &P, uint8_t *active, int *partner, double *tcoll,

@@ -1111,3 +1111,129 @@ hipError_t launch_resolve_public(hipStream_t s, int n, const Rec *rec, const int
 }
 
 }  // namespace pcol
+
+namespace pcol {
+
+// ---------------------------------------------------------------- adjoint of one step
+
+// Reverse-mode derivative of one step with the pair set fixed (caller order).
+// Forward quantities of a pair (i, j) from i's side, as in resolve_one:
+//   d = x_j - x_i (minimum image), u = v_j - v_i, t = contact time, w = d + t u,
+//   n = w / s, g = u . n, c = m_r (1 + e), J = c g,
+//   vi' = v_i + (J/m_i) n,  vj' = v_j - (J/m_j) n,
+//   xi' = x_i + t v_i + (dt - t) vi',  xj' = x_j + t v_j + (dt - t) vj'.
+// The contact time depends on (d, u) through |d + t u| = s:  dt/dd = -n/g,
+// dt/du = -t n/g.  Given the gradients G of the loss with respect to the
+// end-of-step state of i and j, the sweep of adjoints below returns the
+// gradient with respect to i's start state; each thread writes only its own
+// sphere, and the e-gradient of the pair is stored once (by the smaller index).
+// Spheres without a collision: x' = x + dt v gives gx = Gx, gv = Gv + dt Gx.
+__global__ __launch_bounds__(256) void k_step_backward(int n, const double *x, const double *y,
+                                                       const double *z, const double *vx,
+                                                       const double *vy, const double *vz,
+                                                       const double *r, const double *m, Grid G,
+                                                       double dt, double e, const int *partner,
+                                                       const double *tcoll, StateGrad gout,
+                                                       StateGrad gin, double *ebuf) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int j = partner[i];
+  const double Gxi[3] = {gout.x[i], gout.y[i], gout.z[i]};
+  const double Gvi[3] = {gout.vx[i], gout.vy[i], gout.vz[i]};
+  if (j < 0) {
+    gin.x[i] = Gxi[0];
+    gin.y[i] = Gxi[1];
+    gin.z[i] = Gxi[2];
+    gin.vx[i] = Gvi[0] + dt * Gxi[0];
+    gin.vy[i] = Gvi[1] + dt * Gxi[1];
+    gin.vz[i] = Gvi[2] + dt * Gxi[2];
+    ebuf[i] = 0.0;
+    return;
+  }
+  const double Gxj[3] = {gout.x[j], gout.y[j], gout.z[j]};
+  const double Gvj[3] = {gout.vx[j], gout.vy[j], gout.vz[j]};
+  const double xi[3] = {x[i], y[i], z[i]}, xj[3] = {x[j], y[j], z[j]};
+  const double vi[3] = {vx[i], vy[i], vz[i]}, vj[3] = {vx[j], vy[j], vz[j]};
+  const double t = tcoll[i];
+  double d[3], u[3], nn[3];
+  for (int k = 0; k < 3; ++k) {
+    d[k] = wrap_sep(xj[k] - xi[k], G.L[k], G.halfL[k]);
+    u[k] = vj[k] - vi[k];
+  }
+  const double s = r[i] + r[j];
+  for (int k = 0; k < 3; ++k) nn[k] = (d[k] + t * u[k]) / s;
+  const double g = (u[0] * nn[0] + u[1] * nn[1]) + u[2] * nn[2];
+  const double mr = (m[i] * m[j]) / (m[i] + m[j]);
+  const double c = mr * (1.0 + e);
+  const double J = c * g;
+  double vin[3], vjn[3];
+  for (int k = 0; k < 3; ++k) {
+    vin[k] = vi[k] + (J / m[i]) * nn[k];
+    vjn[k] = vj[k] - (J / m[j]) * nn[k];
+  }
+  // adjoints
+  double tb = 0.0, Jb = 0.0, bvi[3], bvj[3], bvin[3], bvjn[3], bn[3], bu[3], bd[3];
+  for (int k = 0; k < 3; ++k) {
+    tb += Gxi[k] * (vi[k] - vin[k]) + Gxj[k] * (vj[k] - vjn[k]);
+    bvin[k] = Gvi[k] + (dt - t) * Gxi[k];
+    bvjn[k] = Gvj[k] + (dt - t) * Gxj[k];
+    bvi[k] = t * Gxi[k] + bvin[k];
+    bvj[k] = t * Gxj[k] + bvjn[k];
+    Jb += bvin[k] * nn[k] / m[i] - bvjn[k] * nn[k] / m[j];
+    bn[k] = (J / m[i]) * bvin[k] - (J / m[j]) * bvjn[k];
+  }
+  const double gb = c * Jb;
+  const double eb = mr * g * Jb;
+  for (int k = 0; k < 3; ++k) {
+    bu[k] = gb * nn[k];
+    bn[k] += gb * u[k];
+  }
+  double wb[3];
+  for (int k = 0; k < 3; ++k) {
+    wb[k] = bn[k] / s;
+    bd[k] = wb[k];
+    tb += wb[k] * u[k];
+    bu[k] += t * wb[k];
+  }
+  for (int k = 0; k < 3; ++k) {
+    bd[k] += (-tb / g) * nn[k];
+    bu[k] += (-tb * t / g) * nn[k];
+  }
+  // d = x_j - x_i, u = v_j - v_i
+  gin.x[i] = Gxi[0] - bd[0];
+  gin.y[i] = Gxi[1] - bd[1];
+  gin.z[i] = Gxi[2] - bd[2];
+  gin.vx[i] = bvi[0] - bu[0];
+  gin.vy[i] = bvi[1] - bu[1];
+  gin.vz[i] = bvi[2] - bu[2];
+  (void)bvj;
+  ebuf[i] = i < j ? eb : 0.0;
+}
+
+// deterministic sum of v[0..n) (fixed tree order) added to *out; one block
+__global__ __launch_bounds__(1024) void k_sum_det(const double *v, int n, double *out) {
+  __shared__ double part[1024];
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < n; k += 1024) acc += v[k];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out += part[0];
+}
+
+hipError_t launch_step_backward(hipStream_t s, const Particles &P, const Grid &G, double dt,
+                                double e, const int *partner, const double *tcoll,
+                                const StateGrad &gout, const StateGrad &gin, double *ebuf,
+                                double *ge) {
+  const int n = (int)P.n;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_step_backward, dim3((n + 255) / 256), dim3(256), 0, s, n, P.x, P.y, P.z,
+                     P.vx, P.vy, P.vz, P.r, P.m, G, dt, e, partner, tcoll, gout, gin, ebuf);
+  hipLaunchKernelGGL(k_sum_det, dim3(1), dim3(1024), 0, s, ebuf, n, ge);
+  return hipGetLastError();
+}
+
+}  // namespace pcol

@@ -1,0 +1,138 @@
+"""GPU tests of the hand-written adjoint (pcol_step_backward behind
+torch.autograd): duality with the oracle's forward-mode derivative, central
+finite differences on the 1M-sphere, 10-step rollout with a learnable e,
+checkpoint recomputation and determinism."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+pc = pytest.importorskip("paper_2501_05340_amd")
+
+FIELDS = ("x", "y", "z", "vx", "vy", "vz")
+
+
+def _leaf(box):
+    p = pc.Particles.from_box(box)
+    ts = [getattr(p, f).clone().requires_grad_(True) for f in FIELDS]
+    e = torch.tensor(box.e, dtype=torch.float64, device="cuda", requires_grad=True)
+    return p, ts, e
+
+
+def test_adjoint_is_dual_to_oracle_jvp():
+    """<G, J q> from the oracle's tangent (chained over 4 steps) equals <J^T G, q>
+    from the GPU adjoint, for random G and q including the e direction."""
+    box = workloads.make_box(3000, seed=21, phi=0.25, lognormal=(0.5, 0.3, 0.25, 1.0), e=0.8,
+                             dt=0.15)
+    nsteps = 4
+    rng = np.random.default_rng(1)
+    n = box.n
+    G = rng.normal(size=(6, n))
+    q_x, q_v, q_e = rng.normal(size=(3, n)), rng.normal(size=(3, n)), float(rng.normal())
+    # oracle: primal and tangent through the steps
+    b = box.copy()
+    tx, tv, te = q_x, q_v, q_e
+    for _ in range(nsteps):
+        xo, vo, tx, tv, _ = oracle.step_jvp(b, tx, tv, te)
+        b = workloads.Box(*xo, *vo, b.r, b.m, b.L, b.dt, b.e)
+    jq = float(np.sum(G[:3] * tx) + np.sum(G[3:] * tv))
+    # GPU: forward rollout and adjoint
+    p, ts, e = _leaf(box)
+    ctx = pc.Context(n)
+    out = pc.Rollout.apply(*ts, e, p.r, p.m, box.L, box.dt, nsteps, ctx, 1)
+    for k, f in enumerate(FIELDS):
+        ref = getattr(b, f)
+        assert np.array_equal(out[k].detach().cpu().numpy(), ref)  # primal bitwise
+    loss = sum((out[k] * torch.from_numpy(G[k]).cuda()).sum() for k in range(6))
+    loss.backward()
+    g_in = [t.grad.cpu().numpy() for t in ts]
+    jtg_q = float(np.sum(np.array(g_in[:3]) * q_x) + np.sum(np.array(g_in[3:]) * q_v) +
+                  e.grad.item() * q_e)
+    assert jtg_q == pytest.approx(jq, rel=1e-10)
+
+
+@pytest.fixture(scope="module")
+def cfg5():
+    return workloads.config(5)
+
+
+def _final_state(p0, e, box, nsteps, ctx, partners=None):
+    p = p0.clone()
+    seen = []
+    n = box.n
+    for k in range(nsteps):
+        partner = torch.empty(n, dtype=torch.int32, device="cuda")
+        pc.pcol_step(ctx, p, box.L, box.dt, e, partner, None, stats=False)
+        seen.append(partner)
+    same = partners is None or all(torch.equal(a, b) for a, b in zip(seen, partners))
+    loss = (p.vx * p.vx + p.vy * p.vy + p.vz * p.vz).sum().item()
+    return loss, seen, same
+
+
+@pytest.mark.timeout(900)
+def test_config5_adjoint_matches_central_differences(cfg5):
+    """1M spheres (phi 0.2, r = 1), 10 FP64 steps, e = 0.9 learnable, loss = sum |v|^2;
+    64 random unit directions in (v0, e) space, central differences with h = 1e-6.
+    Directions whose +-h runs change any pair set are excluded and counted."""
+    box = cfg5
+    nsteps = 10
+    n = box.n
+    ctx = pc.Context(n)
+    p0, ts, e = _leaf(box)
+    out = pc.Rollout.apply(*ts, e, p0.r, p0.m, box.L, box.dt, nsteps, ctx, 1)
+    loss = (out[3] * out[3] + out[4] * out[4] + out[5] * out[5]).sum()
+    loss.backward()
+    gv = torch.stack([t.grad for t in ts[3:]])          # (3, n)
+    ge = e.grad.item()
+    gnorm = float(torch.sqrt((gv * gv).sum() + ge * ge).item())
+    base_loss, base_partners, _ = _final_state(p0, box.e, box, nsteps, ctx)
+    assert base_loss == pytest.approx(loss.item(), rel=0, abs=0)
+    rng = np.random.default_rng(5)
+    h = 1e-6
+    valid, excluded, worst = 0, 0, 0.0
+    for d in range(64):
+        q = rng.normal(size=3 * n + 1)
+        q /= np.linalg.norm(q)
+        qv = torch.from_numpy(q[:-1].reshape(3, n)).cuda()
+        qe = float(q[-1])
+        pred = float((gv * qv).sum().item()) + ge * qe
+        fd = []
+        ok = True
+        for sgn in (1, -1):
+            pp = p0.clone()
+            pp.vx += sgn * h * qv[0]
+            pp.vy += sgn * h * qv[1]
+            pp.vz += sgn * h * qv[2]
+            lval, _, same = _final_state(pp, box.e + sgn * h * qe, box, nsteps, ctx, base_partners)
+            ok = ok and same
+            fd.append(lval)
+        if not ok:
+            excluded += 1
+            continue
+        valid += 1
+        err = abs((fd[0] - fd[1]) / (2 * h) - pred) / gnorm
+        worst = max(worst, err)
+    print(f"[gpu-test] adjoint FD: {valid} directions checked, {excluded} excluded, "
+          f"worst error {worst:.3e} of |grad| = {gnorm:.4e}", flush=True)
+    assert valid >= 48
+    assert worst < 1e-6
+
+
+def test_checkpoint_recompute_and_determinism():
+    box = workloads.make_box(20000, seed=9, phi=0.2, radius=1.0, e=0.9, dt=0.4)
+    ctx = pc.Context(box.n)
+    grads = []
+    for every in (1, 3, 1):
+        p0, ts, e = _leaf(box)
+        out = pc.Rollout.apply(*ts, e, p0.r, p0.m, box.L, box.dt, 7, ctx, every)
+        loss = sum((o * o).sum() for o in out[3:])
+        loss.backward()
+        grads.append([t.grad.clone() for t in ts] + [e.grad.clone()])
+    for a, b in zip(grads[0], grads[1]):
+        assert torch.equal(a, b)
+    for a, b in zip(grads[0], grads[2]):
+        assert torch.equal(a, b)
