@@ -98,13 +98,16 @@ typedef struct {
 
 typedef struct {
   double cell_mult;   /* grid cell side >= reach * cell_mult, cell_mult >= 1 (default 1) */
-  int max_sweeps;     /* 0: no cap (a step needs at most n/2 + 1 sweeps) */
+  int max_sweeps;     /* 0: no cap (a step needs at most n/2 + 1 sweeps); pcol_step_batched:
+                         sweeps captured in its graph (see there) */
   int home_cells;     /* home cells per workgroup along x in the sweep-1 detect; 0 = auto */
   int contact_slots;  /* contacts kept per sphere from the sweep-1 detect; spheres with more
                          fall back to an exact neighbourhood search (default 12) */
   int fp32_filter;    /* 1: FP32 pair filter with FP64 recheck (same results) */
   double band_rel;    /* FP32 filter safety band, relative to r_i + r_j (default 1e-4) */
   int timing;         /* 1: time kernels with HIP events; times land in pcol_stats */
+  int autotune;       /* pcol_step_batched: 1 = pick cell size and workgroup shape by timing
+                         candidates on the first call (cached, see pcol_step_batched) */
 } pcol_opts;
 
 typedef struct {
@@ -186,6 +189,51 @@ pcol_status pcol_advance(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, 
  * have been written to p and the free flight has not run. */
 pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, double dt, double e,
                       int32_t *partner, double *tcoll, pcol_stats *stats);
+
+/* Statistics of one pcol_step_batched call. */
+typedef struct {
+  int64_t n_pairs;       /* collisions resolved over all boxes */
+  int64_t n_sweeps;      /* sweeps of the step (the slowest box decides) */
+  int64_t contacts;      /* unordered pairs with a contact within dt */
+  int64_t n_overflow;    /* spheres whose contacts exceeded contact_slots, summed over sweeps */
+  int64_t total_cells;   /* cells of all boxes */
+  int32_t replanned;     /* 1 if this call (re)built the per-box grids and the graph */
+  int32_t finished_on_host; /* 1 if the captured sweeps did not suffice and the host finished */
+  int32_t tuned;         /* 1 if this call ran the autotuner */
+  int32_t waves_per_block; /* chosen workgroup shape of the pair-test launch */
+  double cell_mult;      /* chosen cell size factor */
+} pcol_batch_stats;
+
+/* Step many independent periodic boxes at once (the batched form).  Box b owns
+ * spheres [box_off[b], box_off[b+1]) of the concatenated arrays in p and the
+ * periodic box boxes[b]; every box follows rules 1-5 on its own (spheres of
+ * different boxes never interact).  box_off (nbox + 1 entries, box_off[0] = 0,
+ * box_off[nbox] = p->n) and boxes are HOST arrays.
+ *
+ * Each box gets its own grid (cell side >= the box's reach times cell_mult,
+ * at least 3 cells per axis: a box with L_k < 3 reach is rejected with
+ * PCOL_E_BOX).  The whole step (validation, binning, one persistent pair-test
+ * launch over the cells of all boxes, up to a planned number of sweeps with a
+ * device flag ending them early, free flight) is captured once into a HIP
+ * graph and replayed by later calls with the same arrays, layout, dt and e.
+ * The graph re-validates on the device each step: if a box's reach has
+ * outgrown its planned cells, the host re-plans and re-captures before any
+ * state changes; if the planned sweeps do not finish the step, the host runs
+ * the remaining sweeps.  Results equal pcol_step applied box by box: partner
+ * holds global indices (sphere k of box b is box_off[b] + k), which order the
+ * spheres of a box as their local indices do, so rule 2's ties break alike.
+ * Every step runs to completion: opts.max_sweeps > 0 fixes the number of
+ * sweeps captured in the graph (the host runs any beyond them); with 0 the
+ * graph starts with 12 and is re-captured with more after a step that needed
+ * more.
+ * With opts.autotune, the first call times candidate cell sizes and workgroup
+ * shapes on scratch copies of the input and keeps the fastest; choices are
+ * cached in the text file named by the environment variable PCOL_TUNE_CACHE
+ * (default $HOME/.cache/pcol_tune.txt), keyed by GPU and batch shape.
+ * Synchronises once per call (plus planning and tuning calls). */
+pcol_status pcol_step_batched(pcol_ctx *ctx, int32_t nbox, const int64_t *box_off,
+                              const pcol_box *boxes, pcol_particles *p, double dt, double e,
+                              int32_t *partner, double *tcoll, pcol_batch_stats *stats);
 
 /* Gradient of a scalar loss with respect to the positions and velocities of
  * all spheres (device arrays, caller order, n each). */

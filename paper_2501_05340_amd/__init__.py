@@ -41,7 +41,7 @@ class pcol_opts(ctypes.Structure):
     _fields_ = [("cell_mult", ctypes.c_double), ("max_sweeps", ctypes.c_int),
                 ("home_cells", ctypes.c_int), ("contact_slots", ctypes.c_int),
                 ("fp32_filter", ctypes.c_int), ("band_rel", ctypes.c_double),
-                ("timing", ctypes.c_int)]
+                ("timing", ctypes.c_int), ("autotune", ctypes.c_int)]
 
 
 class pcol_stats(ctypes.Structure):
@@ -61,6 +61,16 @@ class pcol_stats(ctypes.Structure):
             v = getattr(self, name)
             out[name] = list(v) if hasattr(v, "__len__") else v
         return out
+
+
+class pcol_batch_stats(ctypes.Structure):
+    _fields_ = [("n_pairs", ctypes.c_int64), ("n_sweeps", ctypes.c_int64),
+                ("contacts", ctypes.c_int64), ("n_overflow", ctypes.c_int64),
+                ("total_cells", ctypes.c_int64), ("replanned", ctypes.c_int32),
+                ("finished_on_host", ctypes.c_int32), ("tuned", ctypes.c_int32),
+                ("waves_per_block", ctypes.c_int32), ("cell_mult", ctypes.c_double)]
+
+    as_dict = pcol_stats.as_dict
 
 
 class pcol_state_grad(ctypes.Structure):
@@ -100,6 +110,10 @@ def _load():
                                        ctypes.c_double, V, V, P(pcol_state_grad),
                                        P(pcol_state_grad), V]
     lib.pcol_step_backward.restype = ctypes.c_int
+    lib.pcol_step_batched.argtypes = [ctx_p, ctypes.c_int32, V, P(pcol_box), P(pcol_particles),
+                                      ctypes.c_double, ctypes.c_double, V, V,
+                                      P(pcol_batch_stats)]
+    lib.pcol_step_batched.restype = ctypes.c_int
     return lib
 
 
@@ -107,7 +121,7 @@ lib = _load()
 
 EXPORTED = ["pcol_default_opts", "pcol_create", "pcol_destroy", "pcol_last_error",
             "pcol_set_stream", "pcol_bin", "pcol_detect", "pcol_resolve", "pcol_advance",
-            "pcol_step", "pcol_step_backward"]
+            "pcol_step", "pcol_step_backward", "pcol_step_batched"]
 
 
 class PcolError(RuntimeError):
@@ -283,6 +297,32 @@ def pcol_step(ctx: Context, p: Particles, L, dt: float, e: float, partner=None, 
     ctx.check(lib.pcol_step(ctx.handle, ctypes.byref(ps), ctypes.byref(_box(L)), float(dt),
                             float(e), _ptr(partner, torch.int32, n), _ptr(tcoll, torch.float64, n),
                             ctypes.byref(st) if st is not None else None))
+    return st.as_dict() if st is not None else None
+
+
+def pcol_step_batched(ctx: Context, p: Particles, box_off, Ls, dt: float, e: float, partner=None,
+                      tcoll=None, stats: bool = True):
+    """One step of many independent periodic boxes in place.  The spheres of box b
+    are p[box_off[b]:box_off[b+1]] (positions within [0, Ls[b]) per axis);
+    partner indices are global (into p).  Returns a dict of pcol_batch_stats."""
+    n = p.n
+    off = [int(v) for v in box_off]
+    nbox = len(off) - 1
+    if nbox < 1 or len(Ls) != nbox:
+        raise ValueError("box_off needs nbox + 1 entries and Ls nbox boxes")
+    off_arr = (ctypes.c_int64 * (nbox + 1))(*off)
+    boxes = (pcol_box * nbox)()
+    for b, L in enumerate(Ls):
+        Lb = (L, L, L) if isinstance(L, (int, float)) else L
+        for a in range(3):
+            boxes[b].len[a] = float(Lb[a])
+    st = pcol_batch_stats() if stats else None
+    ctx.sync_stream()
+    ps = p.struct()
+    ctx.check(lib.pcol_step_batched(ctx.handle, nbox, ctypes.cast(off_arr, ctypes.c_void_p), boxes,
+                                    ctypes.byref(ps), float(dt), float(e),
+                                    _ptr(partner, torch.int32, n), _ptr(tcoll, torch.float64, n),
+                                    ctypes.byref(st) if st is not None else None))
     return st.as_dict() if st is not None else None
 
 

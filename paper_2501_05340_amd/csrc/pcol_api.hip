@@ -4,8 +4,13 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <cstdlib>
+#include <fstream>
 #include <new>
+#include <sstream>
 #include <string>
+#include <vector>
 
 #include "../../include/pcol.h"
 #include "pcol_internal.h"
@@ -61,6 +66,49 @@ struct pcol_ctx {
   int maxcell = 0;
   bool small = false;  // some axis has fewer than 3 cells
   bool detect_timed = false;
+  struct BatchPlan *bp = nullptr;  // batched form (pcol_step_batched)
+};
+
+// State of the batched form: per-box grids on the host and device, the
+// captured step graph and what it was captured for.
+struct BatchPlan {
+  // layout the tables were built for
+  int nbox = 0;
+  int64_t n = 0;
+  std::vector<int64_t> box_off;
+  std::vector<double> len;  // 3 per box
+  // device tables
+  Grid *gtab = nullptr;
+  int *cell_base = nullptr;
+  int *box_of = nullptr;
+  int *sbox = nullptr;
+  int64_t *box_off_d = nullptr;
+  double *breach = nullptr;
+  unsigned int *flags = nullptr;          // FLAG_* words
+  unsigned long long *totals = nullptr;   // pairs, contacts, overflow
+  int cap_box = 0;
+  int64_t cap_n = 0;
+  unsigned int *flags_h = nullptr;        // pinned: 4 flags + padding, then 3 totals
+  std::vector<double> breach_h;
+  std::vector<Grid> gtab_h;
+  std::vector<int> cell_base_h;
+  int total_cells = 0;
+  bool tables = false;  // grids planned for the current layout
+  // tuning choice
+  double cell_mult = 1.0;
+  int wpb = 1;
+  bool tuned = false;
+  int kmax = 12;        // sweeps captured in the graph
+  // captured graph and its arguments
+  hipStream_t gstream = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool captured = false;
+  const void *cap_ptr[8] = {};
+  const void *cap_part = nullptr, *cap_tc = nullptr;
+  double cap_dt = 0.0, cap_e = 0.0;
+  // tuning scratch
+  double *tune_buf = nullptr;
+  int64_t tune_cap = 0;
 };
 
 namespace {
@@ -136,6 +184,7 @@ void pcol_default_opts(pcol_opts *o) {
   o->fp32_filter = 0;
   o->band_rel = 1e-4;
   o->timing = 0;
+  o->autotune = 1;
 }
 
 const char *pcol_last_error(const pcol_ctx *ctx) {
@@ -163,6 +212,16 @@ void pcol_destroy(pcol_ctx *ctx) {
   if (ctx->tests_h) (void)hipHostFree(ctx->tests_h);
   for (hipEvent_t &e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
+  if (BatchPlan *bp = ctx->bp) {
+    void *bd[] = {bp->gtab, bp->cell_base, bp->box_of, bp->sbox, bp->box_off_d,
+                  bp->breach, bp->flags, bp->totals, bp->tune_buf};
+    for (void *q : bd)
+      if (q) (void)hipFree(q);
+    if (bp->flags_h) (void)hipHostFree(bp->flags_h);
+    if (bp->exec) (void)hipGraphExecDestroy(bp->exec);
+    if (bp->gstream) (void)hipStreamDestroy(bp->gstream);
+    delete bp;
+  }
   delete ctx;
 }
 
@@ -278,6 +337,7 @@ pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box
     if (ctx->blocksum) (void)hipFree(ctx->blocksum);
     ctx->count = ctx->start = ctx->blocksum = nullptr;
     ctx->cell_cap = 0;
+    if (ctx->bp) ctx->bp->captured = false;  // its graph holds the old cell arrays
     const int64_t cap = (int64_t)G.ncell + 2;
     hipError_t e = dalloc(&ctx->count, (size_t)cap);
     if (e == hipSuccess) e = dalloc(&ctx->start, (size_t)cap + 1);
@@ -290,7 +350,8 @@ pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box
   PCOL_HIP(launch_cell_hist(s, P, G, ctx->cid, ctx->slot, ctx->count));
   PCOL_HIP(launch_scan(s, ctx->count, G.ncell, ctx->start, ctx->blocksum, ctx->reach_d));
   PCOL_HIP(launch_scatter(s, P, G, ctx->cid, ctx->slot, ctx->start, ctx->rec,
-                          ctx->opts.fp32_filter ? ctx->rec32 : nullptr, ctx->perm, ctx->rank));
+                          ctx->opts.fp32_filter ? ctx->rec32 : nullptr, ctx->perm, ctx->rank,
+                          nullptr));
   PCOL_HIP(hipMemcpyAsync(ctx->reach_h, ctx->reach_d, sizeof(ReachOut), hipMemcpyDeviceToHost, s));
   PCOL_HIP(hipStreamSynchronize(s));
   ctx->maxcell = (int)ctx->reach_h->maxcell;
@@ -380,13 +441,14 @@ static pcol_status detect_all(pcol_ctx *ctx, double dt) {
     if (ctx->opts.timing) PCOL_HIP(hipEventRecord(ctx->ev[6], s));
     ctx->detect_timed = true;
     PCOL_HIP(launch_slot_min(s, n, 1, ctx->cnt, ctx->slot_t, ctx->slot_j, ctx->K, ctx->status,
-                             ctx->perm, ctx->key_j, ctx->key_t, ctx->ovf, ctx->ctr_d));
+                             ctx->perm, ctx->key_j, ctx->key_t, ctx->ovf, ctx->ctr_d,
+                             nullptr));
     PCOL_HIP(launch_gather_exact(s, ctx->ovf, 0, &ctx->ctr_d->n_overflow, -1, ctx->rec, ctx->start,
-                                 ctx->G, dt, ctx->status, ctx->perm, ctx->key_j, ctx->key_t));
+                                 ctx->G, dt, ctx->status, ctx->perm, ctx->key_j, ctx->key_t, nullptr));
   } else {
     // fewer than 3 cells on some axis: exact search for every sphere
     PCOL_HIP(launch_gather_exact(s, nullptr, n, nullptr, -1, ctx->rec, ctx->start, ctx->G, dt,
-                                 ctx->status, ctx->perm, ctx->key_j, ctx->key_t));
+                                 ctx->status, ctx->perm, ctx->key_j, ctx->key_t, nullptr));
   }
   return PCOL_OK;
 }
@@ -417,7 +479,7 @@ pcol_status pcol_detect(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *
     PCOL_HIP(launch_status_from_active(s, active, ctx->perm, n, ctx->status));
     PCOL_HIP(launch_fill_i32(s, ctx->key_j, -1, n));
     PCOL_HIP(launch_gather_exact(s, nullptr, n, nullptr, ST_ACTIVE, ctx->rec, ctx->start, ctx->G,
-                                 dt, ctx->status, ctx->perm, ctx->key_j, ctx->key_t));
+                                 dt, ctx->status, ctx->perm, ctx->key_j, ctx->key_t, nullptr));
   }
   PCOL_HIP(launch_export_keys(s, n, ctx->perm, ctx->key_j, ctx->key_t, ctx->status, key_out,
                               tmin_out));
@@ -472,7 +534,7 @@ pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, dou
     if (timing) PCOL_HIP(hipEventRecord(ctx->ev[2], s));
     for (;;) {
       PCOL_HIP(launch_resolve_sweep(s, n, ctx->rec, ctx->G, dt, e, ctx->key_j, ctx->key_t,
-                                    ctx->status, ctx->perm, ctx->out, ctx->ctr_d));
+                                    ctx->status, ctx->perm, ctx->out, ctx->ctr_d, nullptr));
       PCOL_HIP(hipMemcpyAsync(ctx->ctr_h, ctx->ctr_d, sizeof(SweepCounters),
                               hipMemcpyDeviceToHost, s));
       PCOL_HIP(hipStreamSynchronize(s));
@@ -492,19 +554,20 @@ pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, dou
       PCOL_HIP(hipMemsetAsync(ctx->ctr_d, 0, sizeof(SweepCounters), s));
       if (!ctx->small) {
         PCOL_HIP(launch_slot_min(s, n, 0, ctx->cnt, ctx->slot_t, ctx->slot_j, ctx->K, ctx->status,
-                                 ctx->perm, ctx->key_j, ctx->key_t, ctx->ovf, ctx->ctr_d));
+                                 ctx->perm, ctx->key_j, ctx->key_t, ctx->ovf, ctx->ctr_d,
+                             nullptr));
         PCOL_HIP(launch_gather_exact(s, ctx->ovf, 0, &ctx->ctr_d->n_overflow, -1, ctx->rec,
                                      ctx->start, ctx->G, dt, ctx->status, ctx->perm, ctx->key_j,
-                                     ctx->key_t));
+                                     ctx->key_t, nullptr));
       } else {
         PCOL_HIP(launch_gather_exact(s, nullptr, n, nullptr, ST_DIRTY, ctx->rec, ctx->start,
                                      ctx->G, dt, ctx->status, ctx->perm, ctx->key_j,
-                                     ctx->key_t));
+                                     ctx->key_t, nullptr));
       }
     }
     if (timing) PCOL_HIP(hipEventRecord(ctx->ev[3], s));
-    PCOL_HIP(launch_advance_sorted(s, n, ctx->rec, ctx->status, dt, ctx->G, ctx->out));
-    PCOL_HIP(launch_unpermute(s, P, ctx->rank, ctx->out, part, tc));
+    PCOL_HIP(launch_advance_sorted(s, n, ctx->rec, ctx->status, dt, ctx->G, ctx->out, nullptr));
+    PCOL_HIP(launch_unpermute(s, P, ctx->rank, ctx->out, part, tc, nullptr));
     if (timing) {
       PCOL_HIP(hipEventRecord(ctx->ev[4], s));
       PCOL_HIP(hipEventSynchronize(ctx->ev[4]));
@@ -569,3 +632,495 @@ pcol_status pcol_step_backward(pcol_ctx *ctx, const pcol_particles *start, const
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- batched form
+
+namespace {
+
+BatchDev batch_dev(const BatchPlan *bp) {
+  BatchDev B{};
+  B.gtab = bp->gtab;
+  B.cell_base = bp->cell_base;
+  B.box_of = bp->box_of;
+  B.sbox = bp->sbox;
+  B.box_off = bp->box_off_d;
+  B.breach = bp->breach;
+  B.flags = bp->flags;
+  B.nbox = bp->nbox;
+  return B;
+}
+
+// Grid of one box: cell side >= reach * mult * 1.05 per axis (the slack lets
+// the reach grow a little over later steps before a re-plan), no more cells
+// than max(27, 2 n_b) for a box of n_b spheres, and at least 3 cells per axis
+// (else the box is rejected).
+bool box_grid(const double len[3], int64_t nb, double reach, double mult, Grid &G) {
+  double cell = reach * mult * 1.05;
+  const double vol = len[0] * len[1] * len[2];
+  const double most = (double)(nb > 13 ? 2 * nb : 27);
+  const double floor_side = cbrt(vol / most);
+  if (!(cell >= floor_side)) cell = floor_side;
+  for (int a = 0; a < 3; ++a) {
+    double q = floor(len[a] / (cell * (1.0 + 1e-9)));
+    if (q > 1024.0) q = 1024.0;
+    if (q < 3.0) {
+      // fall back to exactly 3 cells when they are still at least the reach wide
+      if (len[a] / 3.0 >= reach * (1.0 + 1e-9))
+        q = 3.0;
+      else
+        return false;
+    }
+    G.nc[a] = (int)q;
+    G.L[a] = len[a];
+    G.halfL[a] = 0.5 * len[a];
+    G.inv_h[a] = q / len[a];
+    G.h[a] = len[a] / q;
+  }
+  G.ncell = G.nc[0] * G.nc[1] * G.nc[2];
+  return true;
+}
+
+template <typename T>
+hipError_t regrow(T **p, int64_t want) {
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  return hipMalloc((void **)p, (size_t)(want > 0 ? want : 1) * sizeof(T));
+}
+
+// read back the flags and totals of the last batched run
+hipError_t batch_readback(pcol_ctx *ctx, BatchPlan *bp) {
+  hipError_t e = hipMemcpyAsync(bp->flags_h, bp->flags, 16 * sizeof(unsigned int),
+                                hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(bp->flags_h + 16, bp->totals, 3 * sizeof(unsigned long long),
+                       hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  return e;
+}
+
+unsigned long long batch_total(const BatchPlan *bp, int k) {
+  unsigned long long v;
+  memcpy(&v, (const char *)(bp->flags_h + 16) + 8 * k, 8);
+  return v;
+}
+
+}  // namespace
+
+// (Re)build the per-box tables for this layout and the current data: per-box
+// reach on the device, then grids and cell numbering on the host.
+static pcol_status batch_plan(pcol_ctx *ctx, int nbox, const int64_t *box_off,
+                              const pcol_box *boxes, const Particles &P, double dt, double mult) {
+  BatchPlan *bp = ctx->bp;
+  hipStream_t s = ctx->stream;
+  hipError_t e = hipSuccess;
+  if (nbox > bp->cap_box) {
+    if ((e = regrow(&bp->gtab, nbox)) != hipSuccess ||
+        (e = regrow(&bp->cell_base, nbox + 1)) != hipSuccess ||
+        (e = regrow(&bp->box_off_d, nbox + 1)) != hipSuccess ||
+        (e = regrow(&bp->breach, nbox)) != hipSuccess)
+      return fail(ctx, PCOL_E_NOMEM, "batched tables");
+    bp->cap_box = nbox;
+  }
+  if (P.n > bp->cap_n) {
+    if ((e = regrow(&bp->box_of, P.n)) != hipSuccess || (e = regrow(&bp->sbox, P.n)) != hipSuccess)
+      return fail(ctx, PCOL_E_NOMEM, "batched tables");
+    bp->cap_n = P.n;
+  }
+  if (!bp->flags) {
+    if (hipMalloc((void **)&bp->flags, 16 * sizeof(unsigned int)) != hipSuccess ||
+        hipMalloc((void **)&bp->totals, 4 * sizeof(unsigned long long)) != hipSuccess ||
+        hipHostMalloc((void **)&bp->flags_h, 16 * sizeof(unsigned int) + 4 * 8) != hipSuccess)
+      return fail(ctx, PCOL_E_NOMEM, "batched flags");
+  }
+  bp->nbox = nbox;
+  bp->n = P.n;
+  bp->box_off.assign(box_off, box_off + nbox + 1);
+  bp->len.resize((size_t)3 * nbox);
+  bp->gtab_h.assign(nbox, Grid{});
+  for (int b = 0; b < nbox; ++b)
+    for (int a = 0; a < 3; ++a) {
+      bp->len[3 * b + a] = boxes[b].len[a];
+      bp->gtab_h[b].L[a] = boxes[b].len[a];
+      bp->gtab_h[b].nc[a] = 1;
+    }
+  PCOL_HIP(hipMemcpyAsync(bp->box_off_d, box_off, (nbox + 1) * sizeof(int64_t),
+                          hipMemcpyHostToDevice, s));
+  PCOL_HIP(hipMemcpyAsync(bp->gtab, bp->gtab_h.data(), nbox * sizeof(Grid), hipMemcpyHostToDevice, s));
+  PCOL_HIP(launch_fill_box_of(s, nbox, bp->box_off_d, bp->box_of));
+  PCOL_HIP(launch_fill_u32(s, bp->flags, 0u, 16));
+  PCOL_HIP(launch_breach(s, P, batch_dev(bp), dt, 0));
+  bp->breach_h.resize(nbox);
+  PCOL_HIP(hipMemcpyAsync(bp->breach_h.data(), bp->breach, nbox * sizeof(double),
+                          hipMemcpyDeviceToHost, s));
+  PCOL_HIP(batch_readback(ctx, bp));
+  const unsigned int err = bp->flags_h[FLAG_ERR];
+  if (err & ERR_INVALID) return fail(ctx, PCOL_E_INVALID, "non-finite value, r <= 0, m <= 0 or position outside its box");
+  if (err & ERR_BOX) return fail(ctx, PCOL_E_BOX, "a box side <= 2 * reach");
+  bp->cell_base_h.assign(nbox + 1, 0);
+  int64_t total = 0;
+  for (int b = 0; b < nbox; ++b) {
+    double len[3] = {boxes[b].len[0], boxes[b].len[1], boxes[b].len[2]};
+    if (!box_grid(len, box_off[b + 1] - box_off[b], bp->breach_h[b], mult, bp->gtab_h[b]))
+      return fail(ctx, PCOL_E_BOX, "batched form needs 3 cells of at least the reach per axis");
+    bp->cell_base_h[b] = (int)total;
+    total += bp->gtab_h[b].ncell;
+    if (total > (1 << 28)) return fail(ctx, PCOL_E_BOX, "too many cells in the batch");
+  }
+  bp->cell_base_h[nbox] = (int)total;
+  bp->total_cells = (int)total;
+  PCOL_HIP(hipMemcpyAsync(bp->gtab, bp->gtab_h.data(), nbox * sizeof(Grid), hipMemcpyHostToDevice, s));
+  PCOL_HIP(hipMemcpyAsync(bp->cell_base, bp->cell_base_h.data(), (nbox + 1) * sizeof(int),
+                          hipMemcpyHostToDevice, s));
+  if (total + 2 > ctx->cell_cap) {
+    if (ctx->count) (void)hipFree(ctx->count);
+    if (ctx->start) (void)hipFree(ctx->start);
+    if (ctx->blocksum) (void)hipFree(ctx->blocksum);
+    ctx->count = ctx->start = ctx->blocksum = nullptr;
+    ctx->cell_cap = 0;
+    const int64_t cap = total + 2;
+    hipError_t a = dalloc(&ctx->count, (size_t)cap);
+    if (a == hipSuccess) a = dalloc(&ctx->start, (size_t)cap + 1);
+    if (a == hipSuccess) a = dalloc(&ctx->blocksum, (size_t)(cap / 4096 + 2));
+    if (a != hipSuccess) return fail(ctx, PCOL_E_NOMEM, "cell arrays");
+    ctx->cell_cap = cap;
+  }
+  PCOL_HIP(hipStreamSynchronize(s));
+  bp->tables = true;
+  bp->cell_mult = mult;
+  return PCOL_OK;
+}
+
+// Enqueue the whole batched step on stream s (captured into a graph).
+static pcol_status batch_enqueue(pcol_ctx *ctx, hipStream_t s, const Particles &P, int32_t *part,
+                                 double *tc, double dt, double e, int kmax, int wpb) {
+  BatchPlan *bp = ctx->bp;
+  const BatchDev B = batch_dev(bp);
+  const int n = (int)P.n;
+  const int ncell = bp->total_cells;
+  PCOL_HIP(launch_fill_u32(s, bp->flags, 0u, 16));
+  PCOL_HIP(launch_fill_u32(s, (unsigned int *)bp->totals, 0u, 8));
+  PCOL_HIP(launch_fill_u32(s, (unsigned int *)ctx->ctr_d, 0u, sizeof(SweepCounters) / 4));
+  PCOL_HIP(launch_breach(s, P, B, dt, 1));
+  PCOL_HIP(launch_fill_i32(s, ctx->count, 0, ncell));
+  PCOL_HIP(launch_cell_hist_b(s, P, B, ctx->cid, ctx->slot, ctx->count));
+  PCOL_HIP(launch_scan(s, ctx->count, ncell, ctx->start, ctx->blocksum, ctx->reach_d));
+  PCOL_HIP(launch_scatter(s, P, ctx->G, ctx->cid, ctx->slot, ctx->start, ctx->rec, nullptr,
+                          ctx->perm, ctx->rank, &B));
+  PCOL_HIP(launch_fill_u8(s, ctx->status, ST_ACTIVE, n));
+  PCOL_HIP(launch_fill_i32(s, ctx->cnt, 0, n));
+  DetectArgs A{};
+  A.rec = ctx->rec;
+  A.start = ctx->start;
+  A.cnt = ctx->cnt;
+  A.slot_t = ctx->slot_t;
+  A.slot_j = ctx->slot_j;
+  A.ctr = ctx->ctr_d;
+  A.n = n;
+  A.dt = dt;
+  A.dt2 = 2.0 * dt * (1.0 + 0x1.0p-20);
+  // Filter tolerance (see the single-box detect) from bounds that hold for any
+  // data the graph accepts: the re-plan check stops the step unless every
+  // box's reach 2 rmax + 2 vmax dt is at most its cell side, so with hmax the
+  // largest cell side, reach <= hmax, 2 rmax <= hmax and 2 vmax <= hmax / dt.
+  double hmax = 0.0;
+  for (const Grid &G : bp->gtab_h)
+    for (int a = 0; a < 3; ++a) hmax = G.h[a] > hmax ? G.h[a] : hmax;
+  A.tol = 16.0 * 0x1.0p-53 * hmax * hmax * (2.0 + A.dt2 / dt);
+  A.K = ctx->K;
+  A.cap = 0;
+  A.fp32 = 0;
+  int blocks = 256 * 8 * 4 / wpb;  // about 8 resident waves per SIMD
+  PCOL_HIP(launch_detect_batched(s, A, B, blocks, wpb));
+  PCOL_HIP(launch_slot_min(s, n, 1, ctx->cnt, ctx->slot_t, ctx->slot_j, ctx->K, ctx->status,
+                           ctx->perm, ctx->key_j, ctx->key_t, ctx->ovf, ctx->ctr_d, bp->flags));
+  PCOL_HIP(launch_gather_exact(s, ctx->ovf, 0, &ctx->ctr_d->n_overflow, -1, ctx->rec, ctx->start,
+                               ctx->G, dt, ctx->status, ctx->perm, ctx->key_j, ctx->key_t, &B));
+  for (int k = 0; k < kmax; ++k) {
+    PCOL_HIP(launch_resolve_sweep(s, n, ctx->rec, ctx->G, dt, e, ctx->key_j, ctx->key_t,
+                                  ctx->status, ctx->perm, ctx->out, ctx->ctr_d, &B));
+    PCOL_HIP(launch_sweep_check(s, ctx->ctr_d, bp->flags, bp->totals, k == kmax - 1));
+    PCOL_HIP(launch_slot_min(s, n, 0, ctx->cnt, ctx->slot_t, ctx->slot_j, ctx->K, ctx->status,
+                             ctx->perm, ctx->key_j, ctx->key_t, ctx->ovf, ctx->ctr_d, bp->flags));
+    PCOL_HIP(launch_gather_exact(s, ctx->ovf, 0, &ctx->ctr_d->n_overflow, -1, ctx->rec,
+                                 ctx->start, ctx->G, dt, ctx->status, ctx->perm, ctx->key_j,
+                                 ctx->key_t, &B));
+  }
+  PCOL_HIP(launch_advance_sorted(s, n, ctx->rec, ctx->status, dt, ctx->G, ctx->out, &B));
+  PCOL_HIP(launch_unpermute(s, P, ctx->rank, ctx->out, part, tc, bp->flags));
+  return PCOL_OK;
+}
+
+static pcol_status batch_capture(pcol_ctx *ctx, const Particles &P, int32_t *part, double *tc,
+                                 double dt, double e, int kmax, int wpb, hipGraphExec_t *exec) {
+  BatchPlan *bp = ctx->bp;
+  if (!bp->gstream) PCOL_HIP(hipStreamCreateWithFlags(&bp->gstream, hipStreamNonBlocking));
+  PCOL_HIP(hipStreamBeginCapture(bp->gstream, hipStreamCaptureModeRelaxed));
+  pcol_status st = batch_enqueue(ctx, bp->gstream, P, part, tc, dt, e, kmax, wpb);
+  hipGraph_t g = nullptr;
+  hipError_t ee = hipStreamEndCapture(bp->gstream, &g);
+  if (st != PCOL_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (ee != hipSuccess) return hip_fail(ctx, ee, "hipStreamEndCapture");
+  ee = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ee != hipSuccess) return hip_fail(ctx, ee, "hipGraphInstantiate");
+  return PCOL_OK;
+}
+
+// Finish a step whose captured sweeps ran out: remaining sweeps on the host
+// loop, then free flight and the copy back (the graph skipped both).
+static pcol_status batch_finish(pcol_ctx *ctx, const Particles &P, int32_t *part, double *tc,
+                                double dt, double e, int64_t &pairs, int64_t &sweeps) {
+  BatchPlan *bp = ctx->bp;
+  const BatchDev B = batch_dev(bp);
+  hipStream_t s = ctx->stream;
+  const int n = (int)P.n;
+  for (;;) {
+    PCOL_HIP(launch_fill_u32(s, (unsigned int *)ctx->ctr_d, 0u, sizeof(SweepCounters) / 4));
+    PCOL_HIP(launch_resolve_sweep(s, n, ctx->rec, ctx->G, dt, e, ctx->key_j, ctx->key_t,
+                                  ctx->status, ctx->perm, ctx->out, ctx->ctr_d, &B));
+    PCOL_HIP(hipMemcpyAsync(ctx->ctr_h, ctx->ctr_d, sizeof(SweepCounters), hipMemcpyDeviceToHost, s));
+    PCOL_HIP(hipStreamSynchronize(s));
+    unsigned long long sp, sc;
+    sum_counters(*ctx->ctr_h, sp, sc);
+    ++sweeps;
+    pairs += (int64_t)sp;
+    if (sp == 0ull) break;
+    PCOL_HIP(launch_fill_u32(s, (unsigned int *)ctx->ctr_d, 0u, sizeof(SweepCounters) / 4));
+    PCOL_HIP(launch_slot_min(s, n, 0, ctx->cnt, ctx->slot_t, ctx->slot_j, ctx->K, ctx->status,
+                             ctx->perm, ctx->key_j, ctx->key_t, ctx->ovf, ctx->ctr_d, bp->flags));
+    PCOL_HIP(launch_gather_exact(s, ctx->ovf, 0, &ctx->ctr_d->n_overflow, -1, ctx->rec,
+                                 ctx->start, ctx->G, dt, ctx->status, ctx->perm, ctx->key_j,
+                                 ctx->key_t, &B));
+  }
+  PCOL_HIP(launch_fill_u32(s, bp->flags + FLAG_UNFINISHED, 0u, 1));
+  PCOL_HIP(launch_advance_sorted(s, n, ctx->rec, ctx->status, dt, ctx->G, ctx->out, &B));
+  PCOL_HIP(launch_unpermute(s, P, ctx->rank, ctx->out, part, tc, bp->flags));
+  return PCOL_OK;
+}
+
+static std::string tune_key(int nbox, int64_t n, const int64_t *box_off, const pcol_box *boxes,
+                            double dt) {
+  hipDeviceProp_t prop{};
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipGetDeviceProperties(&prop, dev);
+  double vol = 0.0;
+  for (int b = 0; b < nbox; ++b) vol += boxes[b].len[0] * boxes[b].len[1] * boxes[b].len[2];
+  std::ostringstream k;
+  k << prop.gcnArchName << "|n" << (int)round(log2((double)(n > 0 ? n : 1))) << "|b"
+    << (int)round(log2((double)nbox)) << "|rho" << (int)round(4.0 * log2(n / vol + 1e-300))
+    << "|dt" << dt;
+  (void)box_off;
+  std::string key = k.str();
+  for (char &c : key)
+    if (c == ' ') c = '_';
+  return key;
+}
+
+static std::string tune_path() {
+  const char *p = getenv("PCOL_TUNE_CACHE");
+  if (p && *p) return p;
+  const char *h = getenv("HOME");
+  return std::string(h ? h : ".") + "/.cache/pcol_tune.txt";
+}
+
+static bool tune_lookup(const std::string &key, double &mult, int &wpb) {
+  std::ifstream f(tune_path());
+  std::string k;
+  double m;
+  int w;
+  bool found = false;
+  while (f >> k >> m >> w)
+    if (k == key) {
+      mult = m;
+      wpb = w;
+      found = true;
+    }
+  return found;
+}
+
+static void tune_store(const std::string &key, double mult, int wpb) {
+  std::ofstream f(tune_path(), std::ios::app);
+  if (f) f << key << " " << mult << " " << wpb << "\n";
+}
+
+// Time candidate (cell size factor, workgroup shape) pairs on scratch copies of
+// the input; keep the fastest.  Every candidate computes the same step (the
+// result does not depend on the cell size or the launch shape).
+static pcol_status batch_autotune(pcol_ctx *ctx, int nbox, const int64_t *box_off,
+                                  const pcol_box *boxes, const Particles &P, double dt,
+                                  double e) {
+  BatchPlan *bp = ctx->bp;
+  hipStream_t s = ctx->stream;
+  const int64_t n = P.n;
+  if (bp->tune_cap < n) {
+    if (bp->tune_buf) (void)hipFree(bp->tune_buf);
+    bp->tune_buf = nullptr;
+    if (hipMalloc((void **)&bp->tune_buf, (size_t)(n > 0 ? n : 1) * 6 * sizeof(double)) != hipSuccess)
+      return fail(ctx, PCOL_E_NOMEM, "tuning scratch");
+    bp->tune_cap = n;
+  }
+  Particles T = P;
+  double *src[6] = {P.x, P.y, P.z, P.vx, P.vy, P.vz};
+  double *dst[6];
+  for (int k = 0; k < 6; ++k) dst[k] = bp->tune_buf + (size_t)k * n;
+  T.x = dst[0];
+  T.y = dst[1];
+  T.z = dst[2];
+  T.vx = dst[3];
+  T.vy = dst[4];
+  T.vz = dst[5];
+  const double mults[3] = {1.0, 1.15, 1.3};
+  const int shapes[2] = {1, 4};
+  double best = 1e300, best_mult = 1.0;
+  int best_wpb = 1;
+  for (double mult : mults) {
+    pcol_status st = batch_plan(ctx, nbox, box_off, boxes, P, dt, mult);
+    if (st == PCOL_E_BOX) continue;  // this cell size leaves some box under 3 cells
+    if (st != PCOL_OK) return st;
+    for (int wpb : shapes) {
+      hipGraphExec_t ex = nullptr;
+      if ((st = batch_capture(ctx, T, ctx->partner_tmp, ctx->tcoll_tmp, dt, e, bp->kmax, wpb,
+                              &ex)) != PCOL_OK)
+        return st;
+      float times[3];
+      for (int rep = 0; rep < 3; ++rep) {
+        for (int k = 0; k < 6; ++k)
+          PCOL_HIP(hipMemcpyAsync(dst[k], src[k], n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        PCOL_HIP(hipEventRecord(ctx->ev[0], s));
+        PCOL_HIP(hipGraphLaunch(ex, s));
+        PCOL_HIP(hipEventRecord(ctx->ev[1], s));
+        PCOL_HIP(hipEventSynchronize(ctx->ev[1]));
+        (void)hipEventElapsedTime(&times[rep], ctx->ev[0], ctx->ev[1]);
+      }
+      (void)hipGraphExecDestroy(ex);
+      std::sort(times, times + 3);
+      if (times[1] < best) {
+        best = times[1];
+        best_mult = mult;
+        best_wpb = wpb;
+      }
+    }
+  }
+  bp->cell_mult = best_mult;
+  bp->wpb = best_wpb;
+  bp->tuned = true;
+  bp->tables = false;
+  return PCOL_OK;
+}
+
+extern "C" pcol_status pcol_step_batched(pcol_ctx *ctx, int32_t nbox, const int64_t *box_off,
+                                         const pcol_box *boxes, pcol_particles *p, double dt,
+                                         double e, int32_t *partner, double *tcoll,
+                                         pcol_batch_stats *stats) {
+  if (!ctx) return PCOL_E_INVALID;
+  if (nbox < 1 || !box_off || !boxes || !p) return fail(ctx, PCOL_E_INVALID, "bad batch arguments");
+  pcol_box any{{1.0, 1.0, 1.0}};
+  pcol_status st = check_common(ctx, p, &any, dt);
+  if (st != PCOL_OK) return st;
+  if (!(e >= 0.0 && e <= 1.0)) return fail(ctx, PCOL_E_INVALID, "e outside [0, 1]");
+  if (box_off[0] != 0 || box_off[nbox] != p->n)
+    return fail(ctx, PCOL_E_INVALID, "box_off must run from 0 to n");
+  for (int b = 0; b < nbox; ++b) {
+    if (box_off[b + 1] < box_off[b]) return fail(ctx, PCOL_E_INVALID, "box_off not increasing");
+    for (int a = 0; a < 3; ++a)
+      if (!finite_pos(boxes[b].len[a])) return fail(ctx, PCOL_E_INVALID, "box side not finite positive");
+  }
+  if (!ctx->bp) {
+    ctx->bp = new (std::nothrow) BatchPlan();
+    if (!ctx->bp) return PCOL_E_NOMEM;
+    if (ctx->opts.max_sweeps > 0) ctx->bp->kmax = ctx->opts.max_sweeps;
+  }
+  BatchPlan *bp = ctx->bp;
+  const Particles P = to_dev(p);
+  int32_t *part = partner ? partner : ctx->partner_tmp;
+  double *tc = tcoll ? tcoll : ctx->tcoll_tmp;
+  const void *ptrs[8] = {p->x, p->y, p->z, p->vx, p->vy, p->vz, p->r, p->m};
+  bool same_layout = bp->tables && bp->nbox == nbox && bp->n == p->n &&
+                     std::equal(box_off, box_off + nbox + 1, bp->box_off.begin());
+  for (int b = 0; same_layout && b < nbox; ++b)
+    for (int a = 0; a < 3; ++a)
+      if (bp->len[3 * b + a] != boxes[b].len[a]) same_layout = false;
+  int replanned = 0, tuned = 0, host_finish = 0;
+  if (!same_layout && !bp->tuned && ctx->opts.autotune) {
+    const std::string key = tune_key(nbox, p->n, box_off, boxes, dt);
+    double m;
+    int w;
+    if (tune_lookup(key, m, w)) {
+      bp->cell_mult = m;
+      bp->wpb = w;
+      bp->tuned = true;
+    } else {
+      if ((st = batch_autotune(ctx, nbox, box_off, boxes, P, dt, e)) != PCOL_OK) return st;
+      tune_store(key, bp->cell_mult, bp->wpb);
+      tuned = 1;
+    }
+  }
+  if (!ctx->opts.autotune && !bp->tuned) {
+    bp->cell_mult = ctx->opts.cell_mult;
+    bp->wpb = 1;
+  }
+  for (int attempt = 0;; ++attempt) {
+    if (!same_layout || !bp->tables) {
+      if ((st = batch_plan(ctx, nbox, box_off, boxes, P, dt, bp->cell_mult)) != PCOL_OK) return st;
+      same_layout = true;
+      bp->captured = false;
+      replanned = 1;
+    }
+    bool recapture = !bp->captured || bp->cap_dt != dt || bp->cap_e != e || bp->cap_part != part ||
+                     bp->cap_tc != tc;
+    for (int k = 0; k < 8 && !recapture; ++k) recapture = bp->cap_ptr[k] != ptrs[k];
+    if (recapture) {
+      if (bp->exec) (void)hipGraphExecDestroy(bp->exec);
+      bp->exec = nullptr;
+      if ((st = batch_capture(ctx, P, part, tc, dt, e, bp->kmax, bp->wpb, &bp->exec)) != PCOL_OK)
+        return st;
+      bp->captured = true;
+      bp->cap_dt = dt;
+      bp->cap_e = e;
+      bp->cap_part = part;
+      bp->cap_tc = tc;
+      for (int k = 0; k < 8; ++k) bp->cap_ptr[k] = ptrs[k];
+    }
+    PCOL_HIP(hipGraphLaunch(bp->exec, ctx->stream));
+    PCOL_HIP(batch_readback(ctx, bp));
+    const unsigned int err = bp->flags_h[FLAG_ERR];
+    if (err & ERR_INVALID)
+      return fail(ctx, PCOL_E_INVALID, "non-finite value, r <= 0, m <= 0 or position outside its box");
+    if (err & ERR_BOX) return fail(ctx, PCOL_E_BOX, "a box side <= 2 * reach");
+    if (err & ERR_REPLAN) {  // reach outgrew the planned cells; nothing was written
+      if (attempt > 0) return fail(ctx, PCOL_E_HIP, "batched re-plan did not settle");
+      bp->tables = false;
+      continue;
+    }
+    break;
+  }
+  int64_t pairs = (int64_t)batch_total(bp, 0);
+  int64_t sweeps = bp->flags_h[FLAG_SWEEPS];
+  if (bp->flags_h[FLAG_UNFINISHED]) {
+    if ((st = batch_finish(ctx, P, part, tc, dt, e, pairs, sweeps)) != PCOL_OK) return st;
+    PCOL_HIP(hipStreamSynchronize(ctx->stream));
+    host_finish = 1;
+    if (ctx->opts.max_sweeps == 0) {  // capture enough sweeps next time
+      bp->kmax = (int)sweeps + 4;
+      bp->captured = false;
+    }
+  }
+  if (stats) {
+    memset(stats, 0, sizeof(*stats));
+    stats->n_pairs = pairs;
+    stats->n_sweeps = sweeps;
+    stats->contacts = (int64_t)(batch_total(bp, 1) / 2ull);
+    stats->n_overflow = (int64_t)batch_total(bp, 2);
+    stats->total_cells = bp->total_cells;
+    stats->replanned = replanned;
+    stats->finished_on_host = host_finish;
+    stats->tuned = tuned;
+    stats->waves_per_block = bp->wpb;
+    stats->cell_mult = bp->cell_mult;
+  }
+  return PCOL_OK;
+}

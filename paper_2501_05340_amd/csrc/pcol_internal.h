@@ -164,6 +164,22 @@ struct StateGrad {
   double *x, *y, *z, *vx, *vy, *vz;
 };
 
+// Device tables of the batched form: one grid per box, boxes' cells numbered
+// consecutively (cell_base), the box of every sphere, and status flags that
+// let every kernel of a captured step skip its work.
+enum { FLAG_DONE = 0, FLAG_ERR = 1, FLAG_SWEEPS = 2, FLAG_UNFINISHED = 3 };
+enum : unsigned int { ERR_INVALID = 1u, ERR_REPLAN = 2u, ERR_BOX = 4u };
+struct BatchDev {
+  const Grid *gtab;       // [nbox]
+  const int *cell_base;   // [nbox + 1]
+  const int *box_of;      // caller order: box of each sphere
+  int *sbox;              // cell-sorted order: box of each sphere
+  const int64_t *box_off; // [nbox + 1] sphere ranges (caller order)
+  double *breach;         // [nbox] reach found by the last step
+  unsigned int *flags;    // FLAG_* words
+  int nbox;
+};
+
 // Everything the sweep-1 detect needs.
 struct DetectArgs {
   const Rec *rec;
@@ -197,24 +213,35 @@ hipError_t launch_scan(hipStream_t s, const int *count, int ncell, int *start, i
                        ReachOut *out);
 hipError_t launch_scatter(hipStream_t s, const Particles &P, const Grid &G, const int *cid,
                           const int *slot, const int *start, Rec *rec, Rec32 *rec32, int *perm,
-                          int *rank);
+                          int *rank, const BatchDev *B);
 hipError_t launch_detect_half(hipStream_t s, const DetectArgs &A);
 hipError_t launch_count_pairs(hipStream_t s, const int *start, const Grid &G,
                               unsigned long long *out);
 hipError_t launch_slot_min(hipStream_t s, int n, int first, const int *cnt, const double *slot_t,
                            const int *slot_j, int K, uint8_t *status, const int *perm, int *key_j,
-                           double *key_t, int *ovf_list, SweepCounters *ctr);
+                           double *key_t, int *ovf_list, SweepCounters *ctr,
+                           const unsigned int *flags);
 hipError_t launch_gather_exact(hipStream_t s, const int *list, int nlist, const unsigned int *nlist_dev,
                                int select, const Rec *rec, const int *start, const Grid &G,
                                double dt, uint8_t *status, const int *perm, int *key_j,
-                               double *key_t);
+                               double *key_t, const BatchDev *B);
 hipError_t launch_resolve_sweep(hipStream_t s, int n, const Rec *rec, const Grid &G, double dt,
                                 double e, const int *key_j, const double *key_t, uint8_t *status,
-                                const int *perm, OutRec *out, SweepCounters *ctr);
+                                const int *perm, OutRec *out, SweepCounters *ctr,
+                                const BatchDev *B);
 hipError_t launch_advance_sorted(hipStream_t s, int n, const Rec *rec, const uint8_t *status,
-                                 double dt, const Grid &G, OutRec *out);
+                                 double dt, const Grid &G, OutRec *out, const BatchDev *B);
 hipError_t launch_unpermute(hipStream_t s, const Particles &P, const int *rank, const OutRec *out,
-                            int *partner, double *tcoll);
+                            int *partner, double *tcoll, const unsigned int *flags);
+hipError_t launch_fill_box_of(hipStream_t s, int nbox, const int64_t *box_off, int *box_of);
+hipError_t launch_breach(hipStream_t s, const Particles &P, const BatchDev &B, double dt,
+                         int check_plan);
+hipError_t launch_cell_hist_b(hipStream_t s, const Particles &P, const BatchDev &B, int *cid,
+                              int *slot, int *count);
+hipError_t launch_detect_batched(hipStream_t s, const DetectArgs &A, const BatchDev &B,
+                                 int blocks, int waves_per_block);
+hipError_t launch_sweep_check(hipStream_t s, SweepCounters *ctr, unsigned int *flags,
+                              unsigned long long *totals, int last);
 hipError_t launch_advance(hipStream_t s, const Particles &P, const int *partner, double dt,
                           const double L[3]);
 hipError_t launch_status_from_active(hipStream_t s, const uint8_t *active, const int *perm, int n,

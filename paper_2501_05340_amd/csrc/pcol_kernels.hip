@@ -286,9 +286,11 @@ hipError_t launch_scan(hipStream_t s, const int *count, int ncell, int *start, i
 // the 32-B FP32 filter record (position relative to the cell centre).
 __global__ __launch_bounds__(256) void k_scatter(Particles P, Grid G, const int *cid,
                                                  const int *slot, const int *start, Rec *rec,
-                                                 Rec32 *rec32, int *perm, int *rank) {
+                                                 Rec32 *rec32, int *perm, int *rank,
+                                                 const int *box_of, int *sbox,
+                                                 const unsigned int *flags) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= P.n) return;
+  if (i >= P.n || (flags && flags[FLAG_ERR])) return;
   const int c = cid[i];
   const int pos = start[c] + slot[i];
   Rec q;
@@ -303,6 +305,7 @@ __global__ __launch_bounds__(256) void k_scatter(Particles P, Grid G, const int 
   rec[pos] = q;
   perm[pos] = (int)i;
   rank[i] = pos;
+  if (sbox) sbox[pos] = box_of[i];
   if (rec32) {
     const int cx = c % G.nc[0], cy = (c / G.nc[0]) % G.nc[1], cz = c / (G.nc[0] * G.nc[1]);
     Rec32 f;
@@ -320,10 +323,11 @@ __global__ __launch_bounds__(256) void k_scatter(Particles P, Grid G, const int 
 
 hipError_t launch_scatter(hipStream_t s, const Particles &P, const Grid &G, const int *cid,
                           const int *slot, const int *start, Rec *rec, Rec32 *rec32, int *perm,
-                          int *rank) {
+                          int *rank, const BatchDev *B) {
   if (P.n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_scatter, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, s, P, G, cid,
-                     slot, start, rec, rec32, perm, rank);
+                     slot, start, rec, rec32, perm, rank, B ? B->box_of : nullptr,
+                     B ? B->sbox : nullptr, B ? (const unsigned int *)B->flags : nullptr);
   return hipGetLastError();
 }
 
@@ -448,7 +452,8 @@ __device__ __forceinline__ void detect_chunk(const DetectArgs &A, HP p, int h0, 
 
 // One home sphere (FP32 record in scalar registers) against the lane's candidate.
 template <bool SHIFT, bool MASK>
-__device__ __forceinline__ void pair32(const DetectArgs &A, int g, int thr, int code, float bx,
+__device__ __forceinline__ void pair32(const DetectArgs &A, const Grid &G, int g, int thr, int code,
+                                       float bx,
                                        float by, float bz, float br, float bvx, float bvy,
                                        float bvz, int i, float ax, float ay, float az, float ar,
                                        float avx, float avy, float avz, unsigned int *nrecheck) {
@@ -461,7 +466,6 @@ __device__ __forceinline__ void pair32(const DetectArgs &A, int g, int thr, int 
   if ((!MASK || i < thr) && __builtin_fmaf(bb, A.dt2f, cc) <= 0.0f) {
     ++*nrecheck;
     // binary64 rule for the survivor, from the full records
-    const Grid &G = A.G;
     const crec_ptr hrec = (crec_ptr)A.rec;
     const Rec b = A.rec[g];
     const double xi = hrec[i].x, yi = hrec[i].y, zi = hrec[i].z, ri = hrec[i].r;
@@ -479,10 +483,9 @@ __device__ __forceinline__ void pair32(const DetectArgs &A, int g, int thr, int 
 }
 
 template <bool SHIFT, bool MASK, typename HP>
-__device__ __forceinline__ void detect_chunk32(const DetectArgs &A, HP p, int h0, int h1, int g,
-                                               int thr, int code, double ox, double oy, double oz,
-                                               unsigned int *nrecheck) {
-  const Grid &G = A.G;
+__device__ __forceinline__ void detect_chunk32(const DetectArgs &A, const Grid &G, HP p, int h0,
+                                               int h1, int g, int thr, int code, double ox,
+                                               double oy, double oz, unsigned int *nrecheck) {
   float bx, by, bz, bvx, bvy, bvz, br;
   if (thr >= 0) {
     const Rec b = A.rec[g];
@@ -501,24 +504,26 @@ __device__ __forceinline__ void detect_chunk32(const DetectArgs &A, HP p, int h0
   }
   int i = h0;
   for (; i + 1 < h1; i += 2, p += 2) {
-    pair32<SHIFT, MASK>(A, g, thr, code, bx, by, bz, br, bvx, bvy, bvz, i, p[0].x, p[0].y, p[0].z,
+    pair32<SHIFT, MASK>(A, G, g, thr, code, bx, by, bz, br, bvx, bvy, bvz, i, p[0].x, p[0].y, p[0].z,
                         p[0].r, p[0].vx, p[0].vy, p[0].vz, nrecheck);
-    pair32<SHIFT, MASK>(A, g, thr, code, bx, by, bz, br, bvx, bvy, bvz, i + 1, p[1].x, p[1].y,
+    pair32<SHIFT, MASK>(A, G, g, thr, code, bx, by, bz, br, bvx, bvy, bvz, i + 1, p[1].x, p[1].y,
                         p[1].z, p[1].r, p[1].vx, p[1].vy, p[1].vz, nrecheck);
   }
   if (i < h1)
-    pair32<SHIFT, MASK>(A, g, thr, code, bx, by, bz, br, bvx, bvy, bvz, i, p[0].x, p[0].y, p[0].z,
+    pair32<SHIFT, MASK>(A, G, g, thr, code, bx, by, bz, br, bvx, bvy, bvz, i, p[0].x, p[0].y, p[0].z,
                         p[0].r, p[0].vx, p[0].vy, p[0].vz, nrecheck);
 }
 
+// Pair tests of one home cell (see k_detect_half).  `start` points at the first
+// cell of the box whose grid is G (cell numbers below are local to that box;
+// sphere positions in start[] are global).  LDSI: lds_raw holds room for the
+// home cell and the workgroup is this single wave.
 template <bool FP32, bool LDSI>
-__global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
-  extern __shared__ double4 lds_raw[];  // LDSI: the home cell's records (Rec or Rec32)
-  const Grid &G = A.G;
-  const int cell = xcd_remap(blockIdx.x, gridDim.x);
+__device__ __forceinline__ void detect_cell(const DetectArgs &A, const Grid &G, const int *start,
+                                            int cell, unsigned int &nrc, double4 *lds_raw) {
   const int nc0 = G.nc[0], nc1 = G.nc[1], nc2 = G.nc[2];
   const int cx = cell % nc0, cy = (cell / nc0) % nc1, cz = cell / (nc0 * nc1);
-  const int h0 = A.start[cell], h1 = A.start[cell + 1];
+  const int h0 = start[cell], h1 = start[cell + 1];
   if (h1 <= h0) return;
   if (LDSI) {  // stage the home cell (cap >= occupancy of every cell)
     for (int k = threadIdx.x; k < h1 - h0; k += WAVE) {
@@ -545,13 +550,13 @@ __global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
   rc[0] = run_code(0, 0, 0, 1);
   if (cx + 1 >= nc0) {
     const int rowbase = (cz * nc1 + cy) * nc0;
-    rg[1] = A.start[rowbase];
-    rl[1] = A.start[rowbase + 1] - rg[1];
+    rg[1] = start[rowbase];
+    rl[1] = start[rowbase + 1] - rg[1];
     rc[1] = run_code(1, 0, 0, 0);
     any_shift = true;
   } else {
     rg[1] = h1;
-    rl[1] = A.start[cell + 2] - h1;
+    rl[1] = start[cell + 2] - h1;
   }
   const int dys[4] = {1, -1, 0, 1}, dzs[4] = {0, 1, 1, 1};
 #pragma unroll
@@ -572,24 +577,24 @@ __global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
     const int rowbase = (z * nc1 + y) * nc0;
     const int k0 = 2 + 2 * row, k1 = 3 + 2 * row;
     if (cx - 1 < 0) {  // the wrapped left cell, then cells 0..1
-      rg[k0] = A.start[rowbase + nc0 - 1];
-      rl[k0] = A.start[rowbase + nc0] - rg[k0];
+      rg[k0] = start[rowbase + nc0 - 1];
+      rl[k0] = start[rowbase + nc0] - rg[k0];
       rc[k0] = run_code(-1, sy, sz, 0);
-      rg[k1] = A.start[rowbase];
-      rl[k1] = A.start[rowbase + 2] - rg[k1];
+      rg[k1] = start[rowbase];
+      rl[k1] = start[rowbase + 2] - rg[k1];
       rc[k1] = run_code(0, sy, sz, 0);
       any_shift = true;
     } else if (cx + 1 >= nc0) {  // cells cx-1..cx, then the wrapped right cell 0
-      rg[k0] = A.start[rowbase + cx - 1];
-      rl[k0] = A.start[rowbase + cx + 1] - rg[k0];
+      rg[k0] = start[rowbase + cx - 1];
+      rl[k0] = start[rowbase + cx + 1] - rg[k0];
       rc[k0] = run_code(0, sy, sz, 0);
-      rg[k1] = A.start[rowbase];
-      rl[k1] = A.start[rowbase + 1] - rg[k1];
+      rg[k1] = start[rowbase];
+      rl[k1] = start[rowbase + 1] - rg[k1];
       rc[k1] = run_code(1, sy, sz, 0);
       any_shift = true;
     } else {
-      rg[k0] = A.start[rowbase + cx - 1];
-      rl[k0] = A.start[rowbase + cx + 2] - rg[k0];
+      rg[k0] = start[rowbase + cx - 1];
+      rl[k0] = start[rowbase + cx + 2] - rg[k0];
       rc[k0] = run_code(0, sy, sz, 0);
     }
     if (sy != 0 || sz != 0) any_shift = true;
@@ -602,8 +607,7 @@ __global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
     total += rl[k];
   }
 
-  const int lane = threadIdx.x;
-  unsigned int nrc = 0u;
+  const int lane = __lane_id();
   for (int base = 0; base < total; base += WAVE) {
     const int v = base + lane;
     int g = 0, code = run_code(0, 0, 0, 0);
@@ -626,27 +630,27 @@ __global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
         const Rec32 *p = (const Rec32 *)lds_raw;
         if (base < rl[0]) {
           if (any_shift)
-            detect_chunk32<true, true>(A, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
+            detect_chunk32<true, true>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
           else
-            detect_chunk32<false, true>(A, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
+            detect_chunk32<false, true>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
         } else {
           if (any_shift)
-            detect_chunk32<true, false>(A, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
+            detect_chunk32<true, false>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
           else
-            detect_chunk32<false, false>(A, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
+            detect_chunk32<false, false>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
         }
       } else {
         const crec32_ptr p = (crec32_ptr)A.rec32 + h0;
         if (base < rl[0]) {
           if (any_shift)
-            detect_chunk32<true, true>(A, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
+            detect_chunk32<true, true>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
           else
-            detect_chunk32<false, true>(A, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
+            detect_chunk32<false, true>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
         } else {
           if (any_shift)
-            detect_chunk32<true, false>(A, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
+            detect_chunk32<true, false>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
           else
-            detect_chunk32<false, false>(A, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
+            detect_chunk32<false, false>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
         }
       }
       continue;
@@ -679,9 +683,49 @@ __global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
       }
     }
   }
+}
+
+template <bool FP32, bool LDSI>
+__global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
+  extern __shared__ double4 lds_raw[];  // LDSI: the home cell's records (Rec or Rec32)
+  unsigned int nrc = 0u;
+  detect_cell<FP32, LDSI>(A, A.G, A.start, xcd_remap(blockIdx.x, gridDim.x), nrc, lds_raw);
   if (FP32) {
     const unsigned long long tot = wave_sum((unsigned long long)nrc);
-    if (lane == 0 && tot) atomicAdd(&A.ctr->shard[blockIdx.x % NSHARD].recheck, tot);
+    if (__lane_id() == 0 && tot) atomicAdd(&A.ctr->shard[blockIdx.x % NSHARD].recheck, tot);
+  }
+}
+
+// Box of a global cell number: the last b with cell_base[b] <= c.
+__device__ __forceinline__ int box_of_cell(const int *cell_base, int nbox, int c) {
+  int lo = 0, hi = nbox - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (cell_base[mid] <= c)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Batched form: one persistent launch over the cells of all boxes.  Each wave
+// takes work items (global cell numbers) in a fixed interleaved order and runs
+// the single-box pair tests with its box's grid from the table.  Plain FP64
+// filter, home spheres through the scalar cache (no LDS, so a workgroup may
+// hold several independent waves).
+__global__ __launch_bounds__(256) void k_detect_batched(DetectArgs A, BatchDev B) {
+  if (B.flags[FLAG_ERR]) return;
+  const int wpb = blockDim.x / WAVE;
+  const int wave = threadIdx.x / WAVE;
+  const int total = B.cell_base[B.nbox];
+  const int stride = gridDim.x * wpb;
+  unsigned int nrc = 0u;
+  for (int item = blockIdx.x * wpb + wave; item < total; item += stride) {
+    const int b = box_of_cell(B.cell_base, B.nbox, item);
+    const Grid G = B.gtab[b];
+    const int base = B.cell_base[b];
+    detect_cell<false, false>(A, G, A.start + base, item - base, nrc, nullptr);
   }
 }
 
@@ -750,7 +794,8 @@ __global__ __launch_bounds__(256) void k_slot_min(int n, int first, const int *c
                                                   const double *slot_t, const int *slot_j, int K,
                                                   uint8_t *status, const int *perm, int *key_j,
                                                   double *key_t, int *ovf_list,
-                                                  SweepCounters *ctr) {
+                                                  SweepCounters *ctr, const unsigned int *flags) {
+  if (flags && (flags[FLAG_ERR] || flags[FLAG_DONE])) return;
   const int i = blockIdx.x * 256 + threadIdx.x;
   bool ovf = false;
   unsigned long long nc = 0ull;
@@ -788,10 +833,11 @@ __global__ __launch_bounds__(256) void k_slot_min(int n, int first, const int *c
 
 hipError_t launch_slot_min(hipStream_t s, int n, int first, const int *cnt, const double *slot_t,
                            const int *slot_j, int K, uint8_t *status, const int *perm, int *key_j,
-                           double *key_t, int *ovf_list, SweepCounters *ctr) {
+                           double *key_t, int *ovf_list, SweepCounters *ctr,
+                           const unsigned int *flags) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_slot_min, dim3((n + 255) / 256), dim3(256), 0, s, n, first, cnt, slot_t,
-                     slot_j, K, status, perm, key_j, key_t, ovf_list, ctr);
+                     slot_j, K, status, perm, key_j, key_t, ovf_list, ctr, flags);
   return hipGetLastError();
 }
 
@@ -808,22 +854,27 @@ hipError_t launch_slot_min(hipStream_t s, int n, int first, const int *cnt, cons
 // than 3 cells along some axis.
 __global__ __launch_bounds__(256) void k_gather_exact(const int *list, int nlist,
                                                       const unsigned int *nlist_dev, int select,
-                                                      const Rec *rec, const int *start, Grid G,
+                                                      const Rec *rec, const int *start, Grid G0,
                                                       double dt, uint8_t *status,
                                                       const int *perm, int *key_j,
-                                                      double *key_t) {
+                                                      double *key_t, BatchDev B) {
+  if (B.flags && (B.flags[FLAG_ERR] || B.flags[FLAG_DONE])) return;
   const int lane = __lane_id();
   const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   const int nw = (gridDim.x * blockDim.x) / WAVE;
   const int count = nlist_dev ? (int)*nlist_dev : nlist;
-  int nb[3], lo[3];
-  for (int a = 0; a < 3; ++a) {
-    nb[a] = G.nc[a] >= 3 ? 3 : G.nc[a];
-    lo[a] = G.nc[a] >= 3 ? -1 : 0;
-  }
   for (int w = wid; w < count; w += nw) {
     const int i = list ? list[w] : w;
     if (!list && select >= 0 && status[i] != (uint8_t)select) continue;
+    // the sphere's grid: the single one, or its box's in the batched form
+    const int bx = B.gtab ? B.sbox[i] : 0;
+    const Grid G = B.gtab ? B.gtab[bx] : G0;
+    const int *st = B.gtab ? start + B.cell_base[bx] : start;
+    int nb[3], lo[3];
+    for (int a = 0; a < 3; ++a) {
+      nb[a] = G.nc[a] >= 3 ? 3 : G.nc[a];
+      lo[a] = G.nc[a] >= 3 ? -1 : 0;
+    }
     const Rec a = rec[i];
     const int cx = cell_coord(a.x, G.inv_h[0], G.nc[0]);
     const int cy = cell_coord(a.y, G.inv_h[1], G.nc[1]);
@@ -837,7 +888,7 @@ __global__ __launch_bounds__(256) void k_gather_exact(const int *list, int nlist
           const int y = (cy + lo[1] + ky + G.nc[1]) % G.nc[1];
           const int z = (cz + lo[2] + kz + G.nc[2]) % G.nc[2];
           const int q = (z * G.nc[1] + y) * G.nc[0] + x;
-          const int s0 = start[q], s1 = start[q + 1];
+          const int s0 = st[q], s1 = st[q + 1];
           for (int j = s0 + lane; j < s1; j += WAVE) {
             if (j == i) continue;
             if (status[j] == ST_COLLIDED) continue;
@@ -874,13 +925,14 @@ __global__ __launch_bounds__(256) void k_gather_exact(const int *list, int nlist
 hipError_t launch_gather_exact(hipStream_t s, const int *list, int nlist, const unsigned int *nlist_dev,
                                int select, const Rec *rec, const int *start, const Grid &G,
                                double dt, uint8_t *status, const int *perm, int *key_j,
-                               double *key_t) {
+                               double *key_t, const BatchDev *B) {
   int64_t waves = nlist_dev ? 8192 : nlist;
   if (waves <= 0) return hipSuccess;
   if (waves > 8192) waves = 8192;
   const int blocks = (int)((waves + 3) / 4);
+  BatchDev none{};
   hipLaunchKernelGGL(k_gather_exact, dim3(blocks), dim3(256), 0, s, list, nlist, nlist_dev, select,
-                     rec, start, G, dt, status, perm, key_j, key_t);
+                     rec, start, G, dt, status, perm, key_j, key_t, B ? *B : none);
   return hipGetLastError();
 }
 
@@ -895,11 +947,12 @@ hipError_t launch_gather_exact(hipStream_t s, const int *list, int nlist, const 
 // thread writes only its own status, and reads only keys, so the sweep is a
 // pure function of the keys.  Partners are spatial neighbours, so the partner
 // reads stay within a few cells of the sorted order.
-__global__ __launch_bounds__(256) void k_resolve_sweep(int n, const Rec *rec, Grid G, double dt,
+__global__ __launch_bounds__(256) void k_resolve_sweep(int n, const Rec *rec, Grid G0, double dt,
                                                        double e, const int *key_j,
                                                        const double *key_t, uint8_t *status,
                                                        const int *perm, OutRec *out,
-                                                       SweepCounters *ctr) {
+                                                       SweepCounters *ctr, BatchDev B) {
+  if (B.flags && (B.flags[FLAG_ERR] || B.flags[FLAG_DONE])) return;
   const int i = blockIdx.x * 256 + threadIdx.x;
   unsigned long long npair = 0ull;
   if (i < n && status[i] == ST_ACTIVE) {
@@ -912,7 +965,12 @@ __global__ __launch_bounds__(256) void k_resolve_sweep(int n, const Rec *rec, Gr
         const Rec a = rec[i], b = rec[p];
         const double t = key_t[i];
         double xo[3], vo[3];
-        resolve_one(a, b, G, t, dt, e, xo, vo);
+        if (B.gtab) {
+          const Grid G = B.gtab[B.sbox[i]];
+          resolve_one(a, b, G, t, dt, e, xo, vo);
+        } else {
+          resolve_one(a, b, G0, t, dt, e, xo, vo);
+        }
         OutRec o;
         o.x = xo[0];
         o.y = xo[1];
@@ -936,20 +994,24 @@ __global__ __launch_bounds__(256) void k_resolve_sweep(int n, const Rec *rec, Gr
 
 hipError_t launch_resolve_sweep(hipStream_t s, int n, const Rec *rec, const Grid &G, double dt,
                                 double e, const int *key_j, const double *key_t, uint8_t *status,
-                                const int *perm, OutRec *out, SweepCounters *ctr) {
+                                const int *perm, OutRec *out, SweepCounters *ctr,
+                                const BatchDev *B) {
   if (n <= 0) return hipSuccess;
+  BatchDev none{};
   hipLaunchKernelGGL(k_resolve_sweep, dim3((n + 255) / 256), dim3(256), 0, s, n, rec, G, dt, e,
-                     key_j, key_t, status, perm, out, ctr);
+                     key_j, key_t, status, perm, out, ctr, B ? *B : none);
   return hipGetLastError();
 }
 
 // rule 5 in cell-sorted order: spheres that did not collide fly the whole step
 __global__ __launch_bounds__(256) void k_advance_sorted(int n, const Rec *rec,
-                                                        const uint8_t *status, double dt, Grid G,
-                                                        OutRec *out) {
+                                                        const uint8_t *status, double dt, Grid G0,
+                                                        OutRec *out, BatchDev B) {
+  if (B.flags && (B.flags[FLAG_ERR] || B.flags[FLAG_UNFINISHED])) return;
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n || status[i] == ST_COLLIDED) return;
   const Rec a = rec[i];
+  const Grid G = B.gtab ? B.gtab[B.sbox[i]] : G0;
   OutRec o;
   o.x = wrap_pos(a.x + dt * a.vx, G.L[0]);
   o.y = wrap_pos(a.y + dt * a.vy, G.L[1]);
@@ -964,17 +1026,20 @@ __global__ __launch_bounds__(256) void k_advance_sorted(int n, const Rec *rec,
 }
 
 hipError_t launch_advance_sorted(hipStream_t s, int n, const Rec *rec, const uint8_t *status,
-                                 double dt, const Grid &G, OutRec *out) {
+                                 double dt, const Grid &G, OutRec *out, const BatchDev *B) {
   if (n <= 0) return hipSuccess;
+  BatchDev none{};
   hipLaunchKernelGGL(k_advance_sorted, dim3((n + 255) / 256), dim3(256), 0, s, n, rec, status, dt,
-                     G, out);
+                     G, out, B ? *B : none);
   return hipGetLastError();
 }
 
 // end-of-step state back to the caller's order: one 64-B record gathered per
 // sphere, coalesced writes
 __global__ __launch_bounds__(256) void k_unpermute(Particles P, const int *rank, const OutRec *out,
-                                                   int *partner, double *tcoll) {
+                                                   int *partner, double *tcoll,
+                                                   const unsigned int *flags) {
+  if (flags && (flags[FLAG_ERR] || flags[FLAG_UNFINISHED])) return;
   const int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (o >= P.n) return;
   const OutRec q = out[rank[o]];
@@ -989,10 +1054,10 @@ __global__ __launch_bounds__(256) void k_unpermute(Particles P, const int *rank,
 }
 
 hipError_t launch_unpermute(hipStream_t s, const Particles &P, const int *rank, const OutRec *out,
-                            int *partner, double *tcoll) {
+                            int *partner, double *tcoll, const unsigned int *flags) {
   if (P.n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_unpermute, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, s, P, rank,
-                     out, partner, tcoll);
+                     out, partner, tcoll, flags);
   return hipGetLastError();
 }
 
@@ -1233,6 +1298,149 @@ hipError_t launch_step_backward(hipStream_t s, const Particles &P, const Grid &G
   hipLaunchKernelGGL(k_step_backward, dim3((n + 255) / 256), dim3(256), 0, s, n, P.x, P.y, P.z,
                      P.vx, P.vy, P.vz, P.r, P.m, G, dt, e, partner, tcoll, gout, gin, ebuf);
   hipLaunchKernelGGL(k_sum_det, dim3(1), dim3(1024), 0, s, ebuf, n, ge);
+  return hipGetLastError();
+}
+
+}  // namespace pcol
+
+namespace pcol {
+
+// ---------------------------------------------------------------- batched form
+
+// box id of every sphere (caller order), one workgroup per box
+__global__ __launch_bounds__(256) void k_fill_box_of(const int64_t *box_off, int *box_of) {
+  const int b = blockIdx.x;
+  for (int64_t i = box_off[b] + threadIdx.x; i < box_off[b + 1]; i += 256) box_of[i] = b;
+}
+
+hipError_t launch_fill_box_of(hipStream_t s, int nbox, const int64_t *box_off, int *box_of) {
+  if (nbox <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_box_of, dim3(nbox), dim3(256), 0, s, box_off, box_of);
+  return hipGetLastError();
+}
+
+// a1 per box, one workgroup per box: data validity, reach = 2 max r + 2 max|v| dt
+// (stored), the box check L > 2 reach, and whether the planned cells are still
+// at least the reach wide (else the host re-plans before any state changes).
+__global__ __launch_bounds__(256) void k_breach(Particles P, BatchDev B, double dt,
+                                                int check_plan) {
+  const int b = blockIdx.x;
+  const Grid G = B.gtab[b];
+  double v2 = 0.0, rm = 0.0;
+  unsigned int bad = 0u;
+  for (int64_t i = B.box_off[b] + threadIdx.x; i < B.box_off[b + 1]; i += 256) {
+    const double x = P.x[i], y = P.y[i], z = P.z[i];
+    const double vx = P.vx[i], vy = P.vy[i], vz = P.vz[i];
+    const double r = P.r[i], m = P.m[i];
+    const double w = (vx * vx + vy * vy) + vz * vz;
+    const bool fin = isfinite(x) && isfinite(y) && isfinite(z) && isfinite(w) && isfinite(r) &&
+                     isfinite(m);
+    if (!fin || !(r > 0.0) || !(m > 0.0)) bad |= ERR_INVALID;
+    if (!(x >= 0.0 && x < G.L[0]) || !(y >= 0.0 && y < G.L[1]) || !(z >= 0.0 && z < G.L[2]))
+      bad |= ERR_INVALID;
+    if (fin) {
+      v2 = w > v2 ? w : v2;
+      rm = r > rm ? r : rm;
+    }
+  }
+  __shared__ double sv[4], sr[4];
+  __shared__ unsigned int sb[4];
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    const double a = __shfl_xor(v2, o), c = __shfl_xor(rm, o);
+    v2 = a > v2 ? a : v2;
+    rm = c > rm ? c : rm;
+    bad |= __shfl_xor(bad, o);
+  }
+  const int w = threadIdx.x / WAVE;
+  if (__lane_id() == 0) {
+    sv[w] = v2;
+    sr[w] = rm;
+    sb[w] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < 4; ++k) {
+      v2 = sv[k] > v2 ? sv[k] : v2;
+      rm = sr[k] > rm ? sr[k] : rm;
+      bad |= sb[k];
+    }
+    const double reach = 2.0 * rm + 2.0 * sqrt(v2) * dt;
+    B.breach[b] = reach;
+    for (int a = 0; a < 3; ++a) {
+      if (!(G.L[a] > 2.0 * reach)) bad |= ERR_BOX;
+      if (check_plan && !(reach * (1.0 + 1e-9) <= G.L[a] / G.nc[a])) bad |= ERR_REPLAN;
+    }
+    if (bad) atomicOr(&B.flags[FLAG_ERR], bad);
+  }
+}
+
+hipError_t launch_breach(hipStream_t s, const Particles &P, const BatchDev &B, double dt,
+                         int check_plan) {
+  if (B.nbox <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_breach, dim3(B.nbox), dim3(256), 0, s, P, B, dt, check_plan);
+  return hipGetLastError();
+}
+
+// a2 for many boxes: global cell number = the box's first cell + its local cell
+__global__ __launch_bounds__(256) void k_cell_hist_b(Particles P, BatchDev B, int *cid, int *slot,
+                                                     int *count) {
+  if (B.flags[FLAG_ERR]) return;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= P.n) return;
+  const int b = B.box_of[i];
+  const Grid G = B.gtab[b];
+  const int cx = cell_coord(P.x[i], G.inv_h[0], G.nc[0]);
+  const int cy = cell_coord(P.y[i], G.inv_h[1], G.nc[1]);
+  const int cz = cell_coord(P.z[i], G.inv_h[2], G.nc[2]);
+  const int c = B.cell_base[b] + (cz * G.nc[1] + cy) * G.nc[0] + cx;
+  cid[i] = c;
+  slot[i] = atomicAdd(&count[c], 1);
+}
+
+hipError_t launch_cell_hist_b(hipStream_t s, const Particles &P, const BatchDev &B, int *cid,
+                              int *slot, int *count) {
+  if (P.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cell_hist_b, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, s, P, B,
+                     cid, slot, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_detect_batched(hipStream_t s, const DetectArgs &A, const BatchDev &B,
+                                 int blocks, int waves_per_block) {
+  hipLaunchKernelGGL(k_detect_batched, dim3(blocks), dim3(WAVE * waves_per_block), 0, s, A, B);
+  return hipGetLastError();
+}
+
+// After a sweep's resolve: total the pairs it resolved (and the running totals),
+// clear the per-sweep counters, and mark the step done when the sweep resolved
+// none.  `last` marks the final sweep slot of a captured step: if pairs were
+// still resolved there, the step is unfinished and the host completes it.
+__global__ __launch_bounds__(64) void k_sweep_check(SweepCounters *ctr, unsigned int *flags,
+                                                    unsigned long long *totals, int last) {
+  if (flags[FLAG_ERR] || flags[FLAG_DONE]) return;
+  const int l = threadIdx.x;
+  unsigned long long p = ctr->shard[l].pairs, c = ctr->shard[l].contacts;
+  ctr->shard[l].pairs = 0ull;
+  ctr->shard[l].contacts = 0ull;
+  p = wave_sum(p);
+  c = wave_sum(c);
+  if (l == 0) {
+    totals[0] += p;
+    totals[1] += c;
+    totals[2] += ctr->n_overflow;
+    ctr->n_overflow = 0u;
+    flags[FLAG_SWEEPS] += 1u;
+    if (p == 0ull) {
+      flags[FLAG_DONE] = 1u;
+    } else if (last) {
+      flags[FLAG_UNFINISHED] = 1u;
+    }
+  }
+}
+
+hipError_t launch_sweep_check(hipStream_t s, SweepCounters *ctr, unsigned int *flags,
+                              unsigned long long *totals, int last) {
+  hipLaunchKernelGGL(k_sweep_check, dim3(1), dim3(64), 0, s, ctr, flags, totals, last);
   return hipGetLastError();
 }
 

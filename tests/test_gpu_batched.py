@@ -1,0 +1,244 @@
+"""GPU tests of the batched form (pcol_step_batched): many uneven periodic boxes
+stepped by one captured graph with a persistent pair-test launch.
+
+Every box must come out exactly as the oracle steps it alone (pair set and
+contact times bitwise, states within 1e-12 relative), across graph replays with
+other GPU work in between, after a forced re-plan, when the captured sweeps run
+out and the host finishes the step, and whatever the autotuner picks.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from workloads import Box
+
+pytestmark = pytest.mark.gpu
+
+pc = pytest.importorskip("paper_2501_05340_amd")
+
+FIELDS = ("x", "y", "z", "vx", "vy", "vz")
+ALL = FIELDS + ("r", "m")
+
+
+def _empty_box(L, dt, e):
+    z = np.zeros(0)
+    return Box(z, z, z, z, z, z, z, z, (L, L, L), dt, e, "empty")
+
+
+def _uneven_boxes(seed=11):
+    """Boxes of different sizes, densities, radius laws and aspect, one step dt."""
+    dt = 0.4
+    boxes = [
+        workloads.make_box(1500, seed=seed, phi=0.3, radius=1.0, e=0.9, dt=dt),
+        workloads.make_box(200, seed=seed + 1, phi=0.05, radius=1.0, e=0.9, dt=dt),
+        workloads.make_box(4000, seed=seed + 2, phi=0.35, lognormal=(1.0, 0.25, 0.5, 2.0),
+                           e=0.9, dt=dt),
+        workloads.make_box(1, seed=seed + 3, phi=0.01, radius=1.0, e=0.9, dt=dt, L=12.0),
+        _empty_box(15.0, dt, 0.9),
+        workloads.make_box(900, seed=seed + 4, phi=0.2, radius=0.7, e=0.9, dt=dt),
+        workloads.make_box(2500, seed=seed + 5, phi=0.25, radius=1.0, e=0.9, dt=dt),
+    ]
+    return boxes
+
+
+def _concat(boxes):
+    off = np.cumsum([0] + [b.n for b in boxes]).astype(np.int64)
+    arrs = [np.concatenate([getattr(b, f) for b in boxes]) for f in ALL]
+    dev = [torch.as_tensor(a, dtype=torch.float64).cuda().contiguous() for a in arrs]
+    return pc.Particles(*dev), off
+
+
+def _oracle_steps(boxes, e):
+    """Each box stepped alone by the oracle; returns the per-box results."""
+    out = []
+    for b in boxes:
+        bb = b.copy()
+        bb.e = e
+        out.append(oracle.step(bb) if bb.n else None)
+    return out
+
+
+def _advance(boxes, res):
+    nxt = []
+    for b, r in zip(boxes, res):
+        if r is None:
+            nxt.append(b)
+        else:
+            nxt.append(Box(r.x, r.y, r.z, r.vx, r.vy, r.vz, b.r, b.m, b.L, b.dt, b.e, b.name))
+    return nxt
+
+
+def _check(boxes, off, res, p, partner, tcoll, rel=1e-12):
+    part = partner.cpu().numpy().astype(np.int64)
+    tc = tcoll.cpu().numpy()
+    st = {f: getattr(p, f).cpu().numpy() for f in FIELDS}
+    pairs = 0
+    for b, (box, r) in enumerate(zip(boxes, res)):
+        lo, hi = int(off[b]), int(off[b + 1])
+        if r is None:
+            assert hi == lo
+            continue
+        local = np.where(part[lo:hi] >= 0, part[lo:hi] - lo, -1)
+        assert np.array_equal(local, r.partner), f"box {b}: pair set differs"
+        assert np.array_equal(tc[lo:hi], r.tcoll, equal_nan=True), f"box {b}: contact times"
+        for f in FIELDS:
+            a, ref = st[f][lo:hi], getattr(r, f)
+            scale = max(1.0, float(np.max(np.abs(ref))))
+            assert np.max(np.abs(a - ref)) / scale <= rel, f"box {b}: {f}"
+        pairs += r.n_pairs
+    return pairs
+
+
+def _tune_env(tmp_path):
+    os.environ["PCOL_TUNE_CACHE"] = str(tmp_path / "tune.txt")
+
+
+def test_batched_matches_oracle_per_box_over_replays(tmp_path):
+    """Four consecutive steps through the same graph, with unrelated GPU work and
+    synchronisations between the replays; every replay checked against the
+    oracle stepping each box alone."""
+    _tune_env(tmp_path)
+    boxes = _uneven_boxes()
+    e = 0.9
+    p, off = _concat(boxes)
+    n = p.n
+    ctx = pc.Context(n, pc.pcol_default_opts(autotune=0))
+    partner = torch.empty(n, dtype=torch.int32, device="cuda")
+    tcoll = torch.empty(n, dtype=torch.float64, device="cuda")
+    Ls = [b.L for b in boxes]
+    cur = boxes
+    for step in range(4):
+        print(f"[gpu-test] batched replay step {step}", flush=True)
+        st = pc.pcol_step_batched(ctx, p, off, Ls, 0.4, e, partner, tcoll)
+        torch.cuda.synchronize()
+        res = _oracle_steps(cur, e)
+        pairs = _check(cur, off, res, p, partner, tcoll)
+        assert st["n_pairs"] == pairs and pairs > 100
+        assert st["n_sweeps"] == max(r.n_sweeps for r in res if r is not None)
+        if step == 0:
+            assert st["replanned"] == 1
+        cur = _advance(cur, res)
+        # eager work on the same stream between replays
+        junk = torch.randn(1 << 20, device="cuda", dtype=torch.float64)
+        junk = (junk * 2.0).sum()
+        torch.cuda.synchronize()
+
+
+def test_batched_replan_when_reach_outgrows_cells(tmp_path):
+    _tune_env(tmp_path)
+    boxes = _uneven_boxes(seed=5)
+    p, off = _concat(boxes)
+    n = p.n
+    ctx = pc.Context(n, pc.pcol_default_opts(autotune=0))
+    Ls = [b.L for b in boxes]
+    partner = torch.empty(n, dtype=torch.int32, device="cuda")
+    tcoll = torch.empty(n, dtype=torch.float64, device="cuda")
+    pc.pcol_step_batched(ctx, p, off, Ls, 0.4, 0.9, partner, tcoll)
+    torch.cuda.synchronize()
+    # speed up box 2 by 1.6x in place: its reach now exceeds its planned cells
+    lo, hi = int(off[2]), int(off[3])
+    for f in ("vx", "vy", "vz"):
+        getattr(p, f)[lo:hi] *= 1.6
+    torch.cuda.synchronize()
+    host = {f: getattr(p, f).cpu().numpy() for f in ALL}
+    cur = [Box(*[host[f][int(off[b]):int(off[b + 1])].copy() for f in ALL], bx.L, 0.4, 0.9)
+           for b, bx in enumerate(boxes)]
+    st = pc.pcol_step_batched(ctx, p, off, Ls, 0.4, 0.9, partner, tcoll)
+    torch.cuda.synchronize()
+    assert st["replanned"] == 1
+    res = _oracle_steps(cur, 0.9)
+    assert _check(cur, off, res, p, partner, tcoll) == st["n_pairs"]
+
+
+def test_batched_host_finishes_unfinished_sweeps(tmp_path):
+    """Only one sweep captured: the host must run the rest and the result is the same."""
+    _tune_env(tmp_path)
+    boxes = _uneven_boxes(seed=7)
+    p, off = _concat(boxes)
+    n = p.n
+    ctx = pc.Context(n, pc.pcol_default_opts(autotune=0, max_sweeps=1))
+    Ls = [b.L for b in boxes]
+    partner = torch.empty(n, dtype=torch.int32, device="cuda")
+    tcoll = torch.empty(n, dtype=torch.float64, device="cuda")
+    cur = boxes
+    for step in range(2):
+        st = pc.pcol_step_batched(ctx, p, off, Ls, 0.4, 0.9, partner, tcoll)
+        torch.cuda.synchronize()
+        res = _oracle_steps(cur, 0.9)
+        assert st["finished_on_host"] == 1 and st["n_sweeps"] > 1
+        assert _check(cur, off, res, p, partner, tcoll) == st["n_pairs"]
+        cur = _advance(cur, res)
+
+
+def test_batched_equals_single_box_steps_config_shape(tmp_path):
+    """64 boxes of the batching workload's recipe (log-uniform N in [1k, 8k],
+    phi in [0.05, 0.35]) against pcol_step run box by box (itself bitwise equal
+    to the oracle), autotuned; then a fresh context reads the tuning cache."""
+    _tune_env(tmp_path)
+    boxes = workloads.batch_boxes(64, seed=4, nmin=1e3, nmax=8e3)
+    p, off = _concat(boxes)
+    n = p.n
+    ref = p.clone()
+    single = pc.Context(max(b.n for b in boxes))
+    ref_part = torch.empty(n, dtype=torch.int32, device="cuda")
+    for b, bx in enumerate(boxes):
+        lo, hi = int(off[b]), int(off[b + 1])
+        sub = pc.Particles(*[t[lo:hi] for t in ref.tensors()])
+        pt = torch.empty(hi - lo, dtype=torch.int32, device="cuda")
+        pc.pcol_step(single, sub, bx.L, bx.dt, bx.e, pt, None, stats=False)
+        ref_part[lo:hi] = torch.where(pt >= 0, pt + lo, pt)
+    torch.cuda.synchronize()
+    results = []
+    for rep in range(2):
+        q = p.clone()
+        ctx = pc.Context(n, pc.pcol_default_opts(autotune=1))
+        partner = torch.empty(n, dtype=torch.int32, device="cuda")
+        st = pc.pcol_step_batched(ctx, q, off, [b.L for b in boxes], boxes[0].dt, boxes[0].e,
+                                  partner, None)
+        torch.cuda.synchronize()
+        assert torch.equal(partner, ref_part)
+        for f in FIELDS:
+            assert torch.equal(getattr(q, f).view(torch.int64), getattr(ref, f).view(torch.int64))
+        results.append(st)
+        ctx.close()
+    assert results[0]["tuned"] == 1 and results[1]["tuned"] == 0
+    assert results[0]["cell_mult"] == results[1]["cell_mult"]
+    assert results[0]["waves_per_block"] == results[1]["waves_per_block"]
+    assert os.path.exists(os.environ["PCOL_TUNE_CACHE"])
+
+
+def test_batched_errors(tmp_path):
+    _tune_env(tmp_path)
+    boxes = _uneven_boxes(seed=3)[:3]
+    p, off = _concat(boxes)
+    n = p.n
+    ctx = pc.Context(n, pc.pcol_default_opts(autotune=0))
+    Ls = [b.L for b in boxes]
+    with pytest.raises(pc.PcolError) as ei:
+        pc.pcol_step_batched(ctx, p, [0, 10, n - 1], Ls[:2], 0.4, 0.9)
+    assert ei.value.code == pc.PCOL_E_INVALID
+    with pytest.raises(pc.PcolError) as ei:
+        pc.pcol_step_batched(ctx, p, [0, 20, 10, n], Ls, 0.4, 0.9)
+    assert ei.value.code == pc.PCOL_E_INVALID
+    # a sphere of box 1 outside box 1 (box 1 is smaller than box 0)
+    q = p.clone()
+    q.x[int(off[1])] = Ls[1][0] + 0.5
+    with pytest.raises(pc.PcolError) as ei:
+        pc.pcol_step_batched(ctx, q, off, Ls, 0.4, 0.9)
+    assert ei.value.code == pc.PCOL_E_INVALID
+    # a dt so long that a box is under 3 reach wide
+    with pytest.raises(pc.PcolError) as ei:
+        pc.pcol_step_batched(ctx, p.clone(), off, Ls, 40.0, 0.9)
+    assert ei.value.code == pc.PCOL_E_BOX
+    # the context still works afterwards
+    q = p.clone()
+    partner = torch.empty(n, dtype=torch.int32, device="cuda")
+    tcoll = torch.empty(n, dtype=torch.float64, device="cuda")
+    pc.pcol_step_batched(ctx, q, off, Ls, 0.4, 0.9, partner, tcoll)
+    torch.cuda.synchronize()
+    res = _oracle_steps(boxes, 0.9)
+    _check(boxes, off, res, q, partner, tcoll)
