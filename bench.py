@@ -11,7 +11,11 @@ region) before each step, so each step processes the same batch.
 
 Prints one JSON line: particles stepped per second (value), pair tests per
 second of the detect kernel, the detect kernel's ALU roofline fraction, and the
-CPU oracle timed on a bounded sample of the same workload.
+CPU oracle timed on a bounded sample of the same workload.  Beside the plain
+FP64 path it reports the FP32 filter form on the same input, the batched form
+(512 uneven boxes, about 8M spheres, one captured graph per step, against a
+loop of single-box steps) and the adjoint form (10-step rollout of 1M spheres,
+forward and backward).
 """
 from __future__ import annotations
 
@@ -26,10 +30,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "pair tests/s + particles stepped/s at 16M; FP32+recheck vs FP64 at equal pair set"
-# FP64 arithmetic operations of one pair test in the detect kernel (separation 3,
-# relative velocity 3, s 1, b 5, c 7, the cheap reject bound 1); compares excluded
-OPS_PER_PAIR_TEST = 20
-# 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz: non-FMA binary64 operations per second
+# FP64 vector operations of one pair test in the detect kernel's filter:
+# separation 3, relative velocity 3, s and s^2 2, b' (1 multiply + 2 FMA),
+# c' (3 FMA), the test c' + b' dt2 (1 FMA); the compare excluded.  An FMA is
+# one operation here (two flops): 9 plain + 6 FMA = 15 operations, 21 flops.
+OPS_PER_PAIR_TEST = 15
+FLOPS_PER_PAIR_TEST = 21
+# 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz: binary64 vector operations per
+# second (an FMA is one; the published 78.6 TFLOP/s counts it as two flops)
 PEAK_FP64_OPS = 256 * 4 * 16 * 2.4e9
 
 
@@ -66,6 +74,145 @@ def cpu_baseline(args):
     }
 
 
+def batched_leg(args, pc, torch):
+    """Batching workload: 512 periodic boxes, N_b log-uniform in [1k, 64k], phi_b
+    uniform in [0.05, 0.35], radius 1, e 0.9, dt 0.4; all boxes stepped by one
+    pcol_step_batched call per step (autotuned on its first call), against the
+    same boxes stepped one pcol_step call at a time."""
+    import numpy as np
+    import workloads
+    t0 = time.perf_counter()
+    boxes = workloads.config(4)
+    off = np.cumsum([0] + [b.n for b in boxes]).astype(np.int64)
+    n = int(off[-1])
+    cat = lambda f: torch.as_tensor(np.concatenate([getattr(b, f) for b in boxes]),
+                                    dtype=torch.float64).cuda().contiguous()
+    p0 = pc.Particles(*[cat(f) for f in ("x", "y", "z", "vx", "vy", "vz", "r", "m")])
+    log(f"batched workload: {len(boxes)} boxes, {n} spheres, generated in "
+        f"{time.perf_counter() - t0:.1f} s")
+    Ls = [b.L for b in boxes]
+    dt, e = boxes[0].dt, boxes[0].e
+    p = p0.clone()
+    partner = torch.empty(n, dtype=torch.int32, device="cuda")
+
+    def restore():
+        for t, t_0 in zip(p.tensors()[:6], p0.tensors()[:6]):
+            t.copy_(t_0)
+
+    ctx = pc.Context(n, pc.pcol_default_opts(autotune=1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st0 = pc.pcol_step_batched(ctx, p, off, Ls, dt, e, partner, None)
+    torch.cuda.synchronize()
+    first_ms = (time.perf_counter() - t0) * 1e3
+    log(f"[batched] first call {first_ms:.1f} ms (plan, tune={st0['tuned']}, capture): "
+        f"cell_mult {st0['cell_mult']} waves/block {st0['waves_per_block']}")
+    for k in range(args.warmup):
+        restore()
+        pc.pcol_step_batched(ctx, p, off, Ls, dt, e, partner, None)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        restore()
+        stats.append(pc.pcol_step_batched(ctx, p, off, Ls, dt, e, partner, None))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for k, st in enumerate(stats):
+        log(f"[batched] step {k}: pairs {st['n_pairs']} sweeps {st['n_sweeps']} replanned "
+            f"{st['replanned']} host-finished {st['finished_on_host']}")
+    # the same step as a loop of single-box calls
+    ctx1 = pc.Context(max(b.n for b in boxes))
+    q = p0.clone()
+    part1 = torch.empty(n, dtype=torch.int32, device="cuda")
+    views = []
+    for b in range(len(boxes)):
+        lo, hi = int(off[b]), int(off[b + 1])
+        views.append((pc.Particles(*[t[lo:hi] for t in q.tensors()]), part1[lo:hi], boxes[b].L))
+
+    def loop_step():
+        for t, t_0 in zip(q.tensors()[:6], p0.tensors()[:6]):
+            t.copy_(t_0)
+        for sub, pt, L in views:
+            pc.pcol_step(ctx1, sub, L, dt, e, pt, None, stats=False)
+
+    loop_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nloop = max(1, min(args.steps, 3))
+    for k in range(nloop):
+        loop_step()
+    torch.cuda.synchronize()
+    loop_wall = (time.perf_counter() - t0) / nloop
+    # pair sets agree (loop partners are box-local)
+    loc = torch.empty_like(partner)
+    restore()
+    pc.pcol_step_batched(ctx, p, off, Ls, dt, e, partner, None)
+    for b in range(len(boxes)):
+        lo, hi = int(off[b]), int(off[b + 1])
+        pt = part1[lo:hi]
+        loc[lo:hi] = torch.where(pt >= 0, pt + lo, pt)
+    torch.cuda.synchronize()
+    mismatch = int((loc != partner).sum().item())
+    same_state = all(torch.equal(getattr(p, f).view(torch.int64), getattr(q, f).view(torch.int64))
+                     for f in ("x", "y", "z", "vx", "vy", "vz"))
+    ms = wall * 1e3 / args.steps
+    out = {
+        "value": n * args.steps / wall, "unit": "particles/s", "ms_per_step": ms,
+        "n_boxes": len(boxes), "n": n,
+        "box_loop_ms_per_step": loop_wall * 1e3,
+        "speedup_vs_box_loop": loop_wall * 1e3 / ms,
+        "pair_set_mismatch_vs_box_loop": mismatch, "state_bitwise_equal_to_box_loop": same_state,
+        "first_call_ms": first_ms, "tuned_on_first_call": bool(st0["tuned"]),
+        "cell_mult": st0["cell_mult"], "waves_per_block": st0["waves_per_block"],
+        "total_cells": st0["total_cells"],
+        "pairs_per_step": statistics.mean(st["n_pairs"] for st in stats),
+        "sweeps_per_step": statistics.mean(st["n_sweeps"] for st in stats),
+        "replans_in_timed_steps": sum(st["replanned"] for st in stats),
+    }
+    ctx.close()
+    ctx1.close()
+    return out
+
+
+def adjoint_leg(args, pc, torch):
+    """Differentiation workload: 1M spheres (phi 0.2, radius 1, e 0.9 learnable),
+    10 FP64 steps through the autograd rollout, loss = sum |v|^2 at the end;
+    forward (steps plus checkpoints) and backward (recompute plus adjoint) timed."""
+    import workloads
+    box = workloads.config(5)
+    n = box.n
+    ctx = pc.Context(n)
+    p0 = pc.Particles.from_box(box)
+    nsteps = 10
+
+    def run():
+        ts = [getattr(p0, f).clone().requires_grad_(True) for f in ("x", "y", "z", "vx", "vy", "vz")]
+        e = torch.tensor(box.e, dtype=torch.float64, device="cuda", requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = pc.Rollout.apply(*ts, e, p0.r, p0.m, box.L, box.dt, nsteps, ctx, 1)
+        loss = (out[3] * out[3] + out[4] * out[4] + out[5] * out[5]).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return (t1 - t0) * 1e3, (t2 - t1) * 1e3, e.grad.item()
+
+    run()
+    fw, bw, ge = [], [], None
+    for k in range(max(1, min(args.steps, 3))):
+        a, b, ge = run()
+        fw.append(a)
+        bw.append(b)
+    ctx.close()
+    return {"n": n, "steps": nsteps, "forward_ms": statistics.median(fw),
+            "backward_ms": statistics.median(bw),
+            "backward_over_forward": statistics.median(bw) / statistics.median(fw),
+            "checkpoint_every": 1, "dloss_de": ge}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +223,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
     ap.add_argument("--form", choices=["both", "fp64", "fp32"], default="both",
                     help="plain FP64 path, FP32 filter + FP64 recheck, or both (value = fp64)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-form leg")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-form leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on one GPU only: the collision step is a single-GPU build; "
@@ -136,6 +285,7 @@ def main():
     tests = sum(st["pair_tests"] for st in stats)
     det_total = sum(det_ms) * 1e-3
     achieved = tests * OPS_PER_PAIR_TEST / det_total
+    flops = tests * FLOPS_PER_PAIR_TEST / det_total
     out = {
         "metric": METRIC,
         "value": box.n * args.steps / wall,
@@ -157,9 +307,11 @@ def main():
         "pairs_per_step": statistics.mean(st["n_pairs"] for st in stats),
         "sweeps_per_step": statistics.mean(st["n_sweeps"] for st in stats),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_OPS / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_OPS, "traffic": None,
+                     "unit": "TOP/s", "frac": achieved / PEAK_FP64_OPS, "traffic": None,
                      "kernel": "k_detect_half",
-                     "note": f"{OPS_PER_PAIR_TEST} non-FMA FP64 ops per unordered pair test"},
+                     "note": f"FP64 vector operations (an FMA counts one): {OPS_PER_PAIR_TEST} per "
+                             f"unordered pair test; as flops ({FLOPS_PER_PAIR_TEST} per test) "
+                             f"{flops / 1e12:.2f} of 78.6 TFLOP/s"},
     }
     if "fp64" in forms and "fp32" in forms:
         A, B = forms["fp64"], forms["fp32"]
@@ -181,6 +333,10 @@ def main():
             "band": sb[0]["band"],
             "rechecks_per_step": statistics.mean(st["n_recheck"] for st in sb),
         }
+    if not args.no_batched:
+        out["batched_form"] = batched_leg(args, pc, torch)
+    if not args.no_adjoint:
+        out["adjoint_form"] = adjoint_leg(args, pc, torch)
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on {args.cpu_sample} spheres")
         out["cpu_baseline"] = cpu_baseline(args)
