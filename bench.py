@@ -41,6 +41,27 @@ FLOPS_PER_PAIR_TEST = 21
 PEAK_FP64_OPS = 256 * 4 * 16 * 2.4e9
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "step_poly16M_fp64_fp32.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2501_05340_amd", "csrc", f)
+                  for f in ("pcol_kernels.hip", "pcol_internal.h")]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the FP64 detect kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the plain-copy calibration), or
+    None when the kernel sources changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        vals = dict(line.split(" = ", 1) for line in text.splitlines() if " = " in line)
+        sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)).hexdigest()
+        if vals.get("kernel_sources_sha256", "").strip() != sha:
+            return None
+        return float(vals["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -307,7 +328,9 @@ def main():
         "pairs_per_step": statistics.mean(st["n_pairs"] for st in stats),
         "sweeps_per_step": statistics.mean(st["n_sweeps"] for st in stats),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_OPS / 1e12,
-                     "unit": "TOP/s", "frac": achieved / PEAK_FP64_OPS, "traffic": None,
+                     "unit": "TOP/s", "frac": achieved / PEAK_FP64_OPS,
+                     "traffic": measured_traffic() if main_form == "fp64" else None,
+                     "traffic_unit": "bytes per launch",
                      "kernel": "k_detect_half",
                      "note": f"FP64 vector operations (an FMA counts one): {OPS_PER_PAIR_TEST} per "
                              f"unordered pair test; as flops ({FLOPS_PER_PAIR_TEST} per test) "
