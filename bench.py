@@ -244,6 +244,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
     ap.add_argument("--form", choices=["both", "fp64", "fp32"], default="both",
                     help="plain FP64 path, FP32 filter + FP64 recheck, or both (value = fp64)")
+    ap.add_argument("--split-quantile", type=float, default=None,
+                    help="extent split quantile of the single-box path (default: the library's)")
+    ap.add_argument("--cell-mult", type=float, default=None,
+                    help="cell side factor of the single-box path (default: the library's)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-form leg")
     args = ap.parse_args()
@@ -263,7 +267,12 @@ def main():
     def run_form(fp32: int):
         """K timed steps of one form, each from the configured input."""
         p = p0.clone()
-        ctx = pc.Context(box.n, pc.pcol_default_opts(timing=1, fp32_filter=fp32))
+        kw = {}
+        if args.split_quantile is not None:
+            kw["split_quantile"] = args.split_quantile
+        if args.cell_mult is not None:
+            kw["cell_mult"] = args.cell_mult
+        ctx = pc.Context(box.n, pc.pcol_default_opts(timing=1, fp32_filter=fp32, **kw))
         partner = torch.empty(box.n, dtype=torch.int32, device="cuda")
         tcoll = torch.empty(box.n, dtype=torch.float64, device="cuda")
 
@@ -276,7 +285,8 @@ def main():
             restore()
             st = pc.pcol_step(ctx, p, box.L, box.dt, box.e, partner, tcoll)
             log(f"[{name}] warmup {k}: {st['n_pairs']} pairs, {st['n_sweeps']} sweeps, "
-                f"detect {st['ms_detect']:.3f} ms")
+                f"detect {st['ms_detect']:.3f} ms, nc {st['nc']}, wide {st['n_wide']}, "
+                f"rho_c {st['rho_c']:.4f}, reach {st['reach']:.4f}")
         torch.cuda.synchronize()
         stats = []
         t_start = time.perf_counter()

@@ -108,12 +108,18 @@ typedef struct {
   int timing;         /* 1: time kernels with HIP events; times land in pcol_stats */
   int autotune;       /* pcol_step_batched: 1 = pick cell size and workgroup shape by timing
                          candidates on the first call (cached, see pcol_step_batched) */
+  double split_quantile; /* extent split (default 0.99; 0 or 1 = off): the spheres whose extent
+                         r + |v| dt lies above this quantile are searched separately, so the
+                         grid's cells need only twice the quantile extent instead of the reach.
+                         Used when that shrinks the cells by 15% or more.  Results do not
+                         depend on it. */
 } pcol_opts;
 
 typedef struct {
   int64_t n_pairs;       /* collisions resolved */
   int64_t n_sweeps;      /* sweeps run, including the last one that resolved nothing */
-  int64_t pair_tests;    /* unordered candidate pairs tested geometrically */
+  int64_t pair_tests;    /* unordered candidate pairs tested geometrically (the half stencil
+                            plus the separate search of the spheres above the split extent) */
   int64_t contacts;      /* unordered pairs with a contact within dt (sweep 1) */
   int64_t n_overflow;    /* spheres whose contacts exceeded contact_slots */
   int64_t n_recheck;     /* FP32 filter survivors rechecked in FP64 (fp32_filter only) */
@@ -127,6 +133,8 @@ typedef struct {
   double ms_detect;      /*   the sweep-1 pair-test kernel alone */
   double ms_sweeps;      /*   partner selection and all resolve sweeps */
   double ms_advance;     /*   free flight and wrap */
+  int64_t n_wide;        /* spheres above the split extent (searched separately; 0 = no split) */
+  double rho_c;          /* split extent in use (0 = no split) */
 } pcol_stats;
 
 /* Fill *opts with the defaults listed above. */

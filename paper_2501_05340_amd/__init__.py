@@ -41,7 +41,8 @@ class pcol_opts(ctypes.Structure):
     _fields_ = [("cell_mult", ctypes.c_double), ("max_sweeps", ctypes.c_int),
                 ("home_cells", ctypes.c_int), ("contact_slots", ctypes.c_int),
                 ("fp32_filter", ctypes.c_int), ("band_rel", ctypes.c_double),
-                ("timing", ctypes.c_int), ("autotune", ctypes.c_int)]
+                ("timing", ctypes.c_int), ("autotune", ctypes.c_int),
+                ("split_quantile", ctypes.c_double)]
 
 
 class pcol_stats(ctypes.Structure):
@@ -53,7 +54,8 @@ class pcol_stats(ctypes.Structure):
                 ("reach", ctypes.c_double), ("band", ctypes.c_double),
                 ("ms_bin", ctypes.c_double),
                 ("ms_detect", ctypes.c_double), ("ms_sweeps", ctypes.c_double),
-                ("ms_advance", ctypes.c_double)]
+                ("ms_advance", ctypes.c_double), ("n_wide", ctypes.c_int64),
+                ("rho_c", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         out = {}

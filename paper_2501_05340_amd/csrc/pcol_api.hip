@@ -61,6 +61,15 @@ struct pcol_ctx {
   Grid G{};
   double reach = 0.0;
   double vmax = 0.0, rmin = 0.0, rmax = 0.0;
+  double binned_dt = 0.0;
+  // extent split: spheres with r + |v| dt > rho_c live in a second layer of
+  // cells; the first layer's pair test then needs cells of side 2 rho_c only
+  bool split = false;
+  double rho_c = INFINITY, rho_max = 0.0;
+  int wide_first = 0, n_wide = 0;  // sorted range of the second layer
+  int *wide_h = nullptr;           // pinned read-back of that range
+  // bounds for the first layer's pair test: reach, speed and radius
+  double reach_pass = 0.0, vmax_pass = 0.0, rmax_pass = 0.0;
   double band = 0.0;   // FP32 filter band in use (relative to r_i + r_j)
   double h[3] = {0, 0, 0};
   int maxcell = 0;
@@ -185,6 +194,7 @@ void pcol_default_opts(pcol_opts *o) {
   o->band_rel = 1e-4;
   o->timing = 0;
   o->autotune = 1;
+  o->split_quantile = 0.99;
 }
 
 const char *pcol_last_error(const pcol_ctx *ctx) {
@@ -210,6 +220,7 @@ void pcol_destroy(pcol_ctx *ctx) {
   if (ctx->reach_h) (void)hipHostFree(ctx->reach_h);
   if (ctx->ctr_h) (void)hipHostFree(ctx->ctr_h);
   if (ctx->tests_h) (void)hipHostFree(ctx->tests_h);
+  if (ctx->wide_h) (void)hipHostFree(ctx->wide_h);
   for (hipEvent_t &e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
   if (BatchPlan *bp = ctx->bp) {
@@ -235,7 +246,8 @@ pcol_status pcol_create(pcol_ctx **out, int64_t n_max, void *hip_stream, const p
   if (opts) ctx->opts = *opts;
   if (!(ctx->opts.cell_mult >= 1.0) || !isfinite(ctx->opts.cell_mult) ||
       ctx->opts.max_sweeps < 0 || ctx->opts.contact_slots < 0 || ctx->opts.contact_slots > 64 ||
-      !(ctx->opts.band_rel >= 0.0)) {
+      !(ctx->opts.band_rel >= 0.0) ||
+      !(ctx->opts.split_quantile >= 0.0 && ctx->opts.split_quantile <= 1.0)) {
     delete ctx;
     return PCOL_E_INVALID;
   }
@@ -269,6 +281,7 @@ pcol_status pcol_create(pcol_ctx **out, int64_t n_max, void *hip_stream, const p
   if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->reach_h, sizeof(ReachOut));
   if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->ctr_h, sizeof(SweepCounters));
   if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->tests_h, sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->wide_h, 2 * sizeof(int));
   for (hipEvent_t &ev : ctx->ev)
     if (e == hipSuccess) e = hipEventCreate(&ev);
   if (e != hipSuccess) {
@@ -289,7 +302,7 @@ pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box
   PCOL_HIP(hipMemsetAsync(ctx->reach_d, 0, sizeof(ReachOut), s));
   PCOL_HIP(launch_fill_u32(s, (unsigned int *)&ctx->reach_d->rmin, 0u, 1));
   PCOL_HIP(launch_fill_u32(s, (unsigned int *)&ctx->reach_d->rmin + 1, 0x7ff00000u, 1));
-  PCOL_HIP(launch_reach(s, P, box->len, ctx->reach_d));
+  PCOL_HIP(launch_reach(s, P, box->len, dt, ctx->reach_d));
   PCOL_HIP(hipMemcpyAsync(ctx->reach_h, ctx->reach_d, sizeof(ReachOut), hipMemcpyDeviceToHost, s));
   PCOL_HIP(hipStreamSynchronize(s));
   const ReachOut ro = *ctx->reach_h;
@@ -303,20 +316,48 @@ pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box
   for (int a = 0; a < 3; ++a)
     if (!(box->len[a] > 2.0 * reach))
       return fail(ctx, PCOL_E_BOX, "box side <= 2 * reach: minimum image not unique");
-  // grid: cell side >= reach * cell_mult, at most 2^27 cells
+  double rho_max;
+  memcpy(&rho_max, &ro.rhomax, sizeof(double));
+  // Extent split: the first layer holds the spheres whose extent is at most
+  // rho_c, the upper edge of the histogram bin where the split quantile of the
+  // extents falls; pairs of them are at most 2 rho_c apart when they can touch.
+  // Used only when it shrinks the cells enough to pay for the separate search
+  // of the others, and the grid keeps 3 cells per axis.
+  double rho_c = INFINITY;
+  const double q = ctx->opts.split_quantile;
+  if (q > 0.0 && q < 1.0 && p->n >= 4096) {
+    const double target = ceil(q * (double)p->n);
+    double cum = 0.0;
+    for (int k = 0; k < RHO_BINS - 1; ++k) {
+      cum += ro.hist[k];
+      if (cum >= target) {
+        // upper edge of bin k: the lower edge of bin k + 1
+        const uint64_t top = (uint64_t)((1023 - 64) * 16 + k + 1);
+        const uint64_t bits = top << 48;
+        memcpy(&rho_c, &bits, sizeof(double));
+        break;
+      }
+    }
+    if (!(2.0 * rho_c < 0.85 * reach)) rho_c = INFINITY;
+    for (int a = 0; a < 3 && isfinite(rho_c); ++a)
+      if (box->len[a] / (2.0 * rho_c * ctx->opts.cell_mult * (1.0 + 1e-9)) < 3.0) rho_c = INFINITY;
+  }
+  const bool split = isfinite(rho_c);
+  const double reach_pass = split ? 2.0 * rho_c : reach;
+  // grid: cell side >= (split ? 2 rho_c : reach) * cell_mult, at most 2^26 cells per layer
   Grid G{};
-  double cell = reach * ctx->opts.cell_mult;
+  double cell = reach_pass * ctx->opts.cell_mult;
   if (!(cell > 0.0)) cell = box->len[0];  // no motion and no size: one cell
   for (;;) {
     int64_t ncell = 1;
     for (int a = 0; a < 3; ++a) {
-      double q = floor(box->len[a] / (cell * (1.0 + 1e-9)));
-      if (!(q >= 1.0)) q = 1.0;
-      if (q > 1024.0) q = 1024.0;
-      G.nc[a] = (int)q;
+      double q3 = floor(box->len[a] / (cell * (1.0 + 1e-9)));
+      if (!(q3 >= 1.0)) q3 = 1.0;
+      if (q3 > 1024.0) q3 = 1024.0;
+      G.nc[a] = (int)q3;
       ncell *= G.nc[a];
     }
-    if (ncell <= (1 << 27)) {
+    if (ncell <= (1 << 26)) {
       G.ncell = (int)ncell;
       break;
     }
@@ -331,14 +372,17 @@ pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box
     ctx->h[a] = G.h[a];
     if (G.nc[a] < 3) ctx->small = true;
   }
-  if ((int64_t)G.ncell + 2 > ctx->cell_cap) {
+  G.layer2 = split ? G.ncell : 0;
+  G.rho_max = split ? rho_max : 0.0;
+  const int cells_all = split ? 2 * G.ncell : G.ncell;
+  if ((int64_t)cells_all + 2 > ctx->cell_cap) {
     if (ctx->count) (void)hipFree(ctx->count);
     if (ctx->start) (void)hipFree(ctx->start);
     if (ctx->blocksum) (void)hipFree(ctx->blocksum);
     ctx->count = ctx->start = ctx->blocksum = nullptr;
     ctx->cell_cap = 0;
     if (ctx->bp) ctx->bp->captured = false;  // its graph holds the old cell arrays
-    const int64_t cap = (int64_t)G.ncell + 2;
+    const int64_t cap = (int64_t)cells_all + 2;
     hipError_t e = dalloc(&ctx->count, (size_t)cap);
     if (e == hipSuccess) e = dalloc(&ctx->start, (size_t)cap + 1);
     if (e == hipSuccess) e = dalloc(&ctx->blocksum, (size_t)(cap / 4096 + 2));
@@ -346,13 +390,16 @@ pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box
     ctx->cell_cap = cap;
   }
   // a2-a4: counting sort into cell-sorted records
-  PCOL_HIP(launch_fill_i32(s, ctx->count, 0, G.ncell));
-  PCOL_HIP(launch_cell_hist(s, P, G, ctx->cid, ctx->slot, ctx->count));
-  PCOL_HIP(launch_scan(s, ctx->count, G.ncell, ctx->start, ctx->blocksum, ctx->reach_d));
+  PCOL_HIP(launch_fill_i32(s, ctx->count, 0, cells_all));
+  PCOL_HIP(launch_cell_hist(s, P, G, dt, rho_c, ctx->cid, ctx->slot, ctx->count));
+  PCOL_HIP(launch_scan(s, ctx->count, cells_all, ctx->start, ctx->blocksum, ctx->reach_d));
   PCOL_HIP(launch_scatter(s, P, G, ctx->cid, ctx->slot, ctx->start, ctx->rec,
                           ctx->opts.fp32_filter ? ctx->rec32 : nullptr, ctx->perm, ctx->rank,
                           nullptr));
-  PCOL_HIP(hipMemcpyAsync(ctx->reach_h, ctx->reach_d, sizeof(ReachOut), hipMemcpyDeviceToHost, s));
+  PCOL_HIP(hipMemcpyAsync(&ctx->reach_h->maxcell, &ctx->reach_d->maxcell, sizeof(unsigned int),
+                          hipMemcpyDeviceToHost, s));
+  if (split)
+    PCOL_HIP(hipMemcpyAsync(ctx->wide_h, ctx->start + G.layer2, sizeof(int), hipMemcpyDeviceToHost, s));
   PCOL_HIP(hipStreamSynchronize(s));
   ctx->maxcell = (int)ctx->reach_h->maxcell;
   ctx->G = G;
@@ -360,15 +407,27 @@ pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box
   ctx->vmax = sqrt(v2);
   ctx->rmin = rmin;
   ctx->rmax = rmax;
+  ctx->binned_dt = dt;
+  ctx->split = split;
+  ctx->rho_c = rho_c;
+  ctx->rho_max = rho_max;
+  ctx->wide_first = split ? ctx->wide_h[0] : (int)p->n;
+  ctx->n_wide = (int)p->n - ctx->wide_first;
+  // first-layer bounds: extent <= rho_c gives |v| <= (rho_c - r_min) / dt, r <= rho_c
+  ctx->reach_pass = reach_pass;
+  ctx->vmax_pass = split ? std::min(ctx->vmax, (rho_c - rmin) / dt) : ctx->vmax;
+  ctx->rmax_pass = split ? std::min(rmax, rho_c) : rmax;
   ctx->binned = true;
   ctx->binned_n = p->n;
   ctx->binned_x = p->x;
   return PCOL_OK;
 }
 
-static pcol_status check_binned(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box) {
+static pcol_status check_binned(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box,
+                                double dt) {
   if (!ctx->binned || ctx->binned_n != p->n)
     return fail(ctx, PCOL_E_STATE, "pcol_bin must run first on the same particle set");
+  if (dt != ctx->binned_dt) return fail(ctx, PCOL_E_STATE, "dt differs from pcol_bin");
   for (int a = 0; a < 3; ++a)
     if (box->len[a] != ctx->G.L[a]) return fail(ctx, PCOL_E_STATE, "box differs from pcol_bin");
   return PCOL_OK;
@@ -387,11 +446,11 @@ static double fp32_band(const pcol_ctx *ctx, double dt) {  // returns the band
   const double u = 0x1.0p-24;
   double h = ctx->h[0];
   for (int a = 1; a < 3; ++a) h = ctx->h[a] > h ? ctx->h[a] : h;
-  const double R = ctx->reach, V = ctx->vmax, smin = 2.0 * ctx->rmin;
+  const double R = ctx->reach_pass, V = ctx->vmax_pass, smin = 2.0 * ctx->rmin;
   const double k0 = 1.0 + ctx->opts.band_rel + 1e-3;  // generous k for the radius term
   const double Dd = (2.0 * h + R) * u, Du = 4.0 * V * u;
   const double ec = 2.0 * sqrt(3.0) * R * Dd + 3.0 * u * R * R +
-                    6.0 * u * (2.0 * ctx->rmax * k0) * (2.0 * ctx->rmax * k0);
+                    6.0 * u * (2.0 * ctx->rmax_pass * k0) * (2.0 * ctx->rmax_pass * k0);
   const double eb = (sqrt(3.0) * (R * Du + 2.0 * V * Dd) + 6.0 * u * R * V) * 2.0 * dt *
                     (1.0 + 0x1.0p-11);
   const double need = 2.0 * (ec + eb) / (2.0 * smin * smin);
@@ -417,8 +476,8 @@ static pcol_status detect_all(pcol_ctx *ctx, double dt) {
     {
       // 16 eps (reach^2 + (2 rmax)^2 + reach * 2 vmax * dt2): twice the bound on the
       // differences between the filter's FMA values and the rule's b, c (pair64)
-      const double R = ctx->reach, smax = 2.0 * ctx->rmax;
-      A.tol = 16.0 * 0x1.0p-53 * (R * R + smax * smax + R * 2.0 * ctx->vmax * A.dt2);
+      const double R = ctx->reach_pass, smax = 2.0 * ctx->rmax_pass;
+      A.tol = 16.0 * 0x1.0p-53 * (R * R + smax * smax + R * 2.0 * ctx->vmax_pass * A.dt2);
     }
     A.K = ctx->K;
     A.rec32 = ctx->rec32;
@@ -438,6 +497,8 @@ static pcol_status detect_all(pcol_ctx *ctx, double dt) {
     PCOL_HIP(launch_fill_i32(s, ctx->cnt, 0, n));
     if (ctx->opts.timing) PCOL_HIP(hipEventRecord(ctx->ev[5], s));
     PCOL_HIP(launch_detect_half(s, A));
+    // spheres of large extent: exact search of their wider neighbourhood
+    if (ctx->split) PCOL_HIP(launch_detect_wide(s, A, ctx->wide_first, ctx->n_wide));
     if (ctx->opts.timing) PCOL_HIP(hipEventRecord(ctx->ev[6], s));
     ctx->detect_timed = true;
     PCOL_HIP(launch_slot_min(s, n, 1, ctx->cnt, ctx->slot_t, ctx->slot_j, ctx->K, ctx->status,
@@ -466,7 +527,7 @@ pcol_status pcol_detect(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *
                         const uint8_t *active, uint64_t *key_out, double *tmin_out) {
   pcol_status st = check_common(ctx, p, box, dt);
   if (st != PCOL_OK) return st;
-  if ((st = check_binned(ctx, p, box)) != PCOL_OK) return st;
+  if ((st = check_binned(ctx, p, box, dt)) != PCOL_OK) return st;
   if (p->n > 0 && !key_out) return fail(ctx, PCOL_E_INVALID, "key_out is null");
   hipStream_t s = ctx->stream;
   const int n = (int)p->n;
@@ -492,7 +553,7 @@ pcol_status pcol_resolve(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, 
   pcol_status st = check_common(ctx, p, box, dt);
   if (st != PCOL_OK) return st;
   if (!(e >= 0.0 && e <= 1.0)) return fail(ctx, PCOL_E_INVALID, "e outside [0, 1]");
-  if ((st = check_binned(ctx, p, box)) != PCOL_OK) return st;
+  if ((st = check_binned(ctx, p, box, dt)) != PCOL_OK) return st;
   if (p->n > 0 && (!key || !active)) return fail(ctx, PCOL_E_INVALID, "key or active is null");
   PCOL_HIP(launch_resolve_public(ctx->stream, (int)p->n, ctx->rec, ctx->rank, ctx->G, dt, e, key,
                                  to_dev(p), active, partner, tcoll, (long long *)n_pairs_dev));
@@ -523,7 +584,7 @@ pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, dou
   double *tc = tcoll ? tcoll : ctx->tcoll_tmp;
   const Particles P = to_dev(p);
   int64_t pairs = 0, sweeps = 0, ovf_total = 0;
-  unsigned long long contacts = 0ull, recheck = 0ull;
+  unsigned long long contacts = 0ull, recheck = 0ull, wide_tests = 0ull;
   double ms_detect = 0.0;
   if (n > 0) {
     PCOL_HIP(launch_fill_u8(s, ctx->status, ST_ACTIVE, n));
@@ -542,7 +603,10 @@ pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, dou
       sum_counters(*ctx->ctr_h, sp, sc);
       if (sweeps == 0) {
         contacts = sc / 2ull;
-        for (int k = 0; k < NSHARD; ++k) recheck += ctx->ctr_h->shard[k].recheck;
+        for (int k = 0; k < NSHARD; ++k) {
+          recheck += ctx->ctr_h->shard[k].recheck;
+          wide_tests += ctx->ctr_h->shard[k].tests;
+        }
       }
       ovf_total += ctx->ctr_h->n_overflow;
       ++sweeps;
@@ -590,13 +654,15 @@ pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, dou
     stats->max_cell = ctx->maxcell;
     stats->home_cells = 1;
     stats->reach = ctx->reach;
+    stats->n_wide = ctx->n_wide;
+    stats->rho_c = ctx->split ? ctx->rho_c : 0.0;
     if (n > 0 && !ctx->small) {
       PCOL_HIP(hipMemsetAsync(ctx->tests_d, 0, sizeof(unsigned long long), s));
       PCOL_HIP(launch_count_pairs(s, ctx->start, ctx->G, ctx->tests_d));
       PCOL_HIP(hipMemcpyAsync(ctx->tests_h, ctx->tests_d, sizeof(unsigned long long),
                               hipMemcpyDeviceToHost, s));
       PCOL_HIP(hipStreamSynchronize(s));
-      stats->pair_tests = (int64_t)*ctx->tests_h;
+      stats->pair_tests = (int64_t)*ctx->tests_h + (int64_t)wide_tests;
     }
     if (timing && n > 0) {
       stats->ms_bin = ms_between(ctx->ev[0], ctx->ev[1]);

@@ -30,14 +30,40 @@ struct alignas(16) OutRec {
 
 // Uniform grid over the periodic box.  Cells are numbered (cz * nc1 + cy) * nc0 + cx,
 // so the cells of one x-row are consecutive and so are their spheres after sorting.
+//
+// With the extent split (see k_cell_hist) the spheres of large extent sit in a
+// second layer of the same cells, numbered layer2 + c; layer2 = 0 means one
+// layer.  rho_max > 0 is the largest extent, which sets the radius of exact
+// searches in a split grid; rho_max = 0 means cell side >= reach, so the 27
+// surrounding cells hold every possible partner.
 struct Grid {
   int nc[3];
-  int ncell;
+  int ncell;        // cells of one layer
   double inv_h[3];  // nc / L, for cell assignment only
   double L[3];
   double halfL[3];  // 0.5 * L, the minimum-image threshold
   double h[3];      // L / nc, cell side
+  int layer2;       // first cell of the second layer (0: none)
+  int pad_;
+  double rho_max;
 };
+
+// Extent of a sphere over a step, r + |v| dt: two spheres can touch within the
+// step only if their separation is at most the sum of their extents.  Written
+// once so every kernel classifies a sphere identically.
+__device__ __forceinline__ double extent(double r, double vx, double vy, double vz, double dt) {
+  return r + __builtin_sqrt((vx * vx + vy * vy) + vz * vz) * dt;
+}
+
+// Range-free histogram of positive doubles: the top 16 bits of the binary64
+// pattern (11 exponent bits, 4 fraction bits) over exponents 2^-64 .. 2^63,
+// 16 bins per octave (bin width at most 1/16 of its lower edge).
+constexpr int RHO_BINS = 2048;
+__device__ __forceinline__ int rho_bin(double v) {
+  const long long b = __double_as_longlong(v) >> 48;  // v > 0: exponent and 4 fraction bits
+  const long long k = b - (long long)((1023 - 64) << 4);
+  return k < 0 ? 0 : (k >= RHO_BINS ? RHO_BINS - 1 : (int)k);
+}
 
 // FP32 copy of a record for the pair filter: position relative to the centre
 // of the sphere's own cell, radius, velocity (32 B).
@@ -51,8 +77,10 @@ struct ReachOut {
   unsigned long long v2max;  // max over spheres of (vx^2 + vy^2) + vz^2
   unsigned long long rmax;
   unsigned long long rmin;   // initialised to the bits of +inf
+  unsigned long long rhomax; // max extent r + |v| dt
   unsigned int bad;          // bit 0: non-finite / r <= 0 / m <= 0; bit 1: position outside [0, L)
   unsigned int maxcell;      // filled by the scan
+  unsigned int hist[RHO_BINS];  // extents by rho_bin
 };
 
 // Per-sweep counters the host reads back.  Sums are spread over NSHARD
@@ -63,7 +91,8 @@ struct alignas(128) CounterShard {
   unsigned long long pairs;     // pairs resolved this sweep
   unsigned long long contacts;  // contacts found (each counted from both spheres)
   unsigned long long recheck;   // FP32 filter survivors rechecked in FP64 (counted per wave)
-  unsigned long long pad[13];
+  unsigned long long tests;     // pair tests of the large-extent search
+  unsigned long long pad[12];
 };
 struct SweepCounters {
   CounterShard shard[NSHARD];
@@ -206,9 +235,11 @@ hipError_t launch_fill_u32(hipStream_t s, unsigned int *p, unsigned int v, int64
 hipError_t launch_fill_u8(hipStream_t s, uint8_t *p, uint8_t v, int64_t n);
 hipError_t launch_fill_f64(hipStream_t s, double *p, double v, int64_t n);
 hipError_t launch_fill_i32(hipStream_t s, int *p, int v, int64_t n);
-hipError_t launch_reach(hipStream_t s, const Particles &P, const double L[3], ReachOut *out);
-hipError_t launch_cell_hist(hipStream_t s, const Particles &P, const Grid &G, int *cid, int *slot,
-                            int *count);
+hipError_t launch_reach(hipStream_t s, const Particles &P, const double L[3], double dt,
+                        ReachOut *out);
+hipError_t launch_cell_hist(hipStream_t s, const Particles &P, const Grid &G, double dt,
+                            double rho_c, int *cid, int *slot, int *count);
+hipError_t launch_detect_wide(hipStream_t s, const DetectArgs &A, int first, int count);
 hipError_t launch_scan(hipStream_t s, const int *count, int ncell, int *start, int *blocksum,
                        ReachOut *out);
 hipError_t launch_scatter(hipStream_t s, const Particles &P, const Grid &G, const int *cid,

@@ -112,12 +112,16 @@ hipError_t launch_fill_f64(hipStream_t s, double *p, double v, int64_t n) {
 
 // ---------------------------------------------------------------- a1: reach + validation
 
-// max (vx^2 + vy^2) + vz^2, max r, and data validity (Sec. "Collision Operator":
-// the halo must cover the distance the fastest sphere travels).  Reads 64 B per
-// sphere, coalesced.
+// Largest |v|^2, radius and extent r + |v| dt, smallest radius, data validity,
+// and the histogram of extents (Sec. "Collision Operator": the halo must hold
+// every partner a sphere can reach within the step).  Grid-stride; each
+// workgroup histograms in LDS and adds its non-empty bins once.
 __global__ __launch_bounds__(256) void k_reach(Particles P, double L0, double L1, double L2,
-                                               ReachOut *out) {
-  double v2 = 0.0, rm = 0.0, rn = INFINITY;
+                                               double dt, ReachOut *out) {
+  __shared__ unsigned int hist[RHO_BINS];
+  for (int k = threadIdx.x; k < RHO_BINS; k += 256) hist[k] = 0u;
+  __syncthreads();
+  double v2 = 0.0, rm = 0.0, rn = INFINITY, em = 0.0;
   unsigned int bad = 0u;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < P.n;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -133,52 +137,67 @@ __global__ __launch_bounds__(256) void k_reach(Particles P, double L0, double L1
       v2 = w > v2 ? w : v2;
       rm = r > rm ? r : rm;
       rn = r < rn ? r : rn;
+      if (r > 0.0) {
+        const double ex = extent(r, vx, vy, vz, dt);
+        em = ex > em ? ex : em;
+        atomicAdd(&hist[rho_bin(ex)], 1u);
+      }
     }
   }
   for (int o = WAVE / 2; o > 0; o >>= 1) {
-    const double a = __shfl_xor(v2, o), b = __shfl_xor(rm, o), c = __shfl_xor(rn, o);
+    const double a = __shfl_xor(v2, o), b = __shfl_xor(rm, o), c = __shfl_xor(rn, o),
+                 d = __shfl_xor(em, o);
     v2 = a > v2 ? a : v2;
     rm = b > rm ? b : rm;
     rn = c < rn ? c : rn;
+    em = d > em ? d : em;
     bad |= __shfl_xor(bad, o);
   }
   if (__lane_id() == 0) {
     atomicMax(&out->v2max, dbits(v2));
     atomicMax(&out->rmax, dbits(rm));
+    atomicMax(&out->rhomax, dbits(em));
     if (rn > 0.0) atomicMin(&out->rmin, dbits(rn));
     if (bad) atomicOr(&out->bad, bad);
   }
+  __syncthreads();
+  for (int k = threadIdx.x; k < RHO_BINS; k += 256)
+    if (hist[k]) atomicAdd(&out->hist[k], hist[k]);
 }
 
-hipError_t launch_reach(hipStream_t s, const Particles &P, const double L[3], ReachOut *out) {
+hipError_t launch_reach(hipStream_t s, const Particles &P, const double L[3], double dt,
+                        ReachOut *out) {
   int64_t g = (P.n + 255) / 256;
-  if (g > 2048) g = 2048;
+  if (g > 1024) g = 1024;
   if (g < 1) g = 1;
-  hipLaunchKernelGGL(k_reach, dim3((int)g), dim3(256), 0, s, P, L[0], L[1], L[2], out);
+  hipLaunchKernelGGL(k_reach, dim3((int)g), dim3(256), 0, s, P, L[0], L[1], L[2], dt, out);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- a2: cell id + histogram
 
-// cell of each sphere and its rank within the cell (the counting-sort slot);
-// Sec. "Collision Operator": particles are sorted by host cell and counted.
-__global__ __launch_bounds__(256) void k_cell_hist(Particles P, Grid G, int *cid, int *slot,
-                                                   int *count) {
+// Cell of each sphere and its rank within the cell (one atomic per sphere).
+// Extent split: a sphere whose extent r + |v| dt exceeds rho_c goes to the
+// second layer of cells (number G.layer2 + c), searched separately; the first
+// layer then only needs cells of side 2 rho_c.  rho_c = +inf: one layer.
+__global__ __launch_bounds__(256) void k_cell_hist(Particles P, Grid G, double dt, double rho_c,
+                                                   int *cid, int *slot, int *count) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= P.n) return;
   const int cx = cell_coord(P.x[i], G.inv_h[0], G.nc[0]);
   const int cy = cell_coord(P.y[i], G.inv_h[1], G.nc[1]);
   const int cz = cell_coord(P.z[i], G.inv_h[2], G.nc[2]);
-  const int c = (cz * G.nc[1] + cy) * G.nc[0] + cx;
+  int c = (cz * G.nc[1] + cy) * G.nc[0] + cx;
+  if (G.layer2 && !(extent(P.r[i], P.vx[i], P.vy[i], P.vz[i], dt) <= rho_c)) c += G.layer2;
   cid[i] = c;
   slot[i] = atomicAdd(&count[c], 1);
 }
 
-hipError_t launch_cell_hist(hipStream_t s, const Particles &P, const Grid &G, int *cid, int *slot,
-                            int *count) {
+hipError_t launch_cell_hist(hipStream_t s, const Particles &P, const Grid &G, double dt,
+                            double rho_c, int *cid, int *slot, int *count) {
   if (P.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cell_hist, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, s, P, G,
-                     cid, slot, count);
+  hipLaunchKernelGGL(k_cell_hist, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, s, P, G, dt,
+                     rho_c, cid, slot, count);
   return hipGetLastError();
 }
 
@@ -307,7 +326,8 @@ __global__ __launch_bounds__(256) void k_scatter(Particles P, Grid G, const int 
   rank[i] = pos;
   if (sbox) sbox[pos] = box_of[i];
   if (rec32) {
-    const int cx = c % G.nc[0], cy = (c / G.nc[0]) % G.nc[1], cz = c / (G.nc[0] * G.nc[1]);
+    const int cl = c >= G.ncell ? c - G.ncell : c;  // cell within its layer
+    const int cx = cl % G.nc[0], cy = (cl / G.nc[0]) % G.nc[1], cz = cl / (G.nc[0] * G.nc[1]);
     Rec32 f;
     f.x = (float)(q.x - (cx + 0.5) * G.h[0]);
     f.y = (float)(q.y - (cy + 0.5) * G.h[1]);
@@ -388,6 +408,54 @@ __device__ __forceinline__ void record_contact(const DetectArgs &A, int i, int g
 }
 
 
+// Filter survivors of one wave awaiting the exact rule: (home i, candidate g)
+// pairs in the wave's LDS queue.  A survivor is rare (about one per home
+// sphere); deciding it at once would run the square root, the division and
+// two atomics for one live lane while the other 63 idle, so survivors are
+// queued and decided 64 at a time at the end of the home cell, where few
+// registers are live.  A survivor that finds the queue full is decided at
+// once.
+constexpr int QCAP = 256;
+
+struct SurvivorQueue {
+  int2 *q;              // QCAP entries in LDS, private to the wave
+  int n;                // entries waiting (wave-uniform)
+  unsigned int pushed;  // survivors seen (wave-uniform)
+};
+
+// The rule for every queued pair (rule 1 with the canonical minimum image,
+// which for every pair that can touch is the image the stencil tested, and
+// for any other pair finds no contact either).
+__device__ __forceinline__ void flush_survivors(const DetectArgs &A, const Grid &G,
+                                                SurvivorQueue &Q) {
+  for (int e0 = 0; e0 < Q.n; e0 += WAVE) {
+    const int e = e0 + (int)__lane_id();
+    if (e < Q.n) {
+      const int2 pr = Q.q[e];
+      const Rec a = A.rec[pr.x], b = A.rec[pr.y];
+      double t;
+      if (pair_time(a, b, G, A.dt, t)) record_contact(A, pr.x, pr.y, t);
+    }
+  }
+  Q.n = 0;
+}
+
+// Queue this lane's survivor (i, g) if `pass`; returns false if the queue had
+// no room for the wave's survivors, which the caller then decides at once.
+__device__ __forceinline__ bool push_survivor(bool pass, int i, int g, SurvivorQueue &Q) {
+  const unsigned long long m = __ballot(pass);
+  if (!m) return true;
+  const int c = __popcll(m);
+  Q.pushed += c;
+  if (Q.n + c > QCAP) return false;
+  if (pass) {
+    const unsigned int lane = __lane_id();
+    Q.q[Q.n + __popcll(m & ((1ull << lane) - 1ull))] = make_int2(i, g);
+  }
+  Q.n += c;
+  return true;
+}
+
 // One home sphere (wave-uniform) against the lane's candidate.
 //
 // Filter: b' = d.u and c' = |d|^2 - s^2 by FMA chains (not the rule's operation
@@ -396,12 +464,13 @@ __device__ __forceinline__ void record_contact(const DetectArgs &A, int i, int g
 // values differ from the rule's b, c by at most 7 eps (|d|^2 + s^2) and
 // 7 eps |d| |u|; tol (set by the host from the reach, the largest radius and
 // speed) bounds those differences for |d| <= reach, so every kept pair passes.
-// Passing pairs are then decided by the rule itself (contact_time), so the
-// result is exactly the rule's.
+// Passing pairs are then decided by the rule itself (queued, or at once), so
+// the result is exactly the rule's.
 template <bool SHIFT, bool MASK>
 __device__ __forceinline__ void pair64(const DetectArgs &A, const Rec &b, int g, int thr, double sx,
                                        double sy, double sz, int i, double xi, double yi,
-                                       double zi, double ri, double vxi, double vyi, double vzi) {
+                                       double zi, double ri, double vxi, double vyi, double vzi,
+                                       SurvivorQueue &Q) {
   double d0 = b.x - xi, d1 = b.y - yi, d2 = b.z - zi;
   if (SHIFT) {
     d0 = d0 + sx;
@@ -414,7 +483,8 @@ __device__ __forceinline__ void pair64(const DetectArgs &A, const Rec &b, int g,
   const double bf = __builtin_fma(d0, u0, __builtin_fma(d1, u1, d2 * u2));
   const double cf = __builtin_fma(d0, d0, __builtin_fma(d1, d1, __builtin_fma(d2, d2, -ss)));
   // in own-cell chunks only j > i is a candidate (thr = j there, INT_MAX elsewhere)
-  if ((!MASK || i < thr) && __builtin_fma(bf, A.dt2, cf) <= A.tol) {
+  const bool pass = (!MASK || i < thr) && __builtin_fma(bf, A.dt2, cf) <= A.tol;
+  if (!push_survivor(pass, i, g, Q) && pass) {
     double t;
     if (contact_time(d0, d1, d2, u0, u1, u2, s, A.dt, t)) record_contact(A, i, g, t);
   }
@@ -428,7 +498,8 @@ __device__ __forceinline__ void pair64(const DetectArgs &A, const Rec &b, int g,
 // rate).
 template <bool SHIFT, bool MASK, typename HP>
 __device__ __forceinline__ void detect_chunk(const DetectArgs &A, HP p, int h0, int h1, int g,
-                                             int thr, double sx, double sy, double sz) {
+                                             int thr, double sx, double sy, double sz,
+                                             SurvivorQueue &Q) {
   Rec b;
   if (thr >= 0) {
     b = A.rec[g];
@@ -441,31 +512,33 @@ __device__ __forceinline__ void detect_chunk(const DetectArgs &A, HP p, int h0, 
   int i = h0;
   for (; i + 1 < h1; i += 2, p += 2) {
     pair64<SHIFT, MASK>(A, b, g, thr, sx, sy, sz, i, p[0].x, p[0].y, p[0].z, p[0].r, p[0].vx,
-                        p[0].vy, p[0].vz);
+                        p[0].vy, p[0].vz, Q);
     pair64<SHIFT, MASK>(A, b, g, thr, sx, sy, sz, i + 1, p[1].x, p[1].y, p[1].z, p[1].r, p[1].vx,
-                        p[1].vy, p[1].vz);
+                        p[1].vy, p[1].vz, Q);
   }
   if (i < h1)
     pair64<SHIFT, MASK>(A, b, g, thr, sx, sy, sz, i, p[0].x, p[0].y, p[0].z, p[0].r, p[0].vx,
-                        p[0].vy, p[0].vz);
+                        p[0].vy, p[0].vz, Q);
 }
 
-// One home sphere (FP32 record in scalar registers) against the lane's candidate.
+// One home sphere (FP32 record in scalar registers) against the lane's
+// candidate: the same filter in binary32 with the contact distance inflated by
+// the band; survivors are decided by the binary64 rule (queued, or at once
+// from the full records).
 template <bool SHIFT, bool MASK>
 __device__ __forceinline__ void pair32(const DetectArgs &A, const Grid &G, int g, int thr, int code,
-                                       float bx,
-                                       float by, float bz, float br, float bvx, float bvy,
-                                       float bvz, int i, float ax, float ay, float az, float ar,
-                                       float avx, float avy, float avz, unsigned int *nrecheck) {
+                                       float bx, float by, float bz, float br, float bvx,
+                                       float bvy, float bvz, int i, float ax, float ay, float az,
+                                       float ar, float avx, float avy, float avz,
+                                       SurvivorQueue &Q) {
   const float d0 = bx - ax, d1 = by - ay, d2 = bz - az;
   const float u0 = bvx - avx, u1 = bvy - avy, u2 = bvz - avz;
   const float sb = (ar + br) * A.kband;
   const float bb = __builtin_fmaf(d0, u0, __builtin_fmaf(d1, u1, d2 * u2));
   const float q = __builtin_fmaf(d0, d0, __builtin_fmaf(d1, d1, d2 * d2));
   const float cc = __builtin_fmaf(-sb, sb, q);
-  if ((!MASK || i < thr) && __builtin_fmaf(bb, A.dt2f, cc) <= 0.0f) {
-    ++*nrecheck;
-    // binary64 rule for the survivor, from the full records
+  const bool pass = (!MASK || i < thr) && __builtin_fmaf(bb, A.dt2f, cc) <= 0.0f;
+  if (!push_survivor(pass, i, g, Q) && pass) {
     const crec_ptr hrec = (crec_ptr)A.rec;
     const Rec b = A.rec[g];
     const double xi = hrec[i].x, yi = hrec[i].y, zi = hrec[i].z, ri = hrec[i].r;
@@ -485,7 +558,7 @@ __device__ __forceinline__ void pair32(const DetectArgs &A, const Grid &G, int g
 template <bool SHIFT, bool MASK, typename HP>
 __device__ __forceinline__ void detect_chunk32(const DetectArgs &A, const Grid &G, HP p, int h0,
                                                int h1, int g, int thr, int code, double ox,
-                                               double oy, double oz, unsigned int *nrecheck) {
+                                               double oy, double oz, SurvivorQueue &Q) {
   float bx, by, bz, bvx, bvy, bvz, br;
   if (thr >= 0) {
     const Rec b = A.rec[g];
@@ -504,14 +577,14 @@ __device__ __forceinline__ void detect_chunk32(const DetectArgs &A, const Grid &
   }
   int i = h0;
   for (; i + 1 < h1; i += 2, p += 2) {
-    pair32<SHIFT, MASK>(A, G, g, thr, code, bx, by, bz, br, bvx, bvy, bvz, i, p[0].x, p[0].y, p[0].z,
-                        p[0].r, p[0].vx, p[0].vy, p[0].vz, nrecheck);
+    pair32<SHIFT, MASK>(A, G, g, thr, code, bx, by, bz, br, bvx, bvy, bvz, i, p[0].x, p[0].y,
+                        p[0].z, p[0].r, p[0].vx, p[0].vy, p[0].vz, Q);
     pair32<SHIFT, MASK>(A, G, g, thr, code, bx, by, bz, br, bvx, bvy, bvz, i + 1, p[1].x, p[1].y,
-                        p[1].z, p[1].r, p[1].vx, p[1].vy, p[1].vz, nrecheck);
+                        p[1].z, p[1].r, p[1].vx, p[1].vy, p[1].vz, Q);
   }
   if (i < h1)
-    pair32<SHIFT, MASK>(A, G, g, thr, code, bx, by, bz, br, bvx, bvy, bvz, i, p[0].x, p[0].y, p[0].z,
-                        p[0].r, p[0].vx, p[0].vy, p[0].vz, nrecheck);
+    pair32<SHIFT, MASK>(A, G, g, thr, code, bx, by, bz, br, bvx, bvy, bvz, i, p[0].x, p[0].y,
+                        p[0].z, p[0].r, p[0].vx, p[0].vy, p[0].vz, Q);
 }
 
 // Pair tests of one home cell (see k_detect_half).  `start` points at the first
@@ -520,7 +593,7 @@ __device__ __forceinline__ void detect_chunk32(const DetectArgs &A, const Grid &
 // home cell and the workgroup is this single wave.
 template <bool FP32, bool LDSI>
 __device__ __forceinline__ void detect_cell(const DetectArgs &A, const Grid &G, const int *start,
-                                            int cell, unsigned int &nrc, double4 *lds_raw) {
+                                            int cell, SurvivorQueue &Q, double4 *lds_raw) {
   const int nc0 = G.nc[0], nc1 = G.nc[1], nc2 = G.nc[2];
   const int cx = cell % nc0, cy = (cell / nc0) % nc1, cz = cell / (nc0 * nc1);
   const int h0 = start[cell], h1 = start[cell + 1];
@@ -630,27 +703,27 @@ __device__ __forceinline__ void detect_cell(const DetectArgs &A, const Grid &G, 
         const Rec32 *p = (const Rec32 *)lds_raw;
         if (base < rl[0]) {
           if (any_shift)
-            detect_chunk32<true, true>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
+            detect_chunk32<true, true>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, Q);
           else
-            detect_chunk32<false, true>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
+            detect_chunk32<false, true>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, Q);
         } else {
           if (any_shift)
-            detect_chunk32<true, false>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
+            detect_chunk32<true, false>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, Q);
           else
-            detect_chunk32<false, false>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
+            detect_chunk32<false, false>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, Q);
         }
       } else {
         const crec32_ptr p = (crec32_ptr)A.rec32 + h0;
         if (base < rl[0]) {
           if (any_shift)
-            detect_chunk32<true, true>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
+            detect_chunk32<true, true>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, Q);
           else
-            detect_chunk32<false, true>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
+            detect_chunk32<false, true>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, Q);
         } else {
           if (any_shift)
-            detect_chunk32<true, false>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
+            detect_chunk32<true, false>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, Q);
           else
-            detect_chunk32<false, false>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, &nrc);
+            detect_chunk32<false, false>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, Q);
         }
       }
       continue;
@@ -659,41 +732,41 @@ __device__ __forceinline__ void detect_cell(const DetectArgs &A, const Grid &G, 
       const Rec *p = (const Rec *)lds_raw;
       if (base < rl[0]) {  // chunk holds own-cell candidates
         if (any_shift)
-          detect_chunk<true, true>(A, p, h0, h1, g, thr, sx, sy, sz);
+          detect_chunk<true, true>(A, p, h0, h1, g, thr, sx, sy, sz, Q);
         else
-          detect_chunk<false, true>(A, p, h0, h1, g, thr, 0.0, 0.0, 0.0);
+          detect_chunk<false, true>(A, p, h0, h1, g, thr, 0.0, 0.0, 0.0, Q);
       } else {
         if (any_shift)
-          detect_chunk<true, false>(A, p, h0, h1, g, thr, sx, sy, sz);
+          detect_chunk<true, false>(A, p, h0, h1, g, thr, sx, sy, sz, Q);
         else
-          detect_chunk<false, false>(A, p, h0, h1, g, thr, 0.0, 0.0, 0.0);
+          detect_chunk<false, false>(A, p, h0, h1, g, thr, 0.0, 0.0, 0.0, Q);
       }
     } else {
       const crec_ptr p = (crec_ptr)A.rec + h0;
       if (base < rl[0]) {
         if (any_shift)
-          detect_chunk<true, true>(A, p, h0, h1, g, thr, sx, sy, sz);
+          detect_chunk<true, true>(A, p, h0, h1, g, thr, sx, sy, sz, Q);
         else
-          detect_chunk<false, true>(A, p, h0, h1, g, thr, 0.0, 0.0, 0.0);
+          detect_chunk<false, true>(A, p, h0, h1, g, thr, 0.0, 0.0, 0.0, Q);
       } else {
         if (any_shift)
-          detect_chunk<true, false>(A, p, h0, h1, g, thr, sx, sy, sz);
+          detect_chunk<true, false>(A, p, h0, h1, g, thr, sx, sy, sz, Q);
         else
-          detect_chunk<false, false>(A, p, h0, h1, g, thr, 0.0, 0.0, 0.0);
+          detect_chunk<false, false>(A, p, h0, h1, g, thr, 0.0, 0.0, 0.0, Q);
       }
     }
   }
+  flush_survivors(A, G, Q);
 }
 
 template <bool FP32, bool LDSI>
 __global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
   extern __shared__ double4 lds_raw[];  // LDSI: the home cell's records (Rec or Rec32)
-  unsigned int nrc = 0u;
-  detect_cell<FP32, LDSI>(A, A.G, A.start, xcd_remap(blockIdx.x, gridDim.x), nrc, lds_raw);
-  if (FP32) {
-    const unsigned long long tot = wave_sum((unsigned long long)nrc);
-    if (__lane_id() == 0 && tot) atomicAdd(&A.ctr->shard[blockIdx.x % NSHARD].recheck, tot);
-  }
+  __shared__ int2 survq[QCAP];
+  SurvivorQueue Q{survq, 0, 0u};
+  detect_cell<FP32, LDSI>(A, A.G, A.start, xcd_remap(blockIdx.x, gridDim.x), Q, lds_raw);
+  if (FP32 && __lane_id() == 0 && Q.pushed)
+    atomicAdd(&A.ctr->shard[blockIdx.x % NSHARD].recheck, (unsigned long long)Q.pushed);
 }
 
 // Box of a global cell number: the last b with cell_base[b] <= c.
@@ -716,16 +789,17 @@ __device__ __forceinline__ int box_of_cell(const int *cell_base, int nbox, int c
 // hold several independent waves).
 __global__ __launch_bounds__(256) void k_detect_batched(DetectArgs A, BatchDev B) {
   if (B.flags[FLAG_ERR]) return;
+  __shared__ int2 survq[4][QCAP];
   const int wpb = blockDim.x / WAVE;
   const int wave = threadIdx.x / WAVE;
   const int total = B.cell_base[B.nbox];
   const int stride = gridDim.x * wpb;
-  unsigned int nrc = 0u;
+  SurvivorQueue Q{survq[wave], 0, 0u};
   for (int item = blockIdx.x * wpb + wave; item < total; item += stride) {
     const int b = box_of_cell(B.cell_base, B.nbox, item);
     const Grid G = B.gtab[b];
     const int base = B.cell_base[b];
-    detect_cell<false, false>(A, G, A.start + base, item - base, nrc, nullptr);
+    detect_cell<false, false>(A, G, A.start + base, item - base, Q, nullptr);
   }
 }
 
@@ -843,15 +917,175 @@ hipError_t launch_slot_min(hipStream_t s, int n, int first, const int *cnt, cons
 
 // ---------------------------------------------------------------- exact neighbourhood search
 
-// Earliest partner (rule 2) by an exact search of the 27 surrounding cells
-// (distinct cells only when an axis has fewer than 3), minimum image by rule
-// 1.  One wave per sphere; lanes over candidates; the wave reduces
-// (t, caller index) exactly.  Spheres come from `list` (length nlist, or
-// *nlist_dev when given) or, with list NULL, are all i < nlist whose status is
-// `select` (select < 0: all); selected DIRTY spheres become ACTIVE.  Collided
-// spheres are never candidates.  Used for spheres whose contacts overflowed
-// the slots, for pcol_detect with an active mask, and for grids with fewer
-// than 3 cells along some axis.
+// Search box of a sphere in cell (cx, cy, cz): kx..kz cells either side along
+// each axis, or the whole axis once when 2k + 1 covers it.  Calls
+// run(first, end) for each run of consecutive sorted records (a row of cells
+// along x, split in two where it wraps) of the layer whose first cell is
+// `base`.  Every cell of the box is visited exactly once.
+template <typename F>
+__device__ __forceinline__ void search_box_runs(const Grid &G, const int *start, int base, int cx,
+                                                int cy, int cz, const int k[3], F run) {
+  const int nc0 = G.nc[0], nc1 = G.nc[1], nc2 = G.nc[2];
+  const bool fx = 2 * k[0] + 1 >= nc0, fy = 2 * k[1] + 1 >= nc1, fz = 2 * k[2] + 1 >= nc2;
+  const int ny = fy ? nc1 : 2 * k[1] + 1, nz = fz ? nc2 : 2 * k[2] + 1;
+  for (int iz = 0; iz < nz; ++iz) {
+    const int z = fz ? iz : (cz - k[2] + iz + nc2) % nc2;
+    for (int iy = 0; iy < ny; ++iy) {
+      const int y = fy ? iy : (cy - k[1] + iy + nc1) % nc1;
+      const int row = base + (z * nc1 + y) * nc0;
+      if (fx) {
+        run(start[row], start[row + nc0]);
+      } else {
+        const int x0 = cx - k[0], x1 = cx + k[0];
+        if (x0 < 0) {
+          run(start[row + x0 + nc0], start[row + nc0]);
+          run(start[row], start[row + x1 + 1]);
+        } else if (x1 >= nc0) {
+          run(start[row + x0], start[row + nc0]);
+          run(start[row], start[row + x1 - nc0 + 1]);
+        } else {
+          run(start[row + x0], start[row + x1 + 1]);
+        }
+      }
+    }
+  }
+}
+
+// Cells either side of sphere a that can hold a partner: 1 when the cell side
+// is at least the reach (one layer), else enough to cover the sphere's extent
+// plus the largest extent (split grid).
+__device__ __forceinline__ void search_radius(const Grid &G, const Rec &a, double dt, int k[3]) {
+  if (G.rho_max > 0.0) {
+    const double R = (extent(a.r, a.vx, a.vy, a.vz, dt) + G.rho_max) * (1.0 + 1e-9);
+    for (int ax = 0; ax < 3; ++ax) k[ax] = (int)ceil(R / G.h[ax]);
+  } else {
+    k[0] = k[1] = k[2] = 1;
+  }
+}
+
+// Run r of a search box (see search_box_runs), numbered
+// ((layer * nz + iz) * ny + iy) * 2 + part, as [first, end) of sorted records;
+// empty for parts a row does not have.
+__device__ __forceinline__ void search_box_run(const Grid &G, const int *start, int r, int ny,
+                                               int nz, int cx, int cy, int cz, const int k[3],
+                                               int &first, int &end) {
+  const int nc0 = G.nc[0], nc1 = G.nc[1], nc2 = G.nc[2];
+  const int part = r & 1;
+  int q = r >> 1;
+  const int iy = q % ny;
+  q /= ny;
+  const int iz = q % nz;
+  const int layer = q / nz;
+  const bool fx = 2 * k[0] + 1 >= nc0, fy = 2 * k[1] + 1 >= nc1, fz = 2 * k[2] + 1 >= nc2;
+  const int z = fz ? iz : (cz - k[2] + iz + nc2) % nc2;
+  const int y = fy ? iy : (cy - k[1] + iy + nc1) % nc1;
+  const int row = (layer ? G.layer2 : 0) + (z * nc1 + y) * nc0;
+  int xa = 0, xb = 0;  // cells [xa, xb) of the row
+  if (fx) {
+    if (!part) xb = nc0;
+  } else {
+    const int x0 = cx - k[0], x1 = cx + k[0];
+    if (x0 < 0) {
+      xa = part ? 0 : x0 + nc0;
+      xb = part ? x1 + 1 : nc0;
+    } else if (x1 >= nc0) {
+      xa = part ? 0 : x0;
+      xb = part ? x1 - nc0 + 1 : nc0;
+    } else if (!part) {
+      xa = x0;
+      xb = x1 + 1;
+    }
+  }
+  if (xb > xa) {
+    first = start[row + xa];
+    end = start[row + xb];
+  } else {
+    first = end = 0;
+  }
+}
+
+// a5 for the spheres of large extent (second layer of a split grid): one wave
+// per sphere p tests every sphere of its search box exactly (rule 1 with the
+// canonical minimum image): all of the first layer, and in the second layer
+// only spheres after p, so each pair of large-extent spheres is tested once.
+// Pairs of two first-layer spheres belong to k_detect_half.  Contacts go to
+// both spheres' slots as there.  The lanes first fetch up to 64 runs of the
+// box at once and scan their lengths; then each lane takes every 64th
+// candidate of the concatenated runs, finding its run by a binary search over
+// the scanned lengths held across the wave.
+__global__ __launch_bounds__(256) void k_detect_wide(DetectArgs A, int first, int count) {
+  const int lane = __lane_id();
+  const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int nw = (gridDim.x * blockDim.x) / WAVE;
+  const Grid &G = A.G;
+  unsigned long long tests = 0ull;
+  for (int w = wid; w < count; w += nw) {
+    const int p = first + w;
+    const Rec a = A.rec[p];
+    int k[3];
+    search_radius(G, a, A.dt, k);
+    const int cx = cell_coord(a.x, G.inv_h[0], G.nc[0]);
+    const int cy = cell_coord(a.y, G.inv_h[1], G.nc[1]);
+    const int cz = cell_coord(a.z, G.inv_h[2], G.nc[2]);
+    const int ny = 2 * k[1] + 1 >= G.nc[1] ? G.nc[1] : 2 * k[1] + 1;
+    const int nz = 2 * k[2] + 1 >= G.nc[2] ? G.nc[2] : 2 * k[2] + 1;
+    const int nruns = 2 * 2 * ny * nz;
+    for (int rb = 0; rb < nruns; rb += WAVE) {
+      int s0 = 0, s1 = 0;
+      if (rb + lane < nruns) {
+        search_box_run(G, A.start, rb + lane, ny, nz, cx, cy, cz, k, s0, s1);
+        if ((((rb + lane) >> 1) / (ny * nz)) == 1) {  // second layer: only j after p
+          s0 = s0 > p + 1 ? s0 : p + 1;
+          s1 = s1 > s0 ? s1 : s0;
+        }
+      }
+      const int len = s1 - s0;
+      int incl = len;
+      for (int o = 1; o < WAVE; o <<= 1) {
+        const int t = __shfl_up(incl, o);
+        if (lane >= o) incl += t;
+      }
+      const int excl = incl - len;
+      const int total = __shfl(incl, WAVE - 1);
+      for (int base = 0; base < total; base += WAVE) {
+        const int v = base + lane;
+        // largest lane l with excl[l] <= v: the run holding candidate v
+        int l = 0;
+        for (int step = WAVE / 2; step > 0; step >>= 1) {
+          const int c = l + step;
+          const int ec = __shfl(excl, c);
+          if (ec <= v) l = c;
+        }
+        const int j = __shfl(s0, l) + (v - __shfl(excl, l));
+        if (v < total) {
+          double t;
+          ++tests;
+          if (pair_time(a, A.rec[j], G, A.dt, t)) record_contact(A, p, j, t);
+        }
+      }
+    }
+  }
+  block_add(tests, &my_shard(A.ctr).tests);
+}
+
+hipError_t launch_detect_wide(hipStream_t s, const DetectArgs &A, int first, int count) {
+  if (count <= 0) return hipSuccess;
+  const int64_t waves = count < (1 << 20) ? count : (1 << 20);
+  hipLaunchKernelGGL(k_detect_wide, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, A, first,
+                     count);
+  return hipGetLastError();
+}
+
+// Earliest partner (rule 2: exact binary64 t, ties to the smaller caller index)
+// by an exact search of the sphere's search box (the 27 surrounding cells, or
+// the wider box of a split grid, in both layers), minimum image by rule 1.
+// One wave per sphere; lanes over candidates; the wave reduces (t, caller
+// index) exactly.  Spheres come from `list` (length nlist, or *nlist_dev when
+// given) or, with list NULL, are all i < nlist whose status is `select`
+// (select < 0: all); selected DIRTY spheres become ACTIVE.  Collided spheres
+// are never candidates.  Used for spheres whose contacts overflowed the slots,
+// for pcol_detect with an active mask, and for grids with fewer than 3 cells
+// along some axis.
 __global__ __launch_bounds__(256) void k_gather_exact(const int *list, int nlist,
                                                       const unsigned int *nlist_dev, int select,
                                                       const Rec *rec, const int *start, Grid G0,
@@ -870,40 +1104,32 @@ __global__ __launch_bounds__(256) void k_gather_exact(const int *list, int nlist
     const int bx = B.gtab ? B.sbox[i] : 0;
     const Grid G = B.gtab ? B.gtab[bx] : G0;
     const int *st = B.gtab ? start + B.cell_base[bx] : start;
-    int nb[3], lo[3];
-    for (int a = 0; a < 3; ++a) {
-      nb[a] = G.nc[a] >= 3 ? 3 : G.nc[a];
-      lo[a] = G.nc[a] >= 3 ? -1 : 0;
-    }
     const Rec a = rec[i];
+    int k[3];
+    search_radius(G, a, dt, k);
     const int cx = cell_coord(a.x, G.inv_h[0], G.nc[0]);
     const int cy = cell_coord(a.y, G.inv_h[1], G.nc[1]);
     const int cz = cell_coord(a.z, G.inv_h[2], G.nc[2]);
     double bt = INFINITY;
     int bo = 0x7fffffff, bj = -1;
-    for (int kz = 0; kz < nb[2]; ++kz)
-      for (int ky = 0; ky < nb[1]; ++ky)
-        for (int kx = 0; kx < nb[0]; ++kx) {
-          const int x = (cx + lo[0] + kx + G.nc[0]) % G.nc[0];
-          const int y = (cy + lo[1] + ky + G.nc[1]) % G.nc[1];
-          const int z = (cz + lo[2] + kz + G.nc[2]) % G.nc[2];
-          const int q = (z * G.nc[1] + y) * G.nc[0] + x;
-          const int s0 = st[q], s1 = st[q + 1];
-          for (int j = s0 + lane; j < s1; j += WAVE) {
-            if (j == i) continue;
-            if (status[j] == ST_COLLIDED) continue;
-            const Rec b = rec[j];
-            double t;
-            if (pair_time(a, b, G, dt, t)) {
-              const int o = perm[j];
-              if (t < bt || (t == bt && o < bo)) {
-                bt = t;
-                bo = o;
-                bj = j;
-              }
+    for (int layer = 0; layer < (G.layer2 ? 2 : 1); ++layer) {
+      search_box_runs(G, st, layer ? G.layer2 : 0, cx, cy, cz, k, [&](int s0, int s1) {
+        for (int j = s0 + lane; j < s1; j += WAVE) {
+          if (j == i) continue;
+          if (status[j] == ST_COLLIDED) continue;
+          const Rec b = rec[j];
+          double t;
+          if (pair_time(a, b, G, dt, t)) {
+            const int o = perm[j];
+            if (t < bt || (t == bt && o < bo)) {
+              bt = t;
+              bo = o;
+              bj = j;
             }
           }
         }
+      });
+    }
     for (int o = WAVE / 2; o > 0; o >>= 1) {
       const double t2 = __shfl_xor(bt, o);
       const int o2 = __shfl_xor(bo, o);
@@ -1407,6 +1633,7 @@ hipError_t launch_cell_hist_b(hipStream_t s, const Particles &P, const BatchDev 
 
 hipError_t launch_detect_batched(hipStream_t s, const DetectArgs &A, const BatchDev &B,
                                  int blocks, int waves_per_block) {
+  if (waves_per_block < 1 || waves_per_block > 4) return hipErrorInvalidValue;  // queue slices
   hipLaunchKernelGGL(k_detect_batched, dim3(blocks), dim3(WAVE * waves_per_block), 0, s, A, B);
   return hipGetLastError();
 }
