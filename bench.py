@@ -12,7 +12,9 @@ region) before each step, so each step processes the same batch.
 Prints one JSON line: particles stepped per second (value), pair tests per
 second of the detect kernel, the detect kernel's ALU roofline fraction, and the
 CPU oracle timed on a bounded sample of the same workload.  Beside the plain
-FP64 path it reports the FP32 filter form on the same input, the batched form
+FP64 path it reports the binary32 filter form and the fp16 Gram filter form on
+the matrix cores on the same input (both decide survivors by the binary64
+rule, so all three compute the same step bitwise), the batched form
 (512 uneven boxes, about 8M spheres, one captured graph per step, against a
 loop of single-box steps) and the adjoint form (10-step rollout of 1M spheres,
 forward and backward).
@@ -242,8 +244,9 @@ def main():
     ap.add_argument("--n", type=int, default=0, help="override N (default 16M)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
-    ap.add_argument("--form", choices=["both", "fp64", "fp32"], default="both",
-                    help="plain FP64 path, FP32 filter + FP64 recheck, or both (value = fp64)")
+    ap.add_argument("--form", choices=["all", "fp64", "fp32", "gram"], default="all",
+                    help="filter form(s) to time: binary64, binary32 or the Gram filter on the "
+                         "matrix cores (value = fp64 when it runs)")
     ap.add_argument("--split-quantile", type=float, default=None,
                     help="extent split quantile of the single-box path (default: the library's)")
     ap.add_argument("--cell-mult", type=float, default=None,
@@ -264,15 +267,15 @@ def main():
     log(f"workload {box.n} spheres, L={box.L[0]:.3f}, generated in {time.perf_counter() - t0:.1f} s")
     p0 = pc.Particles.from_box(box)
 
-    def run_form(fp32: int):
-        """K timed steps of one form, each from the configured input."""
+    def run_form(name: str, flt: int, split):
+        """K timed steps of one filter form, each from the configured input."""
         p = p0.clone()
         kw = {}
-        if args.split_quantile is not None:
-            kw["split_quantile"] = args.split_quantile
+        if split is not None:
+            kw["split_quantile"] = split
         if args.cell_mult is not None:
             kw["cell_mult"] = args.cell_mult
-        ctx = pc.Context(box.n, pc.pcol_default_opts(timing=1, fp32_filter=fp32, **kw))
+        ctx = pc.Context(box.n, pc.pcol_default_opts(timing=1, filter=flt, **kw))
         partner = torch.empty(box.n, dtype=torch.int32, device="cuda")
         tcoll = torch.empty(box.n, dtype=torch.float64, device="cuda")
 
@@ -280,7 +283,6 @@ def main():
             for t, t_0 in zip(p.tensors()[:6], p0.tensors()[:6]):
                 t.copy_(t_0)
 
-        name = "fp32+recheck" if fp32 else "fp64"
         for k in range(args.warmup):
             restore()
             st = pc.pcol_step(ctx, p, box.L, box.dt, box.e, partner, tcoll)
@@ -303,12 +305,14 @@ def main():
         ctx.close()
         return out
 
-    forms = {}
-    if args.form in ("both", "fp64"):
-        forms["fp64"] = run_form(0)
-    if args.form in ("both", "fp32"):
-        forms["fp32"] = run_form(1)
-    main_form = "fp64" if "fp64" in forms else "fp32"
+    # filter 0: binary64 FMA filter (the plain FP64 path); 1: binary32 filter;
+    # 2: fp16 Gram filter on the matrix cores.  Survivors of 1 and 2 go to the
+    # binary64 rule, so every form computes the same step bitwise.
+    specs = {"fp64": (0, args.split_quantile), "fp32": (1, args.split_quantile),
+             "gram": (2, 0.0 if args.split_quantile is None else args.split_quantile)}
+    wanted = list(specs) if args.form == "all" else [args.form]
+    forms = {k: run_form(k, *specs[k]) for k in wanted}
+    main_form = "fp64" if "fp64" in forms else wanted[0]
     R = forms[main_form]
     stats, wall = R["stats"], R["wall"]
     ms_step = wall * 1e3 / args.steps
@@ -317,6 +321,8 @@ def main():
     det_total = sum(det_ms) * 1e-3
     achieved = tests * OPS_PER_PAIR_TEST / det_total
     flops = tests * FLOPS_PER_PAIR_TEST / det_total
+    form_names = {"fp64": "plain_fp64 (binary64 FMA filter)", "fp32": "binary32 filter + binary64 rule",
+                  "gram": "fp16 Gram filter on matrix cores + binary64 rule"}
     out = {
         "metric": METRIC,
         "value": box.n * args.steps / wall,
@@ -328,11 +334,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if main_form == "fp64" else "f32+f64",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{box.name}: {box.n} polydisperse spheres, phi 0.3, e {box.e}, "
                                f"dt {box.dt}, periodic cube L={box.L[0]:.4f}",
-                   "n": box.n, "form": "plain_fp64" if main_form == "fp64" else "fp32_filter+fp64_recheck"},
+                   "n": box.n, "form": form_names[main_form],
+                   "split_quantile": (specs[main_form][1] if specs[main_form][1] is not None
+                                      else pc.pcol_default_opts().split_quantile)},
         "pair_tests_per_s": tests / det_total,
         "detect_ms_median": statistics.median(det_ms),
         "pairs_per_step": statistics.mean(st["n_pairs"] for st in stats),
@@ -341,31 +349,52 @@ def main():
                      "unit": "TOP/s", "frac": achieved / PEAK_FP64_OPS,
                      "traffic": measured_traffic() if main_form == "fp64" else None,
                      "traffic_unit": "bytes per launch",
-                     "kernel": "k_detect_half",
+                     "kernel": "k_detect_half" if main_form != "gram" else "k_detect_gram",
                      "note": f"FP64 vector operations (an FMA counts one): {OPS_PER_PAIR_TEST} per "
                              f"unordered pair test; as flops ({FLOPS_PER_PAIR_TEST} per test) "
                              f"{flops / 1e12:.2f} of 78.6 TFLOP/s"},
     }
-    if "fp64" in forms and "fp32" in forms:
-        A, B = forms["fp64"], forms["fp32"]
+    for name in forms:
+        if name == main_form:
+            continue
+        A, B = R, forms[name]
         mismatch = int((A["partner"] != B["partner"]).sum().item())
+        state_equal = all(torch.equal(getattr(A["p"], f).view(torch.int64),
+                                      getattr(B["p"], f).view(torch.int64))
+                          for f in ("x", "y", "z", "vx", "vy", "vz"))
         errs = []
         for f in ("vx", "vy", "vz"):
             a, b = getattr(A["p"], f), getattr(B["p"], f)
             errs.append(((a - b).abs() / a.abs().clamp_min(1e-300)).max().item())
         sb = B["stats"]
-        dm32 = [st["ms_detect"] for st in sb]
-        out["fp32_form"] = {
+        dmb = [st["ms_detect"] for st in sb]
+        tb = sum(st["pair_tests"] for st in sb)
+        sub = {
+            "form": form_names[name],
             "value": box.n * args.steps / B["wall"], "unit": "particles/s",
             "ms_per_step": B["wall"] * 1e3 / args.steps,
-            "speedup_vs_fp64": A["wall"] / B["wall"],
-            "detect_ms_median": statistics.median(dm32),
-            "detect_speedup_vs_fp64": statistics.median(det_ms) / statistics.median(dm32),
+            "speedup_vs_" + main_form: A["wall"] / B["wall"],
+            "detect_ms_median": statistics.median(dmb),
+            "detect_speedup_vs_" + main_form: statistics.median(det_ms) / statistics.median(dmb),
+            "pair_tests_per_step": tb / args.steps,
+            "pair_tests_per_s": tb / (sum(dmb) * 1e-3),
             "pair_set_mismatch": mismatch,
+            "state_bitwise_equal": state_equal,
             "max_rel_velocity_error": max(errs),
-            "band": sb[0]["band"],
             "rechecks_per_step": statistics.mean(st["n_recheck"] for st in sb),
+            "split_quantile": (specs[name][1] if specs[name][1] is not None
+                               else pc.pcol_default_opts().split_quantile),
         }
+        if name == "fp32":
+            sub["band"] = sb[0]["band"]
+        if name == "gram":
+            # the 23-term dot product per pair (21 split products, alpha, beta) on the
+            # matrix cores against their dense fp16 peak
+            mf = tb * 2 * 23 / (sum(dmb) * 1e-3)
+            sub["roofline"] = {"bound": "mfma", "achieved": mf / 1e12, "peak": 2500.0,
+                               "unit": "TFLOP/s", "frac": mf / 2.5e15, "kernel": "k_detect_gram",
+                               "note": "46 fp16 flops per pair test (algorithmic)"}
+        out[name + "_form"] = sub
     if not args.no_batched:
         out["batched_form"] = batched_leg(args, pc, torch)
     if not args.no_adjoint:

@@ -103,12 +103,15 @@ typedef struct {
   int home_cells;     /* home cells per workgroup along x in the sweep-1 detect; 0 = auto */
   int contact_slots;  /* contacts kept per sphere from the sweep-1 detect; spheres with more
                          fall back to an exact neighbourhood search (default 12) */
-  int fp32_filter;    /* 1: FP32 pair filter with FP64 recheck (same results) */
+  int filter;         /* pair filter ahead of the exact rule (same results for every value):
+                         0 binary64 FMA filter; 1 binary32 filter, contact distance inflated by
+                         a band; 2 Gram filter on the matrix cores (fp16 high and low parts,
+                         fp32 accumulation).  Survivors of 1 and 2 are decided in binary64. */
   double band_rel;    /* FP32 filter safety band, relative to r_i + r_j (default 1e-4) */
   int timing;         /* 1: time kernels with HIP events; times land in pcol_stats */
   int autotune;       /* pcol_step_batched: 1 = pick cell size and workgroup shape by timing
                          candidates on the first call (cached, see pcol_step_batched) */
-  double split_quantile; /* extent split (default 0.99; 0 or 1 = off): the spheres whose extent
+  double split_quantile; /* extent split (default 0.999; 0 or 1 = off): the spheres whose extent
                          r + |v| dt lies above this quantile are searched separately, so the
                          grid's cells need only twice the quantile extent instead of the reach.
                          Used when that shrinks the cells by 15% or more.  Results do not
@@ -122,7 +125,7 @@ typedef struct {
                             plus the separate search of the spheres above the split extent) */
   int64_t contacts;      /* unordered pairs with a contact within dt (sweep 1) */
   int64_t n_overflow;    /* spheres whose contacts exceeded contact_slots */
-  int64_t n_recheck;     /* FP32 filter survivors rechecked in FP64 (fp32_filter only) */
+  int64_t n_recheck;     /* survivors of filter 1 or 2 decided by the binary64 rule */
   int32_t nc[3];         /* grid cells per axis */
   int32_t home_cells;    /* home cells per workgroup used */
   int32_t max_cell;      /* largest cell occupancy */

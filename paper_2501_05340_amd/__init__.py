@@ -40,7 +40,7 @@ class pcol_box(ctypes.Structure):
 class pcol_opts(ctypes.Structure):
     _fields_ = [("cell_mult", ctypes.c_double), ("max_sweeps", ctypes.c_int),
                 ("home_cells", ctypes.c_int), ("contact_slots", ctypes.c_int),
-                ("fp32_filter", ctypes.c_int), ("band_rel", ctypes.c_double),
+                ("filter", ctypes.c_int), ("band_rel", ctypes.c_double),
                 ("timing", ctypes.c_int), ("autotune", ctypes.c_int),
                 ("split_quantile", ctypes.c_double)]
 

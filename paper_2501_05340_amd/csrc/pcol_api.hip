@@ -26,7 +26,7 @@ struct pcol_ctx {
 
   // cell-sorted state of the last pcol_bin
   Rec *rec = nullptr;
-  Rec32 *rec32 = nullptr;  // FP32 filter records (fp32_filter only)
+  Rec32 *rec32 = nullptr;  // FP32 filter records (filter 1 only)
   int *perm = nullptr;  // sorted position -> caller index
   int *rank = nullptr;  // caller index -> sorted position
   int *cid = nullptr;
@@ -44,6 +44,9 @@ struct pcol_ctx {
   double *key_t = nullptr;
   uint8_t *status = nullptr;
   int *ovf = nullptr;
+  int *list_a = nullptr;  // spheres still to act after sweep 1
+  int *keep_cnt = nullptr, *keep_off = nullptr, *keep_bs = nullptr;  // its construction
+  int *nlist_h = nullptr;  // pinned read-back of its length
   OutRec *out = nullptr;
   int *partner_tmp = nullptr;
   double *tcoll_tmp = nullptr;
@@ -190,11 +193,11 @@ void pcol_default_opts(pcol_opts *o) {
   o->max_sweeps = 0;
   o->home_cells = 0;
   o->contact_slots = 12;
-  o->fp32_filter = 0;
+  o->filter = 0;
   o->band_rel = 1e-4;
   o->timing = 0;
   o->autotune = 1;
-  o->split_quantile = 0.99;
+  o->split_quantile = 0.999;
 }
 
 const char *pcol_last_error(const pcol_ctx *ctx) {
@@ -213,7 +216,7 @@ void pcol_destroy(pcol_ctx *ctx) {
   void *dev[] = {ctx->rec,    ctx->rec32,  ctx->perm,   ctx->rank,   ctx->cid,         ctx->slot,
                  ctx->count,  ctx->start,  ctx->blocksum, ctx->cnt,      ctx->slot_t,
                  ctx->slot_j, ctx->key_j,  ctx->key_t,  ctx->status,      ctx->out,
-                 ctx->ovf,    ctx->partner_tmp, ctx->tcoll_tmp,
+                 ctx->ovf,    ctx->partner_tmp, ctx->tcoll_tmp, ctx->list_a, ctx->keep_cnt, ctx->keep_off, ctx->keep_bs,
                  ctx->reach_d, ctx->ctr_d, ctx->tests_d};
   for (void *p : dev)
     if (p) (void)hipFree(p);
@@ -221,6 +224,7 @@ void pcol_destroy(pcol_ctx *ctx) {
   if (ctx->ctr_h) (void)hipHostFree(ctx->ctr_h);
   if (ctx->tests_h) (void)hipHostFree(ctx->tests_h);
   if (ctx->wide_h) (void)hipHostFree(ctx->wide_h);
+  if (ctx->nlist_h) (void)hipHostFree(ctx->nlist_h);
   for (hipEvent_t &e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
   if (BatchPlan *bp = ctx->bp) {
@@ -247,7 +251,8 @@ pcol_status pcol_create(pcol_ctx **out, int64_t n_max, void *hip_stream, const p
   if (!(ctx->opts.cell_mult >= 1.0) || !isfinite(ctx->opts.cell_mult) ||
       ctx->opts.max_sweeps < 0 || ctx->opts.contact_slots < 0 || ctx->opts.contact_slots > 64 ||
       !(ctx->opts.band_rel >= 0.0) ||
-      !(ctx->opts.split_quantile >= 0.0 && ctx->opts.split_quantile <= 1.0)) {
+      !(ctx->opts.split_quantile >= 0.0 && ctx->opts.split_quantile <= 1.0) ||
+      ctx->opts.filter < 0 || ctx->opts.filter > 2) {
     delete ctx;
     return PCOL_E_INVALID;
   }
@@ -260,7 +265,7 @@ pcol_status pcol_create(pcol_ctx **out, int64_t n_max, void *hip_stream, const p
     if (e == hipSuccess && r != hipSuccess) e = r;
   };
   A(dalloc(&ctx->rec, n));
-  if (ctx->opts.fp32_filter) A(dalloc(&ctx->rec32, n));
+  if (ctx->opts.filter == 1) A(dalloc(&ctx->rec32, n));
   A(dalloc(&ctx->perm, n));
   A(dalloc(&ctx->rank, n));
   A(dalloc(&ctx->cid, n));
@@ -273,6 +278,10 @@ pcol_status pcol_create(pcol_ctx **out, int64_t n_max, void *hip_stream, const p
   A(dalloc(&ctx->status, n));
   A(dalloc(&ctx->out, n));
   A(dalloc(&ctx->ovf, n));
+  A(dalloc(&ctx->list_a, n));
+  A(dalloc(&ctx->keep_cnt, n / 256 + 2));
+  A(dalloc(&ctx->keep_off, n / 256 + 3));
+  A(dalloc(&ctx->keep_bs, n / 256 / 4096 + 2));
   A(dalloc(&ctx->partner_tmp, n));
   A(dalloc(&ctx->tcoll_tmp, n));
   A(dalloc(&ctx->reach_d, 1));
@@ -282,6 +291,7 @@ pcol_status pcol_create(pcol_ctx **out, int64_t n_max, void *hip_stream, const p
   if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->ctr_h, sizeof(SweepCounters));
   if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->tests_h, sizeof(unsigned long long));
   if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->wide_h, 2 * sizeof(int));
+  if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->nlist_h, sizeof(int));
   for (hipEvent_t &ev : ctx->ev)
     if (e == hipSuccess) e = hipEventCreate(&ev);
   if (e != hipSuccess) {
@@ -394,7 +404,7 @@ pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box
   PCOL_HIP(launch_cell_hist(s, P, G, dt, rho_c, ctx->cid, ctx->slot, ctx->count));
   PCOL_HIP(launch_scan(s, ctx->count, cells_all, ctx->start, ctx->blocksum, ctx->reach_d));
   PCOL_HIP(launch_scatter(s, P, G, ctx->cid, ctx->slot, ctx->start, ctx->rec,
-                          ctx->opts.fp32_filter ? ctx->rec32 : nullptr, ctx->perm, ctx->rank,
+                          ctx->opts.filter == 1 ? ctx->rec32 : nullptr, ctx->perm, ctx->rank,
                           nullptr));
   PCOL_HIP(hipMemcpyAsync(&ctx->reach_h->maxcell, &ctx->reach_d->maxcell, sizeof(unsigned int),
                           hipMemcpyDeviceToHost, s));
@@ -457,6 +467,37 @@ static double fp32_band(const pcol_ctx *ctx, double dt) {  // returns the band
   return ctx->opts.band_rel > need ? ctx->opts.band_rel : need;
 }
 
+// Tolerance of the Gram filter (filter 2).  For a pair the rule keeps, the
+// real value F = c + b dt2 is at most E0 = 3 eps ((reach^2 + (2 r_max)^2) +
+// reach 2 v_max dt2) (the binary64 argument of the FMA filter), so the filter
+// must pass every pair whose evaluated F exceeds the real one by less than its
+// rounding error E.  With positions relative to the home cell centre, a home
+// sphere has |x_i| <= X_i = (sqrt 3 / 2) h and a kept partner |x_j| <= X_j =
+// X_i + reach, |v| <= v_max, r <= r_max (first-layer values), so
+//   |alpha| <= A_ = X_i^2 + dt2 X_i v + r^2,  |beta| <= B_ = X_j^2 + dt2 X_j v + r^2,
+//   S = sum_k |P_k Q_k| <= X_j (2 X_i + dt2 v) + v dt2 X_i + 2 r^2.
+// Each of P, Q, alpha, beta is rounded to binary32 (2^-24) and represented by
+// fp16 high and low parts to within 2^-22 of itself (fp16 subnormals are kept
+// by the conversions and the matrix cores); the product drops Q_lo P_lo
+// (2^-22); fp32 accumulation of the 32 exact products adds at most
+// 32 2^-24 (A_ + B_ + S).  So E <= 2^-24 (4 (A_ + B_) + 13 S) + 2^-19 (A_ + B_ + S)
+// and the tolerance is 2 (E + E0).
+static float gram_tolerance(const pcol_ctx *ctx, double dt2) {
+  double h = ctx->h[0];
+  for (int a = 1; a < 3; ++a) h = ctx->h[a] > h ? ctx->h[a] : h;
+  const double s3 = sqrt(3.0);
+  const double Xi = 0.5 * s3 * h * (1.0 + 1e-6), R = ctx->reach_pass;
+  const double Xj = Xi + R, V = ctx->vmax_pass, r = ctx->rmax_pass;
+  const double Ab = Xi * Xi + dt2 * Xi * V + r * r, Bb = Xj * Xj + dt2 * Xj * V + r * r;
+  const double S = Xj * (2.0 * Xi + dt2 * V) + V * dt2 * Xi + 2.0 * r * r;
+  const double eps = 0x1.0p-53;
+  const double E0 = 3.0 * eps * ((R * R + 4.0 * r * r) + R * 2.0 * V * dt2);
+  const double E = 0x1.0p-24 * (4.0 * (Ab + Bb) + 13.0 * S) + 0x1.0p-19 * (Ab + Bb + S);
+  float tol = (float)(2.0 * (E + E0));
+  if ((double)tol < 2.0 * (E + E0)) tol = nextafterf(tol, INFINITY);
+  return tol;
+}
+
 // sweep 1: keys of all spheres (all active) into ctx->key_j / key_t (sorted order)
 static pcol_status detect_all(pcol_ctx *ctx, double dt) {
   hipStream_t s = ctx->stream;
@@ -478,10 +519,16 @@ static pcol_status detect_all(pcol_ctx *ctx, double dt) {
       // differences between the filter's FMA values and the rule's b, c (pair64)
       const double R = ctx->reach_pass, smax = 2.0 * ctx->rmax_pass;
       A.tol = 16.0 * 0x1.0p-53 * (R * R + smax * smax + R * 2.0 * ctx->vmax_pass * A.dt2);
+      // pairs with a sphere above the split extent: |d| up to the full reach
+      const double Rw = ctx->reach, sw = 2.0 * ctx->rmax;
+      A.tol_wide = 16.0 * 0x1.0p-53 * (Rw * Rw + sw * sw + Rw * 2.0 * ctx->vmax * A.dt2);
+      A.rho_c = ctx->rho_c;
     }
     A.K = ctx->K;
     A.rec32 = ctx->rec32;
-    A.fp32 = ctx->opts.fp32_filter;
+    A.fp32 = ctx->opts.filter == 1;
+    A.gram = ctx->opts.filter == 2;
+    A.tolg = A.gram ? gram_tolerance(ctx, A.dt2) : 0.0f;
     // the FP32 filter reads its home records from an LDS copy of the home cell
     // (when the largest cell fits in 20 KB); the FP64 filter reads them through
     // the scalar cache, which measured faster for 64-B records
@@ -593,9 +640,21 @@ pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, dou
     ctx->detect_timed = false;
     if ((st = detect_all(ctx, dt)) != PCOL_OK) return st;
     if (timing) PCOL_HIP(hipEventRecord(ctx->ev[2], s));
+    // sweep 1 over every sphere; later sweeps over the list of the spheres it
+    // left ACTIVE or DIRTY (the others are done for the step; entries that
+    // finish later are skipped by their status)
+    const int *lin = nullptr;
+    int nlist = 0;
     for (;;) {
       PCOL_HIP(launch_resolve_sweep(s, n, ctx->rec, ctx->G, dt, e, ctx->key_j, ctx->key_t,
-                                    ctx->status, ctx->perm, ctx->out, ctx->ctr_d, nullptr));
+                                    ctx->status, ctx->perm, ctx->out, ctx->ctr_d, nullptr, lin,
+                                    nlist));
+      if (!lin) {
+        PCOL_HIP(launch_keep_list(s, ctx->status, n, ctx->keep_cnt, ctx->keep_off, ctx->keep_bs,
+                                  ctx->reach_d, ctx->list_a));
+        PCOL_HIP(hipMemcpyAsync(ctx->nlist_h, ctx->keep_off + (n + 255) / 256, sizeof(int),
+                                hipMemcpyDeviceToHost, s));
+      }
       PCOL_HIP(hipMemcpyAsync(ctx->ctr_h, ctx->ctr_d, sizeof(SweepCounters),
                               hipMemcpyDeviceToHost, s));
       PCOL_HIP(hipStreamSynchronize(s));
@@ -614,24 +673,28 @@ pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, dou
       if (sp == 0ull) break;
       if (ctx->opts.max_sweeps > 0 && sweeps >= ctx->opts.max_sweeps)
         return fail(ctx, PCOL_E_SWEEPS, "sweep cap reached with pairs still resolving");
+      if (!lin) {
+        lin = ctx->list_a;
+        nlist = *ctx->nlist_h;
+      }
       // next sweep: new partners for DIRTY spheres (partner collided elsewhere)
       PCOL_HIP(hipMemsetAsync(ctx->ctr_d, 0, sizeof(SweepCounters), s));
       if (!ctx->small) {
         PCOL_HIP(launch_slot_min(s, n, 0, ctx->cnt, ctx->slot_t, ctx->slot_j, ctx->K, ctx->status,
-                                 ctx->perm, ctx->key_j, ctx->key_t, ctx->ovf, ctx->ctr_d,
-                             nullptr));
+                                 ctx->perm, ctx->key_j, ctx->key_t, ctx->ovf, ctx->ctr_d, nullptr,
+                                 lin, nlist));
         PCOL_HIP(launch_gather_exact(s, ctx->ovf, 0, &ctx->ctr_d->n_overflow, -1, ctx->rec,
                                      ctx->start, ctx->G, dt, ctx->status, ctx->perm, ctx->key_j,
                                      ctx->key_t, nullptr));
       } else {
-        PCOL_HIP(launch_gather_exact(s, nullptr, n, nullptr, ST_DIRTY, ctx->rec, ctx->start,
+        PCOL_HIP(launch_gather_exact(s, lin, nlist, nullptr, ST_DIRTY, ctx->rec, ctx->start,
                                      ctx->G, dt, ctx->status, ctx->perm, ctx->key_j,
                                      ctx->key_t, nullptr));
       }
     }
     if (timing) PCOL_HIP(hipEventRecord(ctx->ev[3], s));
-    PCOL_HIP(launch_advance_sorted(s, n, ctx->rec, ctx->status, dt, ctx->G, ctx->out, nullptr));
-    PCOL_HIP(launch_unpermute(s, P, ctx->rank, ctx->out, part, tc, nullptr));
+    PCOL_HIP(launch_finish(s, P, ctx->rank, ctx->rec, ctx->status, ctx->out, part, tc, dt, ctx->G,
+                           nullptr));
     if (timing) {
       PCOL_HIP(hipEventRecord(ctx->ev[4], s));
       PCOL_HIP(hipEventSynchronize(ctx->ev[4]));
@@ -911,8 +974,8 @@ static pcol_status batch_enqueue(pcol_ctx *ctx, hipStream_t s, const Particles &
                                  ctx->start, ctx->G, dt, ctx->status, ctx->perm, ctx->key_j,
                                  ctx->key_t, &B));
   }
-  PCOL_HIP(launch_advance_sorted(s, n, ctx->rec, ctx->status, dt, ctx->G, ctx->out, &B));
-  PCOL_HIP(launch_unpermute(s, P, ctx->rank, ctx->out, part, tc, bp->flags));
+  PCOL_HIP(launch_finish(s, P, ctx->rank, ctx->rec, ctx->status, ctx->out, part, tc, dt, ctx->G,
+                         &B));
   return PCOL_OK;
 }
 
@@ -962,8 +1025,8 @@ static pcol_status batch_finish(pcol_ctx *ctx, const Particles &P, int32_t *part
                                  ctx->key_t, &B));
   }
   PCOL_HIP(launch_fill_u32(s, bp->flags + FLAG_UNFINISHED, 0u, 1));
-  PCOL_HIP(launch_advance_sorted(s, n, ctx->rec, ctx->status, dt, ctx->G, ctx->out, &B));
-  PCOL_HIP(launch_unpermute(s, P, ctx->rank, ctx->out, part, tc, bp->flags));
+  PCOL_HIP(launch_finish(s, P, ctx->rank, ctx->rec, ctx->status, ctx->out, part, tc, dt, ctx->G,
+                         &B));
   return PCOL_OK;
 }
 

@@ -223,12 +223,16 @@ struct DetectArgs {
   double dt;
   double dt2;         // 2 dt (1 + 2^-20): step bound of the FP64 filter
   double tol;         // FP64 filter tolerance (bound on FMA-vs-rule rounding differences)
+  double tol_wide;    // the same for pairs with a sphere above the split extent (full reach)
+  double rho_c;       // split extent (first-layer spheres have extent <= rho_c)
   int K;
   int cap;            // home spheres staged in LDS per cell (largest cell occupancy);
                       // 0: read the home spheres through the scalar cache instead
   int fp32;           // FP32 filter + FP64 recheck
   float kband;        // FP32 filter: contact distance inflated to s * kband
   float dt2f;         // FP32 filter: 2 dt (1 + 2^-12)
+  int gram;           // half-precision Gram filter on the matrix cores + FP64 recheck
+  float tolg;         // its tolerance (bound on its rounding, see gram_tolerance)
 };
 
 hipError_t launch_fill_u32(hipStream_t s, unsigned int *p, unsigned int v, int64_t n);
@@ -251,7 +255,7 @@ hipError_t launch_count_pairs(hipStream_t s, const int *start, const Grid &G,
 hipError_t launch_slot_min(hipStream_t s, int n, int first, const int *cnt, const double *slot_t,
                            const int *slot_j, int K, uint8_t *status, const int *perm, int *key_j,
                            double *key_t, int *ovf_list, SweepCounters *ctr,
-                           const unsigned int *flags);
+                           const unsigned int *flags, const int *list = nullptr, int nlist = 0);
 hipError_t launch_gather_exact(hipStream_t s, const int *list, int nlist, const unsigned int *nlist_dev,
                                int select, const Rec *rec, const int *start, const Grid &G,
                                double dt, uint8_t *status, const int *perm, int *key_j,
@@ -259,11 +263,15 @@ hipError_t launch_gather_exact(hipStream_t s, const int *list, int nlist, const 
 hipError_t launch_resolve_sweep(hipStream_t s, int n, const Rec *rec, const Grid &G, double dt,
                                 double e, const int *key_j, const double *key_t, uint8_t *status,
                                 const int *perm, OutRec *out, SweepCounters *ctr,
-                                const BatchDev *B);
-hipError_t launch_advance_sorted(hipStream_t s, int n, const Rec *rec, const uint8_t *status,
-                                 double dt, const Grid &G, OutRec *out, const BatchDev *B);
-hipError_t launch_unpermute(hipStream_t s, const Particles &P, const int *rank, const OutRec *out,
-                            int *partner, double *tcoll, const unsigned int *flags);
+                                const BatchDev *B, const int *list = nullptr, int nlist = 0);
+// list (n_list entries, read back from off[(n + 255) / 256]) of the ACTIVE or
+// DIRTY spheres; count and off need (n + 255) / 256 + 1 entries, blocksum
+// ((n + 255) / 256) / 4096 + 2
+hipError_t launch_keep_list(hipStream_t s, const uint8_t *status, int n, int *count, int *off,
+                            int *blocksum, ReachOut *scratch_out, int *list);
+hipError_t launch_finish(hipStream_t s, const Particles &P, const int *rank, const Rec *rec,
+                         const uint8_t *status, const OutRec *out, int *partner, double *tcoll,
+                         double dt, const Grid &G, const BatchDev *B);
 hipError_t launch_fill_box_of(hipStream_t s, int nbox, const int64_t *box_off, int *box_of);
 hipError_t launch_breach(hipStream_t s, const Particles &P, const BatchDev &B, double dt,
                          int check_plan);

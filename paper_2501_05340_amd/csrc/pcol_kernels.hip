@@ -137,11 +137,23 @@ __global__ __launch_bounds__(256) void k_reach(Particles P, double L0, double L1
       v2 = w > v2 ? w : v2;
       rm = r > rm ? r : rm;
       rn = r < rn ? r : rn;
-      if (r > 0.0) {
-        const double ex = extent(r, vx, vy, vz, dt);
-        em = ex > em ? ex : em;
-        atomicAdd(&hist[rho_bin(ex)], 1u);
-      }
+    }
+    // histogram: one LDS atomic per distinct bin of the wave (lanes of one
+    // bin add together), so the few busy bins see no lane conflicts
+    const bool has = fin && r > 0.0;
+    int bin = -1;
+    if (has) {
+      const double ex = extent(r, vx, vy, vz, dt);
+      em = ex > em ? ex : em;
+      bin = rho_bin(ex);
+    }
+    unsigned long long todo = __ballot(has);
+    while (todo) {
+      const int leader = __ffsll((long long)todo) - 1;
+      const int lb = __shfl(bin, leader);
+      const unsigned long long same = __ballot(bin == lb);
+      if ((int)__lane_id() == leader) atomicAdd(&hist[lb], (unsigned int)__popcll(same));
+      todo &= ~same;
     }
   }
   for (int o = WAVE / 2; o > 0; o >>= 1) {
@@ -418,9 +430,10 @@ __device__ __forceinline__ void record_contact(const DetectArgs &A, int i, int g
 constexpr int QCAP = 256;
 
 struct SurvivorQueue {
-  int2 *q;              // QCAP entries in LDS, private to the wave
+  int2 *q;              // cap entries in LDS, private to the wave
   int n;                // entries waiting (wave-uniform)
   unsigned int pushed;  // survivors seen (wave-uniform)
+  int cap;
 };
 
 // The rule for every queued pair (rule 1 with the canonical minimum image,
@@ -447,7 +460,7 @@ __device__ __forceinline__ bool push_survivor(bool pass, int i, int g, SurvivorQ
   if (!m) return true;
   const int c = __popcll(m);
   Q.pushed += c;
-  if (Q.n + c > QCAP) return false;
+  if (Q.n + c > Q.cap) return false;
   if (pass) {
     const unsigned int lane = __lane_id();
     Q.q[Q.n + __popcll(m & ((1ull << lane) - 1ull))] = make_int2(i, g);
@@ -591,13 +604,106 @@ __device__ __forceinline__ void detect_chunk32(const DetectArgs &A, const Grid &
 // cell of the box whose grid is G (cell numbers below are local to that box;
 // sphere positions in start[] are global).  LDSI: lds_raw holds room for the
 // home cell and the workgroup is this single wave.
+// Runs of consecutive cell-sorted records that make the half stencil of one
+// home cell: the own cell (pairs with j after i), the next cell along x, and 4
+// rows of 3 cells, a row split in two where it wraps along x; each with its
+// periodic image shift code.  Returns false for an empty home cell.
+struct CellRuns {
+  int rg[MAXRUN], rl[MAXRUN], rc[MAXRUN];
+  int h0, h1, cx, cy, cz;
+  bool any_shift;
+};
+
+__device__ __forceinline__ bool cell_runs(const Grid &G, const int *start, int cell, CellRuns &R) {
+  const int nc0 = G.nc[0], nc1 = G.nc[1], nc2 = G.nc[2];
+  const int cx = cell % nc0, cy = (cell / nc0) % nc1, cz = cell / (nc0 * nc1);
+  const int dys[4] = {1, -1, 0, 1}, dzs[4] = {0, 1, 1, 1};
+  // The 20 cell starts the runs below need, fetched by one vector load (lane
+  // k loads slot k) instead of a chain of dependent scalar loads:
+  //   0, 1   the own cell [h0, h1)
+  //   2, 3   the next cell along x (cell 0 of the row where x wraps)
+  //   4 + 4 row + {0, 1, 2, 3}: the row's first run and second run (the
+  //          second is empty unless the row wraps along x)
+  int v = 0;
+  {
+    const int ln = (int)__lane_id();
+    int idx = cell;
+    if (ln == 1) {
+      idx = cell + 1;
+    } else if (ln == 2 || ln == 3) {
+      const int own_row = (cz * nc1 + cy) * nc0;
+      idx = cx + 1 >= nc0 ? own_row + (ln - 2) : cell + ln - 1;
+    } else if (ln >= 4 && ln < 20) {
+      const int row = (ln - 4) >> 2, w = (ln - 4) & 3;
+      // row offsets (dy, dz) = (1, 0), (-1, 1), (0, 1), (1, 1), as dys / dzs
+      int y = cy + (row == 1 ? -1 : (row == 2 ? 0 : 1)), z = cz + (row == 0 ? 0 : 1);
+      y = y >= nc1 ? y - nc1 : (y < 0 ? y + nc1 : y);
+      z = z >= nc2 ? z - nc2 : z;
+      const int rb = (z * nc1 + y) * nc0;
+      int o;
+      if (cx - 1 < 0)  // the wrapped left cell, then cells 0..1
+        o = w == 0 ? nc0 - 1 : (w == 1 ? nc0 : (w == 2 ? 0 : 2));
+      else if (cx + 1 >= nc0)  // cells cx-1..cx, then the wrapped right cell 0
+        o = w == 0 ? cx - 1 : (w == 1 ? cx + 1 : (w == 2 ? 0 : 1));
+      else  // cells cx-1..cx+1; empty second run
+        o = w == 0 ? cx - 1 : cx + 2;
+      idx = rb + o;
+    }
+    if (ln < 20) v = start[idx];
+  }
+  const int h0 = __builtin_amdgcn_readlane(v, 0), h1 = __builtin_amdgcn_readlane(v, 1);
+  R.h0 = h0;
+  R.h1 = h1;
+  R.cx = cx;
+  R.cy = cy;
+  R.cz = cz;
+  if (h1 <= h0) return false;
+  // runs of consecutive sorted records: global start, length, shift code
+  int *rg = R.rg, *rl = R.rl, *rc = R.rc;
+  bool any_shift = false;
+  // own cell first (pairs with j after i), then the next cell along x
+  rg[0] = h0;
+  rl[0] = h1 - h0;
+  rc[0] = run_code(0, 0, 0, 1);
+  rg[1] = __builtin_amdgcn_readlane(v, 2);
+  rl[1] = __builtin_amdgcn_readlane(v, 3) - rg[1];
+  rc[1] = run_code(cx + 1 >= nc0 ? 1 : 0, 0, 0, 0);
+  if (cx + 1 >= nc0) any_shift = true;
+#pragma unroll
+  for (int row = 0; row < 4; ++row) {
+    const int y = cy + dys[row], z = cz + dzs[row];
+    const int sy = y >= nc1 ? 1 : (y < 0 ? -1 : 0), sz = z >= nc2 ? 1 : 0;
+    const int k0 = 2 + 2 * row, k1 = 3 + 2 * row;
+    rg[k0] = __builtin_amdgcn_readlane(v, 4 + 4 * row);
+    rl[k0] = __builtin_amdgcn_readlane(v, 5 + 4 * row) - rg[k0];
+    rg[k1] = __builtin_amdgcn_readlane(v, 6 + 4 * row);
+    rl[k1] = __builtin_amdgcn_readlane(v, 7 + 4 * row) - rg[k1];
+    if (cx - 1 < 0) {
+      rc[k0] = run_code(-1, sy, sz, 0);
+      rc[k1] = run_code(0, sy, sz, 0);
+      any_shift = true;
+    } else if (cx + 1 >= nc0) {
+      rc[k0] = run_code(0, sy, sz, 0);
+      rc[k1] = run_code(1, sy, sz, 0);
+      any_shift = true;
+    } else {
+      rc[k0] = run_code(0, sy, sz, 0);
+      rc[k1] = run_code(0, sy, sz, 0);
+    }
+    if (sy != 0 || sz != 0) any_shift = true;
+  }
+  R.any_shift = any_shift;
+  return true;
+}
+
 template <bool FP32, bool LDSI>
 __device__ __forceinline__ void detect_cell(const DetectArgs &A, const Grid &G, const int *start,
                                             int cell, SurvivorQueue &Q, double4 *lds_raw) {
-  const int nc0 = G.nc[0], nc1 = G.nc[1], nc2 = G.nc[2];
-  const int cx = cell % nc0, cy = (cell / nc0) % nc1, cz = cell / (nc0 * nc1);
-  const int h0 = start[cell], h1 = start[cell + 1];
-  if (h1 <= h0) return;
+  CellRuns R;
+  if (!cell_runs(G, start, cell, R)) return;
+  const int h0 = R.h0, h1 = R.h1, cx = R.cx, cy = R.cy, cz = R.cz;
+  const int *rg = R.rg, *rl = R.rl, *rc = R.rc;
+  const bool any_shift = R.any_shift;
   if (LDSI) {  // stage the home cell (cap >= occupancy of every cell)
     for (int k = threadIdx.x; k < h1 - h0; k += WAVE) {
       if (FP32)
@@ -608,70 +714,6 @@ __device__ __forceinline__ void detect_cell(const DetectArgs &A, const Grid &G, 
     __syncthreads();
   }
 
-  // runs of consecutive sorted records: global start, length, shift code
-  int rg[MAXRUN], rl[MAXRUN], rc[MAXRUN];
-#pragma unroll
-  for (int k = 0; k < MAXRUN; ++k) {
-    rg[k] = 0;
-    rl[k] = 0;
-    rc[k] = run_code(0, 0, 0, 0);
-  }
-  bool any_shift = false;
-  // own cell first (pairs with j after i), then the next cell along x
-  rg[0] = h0;
-  rl[0] = h1 - h0;
-  rc[0] = run_code(0, 0, 0, 1);
-  if (cx + 1 >= nc0) {
-    const int rowbase = (cz * nc1 + cy) * nc0;
-    rg[1] = start[rowbase];
-    rl[1] = start[rowbase + 1] - rg[1];
-    rc[1] = run_code(1, 0, 0, 0);
-    any_shift = true;
-  } else {
-    rg[1] = h1;
-    rl[1] = start[cell + 2] - h1;
-  }
-  const int dys[4] = {1, -1, 0, 1}, dzs[4] = {0, 1, 1, 1};
-#pragma unroll
-  for (int row = 0; row < 4; ++row) {
-    int y = cy + dys[row], z = cz + dzs[row];
-    int sy = 0, sz = 0;
-    if (y >= nc1) {
-      y -= nc1;
-      sy = 1;
-    } else if (y < 0) {
-      y += nc1;
-      sy = -1;
-    }
-    if (z >= nc2) {
-      z -= nc2;
-      sz = 1;
-    }
-    const int rowbase = (z * nc1 + y) * nc0;
-    const int k0 = 2 + 2 * row, k1 = 3 + 2 * row;
-    if (cx - 1 < 0) {  // the wrapped left cell, then cells 0..1
-      rg[k0] = start[rowbase + nc0 - 1];
-      rl[k0] = start[rowbase + nc0] - rg[k0];
-      rc[k0] = run_code(-1, sy, sz, 0);
-      rg[k1] = start[rowbase];
-      rl[k1] = start[rowbase + 2] - rg[k1];
-      rc[k1] = run_code(0, sy, sz, 0);
-      any_shift = true;
-    } else if (cx + 1 >= nc0) {  // cells cx-1..cx, then the wrapped right cell 0
-      rg[k0] = start[rowbase + cx - 1];
-      rl[k0] = start[rowbase + cx + 1] - rg[k0];
-      rc[k0] = run_code(0, sy, sz, 0);
-      rg[k1] = start[rowbase];
-      rl[k1] = start[rowbase + 1] - rg[k1];
-      rc[k1] = run_code(1, sy, sz, 0);
-      any_shift = true;
-    } else {
-      rg[k0] = start[rowbase + cx - 1];
-      rl[k0] = start[rowbase + cx + 2] - rg[k0];
-      rc[k0] = run_code(0, sy, sz, 0);
-    }
-    if (sy != 0 || sz != 0) any_shift = true;
-  }
   int total = 0;
   int pre[MAXRUN];
 #pragma unroll
@@ -763,9 +805,206 @@ template <bool FP32, bool LDSI>
 __global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
   extern __shared__ double4 lds_raw[];  // LDSI: the home cell's records (Rec or Rec32)
   __shared__ int2 survq[QCAP];
-  SurvivorQueue Q{survq, 0, 0u};
+  SurvivorQueue Q{survq, 0, 0u, QCAP};
   detect_cell<FP32, LDSI>(A, A.G, A.start, xcd_remap(blockIdx.x, gridDim.x), Q, lds_raw);
   if (FP32 && __lane_id() == 0 && Q.pushed)
+    atomicAdd(&A.ctr->shard[blockIdx.x % NSHARD].recheck, (unsigned long long)Q.pushed);
+}
+
+// ---------------------------------------------------------------- a5, Gram filter on the matrix cores
+
+// The filter value of a pair, F = |d|^2 - s^2 + dt2 (d . u) with d = x_j - x_i,
+// u = v_j - v_i, s = r_i + r_j, splits into a term of i, a term of j and one
+// dot product of 7-vectors (positions relative to the home cell centre):
+//   F = alpha_i + beta_j + <P_j, Q_i>,
+//   P_j = (x_j, v_j, r_j),  Q_i = (-2 x_i - dt2 v_i, -dt2 x_i, -2 r_i),
+//   alpha_i = |x_i|^2 + dt2 x_i.v_i - r_i^2,  beta_j = |x_j|^2 + dt2 x_j.v_j - r_j^2.
+// For a home cell (rows i, 16 per tile) against a chunk of 64 candidates
+// (columns j, 4 tiles of 16) it is one dense 16 x 16 x 32 product on the
+// matrix cores.  Every quantity is split into fp16 high and low parts and the
+// K = 32 slots of a row (home) and a column (candidate) hold
+//   slice 0: Q_hi, alpha_hi  |  P_hi, 1          (Q_hi.P_hi + alpha_hi)
+//   slice 1: Q_lo, alpha_lo  |  P_hi, 1          (Q_lo.P_hi + alpha_lo)
+//   slice 2: Q_hi, 1         |  P_lo, beta_hi    (Q_hi.P_lo + beta_hi)
+//   slice 3: 0..0, 1         |  0..0, beta_lo    (beta_lo)
+// accumulated in fp32 from zero.  A pair passes iff the result is <= tolg, a
+// bound on every rounding of this evaluation for pairs the rule can keep
+// (host, gram_tolerance); survivors are decided by the rule, so the result is
+// exactly the rule's.  Rows without a home sphere and columns without a
+// candidate carry alpha or beta = 60000, far above any pass.
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+constexpr int GRAM_ROWS = 64;         // home spheres per cell on this path (4 row tiles)
+constexpr float GRAM_NONE = 60000.0f;  // alpha / beta of an empty row / column (fp16 finite)
+
+struct GramLds {
+  half8_t hi[WAVE];   // candidate (P_hi, 1)
+  half8_t lo[WAVE];   // candidate (P_lo, beta_hi)
+  half8_t bl[WAVE];   // candidate (0, ..., 0, beta_lo)
+  int gj[WAVE];       // candidate sorted index
+  int thr[WAVE];      // -1: no candidate; own cell: its index; else INT_MAX
+};
+
+// fp16 high part of v and the fp16 of the remainder, through binary32 (v is
+// already a small relative quantity, so binary32 holds it to 2^-24)
+__device__ __forceinline__ void split_half(float v, _Float16 &hi, _Float16 &lo) {
+  hi = (_Float16)v;
+  lo = (_Float16)(v - (float)hi);
+}
+
+__device__ __forceinline__ void detect_cell_gram(const DetectArgs &A, const Grid &G,
+                                                 const int *start, int cell, SurvivorQueue &Q,
+                                                 GramLds &S) {
+  CellRuns R;
+  if (!cell_runs(G, start, cell, R)) return;
+  const int h0 = R.h0, h1 = R.h1, nh = h1 - h0;
+  if (nh > GRAM_ROWS) {  // a crowded cell: the binary64 filter
+    detect_cell<false, false>(A, G, start, cell, Q, nullptr);
+    return;
+  }
+  const int lane = __lane_id();
+  const int slice = lane >> 4;  // k slice of the operands, row group of the result
+  const double ox = (R.cx + 0.5) * G.h[0], oy = (R.cy + 0.5) * G.h[1], oz = (R.cz + 0.5) * G.h[2];
+  const double dt2 = A.dt2;
+  const int nrt = (nh + 15) >> 4;
+  const _Float16 one = (_Float16)1.0f, zero = (_Float16)0.0f;
+  // home operand of row tile rt: homes 16 rt .. 16 rt + 15 (see the K layout above)
+  half8_t afr[4];
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt) {
+    half8_t f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) f[k] = zero;
+    const int row = 16 * rt + (lane & 15);
+    if (rt < nrt) {
+      float q[7];
+      float alpha = GRAM_NONE;
+      if (row < nh) {
+        const Rec a = A.rec[h0 + row];
+        const double xh = a.x - ox, yh = a.y - oy, zh = a.z - oz;
+        q[0] = (float)(-2.0 * xh - dt2 * a.vx);
+        q[1] = (float)(-2.0 * yh - dt2 * a.vy);
+        q[2] = (float)(-2.0 * zh - dt2 * a.vz);
+        q[3] = (float)(-dt2 * xh);
+        q[4] = (float)(-dt2 * yh);
+        q[5] = (float)(-dt2 * zh);
+        q[6] = (float)(-2.0 * a.r);
+        alpha = (float)(((xh * xh + yh * yh) + zh * zh) +
+                        dt2 * ((xh * a.vx + yh * a.vy) + zh * a.vz) - a.r * a.r);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 7; ++k) q[k] = 0.0f;
+      }
+      if (slice < 3) {
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+          _Float16 hi, lo;
+          split_half(q[k], hi, lo);
+          f[k] = slice == 1 ? lo : hi;
+        }
+        _Float16 ahi, alo;
+        split_half(alpha, ahi, alo);
+        f[7] = slice == 0 ? ahi : (slice == 1 ? alo : one);
+      } else {
+        f[7] = one;
+      }
+    }
+    afr[rt] = f;
+  }
+  int total = 0;
+  int pre[MAXRUN];
+#pragma unroll
+  for (int k = 0; k < MAXRUN; ++k) {
+    pre[k] = total;
+    total += R.rl[k];
+  }
+  for (int base = 0; base < total; base += WAVE) {
+    // the lane's candidate, as in detect_cell
+    const int v = base + lane;
+    int g = 0, code = run_code(0, 0, 0, 0);
+    bool ok = false;
+#pragma unroll
+    for (int k = 0; k < MAXRUN; ++k) {
+      if (v >= pre[k] && v < pre[k] + R.rl[k]) {
+        g = R.rg[k] + (v - pre[k]);
+        code = R.rc[k];
+        ok = true;
+      }
+    }
+    const bool own = (code >> 6) & 1;
+    const int thr = !ok ? -1 : (own ? g : 0x7fffffff);
+    half8_t ph, pl, pb;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      ph[k] = zero;
+      pl[k] = zero;
+      pb[k] = zero;
+    }
+    float beta = GRAM_NONE;
+    if (thr >= 0) {
+      const Rec b = A.rec[g];
+      const double xj = (b.x + code_shift(code & 3, G.L[0])) - ox;
+      const double yj = (b.y + code_shift((code >> 2) & 3, G.L[1])) - oy;
+      const double zj = (b.z + code_shift((code >> 4) & 3, G.L[2])) - oz;
+      const float p[7] = {(float)xj, (float)yj, (float)zj, (float)b.vx, (float)b.vy, (float)b.vz,
+                          (float)b.r};
+#pragma unroll
+      for (int k = 0; k < 7; ++k) {
+        _Float16 hi, lo;
+        split_half(p[k], hi, lo);
+        ph[k] = hi;
+        pl[k] = lo;
+      }
+      beta = (float)(((xj * xj + yj * yj) + zj * zj) + dt2 * ((xj * b.vx + yj * b.vy) + zj * b.vz) -
+                     b.r * b.r);
+    }
+    ph[7] = one;
+    {
+      _Float16 hi, lo;
+      split_half(beta, hi, lo);
+      pl[7] = hi;
+      pb[7] = lo;
+    }
+    // one wave owns S: its LDS writes reach its later reads in order
+    S.hi[lane] = ph;
+    S.lo[lane] = pl;
+    S.bl[lane] = pb;
+    S.gj[lane] = g;
+    S.thr[lane] = thr;
+#pragma unroll 1
+    for (int t = 0; t < 4; ++t) {
+      const int c = 16 * t + (lane & 15);  // the candidate column this lane feeds and reads
+      const half8_t bfr = slice == 3 ? S.bl[c] : (slice == 2 ? S.lo[c] : S.hi[c]);
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) {
+        if (rt < nrt) {
+          const float4_t z4 = {0.0f, 0.0f, 0.0f, 0.0f};
+          const float4_t d = __builtin_amdgcn_mfma_f32_16x16x32_f16(afr[rt], bfr, z4, 0, 0, 0);
+          const bool p0 = d[0] <= A.tolg, p1 = d[1] <= A.tolg, p2 = d[2] <= A.tolg,
+                     p3 = d[3] <= A.tolg;
+          if (__ballot(p0 || p1 || p2 || p3)) {  // rare: queue this tile's survivors
+            if (Q.n > Q.cap - 4 * WAVE) flush_survivors(A, G, Q);
+            const int gc = S.gj[c], tc = S.thr[c];
+            const int i0 = h0 + 16 * rt + 4 * slice;
+            (void)push_survivor(p0 && i0 < tc, i0, gc, Q);
+            (void)push_survivor(p1 && i0 + 1 < tc, i0 + 1, gc, Q);
+            (void)push_survivor(p2 && i0 + 2 < tc, i0 + 2, gc, Q);
+            (void)push_survivor(p3 && i0 + 3 < tc, i0 + 3, gc, Q);
+          }
+        }
+      }
+    }
+  }
+  flush_survivors(A, G, Q);
+}
+
+__global__ __launch_bounds__(WAVE) void k_detect_gram(DetectArgs A) {
+  __shared__ int2 survq[2 * QCAP];
+  __shared__ GramLds S;
+  SurvivorQueue Q{survq, 0, 0u, 2 * QCAP};
+  detect_cell_gram(A, A.G, A.start, xcd_remap(blockIdx.x, gridDim.x), Q, S);
+  if (__lane_id() == 0 && Q.pushed)
     atomicAdd(&A.ctr->shard[blockIdx.x % NSHARD].recheck, (unsigned long long)Q.pushed);
 }
 
@@ -794,7 +1033,7 @@ __global__ __launch_bounds__(256) void k_detect_batched(DetectArgs A, BatchDev B
   const int wave = threadIdx.x / WAVE;
   const int total = B.cell_base[B.nbox];
   const int stride = gridDim.x * wpb;
-  SurvivorQueue Q{survq[wave], 0, 0u};
+  SurvivorQueue Q{survq[wave], 0, 0u, QCAP};
   for (int item = blockIdx.x * wpb + wave; item < total; item += stride) {
     const int b = box_of_cell(B.cell_base, B.nbox, item);
     const Grid G = B.gtab[b];
@@ -805,6 +1044,10 @@ __global__ __launch_bounds__(256) void k_detect_batched(DetectArgs A, BatchDev B
 
 hipError_t launch_detect_half(hipStream_t s, const DetectArgs &A) {
   if (A.G.ncell <= 0) return hipSuccess;
+  if (A.gram) {
+    hipLaunchKernelGGL(k_detect_gram, dim3(A.G.ncell), dim3(WAVE), 0, s, A);
+    return hipGetLastError();
+  }
   const size_t lds = (size_t)A.cap * (A.fp32 ? sizeof(Rec32) : sizeof(Rec));
   if (A.cap > 0) {
     if (A.fp32)
@@ -868,12 +1111,14 @@ __global__ __launch_bounds__(256) void k_slot_min(int n, int first, const int *c
                                                   const double *slot_t, const int *slot_j, int K,
                                                   uint8_t *status, const int *perm, int *key_j,
                                                   double *key_t, int *ovf_list,
-                                                  SweepCounters *ctr, const unsigned int *flags) {
+                                                  SweepCounters *ctr, const unsigned int *flags,
+                                                  const int *list, int nlist) {
   if (flags && (flags[FLAG_ERR] || flags[FLAG_DONE])) return;
-  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  const int i = list && t < nlist ? list[t] : t;
   bool ovf = false;
   unsigned long long nc = 0ull;
-  if (i < n) {
+  if (list ? t < nlist : i < n) {
     const uint8_t st = status[i];
     if (first ? st == ST_ACTIVE : st == ST_DIRTY) {
       const int c = cnt[i];
@@ -908,10 +1153,11 @@ __global__ __launch_bounds__(256) void k_slot_min(int n, int first, const int *c
 hipError_t launch_slot_min(hipStream_t s, int n, int first, const int *cnt, const double *slot_t,
                            const int *slot_j, int K, uint8_t *status, const int *perm, int *key_j,
                            double *key_t, int *ovf_list, SweepCounters *ctr,
-                           const unsigned int *flags) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_slot_min, dim3((n + 255) / 256), dim3(256), 0, s, n, first, cnt, slot_t,
-                     slot_j, K, status, perm, key_j, key_t, ovf_list, ctr, flags);
+                           const unsigned int *flags, const int *list, int nlist) {
+  const int items = list ? nlist : n;
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_slot_min, dim3((items + 255) / 256), dim3(256), 0, s, n, first, cnt, slot_t,
+                     slot_j, K, status, perm, key_j, key_t, ovf_list, ctr, flags, list, nlist);
   return hipGetLastError();
 }
 
@@ -963,12 +1209,29 @@ __device__ __forceinline__ void search_radius(const Grid &G, const Rec &a, doubl
   }
 }
 
-// Run r of a search box (see search_box_runs), numbered
-// ((layer * nz + iz) * ny + iy) * 2 + part, as [first, end) of sorted records;
-// empty for parts a row does not have.
-__device__ __forceinline__ void search_box_run(const Grid &G, const int *start, int r, int ny,
-                                               int nz, int cx, int cy, int cz, const int k[3],
-                                               int &first, int &end) {
+// Distance along one axis from a sphere at offset f within its cell (cell side
+// h) to the cells `o` cells away: 0 for its own cell, else the gap to the
+// nearer face.  Cell faces are taken `eta` nearer, which covers spheres that
+// rounding placed in a neighbouring cell.
+__device__ __forceinline__ double face_gap(int o, double f, double h, double eta) {
+  double g = 0.0;
+  if (o > 0) g = o * h - f;
+  if (o < 0) g = f - (o + 1) * h;
+  g -= eta;
+  return g > 0.0 ? g : 0.0;
+}
+
+// Run r of the ball-pruned search of a sphere at (px, py, pz) in cell
+// (cx, cy, cz): r = (layer * nz + iz) * ny + iy) * 2 + part over the rows of
+// its search box (kx..kz cells either side, whole axes once when 2k + 1 covers
+// them).  A row is clipped along x to the cells within distance R[layer] of
+// the sphere (exact where the search box does not cover the axis; the whole
+// row otherwise) and split in two where it wraps.  Sets [first, end) of
+// sorted records (empty if the row holds no such cell).
+__device__ __forceinline__ void wide_run(const Grid &G, const int *start, int r, int ny, int nz,
+                                         int cx, int cy, int cz, double fx_, double fy_,
+                                         double fz_, const int k[3], const double R[2],
+                                         int &first, int &end) {
   const int nc0 = G.nc[0], nc1 = G.nc[1], nc2 = G.nc[2];
   const int part = r & 1;
   int q = r >> 1;
@@ -976,15 +1239,28 @@ __device__ __forceinline__ void search_box_run(const Grid &G, const int *start, 
   q /= ny;
   const int iz = q % nz;
   const int layer = q / nz;
+  first = end = 0;
   const bool fx = 2 * k[0] + 1 >= nc0, fy = 2 * k[1] + 1 >= nc1, fz = 2 * k[2] + 1 >= nc2;
-  const int z = fz ? iz : (cz - k[2] + iz + nc2) % nc2;
-  const int y = fy ? iy : (cy - k[1] + iy + nc1) % nc1;
+  const double eta0 = 1e-9 * G.h[0], eta1 = 1e-9 * G.h[1], eta2 = 1e-9 * G.h[2];
+  const int oy = iy - k[1], oz = iz - k[2];
+  const double gy = fy ? 0.0 : face_gap(oy, fy_, G.h[1], eta1);
+  const double gz = fz ? 0.0 : face_gap(oz, fz_, G.h[2], eta2);
+  const double Rl = R[layer];
+  const double rest = Rl * Rl - (gy * gy + gz * gz);
+  if (!(rest >= 0.0)) return;
+  const int z = fz ? iz : (cz + oz + nc2) % nc2;
+  const int y = fy ? iy : (cy + oy + nc1) % nc1;
   const int row = (layer ? G.layer2 : 0) + (z * nc1 + y) * nc0;
-  int xa = 0, xb = 0;  // cells [xa, xb) of the row
+  int xa = 0, xb = 0;  // cells [xa, xb) of the row, in offsets when not wrapping the axis
   if (fx) {
     if (!part) xb = nc0;
   } else {
-    const int x0 = cx - k[0], x1 = cx + k[0];
+    // x offsets whose cells come within the remaining distance
+    const double ext = __builtin_sqrt(rest) * (1.0 + 1e-9) + eta0;
+    int o0 = -k[0], o1 = k[0];
+    while (o0 < 0 && face_gap(o0, fx_, G.h[0], 0.0) > ext) ++o0;
+    while (o1 > 0 && face_gap(o1, fx_, G.h[0], 0.0) > ext) --o1;
+    const int x0 = cx + o0, x1 = cx + o1;
     if (x0 < 0) {
       xa = part ? 0 : x0 + nc0;
       xb = part ? x1 + 1 : nc0;
@@ -999,20 +1275,21 @@ __device__ __forceinline__ void search_box_run(const Grid &G, const int *start, 
   if (xb > xa) {
     first = start[row + xa];
     end = start[row + xb];
-  } else {
-    first = end = 0;
   }
 }
 
 // a5 for the spheres of large extent (second layer of a split grid): one wave
-// per sphere p tests every sphere of its search box exactly (rule 1 with the
-// canonical minimum image): all of the first layer, and in the second layer
-// only spheres after p, so each pair of large-extent spheres is tested once.
-// Pairs of two first-layer spheres belong to k_detect_half.  Contacts go to
-// both spheres' slots as there.  The lanes first fetch up to 64 runs of the
-// box at once and scan their lengths; then each lane takes every 64th
+// per sphere p tests every sphere that can touch it exactly (rule 1 with the
+// canonical minimum image): of the first layer, those within p's extent plus
+// rho_c (their extents are at most rho_c); of the second layer, those after p
+// within p's extent plus the largest extent, so each pair of large-extent
+// spheres is tested once.  Pairs of two first-layer spheres belong to
+// k_detect_half.  The lanes first fetch up to 64 row runs of the ball-pruned
+// search box at once and scan their lengths; then each lane takes every 64th
 // candidate of the concatenated runs, finding its run by a binary search over
-// the scanned lengths held across the wave.
+// the scanned lengths held across the wave.  An FMA pre-filter (tolerance for
+// the full reach) keeps the exact rule for the few pairs that may touch;
+// survivors are decided at once (they are rare).
 __global__ __launch_bounds__(256) void k_detect_wide(DetectArgs A, int first, int count) {
   const int lane = __lane_id();
   const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
@@ -1022,18 +1299,21 @@ __global__ __launch_bounds__(256) void k_detect_wide(DetectArgs A, int first, in
   for (int w = wid; w < count; w += nw) {
     const int p = first + w;
     const Rec a = A.rec[p];
+    const double ea = extent(a.r, a.vx, a.vy, a.vz, A.dt);
+    const double R[2] = {(ea + A.rho_c) * (1.0 + 1e-9), (ea + G.rho_max) * (1.0 + 1e-9)};
     int k[3];
-    search_radius(G, a, A.dt, k);
+    for (int ax = 0; ax < 3; ++ax) k[ax] = (int)ceil(R[1] / G.h[ax]);
     const int cx = cell_coord(a.x, G.inv_h[0], G.nc[0]);
     const int cy = cell_coord(a.y, G.inv_h[1], G.nc[1]);
     const int cz = cell_coord(a.z, G.inv_h[2], G.nc[2]);
+    const double fx_ = a.x - cx * G.h[0], fy_ = a.y - cy * G.h[1], fz_ = a.z - cz * G.h[2];
     const int ny = 2 * k[1] + 1 >= G.nc[1] ? G.nc[1] : 2 * k[1] + 1;
     const int nz = 2 * k[2] + 1 >= G.nc[2] ? G.nc[2] : 2 * k[2] + 1;
     const int nruns = 2 * 2 * ny * nz;
     for (int rb = 0; rb < nruns; rb += WAVE) {
       int s0 = 0, s1 = 0;
       if (rb + lane < nruns) {
-        search_box_run(G, A.start, rb + lane, ny, nz, cx, cy, cz, k, s0, s1);
+        wide_run(G, A.start, rb + lane, ny, nz, cx, cy, cz, fx_, fy_, fz_, k, R, s0, s1);
         if ((((rb + lane) >> 1) / (ny * nz)) == 1) {  // second layer: only j after p
           s0 = s0 > p + 1 ? s0 : p + 1;
           s1 = s1 > s0 ? s1 : s0;
@@ -1058,9 +1338,20 @@ __global__ __launch_bounds__(256) void k_detect_wide(DetectArgs A, int first, in
         }
         const int j = __shfl(s0, l) + (v - __shfl(excl, l));
         if (v < total) {
-          double t;
           ++tests;
-          if (pair_time(a, A.rec[j], G, A.dt, t)) record_contact(A, p, j, t);
+          const Rec b = A.rec[j];
+          const double d0 = wrap_sep(b.x - a.x, G.L[0], G.halfL[0]);
+          const double d1 = wrap_sep(b.y - a.y, G.L[1], G.halfL[1]);
+          const double d2 = wrap_sep(b.z - a.z, G.L[2], G.halfL[2]);
+          const double u0 = b.vx - a.vx, u1 = b.vy - a.vy, u2 = b.vz - a.vz;
+          const double s = a.r + b.r;
+          const double bf = __builtin_fma(d0, u0, __builtin_fma(d1, u1, d2 * u2));
+          const double cf =
+              __builtin_fma(d0, d0, __builtin_fma(d1, d1, __builtin_fma(d2, d2, -(s * s))));
+          double t;
+          if (__builtin_fma(bf, A.dt2, cf) <= A.tol_wide &&
+              contact_time(d0, d1, d2, u0, u1, u2, s, A.dt, t))
+            record_contact(A, p, j, t);
         }
       }
     }
@@ -1099,7 +1390,7 @@ __global__ __launch_bounds__(256) void k_gather_exact(const int *list, int nlist
   const int count = nlist_dev ? (int)*nlist_dev : nlist;
   for (int w = wid; w < count; w += nw) {
     const int i = list ? list[w] : w;
-    if (!list && select >= 0 && status[i] != (uint8_t)select) continue;
+    if (select >= 0 && status[i] != (uint8_t)select) continue;
     // the sphere's grid: the single one, or its box's in the batched form
     const int bx = B.gtab ? B.sbox[i] : 0;
     const Grid G = B.gtab ? B.gtab[bx] : G0;
@@ -1177,11 +1468,14 @@ __global__ __launch_bounds__(256) void k_resolve_sweep(int n, const Rec *rec, Gr
                                                        double e, const int *key_j,
                                                        const double *key_t, uint8_t *status,
                                                        const int *perm, OutRec *out,
-                                                       SweepCounters *ctr, BatchDev B) {
+                                                       SweepCounters *ctr, BatchDev B,
+                                                       const int *list, int nlist) {
   if (B.flags && (B.flags[FLAG_ERR] || B.flags[FLAG_DONE])) return;
-  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int ti = blockIdx.x * 256 + threadIdx.x;
+  const bool valid = list ? ti < nlist : ti < n;
+  const int i = list && valid ? list[ti] : ti;
   unsigned long long npair = 0ull;
-  if (i < n && status[i] == ST_ACTIVE) {
+  if (valid && status[i] == ST_ACTIVE) {
     const int p = key_j[i];
     if (p < 0) {
       status[i] = ST_FREE;
@@ -1221,69 +1515,106 @@ __global__ __launch_bounds__(256) void k_resolve_sweep(int n, const Rec *rec, Gr
 hipError_t launch_resolve_sweep(hipStream_t s, int n, const Rec *rec, const Grid &G, double dt,
                                 double e, const int *key_j, const double *key_t, uint8_t *status,
                                 const int *perm, OutRec *out, SweepCounters *ctr,
-                                const BatchDev *B) {
-  if (n <= 0) return hipSuccess;
+                                const BatchDev *B, const int *list, int nlist) {
+  const int items = list ? nlist : n;
+  if (items <= 0) return hipSuccess;
   BatchDev none{};
-  hipLaunchKernelGGL(k_resolve_sweep, dim3((n + 255) / 256), dim3(256), 0, s, n, rec, G, dt, e,
-                     key_j, key_t, status, perm, out, ctr, B ? *B : none);
+  hipLaunchKernelGGL(k_resolve_sweep, dim3((items + 255) / 256), dim3(256), 0, s, n, rec, G, dt,
+                     e, key_j, key_t, status, perm, out, ctr, B ? *B : none, list, nlist);
   return hipGetLastError();
 }
 
-// rule 5 in cell-sorted order: spheres that did not collide fly the whole step
-__global__ __launch_bounds__(256) void k_advance_sorted(int n, const Rec *rec,
-                                                        const uint8_t *status, double dt, Grid G0,
-                                                        OutRec *out, BatchDev B) {
-  if (B.flags && (B.flags[FLAG_ERR] || B.flags[FLAG_UNFINISHED])) return;
+// The spheres a sweep left ACTIVE or DIRTY, in sorted order, as a list for the
+// later sweeps (the others are done for the step): per-workgroup counts, an
+// exclusive scan of the counts (launch_scan), then each workgroup writes its
+// spheres from its offset.  No shared counter.
+__global__ __launch_bounds__(256) void k_keep_count(const uint8_t *status, int n, int *count) {
   const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= n || status[i] == ST_COLLIDED) return;
-  const Rec a = rec[i];
-  const Grid G = B.gtab ? B.gtab[B.sbox[i]] : G0;
-  OutRec o;
-  o.x = wrap_pos(a.x + dt * a.vx, G.L[0]);
-  o.y = wrap_pos(a.y + dt * a.vy, G.L[1]);
-  o.z = wrap_pos(a.z + dt * a.vz, G.L[2]);
-  o.vx = a.vx;
-  o.vy = a.vy;
-  o.vz = a.vz;
-  o.t = __longlong_as_double(0x7ff8000000000000LL);  // NaN: no collision
-  o.partner = -1;
-  o.pad = 0;
-  out[i] = o;
+  const bool keep = i < n && (status[i] == ST_ACTIVE || status[i] == ST_DIRTY);
+  __shared__ int part[256 / WAVE];
+  const int c = __popcll(__ballot(keep));
+  if (__lane_id() == 0) part[threadIdx.x / WAVE] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) count[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
 }
 
-hipError_t launch_advance_sorted(hipStream_t s, int n, const Rec *rec, const uint8_t *status,
-                                 double dt, const Grid &G, OutRec *out, const BatchDev *B) {
+__global__ __launch_bounds__(256) void k_keep_write(const uint8_t *status, int n, const int *off,
+                                                    int *list) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const bool keep = i < n && (status[i] == ST_ACTIVE || status[i] == ST_DIRTY);
+  __shared__ int part[256 / WAVE];
+  const unsigned long long m = __ballot(keep);
+  const int w = threadIdx.x / WAVE;
+  if (__lane_id() == 0) part[w] = __popcll(m);
+  __syncthreads();
+  int base = off[blockIdx.x];
+  for (int k = 0; k < w; ++k) base += part[k];
+  if (keep) list[base + __popcll(m & ((1ull << __lane_id()) - 1ull))] = i;
+}
+
+hipError_t launch_keep_list(hipStream_t s, const uint8_t *status, int n, int *count, int *off,
+                            int *blocksum, ReachOut *scratch_out, int *list) {
   if (n <= 0) return hipSuccess;
-  BatchDev none{};
-  hipLaunchKernelGGL(k_advance_sorted, dim3((n + 255) / 256), dim3(256), 0, s, n, rec, status, dt,
-                     G, out, B ? *B : none);
+  const int nb = (n + 255) / 256;
+  hipLaunchKernelGGL(k_keep_count, dim3(nb), dim3(256), 0, s, status, n, count);
+  hipError_t e = launch_scan(s, count, nb, off, blocksum, scratch_out);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_keep_write, dim3(nb), dim3(256), 0, s, status, n, off, list);
   return hipGetLastError();
 }
 
-// end-of-step state back to the caller's order: one 64-B record gathered per
-// sphere, coalesced writes
-__global__ __launch_bounds__(256) void k_unpermute(Particles P, const int *rank, const OutRec *out,
-                                                   int *partner, double *tcoll,
-                                                   const unsigned int *flags) {
-  if (flags && (flags[FLAG_ERR] || flags[FLAG_UNFINISHED])) return;
+// a8 and the copy back: the end-of-step state of every sphere in the caller's
+// order (coalesced writes).  A sphere that collided takes the output record its
+// resolve wrote; any other flies the whole step from its start record (rule 5).
+__global__ __launch_bounds__(256) void k_finish(Particles P, const int *rank, const Rec *rec,
+                                                const uint8_t *status, const OutRec *out,
+                                                int *partner, double *tcoll, double dt, Grid G0,
+                                                BatchDev B) {
+  if (B.flags && (B.flags[FLAG_ERR] || B.flags[FLAG_UNFINISHED])) return;
   const int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (o >= P.n) return;
-  const OutRec q = out[rank[o]];
-  P.x[o] = q.x;
-  P.y[o] = q.y;
-  P.z[o] = q.z;
-  P.vx[o] = q.vx;
-  P.vy[o] = q.vy;
-  P.vz[o] = q.vz;
-  partner[o] = q.partner;
-  tcoll[o] = q.t;
+  const int q = rank[o];
+  double x, y, z, vx, vy, vz, t;
+  int pj;
+  if (status[q] == ST_COLLIDED) {
+    const OutRec r = out[q];
+    x = r.x;
+    y = r.y;
+    z = r.z;
+    vx = r.vx;
+    vy = r.vy;
+    vz = r.vz;
+    t = r.t;
+    pj = r.partner;
+  } else {
+    const Rec a = rec[q];
+    const double *L = B.gtab ? B.gtab[B.box_of[o]].L : G0.L;
+    x = wrap_pos(a.x + dt * a.vx, L[0]);
+    y = wrap_pos(a.y + dt * a.vy, L[1]);
+    z = wrap_pos(a.z + dt * a.vz, L[2]);
+    vx = a.vx;
+    vy = a.vy;
+    vz = a.vz;
+    t = __longlong_as_double(0x7ff8000000000000LL);  // NaN: no collision
+    pj = -1;
+  }
+  P.x[o] = x;
+  P.y[o] = y;
+  P.z[o] = z;
+  P.vx[o] = vx;
+  P.vy[o] = vy;
+  P.vz[o] = vz;
+  partner[o] = pj;
+  tcoll[o] = t;
 }
 
-hipError_t launch_unpermute(hipStream_t s, const Particles &P, const int *rank, const OutRec *out,
-                            int *partner, double *tcoll, const unsigned int *flags) {
+hipError_t launch_finish(hipStream_t s, const Particles &P, const int *rank, const Rec *rec,
+                         const uint8_t *status, const OutRec *out, int *partner, double *tcoll,
+                         double dt, const Grid &G, const BatchDev *B) {
   if (P.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_unpermute, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, s, P, rank,
-                     out, partner, tcoll, flags);
+  BatchDev none{};
+  hipLaunchKernelGGL(k_finish, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, s, P, rank, rec,
+                     status, out, partner, tcoll, dt, G, B ? *B : none);
   return hipGetLastError();
 }
 

@@ -57,6 +57,6 @@ def test_struct_layouts_match_header(lib):
     import paper_2501_05340_amd as pc
     o = pc.pcol_default_opts()
     assert o.cell_mult == 1.0 and o.contact_slots == 12 and o.band_rel == 1e-4
-    assert o.max_sweeps == 0 and o.fp32_filter == 0 and o.timing == 0
+    assert o.max_sweeps == 0 and o.filter == 0 and o.timing == 0
     assert ctypes.sizeof(pc.pcol_particles) == 8 + 8 * 8
     assert ctypes.sizeof(pc.pcol_box) == 24

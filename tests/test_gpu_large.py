@@ -37,7 +37,7 @@ def big():
 
 def _step(box, p0, fp32):
     p = p0.clone()
-    ctx = pc.Context(box.n, pc.pcol_default_opts(fp32_filter=fp32))
+    ctx = pc.Context(box.n, pc.pcol_default_opts(filter=fp32))
     partner = torch.empty(box.n, dtype=torch.int32, device="cuda")
     tcoll = torch.empty(box.n, dtype=torch.float64, device="cuda")
     st = pc.pcol_step(ctx, p, box.L, box.dt, box.e, partner, tcoll)
@@ -131,11 +131,12 @@ def test_16M_sampled_keys_and_step_properties(big):
     fp, _ = oracle.earliest_subset(box, probe, active=(~hit).astype(np.uint8))
     assert np.all(fp < 0)
 
-    # the FP32 filter form gives the same step bitwise
-    print("[gpu-test] 16M step, FP32 filter form", flush=True)
-    out32, partner32, tcoll32, st32 = _step(box, p0, 1)
-    assert np.array_equal(partner32, partner)
-    assert np.array_equal(tcoll32, tcoll, equal_nan=True)
-    for f in FIELDS:
-        assert np.array_equal(out32[f].view(np.uint64), out[f].view(np.uint64))
-    assert st32["n_recheck"] > 0
+    # the binary32 and Gram filter forms give the same step bitwise
+    for flt in (1, 2):
+        print(f"[gpu-test] 16M step, filter {flt}", flush=True)
+        out32, partner32, tcoll32, st32 = _step(box, p0, flt)
+        assert np.array_equal(partner32, partner)
+        assert np.array_equal(tcoll32, tcoll, equal_nan=True)
+        for f in FIELDS:
+            assert np.array_equal(out32[f].view(np.uint64), out[f].view(np.uint64))
+        assert st32["n_recheck"] > 0
