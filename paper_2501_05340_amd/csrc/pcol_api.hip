@@ -52,10 +52,8 @@ struct pcol_ctx {
   double *tcoll_tmp = nullptr;
   ReachOut *reach_d = nullptr;
   SweepCounters *ctr_d = nullptr;
-  unsigned long long *tests_d = nullptr;
   ReachOut *reach_h = nullptr;
   SweepCounters *ctr_h = nullptr;
-  unsigned long long *tests_h = nullptr;
   hipEvent_t ev[8] = {};
 
   bool binned = false;
@@ -217,12 +215,11 @@ void pcol_destroy(pcol_ctx *ctx) {
                  ctx->count,  ctx->start,  ctx->blocksum, ctx->cnt,      ctx->slot_t,
                  ctx->slot_j, ctx->key_j,  ctx->key_t,  ctx->status,      ctx->out,
                  ctx->ovf,    ctx->partner_tmp, ctx->tcoll_tmp, ctx->list_a, ctx->keep_cnt, ctx->keep_off, ctx->keep_bs,
-                 ctx->reach_d, ctx->ctr_d, ctx->tests_d};
+                 ctx->reach_d, ctx->ctr_d};
   for (void *p : dev)
     if (p) (void)hipFree(p);
   if (ctx->reach_h) (void)hipHostFree(ctx->reach_h);
   if (ctx->ctr_h) (void)hipHostFree(ctx->ctr_h);
-  if (ctx->tests_h) (void)hipHostFree(ctx->tests_h);
   if (ctx->wide_h) (void)hipHostFree(ctx->wide_h);
   if (ctx->nlist_h) (void)hipHostFree(ctx->nlist_h);
   for (hipEvent_t &e : ctx->ev)
@@ -286,10 +283,8 @@ pcol_status pcol_create(pcol_ctx **out, int64_t n_max, void *hip_stream, const p
   A(dalloc(&ctx->tcoll_tmp, n));
   A(dalloc(&ctx->reach_d, 1));
   A(dalloc(&ctx->ctr_d, 1));
-  A(dalloc(&ctx->tests_d, 1));
   if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->reach_h, sizeof(ReachOut));
   if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->ctr_h, sizeof(SweepCounters));
-  if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->tests_h, sizeof(unsigned long long));
   if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->wide_h, 2 * sizeof(int));
   if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->nlist_h, sizeof(int));
   for (hipEvent_t &ev : ctx->ev)
@@ -528,6 +523,7 @@ static pcol_status detect_all(pcol_ctx *ctx, double dt) {
     A.rec32 = ctx->rec32;
     A.fp32 = ctx->opts.filter == 1;
     A.gram = ctx->opts.filter == 2;
+    A.crowd = ctx->count;  // free after the binning
     A.tolg = A.gram ? gram_tolerance(ctx, A.dt2) : 0.0f;
     // the FP32 filter reads its home records from an LDS copy of the home cell
     // (when the largest cell fits in 20 KB); the FP64 filter reads them through
@@ -631,7 +627,7 @@ pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, dou
   double *tc = tcoll ? tcoll : ctx->tcoll_tmp;
   const Particles P = to_dev(p);
   int64_t pairs = 0, sweeps = 0, ovf_total = 0;
-  unsigned long long contacts = 0ull, recheck = 0ull, wide_tests = 0ull;
+  unsigned long long contacts = 0ull, recheck = 0ull, tests = 0ull;
   double ms_detect = 0.0;
   if (n > 0) {
     PCOL_HIP(launch_fill_u8(s, ctx->status, ST_ACTIVE, n));
@@ -664,7 +660,7 @@ pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, dou
         contacts = sc / 2ull;
         for (int k = 0; k < NSHARD; ++k) {
           recheck += ctx->ctr_h->shard[k].recheck;
-          wide_tests += ctx->ctr_h->shard[k].tests;
+          tests += ctx->ctr_h->shard[k].tests;
         }
       }
       ovf_total += ctx->ctr_h->n_overflow;
@@ -719,14 +715,7 @@ pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, dou
     stats->reach = ctx->reach;
     stats->n_wide = ctx->n_wide;
     stats->rho_c = ctx->split ? ctx->rho_c : 0.0;
-    if (n > 0 && !ctx->small) {
-      PCOL_HIP(hipMemsetAsync(ctx->tests_d, 0, sizeof(unsigned long long), s));
-      PCOL_HIP(launch_count_pairs(s, ctx->start, ctx->G, ctx->tests_d));
-      PCOL_HIP(hipMemcpyAsync(ctx->tests_h, ctx->tests_d, sizeof(unsigned long long),
-                              hipMemcpyDeviceToHost, s));
-      PCOL_HIP(hipStreamSynchronize(s));
-      stats->pair_tests = (int64_t)*ctx->tests_h + (int64_t)wide_tests;
-    }
+    stats->pair_tests = (int64_t)tests;
     if (timing && n > 0) {
       stats->ms_bin = ms_between(ctx->ev[0], ctx->ev[1]);
       stats->ms_detect = ms_detect;

@@ -97,7 +97,7 @@ struct alignas(128) CounterShard {
 struct SweepCounters {
   CounterShard shard[NSHARD];
   unsigned int n_overflow;  // spheres with more contacts than slots (list length)
-  unsigned int n_list;      // length of a list built on the device (public detect)
+  unsigned int n_crowd;     // cells queued for the binary64 filter by the Gram kernel
   unsigned int pad[30];
 };
 
@@ -233,6 +233,7 @@ struct DetectArgs {
   float dt2f;         // FP32 filter: 2 dt (1 + 2^-12)
   int gram;           // half-precision Gram filter on the matrix cores + FP64 recheck
   float tolg;         // its tolerance (bound on its rounding, see gram_tolerance)
+  int *crowd;         // Gram filter: cells of more than GRAM_ROWS spheres, for the FP64 filter
 };
 
 hipError_t launch_fill_u32(hipStream_t s, unsigned int *p, unsigned int v, int64_t n);
@@ -250,8 +251,6 @@ hipError_t launch_scatter(hipStream_t s, const Particles &P, const Grid &G, cons
                           const int *slot, const int *start, Rec *rec, Rec32 *rec32, int *perm,
                           int *rank, const BatchDev *B);
 hipError_t launch_detect_half(hipStream_t s, const DetectArgs &A);
-hipError_t launch_count_pairs(hipStream_t s, const int *start, const Grid &G,
-                              unsigned long long *out);
 hipError_t launch_slot_min(hipStream_t s, int n, int first, const int *cnt, const double *slot_t,
                            const int *slot_j, int K, uint8_t *status, const int *perm, int *key_j,
                            double *key_t, int *ovf_list, SweepCounters *ctr,
@@ -264,7 +263,7 @@ hipError_t launch_resolve_sweep(hipStream_t s, int n, const Rec *rec, const Grid
                                 double e, const int *key_j, const double *key_t, uint8_t *status,
                                 const int *perm, OutRec *out, SweepCounters *ctr,
                                 const BatchDev *B, const int *list = nullptr, int nlist = 0);
-// list (n_list entries, read back from off[(n + 255) / 256]) of the ACTIVE or
+// list (read back from off[(n + 255) / 256] entries) of the ACTIVE or
 // DIRTY spheres; count and off need (n + 255) / 256 + 1 entries, blocksum
 // ((n + 255) / 256) / 4096 + 2
 hipError_t launch_keep_list(hipStream_t s, const uint8_t *status, int n, int *count, int *off,

@@ -269,7 +269,13 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_blocks(const int *count, int n,
     const int t = __shfl_xor(mx, o);
     mx = t > mx ? t : mx;
   }
-  if (__lane_id() == 0) atomicMax(&out->maxcell, (unsigned int)mx);
+  __shared__ int wmax[SCAN_T / WAVE];
+  if (__lane_id() == 0) wmax[threadIdx.x / WAVE] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < SCAN_T / WAVE; ++k) mx = wmax[k] > mx ? wmax[k] : mx;
+    atomicMax(&out->maxcell, (unsigned int)mx);
+  }
 }
 
 // exclusive scan of the block sums in place (one block, chunks of SCAN_T)
@@ -434,6 +440,7 @@ struct SurvivorQueue {
   int n;                // entries waiting (wave-uniform)
   unsigned int pushed;  // survivors seen (wave-uniform)
   int cap;
+  unsigned long long tests;  // unordered pairs tested (wave-uniform)
 };
 
 // The rule for every queued pair (rule 1 with the canonical minimum image,
@@ -721,6 +728,9 @@ __device__ __forceinline__ void detect_cell(const DetectArgs &A, const Grid &G, 
     pre[k] = total;
     total += rl[k];
   }
+  // unordered pairs this cell tests: own cell pairs once, every home against the rest
+  Q.tests += (unsigned long long)(h1 - h0) * (unsigned long long)(total - (h1 - h0)) +
+             (unsigned long long)(h1 - h0) * (unsigned long long)(h1 - h0 - 1) / 2ull;
 
   const int lane = __lane_id();
   for (int base = 0; base < total; base += WAVE) {
@@ -805,10 +815,13 @@ template <bool FP32, bool LDSI>
 __global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
   extern __shared__ double4 lds_raw[];  // LDSI: the home cell's records (Rec or Rec32)
   __shared__ int2 survq[QCAP];
-  SurvivorQueue Q{survq, 0, 0u, QCAP};
+  SurvivorQueue Q{survq, 0, 0u, QCAP, 0ull};
   detect_cell<FP32, LDSI>(A, A.G, A.start, xcd_remap(blockIdx.x, gridDim.x), Q, lds_raw);
-  if (FP32 && __lane_id() == 0 && Q.pushed)
-    atomicAdd(&A.ctr->shard[blockIdx.x % NSHARD].recheck, (unsigned long long)Q.pushed);
+  if (__lane_id() == 0) {
+    CounterShard &sh = A.ctr->shard[blockIdx.x % NSHARD];
+    if (FP32 && Q.pushed) atomicAdd(&sh.recheck, (unsigned long long)Q.pushed);
+    if (Q.tests) atomicAdd(&sh.tests, Q.tests);
+  }
 }
 
 // ---------------------------------------------------------------- a5, Gram filter on the matrix cores
@@ -859,8 +872,8 @@ __device__ __forceinline__ void detect_cell_gram(const DetectArgs &A, const Grid
   CellRuns R;
   if (!cell_runs(G, start, cell, R)) return;
   const int h0 = R.h0, h1 = R.h1, nh = h1 - h0;
-  if (nh > GRAM_ROWS) {  // a crowded cell: the binary64 filter
-    detect_cell<false, false>(A, G, start, cell, Q, nullptr);
+  if (nh > GRAM_ROWS) {  // a crowded cell: queued for the binary64 filter (k_detect_list)
+    if (__lane_id() == 0) A.crowd[atomicAdd(&A.ctr->n_crowd, 1u)] = cell;
     return;
   }
   const int lane = __lane_id();
@@ -919,6 +932,8 @@ __device__ __forceinline__ void detect_cell_gram(const DetectArgs &A, const Grid
     pre[k] = total;
     total += R.rl[k];
   }
+  Q.tests += (unsigned long long)nh * (unsigned long long)(total - nh) +
+             (unsigned long long)nh * (unsigned long long)(nh - 1) / 2ull;
   for (int base = 0; base < total; base += WAVE) {
     // the lane's candidate, as in detect_cell
     const int v = base + lane;
@@ -1002,10 +1017,24 @@ __device__ __forceinline__ void detect_cell_gram(const DetectArgs &A, const Grid
 __global__ __launch_bounds__(WAVE) void k_detect_gram(DetectArgs A) {
   __shared__ int2 survq[2 * QCAP];
   __shared__ GramLds S;
-  SurvivorQueue Q{survq, 0, 0u, 2 * QCAP};
+  SurvivorQueue Q{survq, 0, 0u, 2 * QCAP, 0ull};
   detect_cell_gram(A, A.G, A.start, xcd_remap(blockIdx.x, gridDim.x), Q, S);
-  if (__lane_id() == 0 && Q.pushed)
-    atomicAdd(&A.ctr->shard[blockIdx.x % NSHARD].recheck, (unsigned long long)Q.pushed);
+  if (__lane_id() == 0) {
+    CounterShard &sh = A.ctr->shard[blockIdx.x % NSHARD];
+    if (Q.pushed) atomicAdd(&sh.recheck, (unsigned long long)Q.pushed);
+    if (Q.tests) atomicAdd(&sh.tests, Q.tests);
+  }
+}
+
+// The cells the Gram kernel queued as crowded, through the binary64 filter;
+// one wave per cell over the device-counted list.
+__global__ __launch_bounds__(WAVE) void k_detect_list(DetectArgs A) {
+  __shared__ int2 survq[QCAP];
+  SurvivorQueue Q{survq, 0, 0u, QCAP, 0ull};
+  const int count = (int)A.ctr->n_crowd;
+  for (int w = blockIdx.x; w < count; w += gridDim.x)
+    detect_cell<false, false>(A, A.G, A.start, A.crowd[w], Q, nullptr);
+  if (__lane_id() == 0 && Q.tests) atomicAdd(&A.ctr->shard[blockIdx.x % NSHARD].tests, Q.tests);
 }
 
 // Box of a global cell number: the last b with cell_base[b] <= c.
@@ -1033,7 +1062,7 @@ __global__ __launch_bounds__(256) void k_detect_batched(DetectArgs A, BatchDev B
   const int wave = threadIdx.x / WAVE;
   const int total = B.cell_base[B.nbox];
   const int stride = gridDim.x * wpb;
-  SurvivorQueue Q{survq[wave], 0, 0u, QCAP};
+  SurvivorQueue Q{survq[wave], 0, 0u, QCAP, 0ull};
   for (int item = blockIdx.x * wpb + wave; item < total; item += stride) {
     const int b = box_of_cell(B.cell_base, B.nbox, item);
     const Grid G = B.gtab[b];
@@ -1046,6 +1075,9 @@ hipError_t launch_detect_half(hipStream_t s, const DetectArgs &A) {
   if (A.G.ncell <= 0) return hipSuccess;
   if (A.gram) {
     hipLaunchKernelGGL(k_detect_gram, dim3(A.G.ncell), dim3(WAVE), 0, s, A);
+    // crowded cells: at most ncell, usually none (the kernel exits at once)
+    const int blocks = A.G.ncell < 1024 ? A.G.ncell : 1024;
+    hipLaunchKernelGGL(k_detect_list, dim3(blocks), dim3(WAVE), 0, s, A);
     return hipGetLastError();
   }
   const size_t lds = (size_t)A.cap * (A.fp32 ? sizeof(Rec32) : sizeof(Rec));
@@ -1063,39 +1095,6 @@ hipError_t launch_detect_half(hipStream_t s, const DetectArgs &A) {
   return hipGetLastError();
 }
 
-
-// ---------------------------------------------------------------- unordered pair count
-
-// unordered candidate pairs the half stencil tests: per cell n(n-1)/2 plus n
-// times the occupancy of its 13 forward neighbour cells
-__global__ __launch_bounds__(256) void k_count_pairs(const int *start, Grid G,
-                                                     unsigned long long *out) {
-  const int c = blockIdx.x * 256 + threadIdx.x;
-  unsigned long long acc = 0ull;
-  if (c < G.ncell) {
-    const int nc0 = G.nc[0], nc1 = G.nc[1], nc2 = G.nc[2];
-    const int cx = c % nc0, cy = (c / nc0) % nc1, cz = c / (nc0 * nc1);
-    const long long n = start[c + 1] - start[c];
-    acc = (unsigned long long)(n * (n - 1) / 2);
-    const int off[13][3] = {{1, 0, 0},  {-1, 1, 0}, {0, 1, 0},  {1, 1, 0},  {-1, -1, 1},
-                            {0, -1, 1}, {1, -1, 1}, {-1, 0, 1}, {0, 0, 1},  {1, 0, 1},
-                            {-1, 1, 1}, {0, 1, 1},  {1, 1, 1}};
-    for (int k = 0; k < 13; ++k) {
-      const int x = (cx + off[k][0] + nc0) % nc0, y = (cy + off[k][1] + nc1) % nc1,
-                z = (cz + off[k][2] + nc2) % nc2;
-      const int q = (z * nc1 + y) * nc0 + x;
-      acc += (unsigned long long)(n * (start[q + 1] - start[q]));
-    }
-  }
-  acc = wave_sum(acc);
-  if (__lane_id() == 0 && acc) atomicAdd(out, acc);
-}
-
-hipError_t launch_count_pairs(hipStream_t s, const int *start, const Grid &G,
-                              unsigned long long *out) {
-  hipLaunchKernelGGL(k_count_pairs, dim3((G.ncell + 255) / 256), dim3(256), 0, s, start, G, out);
-  return hipGetLastError();
-}
 
 // ---------------------------------------------------------------- a5/a7: partner from contact slots
 
