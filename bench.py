@@ -32,12 +32,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "pair tests/s + particles stepped/s at 16M; FP32+recheck vs FP64 at equal pair set"
-# FP64 vector operations of one pair test in the detect kernel's filter:
-# separation 3, relative velocity 3, s and s^2 2, b' (1 multiply + 2 FMA),
-# c' (3 FMA), the test c' + b' dt2 (1 FMA); the compare excluded.  An FMA is
-# one operation here (two flops): 9 plain + 6 FMA = 15 operations, 21 flops.
-OPS_PER_PAIR_TEST = 15
-FLOPS_PER_PAIR_TEST = 21
+# FP64 vector operations of one pair test in the detect kernel's filter, the
+# Gram form F = alpha_i + beta_j + <P_j, Q_i>: one add and seven FMAs (the
+# compare excluded; per-sphere terms are formed once per sphere, not per
+# pair).  An FMA is one operation here (two flops): 8 operations, 15 flops.
+OPS_PER_PAIR_TEST = 8
+FLOPS_PER_PAIR_TEST = 15
 # 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz: binary64 vector operations per
 # second (an FMA is one; the published 78.6 TFLOP/s counts it as two flops)
 PEAK_FP64_OPS = 256 * 4 * 16 * 2.4e9

@@ -462,6 +462,33 @@ static double fp32_band(const pcol_ctx *ctx, double dt) {  // returns the band
   return ctx->opts.band_rel > need ? ctx->opts.band_rel : need;
 }
 
+// Tolerance of the binary64 Gram filter (filter 0).  The filter evaluates
+// F = alpha_i + beta_j + <P_j, Q_i> from coordinates relative to the home cell
+// centre.  For a pair the rule keeps, the real F is at most E0 = 3 eps
+// ((reach^2 + (2 r_max)^2) + reach 2 v_max dt2) (the binary64 argument: the kept
+// root c / (-b + sqrt D) <= dt gives c <= 2 |b| dt (1 + 6 eps) < |b| dt2).  The
+// evaluation differs from the real F by
+//  * the relative coordinates: each is one or two roundings of values below
+//    L + h, so the separation d is off by at most delta = eps (2 (Lmax + h) + X_i +
+//    X_j), which moves F by at most delta (2 reach + 2 v_max dt2) + delta^2;
+//  * alpha, beta, Q, P (a few roundings each, <= 6 eps relative) and the eight
+//    operations of the sum (<= 8 eps of the sum of magnitudes): at most
+//    16 eps (A_ + B_ + S) with A_, B_, S the bounds of |alpha|, |beta| and
+//    sum_k |P_k Q_k| for |x_i| <= X_i = (sqrt 3 / 2) h, |x_j| <= X_i + reach.
+// The tolerance is twice the sum.
+static double gram64_tolerance(double h, double R, double V, double r, double Lmax,
+                               double dt2) {
+  const double s3 = sqrt(3.0), eps = 0x1.0p-53;
+  const double Xi = 0.5 * s3 * h * (1.0 + 1e-6), Xj = Xi + R;
+  const double Ab = Xi * Xi + dt2 * Xi * V + r * r, Bb = Xj * Xj + dt2 * Xj * V + r * r;
+  const double S = Xj * (2.0 * Xi + dt2 * V) + V * dt2 * Xi + 2.0 * r * r;
+  const double E0 = 3.0 * eps * ((R * R + 4.0 * r * r) + R * 2.0 * V * dt2);
+  const double delta = eps * (2.0 * (Lmax + h) + Xi + Xj);
+  const double Epos = delta * (2.0 * R + 2.0 * V * dt2) + delta * delta;
+  const double E = 16.0 * eps * (Ab + Bb + S);
+  return 2.0 * (E0 + Epos + E);
+}
+
 // Tolerance of the Gram filter (filter 2).  For a pair the rule keeps, the
 // real value F = c + b dt2 is at most E0 = 3 eps ((reach^2 + (2 r_max)^2) +
 // reach 2 v_max dt2) (the binary64 argument of the FMA filter), so the filter
@@ -514,6 +541,12 @@ static pcol_status detect_all(pcol_ctx *ctx, double dt) {
       // differences between the filter's FMA values and the rule's b, c (pair64)
       const double R = ctx->reach_pass, smax = 2.0 * ctx->rmax_pass;
       A.tol = 16.0 * 0x1.0p-53 * (R * R + smax * smax + R * 2.0 * ctx->vmax_pass * A.dt2);
+      double h = ctx->h[0], Lmax = ctx->G.L[0];
+      for (int a = 1; a < 3; ++a) {
+        h = ctx->h[a] > h ? ctx->h[a] : h;
+        Lmax = ctx->G.L[a] > Lmax ? ctx->G.L[a] : Lmax;
+      }
+      A.tol64 = gram64_tolerance(h, R, ctx->vmax_pass, ctx->rmax_pass, Lmax, A.dt2);
       // pairs with a sphere above the split extent: |d| up to the full reach
       const double Rw = ctx->reach, sw = 2.0 * ctx->rmax;
       A.tol_wide = 16.0 * 0x1.0p-53 * (Rw * Rw + sw * sw + Rw * 2.0 * ctx->vmax * A.dt2);
@@ -944,6 +977,13 @@ static pcol_status batch_enqueue(pcol_ctx *ctx, hipStream_t s, const Particles &
   for (const Grid &G : bp->gtab_h)
     for (int a = 0; a < 3; ++a) hmax = G.h[a] > hmax ? G.h[a] : hmax;
   A.tol = 16.0 * 0x1.0p-53 * hmax * hmax * (2.0 + A.dt2 / dt);
+  {
+    // reach <= hmax, 2 r_max <= hmax and 2 v_max dt <= hmax in every box (see above)
+    double Lmax = 0.0;
+    for (const Grid &G : bp->gtab_h)
+      for (int a = 0; a < 3; ++a) Lmax = G.L[a] > Lmax ? G.L[a] : Lmax;
+    A.tol64 = gram64_tolerance(hmax, hmax, hmax / (2.0 * dt), 0.5 * hmax, Lmax, A.dt2);
+  }
   A.K = ctx->K;
   A.cap = 0;
   A.fp32 = 0;

@@ -222,7 +222,8 @@ struct DetectArgs {
   Grid G;
   double dt;
   double dt2;         // 2 dt (1 + 2^-20): step bound of the FP64 filter
-  double tol;         // FP64 filter tolerance (bound on FMA-vs-rule rounding differences)
+  double tol;         // binary32 filter: unused; kept for the FMA form's bound
+  double tol64;       // binary64 Gram filter tolerance (see gram64_tolerance)
   double tol_wide;    // the same for pairs with a sphere above the split extent (full reach)
   double rho_c;       // split extent (first-layer spheres have extent <= rho_c)
   int K;

@@ -476,71 +476,6 @@ __device__ __forceinline__ bool push_survivor(bool pass, int i, int g, SurvivorQ
   return true;
 }
 
-// One home sphere (wave-uniform) against the lane's candidate.
-//
-// Filter: b' = d.u and c' = |d|^2 - s^2 by FMA chains (not the rule's operation
-// order), pass iff  c' + b' dt2 <= tol.  For a pair the rule keeps, c <= 2|b| dt
-// (1 + 6 eps) (the kept root is c / (-b + sqrt(D)) >= c / (2|b|)), and the FMA
-// values differ from the rule's b, c by at most 7 eps (|d|^2 + s^2) and
-// 7 eps |d| |u|; tol (set by the host from the reach, the largest radius and
-// speed) bounds those differences for |d| <= reach, so every kept pair passes.
-// Passing pairs are then decided by the rule itself (queued, or at once), so
-// the result is exactly the rule's.
-template <bool SHIFT, bool MASK>
-__device__ __forceinline__ void pair64(const DetectArgs &A, const Rec &b, int g, int thr, double sx,
-                                       double sy, double sz, int i, double xi, double yi,
-                                       double zi, double ri, double vxi, double vyi, double vzi,
-                                       SurvivorQueue &Q) {
-  double d0 = b.x - xi, d1 = b.y - yi, d2 = b.z - zi;
-  if (SHIFT) {
-    d0 = d0 + sx;
-    d1 = d1 + sy;
-    d2 = d2 + sz;
-  }
-  const double u0 = b.vx - vxi, u1 = b.vy - vyi, u2 = b.vz - vzi;
-  const double s = ri + b.r;
-  const double ss = s * s;
-  const double bf = __builtin_fma(d0, u0, __builtin_fma(d1, u1, d2 * u2));
-  const double cf = __builtin_fma(d0, d0, __builtin_fma(d1, d1, __builtin_fma(d2, d2, -ss)));
-  // in own-cell chunks only j > i is a candidate (thr = j there, INT_MAX elsewhere)
-  const bool pass = (!MASK || i < thr) && __builtin_fma(bf, A.dt2, cf) <= A.tol;
-  if (!push_survivor(pass, i, g, Q) && pass) {
-    double t;
-    if (contact_time(d0, d1, d2, u0, u1, u2, s, A.dt, t)) record_contact(A, i, g, t);
-  }
-}
-
-// The lane's candidate j against every home sphere i in [h0, h1).  The home
-// records come either from the wave's LDS copy of the home cell (broadcast
-// reads, HP = const Rec *) or through the constant address space (scalar loads,
-// HP = crec_ptr); the loop is unrolled by two and walks a pointer, so the
-// scalar instructions per pair stay few (the scalar pipe issues at the VALU's
-// rate).
-template <bool SHIFT, bool MASK, typename HP>
-__device__ __forceinline__ void detect_chunk(const DetectArgs &A, HP p, int h0, int h1, int g,
-                                             int thr, double sx, double sy, double sz,
-                                             SurvivorQueue &Q) {
-  Rec b;
-  if (thr >= 0) {
-    b = A.rec[g];
-  } else {
-    b.x = b.y = b.z = FAR_AWAY;
-    b.vx = b.vy = b.vz = 0.0;
-    b.r = 0.0;
-    b.m = 1.0;
-  }
-  int i = h0;
-  for (; i + 1 < h1; i += 2, p += 2) {
-    pair64<SHIFT, MASK>(A, b, g, thr, sx, sy, sz, i, p[0].x, p[0].y, p[0].z, p[0].r, p[0].vx,
-                        p[0].vy, p[0].vz, Q);
-    pair64<SHIFT, MASK>(A, b, g, thr, sx, sy, sz, i + 1, p[1].x, p[1].y, p[1].z, p[1].r, p[1].vx,
-                        p[1].vy, p[1].vz, Q);
-  }
-  if (i < h1)
-    pair64<SHIFT, MASK>(A, b, g, thr, sx, sy, sz, i, p[0].x, p[0].y, p[0].z, p[0].r, p[0].vx,
-                        p[0].vy, p[0].vz, Q);
-}
-
 // One home sphere (FP32 record in scalar registers) against the lane's
 // candidate: the same filter in binary32 with the contact distance inflated by
 // the band; survivors are decided by the binary64 rule (queued, or at once
@@ -747,8 +682,6 @@ __device__ __forceinline__ void detect_cell(const DetectArgs &A, const Grid &G, 
     }
     const bool own = (code >> 6) & 1;
     const int thr = !ok ? -1 : (own ? g : 0x7fffffff);
-    const double sx = code_shift(code & 3, G.L[0]), sy = code_shift((code >> 2) & 3, G.L[1]),
-                 sz = code_shift((code >> 4) & 3, G.L[2]);
     if (FP32) {
       const double ox = (cx + 0.5) * G.h[0], oy = (cy + 0.5) * G.h[1], oz = (cz + 0.5) * G.h[2];
       if (LDSI) {
@@ -778,34 +711,142 @@ __device__ __forceinline__ void detect_cell(const DetectArgs &A, const Grid &G, 
             detect_chunk32<false, false>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, Q);
         }
       }
-      continue;
     }
-    if (LDSI) {
-      const Rec *p = (const Rec *)lds_raw;
-      if (base < rl[0]) {  // chunk holds own-cell candidates
-        if (any_shift)
-          detect_chunk<true, true>(A, p, h0, h1, g, thr, sx, sy, sz, Q);
-        else
-          detect_chunk<false, true>(A, p, h0, h1, g, thr, 0.0, 0.0, 0.0, Q);
-      } else {
-        if (any_shift)
-          detect_chunk<true, false>(A, p, h0, h1, g, thr, sx, sy, sz, Q);
-        else
-          detect_chunk<false, false>(A, p, h0, h1, g, thr, 0.0, 0.0, 0.0, Q);
+  }
+  flush_survivors(A, G, Q);
+}
+
+// ---------------------------------------------------------------- a5, binary64 Gram filter
+
+// The binary64 filter in Gram form.  With positions relative to the home cell
+// centre o, F = |d|^2 - s^2 + dt2 (d . u) = alpha_i + beta_j + <P_j, Q_i> where
+//   P_j = (x_j, v_j, r_j),  Q_i = (-2 x_i - dt2 v_i, -dt2 x_i, -2 r_i),
+//   alpha_i = |x_i|^2 + dt2 x_i.v_i - r_i^2,  beta_j = |x_j|^2 + dt2 x_j.v_j - r_j^2
+// (d = x_j - x_i, u = v_j - v_i, s = r_i + r_j).  Q_i and alpha_i are formed once
+// per home sphere into LDS, P_j and beta_j once per candidate and chunk (the
+// run's periodic shift applied), so a pair costs one add and seven FMAs.  A
+// pair passes iff F <= tol64, a bound on the rounding of this evaluation and of
+// the relative coordinates for pairs the rule can keep (host, gram64_tolerance);
+// survivors are decided by the rule (flush_survivors), so the result is exactly
+// the rule's.
+struct alignas(16) HomeQ {
+  double q[7];
+  double alpha;
+};
+
+// Pair tests of one candidate chunk against a batch of homes, two homes per
+// step; a survivor that finds the queue full is decided at once.
+template <bool MASK>
+__device__ __forceinline__ void detect_chunk64(const DetectArgs &A, const Grid &G, const HomeQ *hq,
+                                               int nb, int i0, int g, int thr, const double P[7],
+                                               double beta, SurvivorQueue &Q) {
+  int k = 0;
+  for (; k + 1 < nb; k += 2) {
+    const HomeQ a = hq[k], b = hq[k + 1];
+    double t0 = a.alpha + beta, t1 = b.alpha + beta;
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+      t0 = __builtin_fma(P[c], a.q[c], t0);
+      t1 = __builtin_fma(P[c], b.q[c], t1);
+    }
+    const int i = i0 + k;
+    const bool p0 = t0 <= A.tol64 && (!MASK || i < thr);
+    const bool p1 = t1 <= A.tol64 && (!MASK || i + 1 < thr);
+    if (!push_survivor(p0, i, g, Q) && p0) {
+      double t;
+      if (pair_time(A.rec[i], A.rec[g], G, A.dt, t)) record_contact(A, i, g, t);
+    }
+    if (!push_survivor(p1, i + 1, g, Q) && p1) {
+      double t;
+      if (pair_time(A.rec[i + 1], A.rec[g], G, A.dt, t)) record_contact(A, i + 1, g, t);
+    }
+  }
+  if (k < nb) {
+    const HomeQ a = hq[k];
+    double t0 = a.alpha + beta;
+#pragma unroll
+    for (int c = 0; c < 7; ++c) t0 = __builtin_fma(P[c], a.q[c], t0);
+    const int i = i0 + k;
+    const bool p0 = t0 <= A.tol64 && (!MASK || i < thr);
+    if (!push_survivor(p0, i, g, Q) && p0) {
+      double t;
+      if (pair_time(A.rec[i], A.rec[g], G, A.dt, t)) record_contact(A, i, g, t);
+    }
+  }
+}
+
+// Pair tests of one home cell with the binary64 Gram filter; homes in batches
+// of 64 (hq holds one batch), candidates in chunks of 64 lanes.
+__device__ __forceinline__ void detect_cell64(const DetectArgs &A, const Grid &G, const int *start,
+                                              int cell, SurvivorQueue &Q, HomeQ *hq) {
+  CellRuns R;
+  if (!cell_runs(G, start, cell, R)) return;
+  const int h0 = R.h0, h1 = R.h1, nh = h1 - h0;
+  int total = 0;
+  int pre[MAXRUN];
+#pragma unroll
+  for (int k = 0; k < MAXRUN; ++k) {
+    pre[k] = total;
+    total += R.rl[k];
+  }
+  Q.tests += (unsigned long long)nh * (unsigned long long)(total - nh) +
+             (unsigned long long)nh * (unsigned long long)(nh - 1) / 2ull;
+  const int lane = __lane_id();
+  const double ox = (R.cx + 0.5) * G.h[0], oy = (R.cy + 0.5) * G.h[1], oz = (R.cz + 0.5) * G.h[2];
+  const double dt2 = A.dt2;
+  for (int hb = 0; hb < nh; hb += WAVE) {
+    const int nb = nh - hb < WAVE ? nh - hb : WAVE;
+    if (lane < nb) {  // this batch's home terms (one wave owns hq: in-order LDS)
+      const Rec a = A.rec[h0 + hb + lane];
+      const double xh = a.x - ox, yh = a.y - oy, zh = a.z - oz;
+      HomeQ h;
+      h.q[0] = -2.0 * xh - dt2 * a.vx;
+      h.q[1] = -2.0 * yh - dt2 * a.vy;
+      h.q[2] = -2.0 * zh - dt2 * a.vz;
+      h.q[3] = -dt2 * xh;
+      h.q[4] = -dt2 * yh;
+      h.q[5] = -dt2 * zh;
+      h.q[6] = -2.0 * a.r;
+      h.alpha = ((xh * xh + yh * yh) + zh * zh) + dt2 * ((xh * a.vx + yh * a.vy) + zh * a.vz) -
+                a.r * a.r;
+      hq[lane] = h;
+    }
+    for (int base = 0; base < total; base += WAVE) {
+      const int v = base + lane;
+      int g = 0, code = run_code(0, 0, 0, 0);
+      bool ok = false;
+#pragma unroll
+      for (int k = 0; k < MAXRUN; ++k) {
+        if (v >= pre[k] && v < pre[k] + R.rl[k]) {
+          g = R.rg[k] + (v - pre[k]);
+          code = R.rc[k];
+          ok = true;
+        }
       }
-    } else {
-      const crec_ptr p = (crec_ptr)A.rec + h0;
-      if (base < rl[0]) {
-        if (any_shift)
-          detect_chunk<true, true>(A, p, h0, h1, g, thr, sx, sy, sz, Q);
-        else
-          detect_chunk<false, true>(A, p, h0, h1, g, thr, 0.0, 0.0, 0.0, Q);
-      } else {
-        if (any_shift)
-          detect_chunk<true, false>(A, p, h0, h1, g, thr, sx, sy, sz, Q);
-        else
-          detect_chunk<false, false>(A, p, h0, h1, g, thr, 0.0, 0.0, 0.0, Q);
+      const bool own = (code >> 6) & 1;
+      const int thr = !ok ? -1 : (own ? g : 0x7fffffff);
+      double P[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      double beta = 1e300;  // no candidate: never passes
+      if (thr >= 0) {
+        const Rec b = A.rec[g];
+        const double xj = (b.x + code_shift(code & 3, G.L[0])) - ox;
+        const double yj = (b.y + code_shift((code >> 2) & 3, G.L[1])) - oy;
+        const double zj = (b.z + code_shift((code >> 4) & 3, G.L[2])) - oz;
+        P[0] = xj;
+        P[1] = yj;
+        P[2] = zj;
+        P[3] = b.vx;
+        P[4] = b.vy;
+        P[5] = b.vz;
+        P[6] = b.r;
+        beta = ((xj * xj + yj * yj) + zj * zj) + dt2 * ((xj * b.vx + yj * b.vy) + zj * b.vz) -
+               b.r * b.r;
       }
+      // own-cell candidates (the first rl[0] of the list): only j after i
+      if (base < R.rl[0])
+        detect_chunk64<true>(A, G, hq, nb, h0 + hb, g, thr, P, beta, Q);
+      else
+        detect_chunk64<false>(A, G, hq, nb, h0 + hb, g, thr, P, beta, Q);
     }
   }
   flush_survivors(A, G, Q);
@@ -813,10 +854,15 @@ __device__ __forceinline__ void detect_cell(const DetectArgs &A, const Grid &G, 
 
 template <bool FP32, bool LDSI>
 __global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
-  extern __shared__ double4 lds_raw[];  // LDSI: the home cell's records (Rec or Rec32)
+  extern __shared__ double4 lds_raw[];  // LDSI: the home cell's FP32 records
   __shared__ int2 survq[QCAP];
   SurvivorQueue Q{survq, 0, 0u, QCAP, 0ull};
-  detect_cell<FP32, LDSI>(A, A.G, A.start, xcd_remap(blockIdx.x, gridDim.x), Q, lds_raw);
+  if (FP32) {
+    detect_cell<true, LDSI>(A, A.G, A.start, xcd_remap(blockIdx.x, gridDim.x), Q, lds_raw);
+  } else {
+    __shared__ HomeQ hq[WAVE];
+    detect_cell64(A, A.G, A.start, xcd_remap(blockIdx.x, gridDim.x), Q, hq);
+  }
   if (__lane_id() == 0) {
     CounterShard &sh = A.ctr->shard[blockIdx.x % NSHARD];
     if (FP32 && Q.pushed) atomicAdd(&sh.recheck, (unsigned long long)Q.pushed);
@@ -1031,9 +1077,10 @@ __global__ __launch_bounds__(WAVE) void k_detect_gram(DetectArgs A) {
 __global__ __launch_bounds__(WAVE) void k_detect_list(DetectArgs A) {
   __shared__ int2 survq[QCAP];
   SurvivorQueue Q{survq, 0, 0u, QCAP, 0ull};
+  __shared__ HomeQ hq[WAVE];
   const int count = (int)A.ctr->n_crowd;
   for (int w = blockIdx.x; w < count; w += gridDim.x)
-    detect_cell<false, false>(A, A.G, A.start, A.crowd[w], Q, nullptr);
+    detect_cell64(A, A.G, A.start, A.crowd[w], Q, hq);
   if (__lane_id() == 0 && Q.tests) atomicAdd(&A.ctr->shard[blockIdx.x % NSHARD].tests, Q.tests);
 }
 
@@ -1058,6 +1105,7 @@ __device__ __forceinline__ int box_of_cell(const int *cell_base, int nbox, int c
 __global__ __launch_bounds__(256) void k_detect_batched(DetectArgs A, BatchDev B) {
   if (B.flags[FLAG_ERR]) return;
   __shared__ int2 survq[4][QCAP];
+  __shared__ HomeQ hq[4][WAVE];
   const int wpb = blockDim.x / WAVE;
   const int wave = threadIdx.x / WAVE;
   const int total = B.cell_base[B.nbox];
@@ -1067,7 +1115,7 @@ __global__ __launch_bounds__(256) void k_detect_batched(DetectArgs A, BatchDev B
     const int b = box_of_cell(B.cell_base, B.nbox, item);
     const Grid G = B.gtab[b];
     const int base = B.cell_base[b];
-    detect_cell<false, false>(A, G, A.start + base, item - base, Q, nullptr);
+    detect_cell64(A, G, A.start + base, item - base, Q, hq[wave]);
   }
 }
 
