@@ -47,6 +47,8 @@ struct pcol_ctx {
   int *list_a = nullptr;  // spheres still to act after sweep 1
   int *keep_cnt = nullptr, *keep_off = nullptr, *keep_bs = nullptr;  // its construction
   int *nlist_h = nullptr;  // pinned read-back of its length
+  unsigned int *epoch_d = nullptr;  // step counter stamped into output records
+  int64_t epochs = 0;               // steps since the stamps were last reset
   OutRec *out = nullptr;
   int *partner_tmp = nullptr;
   double *tcoll_tmp = nullptr;
@@ -214,7 +216,7 @@ void pcol_destroy(pcol_ctx *ctx) {
   void *dev[] = {ctx->rec,    ctx->rec32,  ctx->perm,   ctx->rank,   ctx->cid,         ctx->slot,
                  ctx->count,  ctx->start,  ctx->blocksum, ctx->cnt,      ctx->slot_t,
                  ctx->slot_j, ctx->key_j,  ctx->key_t,  ctx->status,      ctx->out,
-                 ctx->ovf,    ctx->partner_tmp, ctx->tcoll_tmp, ctx->list_a, ctx->keep_cnt, ctx->keep_off, ctx->keep_bs,
+                 ctx->ovf,    ctx->partner_tmp, ctx->tcoll_tmp, ctx->list_a, ctx->keep_cnt, ctx->keep_off, ctx->keep_bs, ctx->epoch_d,
                  ctx->reach_d, ctx->ctr_d};
   for (void *p : dev)
     if (p) (void)hipFree(p);
@@ -276,6 +278,7 @@ pcol_status pcol_create(pcol_ctx **out, int64_t n_max, void *hip_stream, const p
   A(dalloc(&ctx->out, n));
   A(dalloc(&ctx->ovf, n));
   A(dalloc(&ctx->list_a, n));
+  A(dalloc(&ctx->epoch_d, 1));
   A(dalloc(&ctx->keep_cnt, n / 256 + 2));
   A(dalloc(&ctx->keep_off, n / 256 + 3));
   A(dalloc(&ctx->keep_bs, n / 256 / 4096 + 2));
@@ -289,6 +292,10 @@ pcol_status pcol_create(pcol_ctx **out, int64_t n_max, void *hip_stream, const p
   if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->nlist_h, sizeof(int));
   for (hipEvent_t &ev : ctx->ev)
     if (e == hipSuccess) e = hipEventCreate(&ev);
+  // output-record stamps: every record stale, epoch 0
+  if (e == hipSuccess) e = launch_init_out(ctx->stream, ctx->out, (int64_t)n);
+  if (e == hipSuccess) e = launch_fill_u32(ctx->stream, ctx->epoch_d, 0u, 1);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) {
     pcol_destroy(ctx);
     return e == hipErrorOutOfMemory ? PCOL_E_NOMEM : PCOL_E_HIP;
@@ -590,6 +597,29 @@ static pcol_status detect_all(pcol_ctx *ctx, double dt) {
   return PCOL_OK;
 }
 
+// Advance the step epoch on the stream (every stamp is reset long before the
+// 32-bit counter could wrap).
+static pcol_status next_epoch(pcol_ctx *ctx, hipStream_t s) {
+  if (++ctx->epochs >= (int64_t)1 << 30) {
+    PCOL_HIP(launch_init_out(s, ctx->out, ctx->n_max));
+    PCOL_HIP(launch_fill_u32(s, ctx->epoch_d, 0u, 1));
+    ctx->epochs = 1;
+  }
+  PCOL_HIP(launch_epoch_next(s, ctx->epoch_d));
+  return PCOL_OK;
+}
+
+// Account for one replay of a captured step, which advances the device epoch
+// itself; resets the stamps (outside the graph) when the counter grows large.
+static pcol_status graph_epoch(pcol_ctx *ctx, hipStream_t s) {
+  if (++ctx->epochs >= (int64_t)1 << 30) {
+    PCOL_HIP(launch_init_out(s, ctx->out, ctx->n_max));
+    PCOL_HIP(launch_fill_u32(s, ctx->epoch_d, 0u, 1));
+    ctx->epochs = 1;
+  }
+  return PCOL_OK;
+}
+
 static void sum_counters(const SweepCounters &c, unsigned long long &pairs,
                          unsigned long long &contacts) {
   pairs = contacts = 0ull;
@@ -663,6 +693,7 @@ pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, dou
   unsigned long long contacts = 0ull, recheck = 0ull, tests = 0ull;
   double ms_detect = 0.0;
   if (n > 0) {
+    if ((st = next_epoch(ctx, s)) != PCOL_OK) return st;
     PCOL_HIP(launch_fill_u8(s, ctx->status, ST_ACTIVE, n));
     PCOL_HIP(hipMemsetAsync(ctx->ctr_d, 0, sizeof(SweepCounters), s));
     // sweep 1: every contact within dt, then the earliest partner of each sphere
@@ -676,8 +707,8 @@ pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, dou
     int nlist = 0;
     for (;;) {
       PCOL_HIP(launch_resolve_sweep(s, n, ctx->rec, ctx->G, dt, e, ctx->key_j, ctx->key_t,
-                                    ctx->status, ctx->perm, ctx->out, ctx->ctr_d, nullptr, lin,
-                                    nlist));
+                                    ctx->status, ctx->perm, ctx->out, ctx->ctr_d, nullptr,
+                                    ctx->epoch_d, lin, nlist));
       if (!lin) {
         PCOL_HIP(launch_keep_list(s, ctx->status, n, ctx->keep_cnt, ctx->keep_off, ctx->keep_bs,
                                   ctx->reach_d, ctx->list_a));
@@ -722,7 +753,7 @@ pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, dou
       }
     }
     if (timing) PCOL_HIP(hipEventRecord(ctx->ev[3], s));
-    PCOL_HIP(launch_finish(s, P, ctx->rank, ctx->rec, ctx->status, ctx->out, part, tc, dt, ctx->G,
+    PCOL_HIP(launch_finish(s, P, ctx->rank, ctx->rec, ctx->out, ctx->epoch_d, part, tc, dt, ctx->G,
                            nullptr));
     if (timing) {
       PCOL_HIP(hipEventRecord(ctx->ev[4], s));
@@ -950,6 +981,7 @@ static pcol_status batch_enqueue(pcol_ctx *ctx, hipStream_t s, const Particles &
   const int ncell = bp->total_cells;
   PCOL_HIP(launch_fill_u32(s, bp->flags, 0u, 16));
   PCOL_HIP(launch_fill_u32(s, (unsigned int *)bp->totals, 0u, 8));
+  PCOL_HIP(launch_epoch_next(s, ctx->epoch_d));  // one step per replay
   PCOL_HIP(launch_fill_u32(s, (unsigned int *)ctx->ctr_d, 0u, sizeof(SweepCounters) / 4));
   PCOL_HIP(launch_breach(s, P, B, dt, 1));
   PCOL_HIP(launch_fill_i32(s, ctx->count, 0, ncell));
@@ -995,7 +1027,8 @@ static pcol_status batch_enqueue(pcol_ctx *ctx, hipStream_t s, const Particles &
                                ctx->G, dt, ctx->status, ctx->perm, ctx->key_j, ctx->key_t, &B));
   for (int k = 0; k < kmax; ++k) {
     PCOL_HIP(launch_resolve_sweep(s, n, ctx->rec, ctx->G, dt, e, ctx->key_j, ctx->key_t,
-                                  ctx->status, ctx->perm, ctx->out, ctx->ctr_d, &B));
+                                  ctx->status, ctx->perm, ctx->out, ctx->ctr_d, &B,
+                                  ctx->epoch_d));
     PCOL_HIP(launch_sweep_check(s, ctx->ctr_d, bp->flags, bp->totals, k == kmax - 1));
     PCOL_HIP(launch_slot_min(s, n, 0, ctx->cnt, ctx->slot_t, ctx->slot_j, ctx->K, ctx->status,
                              ctx->perm, ctx->key_j, ctx->key_t, ctx->ovf, ctx->ctr_d, bp->flags));
@@ -1003,7 +1036,7 @@ static pcol_status batch_enqueue(pcol_ctx *ctx, hipStream_t s, const Particles &
                                  ctx->start, ctx->G, dt, ctx->status, ctx->perm, ctx->key_j,
                                  ctx->key_t, &B));
   }
-  PCOL_HIP(launch_finish(s, P, ctx->rank, ctx->rec, ctx->status, ctx->out, part, tc, dt, ctx->G,
+  PCOL_HIP(launch_finish(s, P, ctx->rank, ctx->rec, ctx->out, ctx->epoch_d, part, tc, dt, ctx->G,
                          &B));
   return PCOL_OK;
 }
@@ -1038,7 +1071,8 @@ static pcol_status batch_finish(pcol_ctx *ctx, const Particles &P, int32_t *part
   for (;;) {
     PCOL_HIP(launch_fill_u32(s, (unsigned int *)ctx->ctr_d, 0u, sizeof(SweepCounters) / 4));
     PCOL_HIP(launch_resolve_sweep(s, n, ctx->rec, ctx->G, dt, e, ctx->key_j, ctx->key_t,
-                                  ctx->status, ctx->perm, ctx->out, ctx->ctr_d, &B));
+                                  ctx->status, ctx->perm, ctx->out, ctx->ctr_d, &B,
+                                  ctx->epoch_d));
     PCOL_HIP(hipMemcpyAsync(ctx->ctr_h, ctx->ctr_d, sizeof(SweepCounters), hipMemcpyDeviceToHost, s));
     PCOL_HIP(hipStreamSynchronize(s));
     unsigned long long sp, sc;
@@ -1054,7 +1088,7 @@ static pcol_status batch_finish(pcol_ctx *ctx, const Particles &P, int32_t *part
                                  ctx->key_t, &B));
   }
   PCOL_HIP(launch_fill_u32(s, bp->flags + FLAG_UNFINISHED, 0u, 1));
-  PCOL_HIP(launch_finish(s, P, ctx->rank, ctx->rec, ctx->status, ctx->out, part, tc, dt, ctx->G,
+  PCOL_HIP(launch_finish(s, P, ctx->rank, ctx->rec, ctx->out, ctx->epoch_d, part, tc, dt, ctx->G,
                          &B));
   return PCOL_OK;
 }
@@ -1149,6 +1183,7 @@ static pcol_status batch_autotune(pcol_ctx *ctx, int nbox, const int64_t *box_of
         for (int k = 0; k < 6; ++k)
           PCOL_HIP(hipMemcpyAsync(dst[k], src[k], n * sizeof(double), hipMemcpyDeviceToDevice, s));
         PCOL_HIP(hipEventRecord(ctx->ev[0], s));
+        if ((st = graph_epoch(ctx, s)) != PCOL_OK) return st;
         PCOL_HIP(hipGraphLaunch(ex, s));
         PCOL_HIP(hipEventRecord(ctx->ev[1], s));
         PCOL_HIP(hipEventSynchronize(ctx->ev[1]));
@@ -1243,6 +1278,7 @@ extern "C" pcol_status pcol_step_batched(pcol_ctx *ctx, int32_t nbox, const int6
       bp->cap_tc = tc;
       for (int k = 0; k < 8; ++k) bp->cap_ptr[k] = ptrs[k];
     }
+    if ((st = graph_epoch(ctx, ctx->stream)) != PCOL_OK) return st;
     PCOL_HIP(hipGraphLaunch(bp->exec, ctx->stream));
     PCOL_HIP(batch_readback(ctx, bp));
     const unsigned int err = bp->flags_h[FLAG_ERR];

@@ -24,8 +24,8 @@ enum : uint8_t { ST_ACTIVE = 0, ST_FREE = 1, ST_COLLIDED = 2, ST_DIRTY = 3 };
 // caller's order by a final gather.
 struct alignas(16) OutRec {
   double x, y, z, vx, vy, vz, t;
-  int partner;  // caller index, -1 = none
-  int pad;
+  int partner;          // caller index, -1 = none
+  unsigned int epoch;   // step that wrote the record (a stale record never matches)
 };
 
 // Uniform grid over the periodic box.  Cells are numbered (cz * nc1 + cy) * nc0 + cx,
@@ -263,15 +263,19 @@ hipError_t launch_gather_exact(hipStream_t s, const int *list, int nlist, const 
 hipError_t launch_resolve_sweep(hipStream_t s, int n, const Rec *rec, const Grid &G, double dt,
                                 double e, const int *key_j, const double *key_t, uint8_t *status,
                                 const int *perm, OutRec *out, SweepCounters *ctr,
-                                const BatchDev *B, const int *list = nullptr, int nlist = 0);
+                                const BatchDev *B, const unsigned int *epoch,
+                                const int *list = nullptr, int nlist = 0);
+// next step's epoch (one thread); every OutRec epoch starts at 0xffffffff
+hipError_t launch_epoch_next(hipStream_t s, unsigned int *epoch);
+hipError_t launch_init_out(hipStream_t s, OutRec *out, int64_t n);
 // list (read back from off[(n + 255) / 256] entries) of the ACTIVE or
 // DIRTY spheres; count and off need (n + 255) / 256 + 1 entries, blocksum
 // ((n + 255) / 256) / 4096 + 2
 hipError_t launch_keep_list(hipStream_t s, const uint8_t *status, int n, int *count, int *off,
                             int *blocksum, ReachOut *scratch_out, int *list);
 hipError_t launch_finish(hipStream_t s, const Particles &P, const int *rank, const Rec *rec,
-                         const uint8_t *status, const OutRec *out, int *partner, double *tcoll,
-                         double dt, const Grid &G, const BatchDev *B);
+                         const OutRec *out, const unsigned int *epoch, int *partner,
+                         double *tcoll, double dt, const Grid &G, const BatchDev *B);
 hipError_t launch_fill_box_of(hipStream_t s, int nbox, const int64_t *box_off, int *box_of);
 hipError_t launch_breach(hipStream_t s, const Particles &P, const BatchDev &B, double dt,
                          int check_plan);

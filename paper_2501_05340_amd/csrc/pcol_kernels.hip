@@ -123,37 +123,59 @@ __global__ __launch_bounds__(256) void k_reach(Particles P, double L0, double L1
   __syncthreads();
   double v2 = 0.0, rm = 0.0, rn = INFINITY, em = 0.0;
   unsigned int bad = 0u;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < P.n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const double x = P.x[i], y = P.y[i], z = P.z[i];
-    const double vx = P.vx[i], vy = P.vy[i], vz = P.vz[i];
-    const double r = P.r[i], m = P.m[i];
-    const double w = (vx * vx + vy * vy) + vz * vz;
-    const bool fin = isfinite(x) && isfinite(y) && isfinite(z) && isfinite(w) && isfinite(r) &&
-                     isfinite(m);
-    if (!fin || !(r > 0.0) || !(m > 0.0)) bad |= 1u;
-    if (!(x >= 0.0 && x < L0) || !(y >= 0.0 && y < L1) || !(z >= 0.0 && z < L2)) bad |= 2u;
-    if (fin) {
-      v2 = w > v2 ? w : v2;
-      rm = r > rm ? r : rm;
-      rn = r < rn ? r : rn;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // four elements per thread per step: their loads are issued together
+  for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i0 < P.n; i0 += 4 * stride) {
+    double x[4], y[4], z[4], vx[4], vy[4], vz[4], r[4], m[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t i = i0 + u * stride;
+      if (i < P.n) {
+        x[u] = P.x[i];
+        y[u] = P.y[i];
+        z[u] = P.z[i];
+        vx[u] = P.vx[i];
+        vy[u] = P.vy[i];
+        vz[u] = P.vz[i];
+        r[u] = P.r[i];
+        m[u] = P.m[i];
+      }
     }
-    // histogram: one LDS atomic per distinct bin of the wave (lanes of one
-    // bin add together), so the few busy bins see no lane conflicts
-    const bool has = fin && r > 0.0;
-    int bin = -1;
-    if (has) {
-      const double ex = extent(r, vx, vy, vz, dt);
-      em = ex > em ? ex : em;
-      bin = rho_bin(ex);
-    }
-    unsigned long long todo = __ballot(has);
-    while (todo) {
-      const int leader = __ffsll((long long)todo) - 1;
-      const int lb = __shfl(bin, leader);
-      const unsigned long long same = __ballot(bin == lb);
-      if ((int)__lane_id() == leader) atomicAdd(&hist[lb], (unsigned int)__popcll(same));
-      todo &= ~same;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool in = i0 + u * stride < P.n;
+      bool has = false;
+      int bin = -1;
+      if (in) {
+        const double w = (vx[u] * vx[u] + vy[u] * vy[u]) + vz[u] * vz[u];
+        const bool fin = isfinite(x[u]) && isfinite(y[u]) && isfinite(z[u]) && isfinite(w) &&
+                         isfinite(r[u]) && isfinite(m[u]);
+        if (!fin || !(r[u] > 0.0) || !(m[u] > 0.0)) bad |= 1u;
+        if (!(x[u] >= 0.0 && x[u] < L0) || !(y[u] >= 0.0 && y[u] < L1) ||
+            !(z[u] >= 0.0 && z[u] < L2))
+          bad |= 2u;
+        if (fin) {
+          v2 = w > v2 ? w : v2;
+          rm = r[u] > rm ? r[u] : rm;
+          rn = r[u] < rn ? r[u] : rn;
+          has = r[u] > 0.0;
+          if (has) {
+            const double ex = extent(r[u], vx[u], vy[u], vz[u], dt);
+            em = ex > em ? ex : em;
+            bin = rho_bin(ex);
+          }
+        }
+      }
+      // histogram: one LDS atomic per distinct bin of the wave (lanes of one
+      // bin add together), so the few busy bins see no lane conflicts
+      unsigned long long todo = __ballot(has);
+      while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int lb = __shfl(bin, leader);
+        const unsigned long long same = __ballot(bin == lb);
+        if ((int)__lane_id() == leader) atomicAdd(&hist[lb], (unsigned int)__popcll(same));
+        todo &= ~same;
+      }
     }
   }
   for (int o = WAVE / 2; o > 0; o >>= 1) {
@@ -638,6 +660,26 @@ __device__ __forceinline__ bool cell_runs(const Grid &G, const int *start, int c
   return true;
 }
 
+// Candidate slot v of a cell's list (see cell_runs): its sorted index and run
+// code.  The run of v is the last run whose first slot is at most v (an empty
+// run shares its first slot with the next one, so it is never the last such
+// run for a slot inside the list); off[k] = rg[k] - pre[k] turns the slot into
+// the index.  ok: v is inside the list.
+__device__ __forceinline__ void cand_of(const int pre[MAXRUN], const int off[MAXRUN],
+                                        const int *rc, int total, int v, int &g, int &code,
+                                        bool &ok) {
+  int o = off[0], c = rc[0];
+#pragma unroll
+  for (int k = 1; k < MAXRUN; ++k) {
+    const bool in = v >= pre[k];
+    o = in ? off[k] : o;
+    c = in ? rc[k] : c;
+  }
+  ok = v < total;
+  g = o + v;
+  code = c;
+}
+
 template <bool FP32, bool LDSI>
 __device__ __forceinline__ void detect_cell(const DetectArgs &A, const Grid &G, const int *start,
                                             int cell, SurvivorQueue &Q, double4 *lds_raw) {
@@ -794,6 +836,9 @@ __device__ __forceinline__ void detect_cell64(const DetectArgs &A, const Grid &G
   const int lane = __lane_id();
   const double ox = (R.cx + 0.5) * G.h[0], oy = (R.cy + 0.5) * G.h[1], oz = (R.cz + 0.5) * G.h[2];
   const double dt2 = A.dt2;
+  int off[MAXRUN];
+#pragma unroll
+  for (int k = 0; k < MAXRUN; ++k) off[k] = R.rg[k] - pre[k];
   for (int hb = 0; hb < nh; hb += WAVE) {
     const int nb = nh - hb < WAVE ? nh - hb : WAVE;
     if (lane < nb) {  // this batch's home terms (one wave owns hq: in-order LDS)
@@ -813,16 +858,9 @@ __device__ __forceinline__ void detect_cell64(const DetectArgs &A, const Grid &G
     }
     for (int base = 0; base < total; base += WAVE) {
       const int v = base + lane;
-      int g = 0, code = run_code(0, 0, 0, 0);
-      bool ok = false;
-#pragma unroll
-      for (int k = 0; k < MAXRUN; ++k) {
-        if (v >= pre[k] && v < pre[k] + R.rl[k]) {
-          g = R.rg[k] + (v - pre[k]);
-          code = R.rc[k];
-          ok = true;
-        }
-      }
+      int g, code;
+      bool ok;
+      cand_of(pre, off, R.rc, total, v, g, code, ok);
       const bool own = (code >> 6) & 1;
       const int thr = !ok ? -1 : (own ? g : 0x7fffffff);
       double P[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -1516,7 +1554,8 @@ __global__ __launch_bounds__(256) void k_resolve_sweep(int n, const Rec *rec, Gr
                                                        const double *key_t, uint8_t *status,
                                                        const int *perm, OutRec *out,
                                                        SweepCounters *ctr, BatchDev B,
-                                                       const int *list, int nlist) {
+                                                       const unsigned int *epoch, const int *list,
+                                                       int nlist) {
   if (B.flags && (B.flags[FLAG_ERR] || B.flags[FLAG_DONE])) return;
   const int ti = blockIdx.x * 256 + threadIdx.x;
   const bool valid = list ? ti < nlist : ti < n;
@@ -1547,7 +1586,7 @@ __global__ __launch_bounds__(256) void k_resolve_sweep(int n, const Rec *rec, Gr
         o.vz = vo[2];
         o.t = t;
         o.partner = perm[p];
-        o.pad = 0;
+        o.epoch = *epoch;
         out[i] = o;
         status[i] = ST_COLLIDED;
         if (i < p) npair = 1ull;
@@ -1562,12 +1601,31 @@ __global__ __launch_bounds__(256) void k_resolve_sweep(int n, const Rec *rec, Gr
 hipError_t launch_resolve_sweep(hipStream_t s, int n, const Rec *rec, const Grid &G, double dt,
                                 double e, const int *key_j, const double *key_t, uint8_t *status,
                                 const int *perm, OutRec *out, SweepCounters *ctr,
-                                const BatchDev *B, const int *list, int nlist) {
+                                const BatchDev *B, const unsigned int *epoch, const int *list,
+                                int nlist) {
   const int items = list ? nlist : n;
   if (items <= 0) return hipSuccess;
   BatchDev none{};
   hipLaunchKernelGGL(k_resolve_sweep, dim3((items + 255) / 256), dim3(256), 0, s, n, rec, G, dt,
-                     e, key_j, key_t, status, perm, out, ctr, B ? *B : none, list, nlist);
+                     e, key_j, key_t, status, perm, out, ctr, B ? *B : none, epoch, list, nlist);
+  return hipGetLastError();
+}
+
+__global__ void k_epoch_next(unsigned int *epoch) { *epoch += 1u; }
+
+hipError_t launch_epoch_next(hipStream_t s, unsigned int *epoch) {
+  hipLaunchKernelGGL(k_epoch_next, dim3(1), dim3(1), 0, s, epoch);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_init_out(OutRec *out, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i].epoch = 0xffffffffu;
+}
+
+hipError_t launch_init_out(hipStream_t s, OutRec *out, int64_t n) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_init_out, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, n);
   return hipGetLastError();
 }
 
@@ -1612,9 +1670,10 @@ hipError_t launch_keep_list(hipStream_t s, const uint8_t *status, int n, int *co
 
 // a8 and the copy back: the end-of-step state of every sphere in the caller's
 // order (coalesced writes).  A sphere that collided takes the output record its
-// resolve wrote; any other flies the whole step from its start record (rule 5).
+// resolve wrote (stamped with this step's epoch); any other flies the whole
+// step from its start record (rule 5).
 __global__ __launch_bounds__(256) void k_finish(Particles P, const int *rank, const Rec *rec,
-                                                const uint8_t *status, const OutRec *out,
+                                                const OutRec *out, const unsigned int *epoch,
                                                 int *partner, double *tcoll, double dt, Grid G0,
                                                 BatchDev B) {
   if (B.flags && (B.flags[FLAG_ERR] || B.flags[FLAG_UNFINISHED])) return;
@@ -1623,8 +1682,8 @@ __global__ __launch_bounds__(256) void k_finish(Particles P, const int *rank, co
   const int q = rank[o];
   double x, y, z, vx, vy, vz, t;
   int pj;
-  if (status[q] == ST_COLLIDED) {
-    const OutRec r = out[q];
+  const OutRec r = out[q];
+  if (r.epoch == *epoch) {  // written by this step's resolve: collided
     x = r.x;
     y = r.y;
     z = r.z;
@@ -1656,12 +1715,12 @@ __global__ __launch_bounds__(256) void k_finish(Particles P, const int *rank, co
 }
 
 hipError_t launch_finish(hipStream_t s, const Particles &P, const int *rank, const Rec *rec,
-                         const uint8_t *status, const OutRec *out, int *partner, double *tcoll,
-                         double dt, const Grid &G, const BatchDev *B) {
+                         const OutRec *out, const unsigned int *epoch, int *partner,
+                         double *tcoll, double dt, const Grid &G, const BatchDev *B) {
   if (P.n <= 0) return hipSuccess;
   BatchDev none{};
   hipLaunchKernelGGL(k_finish, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, s, P, rank, rec,
-                     status, out, partner, tcoll, dt, G, B ? *B : none);
+                     out, epoch, partner, tcoll, dt, G, B ? *B : none);
   return hipGetLastError();
 }
 
