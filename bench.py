@@ -133,14 +133,15 @@ def batched_leg(args, pc, torch):
     for k in range(args.warmup):
         restore()
         pc.pcol_step_batched(ctx, p, off, Ls, dt, e, partner, None)
-    torch.cuda.synchronize()
     stats = []
-    t0 = time.perf_counter()
-    for k in range(args.steps):
+    wall = 0.0
+    for k in range(args.steps):  # each step from the configured input, restored untimed
         restore()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         stats.append(pc.pcol_step_batched(ctx, p, off, Ls, dt, e, partner, None))
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
     for k, st in enumerate(stats):
         log(f"[batched] step {k}: pairs {st['n_pairs']} sweeps {st['n_sweeps']} replanned "
             f"{st['replanned']} host-finished {st['finished_on_host']}")
@@ -156,17 +157,16 @@ def batched_leg(args, pc, torch):
     def loop_step():
         for t, t_0 in zip(q.tensors()[:6], p0.tensors()[:6]):
             t.copy_(t_0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         for sub, pt, L in views:
             pc.pcol_step(ctx1, sub, L, dt, e, pt, None, stats=False)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
 
     loop_step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
     nloop = max(1, min(args.steps, 3))
-    for k in range(nloop):
-        loop_step()
-    torch.cuda.synchronize()
-    loop_wall = (time.perf_counter() - t0) / nloop
+    loop_wall = sum(loop_step() for k in range(nloop)) / nloop
     # pair sets agree (loop partners are box-local)
     loc = torch.empty_like(partner)
     restore()
@@ -268,7 +268,10 @@ def main():
     p0 = pc.Particles.from_box(box)
 
     def run_form(name: str, flt: int, split):
-        """K timed steps of one filter form, each from the configured input."""
+        """W warm-up and K timed steps of one filter form, each from the configured
+        input: the input is restored before a step, outside its timed interval
+        (a step is bracketed by device synchronisations), so every timed step is
+        the configured workload and nothing else."""
         p = p0.clone()
         kw = {}
         if split is not None:
@@ -289,14 +292,15 @@ def main():
             log(f"[{name}] warmup {k}: {st['n_pairs']} pairs, {st['n_sweeps']} sweeps, "
                 f"detect {st['ms_detect']:.3f} ms, nc {st['nc']}, wide {st['n_wide']}, "
                 f"rho_c {st['rho_c']:.4f}, reach {st['reach']:.4f}")
-        torch.cuda.synchronize()
         stats = []
-        t_start = time.perf_counter()
+        wall = 0.0
         for k in range(args.steps):
             restore()
+            torch.cuda.synchronize()
+            t_start = time.perf_counter()
             stats.append(pc.pcol_step(ctx, p, box.L, box.dt, box.e, partner, tcoll))
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t_start
+            torch.cuda.synchronize()
+            wall += time.perf_counter() - t_start
         for k, st in enumerate(stats):
             log(f"[{name}] step {k}: pairs {st['n_pairs']} sweeps {st['n_sweeps']} tests "
                 f"{st['pair_tests']} rechecks {st['n_recheck']} bin {st['ms_bin']:.3f} detect "

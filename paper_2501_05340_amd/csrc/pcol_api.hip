@@ -27,7 +27,6 @@ struct pcol_ctx {
   // cell-sorted state of the last pcol_bin
   Rec *rec = nullptr;
   Rec32 *rec32 = nullptr;  // FP32 filter records (filter 1 only)
-  int *perm = nullptr;  // sorted position -> caller index
   int *rank = nullptr;  // caller index -> sorted position
   int *cid = nullptr;
   int *slot = nullptr;
@@ -93,7 +92,6 @@ struct BatchPlan {
   Grid *gtab = nullptr;
   int *cell_base = nullptr;
   int *box_of = nullptr;
-  int *sbox = nullptr;
   int64_t *box_off_d = nullptr;
   double *breach = nullptr;
   unsigned int *flags = nullptr;          // FLAG_* words
@@ -213,7 +211,7 @@ pcol_status pcol_set_stream(pcol_ctx *ctx, void *hip_stream) {
 
 void pcol_destroy(pcol_ctx *ctx) {
   if (!ctx) return;
-  void *dev[] = {ctx->rec,    ctx->rec32,  ctx->perm,   ctx->rank,   ctx->cid,         ctx->slot,
+  void *dev[] = {ctx->rec,    ctx->rec32,  ctx->rank,   ctx->cid,         ctx->slot,
                  ctx->count,  ctx->start,  ctx->blocksum, ctx->cnt,      ctx->slot_t,
                  ctx->slot_j, ctx->key_j,  ctx->key_t,  ctx->status,      ctx->out,
                  ctx->ovf,    ctx->partner_tmp, ctx->tcoll_tmp, ctx->list_a, ctx->keep_cnt, ctx->keep_off, ctx->keep_bs, ctx->epoch_d,
@@ -227,7 +225,7 @@ void pcol_destroy(pcol_ctx *ctx) {
   for (hipEvent_t &e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
   if (BatchPlan *bp = ctx->bp) {
-    void *bd[] = {bp->gtab, bp->cell_base, bp->box_of, bp->sbox, bp->box_off_d,
+    void *bd[] = {bp->gtab, bp->cell_base, bp->box_of, bp->box_off_d,
                   bp->breach, bp->flags, bp->totals, bp->tune_buf};
     for (void *q : bd)
       if (q) (void)hipFree(q);
@@ -265,7 +263,6 @@ pcol_status pcol_create(pcol_ctx **out, int64_t n_max, void *hip_stream, const p
   };
   A(dalloc(&ctx->rec, n));
   if (ctx->opts.filter == 1) A(dalloc(&ctx->rec32, n));
-  A(dalloc(&ctx->perm, n));
   A(dalloc(&ctx->rank, n));
   A(dalloc(&ctx->cid, n));
   A(dalloc(&ctx->slot, n));
@@ -406,8 +403,7 @@ pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box
   PCOL_HIP(launch_cell_hist(s, P, G, dt, rho_c, ctx->cid, ctx->slot, ctx->count));
   PCOL_HIP(launch_scan(s, ctx->count, cells_all, ctx->start, ctx->blocksum, ctx->reach_d));
   PCOL_HIP(launch_scatter(s, P, G, ctx->cid, ctx->slot, ctx->start, ctx->rec,
-                          ctx->opts.filter == 1 ? ctx->rec32 : nullptr, ctx->perm, ctx->rank,
-                          nullptr));
+                          ctx->opts.filter == 1 ? ctx->rec32 : nullptr, ctx->rank, nullptr));
   PCOL_HIP(hipMemcpyAsync(&ctx->reach_h->maxcell, &ctx->reach_d->maxcell, sizeof(unsigned int),
                           hipMemcpyDeviceToHost, s));
   if (split)
@@ -585,14 +581,14 @@ static pcol_status detect_all(pcol_ctx *ctx, double dt) {
     if (ctx->opts.timing) PCOL_HIP(hipEventRecord(ctx->ev[6], s));
     ctx->detect_timed = true;
     PCOL_HIP(launch_slot_min(s, n, 1, ctx->cnt, ctx->slot_t, ctx->slot_j, ctx->K, ctx->status,
-                             ctx->perm, ctx->key_j, ctx->key_t, ctx->ovf, ctx->ctr_d,
+                             ctx->rec, ctx->key_j, ctx->key_t, ctx->ovf, ctx->ctr_d,
                              nullptr));
     PCOL_HIP(launch_gather_exact(s, ctx->ovf, 0, &ctx->ctr_d->n_overflow, -1, ctx->rec, ctx->start,
-                                 ctx->G, dt, ctx->status, ctx->perm, ctx->key_j, ctx->key_t, nullptr));
+                                 ctx->G, dt, ctx->status, ctx->key_j, ctx->key_t, nullptr));
   } else {
     // fewer than 3 cells on some axis: exact search for every sphere
     PCOL_HIP(launch_gather_exact(s, nullptr, n, nullptr, -1, ctx->rec, ctx->start, ctx->G, dt,
-                                 ctx->status, ctx->perm, ctx->key_j, ctx->key_t, nullptr));
+                                 ctx->status, ctx->key_j, ctx->key_t, nullptr));
   }
   return PCOL_OK;
 }
@@ -643,12 +639,12 @@ pcol_status pcol_detect(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *
     PCOL_HIP(launch_fill_u8(s, ctx->status, ST_ACTIVE, n));
     if ((st = detect_all(ctx, dt)) != PCOL_OK) return st;
   } else {
-    PCOL_HIP(launch_status_from_active(s, active, ctx->perm, n, ctx->status));
+    PCOL_HIP(launch_status_from_active(s, active, ctx->rec, n, ctx->status));
     PCOL_HIP(launch_fill_i32(s, ctx->key_j, -1, n));
     PCOL_HIP(launch_gather_exact(s, nullptr, n, nullptr, ST_ACTIVE, ctx->rec, ctx->start, ctx->G,
-                                 dt, ctx->status, ctx->perm, ctx->key_j, ctx->key_t, nullptr));
+                                 dt, ctx->status, ctx->key_j, ctx->key_t, nullptr));
   }
-  PCOL_HIP(launch_export_keys(s, n, ctx->perm, ctx->key_j, ctx->key_t, ctx->status, key_out,
+  PCOL_HIP(launch_export_keys(s, n, ctx->rec, ctx->key_j, ctx->key_t, ctx->status, key_out,
                               tmin_out));
   return PCOL_OK;
 }
@@ -706,8 +702,8 @@ pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, dou
     const int *lin = nullptr;
     int nlist = 0;
     for (;;) {
-      PCOL_HIP(launch_resolve_sweep(s, n, ctx->rec, ctx->G, dt, e, ctx->key_j, ctx->key_t,
-                                    ctx->status, ctx->perm, ctx->out, ctx->ctr_d, nullptr,
+      PCOL_HIP(launch_resolve_sweep(s, n, ctx->rec, ctx->G, dt, e, P.m, ctx->key_j, ctx->key_t,
+                                    ctx->status, ctx->out, ctx->ctr_d, nullptr,
                                     ctx->epoch_d, lin, nlist));
       if (!lin) {
         PCOL_HIP(launch_keep_list(s, ctx->status, n, ctx->keep_cnt, ctx->keep_off, ctx->keep_bs,
@@ -741,19 +737,19 @@ pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, dou
       PCOL_HIP(hipMemsetAsync(ctx->ctr_d, 0, sizeof(SweepCounters), s));
       if (!ctx->small) {
         PCOL_HIP(launch_slot_min(s, n, 0, ctx->cnt, ctx->slot_t, ctx->slot_j, ctx->K, ctx->status,
-                                 ctx->perm, ctx->key_j, ctx->key_t, ctx->ovf, ctx->ctr_d, nullptr,
+                                 ctx->rec, ctx->key_j, ctx->key_t, ctx->ovf, ctx->ctr_d, nullptr,
                                  lin, nlist));
         PCOL_HIP(launch_gather_exact(s, ctx->ovf, 0, &ctx->ctr_d->n_overflow, -1, ctx->rec,
-                                     ctx->start, ctx->G, dt, ctx->status, ctx->perm, ctx->key_j,
+                                     ctx->start, ctx->G, dt, ctx->status, ctx->key_j,
                                      ctx->key_t, nullptr));
       } else {
         PCOL_HIP(launch_gather_exact(s, lin, nlist, nullptr, ST_DIRTY, ctx->rec, ctx->start,
-                                     ctx->G, dt, ctx->status, ctx->perm, ctx->key_j,
+                                     ctx->G, dt, ctx->status, ctx->key_j,
                                      ctx->key_t, nullptr));
       }
     }
     if (timing) PCOL_HIP(hipEventRecord(ctx->ev[3], s));
-    PCOL_HIP(launch_finish(s, P, ctx->rank, ctx->rec, ctx->out, ctx->epoch_d, part, tc, dt, ctx->G,
+    PCOL_HIP(launch_finish(s, P, ctx->rank, ctx->out, ctx->epoch_d, part, tc, dt, ctx->G,
                            nullptr));
     if (timing) {
       PCOL_HIP(hipEventRecord(ctx->ev[4], s));
@@ -824,7 +820,6 @@ BatchDev batch_dev(const BatchPlan *bp) {
   B.gtab = bp->gtab;
   B.cell_base = bp->cell_base;
   B.box_of = bp->box_of;
-  B.sbox = bp->sbox;
   B.box_off = bp->box_off_d;
   B.breach = bp->breach;
   B.flags = bp->flags;
@@ -904,7 +899,7 @@ static pcol_status batch_plan(pcol_ctx *ctx, int nbox, const int64_t *box_off,
     bp->cap_box = nbox;
   }
   if (P.n > bp->cap_n) {
-    if ((e = regrow(&bp->box_of, P.n)) != hipSuccess || (e = regrow(&bp->sbox, P.n)) != hipSuccess)
+    if ((e = regrow(&bp->box_of, P.n)) != hipSuccess)
       return fail(ctx, PCOL_E_NOMEM, "batched tables");
     bp->cap_n = P.n;
   }
@@ -988,7 +983,7 @@ static pcol_status batch_enqueue(pcol_ctx *ctx, hipStream_t s, const Particles &
   PCOL_HIP(launch_cell_hist_b(s, P, B, ctx->cid, ctx->slot, ctx->count));
   PCOL_HIP(launch_scan(s, ctx->count, ncell, ctx->start, ctx->blocksum, ctx->reach_d));
   PCOL_HIP(launch_scatter(s, P, ctx->G, ctx->cid, ctx->slot, ctx->start, ctx->rec, nullptr,
-                          ctx->perm, ctx->rank, &B));
+                          ctx->rank, &B));
   PCOL_HIP(launch_fill_u8(s, ctx->status, ST_ACTIVE, n));
   PCOL_HIP(launch_fill_i32(s, ctx->cnt, 0, n));
   DetectArgs A{};
@@ -1022,21 +1017,21 @@ static pcol_status batch_enqueue(pcol_ctx *ctx, hipStream_t s, const Particles &
   int blocks = 256 * 8 * 4 / wpb;  // about 8 resident waves per SIMD
   PCOL_HIP(launch_detect_batched(s, A, B, blocks, wpb));
   PCOL_HIP(launch_slot_min(s, n, 1, ctx->cnt, ctx->slot_t, ctx->slot_j, ctx->K, ctx->status,
-                           ctx->perm, ctx->key_j, ctx->key_t, ctx->ovf, ctx->ctr_d, bp->flags));
+                           ctx->rec, ctx->key_j, ctx->key_t, ctx->ovf, ctx->ctr_d, bp->flags));
   PCOL_HIP(launch_gather_exact(s, ctx->ovf, 0, &ctx->ctr_d->n_overflow, -1, ctx->rec, ctx->start,
-                               ctx->G, dt, ctx->status, ctx->perm, ctx->key_j, ctx->key_t, &B));
+                               ctx->G, dt, ctx->status, ctx->key_j, ctx->key_t, &B));
   for (int k = 0; k < kmax; ++k) {
-    PCOL_HIP(launch_resolve_sweep(s, n, ctx->rec, ctx->G, dt, e, ctx->key_j, ctx->key_t,
-                                  ctx->status, ctx->perm, ctx->out, ctx->ctr_d, &B,
+    PCOL_HIP(launch_resolve_sweep(s, n, ctx->rec, ctx->G, dt, e, P.m, ctx->key_j, ctx->key_t,
+                                  ctx->status, ctx->out, ctx->ctr_d, &B,
                                   ctx->epoch_d));
     PCOL_HIP(launch_sweep_check(s, ctx->ctr_d, bp->flags, bp->totals, k == kmax - 1));
     PCOL_HIP(launch_slot_min(s, n, 0, ctx->cnt, ctx->slot_t, ctx->slot_j, ctx->K, ctx->status,
-                             ctx->perm, ctx->key_j, ctx->key_t, ctx->ovf, ctx->ctr_d, bp->flags));
+                             ctx->rec, ctx->key_j, ctx->key_t, ctx->ovf, ctx->ctr_d, bp->flags));
     PCOL_HIP(launch_gather_exact(s, ctx->ovf, 0, &ctx->ctr_d->n_overflow, -1, ctx->rec,
-                                 ctx->start, ctx->G, dt, ctx->status, ctx->perm, ctx->key_j,
+                                 ctx->start, ctx->G, dt, ctx->status, ctx->key_j,
                                  ctx->key_t, &B));
   }
-  PCOL_HIP(launch_finish(s, P, ctx->rank, ctx->rec, ctx->out, ctx->epoch_d, part, tc, dt, ctx->G,
+  PCOL_HIP(launch_finish(s, P, ctx->rank, ctx->out, ctx->epoch_d, part, tc, dt, ctx->G,
                          &B));
   return PCOL_OK;
 }
@@ -1070,8 +1065,8 @@ static pcol_status batch_finish(pcol_ctx *ctx, const Particles &P, int32_t *part
   const int n = (int)P.n;
   for (;;) {
     PCOL_HIP(launch_fill_u32(s, (unsigned int *)ctx->ctr_d, 0u, sizeof(SweepCounters) / 4));
-    PCOL_HIP(launch_resolve_sweep(s, n, ctx->rec, ctx->G, dt, e, ctx->key_j, ctx->key_t,
-                                  ctx->status, ctx->perm, ctx->out, ctx->ctr_d, &B,
+    PCOL_HIP(launch_resolve_sweep(s, n, ctx->rec, ctx->G, dt, e, P.m, ctx->key_j, ctx->key_t,
+                                  ctx->status, ctx->out, ctx->ctr_d, &B,
                                   ctx->epoch_d));
     PCOL_HIP(hipMemcpyAsync(ctx->ctr_h, ctx->ctr_d, sizeof(SweepCounters), hipMemcpyDeviceToHost, s));
     PCOL_HIP(hipStreamSynchronize(s));
@@ -1082,13 +1077,13 @@ static pcol_status batch_finish(pcol_ctx *ctx, const Particles &P, int32_t *part
     if (sp == 0ull) break;
     PCOL_HIP(launch_fill_u32(s, (unsigned int *)ctx->ctr_d, 0u, sizeof(SweepCounters) / 4));
     PCOL_HIP(launch_slot_min(s, n, 0, ctx->cnt, ctx->slot_t, ctx->slot_j, ctx->K, ctx->status,
-                             ctx->perm, ctx->key_j, ctx->key_t, ctx->ovf, ctx->ctr_d, bp->flags));
+                             ctx->rec, ctx->key_j, ctx->key_t, ctx->ovf, ctx->ctr_d, bp->flags));
     PCOL_HIP(launch_gather_exact(s, ctx->ovf, 0, &ctx->ctr_d->n_overflow, -1, ctx->rec,
-                                 ctx->start, ctx->G, dt, ctx->status, ctx->perm, ctx->key_j,
+                                 ctx->start, ctx->G, dt, ctx->status, ctx->key_j,
                                  ctx->key_t, &B));
   }
   PCOL_HIP(launch_fill_u32(s, bp->flags + FLAG_UNFINISHED, 0u, 1));
-  PCOL_HIP(launch_finish(s, P, ctx->rank, ctx->rec, ctx->out, ctx->epoch_d, part, tc, dt, ctx->G,
+  PCOL_HIP(launch_finish(s, P, ctx->rank, ctx->out, ctx->epoch_d, part, tc, dt, ctx->G,
                          &B));
   return PCOL_OK;
 }

@@ -9,10 +9,16 @@
 
 namespace pcol {
 
-// Cell-sorted start-of-step record of one sphere (64 B, one HBM burst).
+// Cell-sorted start-of-step record of one sphere (64 B, one HBM burst).  It
+// carries the sphere's caller index o (the tie-break key of the partner rule and
+// the output position) and its box in the batched form, so binning writes one
+// record per sphere and nothing else in sorted order; the mass, needed only
+// for a collision, is read from the caller's array at o.
 struct alignas(16) Rec {
   double x, y, z, r;
-  double vx, vy, vz, m;
+  double vx, vy, vz;
+  int o;    // caller index
+  int box;  // box of the batched form (0 otherwise)
 };
 
 // Sphere status during a step: ACTIVE has a valid partner key (or none yet),
@@ -150,9 +156,9 @@ __device__ __forceinline__ bool pair_time(const Rec &a, const Rec &b, const Grid
 // Post-collision state of sphere `a` colliding with `b` at time t (rule 4,
 // Sec. "Inter-Particle Collisions" with friction 0, eq. update_vel/update_rho).
 // Bitwise independent of which of the two is `a`.
-__device__ __forceinline__ void resolve_one(const Rec &a, const Rec &b, const Grid &G, double t,
-                                            double dt, double e, double out_x[3],
-                                            double out_v[3]) {
+__device__ __forceinline__ void resolve_one(const Rec &a, const Rec &b, double ma, double mb,
+                                            const Grid &G, double t, double dt, double e,
+                                            double out_x[3], double out_v[3]) {
   const double d0 = wrap_sep(b.x - a.x, G.L[0], G.halfL[0]);
   const double d1 = wrap_sep(b.y - a.y, G.L[1], G.halfL[1]);
   const double d2 = wrap_sep(b.z - a.z, G.L[2], G.halfL[2]);
@@ -162,9 +168,9 @@ __device__ __forceinline__ void resolve_one(const Rec &a, const Rec &b, const Gr
   const double n1 = (d1 + t * u1) / s;
   const double n2 = (d2 + t * u2) / s;
   const double g = (u0 * n0 + u1 * n1) + u2 * n2;
-  const double mr = (a.m * b.m) / (a.m + b.m);
+  const double mr = (ma * mb) / (ma + mb);
   const double J = (mr * (1.0 + e)) * g;
-  const double ai = J / a.m;
+  const double ai = J / ma;
   out_v[0] = a.vx + ai * n0;
   out_v[1] = a.vy + ai * n1;
   out_v[2] = a.vz + ai * n2;
@@ -202,7 +208,6 @@ struct BatchDev {
   const Grid *gtab;       // [nbox]
   const int *cell_base;   // [nbox + 1]
   const int *box_of;      // caller order: box of each sphere
-  int *sbox;              // cell-sorted order: box of each sphere
   const int64_t *box_off; // [nbox + 1] sphere ranges (caller order)
   double *breach;         // [nbox] reach found by the last step
   unsigned int *flags;    // FLAG_* words
@@ -249,20 +254,21 @@ hipError_t launch_detect_wide(hipStream_t s, const DetectArgs &A, int first, int
 hipError_t launch_scan(hipStream_t s, const int *count, int ncell, int *start, int *blocksum,
                        ReachOut *out);
 hipError_t launch_scatter(hipStream_t s, const Particles &P, const Grid &G, const int *cid,
-                          const int *slot, const int *start, Rec *rec, Rec32 *rec32, int *perm,
-                          int *rank, const BatchDev *B);
+                          const int *slot, const int *start, Rec *rec, Rec32 *rec32, int *rank,
+                          const BatchDev *B);
 hipError_t launch_detect_half(hipStream_t s, const DetectArgs &A);
 hipError_t launch_slot_min(hipStream_t s, int n, int first, const int *cnt, const double *slot_t,
-                           const int *slot_j, int K, uint8_t *status, const int *perm, int *key_j,
+                           const int *slot_j, int K, uint8_t *status, const Rec *rec, int *key_j,
                            double *key_t, int *ovf_list, SweepCounters *ctr,
                            const unsigned int *flags, const int *list = nullptr, int nlist = 0);
 hipError_t launch_gather_exact(hipStream_t s, const int *list, int nlist, const unsigned int *nlist_dev,
                                int select, const Rec *rec, const int *start, const Grid &G,
-                               double dt, uint8_t *status, const int *perm, int *key_j,
-                               double *key_t, const BatchDev *B);
+                               double dt, uint8_t *status, int *key_j, double *key_t,
+                               const BatchDev *B);
 hipError_t launch_resolve_sweep(hipStream_t s, int n, const Rec *rec, const Grid &G, double dt,
-                                double e, const int *key_j, const double *key_t, uint8_t *status,
-                                const int *perm, OutRec *out, SweepCounters *ctr,
+                                double e, const double *mass, const int *key_j,
+                                const double *key_t, uint8_t *status, OutRec *out,
+                                SweepCounters *ctr,
                                 const BatchDev *B, const unsigned int *epoch,
                                 const int *list = nullptr, int nlist = 0);
 // next step's epoch (one thread); every OutRec epoch starts at 0xffffffff
@@ -273,9 +279,9 @@ hipError_t launch_init_out(hipStream_t s, OutRec *out, int64_t n);
 // ((n + 255) / 256) / 4096 + 2
 hipError_t launch_keep_list(hipStream_t s, const uint8_t *status, int n, int *count, int *off,
                             int *blocksum, ReachOut *scratch_out, int *list);
-hipError_t launch_finish(hipStream_t s, const Particles &P, const int *rank, const Rec *rec,
-                         const OutRec *out, const unsigned int *epoch, int *partner,
-                         double *tcoll, double dt, const Grid &G, const BatchDev *B);
+hipError_t launch_finish(hipStream_t s, const Particles &P, const int *rank, const OutRec *out,
+                         const unsigned int *epoch, int *partner, double *tcoll, double dt,
+                         const Grid &G, const BatchDev *B);
 hipError_t launch_fill_box_of(hipStream_t s, int nbox, const int64_t *box_off, int *box_of);
 hipError_t launch_breach(hipStream_t s, const Particles &P, const BatchDev &B, double dt,
                          int check_plan);
@@ -287,9 +293,9 @@ hipError_t launch_sweep_check(hipStream_t s, SweepCounters *ctr, unsigned int *f
                               unsigned long long *totals, int last);
 hipError_t launch_advance(hipStream_t s, const Particles &P, const int *partner, double dt,
                           const double L[3]);
-hipError_t launch_status_from_active(hipStream_t s, const uint8_t *active, const int *perm, int n,
+hipError_t launch_status_from_active(hipStream_t s, const uint8_t *active, const Rec *rec, int n,
                                      uint8_t *status);
-hipError_t launch_export_keys(hipStream_t s, int n, const int *perm, const int *key_j,
+hipError_t launch_export_keys(hipStream_t s, int n, const Rec *rec, const int *key_j,
                               const double *key_t, const uint8_t *status, uint64_t *key_out,
                               double *tmin_out);
 hipError_t launch_step_backward(hipStream_t s, const Particles &P, const Grid &G, double dt,

@@ -341,12 +341,12 @@ hipError_t launch_scan(hipStream_t s, const int *count, int ncell, int *start, i
 // ---------------------------------------------------------------- a4: scatter
 
 // cell-sorted 64-B records of the start-of-step state; reads the caller's SoA
-// arrays coalesced and writes one record per sphere.  With rec32 given, also
-// the 32-B FP32 filter record (position relative to the cell centre).
+// arrays coalesced and writes one record per sphere (its caller index and box
+// inside, so no other array is written in sorted order).  With rec32 given,
+// also the 32-B FP32 filter record (position relative to the cell centre).
 __global__ __launch_bounds__(256) void k_scatter(Particles P, Grid G, const int *cid,
                                                  const int *slot, const int *start, Rec *rec,
-                                                 Rec32 *rec32, int *perm, int *rank,
-                                                 const int *box_of, int *sbox,
+                                                 Rec32 *rec32, int *rank, const int *box_of,
                                                  const unsigned int *flags) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= P.n || (flags && flags[FLAG_ERR])) return;
@@ -360,11 +360,10 @@ __global__ __launch_bounds__(256) void k_scatter(Particles P, Grid G, const int 
   q.vx = P.vx[i];
   q.vy = P.vy[i];
   q.vz = P.vz[i];
-  q.m = P.m[i];
+  q.o = (int)i;
+  q.box = box_of ? box_of[i] : 0;
   rec[pos] = q;
-  perm[pos] = (int)i;
   rank[i] = pos;
-  if (sbox) sbox[pos] = box_of[i];
   if (rec32) {
     const int cl = c >= G.ncell ? c - G.ncell : c;  // cell within its layer
     const int cx = cl % G.nc[0], cy = (cl / G.nc[0]) % G.nc[1], cz = cl / (G.nc[0] * G.nc[1]);
@@ -382,12 +381,12 @@ __global__ __launch_bounds__(256) void k_scatter(Particles P, Grid G, const int 
 }
 
 hipError_t launch_scatter(hipStream_t s, const Particles &P, const Grid &G, const int *cid,
-                          const int *slot, const int *start, Rec *rec, Rec32 *rec32, int *perm,
-                          int *rank, const BatchDev *B) {
+                          const int *slot, const int *start, Rec *rec, Rec32 *rec32, int *rank,
+                          const BatchDev *B) {
   if (P.n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_scatter, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, s, P, G, cid,
-                     slot, start, rec, rec32, perm, rank, B ? B->box_of : nullptr,
-                     B ? B->sbox : nullptr, B ? (const unsigned int *)B->flags : nullptr);
+                     slot, start, rec, rec32, rank, B ? B->box_of : nullptr,
+                     B ? (const unsigned int *)B->flags : nullptr);
   return hipGetLastError();
 }
 
@@ -1194,7 +1193,7 @@ hipError_t launch_detect_half(hipStream_t s, const DetectArgs &A) {
 // k-major, so the reads of a wave are coalesced.
 __global__ __launch_bounds__(256) void k_slot_min(int n, int first, const int *cnt,
                                                   const double *slot_t, const int *slot_j, int K,
-                                                  uint8_t *status, const int *perm, int *key_j,
+                                                  uint8_t *status, const Rec *rec, int *key_j,
                                                   double *key_t, int *ovf_list,
                                                   SweepCounters *ctr, const unsigned int *flags,
                                                   const int *list, int nlist) {
@@ -1219,7 +1218,7 @@ __global__ __launch_bounds__(256) void k_slot_min(int n, int first, const int *c
           const int j = slot_j[(size_t)k * n + i];
           if (!first && status[j] == ST_COLLIDED) continue;
           const double t = slot_t[(size_t)k * n + i];
-          if (t < bt || (bj >= 0 && t == bt && perm[j] < perm[bj])) {
+          if (t < bt || (bj >= 0 && t == bt && rec[j].o < rec[bj].o)) {
             bt = t;
             bj = j;
           }
@@ -1236,13 +1235,13 @@ __global__ __launch_bounds__(256) void k_slot_min(int n, int first, const int *c
 }
 
 hipError_t launch_slot_min(hipStream_t s, int n, int first, const int *cnt, const double *slot_t,
-                           const int *slot_j, int K, uint8_t *status, const int *perm, int *key_j,
+                           const int *slot_j, int K, uint8_t *status, const Rec *rec, int *key_j,
                            double *key_t, int *ovf_list, SweepCounters *ctr,
                            const unsigned int *flags, const int *list, int nlist) {
   const int items = list ? nlist : n;
   if (items <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_slot_min, dim3((items + 255) / 256), dim3(256), 0, s, n, first, cnt, slot_t,
-                     slot_j, K, status, perm, key_j, key_t, ovf_list, ctr, flags, list, nlist);
+                     slot_j, K, status, rec, key_j, key_t, ovf_list, ctr, flags, list, nlist);
   return hipGetLastError();
 }
 
@@ -1465,8 +1464,7 @@ hipError_t launch_detect_wide(hipStream_t s, const DetectArgs &A, int first, int
 __global__ __launch_bounds__(256) void k_gather_exact(const int *list, int nlist,
                                                       const unsigned int *nlist_dev, int select,
                                                       const Rec *rec, const int *start, Grid G0,
-                                                      double dt, uint8_t *status,
-                                                      const int *perm, int *key_j,
+                                                      double dt, uint8_t *status, int *key_j,
                                                       double *key_t, BatchDev B) {
   if (B.flags && (B.flags[FLAG_ERR] || B.flags[FLAG_DONE])) return;
   const int lane = __lane_id();
@@ -1477,10 +1475,10 @@ __global__ __launch_bounds__(256) void k_gather_exact(const int *list, int nlist
     const int i = list ? list[w] : w;
     if (select >= 0 && status[i] != (uint8_t)select) continue;
     // the sphere's grid: the single one, or its box's in the batched form
-    const int bx = B.gtab ? B.sbox[i] : 0;
+    const Rec a = rec[i];
+    const int bx = B.gtab ? a.box : 0;
     const Grid G = B.gtab ? B.gtab[bx] : G0;
     const int *st = B.gtab ? start + B.cell_base[bx] : start;
-    const Rec a = rec[i];
     int k[3];
     search_radius(G, a, dt, k);
     const int cx = cell_coord(a.x, G.inv_h[0], G.nc[0]);
@@ -1496,7 +1494,7 @@ __global__ __launch_bounds__(256) void k_gather_exact(const int *list, int nlist
           const Rec b = rec[j];
           double t;
           if (pair_time(a, b, G, dt, t)) {
-            const int o = perm[j];
+            const int o = b.o;
             if (t < bt || (t == bt && o < bo)) {
               bt = t;
               bo = o;
@@ -1526,15 +1524,15 @@ __global__ __launch_bounds__(256) void k_gather_exact(const int *list, int nlist
 
 hipError_t launch_gather_exact(hipStream_t s, const int *list, int nlist, const unsigned int *nlist_dev,
                                int select, const Rec *rec, const int *start, const Grid &G,
-                               double dt, uint8_t *status, const int *perm, int *key_j,
-                               double *key_t, const BatchDev *B) {
+                               double dt, uint8_t *status, int *key_j, double *key_t,
+                               const BatchDev *B) {
   int64_t waves = nlist_dev ? 8192 : nlist;
   if (waves <= 0) return hipSuccess;
   if (waves > 8192) waves = 8192;
   const int blocks = (int)((waves + 3) / 4);
   BatchDev none{};
   hipLaunchKernelGGL(k_gather_exact, dim3(blocks), dim3(256), 0, s, list, nlist, nlist_dev, select,
-                     rec, start, G, dt, status, perm, key_j, key_t, B ? *B : none);
+                     rec, start, G, dt, status, key_j, key_t, B ? *B : none);
   return hipGetLastError();
 }
 
@@ -1550,9 +1548,9 @@ hipError_t launch_gather_exact(hipStream_t s, const int *list, int nlist, const 
 // pure function of the keys.  Partners are spatial neighbours, so the partner
 // reads stay within a few cells of the sorted order.
 __global__ __launch_bounds__(256) void k_resolve_sweep(int n, const Rec *rec, Grid G0, double dt,
-                                                       double e, const int *key_j,
-                                                       const double *key_t, uint8_t *status,
-                                                       const int *perm, OutRec *out,
+                                                       double e, const double *mass,
+                                                       const int *key_j, const double *key_t,
+                                                       uint8_t *status, OutRec *out,
                                                        SweepCounters *ctr, BatchDev B,
                                                        const unsigned int *epoch, const int *list,
                                                        int nlist) {
@@ -1570,12 +1568,13 @@ __global__ __launch_bounds__(256) void k_resolve_sweep(int n, const Rec *rec, Gr
       if (q == i) {
         const Rec a = rec[i], b = rec[p];
         const double t = key_t[i];
+        const double ma = mass[a.o], mb = mass[b.o];
         double xo[3], vo[3];
         if (B.gtab) {
-          const Grid G = B.gtab[B.sbox[i]];
-          resolve_one(a, b, G, t, dt, e, xo, vo);
+          const Grid G = B.gtab[a.box];
+          resolve_one(a, b, ma, mb, G, t, dt, e, xo, vo);
         } else {
-          resolve_one(a, b, G0, t, dt, e, xo, vo);
+          resolve_one(a, b, ma, mb, G0, t, dt, e, xo, vo);
         }
         OutRec o;
         o.x = xo[0];
@@ -1585,7 +1584,7 @@ __global__ __launch_bounds__(256) void k_resolve_sweep(int n, const Rec *rec, Gr
         o.vy = vo[1];
         o.vz = vo[2];
         o.t = t;
-        o.partner = perm[p];
+        o.partner = b.o;
         o.epoch = *epoch;
         out[i] = o;
         status[i] = ST_COLLIDED;
@@ -1599,15 +1598,15 @@ __global__ __launch_bounds__(256) void k_resolve_sweep(int n, const Rec *rec, Gr
 }
 
 hipError_t launch_resolve_sweep(hipStream_t s, int n, const Rec *rec, const Grid &G, double dt,
-                                double e, const int *key_j, const double *key_t, uint8_t *status,
-                                const int *perm, OutRec *out, SweepCounters *ctr,
-                                const BatchDev *B, const unsigned int *epoch, const int *list,
-                                int nlist) {
+                                double e, const double *mass, const int *key_j,
+                                const double *key_t, uint8_t *status, OutRec *out,
+                                SweepCounters *ctr, const BatchDev *B, const unsigned int *epoch,
+                                const int *list, int nlist) {
   const int items = list ? nlist : n;
   if (items <= 0) return hipSuccess;
   BatchDev none{};
   hipLaunchKernelGGL(k_resolve_sweep, dim3((items + 255) / 256), dim3(256), 0, s, n, rec, G, dt,
-                     e, key_j, key_t, status, perm, out, ctr, B ? *B : none, epoch, list, nlist);
+                     e, mass, key_j, key_t, status, out, ctr, B ? *B : none, epoch, list, nlist);
   return hipGetLastError();
 }
 
@@ -1671,8 +1670,8 @@ hipError_t launch_keep_list(hipStream_t s, const uint8_t *status, int n, int *co
 // a8 and the copy back: the end-of-step state of every sphere in the caller's
 // order (coalesced writes).  A sphere that collided takes the output record its
 // resolve wrote (stamped with this step's epoch); any other flies the whole
-// step from its start record (rule 5).
-__global__ __launch_bounds__(256) void k_finish(Particles P, const int *rank, const Rec *rec,
+// step from its start state, still in the caller's arrays (rule 5).
+__global__ __launch_bounds__(256) void k_finish(Particles P, const int *rank,
                                                 const OutRec *out, const unsigned int *epoch,
                                                 int *partner, double *tcoll, double dt, Grid G0,
                                                 BatchDev B) {
@@ -1693,14 +1692,13 @@ __global__ __launch_bounds__(256) void k_finish(Particles P, const int *rank, co
     t = r.t;
     pj = r.partner;
   } else {
-    const Rec a = rec[q];
     const double *L = B.gtab ? B.gtab[B.box_of[o]].L : G0.L;
-    x = wrap_pos(a.x + dt * a.vx, L[0]);
-    y = wrap_pos(a.y + dt * a.vy, L[1]);
-    z = wrap_pos(a.z + dt * a.vz, L[2]);
-    vx = a.vx;
-    vy = a.vy;
-    vz = a.vz;
+    vx = P.vx[o];
+    vy = P.vy[o];
+    vz = P.vz[o];
+    x = wrap_pos(P.x[o] + dt * vx, L[0]);
+    y = wrap_pos(P.y[o] + dt * vy, L[1]);
+    z = wrap_pos(P.z[o] + dt * vz, L[2]);
     t = __longlong_as_double(0x7ff8000000000000LL);  // NaN: no collision
     pj = -1;
   }
@@ -1714,13 +1712,13 @@ __global__ __launch_bounds__(256) void k_finish(Particles P, const int *rank, co
   tcoll[o] = t;
 }
 
-hipError_t launch_finish(hipStream_t s, const Particles &P, const int *rank, const Rec *rec,
-                         const OutRec *out, const unsigned int *epoch, int *partner,
-                         double *tcoll, double dt, const Grid &G, const BatchDev *B) {
+hipError_t launch_finish(hipStream_t s, const Particles &P, const int *rank, const OutRec *out,
+                         const unsigned int *epoch, int *partner, double *tcoll, double dt,
+                         const Grid &G, const BatchDev *B) {
   if (P.n <= 0) return hipSuccess;
   BatchDev none{};
-  hipLaunchKernelGGL(k_finish, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, s, P, rank, rec,
-                     out, epoch, partner, tcoll, dt, G, B ? *B : none);
+  hipLaunchKernelGGL(k_finish, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, s, P, rank, out,
+                     epoch, partner, tcoll, dt, G, B ? *B : none);
   return hipGetLastError();
 }
 
@@ -1750,28 +1748,28 @@ hipError_t launch_advance(hipStream_t s, const Particles &P, const int *partner,
 // caller active mask -> sorted status (inactive spheres are excluded like
 // collided ones)
 __global__ __launch_bounds__(256) void k_status_from_active(const uint8_t *active,
-                                                            const int *perm, int n,
+                                                            const Rec *rec, int n,
                                                             uint8_t *status) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
-  status[i] = (active ? active[perm[i]] != 0 : true) ? ST_ACTIVE : ST_COLLIDED;
+  status[i] = (active ? active[rec[i].o] != 0 : true) ? ST_ACTIVE : ST_COLLIDED;
 }
 
-hipError_t launch_status_from_active(hipStream_t s, const uint8_t *active, const int *perm, int n,
+hipError_t launch_status_from_active(hipStream_t s, const uint8_t *active, const Rec *rec, int n,
                                      uint8_t *status) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_status_from_active, dim3((n + 255) / 256), dim3(256), 0, s, active, perm,
+  hipLaunchKernelGGL(k_status_from_active, dim3((n + 255) / 256), dim3(256), 0, s, active, rec,
                      n, status);
   return hipGetLastError();
 }
 
 // keys in the caller's order: (bits of (float)t) << 32 | caller index of the partner
-__global__ __launch_bounds__(256) void k_export_keys(int n, const int *perm, const int *key_j,
+__global__ __launch_bounds__(256) void k_export_keys(int n, const Rec *rec, const int *key_j,
                                                      const double *key_t, const uint8_t *status,
                                                      uint64_t *key_out, double *tmin_out) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
-  const int o = perm[i];
+  const int o = rec[i].o;
   const int j = key_j[i];
   const bool has = j >= 0 && (!status || status[i] == ST_ACTIVE);
   uint64_t key = ~0ull;
@@ -1779,17 +1777,17 @@ __global__ __launch_bounds__(256) void k_export_keys(int n, const int *perm, con
   if (has) {
     t = key_t[i];
     const float tf = (float)t;
-    key = ((uint64_t)__float_as_uint(tf) << 32) | (uint64_t)(uint32_t)perm[j];
+    key = ((uint64_t)__float_as_uint(tf) << 32) | (uint64_t)(uint32_t)rec[j].o;
   }
   key_out[o] = key;
   if (tmin_out) tmin_out[o] = t;
 }
 
-hipError_t launch_export_keys(hipStream_t s, int n, const int *perm, const int *key_j,
+hipError_t launch_export_keys(hipStream_t s, int n, const Rec *rec, const int *key_j,
                               const double *key_t, const uint8_t *status, uint64_t *key_out,
                               double *tmin_out) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_export_keys, dim3((n + 255) / 256), dim3(256), 0, s, n, perm, key_j, key_t,
+  hipLaunchKernelGGL(k_export_keys, dim3((n + 255) / 256), dim3(256), 0, s, n, rec, key_j, key_t,
                      status, key_out, tmin_out);
   return hipGetLastError();
 }
@@ -1810,7 +1808,7 @@ __global__ __launch_bounds__(256) void k_resolve_public(int n, const Rec *rec, c
       double t;
       if (pair_time(a, b, G, dt, t)) {
         double xo[3], vo[3];
-        resolve_one(a, b, G, t, dt, e, xo, vo);
+        resolve_one(a, b, P.m[i], P.m[p], G, t, dt, e, xo, vo);
         P.x[i] = xo[0];
         P.y[i] = xo[1];
         P.z[i] = xo[2];
