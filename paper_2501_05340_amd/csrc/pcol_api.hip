@@ -34,6 +34,8 @@ struct pcol_ctx {
   int *start = nullptr;
   int *blocksum = nullptr;
   int64_t cell_cap = 0;
+  CellCount *cellc = nullptr;  // per-cell counts of the detect kernels
+  int64_t cellc_cap = 0;
 
   // sweep state
   int *cnt = nullptr;
@@ -215,7 +217,7 @@ void pcol_destroy(pcol_ctx *ctx) {
                  ctx->count,  ctx->start,  ctx->blocksum, ctx->cnt,      ctx->slot_t,
                  ctx->slot_j, ctx->key_j,  ctx->key_t,  ctx->status,      ctx->out,
                  ctx->ovf,    ctx->partner_tmp, ctx->tcoll_tmp, ctx->list_a, ctx->keep_cnt, ctx->keep_off, ctx->keep_bs, ctx->epoch_d,
-                 ctx->reach_d, ctx->ctr_d};
+                 ctx->reach_d, ctx->cellc, ctx->ctr_d};
   for (void *p : dev)
     if (p) (void)hipFree(p);
   if (ctx->reach_h) (void)hipHostFree(ctx->reach_h);
@@ -311,7 +313,9 @@ pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box
   PCOL_HIP(hipMemsetAsync(ctx->reach_d, 0, sizeof(ReachOut), s));
   PCOL_HIP(launch_fill_u32(s, (unsigned int *)&ctx->reach_d->rmin, 0u, 1));
   PCOL_HIP(launch_fill_u32(s, (unsigned int *)&ctx->reach_d->rmin + 1, 0x7ff00000u, 1));
-  PCOL_HIP(launch_reach(s, P, box->len, dt, ctx->reach_d));
+  // the extent histogram only picks the split extent: above 2^20 spheres it
+  // samples one sphere in 16 (the quantile of a million samples is as good)
+  PCOL_HIP(launch_reach(s, P, box->len, dt, p->n >= (1 << 20) ? 4 : 0, ctx->reach_d));
   PCOL_HIP(hipMemcpyAsync(ctx->reach_h, ctx->reach_d, sizeof(ReachOut), hipMemcpyDeviceToHost, s));
   PCOL_HIP(hipStreamSynchronize(s));
   const ReachOut ro = *ctx->reach_h;
@@ -334,8 +338,10 @@ pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box
   // of the others, and the grid keeps 3 cells per axis.
   double rho_c = INFINITY;
   const double q = ctx->opts.split_quantile;
+  double sampled = 0.0;
+  for (int k = 0; k < RHO_BINS; ++k) sampled += ro.hist[k];
   if (q > 0.0 && q < 1.0 && p->n >= 4096) {
-    const double target = ceil(q * (double)p->n);
+    const double target = ceil(q * sampled);
     double cum = 0.0;
     for (int k = 0; k < RHO_BINS - 1; ++k) {
       cum += ro.hist[k];
@@ -383,6 +389,8 @@ pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box
   }
   G.layer2 = split ? G.ncell : 0;
   G.rho_max = split ? rho_max : 0.0;
+  G.inv_row = 1.0 / G.nc[0];
+  G.inv_layer = 1.0 / ((double)G.nc[0] * G.nc[1]);
   const int cells_all = split ? 2 * G.ncell : G.ncell;
   if ((int64_t)cells_all + 2 > ctx->cell_cap) {
     if (ctx->count) (void)hipFree(ctx->count);
@@ -528,7 +536,16 @@ static pcol_status detect_all(pcol_ctx *ctx, double dt) {
   hipStream_t s = ctx->stream;
   const int n = (int)ctx->binned_n;
   if (!ctx->small) {
+    if (ctx->G.ncell > ctx->cellc_cap) {
+      if (ctx->cellc) (void)hipFree(ctx->cellc);
+      ctx->cellc = nullptr;
+      ctx->cellc_cap = 0;
+      if (dalloc(&ctx->cellc, (size_t)ctx->G.ncell) != hipSuccess)
+        return fail(ctx, PCOL_E_NOMEM, "cell counts");
+      ctx->cellc_cap = ctx->G.ncell;
+    }
     DetectArgs A{};
+    A.cellc = ctx->cellc;
     A.rec = ctx->rec;
     A.start = ctx->start;
     A.cnt = ctx->cnt;
@@ -576,6 +593,7 @@ static pcol_status detect_all(pcol_ctx *ctx, double dt) {
     PCOL_HIP(launch_fill_i32(s, ctx->cnt, 0, n));
     if (ctx->opts.timing) PCOL_HIP(hipEventRecord(ctx->ev[5], s));
     PCOL_HIP(launch_detect_half(s, A));
+    PCOL_HIP(launch_cell_counts(s, ctx->cellc, ctx->G.ncell, ctx->ctr_d));
     // spheres of large extent: exact search of their wider neighbourhood
     if (ctx->split) PCOL_HIP(launch_detect_wide(s, A, ctx->wide_first, ctx->n_wide));
     if (ctx->opts.timing) PCOL_HIP(hipEventRecord(ctx->ev[6], s));
@@ -854,6 +872,8 @@ bool box_grid(const double len[3], int64_t nb, double reach, double mult, Grid &
     G.h[a] = len[a] / q;
   }
   G.ncell = G.nc[0] * G.nc[1] * G.nc[2];
+  G.inv_row = 1.0 / G.nc[0];
+  G.inv_layer = 1.0 / ((double)G.nc[0] * G.nc[1]);
   return true;
 }
 

@@ -52,7 +52,20 @@ struct Grid {
   int layer2;       // first cell of the second layer (0: none)
   int pad_;
   double rho_max;
+  double inv_row;    // 1 / nc0 and 1 / (nc0 nc1): cell coordinates without division
+  double inv_layer;
 };
+
+// Coordinates of cell number c of one layer (c < 2^26, nc0 nc1 <= 2^20)
+// without integer division: (c + 0.5) inv is within 2^-26 of the exact
+// quotient, whose fractional part is at least 0.5 / divisor >= 2^-21 from an
+// integer, so truncating it gives the exact floor.
+__device__ __forceinline__ void cell_xyz(const Grid &G, int c, int &cx, int &cy, int &cz) {
+  cz = (int)(((double)c + 0.5) * G.inv_layer);
+  const int rem = c - cz * (G.nc[0] * G.nc[1]);
+  cy = (int)(((double)rem + 0.5) * G.inv_row);
+  cx = rem - cy * G.nc[0];
+}
 
 // Extent of a sphere over a step, r + |v| dt: two spheres can touch within the
 // step only if their separation is at most the sum of their extents.  Written
@@ -214,6 +227,11 @@ struct BatchDev {
   int nbox;
 };
 
+// Pair tests and filter survivors of one home cell (k_detect_half, k_detect_gram).
+struct CellCount {
+  unsigned long long tests, recheck;
+};
+
 // Everything the sweep-1 detect needs.
 struct DetectArgs {
   const Rec *rec;
@@ -240,14 +258,17 @@ struct DetectArgs {
   int gram;           // half-precision Gram filter on the matrix cores + FP64 recheck
   float tolg;         // its tolerance (bound on its rounding, see gram_tolerance)
   int *crowd;         // Gram filter: cells of more than GRAM_ROWS spheres, for the FP64 filter
+  CellCount *cellc;   // per home cell of the one-box detect kernels (G.ncell entries)
 };
 
 hipError_t launch_fill_u32(hipStream_t s, unsigned int *p, unsigned int v, int64_t n);
 hipError_t launch_fill_u8(hipStream_t s, uint8_t *p, uint8_t v, int64_t n);
 hipError_t launch_fill_f64(hipStream_t s, double *p, double v, int64_t n);
 hipError_t launch_fill_i32(hipStream_t s, int *p, int v, int64_t n);
+// hist_shift: the extent histogram covers the spheres whose index is a multiple
+// of 2^hist_shift (the maxima and the validity cover all)
 hipError_t launch_reach(hipStream_t s, const Particles &P, const double L[3], double dt,
-                        ReachOut *out);
+                        int hist_shift, ReachOut *out);
 hipError_t launch_cell_hist(hipStream_t s, const Particles &P, const Grid &G, double dt,
                             double rho_c, int *cid, int *slot, int *count);
 hipError_t launch_detect_wide(hipStream_t s, const DetectArgs &A, int first, int count);
@@ -257,6 +278,8 @@ hipError_t launch_scatter(hipStream_t s, const Particles &P, const Grid &G, cons
                           const int *slot, const int *start, Rec *rec, Rec32 *rec32, int *rank,
                           const BatchDev *B);
 hipError_t launch_detect_half(hipStream_t s, const DetectArgs &A);
+// adds the per-cell counts of launch_detect_half to ctr->shard[0]
+hipError_t launch_cell_counts(hipStream_t s, const CellCount *c, int n, SweepCounters *ctr);
 hipError_t launch_slot_min(hipStream_t s, int n, int first, const int *cnt, const double *slot_t,
                            const int *slot_j, int K, uint8_t *status, const Rec *rec, int *key_j,
                            double *key_t, int *ovf_list, SweepCounters *ctr,

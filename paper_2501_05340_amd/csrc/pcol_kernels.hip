@@ -114,16 +114,20 @@ hipError_t launch_fill_f64(hipStream_t s, double *p, double v, int64_t n) {
 
 // Largest |v|^2, radius and extent r + |v| dt, smallest radius, data validity,
 // and the histogram of extents (Sec. "Collision Operator": the halo must hold
-// every partner a sphere can reach within the step).  Grid-stride; each
-// workgroup histograms in LDS and adds its non-empty bins once.
+// every partner a sphere can reach within the step).  The maxima and the
+// validity cover every sphere; the histogram, which only picks the split
+// extent (a performance choice), covers the spheres whose index is a multiple
+// of 2^hist_shift.  Grid-stride; each workgroup histograms in LDS and adds its
+// non-empty bins once.
 __global__ __launch_bounds__(256) void k_reach(Particles P, double L0, double L1, double L2,
-                                               double dt, ReachOut *out) {
+                                               double dt, int hist_shift, ReachOut *out) {
   __shared__ unsigned int hist[RHO_BINS];
   for (int k = threadIdx.x; k < RHO_BINS; k += 256) hist[k] = 0u;
   __syncthreads();
   double v2 = 0.0, rm = 0.0, rn = INFINITY, em = 0.0;
   unsigned int bad = 0u;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t hmask = ((int64_t)1 << hist_shift) - 1;
   // four elements per thread per step: their loads are issued together
   for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i0 < P.n; i0 += 4 * stride) {
     double x[4], y[4], z[4], vx[4], vy[4], vz[4], r[4], m[4];
@@ -158,11 +162,11 @@ __global__ __launch_bounds__(256) void k_reach(Particles P, double L0, double L1
           v2 = w > v2 ? w : v2;
           rm = r[u] > rm ? r[u] : rm;
           rn = r[u] < rn ? r[u] : rn;
-          has = r[u] > 0.0;
-          if (has) {
+          if (r[u] > 0.0) {
             const double ex = extent(r[u], vx[u], vy[u], vz[u], dt);
             em = ex > em ? ex : em;
-            bin = rho_bin(ex);
+            has = ((i0 + u * stride) & hmask) == 0;
+            if (has) bin = rho_bin(ex);  // -1 (no lane's bin) for the others
           }
         }
       }
@@ -200,11 +204,12 @@ __global__ __launch_bounds__(256) void k_reach(Particles P, double L0, double L1
 }
 
 hipError_t launch_reach(hipStream_t s, const Particles &P, const double L[3], double dt,
-                        ReachOut *out) {
+                        int hist_shift, ReachOut *out) {
   int64_t g = (P.n + 255) / 256;
   if (g > 1024) g = 1024;
   if (g < 1) g = 1;
-  hipLaunchKernelGGL(k_reach, dim3((int)g), dim3(256), 0, s, P, L[0], L[1], L[2], dt, out);
+  hipLaunchKernelGGL(k_reach, dim3((int)g), dim3(256), 0, s, P, L[0], L[1], L[2], dt, hist_shift,
+                     out);
   return hipGetLastError();
 }
 
@@ -366,7 +371,8 @@ __global__ __launch_bounds__(256) void k_scatter(Particles P, Grid G, const int 
   rank[i] = pos;
   if (rec32) {
     const int cl = c >= G.ncell ? c - G.ncell : c;  // cell within its layer
-    const int cx = cl % G.nc[0], cy = (cl / G.nc[0]) % G.nc[1], cz = cl / (G.nc[0] * G.nc[1]);
+    int cx, cy, cz;
+    cell_xyz(G, cl, cx, cy, cz);
     Rec32 f;
     f.x = (float)(q.x - (cx + 0.5) * G.h[0]);
     f.y = (float)(q.y - (cy + 0.5) * G.h[1]);
@@ -579,7 +585,8 @@ struct CellRuns {
 
 __device__ __forceinline__ bool cell_runs(const Grid &G, const int *start, int cell, CellRuns &R) {
   const int nc0 = G.nc[0], nc1 = G.nc[1], nc2 = G.nc[2];
-  const int cx = cell % nc0, cy = (cell / nc0) % nc1, cz = cell / (nc0 * nc1);
+  int cx, cy, cz;
+  cell_xyz(G, cell, cx, cy, cz);
   const int dys[4] = {1, -1, 0, 1}, dzs[4] = {0, 1, 1, 1};
   // The 20 cell starts the runs below need, fetched by one vector load (lane
   // k loads slot k) instead of a chain of dependent scalar loads:
@@ -900,11 +907,9 @@ __global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
     __shared__ HomeQ hq[WAVE];
     detect_cell64(A, A.G, A.start, xcd_remap(blockIdx.x, gridDim.x), Q, hq);
   }
-  if (__lane_id() == 0) {
-    CounterShard &sh = A.ctr->shard[blockIdx.x % NSHARD];
-    if (FP32 && Q.pushed) atomicAdd(&sh.recheck, (unsigned long long)Q.pushed);
-    if (Q.tests) atomicAdd(&sh.tests, Q.tests);
-  }
+  // this cell's counts, summed by launch_cell_counts (a counter atomic per
+  // wave would serialise over the million cells)
+  if (__lane_id() == 0) A.cellc[blockIdx.x] = CellCount{Q.tests, FP32 ? Q.pushed : 0ull};
 }
 
 // ---------------------------------------------------------------- a5, Gram filter on the matrix cores
@@ -1102,11 +1107,7 @@ __global__ __launch_bounds__(WAVE) void k_detect_gram(DetectArgs A) {
   __shared__ GramLds S;
   SurvivorQueue Q{survq, 0, 0u, 2 * QCAP, 0ull};
   detect_cell_gram(A, A.G, A.start, xcd_remap(blockIdx.x, gridDim.x), Q, S);
-  if (__lane_id() == 0) {
-    CounterShard &sh = A.ctr->shard[blockIdx.x % NSHARD];
-    if (Q.pushed) atomicAdd(&sh.recheck, (unsigned long long)Q.pushed);
-    if (Q.tests) atomicAdd(&sh.tests, Q.tests);
-  }
+  if (__lane_id() == 0) A.cellc[blockIdx.x] = CellCount{Q.tests, (unsigned long long)Q.pushed};
 }
 
 // The cells the Gram kernel queued as crowded, through the binary64 filter;
@@ -1154,6 +1155,31 @@ __global__ __launch_bounds__(256) void k_detect_batched(DetectArgs A, BatchDev B
     const int base = B.cell_base[b];
     detect_cell64(A, G, A.start + base, item - base, Q, hq[wave]);
   }
+}
+
+// Sum of the per-cell counts of k_detect_half / k_detect_gram into shard 0
+// (one atomic per workgroup).
+__global__ __launch_bounds__(256) void k_cell_counts(const CellCount *c, int n,
+                                                     SweepCounters *ctr) {
+  unsigned long long t = 0ull, r = 0ull;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    t += c[i].tests;
+    r += c[i].recheck;
+  }
+  t = wave_sum(t);
+  r = wave_sum(r);
+  if (__lane_id() == 0) {
+    if (t) atomicAdd(&ctr->shard[0].tests, t);
+    if (r) atomicAdd(&ctr->shard[0].recheck, r);
+  }
+}
+
+hipError_t launch_cell_counts(hipStream_t s, const CellCount *c, int n, SweepCounters *ctr) {
+  if (n <= 0) return hipSuccess;
+  int g = (n + 255) / 256;
+  if (g > 256) g = 256;
+  hipLaunchKernelGGL(k_cell_counts, dim3(g), dim3(256), 0, s, c, n, ctr);
+  return hipGetLastError();
 }
 
 hipError_t launch_detect_half(hipStream_t s, const DetectArgs &A) {
