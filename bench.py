@@ -309,7 +309,7 @@ def main():
         ctx.close()
         return out
 
-    # filter 0: binary64 FMA filter (the plain FP64 path); 1: binary32 filter;
+    # filter 0: binary64 Gram filter (the plain FP64 path); 1: binary32 filter;
     # 2: fp16 Gram filter on the matrix cores.  Survivors of 1 and 2 go to the
     # binary64 rule, so every form computes the same step bitwise.
     specs = {"fp64": (0, args.split_quantile), "fp32": (1, args.split_quantile),
@@ -325,7 +325,7 @@ def main():
     det_total = sum(det_ms) * 1e-3
     achieved = tests * OPS_PER_PAIR_TEST / det_total
     flops = tests * FLOPS_PER_PAIR_TEST / det_total
-    form_names = {"fp64": "plain_fp64 (binary64 FMA filter)", "fp32": "binary32 filter + binary64 rule",
+    form_names = {"fp64": "plain_fp64 (binary64 Gram filter)", "fp32": "binary32 filter + binary64 rule",
                   "gram": "fp16 Gram filter on matrix cores + binary64 rule"}
     out = {
         "metric": METRIC,

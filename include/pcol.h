@@ -100,11 +100,11 @@ typedef struct {
   double cell_mult;   /* grid cell side >= reach * cell_mult, cell_mult >= 1 (default 1) */
   int max_sweeps;     /* 0: no cap (a step needs at most n/2 + 1 sweeps); pcol_step_batched:
                          sweeps captured in its graph (see there) */
-  int home_cells;     /* home cells per workgroup along x in the sweep-1 detect; 0 = auto */
+  int home_cells;     /* reserved, ignored: the sweep-1 detect runs one home cell per wave */
   int contact_slots;  /* contacts kept per sphere from the sweep-1 detect; spheres with more
                          fall back to an exact neighbourhood search (default 12) */
   int filter;         /* pair filter ahead of the exact rule (same results for every value):
-                         0 binary64 FMA filter; 1 binary32 filter, contact distance inflated by
+                         0 binary64 filter in Gram form; 1 binary32 filter, contact distance inflated by
                          a band; 2 Gram filter on the matrix cores (fp16 high and low parts,
                          fp32 accumulation).  Survivors of 1 and 2 are decided in binary64. */
   double band_rel;    /* FP32 filter safety band, relative to r_i + r_j (default 1e-4) */

@@ -278,7 +278,7 @@ hipError_t launch_scatter(hipStream_t s, const Particles &P, const Grid &G, cons
                           const int *slot, const int *start, Rec *rec, Rec32 *rec32, int *rank,
                           const BatchDev *B);
 hipError_t launch_detect_half(hipStream_t s, const DetectArgs &A);
-// adds the per-cell counts of launch_detect_half to ctr->shard[0]
+// adds the per-cell counts of launch_detect_half to the counter shards of ctr
 hipError_t launch_cell_counts(hipStream_t s, const CellCount *c, int n, SweepCounters *ctr);
 hipError_t launch_slot_min(hipStream_t s, int n, int first, const int *cnt, const double *slot_t,
                            const int *slot_j, int K, uint8_t *status, const Rec *rec, int *key_j,

@@ -1157,8 +1157,9 @@ __global__ __launch_bounds__(256) void k_detect_batched(DetectArgs A, BatchDev B
   }
 }
 
-// Sum of the per-cell counts of k_detect_half / k_detect_gram into shard 0
-// (one atomic per workgroup).
+// Sum of the per-cell counts of k_detect_half / k_detect_gram (a few cells per
+// thread, so the loads of a thread are few and in flight together; one atomic
+// per workgroup and counter, spread over the shards).
 __global__ __launch_bounds__(256) void k_cell_counts(const CellCount *c, int n,
                                                      SweepCounters *ctr) {
   unsigned long long t = 0ull, r = 0ull;
@@ -1166,18 +1167,14 @@ __global__ __launch_bounds__(256) void k_cell_counts(const CellCount *c, int n,
     t += c[i].tests;
     r += c[i].recheck;
   }
-  t = wave_sum(t);
-  r = wave_sum(r);
-  if (__lane_id() == 0) {
-    if (t) atomicAdd(&ctr->shard[0].tests, t);
-    if (r) atomicAdd(&ctr->shard[0].recheck, r);
-  }
+  block_add(t, &my_shard(ctr).tests);
+  block_add(r, &my_shard(ctr).recheck);
 }
 
 hipError_t launch_cell_counts(hipStream_t s, const CellCount *c, int n, SweepCounters *ctr) {
   if (n <= 0) return hipSuccess;
   int g = (n + 255) / 256;
-  if (g > 256) g = 256;
+  if (g > 2048) g = 2048;
   hipLaunchKernelGGL(k_cell_counts, dim3(g), dim3(256), 0, s, c, n, ctr);
   return hipGetLastError();
 }
