@@ -57,6 +57,10 @@ struct pcol_ctx {
   SweepCounters *ctr_d = nullptr;
   ReachOut *reach_h = nullptr;
   SweepCounters *ctr_h = nullptr;
+  // sweeps 2 on run on the device in groups: FLAG_* words and totals (pairs,
+  // contacts, overflow) with their pinned read-back
+  unsigned int *sflags = nullptr, *sflags_h = nullptr;
+  unsigned long long *stotals = nullptr, *stotals_h = nullptr;
   hipEvent_t ev[8] = {};
 
   bool binned = false;
@@ -72,6 +76,7 @@ struct pcol_ctx {
   double rho_c = INFINITY, rho_max = 0.0;
   int wide_first = 0, n_wide = 0;  // sorted range of the second layer
   int *wide_h = nullptr;           // pinned read-back of that range
+  bool bin_pending = false;        // maxcell and the range still in flight (bin_readback)
   // bounds for the first layer's pair test: reach, speed and radius
   double reach_pass = 0.0, vmax_pass = 0.0, rmax_pass = 0.0;
   double band = 0.0;   // FP32 filter band in use (relative to r_i + r_j)
@@ -217,12 +222,14 @@ void pcol_destroy(pcol_ctx *ctx) {
                  ctx->count,  ctx->start,  ctx->blocksum, ctx->cnt,      ctx->slot_t,
                  ctx->slot_j, ctx->key_j,  ctx->key_t,  ctx->status,      ctx->out,
                  ctx->ovf,    ctx->partner_tmp, ctx->tcoll_tmp, ctx->list_a, ctx->keep_cnt, ctx->keep_off, ctx->keep_bs, ctx->epoch_d,
-                 ctx->reach_d, ctx->cellc, ctx->ctr_d};
+                 ctx->reach_d, ctx->cellc, ctx->ctr_d, ctx->sflags, ctx->stotals};
   for (void *p : dev)
     if (p) (void)hipFree(p);
   if (ctx->reach_h) (void)hipHostFree(ctx->reach_h);
   if (ctx->ctr_h) (void)hipHostFree(ctx->ctr_h);
   if (ctx->wide_h) (void)hipHostFree(ctx->wide_h);
+  if (ctx->sflags_h) (void)hipHostFree(ctx->sflags_h);
+  if (ctx->stotals_h) (void)hipHostFree(ctx->stotals_h);
   if (ctx->nlist_h) (void)hipHostFree(ctx->nlist_h);
   for (hipEvent_t &e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
@@ -285,6 +292,10 @@ pcol_status pcol_create(pcol_ctx **out, int64_t n_max, void *hip_stream, const p
   A(dalloc(&ctx->tcoll_tmp, n));
   A(dalloc(&ctx->reach_d, 1));
   A(dalloc(&ctx->ctr_d, 1));
+  A(dalloc(&ctx->sflags, 16));
+  A(dalloc(&ctx->stotals, 4));
+  if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->sflags_h, 16 * sizeof(unsigned int));
+  if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->stotals_h, 4 * sizeof(unsigned long long));
   if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->reach_h, sizeof(ReachOut));
   if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->ctr_h, sizeof(SweepCounters));
   if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->wide_h, 2 * sizeof(int));
@@ -301,6 +312,17 @@ pcol_status pcol_create(pcol_ctx **out, int64_t n_max, void *hip_stream, const p
   }
   *out = ctx;
   return PCOL_OK;
+}
+
+// Host copies of the largest cell occupancy and the second layer's range,
+// once the read-backs pcol_bin queued have landed (after a stream
+// synchronisation).
+static void bin_readback(pcol_ctx *ctx) {
+  if (!ctx->bin_pending) return;
+  ctx->maxcell = (int)ctx->reach_h->maxcell;
+  ctx->wide_first = ctx->split ? ctx->wide_h[0] : (int)ctx->binned_n;
+  ctx->n_wide = (int)ctx->binned_n - ctx->wide_first;
+  ctx->bin_pending = false;
 }
 
 pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box, double dt) {
@@ -412,12 +434,14 @@ pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box
   PCOL_HIP(launch_scan(s, ctx->count, cells_all, ctx->start, ctx->blocksum, ctx->reach_d));
   PCOL_HIP(launch_scatter(s, P, G, ctx->cid, ctx->slot, ctx->start, ctx->rec,
                           ctx->opts.filter == 1 ? ctx->rec32 : nullptr, ctx->rank, nullptr));
+  // the largest cell and the second layer's range are read back without a
+  // wait: only the binary32 filter sizes a launch by them (its LDS staging);
+  // the other paths read them after their next synchronisation (bin_readback)
   PCOL_HIP(hipMemcpyAsync(&ctx->reach_h->maxcell, &ctx->reach_d->maxcell, sizeof(unsigned int),
                           hipMemcpyDeviceToHost, s));
   if (split)
     PCOL_HIP(hipMemcpyAsync(ctx->wide_h, ctx->start + G.layer2, sizeof(int), hipMemcpyDeviceToHost, s));
-  PCOL_HIP(hipStreamSynchronize(s));
-  ctx->maxcell = (int)ctx->reach_h->maxcell;
+  ctx->bin_pending = true;
   ctx->G = G;
   ctx->reach = reach;
   ctx->vmax = sqrt(v2);
@@ -427,8 +451,6 @@ pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box
   ctx->split = split;
   ctx->rho_c = rho_c;
   ctx->rho_max = rho_max;
-  ctx->wide_first = split ? ctx->wide_h[0] : (int)p->n;
-  ctx->n_wide = (int)p->n - ctx->wide_first;
   // first-layer bounds: extent <= rho_c gives |v| <= (rho_c - r_min) / dt, r <= rho_c
   ctx->reach_pass = reach_pass;
   ctx->vmax_pass = split ? std::min(ctx->vmax, (rho_c - rmin) / dt) : ctx->vmax;
@@ -436,6 +458,10 @@ pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box
   ctx->binned = true;
   ctx->binned_n = p->n;
   ctx->binned_x = p->x;
+  if (ctx->opts.filter == 1) {
+    PCOL_HIP(hipStreamSynchronize(s));
+    bin_readback(ctx);
+  }
   return PCOL_OK;
 }
 
@@ -595,7 +621,7 @@ static pcol_status detect_all(pcol_ctx *ctx, double dt) {
     PCOL_HIP(launch_detect_half(s, A));
     PCOL_HIP(launch_cell_counts(s, ctx->cellc, ctx->G.ncell, ctx->ctr_d));
     // spheres of large extent: exact search of their wider neighbourhood
-    if (ctx->split) PCOL_HIP(launch_detect_wide(s, A, ctx->wide_first, ctx->n_wide));
+    if (ctx->split) PCOL_HIP(launch_detect_wide(s, A, ctx->start + ctx->G.layer2, n));
     if (ctx->opts.timing) PCOL_HIP(hipEventRecord(ctx->ev[6], s));
     ctx->detect_timed = true;
     PCOL_HIP(launch_slot_min(s, n, 1, ctx->cnt, ctx->slot_t, ctx->slot_j, ctx->K, ctx->status,
@@ -717,58 +743,90 @@ pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, dou
     // sweep 1 over every sphere; later sweeps over the list of the spheres it
     // left ACTIVE or DIRTY (the others are done for the step; entries that
     // finish later are skipped by their status)
-    const int *lin = nullptr;
-    int nlist = 0;
-    for (;;) {
-      PCOL_HIP(launch_resolve_sweep(s, n, ctx->rec, ctx->G, dt, e, P.m, ctx->key_j, ctx->key_t,
-                                    ctx->status, ctx->out, ctx->ctr_d, nullptr,
-                                    ctx->epoch_d, lin, nlist));
-      if (!lin) {
-        PCOL_HIP(launch_keep_list(s, ctx->status, n, ctx->keep_cnt, ctx->keep_off, ctx->keep_bs,
-                                  ctx->reach_d, ctx->list_a));
-        PCOL_HIP(hipMemcpyAsync(ctx->nlist_h, ctx->keep_off + (n + 255) / 256, sizeof(int),
-                                hipMemcpyDeviceToHost, s));
-      }
-      PCOL_HIP(hipMemcpyAsync(ctx->ctr_h, ctx->ctr_d, sizeof(SweepCounters),
-                              hipMemcpyDeviceToHost, s));
-      PCOL_HIP(hipStreamSynchronize(s));
+    PCOL_HIP(launch_resolve_sweep(s, n, ctx->rec, ctx->G, dt, e, P.m, ctx->key_j, ctx->key_t,
+                                  ctx->status, ctx->out, ctx->ctr_d, nullptr, ctx->epoch_d));
+    PCOL_HIP(launch_keep_list(s, ctx->status, n, ctx->keep_cnt, ctx->keep_off, ctx->keep_bs,
+                              ctx->reach_d, ctx->list_a));
+    PCOL_HIP(hipMemcpyAsync(ctx->nlist_h, ctx->keep_off + (n + 255) / 256, sizeof(int),
+                            hipMemcpyDeviceToHost, s));
+    PCOL_HIP(hipMemcpyAsync(ctx->ctr_h, ctx->ctr_d, sizeof(SweepCounters), hipMemcpyDeviceToHost,
+                            s));
+    PCOL_HIP(hipStreamSynchronize(s));
+    bin_readback(ctx);
+    {
       unsigned long long sp, sc;
       sum_counters(*ctx->ctr_h, sp, sc);
-      if (sweeps == 0) {
-        contacts = sc / 2ull;
-        for (int k = 0; k < NSHARD; ++k) {
-          recheck += ctx->ctr_h->shard[k].recheck;
-          tests += ctx->ctr_h->shard[k].tests;
-        }
+      contacts = sc / 2ull;
+      for (int k = 0; k < NSHARD; ++k) {
+        recheck += ctx->ctr_h->shard[k].recheck;
+        tests += ctx->ctr_h->shard[k].tests;
       }
-      ovf_total += ctx->ctr_h->n_overflow;
-      ++sweeps;
-      pairs += (int64_t)sp;
-      if (sp == 0ull) break;
-      if (ctx->opts.max_sweeps > 0 && sweeps >= ctx->opts.max_sweeps)
-        return fail(ctx, PCOL_E_SWEEPS, "sweep cap reached with pairs still resolving");
-      if (!lin) {
-        lin = ctx->list_a;
-        nlist = *ctx->nlist_h;
-      }
-      // next sweep: new partners for DIRTY spheres (partner collided elsewhere)
-      PCOL_HIP(hipMemsetAsync(ctx->ctr_d, 0, sizeof(SweepCounters), s));
-      if (!ctx->small) {
-        PCOL_HIP(launch_slot_min(s, n, 0, ctx->cnt, ctx->slot_t, ctx->slot_j, ctx->K, ctx->status,
-                                 ctx->rec, ctx->key_j, ctx->key_t, ctx->ovf, ctx->ctr_d, nullptr,
-                                 lin, nlist));
-        PCOL_HIP(launch_gather_exact(s, ctx->ovf, 0, &ctx->ctr_d->n_overflow, -1, ctx->rec,
-                                     ctx->start, ctx->G, dt, ctx->status, ctx->key_j,
-                                     ctx->key_t, nullptr));
-      } else {
-        PCOL_HIP(launch_gather_exact(s, lin, nlist, nullptr, ST_DIRTY, ctx->rec, ctx->start,
-                                     ctx->G, dt, ctx->status, ctx->key_j,
-                                     ctx->key_t, nullptr));
-      }
+      ovf_total = ctx->ctr_h->n_overflow;
+      sweeps = 1;
+      pairs = (int64_t)sp;
     }
-    if (timing) PCOL_HIP(hipEventRecord(ctx->ev[3], s));
-    PCOL_HIP(launch_finish(s, P, ctx->rank, ctx->out, ctx->epoch_d, part, tc, dt, ctx->G,
-                           nullptr));
+    const int *lin = ctx->list_a;
+    const int nlist = *ctx->nlist_h;
+    // Later sweeps run on the device in groups without a host round trip per
+    // sweep: each ends with k_sweep_check, which totals its pairs and, at zero,
+    // raises FLAG_DONE, turning every later kernel into an early exit.  The
+    // group's last check raises FLAG_UNFINISHED if that sweep still paired, so
+    // the free flight queued behind the group only runs once the step is done.
+    BatchDev Bf{};
+    Bf.flags = ctx->sflags;
+    const bool more = pairs > 0;
+    if (more && ctx->opts.max_sweeps == 1)
+      return fail(ctx, PCOL_E_SWEEPS, "sweep cap reached with pairs still resolving");
+    if (more) {
+      PCOL_HIP(launch_fill_u32(s, ctx->sflags, 0u, 16));
+      PCOL_HIP(launch_fill_u32(s, (unsigned int *)ctx->stotals, 0u, 8));
+      PCOL_HIP(hipMemsetAsync(ctx->ctr_d, 0, sizeof(SweepCounters), s));
+    }
+    for (int group = 0; more; ++group) {
+      int S = group == 0 ? 5 : 2;  // a step takes about six sweeps at 16M
+      if (ctx->opts.max_sweeps > 0 && S > ctx->opts.max_sweeps - (int)sweeps)
+        S = ctx->opts.max_sweeps - (int)sweeps;
+      for (int k = 0; k < S; ++k) {
+        // new partners for DIRTY spheres (partner collided elsewhere), then the resolve
+        if (!ctx->small) {
+          PCOL_HIP(launch_slot_min(s, n, 0, ctx->cnt, ctx->slot_t, ctx->slot_j, ctx->K,
+                                   ctx->status, ctx->rec, ctx->key_j, ctx->key_t, ctx->ovf,
+                                   ctx->ctr_d, ctx->sflags, lin, nlist));
+          PCOL_HIP(launch_gather_exact(s, ctx->ovf, 0, &ctx->ctr_d->n_overflow, -1, ctx->rec,
+                                       ctx->start, ctx->G, dt, ctx->status, ctx->key_j,
+                                       ctx->key_t, &Bf));
+        } else {
+          PCOL_HIP(launch_gather_exact(s, lin, nlist, nullptr, ST_DIRTY, ctx->rec, ctx->start,
+                                       ctx->G, dt, ctx->status, ctx->key_j, ctx->key_t, &Bf));
+        }
+        PCOL_HIP(launch_resolve_sweep(s, n, ctx->rec, ctx->G, dt, e, P.m, ctx->key_j,
+                                      ctx->key_t, ctx->status, ctx->out, ctx->ctr_d, &Bf,
+                                      ctx->epoch_d, lin, nlist));
+        PCOL_HIP(launch_sweep_check(s, ctx->ctr_d, ctx->sflags, ctx->stotals, k == S - 1));
+      }
+      if (timing) PCOL_HIP(hipEventRecord(ctx->ev[3], s));
+      PCOL_HIP(launch_finish(s, P, ctx->rank, ctx->out, ctx->epoch_d, part, tc, dt, ctx->G,
+                             &Bf));
+      PCOL_HIP(hipMemcpyAsync(ctx->sflags_h, ctx->sflags, 4 * sizeof(unsigned int),
+                              hipMemcpyDeviceToHost, s));
+      PCOL_HIP(hipMemcpyAsync(ctx->stotals_h, ctx->stotals, 3 * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, s));
+      PCOL_HIP(hipStreamSynchronize(s));
+      if (ctx->sflags_h[FLAG_DONE]) break;
+      if (ctx->opts.max_sweeps > 0 && 1 + (int)ctx->sflags_h[FLAG_SWEEPS] >= ctx->opts.max_sweeps)
+        return fail(ctx, PCOL_E_SWEEPS, "sweep cap reached with pairs still resolving");
+      sweeps = 1 + ctx->sflags_h[FLAG_SWEEPS];
+      PCOL_HIP(launch_fill_u32(s, ctx->sflags + FLAG_UNFINISHED, 0u, 1));
+    }
+    if (more) {
+      sweeps = 1 + ctx->sflags_h[FLAG_SWEEPS];
+      pairs += (int64_t)ctx->stotals_h[0];
+      ovf_total += (int64_t)ctx->stotals_h[2];
+    } else {
+      if (timing) PCOL_HIP(hipEventRecord(ctx->ev[3], s));
+      PCOL_HIP(launch_finish(s, P, ctx->rank, ctx->out, ctx->epoch_d, part, tc, dt, ctx->G,
+                             nullptr));
+    }
     if (timing) {
       PCOL_HIP(hipEventRecord(ctx->ev[4], s));
       PCOL_HIP(hipEventSynchronize(ctx->ev[4]));
@@ -777,6 +835,10 @@ pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, dou
     }
   }
   if (stats) {
+    if (ctx->bin_pending) {  // an empty step: nothing waited for the read-backs yet
+      PCOL_HIP(hipStreamSynchronize(s));
+      bin_readback(ctx);
+    }
     memset(stats, 0, sizeof(*stats));
     stats->n_pairs = pairs;
     stats->n_sweeps = sweeps;

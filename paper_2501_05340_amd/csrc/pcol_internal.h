@@ -271,7 +271,8 @@ hipError_t launch_reach(hipStream_t s, const Particles &P, const double L[3], do
                         int hist_shift, ReachOut *out);
 hipError_t launch_cell_hist(hipStream_t s, const Particles &P, const Grid &G, double dt,
                             double rho_c, int *cid, int *slot, int *count);
-hipError_t launch_detect_wide(hipStream_t s, const DetectArgs &A, int first, int count);
+// the spheres of the second layer, sorted positions [*first_dev, n)
+hipError_t launch_detect_wide(hipStream_t s, const DetectArgs &A, const int *first_dev, int n);
 hipError_t launch_scan(hipStream_t s, const int *count, int ncell, int *start, int *blocksum,
                        ReachOut *out);
 hipError_t launch_scatter(hipStream_t s, const Particles &P, const Grid &G, const int *cid,

@@ -1397,7 +1397,8 @@ __device__ __forceinline__ void wide_run(const Grid &G, const int *start, int r,
 // the scanned lengths held across the wave.  An FMA pre-filter (tolerance for
 // the full reach) keeps the exact rule for the few pairs that may touch;
 // survivors are decided at once (they are rare).
-__global__ __launch_bounds__(256) void k_detect_wide(DetectArgs A, int first, int count) {
+__global__ __launch_bounds__(256) void k_detect_wide(DetectArgs A, const int *first_dev, int n) {
+  const int first = *first_dev, count = n - first;
   const int lane = __lane_id();
   const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   const int nw = (gridDim.x * blockDim.x) / WAVE;
@@ -1466,11 +1467,12 @@ __global__ __launch_bounds__(256) void k_detect_wide(DetectArgs A, int first, in
   block_add(tests, &my_shard(A.ctr).tests);
 }
 
-hipError_t launch_detect_wide(hipStream_t s, const DetectArgs &A, int first, int count) {
-  if (count <= 0) return hipSuccess;
-  const int64_t waves = count < (1 << 20) ? count : (1 << 20);
-  hipLaunchKernelGGL(k_detect_wide, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, A, first,
-                     count);
+hipError_t launch_detect_wide(hipStream_t s, const DetectArgs &A, const int *first_dev, int n) {
+  if (n <= 0) return hipSuccess;
+  // the range is on the device (no read-back before the launch): waves loop over it
+  const int64_t waves = n < 4096 ? n : 4096;
+  hipLaunchKernelGGL(k_detect_wide, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, A,
+                     first_dev, n);
   return hipGetLastError();
 }
 
