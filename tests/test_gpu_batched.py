@@ -18,7 +18,7 @@ from workloads import Box
 
 pytestmark = pytest.mark.gpu
 
-pc = pytest.importorskip("paper_2501_05340_amd")
+import paper_2501_05340_amd as pc  # noqa: E402  (no CPU fallback: a missing library fails)
 
 FIELDS = ("x", "y", "z", "vx", "vy", "vz")
 ALL = FIELDS + ("r", "m")

@@ -21,7 +21,7 @@ import workloads
 
 pytestmark = pytest.mark.gpu
 
-pc = pytest.importorskip("paper_2501_05340_amd")
+import paper_2501_05340_amd as pc  # noqa: E402  (no CPU fallback: a missing library fails)
 
 FIELDS = ("x", "y", "z", "vx", "vy", "vz")
 

@@ -14,7 +14,7 @@ from tests.gpu_helpers import FIELDS, compare_step, gpu_step
 
 pytestmark = pytest.mark.gpu
 
-pc = pytest.importorskip("paper_2501_05340_amd")
+import paper_2501_05340_amd as pc  # noqa: E402  (no CPU fallback: a missing library fails)
 
 
 def _announce(msg):

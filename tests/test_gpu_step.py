@@ -15,7 +15,7 @@ from tests.gpu_helpers import FIELDS, box_slice, compare_step, gpu_step
 
 pytestmark = pytest.mark.gpu
 
-pc = pytest.importorskip("paper_2501_05340_amd")
+import paper_2501_05340_amd as pc  # noqa: E402  (no CPU fallback: a missing library fails)
 
 
 def _announce(msg):
@@ -298,3 +298,44 @@ def test_gram_filter_crowded_cells_fall_back(poly20k):
     for f in FIELDS:
         assert np.array_equal(a[0][f].view(np.uint64), b[0][f].view(np.uint64))
     assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2], equal_nan=True)
+
+
+def _chain(n=40):
+    """Spheres on a line, each closing on its right neighbour at the same speed with
+    gaps shrinking to the right: every sphere's earliest partner is its right
+    neighbour, so only the last pair is mutual, and each sweep resolves one pair
+    from the right end: n/2 pairs in n/2 sweeps plus one that finds none."""
+    r = np.full(n, 0.5)
+    gap = 0.05 - 0.001 * np.arange(n - 1)
+    x = 10.0 + np.concatenate([[0.0], np.cumsum(1.0 + gap)])
+    vx = -0.01 * np.arange(n)
+    z = np.full(n, 200.0)
+    return workloads.Box(x, z.copy(), z.copy(), vx, np.zeros(n), np.zeros(n), r, np.ones(n),
+                         (400.0, 400.0, 400.0), 6.0, 0.9)
+
+
+def test_sweeps_beyond_one_device_group():
+    """21 sweeps: the later sweeps run on the device in several groups (the first
+    group's last check leaves the step unfinished, the host re-arms and queues more),
+    against the oracle; the sweep cap at and before the last pairing sweep."""
+    box = _chain()
+    _announce(f"sweep chain n={box.n}")
+    gpu = gpu_step(box)
+    orc = oracle.step(box)
+    assert compare_step(box, gpu, orc) == 0
+    st = gpu[3]
+    assert st["nc"][0] >= 3 and st["n_pairs"] == 20 and st["n_sweeps"] == 21
+    assert orc.n_pairs == 20 and orc.n_sweeps == 21
+    # a cap that the last sweep (no pairs) meets is fine; one that the last pairing
+    # sweep meets is an error, and the caller's arrays are left as they were
+    gpu2 = gpu_step(box, max_sweeps=21)
+    assert compare_step(box, gpu2, orc) == 0
+    for cap in (20, 6, 2):
+        ctx = pc.Context(box.n, pc.pcol_default_opts(max_sweeps=cap))
+        p = pc.Particles.from_box(box)
+        before = [t.clone() for t in p.tensors()]
+        with pytest.raises(pc.PcolError) as ei:
+            pc.pcol_step(ctx, p, box.L, box.dt, box.e)
+        assert ei.value.code == pc.PCOL_E_SWEEPS, cap
+        for t0, t1 in zip(before, p.tensors()):
+            assert torch.equal(t0.view(torch.int64), t1.view(torch.int64)), cap
