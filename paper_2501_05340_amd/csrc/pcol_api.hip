@@ -572,6 +572,9 @@ static pcol_status detect_all(pcol_ctx *ctx, double dt) {
     }
     DetectArgs A{};
     A.cellc = ctx->cellc;
+    // sparse cells (the split grid holds about 13 spheres per cell at 16M): four
+    // cells per workgroup, so their filter survivors are decided together
+    A.cpw = ctx->opts.filter == 0 && n < 24 * (int64_t)ctx->G.ncell ? 4 : 1;
     A.rec = ctx->rec;
     A.start = ctx->start;
     A.cnt = ctx->cnt;
@@ -619,7 +622,7 @@ static pcol_status detect_all(pcol_ctx *ctx, double dt) {
     PCOL_HIP(launch_fill_i32(s, ctx->cnt, 0, n));
     if (ctx->opts.timing) PCOL_HIP(hipEventRecord(ctx->ev[5], s));
     PCOL_HIP(launch_detect_half(s, A));
-    PCOL_HIP(launch_cell_counts(s, ctx->cellc, ctx->G.ncell, ctx->ctr_d));
+    PCOL_HIP(launch_cell_counts(s, ctx->cellc, detect_half_blocks(A), ctx->ctr_d));
     // spheres of large extent: exact search of their wider neighbourhood
     if (ctx->split) PCOL_HIP(launch_detect_wide(s, A, ctx->start + ctx->G.layer2, n));
     if (ctx->opts.timing) PCOL_HIP(hipEventRecord(ctx->ev[6], s));

@@ -258,7 +258,8 @@ struct DetectArgs {
   int gram;           // half-precision Gram filter on the matrix cores + FP64 recheck
   float tolg;         // its tolerance (bound on its rounding, see gram_tolerance)
   int *crowd;         // Gram filter: cells of more than GRAM_ROWS spheres, for the FP64 filter
-  CellCount *cellc;   // per home cell of the one-box detect kernels (G.ncell entries)
+  CellCount *cellc;   // per workgroup of the one-box detect kernels (G.ncell entries)
+  int cpw;            // binary64 filter: home cells per workgroup (1: one cell per wave)
 };
 
 hipError_t launch_fill_u32(hipStream_t s, unsigned int *p, unsigned int v, int64_t n);
@@ -279,6 +280,8 @@ hipError_t launch_scatter(hipStream_t s, const Particles &P, const Grid &G, cons
                           const int *slot, const int *start, Rec *rec, Rec32 *rec32, int *rank,
                           const BatchDev *B);
 hipError_t launch_detect_half(hipStream_t s, const DetectArgs &A);
+// workgroups of launch_detect_half, each writing one CellCount
+int detect_half_blocks(const DetectArgs &A);
 // adds the per-cell counts of launch_detect_half to the counter shards of ctr
 hipError_t launch_cell_counts(hipStream_t s, const CellCount *c, int n, SweepCounters *ctr);
 hipError_t launch_slot_min(hipStream_t s, int n, int first, const int *cnt, const double *slot_t,

@@ -893,7 +893,8 @@ __device__ __forceinline__ void detect_cell64(const DetectArgs &A, const Grid &G
         detect_chunk64<false>(A, G, hq, nb, h0 + hb, g, thr, P, beta, Q);
     }
   }
-  flush_survivors(A, G, Q);
+  // the survivors left in Q are the caller's to decide (flush_survivors), now
+  // or after later cells of the same grid
 }
 
 template <bool FP32, bool LDSI>
@@ -906,10 +907,37 @@ __global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
   } else {
     __shared__ HomeQ hq[WAVE];
     detect_cell64(A, A.G, A.start, xcd_remap(blockIdx.x, gridDim.x), Q, hq);
+    flush_survivors(A, A.G, Q);
   }
   // this cell's counts, summed by launch_cell_counts (a counter atomic per
   // wave would serialise over the million cells)
   if (__lane_id() == 0) A.cellc[blockIdx.x] = CellCount{Q.tests, FP32 ? Q.pushed : 0ull};
+}
+
+// The binary64 filter over A.cpw consecutive cells per workgroup, for sparse
+// cells: the survivor queue carries over between them and is decided a wave at
+// a time (a cell of 13 spheres leaves about 13 survivors, so deciding them
+// per cell runs the rule's square root and division on a fifth of the lanes).
+// Register-limited to 5 waves per SIMD (a few spills in the per-cell set-up).
+__global__ __launch_bounds__(WAVE, 5) void k_detect_half64g(DetectArgs A) {
+  __shared__ int2 survq[QCAP];
+  __shared__ HomeQ hq[WAVE];
+  SurvivorQueue Q{survq, 0, 0u, QCAP, 0ull};
+  const int c0 = xcd_remap(blockIdx.x, gridDim.x) * A.cpw;
+  const int c1 = c0 + A.cpw < A.G.ncell ? c0 + A.cpw : A.G.ncell;
+  for (int cell = c0; cell < c1; ++cell) {  // one flush site (register pressure)
+    detect_cell64(A, A.G, A.start, cell, Q, hq);
+    if (cell + 1 == c1 || Q.n >= WAVE) flush_survivors(A, A.G, Q);
+  }
+  if (__lane_id() == 0) A.cellc[blockIdx.x] = CellCount{Q.tests, 0ull};
+}
+
+// Workgroups of launch_detect_half (one wave each): one per cell, but for the
+// persistent binary64 kernel a multiple of 8 (the XCDs) near the waves the
+// chip holds at once.  Also the number of per-workgroup counts it writes.
+int detect_half_blocks(const DetectArgs &A) {
+  if (A.gram || A.fp32 || A.cpw <= 1) return A.G.ncell;
+  return (A.G.ncell + A.cpw - 1) / A.cpw;
 }
 
 // ---------------------------------------------------------------- a5, Gram filter on the matrix cores
@@ -1119,6 +1147,7 @@ __global__ __launch_bounds__(WAVE) void k_detect_list(DetectArgs A) {
   const int count = (int)A.ctr->n_crowd;
   for (int w = blockIdx.x; w < count; w += gridDim.x)
     detect_cell64(A, A.G, A.start, A.crowd[w], Q, hq);
+  flush_survivors(A, A.G, Q);
   if (__lane_id() == 0 && Q.tests) atomicAdd(&A.ctr->shard[blockIdx.x % NSHARD].tests, Q.tests);
 }
 
@@ -1154,6 +1183,7 @@ __global__ __launch_bounds__(256) void k_detect_batched(DetectArgs A, BatchDev B
     const Grid G = B.gtab[b];
     const int base = B.cell_base[b];
     detect_cell64(A, G, A.start + base, item - base, Q, hq[wave]);
+    flush_survivors(A, G, Q);  // the next item may be another box's grid
   }
 }
 
@@ -1197,6 +1227,8 @@ hipError_t launch_detect_half(hipStream_t s, const DetectArgs &A) {
   } else {
     if (A.fp32)
       hipLaunchKernelGGL((k_detect_half<true, false>), dim3(A.G.ncell), dim3(WAVE), 0, s, A);
+    else if (A.cpw > 1)
+      hipLaunchKernelGGL(k_detect_half64g, dim3(detect_half_blocks(A)), dim3(WAVE), 0, s, A);
     else
       hipLaunchKernelGGL((k_detect_half<false, false>), dim3(A.G.ncell), dim3(WAVE), 0, s, A);
   }
