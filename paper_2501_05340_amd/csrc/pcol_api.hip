@@ -573,8 +573,9 @@ static pcol_status detect_all(pcol_ctx *ctx, double dt) {
     DetectArgs A{};
     A.cellc = ctx->cellc;
     // sparse cells (the split grid holds about 13 spheres per cell at 16M): four
-    // cells per workgroup, so their filter survivors are decided together
-    A.cpw = ctx->opts.filter == 0 && n < 24 * (int64_t)ctx->G.ncell ? 4 : 1;
+    // cells per workgroup for the binary64 and binary32 filters, so their
+    // survivors are decided together
+    A.cpw = ctx->opts.filter != 2 && n < 24 * (int64_t)ctx->G.ncell ? 4 : 1;
     A.rec = ctx->rec;
     A.start = ctx->start;
     A.cnt = ctx->cnt;

@@ -761,7 +761,7 @@ __device__ __forceinline__ void detect_cell(const DetectArgs &A, const Grid &G, 
       }
     }
   }
-  flush_survivors(A, G, Q);
+  // the survivors left in Q are the caller's to decide
 }
 
 // ---------------------------------------------------------------- a5, binary64 Gram filter
@@ -902,8 +902,13 @@ __global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
   extern __shared__ double4 lds_raw[];  // LDSI: the home cell's FP32 records
   __shared__ int2 survq[QCAP];
   SurvivorQueue Q{survq, 0, 0u, QCAP, 0ull};
-  if (FP32) {
-    detect_cell<true, LDSI>(A, A.G, A.start, xcd_remap(blockIdx.x, gridDim.x), Q, lds_raw);
+  if (FP32) {  // A.cpw consecutive cells per workgroup (see k_detect_half64g)
+    const int c0 = xcd_remap(blockIdx.x, gridDim.x) * A.cpw;
+    const int c1 = c0 + A.cpw < A.G.ncell ? c0 + A.cpw : A.G.ncell;
+    for (int cell = c0; cell < c1; ++cell) {
+      detect_cell<true, LDSI>(A, A.G, A.start, cell, Q, lds_raw);
+      if (cell + 1 == c1 || Q.n >= WAVE) flush_survivors(A, A.G, Q);
+    }
   } else {
     __shared__ HomeQ hq[WAVE];
     detect_cell64(A, A.G, A.start, xcd_remap(blockIdx.x, gridDim.x), Q, hq);
@@ -936,7 +941,7 @@ __global__ __launch_bounds__(WAVE, 5) void k_detect_half64g(DetectArgs A) {
 // persistent binary64 kernel a multiple of 8 (the XCDs) near the waves the
 // chip holds at once.  Also the number of per-workgroup counts it writes.
 int detect_half_blocks(const DetectArgs &A) {
-  if (A.gram || A.fp32 || A.cpw <= 1) return A.G.ncell;
+  if (A.gram || A.cpw <= 1) return A.G.ncell;
   return (A.G.ncell + A.cpw - 1) / A.cpw;
 }
 
@@ -1221,12 +1226,14 @@ hipError_t launch_detect_half(hipStream_t s, const DetectArgs &A) {
   const size_t lds = (size_t)A.cap * (A.fp32 ? sizeof(Rec32) : sizeof(Rec));
   if (A.cap > 0) {
     if (A.fp32)
-      hipLaunchKernelGGL((k_detect_half<true, true>), dim3(A.G.ncell), dim3(WAVE), lds, s, A);
+      hipLaunchKernelGGL((k_detect_half<true, true>), dim3(detect_half_blocks(A)), dim3(WAVE), lds,
+                         s, A);
     else
       hipLaunchKernelGGL((k_detect_half<false, true>), dim3(A.G.ncell), dim3(WAVE), lds, s, A);
   } else {
     if (A.fp32)
-      hipLaunchKernelGGL((k_detect_half<true, false>), dim3(A.G.ncell), dim3(WAVE), 0, s, A);
+      hipLaunchKernelGGL((k_detect_half<true, false>), dim3(detect_half_blocks(A)), dim3(WAVE), 0,
+                         s, A);
     else if (A.cpw > 1)
       hipLaunchKernelGGL(k_detect_half64g, dim3(detect_half_blocks(A)), dim3(WAVE), 0, s, A);
     else
