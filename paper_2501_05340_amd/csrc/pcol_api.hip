@@ -771,22 +771,53 @@ pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, dou
     }
     const int *lin = ctx->list_a;
     const int nlist = *ctx->nlist_h;
-    // Later sweeps run on the device in groups without a host round trip per
-    // sweep: each ends with k_sweep_check, which totals its pairs and, at zero,
-    // raises FLAG_DONE, turning every later kernel into an early exit.  The
-    // group's last check raises FLAG_UNFINISHED if that sweep still paired, so
-    // the free flight queued behind the group only runs once the step is done.
+    // Later sweeps over a long list run on the device in groups without a host
+    // round trip per sweep: each ends with k_sweep_check, which totals its pairs
+    // and, at zero, raises FLAG_DONE, turning every later kernel into an early
+    // exit.  The group's last check raises FLAG_UNFINISHED if that sweep still
+    // paired, so the free flight queued behind the group only runs once the step
+    // is done.  A short list (small boxes, where launches cost more than the
+    // kernels) takes one sweep per round trip, with no launches to spare.
     BatchDev Bf{};
     Bf.flags = ctx->sflags;
     const bool more = pairs > 0;
+    const bool groups = nlist >= (1 << 16);
     if (more && ctx->opts.max_sweeps == 1)
       return fail(ctx, PCOL_E_SWEEPS, "sweep cap reached with pairs still resolving");
-    if (more) {
+    while (more && !groups) {
+      PCOL_HIP(hipMemsetAsync(ctx->ctr_d, 0, sizeof(SweepCounters), s));
+      if (!ctx->small) {
+        PCOL_HIP(launch_slot_min(s, n, 0, ctx->cnt, ctx->slot_t, ctx->slot_j, ctx->K,
+                                 ctx->status, ctx->rec, ctx->key_j, ctx->key_t, ctx->ovf,
+                                 ctx->ctr_d, nullptr, lin, nlist));
+        PCOL_HIP(launch_gather_exact(s, ctx->ovf, 0, &ctx->ctr_d->n_overflow, -1, ctx->rec,
+                                     ctx->start, ctx->G, dt, ctx->status, ctx->key_j,
+                                     ctx->key_t, nullptr));
+      } else {
+        PCOL_HIP(launch_gather_exact(s, lin, nlist, nullptr, ST_DIRTY, ctx->rec, ctx->start,
+                                     ctx->G, dt, ctx->status, ctx->key_j, ctx->key_t, nullptr));
+      }
+      PCOL_HIP(launch_resolve_sweep(s, n, ctx->rec, ctx->G, dt, e, P.m, ctx->key_j, ctx->key_t,
+                                    ctx->status, ctx->out, ctx->ctr_d, nullptr, ctx->epoch_d,
+                                    lin, nlist));
+      PCOL_HIP(hipMemcpyAsync(ctx->ctr_h, ctx->ctr_d, sizeof(SweepCounters),
+                              hipMemcpyDeviceToHost, s));
+      PCOL_HIP(hipStreamSynchronize(s));
+      unsigned long long sp, sc;
+      sum_counters(*ctx->ctr_h, sp, sc);
+      ovf_total += ctx->ctr_h->n_overflow;
+      ++sweeps;
+      pairs += (int64_t)sp;
+      if (sp == 0ull) break;
+      if (ctx->opts.max_sweeps > 0 && sweeps >= ctx->opts.max_sweeps)
+        return fail(ctx, PCOL_E_SWEEPS, "sweep cap reached with pairs still resolving");
+    }
+    if (more && groups) {
       PCOL_HIP(launch_fill_u32(s, ctx->sflags, 0u, 16));
       PCOL_HIP(launch_fill_u32(s, (unsigned int *)ctx->stotals, 0u, 8));
       PCOL_HIP(hipMemsetAsync(ctx->ctr_d, 0, sizeof(SweepCounters), s));
     }
-    for (int group = 0; more; ++group) {
+    for (int group = 0; more && groups; ++group) {
       int S = group == 0 ? 5 : 2;  // a step takes about six sweeps at 16M
       if (ctx->opts.max_sweeps > 0 && S > ctx->opts.max_sweeps - (int)sweeps)
         S = ctx->opts.max_sweeps - (int)sweeps;
@@ -822,7 +853,7 @@ pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, dou
       sweeps = 1 + ctx->sflags_h[FLAG_SWEEPS];
       PCOL_HIP(launch_fill_u32(s, ctx->sflags + FLAG_UNFINISHED, 0u, 1));
     }
-    if (more) {
+    if (more && groups) {
       sweeps = 1 + ctx->sflags_h[FLAG_SWEEPS];
       pairs += (int64_t)ctx->stotals_h[0];
       ovf_total += (int64_t)ctx->stotals_h[2];

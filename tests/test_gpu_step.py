@@ -300,32 +300,40 @@ def test_gram_filter_crowded_cells_fall_back(poly20k):
     assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2], equal_nan=True)
 
 
-def _chain(n=40):
+def _chain(n=40, lines=1):
     """Spheres on a line, each closing on its right neighbour at the same speed with
     gaps shrinking to the right: every sphere's earliest partner is its right
     neighbour, so only the last pair is mutual, and each sweep resolves one pair
-    from the right end: n/2 pairs in n/2 sweeps plus one that finds none."""
-    r = np.full(n, 0.5)
+    from the right end: n/2 pairs in n/2 sweeps plus one that finds none.  lines
+    copies of the chain sit on a square grid of (y, z), 8 apart (beyond the reach)."""
     gap = 0.05 - 0.001 * np.arange(n - 1)
-    x = 10.0 + np.concatenate([[0.0], np.cumsum(1.0 + gap)])
-    vx = -0.01 * np.arange(n)
-    z = np.full(n, 200.0)
-    return workloads.Box(x, z.copy(), z.copy(), vx, np.zeros(n), np.zeros(n), r, np.ones(n),
+    x1 = 10.0 + np.concatenate([[0.0], np.cumsum(1.0 + gap)])
+    side = int(np.ceil(np.sqrt(lines)))
+    k = np.arange(lines)
+    y = np.repeat(4.0 + 8.0 * (k % side), n)
+    z = np.repeat(4.0 + 8.0 * (k // side), n)
+    x = np.tile(x1, lines)
+    vx = np.tile(-0.01 * np.arange(n), lines)
+    m = n * lines
+    return workloads.Box(x, y, z, vx, np.zeros(m), np.zeros(m), np.full(m, 0.5), np.ones(m),
                          (400.0, 400.0, 400.0), 6.0, 0.9)
 
 
-def test_sweeps_beyond_one_device_group():
-    """21 sweeps: the later sweeps run on the device in several groups (the first
-    group's last check leaves the step unfinished, the host re-arms and queues more),
-    against the oracle; the sweep cap at and before the last pairing sweep."""
-    box = _chain()
-    _announce(f"sweep chain n={box.n}")
+@pytest.mark.parametrize("lines", [1, 2500])
+def test_sweeps_beyond_one_device_group(lines):
+    """21 sweeps against the oracle.  One chain: a short list, one sweep per host
+    round trip.  2,500 chains (95,000 spheres listed after sweep 1): the later sweeps
+    run on the device in several groups (the first group's last check leaves the
+    step unfinished, the host re-arms and queues more).  Then the sweep cap at and
+    before the last pairing sweep."""
+    box = _chain(lines=lines)
+    _announce(f"sweep chains n={box.n}")
     gpu = gpu_step(box)
     orc = oracle.step(box)
     assert compare_step(box, gpu, orc) == 0
     st = gpu[3]
-    assert st["nc"][0] >= 3 and st["n_pairs"] == 20 and st["n_sweeps"] == 21
-    assert orc.n_pairs == 20 and orc.n_sweeps == 21
+    assert st["nc"][0] >= 3 and st["n_pairs"] == 20 * lines and st["n_sweeps"] == 21
+    assert orc.n_pairs == 20 * lines and orc.n_sweeps == 21
     # a cap that the last sweep (no pairs) meets is fine; one that the last pairing
     # sweep meets is an error, and the caller's arrays are left as they were
     gpu2 = gpu_step(box, max_sweeps=21)
