@@ -1508,8 +1508,11 @@ __global__ __launch_bounds__(256) void k_detect_wide(DetectArgs A, const int *fi
 
 hipError_t launch_detect_wide(hipStream_t s, const DetectArgs &A, const int *first_dev, int n) {
   if (n <= 0) return hipSuccess;
-  // the range is on the device (no read-back before the launch): waves loop over it
-  const int64_t waves = n < 4096 ? n : 4096;
+  // the range is on the device (no read-back before the launch): waves loop
+  // over it; about one wave per 256 spheres (the split puts about 0.1% of them
+  // in the second layer), 64 to 4096
+  int64_t waves = n / 256;
+  waves = waves < 64 ? 64 : (waves > 4096 ? 4096 : waves);
   hipLaunchKernelGGL(k_detect_wide, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, A,
                      first_dev, n);
   return hipGetLastError();
