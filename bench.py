@@ -353,7 +353,7 @@ def main():
                      "unit": "TOP/s", "frac": achieved / PEAK_FP64_OPS,
                      "traffic": measured_traffic() if main_form == "fp64" else None,
                      "traffic_unit": "bytes per launch",
-                     "kernel": "k_detect_half" if main_form != "gram" else "k_detect_gram",
+                     "kernel": "k_detect_half64g" if main_form != "gram" else "k_detect_gram",
                      "note": f"FP64 vector operations (an FMA counts one): {OPS_PER_PAIR_TEST} per "
                              f"unordered pair test; as flops ({FLOPS_PER_PAIR_TEST} per test) "
                              f"{flops / 1e12:.2f} of 78.6 TFLOP/s"},
