@@ -596,7 +596,11 @@ __device__ __forceinline__ bool cell_runs(const Grid &G, const int *start, int c
   //          second is empty unless the row wraps along x)
   int v = 0;
   {
-    const int ln = (int)__lane_id();
+    // the lane index made opaque per call, so that the lane-constant selections
+    // below are recomputed per cell rather than hoisted out of a cell loop
+    // (held across it they cost registers and, in the grouped kernel, spills)
+    int ln = (int)__lane_id();
+    asm volatile("" : "+v"(ln));
     int idx = cell;
     if (ln == 1) {
       idx = cell + 1;
