@@ -1183,7 +1183,9 @@ __global__ __launch_bounds__(256) void k_detect_batched(DetectArgs A, BatchDev B
   __shared__ int2 survq[4][QCAP];
   __shared__ HomeQ hq[4][WAVE];
   const int wpb = blockDim.x / WAVE;
-  const int wave = threadIdx.x / WAVE;
+  // the wave's index, as a wave-uniform value (so are the items and their box,
+  // whose grid then sits in scalar registers)
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   const int total = B.cell_base[B.nbox];
   const int stride = gridDim.x * wpb;
   SurvivorQueue Q{survq[wave], 0, 0u, QCAP, 0ull};
