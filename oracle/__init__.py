@@ -77,6 +77,13 @@ def _load():
                                                               ctypes.c_int] + [_D] * 6 + \
             [_I64, _D, _I32, ctypes.POINTER(_Stats)]
         lib.orc_step.restype = ctypes.c_int
+        lib.orc_step_spin.argtypes = [ctypes.c_int64] + [_D] * 11 + [
+            _D, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+            ctypes.c_int] + [_D] * 9 + [_I64, _D, _I32, ctypes.POINTER(_Stats)]
+        lib.orc_step_spin.restype = ctypes.c_int
+        lib.orc_resolve_pair_spin.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_double] + \
+            [_D] * 11 + [_D, ctypes.c_double, ctypes.c_double, ctypes.c_double] + [_D] * 9
+        lib.orc_resolve_pair_spin.restype = None
         _lib = lib
     return _lib
 
@@ -177,6 +184,52 @@ def step(box, *, e: float | None = None, grid: bool = True, cell_mult: float = 1
         raise OracleError(rc)
     return StepResult(*outs, partner, tcoll, sweep, st.n_pairs, st.n_sweeps, st.pair_tests,
                       st.reach)
+
+
+@dataclass
+class SpinStepResult(StepResult):
+    wx: np.ndarray = None
+    wy: np.ndarray = None
+    wz: np.ndarray = None
+
+
+def step_spin(box, w, mu: float, *, e: float | None = None, grid: bool = True,
+              cell_mult: float = 1.0, max_sweeps: int = 0) -> SpinStepResult:
+    """One collision step of ``box`` with angular velocities ``w`` (shape (3, n))
+    and Coulomb friction ``mu``; inputs are not modified."""
+    n = box.n
+    arrs = [_c64(a) for a in (box.x, box.y, box.z, box.vx, box.vy, box.vz, w[0], w[1], w[2],
+                              box.r, box.m)]
+    outs = [np.empty(n) for _ in range(9)]
+    partner = np.empty(n, dtype=np.int64)
+    tcoll = np.empty(n)
+    sweep = np.empty(n, dtype=np.int32)
+    st = _Stats()
+    L = _c64(box.L)
+    rc = _load().orc_step_spin(n, *[_d(a) for a in arrs], _d(L), float(box.dt),
+                               float(box.e if e is None else e), float(mu), int(grid),
+                               float(cell_mult), int(max_sweeps), *[_d(o) for o in outs],
+                               partner.ctypes.data_as(_I64), _d(tcoll), sweep.ctypes.data_as(_I32),
+                               ctypes.byref(st))
+    if rc:
+        raise OracleError(rc)
+    return SpinStepResult(*outs[:6], partner, tcoll, sweep, st.n_pairs, st.n_sweeps,
+                          st.pair_tests, st.reach, *outs[6:9])
+
+
+def resolve_pair_spin(box, w, mu: float, i: int, j: int, t: float, *, e: float | None = None):
+    """New (x, v, w) of spheres i and j after their collision at time t, with friction
+    mu (arrays of shape (2, 3))."""
+    n = box.n
+    arrs = [_c64(a) for a in (box.x, box.y, box.z, box.vx, box.vy, box.vz, w[0], w[1], w[2],
+                              box.r, box.m)]
+    outs = [np.zeros(n) for _ in range(9)]
+    L = _c64(box.L)
+    _load().orc_resolve_pair_spin(int(i), int(j), float(t), *[_d(a) for a in arrs], _d(L),
+                                  float(box.dt), float(box.e if e is None else e), float(mu),
+                                  *[_d(o) for o in outs])
+    pick = lambda ks: np.array([[outs[k][i] for k in ks], [outs[k][j] for k in ks]])
+    return pick(range(3)), pick(range(3, 6)), pick(range(6, 9))
 
 
 def step_jvp(box, dx, dv, de: float, *, e: float | None = None):

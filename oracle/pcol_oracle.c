@@ -36,6 +36,12 @@
  *              velocity.
  *  free flight spheres without a collision move x + dt v; every position is
  *              wrapped back into [0, L).
+ *  friction    orc_step_spin: the same step with angular velocities and
+ *              Coulomb friction (coefficient mu) in the resolve: the impulse
+ *              gains the tangential part J_t t_p of Sec. "Inter-Particle
+ *              Collisions" (sliding or sticking) and the spins change by the
+ *              angular jump relations, with the moment of inertia of a solid
+ *              sphere from Sec. "Dispersed Phase".
  *
  * Every function below cites the passage it follows.  Pins: tests/test_oracle_*.
  */
@@ -406,6 +412,103 @@ void orc_resolve_pair(int64_t i, int64_t j, double t, const double *x, const dou
   }
 }
 
+/*
+ * One side of a binary collision with friction and spin: sphere a colliding
+ * with sphere b at time t, Sec. "Inter-Particle Collisions" (jump relations of
+ * momentum and angular momentum, impulse J = J_n n_p + J_t t_p), taking a as
+ * particle 1 (n_p points from a to b):
+ *   n    = (d + t u) / s                 contact normal, d, u as in orc_pair_time
+ *   J_n  = -m_r (1 + e) (v_r . n),  v_r = v_a - v_b = -u   (evaluated as
+ *          (m_r (1 + e)) (u . n), the same number)
+ *   v_c  = v_r + r_a w_a x n + r_b w_b x n, evaluated as v_r + (r_a w_a + r_b w_b) x n
+ *          (the cross product is linear; the grouping makes the evaluation
+ *          the exact negation of b's, so both sides agree to the last bit)
+ *   v_rt = v_c - (v_c . n) n,  t_p = v_rt / |v_rt|
+ *   J_t  = max(mu J_n, -(2/7) (1 + e) m_r |v_rt|)   (sliding, or sticking);
+ *          no tangential impulse when |v_rt| = 0
+ *   v_a' = v_a + J / m_a,  evaluated as v_a + (J_n/m_a) n + (J_t/m_a) t_p
+ *   w_a' = w_a + (d_a/2) (n x J) / I_a = w_a + ((r_a J_t) / I_a) (n x t_p)
+ *          (n x n = 0), I_a = m_a d_a^2 / 10 (a solid sphere: pi rho d^5 / 60)
+ *   x_a' = (x_a + t v_a) + (dt - t) v_a'   (eq. update_rho as in orc_resolve_pair)
+ * When J_t = 0 (mu = 0, or no sliding at contact) the tangential terms are
+ * left out, so the result equals orc_resolve_pair's bitwise and the spin is
+ * unchanged.  Reads start-of-step data; writes a's new state.
+ */
+static void orc_resolve_side_spin(int64_t a, int64_t b, double t, const double *x,
+                                  const double *y, const double *z, const double *vx,
+                                  const double *vy, const double *vz, const double *wx,
+                                  const double *wy, const double *wz, const double *r,
+                                  const double *m, const double L[3], double dt, double e,
+                                  double mu, double *xo, double *yo, double *zo, double *vxo,
+                                  double *vyo, double *vzo, double *wxo, double *wyo,
+                                  double *wzo) {
+  const double xa[3] = {x[a], y[a], z[a]}, xb[3] = {x[b], y[b], z[b]};
+  const double va[3] = {vx[a], vy[a], vz[a]}, vb[3] = {vx[b], vy[b], vz[b]};
+  const double wa[3] = {wx[a], wy[a], wz[a]}, wb[3] = {wx[b], wy[b], wz[b]};
+  double d[3], u[3], n[3];
+  for (int k = 0; k < 3; ++k) {
+    d[k] = orc_wrap_sep(xb[k] - xa[k], L[k]);
+    u[k] = vb[k] - va[k];
+  }
+  const double s = r[a] + r[b];
+  for (int k = 0; k < 3; ++k) n[k] = (d[k] + t * u[k]) / s;
+  const double g = (u[0] * n[0] + u[1] * n[1]) + u[2] * n[2];
+  const double mr = (m[a] * m[b]) / (m[a] + m[b]);
+  const double Jn = (mr * (1.0 + e)) * g;
+  /* contact-point relative velocity and its tangential part */
+  double S[3], vc[3];
+  for (int k = 0; k < 3; ++k) S[k] = r[a] * wa[k] + r[b] * wb[k];
+  const double Sxn[3] = {S[1] * n[2] - S[2] * n[1], S[2] * n[0] - S[0] * n[2],
+                         S[0] * n[1] - S[1] * n[0]};
+  for (int k = 0; k < 3; ++k) vc[k] = -u[k] + Sxn[k];
+  const double vcn = (vc[0] * n[0] + vc[1] * n[1]) + vc[2] * n[2];
+  double vrt[3];
+  for (int k = 0; k < 3; ++k) vrt[k] = vc[k] - vcn * n[k];
+  const double vt = sqrt((vrt[0] * vrt[0] + vrt[1] * vrt[1]) + vrt[2] * vrt[2]);
+  double Jt = 0.0, tp[3] = {0.0, 0.0, 0.0};
+  if (vt > 0.0) {
+    for (int k = 0; k < 3; ++k) tp[k] = vrt[k] / vt;
+    const double slide = mu * Jn;
+    const double stick = -((((2.0 / 7.0) * (1.0 + e)) * mr) * vt);
+    Jt = slide > stick ? slide : stick;
+  }
+  const double an = Jn / m[a], at = Jt / m[a];
+  double van[3];
+  for (int k = 0; k < 3; ++k) {
+    van[k] = va[k] + an * n[k];
+    if (Jt != 0.0) van[k] = van[k] + at * tp[k];
+  }
+  const double rest = dt - t;
+  double *xout[3] = {xo, yo, zo}, *vout[3] = {vxo, vyo, vzo}, *wout[3] = {wxo, wyo, wzo};
+  for (int k = 0; k < 3; ++k) {
+    xout[k][a] = orc_wrap_pos((xa[k] + t * va[k]) + rest * van[k], L[k]);
+    vout[k][a] = van[k];
+    wout[k][a] = wa[k];
+  }
+  if (Jt != 0.0) {
+    const double da = 2.0 * r[a];
+    const double I = (m[a] * (da * da)) / 10.0;
+    const double K = (r[a] * Jt) / I;
+    const double nxt[3] = {n[1] * tp[2] - n[2] * tp[1], n[2] * tp[0] - n[0] * tp[2],
+                           n[0] * tp[1] - n[1] * tp[0]};
+    for (int k = 0; k < 3; ++k) wout[k][a] = wa[k] + K * nxt[k];
+  }
+}
+
+/* Both sides of the collision of i and j at time t, with friction and spin. */
+void orc_resolve_pair_spin(int64_t i, int64_t j, double t, const double *x, const double *y,
+                           const double *z, const double *vx, const double *vy,
+                           const double *vz, const double *wx, const double *wy,
+                           const double *wz, const double *r, const double *m,
+                           const double L[3], double dt, double e, double mu, double *xo,
+                           double *yo, double *zo, double *vxo, double *vyo, double *vzo,
+                           double *wxo, double *wyo, double *wzo) {
+  orc_resolve_side_spin(i, j, t, x, y, z, vx, vy, vz, wx, wy, wz, r, m, L, dt, e, mu, xo, yo, zo,
+                        vxo, vyo, vzo, wxo, wyo, wzo);
+  orc_resolve_side_spin(j, i, t, x, y, z, vx, vy, vz, wx, wy, wz, r, m, L, dt, e, mu, xo, yo, zo,
+                        vxo, vyo, vzo, wxo, wyo, wzo);
+}
+
 typedef struct {
   int64_t n_pairs;    /* collisions resolved in the step */
   int64_t n_sweeps;   /* sweeps run, including the final one that found none */
@@ -420,16 +523,26 @@ typedef struct {
  * Inputs (x*, v*, r, m) are the start-of-step state and are not modified; the
  * new state goes to (xo*, vo*).  partner[i] = the sphere i collided with or -1;
  * tcoll[i] = contact time within the step (NaN if none); sweep_of[i] = sweep
- * (0-based) in which i collided, or -1.  Any of the three may be NULL.
+ * (0-based) in which i collided, or -1.  Any of the three may be NULL.  With
+ * spins (w* not NULL) the resolve also applies friction mu and writes the new
+ * spins to (wo*); without, it is the frictionless orc_resolve_pair.
  */
-int orc_step(int64_t n, const double *x, const double *y, const double *z, const double *vx,
-             const double *vy, const double *vz, const double *r, const double *m,
-             const double L[3], double dt, double e, int use_grid, double cell_mult, int max_sweeps,
-             double *xo, double *yo, double *zo, double *vxo, double *vyo, double *vzo,
-             int64_t *partner, double *tcoll, int32_t *sweep_of, orc_stats *st) {
+static int orc_step_core(int64_t n, const double *x, const double *y, const double *z,
+                         const double *vx, const double *vy, const double *vz, const double *wx,
+                         const double *wy, const double *wz, const double *r, const double *m,
+                         const double L[3], double dt, double e, double mu, int use_grid,
+                         double cell_mult, int max_sweeps, double *xo, double *yo, double *zo,
+                         double *vxo, double *vyo, double *vzo, double *wxo, double *wyo,
+                         double *wzo, int64_t *partner, double *tcoll, int32_t *sweep_of,
+                         orc_stats *st) {
   int rc = orc_check_inputs(n, x, y, z, vx, vy, vz, r, m, L, dt);
   if (rc) return rc;
   if (!(e >= 0.0 && e <= 1.0)) return ORC_E_INVALID;
+  if (wx) {
+    if (!(mu >= 0.0) || !isfinite(mu)) return ORC_E_INVALID;
+    for (int64_t i = 0; i < n; ++i)
+      if (!isfinite(wx[i]) || !isfinite(wy[i]) || !isfinite(wz[i])) return ORC_E_INVALID;
+  }
   const double reach = orc_reach(n, vx, vy, vz, r, dt);
   for (int a = 0; a < 3; ++a)
     if (!(L[a] > 2.0 * reach)) return ORC_E_BOX;
@@ -464,8 +577,12 @@ int orc_step(int64_t n, const double *x, const double *y, const double *z, const
     for (int64_t i = 0; i < n; ++i) {
       const int64_t j = pj[i];
       if (j > i && pj[j] == i) {
-        orc_resolve_pair(i, j, pt[i], x, y, z, vx, vy, vz, r, m, L, dt, e, xo, yo, zo, vxo, vyo,
-                         vzo);
+        if (wx)
+          orc_resolve_pair_spin(i, j, pt[i], x, y, z, vx, vy, vz, wx, wy, wz, r, m, L, dt, e, mu,
+                                xo, yo, zo, vxo, vyo, vzo, wxo, wyo, wzo);
+        else
+          orc_resolve_pair(i, j, pt[i], x, y, z, vx, vy, vz, r, m, L, dt, e, xo, yo, zo, vxo,
+                           vyo, vzo);
         hit[i] = hit[j] = 1;
         if (partner) {
           partner[i] = j;
@@ -494,6 +611,11 @@ int orc_step(int64_t n, const double *x, const double *y, const double *z, const
         po[k][i] = orc_wrap_pos(p[k][i] + dt * v[k][i], L[k]);
         vo[k][i] = v[k][i];
       }
+      if (wx) {
+        wxo[i] = wx[i];
+        wyo[i] = wy[i];
+        wzo[i] = wz[i];
+      }
     }
   }
   if (st) {
@@ -507,6 +629,33 @@ int orc_step(int64_t n, const double *x, const double *y, const double *z, const
   free(pj);
   free(pt);
   return rc;
+}
+
+/* One collision step without friction (see orc_step_core). */
+int orc_step(int64_t n, const double *x, const double *y, const double *z, const double *vx,
+             const double *vy, const double *vz, const double *r, const double *m,
+             const double L[3], double dt, double e, int use_grid, double cell_mult, int max_sweeps,
+             double *xo, double *yo, double *zo, double *vxo, double *vyo, double *vzo,
+             int64_t *partner, double *tcoll, int32_t *sweep_of, orc_stats *st) {
+  return orc_step_core(n, x, y, z, vx, vy, vz, NULL, NULL, NULL, r, m, L, dt, e, 0.0, use_grid,
+                       cell_mult, max_sweeps, xo, yo, zo, vxo, vyo, vzo, NULL, NULL, NULL,
+                       partner, tcoll, sweep_of, st);
+}
+
+/* One collision step with angular velocities (w*) and Coulomb friction mu
+ * (orc_resolve_side_spin); the new spins go to (wo*).  The pair set is the one
+ * of orc_step: contact times do not depend on the spins. */
+int orc_step_spin(int64_t n, const double *x, const double *y, const double *z,
+                  const double *vx, const double *vy, const double *vz, const double *wx,
+                  const double *wy, const double *wz, const double *r, const double *m,
+                  const double L[3], double dt, double e, double mu, int use_grid,
+                  double cell_mult, int max_sweeps, double *xo, double *yo, double *zo,
+                  double *vxo, double *vyo, double *vzo, double *wxo, double *wyo, double *wzo,
+                  int64_t *partner, double *tcoll, int32_t *sweep_of, orc_stats *st) {
+  if (n > 0 && (!wx || !wy || !wz || !wxo || !wyo || !wzo)) return ORC_E_INVALID;
+  return orc_step_core(n, x, y, z, vx, vy, vz, wx, wy, wz, r, m, L, dt, e, mu, use_grid,
+                       cell_mult, max_sweeps, xo, yo, zo, vxo, vyo, vzo, wxo, wyo, wzo, partner,
+                       tcoll, sweep_of, st);
 }
 
 /*
