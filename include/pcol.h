@@ -195,11 +195,31 @@ pcol_status pcol_advance(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, 
  * flight and wrap; p is updated in place.  partner (device int32[n], nullable):
  * the caller index of the sphere i collided with, or -1.  tcoll (device
  * double[n], nullable): contact time within the step, NaN if none.
- * stats (host, nullable).  Synchronises once after validation, once after
- * binning and once per sweep.  On PCOL_E_SWEEPS the pairs resolved so far
- * have been written to p and the free flight has not run. */
+ * stats (host, nullable).  Synchronises once after validation, once after sweep
+ * 1 (and after binning for the binary32 filter), then once per sweep for a
+ * short sweep list, or once per group of sweeps run on the device for a long
+ * one.  On PCOL_E_SWEEPS p is left as it was (the end-of-step state is written
+ * only once the sweeps are done). */
 pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, double dt, double e,
                       int32_t *partner, double *tcoll, pcol_stats *stats);
+
+/* pcol_step with angular velocities and Coulomb friction (Sec. "Inter-Particle
+ * Collisions": the impulse J = J_n n_p + J_t t_p with
+ * J_t = max(mu J_n, -(2/7)(1+e) m_r |v_rt|), sliding or sticking, t_p along the
+ * tangential contact-point velocity v_rt; the jump relations of momentum and
+ * angular momentum, with the moment of inertia of a solid sphere
+ * I = m d^2 / 10, Sec. "Dispersed Phase").
+ * wx, wy, wz: device double[n] angular velocities in the caller's order, read at
+ * the start of the step and updated in place for the spheres that collide
+ * (the others keep theirs); validated with the other inputs (non-finite:
+ * PCOL_E_INVALID, nothing changed).  mu: friction coefficient, >= 0.
+ * Contact times do not depend on the spins, so the pair set is pcol_step's;
+ * with mu = 0 every output equals pcol_step's bitwise and the spins are
+ * unchanged.  Everything else as pcol_step (on PCOL_E_SWEEPS the spins of the
+ * pairs resolved so far have been updated, p has not). */
+pcol_status pcol_step_spin(pcol_ctx *ctx, pcol_particles *p, double *wx, double *wy, double *wz,
+                           const pcol_box *box, double dt, double e, double mu,
+                           int32_t *partner, double *tcoll, pcol_stats *stats);
 
 /* Statistics of one pcol_step_batched call. */
 typedef struct {

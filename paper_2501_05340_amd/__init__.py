@@ -108,6 +108,10 @@ def _load():
     lib.pcol_step.argtypes = [ctx_p, P(pcol_particles), P(pcol_box), ctypes.c_double,
                               ctypes.c_double, V, V, P(pcol_stats)]
     lib.pcol_step.restype = ctypes.c_int
+    lib.pcol_step_spin.argtypes = [ctx_p, P(pcol_particles), V, V, V, P(pcol_box),
+                                   ctypes.c_double, ctypes.c_double, ctypes.c_double, V, V,
+                                   P(pcol_stats)]
+    lib.pcol_step_spin.restype = ctypes.c_int
     lib.pcol_step_backward.argtypes = [ctx_p, P(pcol_particles), P(pcol_box), ctypes.c_double,
                                        ctypes.c_double, V, V, P(pcol_state_grad),
                                        P(pcol_state_grad), V]
@@ -123,7 +127,7 @@ lib = _load()
 
 EXPORTED = ["pcol_default_opts", "pcol_create", "pcol_destroy", "pcol_last_error",
             "pcol_set_stream", "pcol_bin", "pcol_detect", "pcol_resolve", "pcol_advance",
-            "pcol_step", "pcol_step_backward", "pcol_step_batched"]
+            "pcol_step", "pcol_step_spin", "pcol_step_backward", "pcol_step_batched"]
 
 
 class PcolError(RuntimeError):
@@ -299,6 +303,22 @@ def pcol_step(ctx: Context, p: Particles, L, dt: float, e: float, partner=None, 
     ctx.check(lib.pcol_step(ctx.handle, ctypes.byref(ps), ctypes.byref(_box(L)), float(dt),
                             float(e), _ptr(partner, torch.int32, n), _ptr(tcoll, torch.float64, n),
                             ctypes.byref(st) if st is not None else None))
+    return st.as_dict() if st is not None else None
+
+
+def pcol_step_spin(ctx: Context, p: Particles, w, L, dt: float, e: float, mu: float,
+                   partner=None, tcoll=None, stats: bool = True):
+    """One full step with angular velocities w = (wx, wy, wz) (float64 device tensors,
+    updated in place) and Coulomb friction mu; returns a dict of pcol_stats (or None)."""
+    n = p.n
+    st = pcol_stats() if stats else None
+    ctx.sync_stream()
+    ps = p.struct()
+    wp = [_ptr(t, torch.float64, n) for t in w]
+    ctx.check(lib.pcol_step_spin(ctx.handle, ctypes.byref(ps), *wp, ctypes.byref(_box(L)),
+                                 float(dt), float(e), float(mu), _ptr(partner, torch.int32, n),
+                                 _ptr(tcoll, torch.float64, n),
+                                 ctypes.byref(st) if st is not None else None))
     return st.as_dict() if st is not None else None
 
 

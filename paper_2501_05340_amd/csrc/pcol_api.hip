@@ -77,6 +77,7 @@ struct pcol_ctx {
   int wide_first = 0, n_wide = 0;  // sorted range of the second layer
   int *wide_h = nullptr;           // pinned read-back of that range
   bool bin_pending = false;        // maxcell and the range still in flight (bin_readback)
+  const Spin *spin = nullptr;      // set by pcol_step_spin for the step: its spins are validated
   // bounds for the first layer's pair test: reach, speed and radius
   double reach_pass = 0.0, vmax_pass = 0.0, rmax_pass = 0.0;
   double band = 0.0;   // FP32 filter band in use (relative to r_i + r_j)
@@ -329,7 +330,12 @@ pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box
   pcol_status st = check_common(ctx, p, box, dt);
   if (st != PCOL_OK) return st;
   ctx->binned = false;
-  const Particles P = to_dev(p);
+  Particles P = to_dev(p);
+  if (ctx->spin) {
+    P.wx = ctx->spin->wx;
+    P.wy = ctx->spin->wy;
+    P.wz = ctx->spin->wz;
+  }
   hipStream_t s = ctx->stream;
   // a1: reach and data validity (one read-back)
   PCOL_HIP(hipMemsetAsync(ctx->reach_d, 0, sizeof(ReachOut), s));
@@ -719,8 +725,12 @@ pcol_status pcol_advance(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, 
   return PCOL_OK;
 }
 
-pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, double dt, double e,
-                      int32_t *partner, double *tcoll, pcol_stats *stats) {
+}  // extern "C"
+
+// The whole step of pcol_step and pcol_step_spin (spin: nullptr for none).
+static pcol_status step_impl(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, double dt,
+                             double e, int32_t *partner, double *tcoll, pcol_stats *stats,
+                             const Spin *spin) {
   pcol_status st = check_common(ctx, p, box, dt);
   if (st != PCOL_OK) return st;
   if (!(e >= 0.0 && e <= 1.0)) return fail(ctx, PCOL_E_INVALID, "e outside [0, 1]");
@@ -748,7 +758,8 @@ pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, dou
     // left ACTIVE or DIRTY (the others are done for the step; entries that
     // finish later are skipped by their status)
     PCOL_HIP(launch_resolve_sweep(s, n, ctx->rec, ctx->G, dt, e, P.m, ctx->key_j, ctx->key_t,
-                                  ctx->status, ctx->out, ctx->ctr_d, nullptr, ctx->epoch_d));
+                                  ctx->status, ctx->out, ctx->ctr_d, nullptr, ctx->epoch_d,
+                                  nullptr, 0, spin));
     PCOL_HIP(launch_keep_list(s, ctx->status, n, ctx->keep_cnt, ctx->keep_off, ctx->keep_bs,
                               ctx->reach_d, ctx->list_a));
     PCOL_HIP(hipMemcpyAsync(ctx->nlist_h, ctx->keep_off + (n + 255) / 256, sizeof(int),
@@ -799,7 +810,7 @@ pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, dou
       }
       PCOL_HIP(launch_resolve_sweep(s, n, ctx->rec, ctx->G, dt, e, P.m, ctx->key_j, ctx->key_t,
                                     ctx->status, ctx->out, ctx->ctr_d, nullptr, ctx->epoch_d,
-                                    lin, nlist));
+                                    lin, nlist, spin));
       PCOL_HIP(hipMemcpyAsync(ctx->ctr_h, ctx->ctr_d, sizeof(SweepCounters),
                               hipMemcpyDeviceToHost, s));
       PCOL_HIP(hipStreamSynchronize(s));
@@ -836,7 +847,7 @@ pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, dou
         }
         PCOL_HIP(launch_resolve_sweep(s, n, ctx->rec, ctx->G, dt, e, P.m, ctx->key_j,
                                       ctx->key_t, ctx->status, ctx->out, ctx->ctr_d, &Bf,
-                                      ctx->epoch_d, lin, nlist));
+                                      ctx->epoch_d, lin, nlist, spin));
         PCOL_HIP(launch_sweep_check(s, ctx->ctr_d, ctx->sflags, ctx->stotals, k == S - 1));
       }
       if (timing) PCOL_HIP(hipEventRecord(ctx->ev[3], s));
@@ -899,6 +910,26 @@ pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, dou
     }
   }
   return PCOL_OK;
+}
+
+extern "C" {
+
+pcol_status pcol_step(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box, double dt, double e,
+                      int32_t *partner, double *tcoll, pcol_stats *stats) {
+  return step_impl(ctx, p, box, dt, e, partner, tcoll, stats, nullptr);
+}
+
+pcol_status pcol_step_spin(pcol_ctx *ctx, pcol_particles *p, double *wx, double *wy, double *wz,
+                           const pcol_box *box, double dt, double e, double mu,
+                           int32_t *partner, double *tcoll, pcol_stats *stats) {
+  if (!ctx) return PCOL_E_INVALID;
+  if (!(mu >= 0.0) || !isfinite(mu)) return fail(ctx, PCOL_E_INVALID, "mu negative or not finite");
+  if (p && p->n > 0 && (!wx || !wy || !wz)) return fail(ctx, PCOL_E_INVALID, "null spin array");
+  const Spin sp{wx, wy, wz, mu};
+  ctx->spin = &sp;  // the binning validates the spins with the other inputs
+  const pcol_status st = step_impl(ctx, p, box, dt, e, partner, tcoll, stats, &sp);
+  ctx->spin = nullptr;
+  return st;
 }
 
 pcol_status pcol_step_backward(pcol_ctx *ctx, const pcol_particles *start, const pcol_box *box,

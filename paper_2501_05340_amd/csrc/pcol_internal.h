@@ -193,6 +193,72 @@ __device__ __forceinline__ void resolve_one(const Rec &a, const Rec &b, double m
   out_x[2] = wrap_pos((a.z + t * a.vz) + rest * out_v[2], G.L[2]);
 }
 
+// Angular velocities (caller order, updated in place for collided spheres) and
+// the Coulomb friction coefficient of a step with spin; wx == nullptr: none.
+struct Spin {
+  double *wx, *wy, *wz;
+  double mu;
+};
+
+// Post-collision state of sphere `a` colliding with `b` at time t with Coulomb
+// friction mu and spins wa, wb (Sec. "Inter-Particle Collisions": impulse
+// J = J_n n + J_t t_p, J_t = max(mu J_n, -(2/7)(1+e) m_r |v_rt|), jump
+// relations of momentum and angular momentum; solid-sphere inertia m d^2 / 10,
+// Sec. "Dispersed Phase").  The contact-point velocity is evaluated as
+// v_r + (r_a w_a + r_b w_b) x n, so b's evaluation is the exact negation of a's
+// and the two sides agree bitwise; with J_t = 0 the tangential terms are left
+// out (then the velocity equals resolve_one's and the spin is unchanged).
+__device__ __forceinline__ void resolve_one_spin(const Rec &a, const Rec &b, double ma, double mb,
+                                                 const double wa[3], const double wb[3],
+                                                 const Grid &G, double t, double dt, double e,
+                                                 double mu, double out_x[3], double out_v[3],
+                                                 double out_w[3]) {
+  const double d0 = wrap_sep(b.x - a.x, G.L[0], G.halfL[0]);
+  const double d1 = wrap_sep(b.y - a.y, G.L[1], G.halfL[1]);
+  const double d2 = wrap_sep(b.z - a.z, G.L[2], G.halfL[2]);
+  const double u[3] = {b.vx - a.vx, b.vy - a.vy, b.vz - a.vz};
+  const double s = a.r + b.r;
+  const double n[3] = {(d0 + t * u[0]) / s, (d1 + t * u[1]) / s, (d2 + t * u[2]) / s};
+  const double g = (u[0] * n[0] + u[1] * n[1]) + u[2] * n[2];
+  const double mr = (ma * mb) / (ma + mb);
+  const double Jn = (mr * (1.0 + e)) * g;
+  double S[3];
+  for (int k = 0; k < 3; ++k) S[k] = a.r * wa[k] + b.r * wb[k];
+  const double Sxn[3] = {S[1] * n[2] - S[2] * n[1], S[2] * n[0] - S[0] * n[2],
+                         S[0] * n[1] - S[1] * n[0]};
+  double vc[3];
+  for (int k = 0; k < 3; ++k) vc[k] = -u[k] + Sxn[k];
+  const double vcn = (vc[0] * n[0] + vc[1] * n[1]) + vc[2] * n[2];
+  double vrt[3];
+  for (int k = 0; k < 3; ++k) vrt[k] = vc[k] - vcn * n[k];
+  const double vt = __builtin_sqrt((vrt[0] * vrt[0] + vrt[1] * vrt[1]) + vrt[2] * vrt[2]);
+  double Jt = 0.0, tp[3] = {0.0, 0.0, 0.0};
+  if (vt > 0.0) {
+    for (int k = 0; k < 3; ++k) tp[k] = vrt[k] / vt;
+    const double slide = mu * Jn;
+    const double stick = -((((2.0 / 7.0) * (1.0 + e)) * mr) * vt);
+    Jt = slide > stick ? slide : stick;
+  }
+  const double an = Jn / ma, at = Jt / ma;
+  const double va[3] = {a.vx, a.vy, a.vz}, xa[3] = {a.x, a.y, a.z};
+  const double rest = dt - t;
+  for (int k = 0; k < 3; ++k) {
+    double v = va[k] + an * n[k];
+    if (Jt != 0.0) v = v + at * tp[k];
+    out_v[k] = v;
+    out_x[k] = wrap_pos((xa[k] + t * va[k]) + rest * v, G.L[k]);
+    out_w[k] = wa[k];
+  }
+  if (Jt != 0.0) {
+    const double da = 2.0 * a.r;
+    const double I = (ma * (da * da)) / 10.0;
+    const double K = (a.r * Jt) / I;
+    const double nxt[3] = {n[1] * tp[2] - n[2] * tp[1], n[2] * tp[0] - n[0] * tp[2],
+                           n[0] * tp[1] - n[1] * tp[0]};
+    for (int k = 0; k < 3; ++k) out_w[k] = wa[k] + K * nxt[k];
+  }
+}
+
 __device__ __forceinline__ int cell_coord(double x, double inv_h, int nc) {
   int c = (int)(x * inv_h);
   c = c < 0 ? 0 : c;
@@ -205,6 +271,7 @@ struct Particles {
   int64_t n;
   double *x, *y, *z, *vx, *vy, *vz;
   const double *r, *m;
+  const double *wx = nullptr, *wy = nullptr, *wz = nullptr;  // spins, validated when given
 };
 
 // gradient with respect to a step's positions and velocities (SoA)
@@ -292,12 +359,15 @@ hipError_t launch_gather_exact(hipStream_t s, const int *list, int nlist, const 
                                int select, const Rec *rec, const int *start, const Grid &G,
                                double dt, uint8_t *status, int *key_j, double *key_t,
                                const BatchDev *B);
+// spin (nullable): friction and spins (the pair's sphere of smaller sorted index
+// resolves both sides and writes both spins in place)
 hipError_t launch_resolve_sweep(hipStream_t s, int n, const Rec *rec, const Grid &G, double dt,
                                 double e, const double *mass, const int *key_j,
                                 const double *key_t, uint8_t *status, OutRec *out,
                                 SweepCounters *ctr,
                                 const BatchDev *B, const unsigned int *epoch,
-                                const int *list = nullptr, int nlist = 0);
+                                const int *list = nullptr, int nlist = 0,
+                                const Spin *spin = nullptr);
 // next step's epoch (one thread); every OutRec epoch starts at 0xffffffff
 hipError_t launch_epoch_next(hipStream_t s, unsigned int *epoch);
 hipError_t launch_init_out(hipStream_t s, OutRec *out, int64_t n);

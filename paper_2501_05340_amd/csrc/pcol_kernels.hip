@@ -155,6 +155,10 @@ __global__ __launch_bounds__(256) void k_reach(Particles P, double L0, double L1
         const bool fin = isfinite(x[u]) && isfinite(y[u]) && isfinite(z[u]) && isfinite(w) &&
                          isfinite(r[u]) && isfinite(m[u]);
         if (!fin || !(r[u] > 0.0) || !(m[u] > 0.0)) bad |= 1u;
+        if (P.wx) {
+          const int64_t i = i0 + u * stride;
+          if (!isfinite(P.wx[i]) || !isfinite(P.wy[i]) || !isfinite(P.wz[i])) bad |= 1u;
+        }
         if (!(x[u] >= 0.0 && x[u] < L0) || !(y[u] >= 0.0 && y[u] < L1) ||
             !(z[u] >= 0.0 && z[u] < L2))
           bad |= 2u;
@@ -1626,7 +1630,7 @@ __global__ __launch_bounds__(256) void k_resolve_sweep(int n, const Rec *rec, Gr
                                                        uint8_t *status, OutRec *out,
                                                        SweepCounters *ctr, BatchDev B,
                                                        const unsigned int *epoch, const int *list,
-                                                       int nlist) {
+                                                       int nlist, Spin S) {
   if (B.flags && (B.flags[FLAG_ERR] || B.flags[FLAG_DONE])) return;
   const int ti = blockIdx.x * 256 + threadIdx.x;
   const bool valid = list ? ti < nlist : ti < n;
@@ -1638,7 +1642,33 @@ __global__ __launch_bounds__(256) void k_resolve_sweep(int n, const Rec *rec, Gr
       status[i] = ST_FREE;
     } else {
       const int q = key_j[p];
-      if (q == i) {
+      if (q == i && S.wx) {
+        // with spins, the thread of the smaller sorted index resolves both sides
+        // and writes both spins in place (the partner's thread writes nothing,
+        // so no thread reads a spin another one has already changed)
+        if (i < p) {
+          const Rec a = rec[i], b = rec[p];
+          const double t = key_t[i];
+          const double ma = mass[a.o], mb = mass[b.o];
+          const double wa[3] = {S.wx[a.o], S.wy[a.o], S.wz[a.o]};
+          const double wb[3] = {S.wx[b.o], S.wy[b.o], S.wz[b.o]};
+          const unsigned int ep = *epoch;
+          double xo[3], vo[3], wo[3];
+          resolve_one_spin(a, b, ma, mb, wa, wb, G0, t, dt, e, S.mu, xo, vo, wo);
+          out[i] = OutRec{xo[0], xo[1], xo[2], vo[0], vo[1], vo[2], t, b.o, ep};
+          S.wx[a.o] = wo[0];
+          S.wy[a.o] = wo[1];
+          S.wz[a.o] = wo[2];
+          resolve_one_spin(b, a, mb, ma, wb, wa, G0, t, dt, e, S.mu, xo, vo, wo);
+          out[p] = OutRec{xo[0], xo[1], xo[2], vo[0], vo[1], vo[2], t, a.o, ep};
+          S.wx[b.o] = wo[0];
+          S.wy[b.o] = wo[1];
+          S.wz[b.o] = wo[2];
+          status[i] = ST_COLLIDED;
+          status[p] = ST_COLLIDED;
+          npair = 1ull;
+        }
+      } else if (q == i) {
         const Rec a = rec[i], b = rec[p];
         const double t = key_t[i];
         const double ma = mass[a.o], mb = mass[b.o];
@@ -1674,12 +1704,13 @@ hipError_t launch_resolve_sweep(hipStream_t s, int n, const Rec *rec, const Grid
                                 double e, const double *mass, const int *key_j,
                                 const double *key_t, uint8_t *status, OutRec *out,
                                 SweepCounters *ctr, const BatchDev *B, const unsigned int *epoch,
-                                const int *list, int nlist) {
+                                const int *list, int nlist, const Spin *spin) {
   const int items = list ? nlist : n;
   if (items <= 0) return hipSuccess;
   BatchDev none{};
   hipLaunchKernelGGL(k_resolve_sweep, dim3((items + 255) / 256), dim3(256), 0, s, n, rec, G, dt,
-                     e, mass, key_j, key_t, status, out, ctr, B ? *B : none, epoch, list, nlist);
+                     e, mass, key_j, key_t, status, out, ctr, B ? *B : none, epoch, list, nlist,
+                     spin ? *spin : Spin{nullptr, nullptr, nullptr, 0.0});
   return hipGetLastError();
 }
 
