@@ -198,6 +198,49 @@ def batched_leg(args, pc, torch):
     return out
 
 
+def friction_leg(args, pc, torch, box, p0, ref):
+    """The 16M step with spins and Coulomb friction (pcol_step_spin, mu 0.3, spins
+    N(0, 1) / r per component, seed 17), each step from the configured input and
+    spins, restored outside the timed interval; its pair set against the plain step's."""
+    import numpy as np
+    mu = 0.3
+    rng = np.random.default_rng(17)
+    w0 = [torch.as_tensor(rng.normal(size=box.n) / box.r).cuda() for _ in range(3)]
+    p = p0.clone()
+    w = [t.clone() for t in w0]
+    ctx = pc.Context(box.n, pc.pcol_default_opts(timing=1))
+    partner = torch.empty(box.n, dtype=torch.int32, device="cuda")
+
+    def restore():
+        for t, t_0 in zip(list(p.tensors()[:6]) + w, list(p0.tensors()[:6]) + w0):
+            t.copy_(t_0)
+
+    for k in range(args.warmup):
+        restore()
+        pc.pcol_step_spin(ctx, p, w, box.L, box.dt, box.e, mu, partner)
+    stats, wall = [], 0.0
+    for k in range(args.steps):
+        restore()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats.append(pc.pcol_step_spin(ctx, p, w, box.L, box.dt, box.e, mu, partner))
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+    changed = int((w[0] != w0[0]).sum().item())
+    out = {
+        "value": box.n * args.steps / wall, "unit": "particles/s",
+        "ms_per_step": wall * 1e3 / args.steps, "mu": mu,
+        "ms_per_step_over_plain": (wall / args.steps) / (ref["wall"] / args.steps),
+        "pair_set_mismatch_vs_plain": int((partner != ref["partner"]).sum().item()),
+        "pairs_per_step": statistics.mean(st["n_pairs"] for st in stats),
+        "spins_changed": changed,
+        "sweeps_ms_median": statistics.median(st["ms_sweeps"] for st in stats),
+    }
+    ctx.close()
+    log(f"[friction] {out['ms_per_step']:.3f} ms per step, {changed} spins changed")
+    return out
+
+
 def adjoint_leg(args, pc, torch):
     """Differentiation workload: 1M spheres (phi 0.2, radius 1, e 0.9 learnable),
     10 FP64 steps through the autograd rollout, loss = sum |v|^2 at the end;
@@ -253,6 +296,7 @@ def main():
                     help="cell side factor of the single-box path (default: the library's)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-form leg")
+    ap.add_argument("--no-friction", action="store_true", help="skip the friction-and-spin leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on one GPU only: the collision step is a single-GPU build; "
@@ -401,6 +445,8 @@ def main():
         out[name + "_form"] = sub
     if not args.no_batched:
         out["batched_form"] = batched_leg(args, pc, torch)
+    if not args.no_friction and "fp64" in forms:
+        out["friction_form"] = friction_leg(args, pc, torch, box, p0, forms["fp64"])
     if not args.no_adjoint:
         out["adjoint_form"] = adjoint_leg(args, pc, torch)
     if not args.no_cpu_baseline:
