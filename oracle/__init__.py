@@ -84,6 +84,9 @@ def _load():
         lib.orc_resolve_pair_spin.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_double] + \
             [_D] * 11 + [_D, ctypes.c_double, ctypes.c_double, ctypes.c_double] + [_D] * 9
         lib.orc_resolve_pair_spin.restype = None
+        lib.orc_deposit.argtypes = [ctypes.c_int64, _D, _D, _D, _D, ctypes.c_int,
+                                    ctypes.POINTER(ctypes.c_int), _D, _D]
+        lib.orc_deposit.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -264,3 +267,17 @@ def resolve_pair(box, i: int, j: int, t: float, *, e: float | None = None):
     xs = np.array([[outs[k][i] for k in range(3)], [outs[k][j] for k in range(3)]])
     vs = np.array([[outs[k][i] for k in range(3, 6)], [outs[k][j] for k in range(3, 6)]])
     return xs, vs
+
+
+def deposit(x, y, z, a, nc, L):
+    """Node sums of the linear corner deposition of a (shape (comp, n)) onto the periodic
+    grid of nc cells per axis over the box L; returns shape (comp, nc2, nc1, nc0)."""
+    a = np.ascontiguousarray(np.atleast_2d(np.asarray(a, dtype=np.float64)))
+    comp, n = a.shape
+    ncv = (ctypes.c_int * 3)(*[int(v) for v in nc])
+    out = np.empty(comp * int(nc[0]) * int(nc[1]) * int(nc[2]))
+    rc = _load().orc_deposit(n, _d(_c64(x)), _d(_c64(y)), _d(_c64(z)), _d(a), comp, ncv,
+                             _d(_c64(L)), _d(out))
+    if rc:
+        raise OracleError(rc)
+    return out.reshape(comp, int(nc[2]), int(nc[1]), int(nc[0]))

@@ -36,6 +36,12 @@
  *              velocity.
  *  free flight spheres without a collision move x + dt v; every position is
  *              wrapped back into [0, L).
+ *  deposition  orc_deposit: Sec. "Dispersed Phase" and Sec. "Deposition": a
+ *              per-sphere quantity projected linearly onto the eight corner
+ *              nodes of the host cell of a periodic Cartesian grid (the
+ *              C0-continuous inverse-distance weighting with deposition radius
+ *              equal to the cell size, on cells of equal volume: trilinear
+ *              weights), summed over all spheres.
  *  friction    orc_step_spin: the same step with angular velocities and
  *              Coulomb friction (coefficient mu) in the resolve: the impulse
  *              gains the tangential part J_t t_p of Sec. "Inter-Particle
@@ -748,4 +754,53 @@ int orc_step_jvp(int64_t n, const double *x, const double *y, const double *z, c
   free(tc);
   if (!partner) free(pp);
   return rc;
+}
+
+/*
+ * Deposition of a per-sphere quantity onto the corner nodes of a periodic
+ * Cartesian grid, Sec. "Dispersed Phase" (projection operator onto the corner
+ * nodes of the host element) and Sec. "Deposition" (linear deposition with
+ * radius equal to the cell size, conservative).  The grid has nc[d] cells of
+ * side h[d] = L[d] / nc[d] per axis and one node per cell corner, node (i, j, k)
+ * at (i h0, j h1, k h2), numbered (k nc1 + j) nc0 + i, indices periodic.  A
+ * sphere at x in cell c (c[d] = floor(x[d] / h[d]), clamped to nc[d] - 1) with
+ * local coordinate f[d] = x[d] / h[d] - c[d] in [0, 1] gives node
+ * c + (b0, b1, b2), b in {0, 1}^3, the weight
+ *   w = prod_d (b_d ? f_d : 1 - f_d),
+ * which on cells of equal volume is the linear (C0) corner weighting of the
+ * paper's operator: the weights of a sphere sum to 1 and reproduce linear
+ * fields.  comp components per sphere, a[q * n + i]; out[q * nnode + node]
+ * receives the sums (overwritten).  Spheres are added in index order, the
+ * eight corners in the order b0 fastest.
+ */
+int orc_deposit(int64_t n, const double *x, const double *y, const double *z, const double *a,
+                int comp, const int nc[3], const double L[3], double *out) {
+  if (n < 0 || comp < 1) return ORC_E_INVALID;
+  for (int d = 0; d < 3; ++d)
+    if (nc[d] < 1 || !(L[d] > 0.0)) return ORC_E_INVALID;
+  const int64_t nnode = (int64_t)nc[0] * nc[1] * nc[2];
+  for (int64_t k = 0; k < nnode * comp; ++k) out[k] = 0.0;
+  const double h[3] = {L[0] / nc[0], L[1] / nc[1], L[2] / nc[2]};
+  for (int64_t i = 0; i < n; ++i) {
+    const double p[3] = {x[i], y[i], z[i]};
+    int c[3];
+    double f[3];
+    for (int d = 0; d < 3; ++d) {
+      if (!isfinite(p[d]) || !(p[d] >= 0.0 && p[d] < L[d])) return ORC_E_INVALID;
+      const double s = p[d] / h[d];
+      int cd = (int)floor(s);
+      if (cd > nc[d] - 1) cd = nc[d] - 1;
+      c[d] = cd;
+      f[d] = s - (double)cd;
+    }
+    for (int b = 0; b < 8; ++b) {
+      const int b0 = b & 1, b1 = (b >> 1) & 1, b2 = (b >> 2) & 1;
+      const double w = ((b0 ? f[0] : 1.0 - f[0]) * (b1 ? f[1] : 1.0 - f[1])) *
+                       (b2 ? f[2] : 1.0 - f[2]);
+      const int ix = (c[0] + b0) % nc[0], iy = (c[1] + b1) % nc[1], iz = (c[2] + b2) % nc[2];
+      const int64_t node = ((int64_t)iz * nc[1] + iy) * nc[0] + ix;
+      for (int q = 0; q < comp; ++q) out[(int64_t)q * nnode + node] += w * a[(int64_t)q * n + i];
+    }
+  }
+  return ORC_OK;
 }

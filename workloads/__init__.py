@@ -211,3 +211,16 @@ def batch_boxes(nbox: int, *, seed: int, nmin: float = 1e3, nmax: float = 6.4e4,
         boxes.append(make_box(nb, seed=seed * 100003 + b + 1, phi=phib, radius=1.0, e=e,
                               name=f"box{b}"))
     return boxes
+
+
+def deposit_case(n: int, *, seed: int, L=(1.0, 1.0, 1.0), comp: int = 4):
+    """Positions uniform in the periodic box [0, L0) x [0, L1) x [0, L2) and comp
+    standard-normal source components per sphere, shape (comp, n) (a momentum source of
+    three components and an energy source, as carried by the deposition)."""
+    L = tuple(float(v) for v in L)
+    pos = []
+    for d in range(3):
+        u = uniforms(seed, 40 + d, n) * L[d]
+        pos.append(np.where(u < L[d], u, np.nextafter(L[d], 0.0)))
+    a = np.stack([normals(seed, 50 + q, n) for q in range(comp)]) if n else np.zeros((comp, 0))
+    return pos[0], pos[1], pos[2], a
