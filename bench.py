@@ -241,6 +241,41 @@ def friction_leg(args, pc, torch, box, p0, ref):
     return out
 
 
+def deposition_leg(args, pc, torch, box, p0):
+    """Deposition of four source components (momentum and energy; standard normal,
+    seed 3) of the 16M spheres at their start positions onto the corner nodes of a
+    160^3 periodic grid over the same box (3.9 spheres per element), pcol_deposit per
+    call: position check with its readback, zero fill, atomic scatter."""
+    import workloads
+    comp, nc = 4, (160, 160, 160)
+    a = torch.as_tensor(workloads.deposit_case(box.n, seed=3, L=box.L, comp=comp)[3]).cuda()
+    ctx = pc.Context(1)
+    nnode = nc[0] * nc[1] * nc[2]
+    out = torch.empty((nc[2], nc[1], nc[0], comp), dtype=torch.float64, device="cuda")
+    for k in range(args.warmup):
+        pc.pcol_deposit(ctx, p0.x, p0.y, p0.z, a, nc, box.L, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        pc.pcol_deposit(ctx, p0.x, p0.y, p0.z, a, nc, box.L, out)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    # algorithmic bytes: positions and sources read once, the node array written once
+    alg = box.n * (24 + 8 * comp) + nnode * comp * 8
+    res = {
+        "value": box.n / wall, "unit": "particles/s", "ms_per_call": wall * 1e3,
+        "nc": list(nc), "comp": comp, "spheres_per_element": box.n / nnode,
+        "atomic_adds_per_s": box.n * 8 * comp / wall,
+        "algorithmic_bytes": alg, "algorithmic_GBps": alg / wall / 1e9,
+        "conservation_rel_error": float(
+            ((out.sum(dim=(0, 1, 2)) - a.sum(dim=1)).abs().max() / a.abs().sum(dim=1).max()).item()),
+    }
+    ctx.close()
+    log(f"[deposition] {res['ms_per_call']:.3f} ms per call, "
+        f"{res['atomic_adds_per_s'] / 1e9:.1f} G atomic adds/s")
+    return res
+
+
 def adjoint_leg(args, pc, torch):
     """Differentiation workload: 1M spheres (phi 0.2, radius 1, e 0.9 learnable),
     10 FP64 steps through the autograd rollout, loss = sum |v|^2 at the end;
@@ -297,6 +332,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-form leg")
     ap.add_argument("--no-friction", action="store_true", help="skip the friction-and-spin leg")
+    ap.add_argument("--no-deposition", action="store_true", help="skip the deposition leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on one GPU only: the collision step is a single-GPU build; "
@@ -447,6 +483,8 @@ def main():
         out["batched_form"] = batched_leg(args, pc, torch)
     if not args.no_friction and "fp64" in forms:
         out["friction_form"] = friction_leg(args, pc, torch, box, p0, forms["fp64"])
+    if not args.no_deposition:
+        out["deposition"] = deposition_leg(args, pc, torch, box, p0)
     if not args.no_adjoint:
         out["adjoint_form"] = adjoint_leg(args, pc, torch)
     if not args.no_cpu_baseline:

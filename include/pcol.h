@@ -292,6 +292,37 @@ pcol_status pcol_step_backward(pcol_ctx *ctx, const pcol_particles *start, const
                                double dt, double e, const int32_t *partner, const double *tcoll,
                                const pcol_state_grad *g_out, pcol_state_grad *g_in, double *ge);
 
+/* Deposition of per-sphere sources onto the corner nodes of a periodic
+ * Cartesian grid: the projection operator of Sec. "Dispersed Phase" (a linear,
+ * C0-continuous inverse-distance weighting onto the eight corner nodes of the
+ * host element) with the deposition radius equal to the cell size, as in Sec.
+ * "Deposition", and the node-wise sum over all spheres.  On cells of equal
+ * volume the weights are trilinear:
+ *   h_d = L_d / nc_d;  s_d = p_d / h_d;  c_d = min(floor(s_d), nc_d - 1);
+ *   f_d = s_d - c_d;  corner b in {0, 1}^3 (b_0 fastest) receives
+ *   w = ((b_0 ? f_0 : 1 - f_0) (b_1 ? f_1 : 1 - f_1)) (b_2 ? f_2 : 1 - f_2)
+ *   times each component, at node ((c_2 + b_2) mod nc_2, (c_1 + b_1) mod nc_1,
+ *   (c_0 + b_0) mod nc_0), node (i, j, k) sitting at (i h_0, j h_1, k h_2).
+ * The weights of one sphere sum to 1 (the deposition is conservative) and the
+ * operator is the transpose of trilinear interpolation of a node field.
+ *   x, y, z: device, n positions, each in [0, L_d) and finite.
+ *   a:       device, comp x n sources, a[q * n + i] (1 <= comp <= 8; the paper
+ *            carries 4: three momentum components and the energy, each with
+ *            the sign the caller wants deposited).
+ *   nc, len: host, cells per axis (1 .. 2^20) and box sides (> 0).
+ *   out:     device, nc_0 nc_1 nc_2 comp doubles, node-major:
+ *            out[((k nc_1 + j) nc_0 + i) comp + q]; overwritten.
+ * The weights are bitwise those of the formulas above; the node sums are formed
+ * with FP64 atomic adds, so their summation order, and with it the last bits,
+ * varies from run to run (each sum is within (k - 1) 2^-53 sum|w a| of the
+ * exact one, k its number of terms).  Positions are checked on the device
+ * first (one readback, so the call synchronises with the stream); on
+ * PCOL_E_INVALID out is unchanged.  n = 0 gives zeros.  Needs no particle
+ * count of the context; allocates 4 bytes of context scratch on first use. */
+pcol_status pcol_deposit(pcol_ctx *ctx, const double *x, const double *y, const double *z,
+                         int64_t n, const double *a, int comp, const int32_t nc[3],
+                         const double len[3], double *out);
+
 #ifdef __cplusplus
 }
 #endif

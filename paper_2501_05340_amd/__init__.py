@@ -120,6 +120,9 @@ def _load():
                                       ctypes.c_double, ctypes.c_double, V, V,
                                       P(pcol_batch_stats)]
     lib.pcol_step_batched.restype = ctypes.c_int
+    lib.pcol_deposit.argtypes = [ctx_p, V, V, V, ctypes.c_int64, V, ctypes.c_int,
+                                 P(ctypes.c_int32), P(ctypes.c_double), V]
+    lib.pcol_deposit.restype = ctypes.c_int
     return lib
 
 
@@ -127,7 +130,8 @@ lib = _load()
 
 EXPORTED = ["pcol_default_opts", "pcol_create", "pcol_destroy", "pcol_last_error",
             "pcol_set_stream", "pcol_bin", "pcol_detect", "pcol_resolve", "pcol_advance",
-            "pcol_step", "pcol_step_spin", "pcol_step_backward", "pcol_step_batched"]
+            "pcol_step", "pcol_step_spin", "pcol_step_backward", "pcol_step_batched",
+            "pcol_deposit"]
 
 
 class PcolError(RuntimeError):
@@ -426,3 +430,26 @@ def rollout(p: Particles, e, L, dt: float, nsteps: int, ctx: Context, checkpoint
     e: float64 0-d tensor (requires_grad for its gradient)."""
     return Rollout.apply(p.x, p.y, p.z, p.vx, p.vy, p.vz, e, p.r, p.m, L, dt, nsteps, ctx,
                          checkpoint_every)
+
+
+def pcol_deposit(ctx: Context, x, y, z, a, nc, L, out=None):
+    """Deposit the sources a (float64 device tensor, shape (comp, n)) of spheres at
+    x, y, z onto the corner nodes of the periodic grid of nc cells per axis over the
+    box L.  Returns out, shape (nc2, nc1, nc0, comp) (node-major), overwritten."""
+    n = int(x.shape[0])
+    comp = int(a.shape[0])
+    if a.dim() != 2 or a.shape[1] != n:
+        raise ValueError("a must have shape (comp, n)")
+    ncs = [int(v) for v in nc]
+    Lb = (L, L, L) if isinstance(L, (int, float)) else L
+    if out is None:
+        out = torch.empty((ncs[2], ncs[1], ncs[0], comp), dtype=torch.float64, device=x.device)
+    if out.numel() != ncs[0] * ncs[1] * ncs[2] * comp:
+        raise ValueError("out has the wrong size")
+    ncv = (ctypes.c_int32 * 3)(*ncs)
+    Lv = (ctypes.c_double * 3)(*[float(v) for v in Lb])
+    ctx.sync_stream()
+    ctx.check(lib.pcol_deposit(ctx.handle, _ptr(x, torch.float64, n), _ptr(y, torch.float64, n),
+                               _ptr(z, torch.float64, n), n, _ptr(a, torch.float64), comp, ncv,
+                               Lv, _ptr(out, torch.float64)))
+    return out

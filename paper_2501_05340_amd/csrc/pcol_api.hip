@@ -78,6 +78,7 @@ struct pcol_ctx {
   int *wide_h = nullptr;           // pinned read-back of that range
   bool bin_pending = false;        // maxcell and the range still in flight (bin_readback)
   const Spin *spin = nullptr;      // set by pcol_step_spin for the step: its spins are validated
+  unsigned int *dep_flag = nullptr, *dep_flag_h = nullptr;  // pcol_deposit's position check
   // bounds for the first layer's pair test: reach, speed and radius
   double reach_pass = 0.0, vmax_pass = 0.0, rmax_pass = 0.0;
   double band = 0.0;   // FP32 filter band in use (relative to r_i + r_j)
@@ -223,7 +224,7 @@ void pcol_destroy(pcol_ctx *ctx) {
                  ctx->count,  ctx->start,  ctx->blocksum, ctx->cnt,      ctx->slot_t,
                  ctx->slot_j, ctx->key_j,  ctx->key_t,  ctx->status,      ctx->out,
                  ctx->ovf,    ctx->partner_tmp, ctx->tcoll_tmp, ctx->list_a, ctx->keep_cnt, ctx->keep_off, ctx->keep_bs, ctx->epoch_d,
-                 ctx->reach_d, ctx->cellc, ctx->ctr_d, ctx->sflags, ctx->stotals};
+                 ctx->reach_d, ctx->cellc, ctx->ctr_d, ctx->sflags, ctx->stotals, ctx->dep_flag};
   for (void *p : dev)
     if (p) (void)hipFree(p);
   if (ctx->reach_h) (void)hipHostFree(ctx->reach_h);
@@ -232,6 +233,7 @@ void pcol_destroy(pcol_ctx *ctx) {
   if (ctx->sflags_h) (void)hipHostFree(ctx->sflags_h);
   if (ctx->stotals_h) (void)hipHostFree(ctx->stotals_h);
   if (ctx->nlist_h) (void)hipHostFree(ctx->nlist_h);
+  if (ctx->dep_flag_h) (void)hipHostFree(ctx->dep_flag_h);
   for (hipEvent_t &e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
   if (BatchPlan *bp = ctx->bp) {
@@ -952,6 +954,49 @@ pcol_status pcol_step_backward(pcol_ctx *ctx, const pcol_particles *start, const
   StateGrad gi{g_in->x, g_in->y, g_in->z, g_in->vx, g_in->vy, g_in->vz};
   PCOL_HIP(launch_step_backward(ctx->stream, to_dev(start), G, dt, e, partner, tcoll, go, gi,
                                 ctx->key_t, ge));
+  return PCOL_OK;
+}
+
+pcol_status pcol_deposit(pcol_ctx *ctx, const double *x, const double *y, const double *z,
+                         int64_t n, const double *a, int comp, const int32_t nc[3],
+                         const double len[3], double *out) {
+  if (!ctx) return PCOL_E_INVALID;
+  if (n < 0 || n > INT32_MAX) return fail(ctx, PCOL_E_INVALID, "n outside [0, 2^31 - 1]");
+  if (comp < 1 || comp > 8) return fail(ctx, PCOL_E_INVALID, "comp outside [1, 8]");
+  if (!nc || !len || !out) return fail(ctx, PCOL_E_INVALID, "null grid or output");
+  if (n > 0 && (!x || !y || !z || !a)) return fail(ctx, PCOL_E_INVALID, "null array");
+  DepositArgs D{};
+  D.x = x;
+  D.y = y;
+  D.z = z;
+  D.a = a;
+  D.n = n;
+  D.comp = comp;
+  D.out = out;
+  D.nnode = 1;
+  for (int d = 0; d < 3; ++d) {
+    if (nc[d] < 1 || nc[d] > (1 << 20)) return fail(ctx, PCOL_E_INVALID, "nc outside [1, 2^20]");
+    if (!(len[d] > 0.0) || !isfinite(len[d])) return fail(ctx, PCOL_E_INVALID, "box side <= 0");
+    D.nc[d] = nc[d];
+    D.L[d] = len[d];
+    D.h[d] = len[d] / nc[d];
+    D.nnode *= nc[d];
+  }
+  if (D.nnode * comp > (int64_t(1) << 36)) return fail(ctx, PCOL_E_INVALID, "grid too large");
+  hipStream_t s = ctx->stream;
+  if (n > 0) {
+    if (!ctx->dep_flag) {
+      PCOL_HIP(dalloc(&ctx->dep_flag, 1));
+      PCOL_HIP(hipHostMalloc((void **)&ctx->dep_flag_h, sizeof(unsigned int)));
+    }
+    PCOL_HIP(hipMemsetAsync(ctx->dep_flag, 0, sizeof(unsigned int), s));
+    PCOL_HIP(launch_deposit_check(s, D, ctx->dep_flag));
+    PCOL_HIP(hipMemcpyAsync(ctx->dep_flag_h, ctx->dep_flag, sizeof(unsigned int),
+                            hipMemcpyDeviceToHost, s));
+    PCOL_HIP(hipStreamSynchronize(s));
+    if (*ctx->dep_flag_h) return fail(ctx, PCOL_E_INVALID, "position outside [0, L) or not finite");
+  }
+  PCOL_HIP(launch_deposit(s, D));
   return PCOL_OK;
 }
 

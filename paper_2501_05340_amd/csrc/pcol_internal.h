@@ -399,6 +399,21 @@ hipError_t launch_step_backward(hipStream_t s, const Particles &P, const Grid &G
                                 double e, const int *partner, const double *tcoll,
                                 const StateGrad &gout, const StateGrad &gin, double *ebuf,
                                 double *ge);
+// Deposition of per-sphere sources onto the corner nodes of a periodic
+// Cartesian grid: positions x, y, z (n), sources a[q * n + i] (comp <= 8),
+// nc cells of side h = L / nc per axis, out[node * comp + q] (nnode nodes).
+struct DepositArgs {
+  const double *x, *y, *z, *a;
+  int64_t n;
+  int comp;
+  int nc[3];
+  double L[3], h[3];
+  int64_t nnode;
+  double *out;
+};
+hipError_t launch_deposit_check(hipStream_t s, const DepositArgs &D, unsigned int *flag);
+// zeroes out, then adds every sphere's eight corner contributions
+hipError_t launch_deposit(hipStream_t s, const DepositArgs &D);
 hipError_t launch_resolve_public(hipStream_t s, int n, const Rec *rec, const int *rank,
                                  const Grid &G, double dt, double e, const uint64_t *key,
                                  const Particles &P, uint8_t *active, int *partner, double *tcoll,

@@ -5,6 +5,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 namespace pcol {
 
 namespace {
@@ -2208,6 +2210,113 @@ hipError_t launch_sweep_check(hipStream_t s, SweepCounters *ctr, unsigned int *f
                               unsigned long long *totals, int last) {
   hipLaunchKernelGGL(k_sweep_check, dim3(1), dim3(64), 0, s, ctr, flags, totals, last);
   return hipGetLastError();
+}
+
+}  // namespace pcol
+
+// ---------------------------------------------------------------- deposition
+//
+// Sec. "Dispersed Phase" (projection operator) and Sec. "Deposition": each
+// sphere's source components are imposed linearly on the eight corner nodes of
+// its host cell of a periodic Cartesian grid (deposition radius = cell side;
+// on equal cells the C0 inverse-distance weights are the trilinear ones), and
+// the node sums are formed with atomic adds, the device counterpart of the
+// node-local accumulate of the paper.  Nodes are stored node-major:
+// out[node * comp + q], node = (k nc1 + j) nc0 + i.
+namespace pcol {
+
+namespace {
+
+// Positions inside [0, L) and finite on every axis; one flag word for all.
+__global__ __launch_bounds__(256) void k_deposit_check(DepositArgs D, unsigned int *flag) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < D.n; i += stride) {
+    const double p0 = D.x[i], p1 = D.y[i], p2 = D.z[i];
+    bad |= !(p0 >= 0.0 && p0 < D.L[0]) || !(p1 >= 0.0 && p1 < D.L[1]) ||
+           !(p2 >= 0.0 && p2 < D.L[2]);
+  }
+  if (__ballot(bad) != 0ull && __lane_id() == 0) atomicOr(flag, 1u);
+}
+
+__global__ __launch_bounds__(256) void k_fill_zero(double *out, int64_t len) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < len; k += stride)
+    out[k] = 0.0;
+}
+
+// Host cell and local coordinate of p on one axis: s = p / h, c = floor(s)
+// (at most nc - 1), f = s - c in [0, 1].
+__device__ __forceinline__ int dep_cell(double p, double h, int nc, double &f) {
+  const double s = p / h;
+  int c = (int)floor(s);
+  c = c > nc - 1 ? nc - 1 : c;
+  f = s - (double)c;
+  return c;
+}
+
+// One sphere per thread: its COMP components stay in registers, and each of
+// the eight corners receives w a_q by a hardware FP64 atomic add at the node
+// (no return value, so the adds are fire-and-forget at the L2).
+template <int COMP>
+__global__ __launch_bounds__(256) void k_deposit(DepositArgs D) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= D.n) return;
+  double f0, f1, f2;
+  const int c0 = dep_cell(D.x[i], D.h[0], D.nc[0], f0);
+  const int c1 = dep_cell(D.y[i], D.h[1], D.nc[1], f1);
+  const int c2 = dep_cell(D.z[i], D.h[2], D.nc[2], f2);
+  double a[COMP];
+#pragma unroll
+  for (int q = 0; q < COMP; ++q) a[q] = D.a[(int64_t)q * D.n + i];
+  const int i1 = c0 + 1 == D.nc[0] ? 0 : c0 + 1;
+  const int j1 = c1 + 1 == D.nc[1] ? 0 : c1 + 1;
+  const int k1 = c2 + 1 == D.nc[2] ? 0 : c2 + 1;
+  const double g0 = 1.0 - f0, g1 = 1.0 - f1, g2 = 1.0 - f2;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const int b0 = b & 1, b1 = (b >> 1) & 1, b2 = (b >> 2) & 1;
+    const double w = ((b0 ? f0 : g0) * (b1 ? f1 : g1)) * (b2 ? f2 : g2);
+    const int64_t node =
+        ((int64_t)(b2 ? k1 : c2) * D.nc[1] + (b1 ? j1 : c1)) * D.nc[0] + (b0 ? i1 : c0);
+    double *dst = D.out + node * COMP;
+#pragma unroll
+    for (int q = 0; q < COMP; ++q) unsafeAtomicAdd(dst + q, w * a[q]);
+  }
+}
+
+template <int COMP>
+hipError_t deposit_comp(hipStream_t s, const DepositArgs &D) {
+  hipLaunchKernelGGL(k_deposit<COMP>, dim3((unsigned)((D.n + 255) / 256)), dim3(256), 0, s, D);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_deposit_check(hipStream_t s, const DepositArgs &D, unsigned int *flag) {
+  if (D.n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((D.n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_deposit_check, dim3((unsigned)blocks), dim3(256), 0, s, D, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_deposit(hipStream_t s, const DepositArgs &D) {
+  const int64_t len = D.nnode * D.comp;
+  const int64_t zb = std::min<int64_t>((len + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)zb), dim3(256), 0, s, D.out, len);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || D.n <= 0) return e;
+  switch (D.comp) {
+    case 1: return deposit_comp<1>(s, D);
+    case 2: return deposit_comp<2>(s, D);
+    case 3: return deposit_comp<3>(s, D);
+    case 4: return deposit_comp<4>(s, D);
+    case 5: return deposit_comp<5>(s, D);
+    case 6: return deposit_comp<6>(s, D);
+    case 7: return deposit_comp<7>(s, D);
+    case 8: return deposit_comp<8>(s, D);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace pcol

@@ -19,8 +19,12 @@ def declared_functions():
 
 @pytest.fixture(scope="module")
 def lib():
-    if not os.path.exists(LIB):
-        from paper_2501_05340_amd import build as b
+    if not os.path.exists(LIB):  # the build script by path: the package itself loads LIB
+        import importlib.util
+        spec = importlib.util.spec_from_file_location(
+            "_pcol_build", os.path.join(ROOT, "paper_2501_05340_amd", "build.py"))
+        b = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(b)
         b.build()
     return ctypes.CDLL(LIB)
 
