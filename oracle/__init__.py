@@ -84,6 +84,10 @@ def _load():
         lib.orc_resolve_pair_spin.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_double] + \
             [_D] * 11 + [_D, ctypes.c_double, ctypes.c_double, ctypes.c_double] + [_D] * 9
         lib.orc_resolve_pair_spin.restype = None
+        lib.orc_step_sequential.argtypes = [ctypes.c_int64] + [_D] * 8 + [
+            _D, ctypes.c_double, ctypes.c_double, ctypes.c_double] + [_D] * 6 + [
+            _I64, _D, ctypes.POINTER(_Stats)]
+        lib.orc_step_sequential.restype = ctypes.c_int
         lib.orc_deposit.argtypes = [ctypes.c_int64, _D, _D, _D, _D, ctypes.c_int,
                                     ctypes.POINTER(ctypes.c_int), _D, _D]
         lib.orc_deposit.restype = ctypes.c_int
@@ -281,3 +285,23 @@ def deposit(x, y, z, a, nc, L):
     if rc:
         raise OracleError(rc)
     return out.reshape(comp, int(nc[2]), int(nc[1]), int(nc[0]))
+
+
+def step_sequential(box, *, e: float | None = None, cell_mult: float = 1.0) -> StepResult:
+    """One step of ``box`` with the paper's collision order taken literally (elements
+    along a Morton curve, first valid collision found, one pass); inputs unchanged."""
+    n = box.n
+    arrs = [_c64(a) for a in (box.x, box.y, box.z, box.vx, box.vy, box.vz, box.r, box.m)]
+    outs = [np.empty(n) for _ in range(6)]
+    partner = np.empty(n, dtype=np.int64)
+    tcoll = np.empty(n)
+    st = _Stats()
+    rc = _load().orc_step_sequential(n, *[_d(a) for a in arrs], _d(_c64(box.L)), float(box.dt),
+                                     float(box.e if e is None else e), float(cell_mult),
+                                     *[_d(o) for o in outs], partner.ctypes.data_as(_I64),
+                                     _d(tcoll), ctypes.byref(st))
+    if rc:
+        raise OracleError(rc)
+    sweep = np.where(partner >= 0, 0, -1).astype(np.int32)
+    return StepResult(*outs, partner, tcoll, sweep, st.n_pairs, st.n_sweeps, st.pair_tests,
+                      st.reach)

@@ -42,6 +42,13 @@
  *              C0-continuous inverse-distance weighting with deposition radius
  *              equal to the cell size, on cells of equal volume: trilinear
  *              weights), summed over all spheres.
+ *  literal     orc_step_sequential: the order of Sec. "Collision Operator" and
+ *  order       Sec. "Particle-Particle Collisions" taken literally: elements visited
+ *              one after another along a space-filling curve, each particle
+ *              scanning its candidate elements in curve order and taking the
+ *              first valid collision it finds; both particles then leave the
+ *              eligible set.  Sequential by definition; it serves to measure
+ *              how far the order-free rule above departs from it.
  *  friction    orc_step_spin: the same step with angular velocities and
  *              Coulomb friction (coefficient mu) in the resolve: the impulse
  *              gains the tangential part J_t t_p of Sec. "Inter-Particle
@@ -802,5 +809,143 @@ int orc_deposit(int64_t n, const double *x, const double *y, const double *z, co
       for (int q = 0; q < comp; ++q) out[(int64_t)q * nnode + node] += w * a[(int64_t)q * n + i];
     }
   }
+  return ORC_OK;
+}
+
+/* Morton (Z-order) key of a cell: bits of cx, cy, cz interleaved, x lowest. */
+static uint64_t orc_morton(int cx, int cy, int cz) {
+  uint64_t k = 0;
+  for (int b = 0; b < 21; ++b) {
+    k |= (uint64_t)((cx >> b) & 1) << (3 * b);
+    k |= (uint64_t)((cy >> b) & 1) << (3 * b + 1);
+    k |= (uint64_t)((cz >> b) & 1) << (3 * b + 2);
+  }
+  return k;
+}
+
+typedef struct {
+  uint64_t key;
+  int64_t cell;
+} orc_keyed;
+
+static int orc_keyed_cmp(const void *a, const void *b) {
+  const orc_keyed *p = (const orc_keyed *)a, *q = (const orc_keyed *)b;
+  return p->key < q->key ? -1 : (p->key > q->key ? 1 : 0);
+}
+
+/*
+ * One step with the collision order of the paper taken literally, Sec.
+ * "Collision Operator" and Sec. "Particle-Particle Collisions": the elements
+ * (here the cells of the plain grid, side >= reach * cell_mult) are visited in
+ * the order of a space-filling curve (Morton order: the paper names none); the
+ * particles of an element in index order; each still eligible particle i scans
+ * its candidate elements (its own and the adjacent ones, periodic, sorted along
+ * the same curve), their particles in index order, and the first eligible j
+ * whose contact time (orc_pair_time: two positive roots, approach, t <= dt)
+ * exists is its partner: both are resolved at once (orc_resolve_pair, from
+ * start-of-step data) and leave the eligible set.  Every particle without a
+ * collision flies freely.  One pass, no sweeps; the result is a maximal set
+ * of disjoint colliding pairs, not in general the earliest-partner set.
+ * Outputs as orc_step; st->n_sweeps = 1, st->pair_tests counts contact-time
+ * evaluations.
+ */
+int orc_step_sequential(int64_t n, const double *x, const double *y, const double *z,
+                        const double *vx, const double *vy, const double *vz, const double *r,
+                        const double *m, const double L[3], double dt, double e, double cell_mult,
+                        double *xo, double *yo, double *zo, double *vxo, double *vyo,
+                        double *vzo, int64_t *partner, double *tcoll, orc_stats *st) {
+  int rc = orc_check_inputs(n, x, y, z, vx, vy, vz, r, m, L, dt);
+  if (rc) return rc;
+  if (!(e >= 0.0 && e <= 1.0) || !(cell_mult >= 1.0)) return ORC_E_INVALID;
+  const double reach = orc_reach(n, vx, vy, vz, r, dt);
+  for (int a = 0; a < 3; ++a)
+    if (!(L[a] > 2.0 * reach)) return ORC_E_BOX;
+  orc_grid G;
+  rc = orc_grid_build(&G, n, x, y, z, L, reach * cell_mult);
+  if (rc) return rc;
+  const int64_t ncell = (int64_t)G.nc[0] * G.nc[1] * G.nc[2];
+  orc_keyed *order = (orc_keyed *)malloc((size_t)(ncell > 0 ? ncell : 1) * sizeof(orc_keyed));
+  uint8_t *hit = (uint8_t *)calloc((size_t)(n > 0 ? n : 1), 1);
+  if (!order || !hit) {
+    free(order);
+    free(hit);
+    orc_grid_free(&G);
+    return ORC_E_NOMEM;
+  }
+  for (int64_t c = 0; c < ncell; ++c) {
+    const int cx = (int)(c % G.nc[0]), cy = (int)((c / G.nc[0]) % G.nc[1]),
+              cz = (int)(c / ((int64_t)G.nc[0] * G.nc[1]));
+    order[c].key = orc_morton(cx, cy, cz);
+    order[c].cell = c;
+  }
+  qsort(order, (size_t)ncell, sizeof(orc_keyed), orc_keyed_cmp);
+  for (int64_t i = 0; i < n; ++i) {
+    if (partner) partner[i] = -1;
+    if (tcoll) tcoll[i] = NAN;
+  }
+  int64_t pairs = 0, tests = 0;
+  for (int64_t oc = 0; oc < ncell; ++oc) {
+    const int64_t c = order[oc].cell;
+    const int cx = (int)(c % G.nc[0]), cy = (int)((c / G.nc[0]) % G.nc[1]),
+              cz = (int)(c / ((int64_t)G.nc[0] * G.nc[1]));
+    /* candidate elements of this element, sorted along the curve */
+    orc_keyed cand[27];
+    int nk = 0;
+    for (int a = 0; a < G.nb[2]; ++a)
+      for (int b = 0; b < G.nb[1]; ++b)
+        for (int d = 0; d < G.nb[0]; ++d) {
+          const int qx = (cx + G.off[0][d] + G.nc[0]) % G.nc[0];
+          const int qy = (cy + G.off[1][b] + G.nc[1]) % G.nc[1];
+          const int qz = (cz + G.off[2][a] + G.nc[2]) % G.nc[2];
+          cand[nk].key = orc_morton(qx, qy, qz);
+          cand[nk].cell = ((int64_t)qz * G.nc[1] + qy) * G.nc[0] + qx;
+          ++nk;
+        }
+    qsort(cand, (size_t)nk, sizeof(orc_keyed), orc_keyed_cmp);
+    for (int64_t s = G.start[c]; s < G.start[c + 1]; ++s) {
+      const int64_t i = G.item[s];
+      if (hit[i]) continue;
+      const double xi[3] = {x[i], y[i], z[i]}, vi[3] = {vx[i], vy[i], vz[i]};
+      for (int k = 0; k < nk && !hit[i]; ++k) {
+        const int64_t q = cand[k].cell;
+        for (int64_t u = G.start[q]; u < G.start[q + 1]; ++u) {
+          const int64_t j = G.item[u];
+          if (j == i || hit[j]) continue;
+          const double xj[3] = {x[j], y[j], z[j]}, vj[3] = {vx[j], vy[j], vz[j]};
+          double t;
+          ++tests;
+          if (!orc_pair_time(xi, vi, r[i], xj, vj, r[j], L, dt, &t)) continue;
+          orc_resolve_pair(i, j, t, x, y, z, vx, vy, vz, r, m, L, dt, e, xo, yo, zo, vxo, vyo,
+                           vzo);
+          hit[i] = hit[j] = 1;
+          if (partner) {
+            partner[i] = j;
+            partner[j] = i;
+          }
+          if (tcoll) tcoll[i] = tcoll[j] = t;
+          ++pairs;
+          break;
+        }
+      }
+    }
+  }
+  const double *p[3] = {x, y, z}, *v[3] = {vx, vy, vz};
+  double *po[3] = {xo, yo, zo}, *vo[3] = {vxo, vyo, vzo};
+  for (int64_t i = 0; i < n; ++i) {
+    if (hit[i]) continue;
+    for (int k = 0; k < 3; ++k) {
+      po[k][i] = orc_wrap_pos(p[k][i] + dt * v[k][i], L[k]);
+      vo[k][i] = v[k][i];
+    }
+  }
+  if (st) {
+    st->n_pairs = pairs;
+    st->n_sweeps = 1;
+    st->pair_tests = tests;
+    st->reach = reach;
+  }
+  free(order);
+  free(hit);
+  orc_grid_free(&G);
   return ORC_OK;
 }
