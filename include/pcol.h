@@ -309,16 +309,23 @@ pcol_status pcol_step_backward(pcol_ctx *ctx, const pcol_particles *start, const
  *   a:       device, comp x n sources, a[q * n + i] (1 <= comp <= 8; the paper
  *            carries 4: three momentum components and the energy, each with
  *            the sign the caller wants deposited).
- *   nc, len: host, cells per axis (1 .. 2^20) and box sides (> 0).
+ *   nc, len: host, cells per axis (1 .. 2^20, at most 2^31 - 1 elements in all)
+ *            and box sides (> 0).
  *   out:     device, nc_0 nc_1 nc_2 comp doubles, node-major:
  *            out[((k nc_1 + j) nc_0 + i) comp + q]; overwritten.
- * The weights are bitwise those of the formulas above; the node sums are formed
- * with FP64 atomic adds, so their summation order, and with it the last bits,
- * varies from run to run (each sum is within (k - 1) 2^-53 sum|w a| of the
- * exact one, k its number of terms).  Positions are checked on the device
- * first (one readback, so the call synchronises with the stream); on
- * PCOL_E_INVALID out is unchanged.  n = 0 gives zeros.  Needs no particle
- * count of the context; allocates 4 bytes of context scratch on first use. */
+ * The weights are bitwise those of the formulas above.  The node sums are
+ * formed without floating-point atomics: the spheres are counted and scattered
+ * by element (a counting sort), each element sums w a over its spheres in
+ * caller-index order (scatter order for an element of more than 64 spheres),
+ * and each node adds the corner sums of its eight elements in the order
+ * b = 0..7.  Repeated calls on the same input therefore agree bit for bit (up
+ * to 64 spheres per element); against a sum in caller-index order each node is
+ * within 2 (k - 1) 2^-53 sum|w a| (k its number of terms), and a node with one
+ * term is exact.  Positions are checked on the device first (one readback, so
+ * the call synchronises with the stream); on PCOL_E_INVALID out is unchanged.
+ * n = 0 gives zeros.  Scratch: about (72 + 8 comp) bytes per sphere and
+ * (12 + 64 comp) bytes per element, held by the context and grown on demand
+ * (independent of n_max); growing it synchronises with the stream. */
 pcol_status pcol_deposit(pcol_ctx *ctx, const double *x, const double *y, const double *z,
                          int64_t n, const double *a, int comp, const int32_t nc[3],
                          const double len[3], double *out);

@@ -78,7 +78,14 @@ struct pcol_ctx {
   int *wide_h = nullptr;           // pinned read-back of that range
   bool bin_pending = false;        // maxcell and the range still in flight (bin_readback)
   const Spin *spin = nullptr;      // set by pcol_step_spin for the step: its spins are validated
-  unsigned int *dep_flag = nullptr, *dep_flag_h = nullptr;  // pcol_deposit's position check
+  // pcol_deposit: position check flag, and the element sort's scratch with its capacities
+  unsigned int *dep_flag = nullptr, *dep_flag_h = nullptr;
+  int *dep_eid = nullptr, *dep_slot = nullptr, *dep_cnt = nullptr, *dep_start = nullptr,
+      *dep_bsum = nullptr;
+  unsigned char *dep_rec = nullptr;
+  double *dep_E = nullptr;
+  ReachOut *dep_ro = nullptr;
+  int64_t dep_cap_n = 0, dep_cap_rec = 0, dep_cap_el = 0, dep_cap_E = 0;
   // bounds for the first layer's pair test: reach, speed and radius
   double reach_pass = 0.0, vmax_pass = 0.0, rmax_pass = 0.0;
   double band = 0.0;   // FP32 filter band in use (relative to r_i + r_j)
@@ -183,6 +190,18 @@ Particles to_dev(const pcol_particles *p) {
   return P;
 }
 
+// (re)allocate *p for at least `want` elements when its capacity `cap` is short
+template <typename T>
+hipError_t grow(T **p, int64_t &cap, int64_t want) {
+  if (*p && cap >= want) return hipSuccess;
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  cap = 0;
+  const hipError_t e = hipMalloc((void **)p, (size_t)(want > 0 ? want : 1) * sizeof(T));
+  if (e == hipSuccess) cap = want;
+  return e;
+}
+
 double ms_between(hipEvent_t a, hipEvent_t b) {
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0;
@@ -224,7 +243,9 @@ void pcol_destroy(pcol_ctx *ctx) {
                  ctx->count,  ctx->start,  ctx->blocksum, ctx->cnt,      ctx->slot_t,
                  ctx->slot_j, ctx->key_j,  ctx->key_t,  ctx->status,      ctx->out,
                  ctx->ovf,    ctx->partner_tmp, ctx->tcoll_tmp, ctx->list_a, ctx->keep_cnt, ctx->keep_off, ctx->keep_bs, ctx->epoch_d,
-                 ctx->reach_d, ctx->cellc, ctx->ctr_d, ctx->sflags, ctx->stotals, ctx->dep_flag};
+                 ctx->reach_d, ctx->cellc, ctx->ctr_d, ctx->sflags, ctx->stotals, ctx->dep_flag,
+                 ctx->dep_eid, ctx->dep_slot, ctx->dep_cnt, ctx->dep_start, ctx->dep_bsum,
+                 ctx->dep_rec, ctx->dep_E, ctx->dep_ro};
   for (void *p : dev)
     if (p) (void)hipFree(p);
   if (ctx->reach_h) (void)hipHostFree(ctx->reach_h);
@@ -981,8 +1002,8 @@ pcol_status pcol_deposit(pcol_ctx *ctx, const double *x, const double *y, const 
     D.L[d] = len[d];
     D.h[d] = len[d] / nc[d];
     D.nnode *= nc[d];
+    if (D.nnode > INT32_MAX) return fail(ctx, PCOL_E_INVALID, "more than 2^31 - 1 elements");
   }
-  if (D.nnode * comp > (int64_t(1) << 36)) return fail(ctx, PCOL_E_INVALID, "grid too large");
   hipStream_t s = ctx->stream;
   if (n > 0) {
     if (!ctx->dep_flag) {
@@ -996,6 +1017,34 @@ pcol_status pcol_deposit(pcol_ctx *ctx, const double *x, const double *y, const 
     PCOL_HIP(hipStreamSynchronize(s));
     if (*ctx->dep_flag_h) return fail(ctx, PCOL_E_INVALID, "position outside [0, L) or not finite");
   }
+  const int64_t ne = D.nnode;
+  int64_t cap_start = ctx->dep_cap_el, cap_bsum = ctx->dep_cap_el, cap_ro = ctx->dep_ro ? 1 : 0;
+  int64_t cap_slot = ctx->dep_cap_n;
+  if (ctx->dep_cap_n < n || ctx->dep_cap_rec < n * deposit_record_bytes(comp) ||
+      ctx->dep_cap_el < ne + 1 || ctx->dep_cap_E < 8 * comp * ne || !ctx->dep_ro)
+    PCOL_HIP(hipStreamSynchronize(s));  // the frees below wait for nothing queued
+  hipError_t e = grow(&ctx->dep_eid, ctx->dep_cap_n, n);
+  if (e == hipSuccess) e = grow(&ctx->dep_slot, cap_slot, n);
+  if (e == hipSuccess) e = grow(&ctx->dep_rec, ctx->dep_cap_rec, n * deposit_record_bytes(comp));
+  if (e == hipSuccess) e = grow(&ctx->dep_cnt, ctx->dep_cap_el, ne + 1);
+  if (e == hipSuccess) e = grow(&ctx->dep_start, cap_start, ne + 1);
+  if (e == hipSuccess) e = grow(&ctx->dep_bsum, cap_bsum, ne + 1);
+  if (e == hipSuccess) e = grow(&ctx->dep_E, ctx->dep_cap_E, 8 * comp * ne);
+  if (e == hipSuccess) e = grow(&ctx->dep_ro, cap_ro, 1);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, e == hipErrorOutOfMemory ? PCOL_E_NOMEM : PCOL_E_HIP,
+                "deposition scratch allocation failed");
+  }
+  D.eid = ctx->dep_eid;
+  D.slot = ctx->dep_slot;
+  D.cnt = ctx->dep_cnt;
+  D.start = ctx->dep_start;
+  D.rec = ctx->dep_rec;
+  D.E = ctx->dep_E;
+  PCOL_HIP(hipMemsetAsync(ctx->dep_cnt, 0, (size_t)ne * sizeof(int), s));
+  PCOL_HIP(launch_deposit_count(s, D));
+  PCOL_HIP(launch_scan(s, ctx->dep_cnt, (int)ne, ctx->dep_start, ctx->dep_bsum, ctx->dep_ro));
   PCOL_HIP(launch_deposit(s, D));
   return PCOL_OK;
 }

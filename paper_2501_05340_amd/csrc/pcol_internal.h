@@ -401,7 +401,10 @@ hipError_t launch_step_backward(hipStream_t s, const Particles &P, const Grid &G
                                 double *ge);
 // Deposition of per-sphere sources onto the corner nodes of a periodic
 // Cartesian grid: positions x, y, z (n), sources a[q * n + i] (comp <= 8),
-// nc cells of side h = L / nc per axis, out[node * comp + q] (nnode nodes).
+// nc cells of side h = L / nc per axis, out[node * comp + q] (nnode nodes,
+// one per element).  Scratch: eid, slot (n each), cnt (nnode, zeroed before the
+// count), start (nnode + 1), rec (n records of deposit_record_bytes(comp)), E
+// (8 comp nnode corner sums).
 struct DepositArgs {
   const double *x, *y, *z, *a;
   int64_t n;
@@ -410,9 +413,15 @@ struct DepositArgs {
   double L[3], h[3];
   int64_t nnode;
   double *out;
+  int *eid, *slot, *cnt, *start;
+  void *rec;
+  double *E;
 };
+int64_t deposit_record_bytes(int comp);
 hipError_t launch_deposit_check(hipStream_t s, const DepositArgs &D, unsigned int *flag);
-// zeroes out, then adds every sphere's eight corner contributions
+// element and slot of every sphere (cnt must be zero)
+hipError_t launch_deposit_count(hipStream_t s, const DepositArgs &D);
+// after the scan of cnt into start: scatter, element corner sums, node sums
 hipError_t launch_deposit(hipStream_t s, const DepositArgs &D);
 hipError_t launch_resolve_public(hipStream_t s, int n, const Rec *rec, const int *rank,
                                  const Grid &G, double dt, double e, const uint64_t *key,

@@ -2220,12 +2220,30 @@ hipError_t launch_sweep_check(hipStream_t s, SweepCounters *ctr, unsigned int *f
 // sphere's source components are imposed linearly on the eight corner nodes of
 // its host cell of a periodic Cartesian grid (deposition radius = cell side;
 // on equal cells the C0 inverse-distance weights are the trilinear ones), and
-// the node sums are formed with atomic adds, the device counterpart of the
-// node-local accumulate of the paper.  Nodes are stored node-major:
-// out[node * comp + q], node = (k nc1 + j) nc0 + i.
+// every node receives the sum over spheres.  The paper accumulates with atomic
+// adds; on this GPU FP64 atomics to HBM run at about 23e9 per second, so 32 per
+// sphere would bound the operator at 0.7e9 spheres/s whatever the memory
+// order.  Instead the spheres are counted and scattered by element (a counting
+// sort, one integer atomic per sphere), each element sums its spheres' corner
+// contributions in caller-index order, and each node gathers the eight corner
+// sums that touch it in a fixed order: no floating-point atomics, and the
+// result is the same bit for bit on every run.  Nodes are stored node-major:
+// out[node * comp + q], node = (k nc1 + j) nc0 + i; element e has the node of
+// the same number as its corner (0, 0, 0).
 namespace pcol {
 
 namespace {
+
+// Members of an element are taken in caller-index order (a selection over the
+// element's records) up to this many; a larger element sums in scatter order.
+constexpr int DEP_SORT_MAX = 64;
+
+template <int COMP>
+struct alignas(16) DepRec {
+  double p[3];
+  double a[COMP];
+  long long o;  // caller index
+};
 
 // Positions inside [0, L) and finite on every axis; one flag word for all.
 __global__ __launch_bounds__(256) void k_deposit_check(DepositArgs D, unsigned int *flag) {
@@ -2239,12 +2257,6 @@ __global__ __launch_bounds__(256) void k_deposit_check(DepositArgs D, unsigned i
   if (__ballot(bad) != 0ull && __lane_id() == 0) atomicOr(flag, 1u);
 }
 
-__global__ __launch_bounds__(256) void k_fill_zero(double *out, int64_t len) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < len; k += stride)
-    out[k] = 0.0;
-}
-
 // Host cell and local coordinate of p on one axis: s = p / h, c = floor(s)
 // (at most nc - 1), f = s - c in [0, 1].
 __device__ __forceinline__ int dep_cell(double p, double h, int nc, double &f) {
@@ -2255,43 +2267,122 @@ __device__ __forceinline__ int dep_cell(double p, double h, int nc, double &f) {
   return c;
 }
 
-// One sphere per thread: its COMP components stay in registers, and each of
-// the eight corners receives w a_q by a hardware FP64 atomic add at the node
-// (no return value, so the adds are fire-and-forget at the L2).
-template <int COMP>
-__global__ __launch_bounds__(256) void k_deposit(DepositArgs D) {
+// element of every sphere and its slot among the element's spheres
+__global__ __launch_bounds__(256) void k_dep_count(DepositArgs D) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= D.n) return;
-  double f0, f1, f2;
-  const int c0 = dep_cell(D.x[i], D.h[0], D.nc[0], f0);
-  const int c1 = dep_cell(D.y[i], D.h[1], D.nc[1], f1);
-  const int c2 = dep_cell(D.z[i], D.h[2], D.nc[2], f2);
-  double a[COMP];
+  double f;
+  const int c0 = dep_cell(D.x[i], D.h[0], D.nc[0], f);
+  const int c1 = dep_cell(D.y[i], D.h[1], D.nc[1], f);
+  const int c2 = dep_cell(D.z[i], D.h[2], D.nc[2], f);
+  const int e = (c2 * D.nc[1] + c1) * D.nc[0] + c0;
+  D.eid[i] = e;
+  D.slot[i] = atomicAdd(&D.cnt[e], 1);
+}
+
+// one record per sphere at its element-sorted position (caller arrays read
+// coalesced)
+template <int COMP>
+__global__ __launch_bounds__(256) void k_dep_scatter(DepositArgs D) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= D.n) return;
+  DepRec<COMP> r;
+  r.p[0] = D.x[i];
+  r.p[1] = D.y[i];
+  r.p[2] = D.z[i];
 #pragma unroll
-  for (int q = 0; q < COMP; ++q) a[q] = D.a[(int64_t)q * D.n + i];
-  const int i1 = c0 + 1 == D.nc[0] ? 0 : c0 + 1;
-  const int j1 = c1 + 1 == D.nc[1] ? 0 : c1 + 1;
-  const int k1 = c2 + 1 == D.nc[2] ? 0 : c2 + 1;
-  const double g0 = 1.0 - f0, g1 = 1.0 - f1, g2 = 1.0 - f2;
+  for (int q = 0; q < COMP; ++q) r.a[q] = D.a[(int64_t)q * D.n + i];
+  r.o = i;
+  reinterpret_cast<DepRec<COMP> *>(D.rec)[D.start[D.eid[i]] + D.slot[i]] = r;
+}
+
+// One thread per element: the eight corner sums of its spheres, each a sum in
+// caller-index order of w_b a_q with the trilinear weight
+// w_b = ((b0 ? f0 : 1 - f0) (b1 ? f1 : 1 - f1)) (b2 ? f2 : 1 - f2).
+// E[(b COMP + q) nelem + e]: coalesced across the element threads.
+template <int COMP>
+__global__ __launch_bounds__(256) void k_dep_elem(DepositArgs D) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= D.nnode) return;
+  const DepRec<COMP> *R = reinterpret_cast<const DepRec<COMP> *>(D.rec);
+  const int m0 = D.start[e], m1 = D.start[e + 1];
+  const bool ordered = m1 - m0 <= DEP_SORT_MAX;
+  double acc[8][COMP];
+#pragma unroll
+  for (int b = 0; b < 8; ++b)
+#pragma unroll
+    for (int q = 0; q < COMP; ++q) acc[b][q] = 0.0;
+  long long last = -1;
+  for (int t = m0; t < m1; ++t) {
+    int k = t;
+    if (ordered) {  // the next caller index after `last`
+      long long best = 0x7fffffffffffffffll;
+      for (int u = m0; u < m1; ++u) {
+        const long long o = R[u].o;
+        if (o > last && o < best) {
+          best = o;
+          k = u;
+        }
+      }
+      last = best;
+    }
+    const DepRec<COMP> r = R[k];
+    double f0, f1, f2;
+    (void)dep_cell(r.p[0], D.h[0], D.nc[0], f0);
+    (void)dep_cell(r.p[1], D.h[1], D.nc[1], f1);
+    (void)dep_cell(r.p[2], D.h[2], D.nc[2], f2);
+    const double g0 = 1.0 - f0, g1 = 1.0 - f1, g2 = 1.0 - f2;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const double w = (((b & 1) ? f0 : g0) * ((b & 2) ? f1 : g1)) * ((b & 4) ? f2 : g2);
+#pragma unroll
+      for (int q = 0; q < COMP; ++q) acc[b][q] += w * r.a[q];
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < 8; ++b)
+#pragma unroll
+    for (int q = 0; q < COMP; ++q) D.E[(int64_t)(b * COMP + q) * D.nnode + e] = acc[b][q];
+}
+
+// One thread per node: node (i, j, k) is corner b of element (i - b0, j - b1,
+// k - b2) (periodic); the eight corner sums are added in the order b = 0..7.
+template <int COMP>
+__global__ __launch_bounds__(256) void k_dep_node(DepositArgs D) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= D.nnode) return;
+  const int i = (int)(n % D.nc[0]);
+  const int j = (int)((n / D.nc[0]) % D.nc[1]);
+  const int k = (int)(n / ((int64_t)D.nc[0] * D.nc[1]));
+  const int im = i == 0 ? D.nc[0] - 1 : i - 1;
+  const int jm = j == 0 ? D.nc[1] - 1 : j - 1;
+  const int km = k == 0 ? D.nc[2] - 1 : k - 1;
+  double s[COMP];
+#pragma unroll
+  for (int q = 0; q < COMP; ++q) s[q] = 0.0;
 #pragma unroll
   for (int b = 0; b < 8; ++b) {
-    const int b0 = b & 1, b1 = (b >> 1) & 1, b2 = (b >> 2) & 1;
-    const double w = ((b0 ? f0 : g0) * (b1 ? f1 : g1)) * (b2 ? f2 : g2);
-    const int64_t node =
-        ((int64_t)(b2 ? k1 : c2) * D.nc[1] + (b1 ? j1 : c1)) * D.nc[0] + (b0 ? i1 : c0);
-    double *dst = D.out + node * COMP;
+    const int64_t e = ((int64_t)((b & 4) ? km : k) * D.nc[1] + ((b & 2) ? jm : j)) * D.nc[0] +
+                      ((b & 1) ? im : i);
 #pragma unroll
-    for (int q = 0; q < COMP; ++q) unsafeAtomicAdd(dst + q, w * a[q]);
+    for (int q = 0; q < COMP; ++q) s[q] += D.E[(int64_t)(b * COMP + q) * D.nnode + e];
   }
+#pragma unroll
+  for (int q = 0; q < COMP; ++q) D.out[n * COMP + q] = s[q];
 }
 
 template <int COMP>
-hipError_t deposit_comp(hipStream_t s, const DepositArgs &D) {
-  hipLaunchKernelGGL(k_deposit<COMP>, dim3((unsigned)((D.n + 255) / 256)), dim3(256), 0, s, D);
+hipError_t deposit_sorted(hipStream_t s, const DepositArgs &D) {
+  const unsigned gn = (unsigned)((D.n + 255) / 256), ge = (unsigned)((D.nnode + 255) / 256);
+  if (D.n > 0) hipLaunchKernelGGL(k_dep_scatter<COMP>, dim3(gn), dim3(256), 0, s, D);
+  hipLaunchKernelGGL(k_dep_elem<COMP>, dim3(ge), dim3(256), 0, s, D);
+  hipLaunchKernelGGL(k_dep_node<COMP>, dim3(ge), dim3(256), 0, s, D);
   return hipGetLastError();
 }
 
 }  // namespace
+
+int64_t deposit_record_bytes(int comp) { return ((int64_t)(4 + comp) * 8 + 15) / 16 * 16; }
 
 hipError_t launch_deposit_check(hipStream_t s, const DepositArgs &D, unsigned int *flag) {
   if (D.n <= 0) return hipSuccess;
@@ -2300,21 +2391,22 @@ hipError_t launch_deposit_check(hipStream_t s, const DepositArgs &D, unsigned in
   return hipGetLastError();
 }
 
+hipError_t launch_deposit_count(hipStream_t s, const DepositArgs &D) {
+  if (D.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dep_count, dim3((unsigned)((D.n + 255) / 256)), dim3(256), 0, s, D);
+  return hipGetLastError();
+}
+
 hipError_t launch_deposit(hipStream_t s, const DepositArgs &D) {
-  const int64_t len = D.nnode * D.comp;
-  const int64_t zb = std::min<int64_t>((len + 255) / 256, 8192);
-  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)zb), dim3(256), 0, s, D.out, len);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || D.n <= 0) return e;
   switch (D.comp) {
-    case 1: return deposit_comp<1>(s, D);
-    case 2: return deposit_comp<2>(s, D);
-    case 3: return deposit_comp<3>(s, D);
-    case 4: return deposit_comp<4>(s, D);
-    case 5: return deposit_comp<5>(s, D);
-    case 6: return deposit_comp<6>(s, D);
-    case 7: return deposit_comp<7>(s, D);
-    case 8: return deposit_comp<8>(s, D);
+    case 1: return deposit_sorted<1>(s, D);
+    case 2: return deposit_sorted<2>(s, D);
+    case 3: return deposit_sorted<3>(s, D);
+    case 4: return deposit_sorted<4>(s, D);
+    case 5: return deposit_sorted<5>(s, D);
+    case 6: return deposit_sorted<6>(s, D);
+    case 7: return deposit_sorted<7>(s, D);
+    case 8: return deposit_sorted<8>(s, D);
     default: return hipErrorInvalidValue;
   }
 }

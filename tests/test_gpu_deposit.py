@@ -1,10 +1,12 @@
 """pcol_deposit on the GPU against the oracle's orc_deposit, node by node.
 
 The weights are computed by the same binary64 formulas on both sides, so a node
-that receives a single contribution is compared bitwise; the other node sums are
-formed with FP64 atomic adds in an order that varies, and each must lie within
-2 (k - 1) 2^-53 sum|w a| of the oracle's (both sides are within (k - 1) 2^-53
-sum|w a| of the exact sum, k the node's number of contributions)."""
+that receives a single contribution is compared bitwise.  The other node sums are
+associated differently (the GPU sums per element, then over a node's eight
+elements; the oracle over all spheres in index order), and each must lie within
+2 (k - 1) 2^-53 sum|w a| of the oracle's: both are within (k - 1) 2^-53 sum|w a|
+of the exact sum, k the node's number of contributions.  Repeated calls agree
+bitwise."""
 import numpy as np
 import pytest
 import torch
@@ -143,6 +145,23 @@ def test_deposit_errors_leave_output_unchanged():
     with pytest.raises(pc.PcolError):
         pc.pcol_deposit(ctx, _dev(x), _dev(y), _dev(z), _dev(a9), nc, L)
     assert torch.all(out == 7.0).item()
+
+
+def test_deposit_repeats_bitwise_and_dense_elements():
+    L = (1.0, 1.0, 1.0)
+    x, y, z, a = workloads.deposit_case(200_000, seed=21, L=L, comp=4)
+    ctx = pc.Context(1)
+    _announce("deposit repeat")
+    one = gpu_deposit(x, y, z, a, (24, 24, 24), L, ctx)
+    two = gpu_deposit(x, y, z, a, (24, 24, 24), L, ctx)
+    assert np.array_equal(one.view(np.uint64), two.view(np.uint64))
+    check(x, y, z, a, (24, 24, 24), L, one)
+    # 2 x 3 x 2 elements of about 17,000 spheres each: sums in scatter order
+    _announce("deposit dense elements")
+    check(x, y, z, a, (2, 3, 2), L, gpu_deposit(x, y, z, a, (2, 3, 2), L, ctx))
+    # a smaller call after the larger ones reuses the grown scratch
+    check(x[:999], y[:999], z[:999], a[:, :999].copy(), (5, 4, 3), L,
+          gpu_deposit(x[:999], y[:999], z[:999], a[:, :999].copy(), (5, 4, 3), L, ctx))
 
 
 def test_deposit_full_size_16M():
