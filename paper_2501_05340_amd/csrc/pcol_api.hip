@@ -1005,23 +1005,12 @@ pcol_status pcol_deposit(pcol_ctx *ctx, const double *x, const double *y, const 
     if (D.nnode > INT32_MAX) return fail(ctx, PCOL_E_INVALID, "more than 2^31 - 1 elements");
   }
   hipStream_t s = ctx->stream;
-  if (n > 0) {
-    if (!ctx->dep_flag) {
-      PCOL_HIP(dalloc(&ctx->dep_flag, 1));
-      PCOL_HIP(hipHostMalloc((void **)&ctx->dep_flag_h, sizeof(unsigned int)));
-    }
-    PCOL_HIP(hipMemsetAsync(ctx->dep_flag, 0, sizeof(unsigned int), s));
-    PCOL_HIP(launch_deposit_check(s, D, ctx->dep_flag));
-    PCOL_HIP(hipMemcpyAsync(ctx->dep_flag_h, ctx->dep_flag, sizeof(unsigned int),
-                            hipMemcpyDeviceToHost, s));
-    PCOL_HIP(hipStreamSynchronize(s));
-    if (*ctx->dep_flag_h) return fail(ctx, PCOL_E_INVALID, "position outside [0, L) or not finite");
-  }
   const int64_t ne = D.nnode;
   int64_t cap_start = ctx->dep_cap_el, cap_bsum = ctx->dep_cap_el, cap_ro = ctx->dep_ro ? 1 : 0;
-  int64_t cap_slot = ctx->dep_cap_n;
+  int64_t cap_slot = ctx->dep_cap_n, cap_flag = ctx->dep_flag ? 1 : 0;
   if (ctx->dep_cap_n < n || ctx->dep_cap_rec < n * deposit_record_bytes(comp) ||
-      ctx->dep_cap_el < ne + 1 || ctx->dep_cap_E < 8 * comp * ne || !ctx->dep_ro)
+      ctx->dep_cap_el < ne + 1 || ctx->dep_cap_E < 8 * comp * ne || !ctx->dep_ro ||
+      !ctx->dep_flag)
     PCOL_HIP(hipStreamSynchronize(s));  // the frees below wait for nothing queued
   hipError_t e = grow(&ctx->dep_eid, ctx->dep_cap_n, n);
   if (e == hipSuccess) e = grow(&ctx->dep_slot, cap_slot, n);
@@ -1031,6 +1020,9 @@ pcol_status pcol_deposit(pcol_ctx *ctx, const double *x, const double *y, const 
   if (e == hipSuccess) e = grow(&ctx->dep_bsum, cap_bsum, ne + 1);
   if (e == hipSuccess) e = grow(&ctx->dep_E, ctx->dep_cap_E, 8 * comp * ne);
   if (e == hipSuccess) e = grow(&ctx->dep_ro, cap_ro, 1);
+  if (e == hipSuccess) e = grow(&ctx->dep_flag, cap_flag, 1);
+  if (e == hipSuccess && !ctx->dep_flag_h)
+    e = hipHostMalloc((void **)&ctx->dep_flag_h, sizeof(unsigned int));
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return fail(ctx, e == hipErrorOutOfMemory ? PCOL_E_NOMEM : PCOL_E_HIP,
@@ -1043,7 +1035,14 @@ pcol_status pcol_deposit(pcol_ctx *ctx, const double *x, const double *y, const 
   D.rec = ctx->dep_rec;
   D.E = ctx->dep_E;
   PCOL_HIP(hipMemsetAsync(ctx->dep_cnt, 0, (size_t)ne * sizeof(int), s));
-  PCOL_HIP(launch_deposit_count(s, D));
+  if (n > 0) {  // the count checks the positions; nothing of the caller's is written yet
+    PCOL_HIP(hipMemsetAsync(ctx->dep_flag, 0, sizeof(unsigned int), s));
+    PCOL_HIP(launch_deposit_count(s, D, ctx->dep_flag));
+    PCOL_HIP(hipMemcpyAsync(ctx->dep_flag_h, ctx->dep_flag, sizeof(unsigned int),
+                            hipMemcpyDeviceToHost, s));
+    PCOL_HIP(hipStreamSynchronize(s));
+    if (*ctx->dep_flag_h) return fail(ctx, PCOL_E_INVALID, "position outside [0, L) or not finite");
+  }
   PCOL_HIP(launch_scan(s, ctx->dep_cnt, (int)ne, ctx->dep_start, ctx->dep_bsum, ctx->dep_ro));
   PCOL_HIP(launch_deposit(s, D));
   return PCOL_OK;

@@ -418,9 +418,9 @@ struct DepositArgs {
   double *E;
 };
 int64_t deposit_record_bytes(int comp);
-hipError_t launch_deposit_check(hipStream_t s, const DepositArgs &D, unsigned int *flag);
-// element and slot of every sphere (cnt must be zero)
-hipError_t launch_deposit_count(hipStream_t s, const DepositArgs &D);
+// element and slot of every sphere (cnt must be zero); positions outside
+// [0, L) or not finite set bit 0 of *flag and are skipped
+hipError_t launch_deposit_count(hipStream_t s, const DepositArgs &D, unsigned int *flag);
 // after the scan of cnt into start: scatter, element corner sums, node sums
 hipError_t launch_deposit(hipStream_t s, const DepositArgs &D);
 hipError_t launch_resolve_public(hipStream_t s, int n, const Rec *rec, const int *rank,

@@ -2245,18 +2245,6 @@ struct alignas(16) DepRec {
   long long o;  // caller index
 };
 
-// Positions inside [0, L) and finite on every axis; one flag word for all.
-__global__ __launch_bounds__(256) void k_deposit_check(DepositArgs D, unsigned int *flag) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  bool bad = false;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < D.n; i += stride) {
-    const double p0 = D.x[i], p1 = D.y[i], p2 = D.z[i];
-    bad |= !(p0 >= 0.0 && p0 < D.L[0]) || !(p1 >= 0.0 && p1 < D.L[1]) ||
-           !(p2 >= 0.0 && p2 < D.L[2]);
-  }
-  if (__ballot(bad) != 0ull && __lane_id() == 0) atomicOr(flag, 1u);
-}
-
 // Host cell and local coordinate of p on one axis: s = p / h, c = floor(s)
 // (at most nc - 1), f = s - c in [0, 1].
 __device__ __forceinline__ int dep_cell(double p, double h, int nc, double &f) {
@@ -2267,14 +2255,22 @@ __device__ __forceinline__ int dep_cell(double p, double h, int nc, double &f) {
   return c;
 }
 
-// element of every sphere and its slot among the element's spheres
-__global__ __launch_bounds__(256) void k_dep_count(DepositArgs D) {
+// Element of every sphere and its slot among the element's spheres.  A
+// position outside [0, L) or not finite raises bit 0 of *flag and is not
+// counted (the host reads the flag before anything else runs).
+__global__ __launch_bounds__(256) void k_dep_count(DepositArgs D, unsigned int *flag) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= D.n) return;
+  const double p0 = D.x[i], p1 = D.y[i], p2 = D.z[i];
+  const bool bad = !(p0 >= 0.0 && p0 < D.L[0]) || !(p1 >= 0.0 && p1 < D.L[1]) ||
+                   !(p2 >= 0.0 && p2 < D.L[2]);
+  if (__ballot(bad) != 0ull && __lane_id() == __ffsll((long long)__ballot(bad)) - 1)
+    atomicOr(flag, 1u);
+  if (bad) return;
   double f;
-  const int c0 = dep_cell(D.x[i], D.h[0], D.nc[0], f);
-  const int c1 = dep_cell(D.y[i], D.h[1], D.nc[1], f);
-  const int c2 = dep_cell(D.z[i], D.h[2], D.nc[2], f);
+  const int c0 = dep_cell(p0, D.h[0], D.nc[0], f);
+  const int c1 = dep_cell(p1, D.h[1], D.nc[1], f);
+  const int c2 = dep_cell(p2, D.h[2], D.nc[2], f);
   const int e = (c2 * D.nc[1] + c1) * D.nc[0] + c0;
   D.eid[i] = e;
   D.slot[i] = atomicAdd(&D.cnt[e], 1);
@@ -2384,16 +2380,9 @@ hipError_t deposit_sorted(hipStream_t s, const DepositArgs &D) {
 
 int64_t deposit_record_bytes(int comp) { return ((int64_t)(4 + comp) * 8 + 15) / 16 * 16; }
 
-hipError_t launch_deposit_check(hipStream_t s, const DepositArgs &D, unsigned int *flag) {
+hipError_t launch_deposit_count(hipStream_t s, const DepositArgs &D, unsigned int *flag) {
   if (D.n <= 0) return hipSuccess;
-  const int64_t blocks = std::min<int64_t>((D.n + 255) / 256, 8192);
-  hipLaunchKernelGGL(k_deposit_check, dim3((unsigned)blocks), dim3(256), 0, s, D, flag);
-  return hipGetLastError();
-}
-
-hipError_t launch_deposit_count(hipStream_t s, const DepositArgs &D) {
-  if (D.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_dep_count, dim3((unsigned)((D.n + 255) / 256)), dim3(256), 0, s, D);
+  hipLaunchKernelGGL(k_dep_count, dim3((unsigned)((D.n + 255) / 256)), dim3(256), 0, s, D, flag);
   return hipGetLastError();
 }
 
