@@ -164,6 +164,56 @@ def test_deposit_repeats_bitwise_and_dense_elements():
           gpu_deposit(x[:999], y[:999], z[:999], a[:, :999].copy(), (5, 4, 3), L, ctx))
 
 
+def _ordered_reference(x, y, z, a, nc, L):
+    """The node sums in the association the header states: per element, w a summed
+    over its spheres in caller-index order; per node, the eight corner sums in the
+    order b = 0..7 (plain Python floats: binary64, no contraction)."""
+    comp, n = a.shape
+    h = [L[d] / nc[d] for d in range(3)]
+    E = {}
+    for i in range(n):
+        c, f = [], []
+        for d, p in enumerate((x[i], y[i], z[i])):
+            s = float(p) / h[d]
+            cd = min(int(np.floor(s)), nc[d] - 1)
+            c.append(cd)
+            f.append(s - cd)
+        e = (c[2] * nc[1] + c[1]) * nc[0] + c[0]
+        acc = E.setdefault(e, [[0.0] * comp for _ in range(8)])
+        for b in range(8):
+            w = (((f[0] if b & 1 else 1.0 - f[0]) * (f[1] if b & 2 else 1.0 - f[1]))
+                 * (f[2] if b & 4 else 1.0 - f[2]))
+            for q in range(comp):
+                acc[b][q] += w * float(a[q, i])
+    out = np.zeros((comp, nc[2], nc[1], nc[0]))
+    zero = [[0.0] * comp for _ in range(8)]
+    for k in range(nc[2]):
+        for j in range(nc[1]):
+            for i in range(nc[0]):
+                sq = [0.0] * comp
+                for b in range(8):
+                    ei = (i - (b & 1)) % nc[0]
+                    ej = (j - ((b >> 1) & 1)) % nc[1]
+                    ek = (k - ((b >> 2) & 1)) % nc[2]
+                    src = E.get((ek * nc[1] + ej) * nc[0] + ei, zero)
+                    for q in range(comp):
+                        sq[q] += src[b][q]
+                out[:, k, j, i] = sq
+    return out
+
+
+@pytest.mark.parametrize("n,nc", [(30000, (16, 16, 16)), (30000, (12, 10, 9))])
+def test_deposit_summation_order_bitwise(n, nc):
+    # 7 to 28 spheres per element: both the register and the memory selection
+    L = (1.0, 0.8, 1.3)
+    x, y, z, a = workloads.deposit_case(n, seed=n + nc[1], L=L, comp=2)
+    _announce(f"deposit order n={n} nc={nc}")
+    got = gpu_deposit(x, y, z, a, nc, L)
+    ref = _ordered_reference(x, y, z, a, nc, L)
+    assert np.array_equal(got.view(np.uint64), ref.view(np.uint64))
+    check(x, y, z, a, nc, L, got)
+
+
 def test_deposit_full_size_16M():
     """The bench workload's shape: 16M spheres uniform in the box on 160^3 elements
     (3.9 spheres per element), four source components, every node against the oracle."""
