@@ -284,6 +284,11 @@ def deposition_leg(args, pc, torch, box, p0):
         "nc": list(nc), "comp": comp, "spheres_per_element": box.n / nnode,
         "corner_terms_per_s": box.n * 8 * comp / wall,
         "algorithmic_bytes": alg, "algorithmic_GBps": alg / wall / 1e9,
+        # the whole call (sort and sums) against the HBM peak, on its algorithmic bytes
+        "roofline": {"bound": "hbm", "achieved": alg / wall / 1e9, "peak": 8000.0,
+                     "unit": "GB/s", "frac": alg / wall / 8e12, "traffic": None,
+                     "kernel": "pcol_deposit (k_dep_count, scan, k_dep_scatter, k_dep_elem, "
+                               "k_dep_node)"},
         "element_sorted_ms_per_call": wall_sorted * 1e3,
         "element_sorted_max_abs_diff": sorted_diff,
         "conservation_rel_error": float(
