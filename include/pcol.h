@@ -13,12 +13,15 @@
  *   - Sec. "Inter-Particle Collisions": momentum jump relations with the normal
  *     impulse J_n = -m_r (1 + e) (v_r . n_p), v_r = v_1 - v_2, n_p the unit
  *     vector from sphere 1 to sphere 2, m_r = m_1 m_2 / (m_1 + m_2); friction
- *     coefficient 0, so no tangential impulse and no spin.
+ *     coefficient 0 (no tangential impulse, no spin) except in pcol_step_spin,
+ *     which adds the tangential impulse and the spin update.
  *   - eq. (update_vel1/update_vel2/update_rho): new velocities v + J/m, and the
  *     sphere is moved to the contact point and flies the rest of the step with
  *     its new velocity.
  *   - Sec. "Collision Operator": one collision per sphere per step; spheres
  *     that collided leave the set of eligible partners.
+ *   - Sec. "Dispersed Phase" and Sec. "Deposition" (pcol_deposit only): the
+ *     linear projection of per-particle sources onto element corner nodes.
  *
  * THE ORDERING RULE (the paper asks only for a deterministic order; this is
  * the order-independent rule every entry point computes):
