@@ -140,3 +140,46 @@ def test_16M_sampled_keys_and_step_properties(big):
         for f in FIELDS:
             assert np.array_equal(out32[f].view(np.uint64), out[f].view(np.uint64))
         assert st32["n_recheck"] > 0
+
+
+@pytest.mark.timeout(900)
+def test_16M_friction_and_spin_sampled(big):
+    """pcol_step_spin at 16M (mu 0.3, spins N(0, 1) / r, as bench.py times it): the
+    pair set and contact times equal the plain step's; spheres without a collision
+    keep their spins; 300 sampled pairs equal the oracle's friction resolve bitwise;
+    linear momentum is conserved."""
+    box, p0 = big
+    n, mu = box.n, 0.3
+    rng = np.random.default_rng(17)
+    w0 = np.stack([rng.normal(size=n) / box.r for _ in range(3)])
+    print("[gpu-test] 16M step with friction and spin", flush=True)
+    p = p0.clone()
+    w = [torch.as_tensor(w0[k]).cuda() for k in range(3)]
+    ctx = pc.Context(n)
+    partner = torch.empty(n, dtype=torch.int32, device="cuda")
+    tcoll = torch.empty(n, dtype=torch.float64, device="cuda")
+    st = pc.pcol_step_spin(ctx, p, w, box.L, box.dt, box.e, mu, partner, tcoll)
+    torch.cuda.synchronize()
+    ctx.close()
+    out = {f: getattr(p, f).cpu().numpy() for f in FIELDS}
+    ws = np.stack([t.cpu().numpy() for t in w])
+    partner, tcoll = partner.cpu().numpy().astype(np.int64), tcoll.cpu().numpy()
+    del p, w
+    _, partner0, tcoll0, st0 = _step(box, p0, 0)
+    assert np.array_equal(partner, partner0) and st["n_pairs"] == st0["n_pairs"]
+    assert np.array_equal(tcoll, tcoll0, equal_nan=True)
+    hit = partner >= 0
+    assert np.array_equal(ws[:, ~hit], w0[:, ~hit])
+    assert np.count_nonzero(ws[:, hit] != w0[:, hit]) > st["n_pairs"]
+    pairs = np.where(hit & (np.arange(n) < partner))[0]
+    for i in rng.choice(pairs, 300, replace=False):
+        j = partner[i]
+        xs, vs, wsr = oracle.resolve_pair_spin(box, w0, mu, i, j, tcoll[i])
+        for got, ref, names in ((out, xs, ("x", "y", "z")), (out, vs, ("vx", "vy", "vz"))):
+            g = np.array([[got[f][i] for f in names], [got[f][j] for f in names]])
+            assert np.array_equal(g, ref)
+        assert np.array_equal(np.array([ws[:, i], ws[:, j]]), wsr)
+    m = box.m
+    for f in ("vx", "vy", "vz"):
+        p_in = math.fsum(m * getattr(box, f))
+        assert abs(math.fsum(m * out[f]) - p_in) <= 1e-10 * math.fsum(m * np.abs(getattr(box, f)))
