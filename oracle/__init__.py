@@ -88,6 +88,10 @@ def _load():
             _D, ctypes.c_double, ctypes.c_double, ctypes.c_double] + [_D] * 6 + [
             _I64, _D, ctypes.POINTER(_Stats)]
         lib.orc_step_sequential.restype = ctypes.c_int
+        lib.orc_step_walls.argtypes = [ctypes.c_int64] + [_D] * 8 + [
+            _D, _I32, ctypes.c_double, ctypes.c_double] + [_D] * 6 + [
+            _I64, _D, ctypes.POINTER(_Stats)]
+        lib.orc_step_walls.restype = ctypes.c_int
         lib.orc_deposit.argtypes = [ctypes.c_int64, _D, _D, _D, _D, ctypes.c_int,
                                     ctypes.POINTER(ctypes.c_int), _D, _D]
         lib.orc_deposit.restype = ctypes.c_int
@@ -300,6 +304,27 @@ def step_sequential(box, *, e: float | None = None, cell_mult: float = 1.0) -> S
                                      float(box.e if e is None else e), float(cell_mult),
                                      *[_d(o) for o in outs], partner.ctypes.data_as(_I64),
                                      _d(tcoll), ctypes.byref(st))
+    if rc:
+        raise OracleError(rc)
+    sweep = np.where(partner >= 0, 0, -1).astype(np.int32)
+    return StepResult(*outs, partner, tcoll, sweep, st.n_pairs, st.n_sweeps, st.pair_tests,
+                      st.reach)
+
+
+def step_walls(box, walls, *, e: float | None = None) -> StepResult:
+    """One step of ``box`` with reflective walls on the axes where walls[k] is true (the
+    others periodic); inputs unchanged."""
+    n = box.n
+    arrs = [_c64(a) for a in (box.x, box.y, box.z, box.vx, box.vy, box.vz, box.r, box.m)]
+    outs = [np.empty(n) for _ in range(6)]
+    partner = np.empty(n, dtype=np.int64)
+    tcoll = np.empty(n)
+    st = _Stats()
+    wl = np.ascontiguousarray([1 if w else 0 for w in walls], dtype=np.int32)
+    rc = _load().orc_step_walls(n, *[_d(a) for a in arrs], _d(_c64(box.L)),
+                                wl.ctypes.data_as(_I32), float(box.dt),
+                                float(box.e if e is None else e), *[_d(o) for o in outs],
+                                partner.ctypes.data_as(_I64), _d(tcoll), ctypes.byref(st))
     if rc:
         raise OracleError(rc)
     sweep = np.where(partner >= 0, 0, -1).astype(np.int32)

@@ -49,6 +49,12 @@
  *              first valid collision it finds; both particles then leave the
  *              eligible set.  Sequential by definition; it serves to measure
  *              how far the order-free rule above departs from it.
+ *  walls       orc_step_walls: the same step with reflective walls on chosen
+ *              axes (Sec. "Intersection of Particles with Solid Walls", Sec.
+ *              "Particle Collisions"): no minimum image across a wall, a
+ *              collision counts only before either sphere's next boundary
+ *              intersection, and a centre that reaches a wall plane within the
+ *              step is reflected (elastic wall).
  *  friction    orc_step_spin: the same step with angular velocities and
  *              Coulomb friction (coefficient mu) in the resolve: the impulse
  *              gains the tangential part J_t t_p of Sec. "Inter-Particle
@@ -946,6 +952,232 @@ int orc_step_sequential(int64_t n, const double *x, const double *y, const doubl
   }
   free(order);
   free(hit);
+  orc_grid_free(&G);
+  return ORC_OK;
+}
+
+/* ---------------------------------------------------------------- walls */
+
+/* separation along one axis: the minimum image on a periodic axis, the plain
+ * difference between two walls */
+static double orc_sep_axis(double d, double len, int wall) {
+  return wall ? d : orc_wrap_sep(d, len);
+}
+
+/* Time of flight of a centre at x with velocity v until it reaches a wall plane
+ * (x_k = 0 or x_k = L_k on a wall axis), +inf if it moves along no wall axis:
+ * Sec. "Particle-Particle Collisions" (each particle's time of flight to its
+ * next boundary intersection) with the particle tracked by its centre. */
+static double orc_time_to_wall(const double x[3], const double v[3], const double L[3],
+                               const int wall[3]) {
+  double tw = INFINITY;
+  for (int k = 0; k < 3; ++k) {
+    if (!wall[k]) continue;
+    double t;
+    if (v[k] > 0.0)
+      t = (L[k] - x[k]) / v[k];
+    else if (v[k] < 0.0)
+      t = -x[k] / v[k];
+    else
+      continue;
+    if (t < tw) tw = t;
+  }
+  return tw;
+}
+
+/* Contact time of spheres i and j as orc_pair_time, with the separation of
+ * orc_sep_axis, and valid only if it is no later than either sphere's time of
+ * flight to a wall (Sec. "Particle Collisions": the collision must occur
+ * before an intersection with a domain boundary). */
+static int orc_pair_time_walls(const double xi[3], const double vi[3], double ri,
+                               const double xj[3], const double vj[3], double rj,
+                               const double L[3], const int wall[3], double dt, double *t_out) {
+  double d[3], u[3];
+  for (int k = 0; k < 3; ++k) {
+    d[k] = orc_sep_axis(xj[k] - xi[k], L[k], wall[k]);
+    u[k] = vj[k] - vi[k];
+  }
+  const double s = ri + rj;
+  const double a = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
+  const double b = (d[0] * u[0] + d[1] * u[1]) + d[2] * u[2];
+  const double c = ((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]) - s * s;
+  if (!(a > 0.0) || !(b < 0.0) || !(c > 0.0)) return 0;
+  const double D = b * b - a * c;
+  if (!(D >= 0.0)) return 0;
+  const double t = c / (-b + sqrt(D));
+  if (!(t <= dt)) return 0;
+  if (!(t <= orc_time_to_wall(xi, vi, L, wall)) || !(t <= orc_time_to_wall(xj, vj, L, wall)))
+    return 0;
+  *t_out = t;
+  return 1;
+}
+
+/* End of a flight along one axis: p is the unconstrained coordinate.  On a
+ * periodic axis it is wrapped (orc_wrap_pos).  On a wall axis a centre beyond a
+ * wall plane is reflected at it, Sec. "Intersection of Particles with Solid
+ * Walls" with a perfectly reflective wall (momentum change zero: the normal
+ * velocity component changes sign, the spin is unchanged); at most one plane is
+ * crossed because no sphere moves more than L/4 in a step.  A coordinate that
+ * lands on L itself becomes the largest double below L. */
+static double orc_fly_axis(double p, double len, int wall, double *v) {
+  if (!wall) return orc_wrap_pos(p, len);
+  if (p >= len) {
+    p = len - (p - len);
+    *v = -*v;
+  } else if (p < 0.0) {
+    p = -p;
+    *v = -*v;
+  }
+  if (p >= len) p = nextafter(len, 0.0);
+  return p;
+}
+
+/* Resolve of the pair (i, j) at time t as orc_resolve_pair, with the
+ * separation of orc_sep_axis and the rest of the step flown with orc_fly_axis. */
+static void orc_resolve_pair_walls(int64_t i, int64_t j, double t, const double *x,
+                                   const double *y, const double *z, const double *vx,
+                                   const double *vy, const double *vz, const double *r,
+                                   const double *m, const double L[3], const int wall[3],
+                                   double dt, double e, double *xo, double *yo, double *zo,
+                                   double *vxo, double *vyo, double *vzo) {
+  const double xi[3] = {x[i], y[i], z[i]}, xj[3] = {x[j], y[j], z[j]};
+  const double vi[3] = {vx[i], vy[i], vz[i]}, vj[3] = {vx[j], vy[j], vz[j]};
+  double d[3], u[3], nrm[3];
+  for (int k = 0; k < 3; ++k) {
+    d[k] = orc_sep_axis(xj[k] - xi[k], L[k], wall[k]);
+    u[k] = vj[k] - vi[k];
+  }
+  const double s = r[i] + r[j];
+  for (int k = 0; k < 3; ++k) nrm[k] = (d[k] + t * u[k]) / s;
+  const double g = (u[0] * nrm[0] + u[1] * nrm[1]) + u[2] * nrm[2];
+  const double mr = (m[i] * m[j]) / (m[i] + m[j]);
+  const double J = (mr * (1.0 + e)) * g;
+  const double ai = J / m[i], aj = J / m[j];
+  const double rest = dt - t;
+  double *xout[3] = {xo, yo, zo}, *vout[3] = {vxo, vyo, vzo};
+  for (int k = 0; k < 3; ++k) {
+    double vin = vi[k] + ai * nrm[k];
+    double vjn = vj[k] - aj * nrm[k];
+    xout[k][i] = orc_fly_axis((xi[k] + t * vi[k]) + rest * vin, L[k], wall[k], &vin);
+    xout[k][j] = orc_fly_axis((xj[k] + t * vj[k]) + rest * vjn, L[k], wall[k], &vjn);
+    vout[k][i] = vin;
+    vout[k][j] = vjn;
+  }
+}
+
+/*
+ * One collision step with reflective walls on the axes where wall[k] != 0 (the
+ * other axes periodic): the rule of orc_step with the pair time of
+ * orc_pair_time_walls, the resolve of orc_resolve_pair_walls and the free flight
+ * of orc_fly_axis.  Candidates come from the plain grid with periodic
+ * neighbours: a pair that is neighbours only through a wall is at least a cell
+ * side (>= reach) apart without the minimum image and cannot touch within the
+ * step.  Outputs and errors as orc_step.
+ */
+int orc_step_walls(int64_t n, const double *x, const double *y, const double *z,
+                   const double *vx, const double *vy, const double *vz, const double *r,
+                   const double *m, const double L[3], const int wall[3], double dt, double e,
+                   double *xo, double *yo, double *zo, double *vxo, double *vyo, double *vzo,
+                   int64_t *partner, double *tcoll, orc_stats *st) {
+  int rc = orc_check_inputs(n, x, y, z, vx, vy, vz, r, m, L, dt);
+  if (rc) return rc;
+  if (!(e >= 0.0 && e <= 1.0)) return ORC_E_INVALID;
+  const double reach = orc_reach(n, vx, vy, vz, r, dt);
+  for (int a = 0; a < 3; ++a)
+    if (!(L[a] > 2.0 * reach)) return ORC_E_BOX;
+  orc_grid G;
+  rc = orc_grid_build(&G, n, x, y, z, L, reach);
+  if (rc) return rc;
+  const size_t nn = (size_t)(n > 0 ? n : 1);
+  uint8_t *hit = (uint8_t *)calloc(nn, 1);
+  int64_t *pj = (int64_t *)malloc(nn * sizeof(int64_t));
+  double *pt = (double *)malloc(nn * sizeof(double));
+  if (!hit || !pj || !pt) {
+    free(hit);
+    free(pj);
+    free(pt);
+    orc_grid_free(&G);
+    return ORC_E_NOMEM;
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    if (partner) partner[i] = -1;
+    if (tcoll) tcoll[i] = NAN;
+  }
+  int64_t pairs = 0, tests = 0, sweeps = 0;
+  for (;;) {
+    int64_t tk = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : tk)
+    for (int64_t i = 0; i < n; ++i) {
+      pj[i] = -1;
+      pt[i] = INFINITY;
+      if (hit[i]) continue;
+      const double xi[3] = {x[i], y[i], z[i]}, vi[3] = {vx[i], vy[i], vz[i]};
+      const int c0 = orc_cell_of(x[i], G.h[0], G.nc[0]);
+      const int c1 = orc_cell_of(y[i], G.h[1], G.nc[1]);
+      const int c2 = orc_cell_of(z[i], G.h[2], G.nc[2]);
+      for (int a2 = 0; a2 < G.nb[2]; ++a2)
+        for (int a1 = 0; a1 < G.nb[1]; ++a1)
+          for (int a0 = 0; a0 < G.nb[0]; ++a0) {
+            const int q0 = (c0 + G.off[0][a0] + G.nc[0]) % G.nc[0];
+            const int q1 = (c1 + G.off[1][a1] + G.nc[1]) % G.nc[1];
+            const int q2 = (c2 + G.off[2][a2] + G.nc[2]) % G.nc[2];
+            const int64_t q = ((int64_t)q2 * G.nc[1] + q1) * G.nc[0] + q0;
+            for (int64_t k = G.start[q]; k < G.start[q + 1]; ++k) {
+              const int64_t j = G.item[k];
+              if (j == i || hit[j]) continue;
+              ++tk;
+              const double xj[3] = {x[j], y[j], z[j]}, vj[3] = {vx[j], vy[j], vz[j]};
+              double t;
+              if (orc_pair_time_walls(xi, vi, r[i], xj, vj, r[j], L, wall, dt, &t) &&
+                  orc_before(t, j, pt[i], pj[i] < 0 ? INT64_MAX : pj[i])) {
+                pt[i] = t;
+                pj[i] = j;
+              }
+            }
+          }
+    }
+    tests += tk / 2;
+    ++sweeps;
+    int64_t found = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t j = pj[i];
+      if (j > i && pj[j] == i) {
+        orc_resolve_pair_walls(i, j, pt[i], x, y, z, vx, vy, vz, r, m, L, wall, dt, e, xo, yo,
+                               zo, vxo, vyo, vzo);
+        if (partner) {
+          partner[i] = j;
+          partner[j] = i;
+        }
+        if (tcoll) tcoll[i] = tcoll[j] = pt[i];
+        ++found;
+      }
+    }
+    if (found == 0) break;
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t j = pj[i];
+      if (j >= 0 && pj[j] == i) hit[i] = 1;
+    }
+    pairs += found;
+  }
+  const double *p[3] = {x, y, z}, *v[3] = {vx, vy, vz};
+  double *po[3] = {xo, yo, zo}, *vo[3] = {vxo, vyo, vzo};
+  for (int64_t i = 0; i < n; ++i) {
+    if (hit[i]) continue;
+    for (int k = 0; k < 3; ++k) {
+      double vk = v[k][i];
+      po[k][i] = orc_fly_axis(p[k][i] + dt * vk, L[k], wall[k], &vk);
+      vo[k][i] = vk;
+    }
+  }
+  if (st) {
+    st->n_pairs = pairs;
+    st->n_sweeps = sweeps;
+    st->pair_tests = tests;
+    st->reach = reach;
+  }
+  free(hit);
+  free(pj);
+  free(pt);
   orc_grid_free(&G);
   return ORC_OK;
 }
