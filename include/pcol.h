@@ -276,6 +276,27 @@ typedef struct {
   double *vx, *vy, *vz;
 } pcol_state_grad;
 
+/* One pcol_step with reflective walls at 0 and len_k on every axis k with
+ * walls[k] != 0 (host array of 3; the other axes stay periodic): Sec.
+ * "Intersection of Particles with Solid Walls" with a perfectly reflective wall,
+ * and the condition of Sec. "Particle Collisions" that a collision must occur
+ * before an intersection with a domain boundary.  The particle is tracked by its
+ * centre.  Rules 1-5 change as follows:
+ *   1. along a wall axis d_k = x_j,k - x_i,k (no minimum image), and a contact
+ *      at t is kept only if t <= T_i and t <= T_j, where T is the centre's time
+ *      of flight to a wall plane: the least over wall axes with v_k != 0 of
+ *      (len_k - x_k) / v_k for v_k > 0 and -x_k / v_k for v_k < 0 (+inf if none);
+ *   4, 5. a final coordinate p (free flight, or the rest of the step after a
+ *      collision) along a wall axis is reflected: p >= len: p = len - (p - len),
+ *      p < 0: p = -p, and the velocity component changes sign; a result equal
+ *      to len becomes the largest double below len.
+ * Positions stay in [0, len_k).  Every filter form works with walls; pcol_bin,
+ * pcol_detect and pcol_resolve do not (pcol_detect and pcol_resolve after this
+ * call return PCOL_E_STATE until pcol_bin runs again).  Otherwise as pcol_step. */
+pcol_status pcol_step_walls(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box,
+                            const int32_t walls[3], double dt, double e, int32_t *partner,
+                            double *tcoll, pcol_stats *stats);
+
 /* Adjoint of one pcol_step with its pair set held fixed (reverse mode; the
  * derivative of rule 4 and of the contact time of rule 1, which depends on the
  * start positions and velocities through |d + t u| = r_i + r_j).  For a

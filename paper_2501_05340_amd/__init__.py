@@ -120,6 +120,9 @@ def _load():
                                       ctypes.c_double, ctypes.c_double, V, V,
                                       P(pcol_batch_stats)]
     lib.pcol_step_batched.restype = ctypes.c_int
+    lib.pcol_step_walls.argtypes = [ctx_p, P(pcol_particles), P(pcol_box), P(ctypes.c_int32),
+                                    ctypes.c_double, ctypes.c_double, V, V, P(pcol_stats)]
+    lib.pcol_step_walls.restype = ctypes.c_int
     lib.pcol_deposit.argtypes = [ctx_p, V, V, V, ctypes.c_int64, V, ctypes.c_int,
                                  P(ctypes.c_int32), P(ctypes.c_double), V]
     lib.pcol_deposit.restype = ctypes.c_int
@@ -131,7 +134,7 @@ lib = _load()
 EXPORTED = ["pcol_default_opts", "pcol_create", "pcol_destroy", "pcol_last_error",
             "pcol_set_stream", "pcol_bin", "pcol_detect", "pcol_resolve", "pcol_advance",
             "pcol_step", "pcol_step_spin", "pcol_step_backward", "pcol_step_batched",
-            "pcol_deposit"]
+            "pcol_deposit", "pcol_step_walls"]
 
 
 class PcolError(RuntimeError):
@@ -453,3 +456,19 @@ def pcol_deposit(ctx: Context, x, y, z, a, nc, L, out=None):
                                _ptr(z, torch.float64, n), n, _ptr(a, torch.float64), comp, ncv,
                                Lv, _ptr(out, torch.float64)))
     return out
+
+
+def pcol_step_walls(ctx: Context, p: Particles, L, walls, dt: float, e: float, partner=None,
+                    tcoll=None, stats: bool = True):
+    """One full step in place with reflective walls on the axes where walls[k] is true
+    (the others periodic); returns a dict of pcol_stats (or None)."""
+    n = p.n
+    st = pcol_stats() if stats else None
+    ctx.sync_stream()
+    ps = p.struct()
+    wl = (ctypes.c_int32 * 3)(*[1 if w else 0 for w in walls])
+    ctx.check(lib.pcol_step_walls(ctx.handle, ctypes.byref(ps), ctypes.byref(_box(L)), wl,
+                                  float(dt), float(e), _ptr(partner, torch.int32, n),
+                                  _ptr(tcoll, torch.float64, n),
+                                  ctypes.byref(st) if st is not None else None))
+    return st.as_dict() if st is not None else None

@@ -78,6 +78,7 @@ struct pcol_ctx {
   int *wide_h = nullptr;           // pinned read-back of that range
   bool bin_pending = false;        // maxcell and the range still in flight (bin_readback)
   const Spin *spin = nullptr;      // set by pcol_step_spin for the step: its spins are validated
+  int walls = 0;                   // set by pcol_step_walls for the step: bit k = walls on axis k
   // pcol_deposit: position check flag, and the element sort's scratch with its capacities
   unsigned int *dep_flag = nullptr, *dep_flag_h = nullptr;
   int *dep_eid = nullptr, *dep_slot = nullptr, *dep_cnt = nullptr, *dep_start = nullptr,
@@ -430,9 +431,13 @@ pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box
     cell *= 1.25;
   }
   ctx->small = false;
+  G.walls = ctx->walls;
   for (int a = 0; a < 3; ++a) {
+    const bool wall = (ctx->walls >> a) & 1;
     G.L[a] = box->len[a];
-    G.halfL[a] = 0.5 * box->len[a];
+    // between walls there is no minimum image and no periodic image shift
+    G.halfL[a] = wall ? INFINITY : 0.5 * box->len[a];
+    G.sL[a] = wall ? 0.0 : box->len[a];
     G.inv_h[a] = (double)G.nc[a] / box->len[a];
     G.h[a] = box->len[a] / G.nc[a];
     ctx->h[a] = G.h[a];
@@ -498,6 +503,7 @@ static pcol_status check_binned(pcol_ctx *ctx, const pcol_particles *p, const pc
                                 double dt) {
   if (!ctx->binned || ctx->binned_n != p->n)
     return fail(ctx, PCOL_E_STATE, "pcol_bin must run first on the same particle set");
+  if (ctx->G.walls) return fail(ctx, PCOL_E_STATE, "the last binning was for a box with walls");
   if (dt != ctx->binned_dt) return fail(ctx, PCOL_E_STATE, "dt differs from pcol_bin");
   for (int a = 0; a < 3; ++a)
     if (box->len[a] != ctx->G.L[a]) return fail(ctx, PCOL_E_STATE, "box differs from pcol_bin");
@@ -659,7 +665,7 @@ static pcol_status detect_all(pcol_ctx *ctx, double dt) {
     ctx->detect_timed = true;
     PCOL_HIP(launch_slot_min(s, n, 1, ctx->cnt, ctx->slot_t, ctx->slot_j, ctx->K, ctx->status,
                              ctx->rec, ctx->key_j, ctx->key_t, ctx->ovf, ctx->ctr_d,
-                             nullptr));
+                             nullptr, nullptr, 0, &ctx->G));
     PCOL_HIP(launch_gather_exact(s, ctx->ovf, 0, &ctx->ctr_d->n_overflow, -1, ctx->rec, ctx->start,
                                  ctx->G, dt, ctx->status, ctx->key_j, ctx->key_t, nullptr));
   } else {
@@ -823,7 +829,7 @@ static pcol_status step_impl(pcol_ctx *ctx, pcol_particles *p, const pcol_box *b
       if (!ctx->small) {
         PCOL_HIP(launch_slot_min(s, n, 0, ctx->cnt, ctx->slot_t, ctx->slot_j, ctx->K,
                                  ctx->status, ctx->rec, ctx->key_j, ctx->key_t, ctx->ovf,
-                                 ctx->ctr_d, nullptr, lin, nlist));
+                                 ctx->ctr_d, nullptr, lin, nlist, &ctx->G));
         PCOL_HIP(launch_gather_exact(s, ctx->ovf, 0, &ctx->ctr_d->n_overflow, -1, ctx->rec,
                                      ctx->start, ctx->G, dt, ctx->status, ctx->key_j,
                                      ctx->key_t, nullptr));
@@ -860,7 +866,7 @@ static pcol_status step_impl(pcol_ctx *ctx, pcol_particles *p, const pcol_box *b
         if (!ctx->small) {
           PCOL_HIP(launch_slot_min(s, n, 0, ctx->cnt, ctx->slot_t, ctx->slot_j, ctx->K,
                                    ctx->status, ctx->rec, ctx->key_j, ctx->key_t, ctx->ovf,
-                                   ctx->ctr_d, ctx->sflags, lin, nlist));
+                                   ctx->ctr_d, ctx->sflags, lin, nlist, &ctx->G));
           PCOL_HIP(launch_gather_exact(s, ctx->ovf, 0, &ctx->ctr_d->n_overflow, -1, ctx->rec,
                                        ctx->start, ctx->G, dt, ctx->status, ctx->key_j,
                                        ctx->key_t, &Bf));
@@ -955,6 +961,20 @@ pcol_status pcol_step_spin(pcol_ctx *ctx, pcol_particles *p, double *wx, double 
   return st;
 }
 
+pcol_status pcol_step_walls(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box,
+                            const int32_t walls[3], double dt, double e, int32_t *partner,
+                            double *tcoll, pcol_stats *stats) {
+  if (!ctx) return PCOL_E_INVALID;
+  if (!walls) return fail(ctx, PCOL_E_INVALID, "null walls");
+  int mask = 0;
+  for (int a = 0; a < 3; ++a)
+    if (walls[a]) mask |= 1 << a;
+  ctx->walls = mask;  // the binning builds its grid with these walls
+  const pcol_status st = step_impl(ctx, p, box, dt, e, partner, tcoll, stats, nullptr);
+  ctx->walls = 0;
+  return st;
+}
+
 pcol_status pcol_step_backward(pcol_ctx *ctx, const pcol_particles *start, const pcol_box *box,
                                double dt, double e, const int32_t *partner, const double *tcoll,
                                const pcol_state_grad *g_out, pcol_state_grad *g_in, double *ge) {
@@ -970,6 +990,7 @@ pcol_status pcol_step_backward(pcol_ctx *ctx, const pcol_particles *start, const
   for (int a = 0; a < 3; ++a) {
     G.L[a] = box->len[a];
     G.halfL[a] = 0.5 * box->len[a];
+    G.sL[a] = box->len[a];
   }
   StateGrad go{g_out->x, g_out->y, g_out->z, g_out->vx, g_out->vy, g_out->vz};
   StateGrad gi{g_in->x, g_in->y, g_in->z, g_in->vx, g_in->vy, g_in->vz};
@@ -1089,6 +1110,7 @@ bool box_grid(const double len[3], int64_t nb, double reach, double mult, Grid &
     G.nc[a] = (int)q;
     G.L[a] = len[a];
     G.halfL[a] = 0.5 * len[a];
+    G.sL[a] = len[a];
     G.inv_h[a] = q / len[a];
     G.h[a] = len[a] / q;
   }

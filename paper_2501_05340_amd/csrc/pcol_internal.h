@@ -50,10 +50,11 @@ struct Grid {
   double halfL[3];  // 0.5 * L, the minimum-image threshold
   double h[3];      // L / nc, cell side
   int layer2;       // first cell of the second layer (0: none)
-  int pad_;
+  int walls;        // bit k: reflective walls at 0 and L on axis k (else periodic)
   double rho_max;
   double inv_row;    // 1 / nc0 and 1 / (nc0 nc1): cell coordinates without division
   double inv_layer;
+  double sL[3];      // periodic image shift: L on a periodic axis, 0 on a wall axis
 };
 
 // Coordinates of cell number c of one layer (c < 2^26, nc0 nc1 <= 2^20)
@@ -157,13 +158,74 @@ __device__ __forceinline__ double wrap_pos(double p, double L) {
   return p;
 }
 
-// Exact contact time of two records with the canonical minimum image.
+// Time of flight of a centre at x with velocity v until it reaches a wall
+// plane (x_k = 0 or L_k on a wall axis), +inf if it moves along no wall axis
+// (Sec. "Particle Collisions": a collision counts only before an intersection
+// with a domain boundary).
+__device__ __forceinline__ double time_to_wall(double x0, double x1, double x2, double v0,
+                                               double v1, double v2, const Grid &G) {
+  const double x[3] = {x0, x1, x2}, v[3] = {v0, v1, v2};
+  double tw = __longlong_as_double(0x7ff0000000000000LL);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (!((G.walls >> k) & 1)) continue;
+    double t;
+    if (v[k] > 0.0)
+      t = (G.L[k] - x[k]) / v[k];
+    else if (v[k] < 0.0)
+      t = -x[k] / v[k];
+    else
+      continue;
+    tw = t < tw ? t : tw;
+  }
+  return tw;
+}
+
+// Contact at time t of spheres (xa, va) and (xb, vb) allowed by the walls:
+// no later than either centre's time of flight to a wall.
+__device__ __forceinline__ bool before_walls(double xa0, double xa1, double xa2, double va0,
+                                             double va1, double va2, double xb0, double xb1,
+                                             double xb2, double vb0, double vb1, double vb2,
+                                             const Grid &G, double t) {
+  return G.walls == 0 || (t <= time_to_wall(xa0, xa1, xa2, va0, va1, va2, G) &&
+                          t <= time_to_wall(xb0, xb1, xb2, vb0, vb1, vb2, G));
+}
+
+// Exact contact time of two records with the canonical minimum image (none
+// across a wall: halfL is +inf there).  The detect kernels record every such
+// contact; the wall condition is applied where partners are chosen
+// (k_slot_min, and pair_time_walls in the exact search).
 __device__ __forceinline__ bool pair_time(const Rec &a, const Rec &b, const Grid &G, double dt,
                                           double &t) {
   const double d0 = wrap_sep(b.x - a.x, G.L[0], G.halfL[0]);
   const double d1 = wrap_sep(b.y - a.y, G.L[1], G.halfL[1]);
   const double d2 = wrap_sep(b.z - a.z, G.L[2], G.halfL[2]);
   return contact_time(d0, d1, d2, b.vx - a.vx, b.vy - a.vy, b.vz - a.vz, a.r + b.r, dt, t);
+}
+
+// pair_time, valid only before either sphere reaches a wall
+__device__ __forceinline__ bool pair_time_walls(const Rec &a, const Rec &b, const Grid &G,
+                                                double dt, double &t) {
+  return pair_time(a, b, G, dt, t) &&
+         before_walls(a.x, a.y, a.z, a.vx, a.vy, a.vz, b.x, b.y, b.z, b.vx, b.vy, b.vz, G, t);
+}
+
+// End of a flight along axis k, p the unconstrained coordinate: wrapped on a
+// periodic axis; on a wall axis reflected at the plane crossed (a perfectly
+// reflective wall, Sec. "Intersection of Particles with Solid Walls": the
+// velocity component v changes sign), at most one plane per step; a coordinate
+// that lands on L itself becomes the largest double below L.
+__device__ __forceinline__ double fly_axis(double p, double L, bool wall, double &v) {
+  if (!wall) return wrap_pos(p, L);
+  if (p >= L) {
+    p = L - (p - L);
+    v = -v;
+  } else if (p < 0.0) {
+    p = -p;
+    v = -v;
+  }
+  if (p >= L) p = nextafter(L, 0.0);
+  return p;
 }
 
 // Post-collision state of sphere `a` colliding with `b` at time t (rule 4,
@@ -188,9 +250,9 @@ __device__ __forceinline__ void resolve_one(const Rec &a, const Rec &b, double m
   out_v[1] = a.vy + ai * n1;
   out_v[2] = a.vz + ai * n2;
   const double rest = dt - t;
-  out_x[0] = wrap_pos((a.x + t * a.vx) + rest * out_v[0], G.L[0]);
-  out_x[1] = wrap_pos((a.y + t * a.vy) + rest * out_v[1], G.L[1]);
-  out_x[2] = wrap_pos((a.z + t * a.vz) + rest * out_v[2], G.L[2]);
+  out_x[0] = fly_axis((a.x + t * a.vx) + rest * out_v[0], G.L[0], G.walls & 1, out_v[0]);
+  out_x[1] = fly_axis((a.y + t * a.vy) + rest * out_v[1], G.L[1], G.walls & 2, out_v[1]);
+  out_x[2] = fly_axis((a.z + t * a.vz) + rest * out_v[2], G.L[2], G.walls & 4, out_v[2]);
 }
 
 // Angular velocities (caller order, updated in place for collided spheres) and
@@ -354,7 +416,8 @@ hipError_t launch_cell_counts(hipStream_t s, const CellCount *c, int n, SweepCou
 hipError_t launch_slot_min(hipStream_t s, int n, int first, const int *cnt, const double *slot_t,
                            const int *slot_j, int K, uint8_t *status, const Rec *rec, int *key_j,
                            double *key_t, int *ovf_list, SweepCounters *ctr,
-                           const unsigned int *flags, const int *list = nullptr, int nlist = 0);
+                           const unsigned int *flags, const int *list = nullptr, int nlist = 0,
+                           const Grid *G = nullptr);  // G: walls of the single box (none: periodic)
 hipError_t launch_gather_exact(hipStream_t s, const int *list, int nlist, const unsigned int *nlist_dev,
                                int select, const Rec *rec, const int *start, const Grid &G,
                                double dt, uint8_t *status, int *key_j, double *key_t,

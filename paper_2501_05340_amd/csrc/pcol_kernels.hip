@@ -533,9 +533,9 @@ __device__ __forceinline__ void pair32(const DetectArgs &A, const Grid &G, int g
     const double vxi = hrec[i].vx, vyi = hrec[i].vy, vzi = hrec[i].vz;
     double e0 = b.x - xi, e1 = b.y - yi, e2 = b.z - zi;
     if (SHIFT) {
-      e0 = e0 + code_shift(code & 3, G.L[0]);
-      e1 = e1 + code_shift((code >> 2) & 3, G.L[1]);
-      e2 = e2 + code_shift((code >> 4) & 3, G.L[2]);
+      e0 = e0 + code_shift(code & 3, G.sL[0]);
+      e1 = e1 + code_shift((code >> 2) & 3, G.sL[1]);
+      e2 = e2 + code_shift((code >> 4) & 3, G.sL[2]);
     }
     double t;
     if (contact_time(e0, e1, e2, b.vx - vxi, b.vy - vyi, b.vz - vzi, ri + b.r, A.dt, t))
@@ -551,9 +551,9 @@ __device__ __forceinline__ void detect_chunk32(const DetectArgs &A, const Grid &
   if (thr >= 0) {
     const Rec b = A.rec[g];
     // candidate relative to the home cell centre (ox, oy, oz), image shift applied
-    bx = (float)((b.x + code_shift(code & 3, G.L[0])) - ox);
-    by = (float)((b.y + code_shift((code >> 2) & 3, G.L[1])) - oy);
-    bz = (float)((b.z + code_shift((code >> 4) & 3, G.L[2])) - oz);
+    bx = (float)((b.x + code_shift(code & 3, G.sL[0])) - ox);
+    by = (float)((b.y + code_shift((code >> 2) & 3, G.sL[1])) - oy);
+    bz = (float)((b.z + code_shift((code >> 4) & 3, G.sL[2])) - oz);
     bvx = (float)b.vx;
     bvy = (float)b.vy;
     bvz = (float)b.vz;
@@ -883,9 +883,9 @@ __device__ __forceinline__ void detect_cell64(const DetectArgs &A, const Grid &G
       double beta = 1e300;  // no candidate: never passes
       if (thr >= 0) {
         const Rec b = A.rec[g];
-        const double xj = (b.x + code_shift(code & 3, G.L[0])) - ox;
-        const double yj = (b.y + code_shift((code >> 2) & 3, G.L[1])) - oy;
-        const double zj = (b.z + code_shift((code >> 4) & 3, G.L[2])) - oz;
+        const double xj = (b.x + code_shift(code & 3, G.sL[0])) - ox;
+        const double yj = (b.y + code_shift((code >> 2) & 3, G.sL[1])) - oy;
+        const double zj = (b.z + code_shift((code >> 4) & 3, G.sL[2])) - oz;
         P[0] = xj;
         P[1] = yj;
         P[2] = zj;
@@ -1090,9 +1090,9 @@ __device__ __forceinline__ void detect_cell_gram(const DetectArgs &A, const Grid
     float beta = GRAM_NONE;
     if (thr >= 0) {
       const Rec b = A.rec[g];
-      const double xj = (b.x + code_shift(code & 3, G.L[0])) - ox;
-      const double yj = (b.y + code_shift((code >> 2) & 3, G.L[1])) - oy;
-      const double zj = (b.z + code_shift((code >> 4) & 3, G.L[2])) - oz;
+      const double xj = (b.x + code_shift(code & 3, G.sL[0])) - ox;
+      const double yj = (b.y + code_shift((code >> 2) & 3, G.sL[1])) - oy;
+      const double zj = (b.z + code_shift((code >> 4) & 3, G.sL[2])) - oz;
       const float p[7] = {(float)xj, (float)yj, (float)zj, (float)b.vx, (float)b.vy, (float)b.vz,
                           (float)b.r};
 #pragma unroll
@@ -1270,7 +1270,7 @@ __global__ __launch_bounds__(256) void k_slot_min(int n, int first, const int *c
                                                   uint8_t *status, const Rec *rec, int *key_j,
                                                   double *key_t, int *ovf_list,
                                                   SweepCounters *ctr, const unsigned int *flags,
-                                                  const int *list, int nlist) {
+                                                  const int *list, int nlist, Grid G) {
   if (flags && (flags[FLAG_ERR] || flags[FLAG_DONE])) return;
   const int t = blockIdx.x * 256 + threadIdx.x;
   const int i = list && t < nlist ? list[t] : t;
@@ -1288,10 +1288,20 @@ __global__ __launch_bounds__(256) void k_slot_min(int n, int first, const int *c
       } else {
         double bt = INFINITY;
         int bj = -1;
+        // between walls a contact counts only before both centres reach a wall
+        double ti = INFINITY;
+        if (G.walls) {
+          const Rec a = rec[i];
+          ti = time_to_wall(a.x, a.y, a.z, a.vx, a.vy, a.vz, G);
+        }
         for (int k = 0; k < c; ++k) {
           const int j = slot_j[(size_t)k * n + i];
           if (!first && status[j] == ST_COLLIDED) continue;
           const double t = slot_t[(size_t)k * n + i];
+          if (G.walls) {
+            const Rec b = rec[j];
+            if (!(t <= ti) || !(t <= time_to_wall(b.x, b.y, b.z, b.vx, b.vy, b.vz, G))) continue;
+          }
           if (t < bt || (bj >= 0 && t == bt && rec[j].o < rec[bj].o)) {
             bt = t;
             bj = j;
@@ -1311,11 +1321,14 @@ __global__ __launch_bounds__(256) void k_slot_min(int n, int first, const int *c
 hipError_t launch_slot_min(hipStream_t s, int n, int first, const int *cnt, const double *slot_t,
                            const int *slot_j, int K, uint8_t *status, const Rec *rec, int *key_j,
                            double *key_t, int *ovf_list, SweepCounters *ctr,
-                           const unsigned int *flags, const int *list, int nlist) {
+                           const unsigned int *flags, const int *list, int nlist,
+                           const Grid *G) {
   const int items = list ? nlist : n;
   if (items <= 0) return hipSuccess;
+  const Grid none{};  // walls = 0: periodic
   hipLaunchKernelGGL(k_slot_min, dim3((items + 255) / 256), dim3(256), 0, s, n, first, cnt, slot_t,
-                     slot_j, K, status, rec, key_j, key_t, ovf_list, ctr, flags, list, nlist);
+                     slot_j, K, status, rec, key_j, key_t, ovf_list, ctr, flags, list, nlist,
+                     G ? *G : none);
   return hipGetLastError();
 }
 
@@ -1572,7 +1585,7 @@ __global__ __launch_bounds__(256) void k_gather_exact(const int *list, int nlist
           if (status[j] == ST_COLLIDED) continue;
           const Rec b = rec[j];
           double t;
-          if (pair_time(a, b, G, dt, t)) {
+          if (pair_time_walls(a, b, G, dt, t)) {
             const int o = b.o;
             if (t < bt || (t == bt && o < bo)) {
               bt = t;
@@ -1799,12 +1812,13 @@ __global__ __launch_bounds__(256) void k_finish(Particles P, const int *rank,
     pj = r.partner;
   } else {
     const double *L = B.gtab ? B.gtab[B.box_of[o]].L : G0.L;
+    const int walls = B.gtab ? 0 : G0.walls;  // the batched form has periodic boxes only
     vx = P.vx[o];
     vy = P.vy[o];
     vz = P.vz[o];
-    x = wrap_pos(P.x[o] + dt * vx, L[0]);
-    y = wrap_pos(P.y[o] + dt * vy, L[1]);
-    z = wrap_pos(P.z[o] + dt * vz, L[2]);
+    x = fly_axis(P.x[o] + dt * vx, L[0], walls & 1, vx);
+    y = fly_axis(P.y[o] + dt * vy, L[1], walls & 2, vy);
+    z = fly_axis(P.z[o] + dt * vz, L[2], walls & 4, vz);
     t = __longlong_as_double(0x7ff8000000000000LL);  // NaN: no collision
     pj = -1;
   }

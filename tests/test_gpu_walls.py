@@ -1,0 +1,105 @@
+"""pcol_step_walls (reflective walls on chosen axes) on the GPU against the oracle's
+orc_step_walls, element by element: pair set and contact times bit-exact, positions
+and velocities within 1e-12 relative (in practice bitwise)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from tests.gpu_helpers import FIELDS, box_slice, compare_step, to_host
+import paper_2501_05340_amd as pc  # noqa: E402  (no CPU fallback: a missing library fails)
+
+pytestmark = pytest.mark.gpu
+
+
+def _announce(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def poly20k():
+    return workloads.make_box(20000, seed=13, phi=0.3, lognormal=(1.0, 0.25, 0.5, 2.0), e=0.8)
+
+
+def gpu_step_walls(box, walls, ctx=None, **opts):
+    p = pc.Particles.from_box(box)
+    if ctx is None:
+        ctx = pc.Context(max(box.n, 1), pc.pcol_default_opts(**opts) if opts else None)
+    partner = torch.empty(box.n, dtype=torch.int32, device="cuda")
+    tcoll = torch.empty(box.n, dtype=torch.float64, device="cuda")
+    st = pc.pcol_step_walls(ctx, p, box.L, walls, box.dt, box.e, partner, tcoll)
+    torch.cuda.synchronize()
+    return to_host(p), partner.cpu().numpy().astype(np.int64), tcoll.cpu().numpy(), st
+
+
+def test_no_walls_equals_pcol_step_bitwise(poly20k):
+    _announce("walls none poly20k")
+    g = gpu_step_walls(poly20k, (0, 0, 0))
+    assert compare_step(poly20k, g, oracle.step(poly20k)) == 0
+
+
+@pytest.mark.parametrize("walls", [(1, 1, 1), (1, 0, 0), (0, 1, 1)])
+@pytest.mark.parametrize("case", ["config1", "poly20k", "poly4097", "config2"])
+def test_walls_match_oracle(poly20k, case, walls):
+    box = {"config1": lambda: workloads.config(1), "poly20k": lambda: poly20k,
+           "poly4097": lambda: box_slice(poly20k, 4097),
+           "config2": lambda: workloads.config(2)}[case]()
+    if case == "config2" and walls != (1, 1, 1):
+        pytest.skip("one wall layout at 1M")
+    _announce(f"walls {walls} {case} n={box.n}")
+    g = gpu_step_walls(box, walls)
+    orc = oracle.step_walls(box, walls)
+    assert orc.n_pairs > 0
+    assert compare_step(box, g, orc) == 0
+
+
+@pytest.mark.parametrize("opts", [{"filter": 1}, {"filter": 2}, {"contact_slots": 1},
+                                  {"split_quantile": 0.9}, {"split_quantile": 0.0}])
+def test_walls_every_filter_and_search_path(poly20k, opts):
+    walls = (1, 0, 1)
+    _announce(f"walls {walls} poly20k {opts}")
+    g = gpu_step_walls(poly20k, walls, **opts)
+    assert compare_step(poly20k, g, oracle.step_walls(poly20k, walls)) == 0
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_walls_small_box_fewer_than_three_cells(seed):
+    box = workloads.make_box(250, seed=seed, phi=0.3, radius=0.5, e=0.85, dt=0.25)
+    _announce(f"walls small box seed={seed}")
+    g = gpu_step_walls(box, (1, 1, 1))
+    assert min(g[3]["nc"]) < 3
+    assert compare_step(box, g, oracle.step_walls(box, (1, 1, 1))) == 0
+
+
+def test_walls_many_steps_in_lockstep_energy_conserved():
+    box = workloads.make_box(3000, seed=9, phi=0.2, radius=0.5, e=1.0, dt=0.25)
+    walls = (1, 0, 1)
+    p = pc.Particles.from_box(box)
+    ctx = pc.Context(box.n)
+    ref = box.copy()
+    ke0 = 0.5 * np.sum(box.m * (box.vx ** 2 + box.vy ** 2 + box.vz ** 2))
+    _announce("walls 30 steps lockstep")
+    for step in range(30):
+        pc.pcol_step_walls(ctx, p, box.L, walls, box.dt, box.e)
+        r = oracle.step_walls(ref, walls)
+        ref.x, ref.y, ref.z, ref.vx, ref.vy, ref.vz = r.x, r.y, r.z, r.vx, r.vy, r.vz
+        got = to_host(p)
+        for f in FIELDS:
+            assert np.array_equal(got[f].view(np.uint64), getattr(ref, f).view(np.uint64)), \
+                (step, f)
+    ke = 0.5 * np.sum(box.m * (ref.vx ** 2 + ref.vy ** 2 + ref.vz ** 2))
+    assert ke == pytest.approx(ke0, rel=1e-12)
+
+
+def test_composed_api_refuses_a_walls_binning(poly20k):
+    box = box_slice(poly20k, 2000)
+    p = pc.Particles.from_box(box)
+    ctx = pc.Context(box.n)
+    pc.pcol_step_walls(ctx, p, box.L, (1, 0, 0), box.dt, box.e)
+    with pytest.raises(pc.PcolError) as ei:
+        pc.pcol_detect(ctx, p, box.L, box.dt)
+    assert ei.value.code == pc.PCOL_E_STATE
+    pc.pcol_bin(ctx, p, box.L, box.dt)
+    pc.pcol_detect(ctx, p, box.L, box.dt)   # a periodic binning works again
+    torch.cuda.synchronize()
