@@ -241,6 +241,42 @@ def friction_leg(args, pc, torch, box, p0, ref):
     return out
 
 
+def walls_leg(args, pc, torch, box, p0, ref):
+    """The 16M step between reflective walls on all three axes (pcol_step_walls), each
+    step from the configured input, restored outside the timed interval."""
+    walls = (1, 1, 1)
+    p = p0.clone()
+    ctx = pc.Context(box.n)
+    partner = torch.empty(box.n, dtype=torch.int32, device="cuda")
+
+    def restore():
+        for t, t_0 in zip(p.tensors()[:6], p0.tensors()[:6]):
+            t.copy_(t_0)
+
+    for k in range(args.warmup):
+        restore()
+        pc.pcol_step_walls(ctx, p, box.L, walls, box.dt, box.e, partner)
+    stats, wall = [], 0.0
+    for k in range(args.steps):
+        restore()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats.append(pc.pcol_step_walls(ctx, p, box.L, walls, box.dt, box.e, partner))
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+    out = {
+        "value": box.n * args.steps / wall, "unit": "particles/s",
+        "ms_per_step": wall * 1e3 / args.steps, "walls": list(walls),
+        "ms_per_step_over_plain": (wall / args.steps) / (ref["wall"] / args.steps),
+        "pairs_per_step": statistics.mean(st["n_pairs"] for st in stats),
+        "pairs_per_step_plain": statistics.mean(st["n_pairs"] for st in ref["stats"]),
+        "partners_differing_from_plain": int((partner != ref["partner"]).sum().item()),
+    }
+    ctx.close()
+    log(f"[walls] {out['ms_per_step']:.3f} ms per step, {out['pairs_per_step']:.0f} pairs")
+    return out
+
+
 def deposition_leg(args, pc, torch, box, p0):
     """Deposition of four source components (momentum and energy; standard normal,
     seed 3) of the 16M spheres at their start positions onto the corner nodes of a
@@ -358,6 +394,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-form leg")
     ap.add_argument("--no-friction", action="store_true", help="skip the friction-and-spin leg")
     ap.add_argument("--no-deposition", action="store_true", help="skip the deposition leg")
+    ap.add_argument("--no-walls", action="store_true", help="skip the walls leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on one GPU only: the collision step is a single-GPU build; "
@@ -508,6 +545,8 @@ def main():
         out["batched_form"] = batched_leg(args, pc, torch)
     if not args.no_friction and "fp64" in forms:
         out["friction_form"] = friction_leg(args, pc, torch, box, p0, forms["fp64"])
+    if not args.no_walls and "fp64" in forms:
+        out["walls_form"] = walls_leg(args, pc, torch, box, p0, forms["fp64"])
     if not args.no_deposition:
         out["deposition"] = deposition_leg(args, pc, torch, box, p0)
     if not args.no_adjoint:
