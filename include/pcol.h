@@ -20,6 +20,8 @@
  *     its new velocity.
  *   - Sec. "Collision Operator": one collision per sphere per step; spheres
  *     that collided leave the set of eligible partners.
+ *   - Sec. "Intersection of Particles with Solid Walls" (pcol_step_walls only):
+ *     reflective walls on chosen axes.
  *   - Sec. "Dispersed Phase" and Sec. "Deposition" (pcol_deposit only): the
  *     linear projection of per-particle sources onto element corner nodes.
  *
