@@ -183,3 +183,63 @@ def test_16M_friction_and_spin_sampled(big):
     for f in ("vx", "vy", "vz"):
         p_in = math.fsum(m * getattr(box, f))
         assert abs(math.fsum(m * out[f]) - p_in) <= 1e-10 * math.fsum(m * np.abs(getattr(box, f)))
+
+
+def _reflect(p, L):
+    """Free-flight end coordinate between walls at 0 and L (at most one plane crossed)."""
+    flip = (p >= L) | (p < 0)
+    q = np.where(p >= L, L - (p - L), np.where(p < 0, -p, p))
+    q = np.where(q >= L, np.nextafter(L, 0.0), q)
+    return q, flip
+
+
+@pytest.mark.timeout(900)
+def test_16M_walls_properties(big):
+    """pcol_step_walls at 16M with walls on x and z (the oracle's walls step is too slow at
+    this size): mutual pairs with bitwise-symmetric times, every contact no later than both
+    centres' times of flight to a wall, the reflected free flight of every sphere without
+    a collision exactly, y periodic, momentum along y conserved, positions inside."""
+    box, p0 = big
+    n, walls = box.n, (1, 0, 1)
+    print("[gpu-test] 16M step between walls", flush=True)
+    p = p0.clone()
+    ctx = pc.Context(n)
+    partner = torch.empty(n, dtype=torch.int32, device="cuda")
+    tcoll = torch.empty(n, dtype=torch.float64, device="cuda")
+    st = pc.pcol_step_walls(ctx, p, box.L, walls, box.dt, box.e, partner, tcoll)
+    torch.cuda.synchronize()
+    ctx.close()
+    out = {f: getattr(p, f).cpu().numpy() for f in FIELDS}
+    partner, tcoll = partner.cpu().numpy().astype(np.int64), tcoll.cpu().numpy()
+    del p
+    hit = partner >= 0
+    assert st["n_pairs"] * 2 == int(hit.sum()) and st["n_pairs"] > 1_000_000
+    assert np.array_equal(partner[partner[hit]], np.where(hit)[0])
+    assert np.array_equal(tcoll[hit], tcoll[partner[hit]])
+    L = np.array(box.L)
+    tof = np.full(n, np.inf)
+    for a, (f, v) in enumerate((("x", box.vx), ("y", box.vy), ("z", box.vz))):
+        if not walls[a]:
+            continue
+        x = getattr(box, f)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            t = np.where(v > 0, (L[a] - x) / v, np.where(v < 0, -x / v, np.inf))
+        tof = np.minimum(tof, t)
+    i = np.where(hit)[0]
+    assert np.all(tcoll[i] <= tof[i]) and np.all(tcoll[i] <= tof[partner[i]])
+    for a, (f, vf) in enumerate((("x", "vx"), ("y", "vy"), ("z", "vz"))):
+        x0, v0 = getattr(box, f)[~hit], getattr(box, vf)[~hit]
+        x1 = x0 + box.dt * v0
+        if walls[a]:
+            x1, flip = _reflect(x1, L[a])
+            v1 = np.where(flip, -v0, v0)
+            assert flip.sum() > 1000
+        else:
+            x1 = np.where(x1 >= L[a], x1 - L[a], np.where(x1 < 0, x1 + L[a], x1))
+            x1 = np.where(x1 >= L[a], 0.0, x1)
+            v1 = v0
+        assert np.array_equal(out[f][~hit], x1) and np.array_equal(out[vf][~hit], v1)
+        assert np.all(out[f] >= 0.0) and np.all(out[f] < L[a])
+    m = box.m
+    p_in = math.fsum(m * box.vy)
+    assert abs(math.fsum(m * out["vy"]) - p_in) <= 1e-10 * math.fsum(m * np.abs(box.vy))
