@@ -2274,23 +2274,44 @@ __device__ __forceinline__ int dep_cell(double p, double h, int nc, double &f) {
 
 // Element of every sphere and its slot among the element's spheres.  A
 // position outside [0, L) or not finite raises bit 0 of *flag and is not
-// counted (the host reads the flag before anything else runs).
+// counted (the host reads the flag before anything else runs).  Consecutive
+// lanes of one element (spheres stored in element order) take their slots with
+// one atomic per run.
 __global__ __launch_bounds__(256) void k_dep_count(DepositArgs D, unsigned int *flag) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= D.n) return;
-  const double p0 = D.x[i], p1 = D.y[i], p2 = D.z[i];
-  const bool bad = !(p0 >= 0.0 && p0 < D.L[0]) || !(p1 >= 0.0 && p1 < D.L[1]) ||
-                   !(p2 >= 0.0 && p2 < D.L[2]);
-  if (__ballot(bad) != 0ull && __lane_id() == __ffsll((long long)__ballot(bad)) - 1)
-    atomicOr(flag, 1u);
-  if (bad) return;
-  double f;
-  const int c0 = dep_cell(p0, D.h[0], D.nc[0], f);
-  const int c1 = dep_cell(p1, D.h[1], D.nc[1], f);
-  const int c2 = dep_cell(p2, D.h[2], D.nc[2], f);
-  const int e = (c2 * D.nc[1] + c1) * D.nc[0] + c0;
-  D.eid[i] = e;
-  D.slot[i] = atomicAdd(&D.cnt[e], 1);
+  int e = -1;  // -1: no element (past the end, or a bad position)
+  bool bad = false;
+  if (i < D.n) {
+    const double p0 = D.x[i], p1 = D.y[i], p2 = D.z[i];
+    bad = !(p0 >= 0.0 && p0 < D.L[0]) || !(p1 >= 0.0 && p1 < D.L[1]) ||
+          !(p2 >= 0.0 && p2 < D.L[2]);
+    if (!bad) {
+      double f;
+      const int c0 = dep_cell(p0, D.h[0], D.nc[0], f);
+      const int c1 = dep_cell(p1, D.h[1], D.nc[1], f);
+      const int c2 = dep_cell(p2, D.h[2], D.nc[2], f);
+      e = (c2 * D.nc[1] + c1) * D.nc[0] + c0;
+    }
+  }
+  const int lane = (int)__lane_id();
+  const unsigned long long badm = __ballot(bad);
+  if (badm != 0ull && lane == __ffsll((long long)badm) - 1) atomicOr(flag, 1u);
+  // runs: a lane starts one unless it continues its left neighbour's element
+  const int prev = __shfl_up(e, 1);
+  const unsigned long long starts = __ballot(lane == 0 || prev != e);
+  const unsigned long long upto = starts & ((2ull << lane) - 1ull);  // bit 0 always set
+  const int h = 63 - __clzll(upto);                                   // this lane's run start
+  const unsigned long long after = starts & ~((2ull << lane) - 1ull);
+  int base = 0;
+  if (e >= 0 && lane == h) {
+    const int len = (after ? __ffsll((long long)after) - 1 : WAVE) - h;
+    base = atomicAdd(&D.cnt[e], len);
+  }
+  base = __shfl(base, h);
+  if (e >= 0) {
+    D.eid[i] = e;
+    D.slot[i] = base + (lane - h);
+  }
 }
 
 // one record per sphere at its element-sorted position (caller arrays read
