@@ -32,6 +32,25 @@ __device__ __forceinline__ unsigned int wave_append(bool pred, unsigned int *cou
   return base + below;
 }
 
+// Slot of this lane's key among all items of that key (key < 0: none, returns
+// 0): consecutive lanes with one key (inputs stored in key order) share one
+// atomic on count[key] per run and take consecutive slots.  Every lane of the
+// wave must call it.
+__device__ __forceinline__ int run_slot(int key, int *count) {
+  const int lane = (int)__lane_id();
+  const int prev = __shfl_up(key, 1);
+  const unsigned long long starts = __ballot(lane == 0 || prev != key);
+  const unsigned long long upto = starts & ((2ull << lane) - 1ull);  // bit 0 always set
+  const int h = 63 - __clzll(upto);                                   // this lane's run start
+  const unsigned long long after = starts & ~((2ull << lane) - 1ull);
+  int base = 0;
+  if (key >= 0 && lane == h) {
+    const int len = (after ? __ffsll((long long)after) - 1 : WAVE) - h;
+    base = atomicAdd(&count[key], len);
+  }
+  return __shfl(base, h) + (lane - h);
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
   for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -221,21 +240,27 @@ hipError_t launch_reach(hipStream_t s, const Particles &P, const double L[3], do
 
 // ---------------------------------------------------------------- a2: cell id + histogram
 
-// Cell of each sphere and its rank within the cell (one atomic per sphere).
+// Cell of each sphere and its rank within the cell (one atomic per sphere, or
+// per run of spheres of one cell in consecutive lanes).
 // Extent split: a sphere whose extent r + |v| dt exceeds rho_c goes to the
 // second layer of cells (number G.layer2 + c), searched separately; the first
 // layer then only needs cells of side 2 rho_c.  rho_c = +inf: one layer.
 __global__ __launch_bounds__(256) void k_cell_hist(Particles P, Grid G, double dt, double rho_c,
                                                    int *cid, int *slot, int *count) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= P.n) return;
-  const int cx = cell_coord(P.x[i], G.inv_h[0], G.nc[0]);
-  const int cy = cell_coord(P.y[i], G.inv_h[1], G.nc[1]);
-  const int cz = cell_coord(P.z[i], G.inv_h[2], G.nc[2]);
-  int c = (cz * G.nc[1] + cy) * G.nc[0] + cx;
-  if (G.layer2 && !(extent(P.r[i], P.vx[i], P.vy[i], P.vz[i], dt) <= rho_c)) c += G.layer2;
-  cid[i] = c;
-  slot[i] = atomicAdd(&count[c], 1);
+  int c = -1;
+  if (i < P.n) {
+    const int cx = cell_coord(P.x[i], G.inv_h[0], G.nc[0]);
+    const int cy = cell_coord(P.y[i], G.inv_h[1], G.nc[1]);
+    const int cz = cell_coord(P.z[i], G.inv_h[2], G.nc[2]);
+    c = (cz * G.nc[1] + cy) * G.nc[0] + cx;
+    if (G.layer2 && !(extent(P.r[i], P.vx[i], P.vy[i], P.vz[i], dt) <= rho_c)) c += G.layer2;
+  }
+  const int sl = run_slot(c, count);
+  if (c >= 0) {
+    cid[i] = c;
+    slot[i] = sl;
+  }
 }
 
 hipError_t launch_cell_hist(hipStream_t s, const Particles &P, const Grid &G, double dt,
@@ -2296,21 +2321,10 @@ __global__ __launch_bounds__(256) void k_dep_count(DepositArgs D, unsigned int *
   const int lane = (int)__lane_id();
   const unsigned long long badm = __ballot(bad);
   if (badm != 0ull && lane == __ffsll((long long)badm) - 1) atomicOr(flag, 1u);
-  // runs: a lane starts one unless it continues its left neighbour's element
-  const int prev = __shfl_up(e, 1);
-  const unsigned long long starts = __ballot(lane == 0 || prev != e);
-  const unsigned long long upto = starts & ((2ull << lane) - 1ull);  // bit 0 always set
-  const int h = 63 - __clzll(upto);                                   // this lane's run start
-  const unsigned long long after = starts & ~((2ull << lane) - 1ull);
-  int base = 0;
-  if (e >= 0 && lane == h) {
-    const int len = (after ? __ffsll((long long)after) - 1 : WAVE) - h;
-    base = atomicAdd(&D.cnt[e], len);
-  }
-  base = __shfl(base, h);
+  const int sl = run_slot(e, D.cnt);
   if (e >= 0) {
     D.eid[i] = e;
-    D.slot[i] = base + (lane - h);
+    D.slot[i] = sl;
   }
 }
 
