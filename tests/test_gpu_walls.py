@@ -103,3 +103,36 @@ def test_composed_api_refuses_a_walls_binning(poly20k):
     pc.pcol_bin(ctx, p, box.L, box.dt)
     pc.pcol_detect(ctx, p, box.L, box.dt)   # a periodic binning works again
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("n", [0, 1, 2])
+def test_walls_degenerate_sizes(n):
+    # two spheres colliding at t = 0.2, before the first reaches the x wall (t = 0.3), both
+    # reflected afterwards; one sphere alone crosses the wall
+    full = workloads.Box(np.array([0.6, 2.0]), np.array([5.0, 5.0]), np.array([5.0, 5.0]),
+                         np.array([-2.0, -4.0]), np.zeros(2), np.zeros(2), np.full(2, 0.5),
+                         np.ones(2), (20.0, 20.0, 20.0), 0.5, 0.9)
+    box = box_slice(full, n)
+    _announce(f"walls n={n}")
+    g = gpu_step_walls(box, (1, 0, 0))
+    assert compare_step(box, g, oracle.step_walls(box, (1, 0, 0))) == 0
+
+
+def test_walls_restitution_zero_and_errors(poly20k):
+    box = box_slice(poly20k, 6000)
+    box.e = 0.0
+    _announce("walls e=0")
+    g = gpu_step_walls(box, (0, 1, 0))
+    assert compare_step(box, g, oracle.step_walls(box, (0, 1, 0))) == 0
+    p = pc.Particles.from_box(box)
+    ctx = pc.Context(box.n)
+    with pytest.raises(pc.PcolError) as ei:   # e outside [0, 1]
+        pc.pcol_step_walls(ctx, p, box.L, (1, 1, 1), box.dt, 1.5)
+    assert ei.value.code == pc.PCOL_E_INVALID
+    x0 = p.x.clone()
+    p.x[3] = box.L[0]   # a position outside [0, L) is refused, inputs unchanged otherwise
+    with pytest.raises(pc.PcolError) as ei:
+        pc.pcol_step_walls(ctx, p, box.L, (1, 1, 1), box.dt, box.e)
+    assert ei.value.code == pc.PCOL_E_INVALID
+    torch.cuda.synchronize()
+    assert torch.equal(p.x[4:], x0[4:]) and torch.equal(p.vx, pc.Particles.from_box(box).vx)
