@@ -241,6 +241,48 @@ def friction_leg(args, pc, torch, box, p0, ref):
     return out
 
 
+def cell_order_leg(args, pc, torch, box, p0, ref):
+    """The same 16M step with the spheres stored in cell order (sorted by the cell of a
+    106^3 grid over the box, z slowest: a caller that keeps its particles sorted by
+    element), permuted before timing; the pair count must equal the stored-order step's."""
+    nc = 106
+    cell = [torch.clamp(torch.floor(t / (box.L[d] / nc)), max=nc - 1).long()
+            for d, t in enumerate((p0.x, p0.y, p0.z))]
+    perm = torch.argsort((cell[2] * nc + cell[1]) * nc + cell[0], stable=True)
+    q0 = pc.Particles(*[t[perm].contiguous() for t in p0.tensors()])
+    del cell, perm
+    p = q0.clone()
+    ctx = pc.Context(box.n, pc.pcol_default_opts(timing=1))
+
+    def restore():
+        for t, t_0 in zip(p.tensors()[:6], q0.tensors()[:6]):
+            t.copy_(t_0)
+
+    for k in range(args.warmup):
+        restore()
+        pc.pcol_step(ctx, p, box.L, box.dt, box.e)
+    stats, wall = [], 0.0
+    for k in range(args.steps):
+        restore()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats.append(pc.pcol_step(ctx, p, box.L, box.dt, box.e))
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+    out = {
+        "value": box.n * args.steps / wall, "unit": "particles/s",
+        "ms_per_step": wall * 1e3 / args.steps,
+        "ms_per_step_over_stored_order": (wall / args.steps) / (ref["wall"] / args.steps),
+        "bin_ms_median": statistics.median(st["ms_bin"] for st in stats),
+        "advance_ms_median": statistics.median(st["ms_advance"] for st in stats),
+        "pairs_per_step": statistics.mean(st["n_pairs"] for st in stats),
+        "pairs_per_step_stored_order": statistics.mean(st["n_pairs"] for st in ref["stats"]),
+    }
+    ctx.close()
+    log(f"[cell order] {out['ms_per_step']:.3f} ms per step, bin {out['bin_ms_median']:.3f} ms")
+    return out
+
+
 def walls_leg(args, pc, torch, box, p0, ref):
     """The 16M step between reflective walls on all three axes (pcol_step_walls), each
     step from the configured input, restored outside the timed interval."""
@@ -395,6 +437,8 @@ def main():
     ap.add_argument("--no-friction", action="store_true", help="skip the friction-and-spin leg")
     ap.add_argument("--no-deposition", action="store_true", help="skip the deposition leg")
     ap.add_argument("--no-walls", action="store_true", help="skip the walls leg")
+    ap.add_argument("--no-cell-order", action="store_true",
+                    help="skip the leg with the spheres stored in cell order")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on one GPU only: the collision step is a single-GPU build; "
@@ -545,6 +589,8 @@ def main():
         out["batched_form"] = batched_leg(args, pc, torch)
     if not args.no_friction and "fp64" in forms:
         out["friction_form"] = friction_leg(args, pc, torch, box, p0, forms["fp64"])
+    if not args.no_cell_order and "fp64" in forms:
+        out["cell_order_form"] = cell_order_leg(args, pc, torch, box, p0, forms["fp64"])
     if not args.no_walls and "fp64" in forms:
         out["walls_form"] = walls_leg(args, pc, torch, box, p0, forms["fp64"])
     if not args.no_deposition:

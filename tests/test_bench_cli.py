@@ -19,6 +19,6 @@ def test_help_lists_every_leg_switch():
     res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"],
                          capture_output=True, text=True, timeout=120)
     assert res.returncode == 0
-    for flag in ("--no-batched", "--no-adjoint", "--no-friction", "--no-walls", "--no-deposition",
+    for flag in ("--no-batched", "--no-adjoint", "--no-friction", "--no-walls", "--no-deposition", "--no-cell-order",
                  "--no-cpu-baseline", "--steps", "--warmup", "--gpus"):
         assert flag in res.stdout, flag
