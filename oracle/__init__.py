@@ -92,6 +92,10 @@ def _load():
             _D, _I32, ctypes.c_double, ctypes.c_double] + [_D] * 6 + [
             _I64, _D, ctypes.POINTER(_Stats)]
         lib.orc_step_walls.restype = ctypes.c_int
+        lib.orc_step_walls_spin.argtypes = [ctypes.c_int64] + [_D] * 11 + [
+            _D, _I32, ctypes.c_double, ctypes.c_double, ctypes.c_double] + [_D] * 9 + [
+            _I64, _D, ctypes.POINTER(_Stats)]
+        lib.orc_step_walls_spin.restype = ctypes.c_int
         lib.orc_deposit.argtypes = [ctypes.c_int64, _D, _D, _D, _D, ctypes.c_int,
                                     ctypes.POINTER(ctypes.c_int), _D, _D]
         lib.orc_deposit.restype = ctypes.c_int
@@ -330,3 +334,26 @@ def step_walls(box, walls, *, e: float | None = None) -> StepResult:
     sweep = np.where(partner >= 0, 0, -1).astype(np.int32)
     return StepResult(*outs, partner, tcoll, sweep, st.n_pairs, st.n_sweeps, st.pair_tests,
                       st.reach)
+
+
+def step_walls_spin(box, walls, w, mu: float, *, e: float | None = None) -> SpinStepResult:
+    """One step of ``box`` between walls (walls[k] true: walls on axis k) with angular
+    velocities ``w`` (shape (3, n)) and Coulomb friction ``mu``; inputs unchanged."""
+    n = box.n
+    arrs = [_c64(a) for a in (box.x, box.y, box.z, box.vx, box.vy, box.vz, w[0], w[1], w[2],
+                              box.r, box.m)]
+    outs = [np.empty(n) for _ in range(9)]
+    partner = np.empty(n, dtype=np.int64)
+    tcoll = np.empty(n)
+    st = _Stats()
+    wl = np.ascontiguousarray([1 if v else 0 for v in walls], dtype=np.int32)
+    rc = _load().orc_step_walls_spin(n, *[_d(a) for a in arrs], _d(_c64(box.L)),
+                                     wl.ctypes.data_as(_I32), float(box.dt),
+                                     float(box.e if e is None else e), float(mu),
+                                     *[_d(o) for o in outs], partner.ctypes.data_as(_I64),
+                                     _d(tcoll), ctypes.byref(st))
+    if rc:
+        raise OracleError(rc)
+    sweep = np.where(partner >= 0, 0, -1).astype(np.int32)
+    return SpinStepResult(*outs[:6], partner, tcoll, sweep, st.n_pairs, st.n_sweeps,
+                          st.pair_tests, st.reach, outs[6], outs[7], outs[8])

@@ -453,20 +453,25 @@ void orc_resolve_pair(int64_t i, int64_t j, double t, const double *x, const dou
  * left out, so the result equals orc_resolve_pair's bitwise and the spin is
  * unchanged.  Reads start-of-step data; writes a's new state.
  */
+static double orc_sep_axis(double d, double len, int wall);
+static double orc_fly_axis(double p, double len, int wall, double *v);
+
+/* wall: NULL for a periodic box, else the wall flags of orc_step_walls (the
+ * separation of orc_sep_axis and the rest of the step flown with orc_fly_axis) */
 static void orc_resolve_side_spin(int64_t a, int64_t b, double t, const double *x,
                                   const double *y, const double *z, const double *vx,
                                   const double *vy, const double *vz, const double *wx,
                                   const double *wy, const double *wz, const double *r,
-                                  const double *m, const double L[3], double dt, double e,
-                                  double mu, double *xo, double *yo, double *zo, double *vxo,
-                                  double *vyo, double *vzo, double *wxo, double *wyo,
+                                  const double *m, const double L[3], const int *wall, double dt,
+                                  double e, double mu, double *xo, double *yo, double *zo,
+                                  double *vxo, double *vyo, double *vzo, double *wxo, double *wyo,
                                   double *wzo) {
   const double xa[3] = {x[a], y[a], z[a]}, xb[3] = {x[b], y[b], z[b]};
   const double va[3] = {vx[a], vy[a], vz[a]}, vb[3] = {vx[b], vy[b], vz[b]};
   const double wa[3] = {wx[a], wy[a], wz[a]}, wb[3] = {wx[b], wy[b], wz[b]};
   double d[3], u[3], n[3];
   for (int k = 0; k < 3; ++k) {
-    d[k] = orc_wrap_sep(xb[k] - xa[k], L[k]);
+    d[k] = wall ? orc_sep_axis(xb[k] - xa[k], L[k], wall[k]) : orc_wrap_sep(xb[k] - xa[k], L[k]);
     u[k] = vb[k] - va[k];
   }
   const double s = r[a] + r[b];
@@ -500,8 +505,10 @@ static void orc_resolve_side_spin(int64_t a, int64_t b, double t, const double *
   const double rest = dt - t;
   double *xout[3] = {xo, yo, zo}, *vout[3] = {vxo, vyo, vzo}, *wout[3] = {wxo, wyo, wzo};
   for (int k = 0; k < 3; ++k) {
-    xout[k][a] = orc_wrap_pos((xa[k] + t * va[k]) + rest * van[k], L[k]);
-    vout[k][a] = van[k];
+    double vk = van[k];
+    xout[k][a] = wall ? orc_fly_axis((xa[k] + t * va[k]) + rest * van[k], L[k], wall[k], &vk)
+                      : orc_wrap_pos((xa[k] + t * va[k]) + rest * van[k], L[k]);
+    vout[k][a] = vk;
     wout[k][a] = wa[k];
   }
   if (Jt != 0.0) {
@@ -522,9 +529,9 @@ void orc_resolve_pair_spin(int64_t i, int64_t j, double t, const double *x, cons
                            const double L[3], double dt, double e, double mu, double *xo,
                            double *yo, double *zo, double *vxo, double *vyo, double *vzo,
                            double *wxo, double *wyo, double *wzo) {
-  orc_resolve_side_spin(i, j, t, x, y, z, vx, vy, vz, wx, wy, wz, r, m, L, dt, e, mu, xo, yo, zo,
+  orc_resolve_side_spin(i, j, t, x, y, z, vx, vy, vz, wx, wy, wz, r, m, L, NULL, dt, e, mu, xo, yo, zo,
                         vxo, vyo, vzo, wxo, wyo, wzo);
-  orc_resolve_side_spin(j, i, t, x, y, z, vx, vy, vz, wx, wy, wz, r, m, L, dt, e, mu, xo, yo, zo,
+  orc_resolve_side_spin(j, i, t, x, y, z, vx, vy, vz, wx, wy, wz, r, m, L, NULL, dt, e, mu, xo, yo, zo,
                         vxo, vyo, vzo, wxo, wyo, wzo);
 }
 
@@ -1074,14 +1081,22 @@ static void orc_resolve_pair_walls(int64_t i, int64_t j, double t, const double 
  * side (>= reach) apart without the minimum image and cannot touch within the
  * step.  Outputs and errors as orc_step.
  */
-int orc_step_walls(int64_t n, const double *x, const double *y, const double *z,
-                   const double *vx, const double *vy, const double *vz, const double *r,
-                   const double *m, const double L[3], const int wall[3], double dt, double e,
-                   double *xo, double *yo, double *zo, double *vxo, double *vyo, double *vzo,
-                   int64_t *partner, double *tcoll, orc_stats *st) {
+static int orc_step_walls_core(int64_t n, const double *x, const double *y, const double *z,
+                               const double *vx, const double *vy, const double *vz,
+                               const double *wx, const double *wy, const double *wz,
+                               const double *r, const double *m, const double L[3],
+                               const int wall[3], double dt, double e, double mu, double *xo,
+                               double *yo, double *zo, double *vxo, double *vyo, double *vzo,
+                               double *wxo, double *wyo, double *wzo, int64_t *partner,
+                               double *tcoll, orc_stats *st) {
   int rc = orc_check_inputs(n, x, y, z, vx, vy, vz, r, m, L, dt);
   if (rc) return rc;
   if (!(e >= 0.0 && e <= 1.0)) return ORC_E_INVALID;
+  if (wx) {
+    if (!(mu >= 0.0) || !isfinite(mu)) return ORC_E_INVALID;
+    for (int64_t i = 0; i < n; ++i)
+      if (!isfinite(wx[i]) || !isfinite(wy[i]) || !isfinite(wz[i])) return ORC_E_INVALID;
+  }
   const double reach = orc_reach(n, vx, vy, vz, r, dt);
   for (int a = 0; a < 3; ++a)
     if (!(L[a] > 2.0 * reach)) return ORC_E_BOX;
@@ -1142,8 +1157,15 @@ int orc_step_walls(int64_t n, const double *x, const double *y, const double *z,
     for (int64_t i = 0; i < n; ++i) {
       const int64_t j = pj[i];
       if (j > i && pj[j] == i) {
-        orc_resolve_pair_walls(i, j, pt[i], x, y, z, vx, vy, vz, r, m, L, wall, dt, e, xo, yo,
-                               zo, vxo, vyo, vzo);
+        if (wx) {
+          orc_resolve_side_spin(i, j, pt[i], x, y, z, vx, vy, vz, wx, wy, wz, r, m, L, wall, dt, e,
+                                mu, xo, yo, zo, vxo, vyo, vzo, wxo, wyo, wzo);
+          orc_resolve_side_spin(j, i, pt[i], x, y, z, vx, vy, vz, wx, wy, wz, r, m, L, wall, dt, e,
+                                mu, xo, yo, zo, vxo, vyo, vzo, wxo, wyo, wzo);
+        } else {
+          orc_resolve_pair_walls(i, j, pt[i], x, y, z, vx, vy, vz, r, m, L, wall, dt, e, xo, yo,
+                                 zo, vxo, vyo, vzo);
+        }
         if (partner) {
           partner[i] = j;
           partner[j] = i;
@@ -1168,6 +1190,11 @@ int orc_step_walls(int64_t n, const double *x, const double *y, const double *z,
       po[k][i] = orc_fly_axis(p[k][i] + dt * vk, L[k], wall[k], &vk);
       vo[k][i] = vk;
     }
+    if (wx) { /* an elastic wall leaves the spin unchanged */
+      wxo[i] = wx[i];
+      wyo[i] = wy[i];
+      wzo[i] = wz[i];
+    }
   }
   if (st) {
     st->n_pairs = pairs;
@@ -1180,4 +1207,30 @@ int orc_step_walls(int64_t n, const double *x, const double *y, const double *z,
   free(pt);
   orc_grid_free(&G);
   return ORC_OK;
+}
+
+/* One step between walls without friction (orc_step_walls_core). */
+int orc_step_walls(int64_t n, const double *x, const double *y, const double *z,
+                   const double *vx, const double *vy, const double *vz, const double *r,
+                   const double *m, const double L[3], const int wall[3], double dt, double e,
+                   double *xo, double *yo, double *zo, double *vxo, double *vyo, double *vzo,
+                   int64_t *partner, double *tcoll, orc_stats *st) {
+  return orc_step_walls_core(n, x, y, z, vx, vy, vz, NULL, NULL, NULL, r, m, L, wall, dt, e, 0.0,
+                             xo, yo, zo, vxo, vyo, vzo, NULL, NULL, NULL, partner, tcoll, st);
+}
+
+/* One step between walls with spins and Coulomb friction mu: the pair resolve
+ * of orc_step_spin (orc_resolve_side_spin) with the separation and flight of
+ * the walls; an elastic wall leaves the spin unchanged (its momentum change is
+ * zero, so the angular jump relation of Sec. "Intersection of Particles with
+ * Solid Walls" gives no spin change). */
+int orc_step_walls_spin(int64_t n, const double *x, const double *y, const double *z,
+                        const double *vx, const double *vy, const double *vz, const double *wx,
+                        const double *wy, const double *wz, const double *r, const double *m,
+                        const double L[3], const int wall[3], double dt, double e, double mu,
+                        double *xo, double *yo, double *zo, double *vxo, double *vyo,
+                        double *vzo, double *wxo, double *wyo, double *wzo, int64_t *partner,
+                        double *tcoll, orc_stats *st) {
+  return orc_step_walls_core(n, x, y, z, vx, vy, vz, wx, wy, wz, r, m, L, wall, dt, e, mu, xo, yo,
+                             zo, vxo, vyo, vzo, wxo, wyo, wzo, partner, tcoll, st);
 }

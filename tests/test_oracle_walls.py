@@ -164,3 +164,41 @@ def test_storage_permutation_invariance():
     assert np.array_equal(np.where(rp.partner[inv] >= 0, perm[rp.partner[inv]], -1), res.partner)
     for f in FIELDS:
         assert np.array_equal(getattr(rp, f)[inv], getattr(res, f))
+
+
+def _spins(n, seed, scale=3.0):
+    return np.random.default_rng(seed).normal(size=(3, n)) * scale
+
+
+def test_walls_with_spin_reduce_to_each_part_bitwise():
+    box = workloads.make_box(3000, seed=6, phi=0.25, radius=0.5, e=0.8, dt=0.25)
+    w = _spins(box.n, 2)
+    # no wall: the periodic friction step
+    a, b = oracle.step_spin(box, w, 0.4), oracle.step_walls_spin(box, (0, 0, 0), w, 0.4)
+    assert np.array_equal(a.partner, b.partner)
+    for f in FIELDS + ("wx", "wy", "wz"):
+        assert np.array_equal(getattr(a, f).view(np.uint64), getattr(b, f).view(np.uint64)), f
+    # no friction: the frictionless walls step, spins unchanged
+    c, d = oracle.step_walls(box, (1, 0, 1)), oracle.step_walls_spin(box, (1, 0, 1), w, 0.0)
+    assert np.array_equal(c.partner, d.partner) and c.n_pairs > 50
+    for f in FIELDS:
+        assert np.array_equal(getattr(c, f).view(np.uint64), getattr(d, f).view(np.uint64)), f
+    for k, f in enumerate(("wx", "wy", "wz")):
+        assert np.array_equal(getattr(d, f), w[k])
+
+
+def test_walls_with_friction_pairs_and_reflections():
+    box = workloads.make_box(3000, seed=7, phi=0.25, radius=0.5, e=0.8, dt=0.25)
+    w = _spins(box.n, 3)
+    walls = (1, 1, 0)
+    res = oracle.step_walls_spin(box, walls, w, 0.5)
+    plain = oracle.step_walls(box, walls)
+    assert np.array_equal(res.partner, plain.partner)           # spins do not move contacts
+    free = res.partner < 0
+    for k, f in enumerate(("wx", "wy", "wz")):                    # walls leave spins alone
+        assert np.array_equal(getattr(res, f)[free], w[k][free])
+    # free spheres between walls move exactly as without friction (reflections included)
+    for f in FIELDS:
+        assert np.array_equal(getattr(res, f)[free], getattr(plain, f)[free])
+    hit = ~free
+    assert np.count_nonzero(res.wx[hit] != w[0][hit]) > 0.9 * hit.sum()
