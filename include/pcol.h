@@ -299,6 +299,17 @@ pcol_status pcol_step_walls(pcol_ctx *ctx, pcol_particles *p, const pcol_box *bo
                             const int32_t walls[3], double dt, double e, int32_t *partner,
                             double *tcoll, pcol_stats *stats);
 
+/* pcol_step_spin between reflective walls (walls as in pcol_step_walls): the
+ * friction resolve of pcol_step_spin with the separation and flight of
+ * pcol_step_walls.  An elastic wall changes no spin (its momentum change is
+ * zero, so the angular jump relation of Sec. "Intersection of Particles with
+ * Solid Walls" gives none).  Arguments, errors and synchronisation as
+ * pcol_step_spin. */
+pcol_status pcol_step_spin_walls(pcol_ctx *ctx, pcol_particles *p, double *wx, double *wy,
+                                 double *wz, const pcol_box *box, const int32_t walls[3],
+                                 double dt, double e, double mu, int32_t *partner, double *tcoll,
+                                 pcol_stats *stats);
+
 /* Adjoint of one pcol_step with its pair set held fixed (reverse mode; the
  * derivative of rule 4 and of the contact time of rule 1, which depends on the
  * start positions and velocities through |d + t u| = r_i + r_j).  For a

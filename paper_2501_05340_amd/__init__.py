@@ -123,6 +123,10 @@ def _load():
     lib.pcol_step_walls.argtypes = [ctx_p, P(pcol_particles), P(pcol_box), P(ctypes.c_int32),
                                     ctypes.c_double, ctypes.c_double, V, V, P(pcol_stats)]
     lib.pcol_step_walls.restype = ctypes.c_int
+    lib.pcol_step_spin_walls.argtypes = [ctx_p, P(pcol_particles), V, V, V, P(pcol_box),
+                                         P(ctypes.c_int32), ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, V, V, P(pcol_stats)]
+    lib.pcol_step_spin_walls.restype = ctypes.c_int
     lib.pcol_deposit.argtypes = [ctx_p, V, V, V, ctypes.c_int64, V, ctypes.c_int,
                                  P(ctypes.c_int32), P(ctypes.c_double), V]
     lib.pcol_deposit.restype = ctypes.c_int
@@ -134,7 +138,7 @@ lib = _load()
 EXPORTED = ["pcol_default_opts", "pcol_create", "pcol_destroy", "pcol_last_error",
             "pcol_set_stream", "pcol_bin", "pcol_detect", "pcol_resolve", "pcol_advance",
             "pcol_step", "pcol_step_spin", "pcol_step_backward", "pcol_step_batched",
-            "pcol_deposit", "pcol_step_walls"]
+            "pcol_deposit", "pcol_step_walls", "pcol_step_spin_walls"]
 
 
 class PcolError(RuntimeError):
@@ -471,4 +475,21 @@ def pcol_step_walls(ctx: Context, p: Particles, L, walls, dt: float, e: float, p
                                   float(dt), float(e), _ptr(partner, torch.int32, n),
                                   _ptr(tcoll, torch.float64, n),
                                   ctypes.byref(st) if st is not None else None))
+    return st.as_dict() if st is not None else None
+
+
+def pcol_step_spin_walls(ctx: Context, p: Particles, w, L, walls, dt: float, e: float, mu: float,
+                         partner=None, tcoll=None, stats: bool = True):
+    """pcol_step_spin between reflective walls on the axes where walls[k] is true; the
+    spins w = (wx, wy, wz) are updated in place.  Returns a dict of pcol_stats (or None)."""
+    n = p.n
+    st = pcol_stats() if stats else None
+    ctx.sync_stream()
+    ps = p.struct()
+    wp = [_ptr(t, torch.float64, n) for t in w]
+    wl = (ctypes.c_int32 * 3)(*[1 if v else 0 for v in walls])
+    ctx.check(lib.pcol_step_spin_walls(ctx.handle, ctypes.byref(ps), *wp, ctypes.byref(_box(L)),
+                                       wl, float(dt), float(e), float(mu),
+                                       _ptr(partner, torch.int32, n), _ptr(tcoll, torch.float64, n),
+                                       ctypes.byref(st) if st is not None else None))
     return st.as_dict() if st is not None else None

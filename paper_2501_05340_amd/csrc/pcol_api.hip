@@ -961,6 +961,21 @@ pcol_status pcol_step_spin(pcol_ctx *ctx, pcol_particles *p, double *wx, double 
   return st;
 }
 
+pcol_status pcol_step_spin_walls(pcol_ctx *ctx, pcol_particles *p, double *wx, double *wy,
+                                 double *wz, const pcol_box *box, const int32_t walls[3],
+                                 double dt, double e, double mu, int32_t *partner, double *tcoll,
+                                 pcol_stats *stats) {
+  if (!ctx) return PCOL_E_INVALID;
+  if (!walls) return fail(ctx, PCOL_E_INVALID, "null walls");
+  int mask = 0;
+  for (int a = 0; a < 3; ++a)
+    if (walls[a]) mask |= 1 << a;
+  ctx->walls = mask;
+  const pcol_status st = pcol_step_spin(ctx, p, wx, wy, wz, box, dt, e, mu, partner, tcoll, stats);
+  ctx->walls = 0;
+  return st;
+}
+
 pcol_status pcol_step_walls(pcol_ctx *ctx, pcol_particles *p, const pcol_box *box,
                             const int32_t walls[3], double dt, double e, int32_t *partner,
                             double *tcoll, pcol_stats *stats) {

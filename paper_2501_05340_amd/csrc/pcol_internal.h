@@ -307,8 +307,9 @@ __device__ __forceinline__ void resolve_one_spin(const Rec &a, const Rec &b, dou
   for (int k = 0; k < 3; ++k) {
     double v = va[k] + an * n[k];
     if (Jt != 0.0) v = v + at * tp[k];
-    out_v[k] = v;
-    out_x[k] = wrap_pos((xa[k] + t * va[k]) + rest * v, G.L[k]);
+    double vk = v;  // reflected on a wall axis (the spin is unchanged by an elastic wall)
+    out_x[k] = fly_axis((xa[k] + t * va[k]) + rest * v, G.L[k], (G.walls >> k) & 1, vk);
+    out_v[k] = vk;
     out_w[k] = wa[k];
   }
   if (Jt != 0.0) {

@@ -136,3 +136,31 @@ def test_walls_restitution_zero_and_errors(poly20k):
     assert ei.value.code == pc.PCOL_E_INVALID
     torch.cuda.synchronize()
     assert torch.equal(p.x[4:], x0[4:]) and torch.equal(p.vx, pc.Particles.from_box(box).vx)
+
+
+def _spin_step_walls(box, w, walls, mu):
+    p = pc.Particles.from_box(box)
+    wt = [torch.as_tensor(np.ascontiguousarray(w[k]), dtype=torch.float64).cuda() for k in range(3)]
+    ctx = pc.Context(max(box.n, 1))
+    partner = torch.empty(box.n, dtype=torch.int32, device="cuda")
+    tcoll = torch.empty(box.n, dtype=torch.float64, device="cuda")
+    st = pc.pcol_step_spin_walls(ctx, p, wt, box.L, walls, box.dt, box.e, mu, partner, tcoll)
+    torch.cuda.synchronize()
+    ws = np.stack([t.cpu().numpy() for t in wt])
+    return (to_host(p), partner.cpu().numpy().astype(np.int64), tcoll.cpu().numpy(), st), ws
+
+
+@pytest.mark.parametrize("case,walls,mu", [("config1", (1, 1, 1), 0.4), ("poly20k", (1, 0, 1), 0.1),
+                                           ("poly20k", (1, 1, 1), 5.0), ("config2", (1, 1, 1), 0.4),
+                                           ("poly20k", (0, 0, 0), 0.4)])
+def test_friction_between_walls_matches_oracle(poly20k, case, walls, mu):
+    box = {"config1": lambda: workloads.config(1), "poly20k": lambda: poly20k,
+           "config2": lambda: workloads.config(2)}[case]()
+    w = np.random.default_rng(box.n % 97).normal(size=(3, box.n)) / box.r
+    _announce(f"friction between walls {walls} {case} n={box.n} mu={mu}")
+    g, ws = _spin_step_walls(box, w, walls, mu)
+    orc = oracle.step_walls_spin(box, walls, w, mu)
+    assert orc.n_pairs > 0
+    assert compare_step(box, g, orc) == 0
+    ref = np.stack([orc.wx, orc.wy, orc.wz])
+    assert np.array_equal(ws.view(np.uint64), ref.view(np.uint64))
