@@ -12,9 +12,9 @@ region) before each step, so each step processes the same batch.
 Prints one JSON line: particles stepped per second (value), pair tests per
 second of the detect kernel, the detect kernel's ALU roofline fraction, and the
 CPU oracle timed on a bounded sample of the same workload.  Beside the plain
-FP64 path it reports the binary32 filter form and the fp16 Gram filter form on
-the matrix cores on the same input (both decide survivors by the binary64
-rule, so all three compute the same step bitwise), the batched form
+FP64 path it reports the binary32 filter form on the same input (it decides
+its survivors by the binary64 rule, so both compute the same step bitwise),
+the batched form
 (512 uneven boxes, about 8M spheres, one captured graph per step, against a
 loop of single-box steps) and the adjoint form (10-step rollout of 1M spheres,
 forward and backward).
@@ -425,9 +425,8 @@ def main():
     ap.add_argument("--n", type=int, default=0, help="override N (default 16M)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
-    ap.add_argument("--form", choices=["all", "fp64", "fp32", "gram"], default="all",
-                    help="filter form(s) to time: binary64, binary32 or the Gram filter on the "
-                         "matrix cores (value = fp64 when it runs)")
+    ap.add_argument("--form", choices=["all", "fp64", "fp32"], default="all",
+                    help="filter form(s) to time: binary64 or binary32 (value = fp64 when it runs)")
     ap.add_argument("--split-quantile", type=float, default=None,
                     help="extent split quantile of the single-box path (default: the library's)")
     ap.add_argument("--cell-mult", type=float, default=None,
@@ -495,11 +494,9 @@ def main():
         ctx.close()
         return out
 
-    # filter 0: binary64 Gram filter (the plain FP64 path); 1: binary32 filter;
-    # 2: fp16 Gram filter on the matrix cores.  Survivors of 1 and 2 go to the
-    # binary64 rule, so every form computes the same step bitwise.
-    specs = {"fp64": (0, args.split_quantile), "fp32": (1, args.split_quantile),
-             "gram": (2, 0.0 if args.split_quantile is None else args.split_quantile)}
+    # filter 0: binary64 Gram filter (the plain FP64 path); 1: binary32 filter whose
+    # survivors go to the binary64 rule, so both forms compute the same step bitwise.
+    specs = {"fp64": (0, args.split_quantile), "fp32": (1, args.split_quantile)}
     wanted = list(specs) if args.form == "all" else [args.form]
     forms = {k: run_form(k, *specs[k]) for k in wanted}
     main_form = "fp64" if "fp64" in forms else wanted[0]
@@ -511,8 +508,7 @@ def main():
     det_total = sum(det_ms) * 1e-3
     achieved = tests * OPS_PER_PAIR_TEST / det_total
     flops = tests * FLOPS_PER_PAIR_TEST / det_total
-    form_names = {"fp64": "plain_fp64 (binary64 Gram filter)", "fp32": "binary32 filter + binary64 rule",
-                  "gram": "fp16 Gram filter on matrix cores + binary64 rule"}
+    form_names = {"fp64": "plain_fp64 (binary64 Gram filter)", "fp32": "binary32 filter + binary64 rule"}
     out = {
         "metric": METRIC,
         "value": box.n * args.steps / wall,
@@ -539,7 +535,7 @@ def main():
                      "unit": "TOP/s", "frac": achieved / PEAK_FP64_OPS,
                      "traffic": measured_traffic() if main_form == "fp64" else None,
                      "traffic_unit": "bytes per launch",
-                     "kernel": "k_detect_half64g" if main_form != "gram" else "k_detect_gram",
+                     "kernel": "k_detect_half64g",
                      "note": f"FP64 vector operations (an FMA counts one): {OPS_PER_PAIR_TEST} per "
                              f"unordered pair test; as flops ({FLOPS_PER_PAIR_TEST} per test) "
                              f"{flops / 1e12:.2f} of 78.6 TFLOP/s"},
@@ -577,13 +573,6 @@ def main():
         }
         if name == "fp32":
             sub["band"] = sb[0]["band"]
-        if name == "gram":
-            # the 23-term dot product per pair (21 split products, alpha, beta) on the
-            # matrix cores against their dense fp16 peak
-            mf = tb * 2 * 23 / (sum(dmb) * 1e-3)
-            sub["roofline"] = {"bound": "mfma", "achieved": mf / 1e12, "peak": 2500.0,
-                               "unit": "TFLOP/s", "frac": mf / 2.5e15, "kernel": "k_detect_gram",
-                               "note": "46 fp16 flops per pair test (algorithmic)"}
         out[name + "_form"] = sub
     if not args.no_batched:
         out["batched_form"] = batched_leg(args, pc, torch)

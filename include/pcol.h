@@ -105,13 +105,15 @@ typedef struct {
   double cell_mult;   /* grid cell side >= reach * cell_mult, cell_mult >= 1 (default 1) */
   int max_sweeps;     /* 0: no cap (a step needs at most n/2 + 1 sweeps); pcol_step_batched:
                          sweeps captured in its graph (see there) */
-  int home_cells;     /* reserved, ignored: the sweep-1 detect runs one home cell per wave */
+  int home_cells;     /* consecutive home cells per workgroup of the sweep-1 pair test, whose
+                         filter survivors are decided together (0: automatic, 4 when the
+                         cells average under 24 spheres, else 1; at most 16).  Results do
+                         not depend on it. */
   int contact_slots;  /* contacts kept per sphere from the sweep-1 detect; spheres with more
                          fall back to an exact neighbourhood search (default 12) */
   int filter;         /* pair filter ahead of the exact rule (same results for every value):
-                         0 binary64 filter in Gram form; 1 binary32 filter, contact distance inflated by
-                         a band; 2 Gram filter on the matrix cores (fp16 high and low parts,
-                         fp32 accumulation).  Survivors of 1 and 2 are decided in binary64. */
+                         0 binary64 filter in Gram form; 1 binary32 filter, contact distance
+                         inflated by a band, survivors decided in binary64. */
   double band_rel;    /* FP32 filter safety band, relative to r_i + r_j (default 1e-4) */
   int timing;         /* 1: time kernels with HIP events; times land in pcol_stats */
   int autotune;       /* pcol_step_batched: 1 = pick cell size and workgroup shape by timing
@@ -130,9 +132,10 @@ typedef struct {
                             plus the separate search of the spheres above the split extent) */
   int64_t contacts;      /* unordered pairs with a contact within dt (sweep 1) */
   int64_t n_overflow;    /* spheres whose contacts exceeded contact_slots */
-  int64_t n_recheck;     /* survivors of filter 1 or 2 decided by the binary64 rule */
+  int64_t n_recheck;     /* survivors of filter 1 decided by the binary64 rule */
   int32_t nc[3];         /* grid cells per axis */
-  int32_t home_cells;    /* home cells per workgroup used */
+  int32_t home_cells;    /* home cells per workgroup of the sweep-1 pair test (0: the exact
+                            per-sphere search of a box with fewer than 3 cells on an axis) */
   int32_t max_cell;      /* largest cell occupancy */
   double h[3];           /* grid cell side per axis */
   double reach;          /* 2 max r + 2 max|v| dt */

@@ -8,7 +8,10 @@ it, and the two share no code.
 
 Pins of this oracle against the paper and the mathematics are in
 ``tests/test_oracle_pins.py``; the forward-mode derivative ``step_jvp`` is
-pinned in ``tests/test_oracle_jvp.py``.
+pinned in ``tests/test_oracle_jvp.py``, the per-sphere search
+``earliest_subset`` in ``tests/test_oracle_subset.py``, and the friction,
+walls, deposition and literal-order functions in their own
+``tests/test_oracle_*.py``.
 """
 from __future__ import annotations
 

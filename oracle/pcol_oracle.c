@@ -320,7 +320,8 @@ int orc_earliest(int64_t n, const double *x, const double *y, const double *z, c
 /*
  * The same earliest-partner rule as orc_earliest, evaluated only for the
  * spheres listed in idx[0..nsub) (over all active candidates, grid search).
- * Used to check large inputs at sampled spheres.
+ * Used to check large inputs at sampled spheres.  Entries that are inactive
+ * or outside [0, n) get partner -1 and time +inf.
  */
 int orc_earliest_subset(int64_t n, const double *x, const double *y, const double *z,
                         const double *vx, const double *vy, const double *vz, const double *r,

@@ -94,6 +94,7 @@ struct pcol_ctx {
   int maxcell = 0;
   bool small = false;  // some axis has fewer than 3 cells
   bool detect_timed = false;
+  int cpw_used = 0;  // home cells per workgroup of the last sweep-1 detect (0: exact search)
   struct BatchPlan *bp = nullptr;  // batched form (pcol_step_batched)
 };
 
@@ -281,9 +282,10 @@ pcol_status pcol_create(pcol_ctx **out, int64_t n_max, void *hip_stream, const p
   if (opts) ctx->opts = *opts;
   if (!(ctx->opts.cell_mult >= 1.0) || !isfinite(ctx->opts.cell_mult) ||
       ctx->opts.max_sweeps < 0 || ctx->opts.contact_slots < 0 || ctx->opts.contact_slots > 64 ||
+      ctx->opts.home_cells < 0 || ctx->opts.home_cells > 16 ||
       !(ctx->opts.band_rel >= 0.0) ||
       !(ctx->opts.split_quantile >= 0.0 && ctx->opts.split_quantile <= 1.0) ||
-      ctx->opts.filter < 0 || ctx->opts.filter > 2) {
+      ctx->opts.filter < 0 || ctx->opts.filter > 1) {
     delete ctx;
     return PCOL_E_INVALID;
   }
@@ -561,37 +563,6 @@ static double gram64_tolerance(double h, double R, double V, double r, double Lm
   return 2.0 * (E0 + Epos + E);
 }
 
-// Tolerance of the Gram filter (filter 2).  For a pair the rule keeps, the
-// real value F = c + b dt2 is at most E0 = 3 eps ((reach^2 + (2 r_max)^2) +
-// reach 2 v_max dt2) (the binary64 argument of the FMA filter), so the filter
-// must pass every pair whose evaluated F exceeds the real one by less than its
-// rounding error E.  With positions relative to the home cell centre, a home
-// sphere has |x_i| <= X_i = (sqrt 3 / 2) h and a kept partner |x_j| <= X_j =
-// X_i + reach, |v| <= v_max, r <= r_max (first-layer values), so
-//   |alpha| <= A_ = X_i^2 + dt2 X_i v + r^2,  |beta| <= B_ = X_j^2 + dt2 X_j v + r^2,
-//   S = sum_k |P_k Q_k| <= X_j (2 X_i + dt2 v) + v dt2 X_i + 2 r^2.
-// Each of P, Q, alpha, beta is rounded to binary32 (2^-24) and represented by
-// fp16 high and low parts to within 2^-22 of itself (fp16 subnormals are kept
-// by the conversions and the matrix cores); the product drops Q_lo P_lo
-// (2^-22); fp32 accumulation of the 32 exact products adds at most
-// 32 2^-24 (A_ + B_ + S).  So E <= 2^-24 (4 (A_ + B_) + 13 S) + 2^-19 (A_ + B_ + S)
-// and the tolerance is 2 (E + E0).
-static float gram_tolerance(const pcol_ctx *ctx, double dt2) {
-  double h = ctx->h[0];
-  for (int a = 1; a < 3; ++a) h = ctx->h[a] > h ? ctx->h[a] : h;
-  const double s3 = sqrt(3.0);
-  const double Xi = 0.5 * s3 * h * (1.0 + 1e-6), R = ctx->reach_pass;
-  const double Xj = Xi + R, V = ctx->vmax_pass, r = ctx->rmax_pass;
-  const double Ab = Xi * Xi + dt2 * Xi * V + r * r, Bb = Xj * Xj + dt2 * Xj * V + r * r;
-  const double S = Xj * (2.0 * Xi + dt2 * V) + V * dt2 * Xi + 2.0 * r * r;
-  const double eps = 0x1.0p-53;
-  const double E0 = 3.0 * eps * ((R * R + 4.0 * r * r) + R * 2.0 * V * dt2);
-  const double E = 0x1.0p-24 * (4.0 * (Ab + Bb) + 13.0 * S) + 0x1.0p-19 * (Ab + Bb + S);
-  float tol = (float)(2.0 * (E + E0));
-  if ((double)tol < 2.0 * (E + E0)) tol = nextafterf(tol, INFINITY);
-  return tol;
-}
-
 // sweep 1: keys of all spheres (all active) into ctx->key_j / key_t (sorted order)
 static pcol_status detect_all(pcol_ctx *ctx, double dt) {
   hipStream_t s = ctx->stream;
@@ -608,9 +579,11 @@ static pcol_status detect_all(pcol_ctx *ctx, double dt) {
     DetectArgs A{};
     A.cellc = ctx->cellc;
     // sparse cells (the split grid holds about 13 spheres per cell at 16M): four
-    // cells per workgroup for the binary64 and binary32 filters, so their
-    // survivors are decided together
-    A.cpw = ctx->opts.filter != 2 && n < 24 * (int64_t)ctx->G.ncell ? 4 : 1;
+    // cells per workgroup, so their survivors are decided together; opts.home_cells
+    // overrides the choice
+    A.cpw = ctx->opts.home_cells > 0 ? ctx->opts.home_cells
+                                     : (n < 24 * (int64_t)ctx->G.ncell ? 4 : 1);
+    ctx->cpw_used = A.cpw;
     A.rec = ctx->rec;
     A.start = ctx->start;
     A.cnt = ctx->cnt;
@@ -640,9 +613,6 @@ static pcol_status detect_all(pcol_ctx *ctx, double dt) {
     A.K = ctx->K;
     A.rec32 = ctx->rec32;
     A.fp32 = ctx->opts.filter == 1;
-    A.gram = ctx->opts.filter == 2;
-    A.crowd = ctx->count;  // free after the binning
-    A.tolg = A.gram ? gram_tolerance(ctx, A.dt2) : 0.0f;
     // the FP32 filter reads its home records from an LDS copy of the home cell
     // (when the largest cell fits in 20 KB); the FP64 filter reads them through
     // the scalar cache, which measured faster for 64-B records
@@ -670,6 +640,7 @@ static pcol_status detect_all(pcol_ctx *ctx, double dt) {
                                  ctx->G, dt, ctx->status, ctx->key_j, ctx->key_t, nullptr));
   } else {
     // fewer than 3 cells on some axis: exact search for every sphere
+    ctx->cpw_used = 0;
     PCOL_HIP(launch_gather_exact(s, nullptr, n, nullptr, -1, ctx->rec, ctx->start, ctx->G, dt,
                                  ctx->status, ctx->key_j, ctx->key_t, nullptr));
   }
@@ -926,7 +897,7 @@ static pcol_status step_impl(pcol_ctx *ctx, pcol_particles *p, const pcol_box *b
       stats->h[a] = ctx->h[a];
     }
     stats->max_cell = ctx->maxcell;
-    stats->home_cells = 1;
+    stats->home_cells = ctx->cpw_used;
     stats->reach = ctx->reach;
     stats->n_wide = ctx->n_wide;
     stats->rho_c = ctx->split ? ctx->rho_c : 0.0;

@@ -117,8 +117,7 @@ struct alignas(128) CounterShard {
 struct SweepCounters {
   CounterShard shard[NSHARD];
   unsigned int n_overflow;  // spheres with more contacts than slots (list length)
-  unsigned int n_crowd;     // cells queued for the binary64 filter by the Gram kernel
-  unsigned int pad[30];
+  unsigned int pad[31];
 };
 
 // ---------------------------------------------------------------- the rule
@@ -357,7 +356,7 @@ struct BatchDev {
   int nbox;
 };
 
-// Pair tests and filter survivors of one home cell (k_detect_half, k_detect_gram).
+// Pair tests and filter survivors of one workgroup of the k_detect_half kernels.
 struct CellCount {
   unsigned long long tests, recheck;
 };
@@ -385,9 +384,6 @@ struct DetectArgs {
   int fp32;           // FP32 filter + FP64 recheck
   float kband;        // FP32 filter: contact distance inflated to s * kband
   float dt2f;         // FP32 filter: 2 dt (1 + 2^-12)
-  int gram;           // half-precision Gram filter on the matrix cores + FP64 recheck
-  float tolg;         // its tolerance (bound on its rounding, see gram_tolerance)
-  int *crowd;         // Gram filter: cells of more than GRAM_ROWS spheres, for the FP64 filter
   CellCount *cellc;   // per workgroup of the one-box detect kernels (G.ncell entries)
   int cpw;            // binary64 filter: home cells per workgroup (1: one cell per wave)
 };

@@ -976,219 +976,8 @@ __global__ __launch_bounds__(WAVE, 5) void k_detect_half64g(DetectArgs A) {
 // persistent binary64 kernel a multiple of 8 (the XCDs) near the waves the
 // chip holds at once.  Also the number of per-workgroup counts it writes.
 int detect_half_blocks(const DetectArgs &A) {
-  if (A.gram || A.cpw <= 1) return A.G.ncell;
+  if (A.cpw <= 1) return A.G.ncell;
   return (A.G.ncell + A.cpw - 1) / A.cpw;
-}
-
-// ---------------------------------------------------------------- a5, Gram filter on the matrix cores
-
-// The filter value of a pair, F = |d|^2 - s^2 + dt2 (d . u) with d = x_j - x_i,
-// u = v_j - v_i, s = r_i + r_j, splits into a term of i, a term of j and one
-// dot product of 7-vectors (positions relative to the home cell centre):
-//   F = alpha_i + beta_j + <P_j, Q_i>,
-//   P_j = (x_j, v_j, r_j),  Q_i = (-2 x_i - dt2 v_i, -dt2 x_i, -2 r_i),
-//   alpha_i = |x_i|^2 + dt2 x_i.v_i - r_i^2,  beta_j = |x_j|^2 + dt2 x_j.v_j - r_j^2.
-// For a home cell (rows i, 16 per tile) against a chunk of 64 candidates
-// (columns j, 4 tiles of 16) it is one dense 16 x 16 x 32 product on the
-// matrix cores.  Every quantity is split into fp16 high and low parts and the
-// K = 32 slots of a row (home) and a column (candidate) hold
-//   slice 0: Q_hi, alpha_hi  |  P_hi, 1          (Q_hi.P_hi + alpha_hi)
-//   slice 1: Q_lo, alpha_lo  |  P_hi, 1          (Q_lo.P_hi + alpha_lo)
-//   slice 2: Q_hi, 1         |  P_lo, beta_hi    (Q_hi.P_lo + beta_hi)
-//   slice 3: 0..0, 1         |  0..0, beta_lo    (beta_lo)
-// accumulated in fp32 from zero.  A pair passes iff the result is <= tolg, a
-// bound on every rounding of this evaluation for pairs the rule can keep
-// (host, gram_tolerance); survivors are decided by the rule, so the result is
-// exactly the rule's.  Rows without a home sphere and columns without a
-// candidate carry alpha or beta = 60000, far above any pass.
-typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
-typedef float float4_t __attribute__((ext_vector_type(4)));
-
-constexpr int GRAM_ROWS = 64;         // home spheres per cell on this path (4 row tiles)
-constexpr float GRAM_NONE = 60000.0f;  // alpha / beta of an empty row / column (fp16 finite)
-
-struct GramLds {
-  half8_t hi[WAVE];   // candidate (P_hi, 1)
-  half8_t lo[WAVE];   // candidate (P_lo, beta_hi)
-  half8_t bl[WAVE];   // candidate (0, ..., 0, beta_lo)
-  int gj[WAVE];       // candidate sorted index
-  int thr[WAVE];      // -1: no candidate; own cell: its index; else INT_MAX
-};
-
-// fp16 high part of v and the fp16 of the remainder, through binary32 (v is
-// already a small relative quantity, so binary32 holds it to 2^-24)
-__device__ __forceinline__ void split_half(float v, _Float16 &hi, _Float16 &lo) {
-  hi = (_Float16)v;
-  lo = (_Float16)(v - (float)hi);
-}
-
-__device__ __forceinline__ void detect_cell_gram(const DetectArgs &A, const Grid &G,
-                                                 const int *start, int cell, SurvivorQueue &Q,
-                                                 GramLds &S) {
-  CellRuns R;
-  if (!cell_runs(G, start, cell, R)) return;
-  const int h0 = R.h0, h1 = R.h1, nh = h1 - h0;
-  if (nh > GRAM_ROWS) {  // a crowded cell: queued for the binary64 filter (k_detect_list)
-    if (__lane_id() == 0) A.crowd[atomicAdd(&A.ctr->n_crowd, 1u)] = cell;
-    return;
-  }
-  const int lane = __lane_id();
-  const int slice = lane >> 4;  // k slice of the operands, row group of the result
-  const double ox = (R.cx + 0.5) * G.h[0], oy = (R.cy + 0.5) * G.h[1], oz = (R.cz + 0.5) * G.h[2];
-  const double dt2 = A.dt2;
-  const int nrt = (nh + 15) >> 4;
-  const _Float16 one = (_Float16)1.0f, zero = (_Float16)0.0f;
-  // home operand of row tile rt: homes 16 rt .. 16 rt + 15 (see the K layout above)
-  half8_t afr[4];
-#pragma unroll
-  for (int rt = 0; rt < 4; ++rt) {
-    half8_t f;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) f[k] = zero;
-    const int row = 16 * rt + (lane & 15);
-    if (rt < nrt) {
-      float q[7];
-      float alpha = GRAM_NONE;
-      if (row < nh) {
-        const Rec a = A.rec[h0 + row];
-        const double xh = a.x - ox, yh = a.y - oy, zh = a.z - oz;
-        q[0] = (float)(-2.0 * xh - dt2 * a.vx);
-        q[1] = (float)(-2.0 * yh - dt2 * a.vy);
-        q[2] = (float)(-2.0 * zh - dt2 * a.vz);
-        q[3] = (float)(-dt2 * xh);
-        q[4] = (float)(-dt2 * yh);
-        q[5] = (float)(-dt2 * zh);
-        q[6] = (float)(-2.0 * a.r);
-        alpha = (float)(((xh * xh + yh * yh) + zh * zh) +
-                        dt2 * ((xh * a.vx + yh * a.vy) + zh * a.vz) - a.r * a.r);
-      } else {
-#pragma unroll
-        for (int k = 0; k < 7; ++k) q[k] = 0.0f;
-      }
-      if (slice < 3) {
-#pragma unroll
-        for (int k = 0; k < 7; ++k) {
-          _Float16 hi, lo;
-          split_half(q[k], hi, lo);
-          f[k] = slice == 1 ? lo : hi;
-        }
-        _Float16 ahi, alo;
-        split_half(alpha, ahi, alo);
-        f[7] = slice == 0 ? ahi : (slice == 1 ? alo : one);
-      } else {
-        f[7] = one;
-      }
-    }
-    afr[rt] = f;
-  }
-  int total = 0;
-  int pre[MAXRUN];
-#pragma unroll
-  for (int k = 0; k < MAXRUN; ++k) {
-    pre[k] = total;
-    total += R.rl[k];
-  }
-  Q.tests += (unsigned long long)nh * (unsigned long long)(total - nh) +
-             (unsigned long long)nh * (unsigned long long)(nh - 1) / 2ull;
-  for (int base = 0; base < total; base += WAVE) {
-    // the lane's candidate, as in detect_cell
-    const int v = base + lane;
-    int g = 0, code = run_code(0, 0, 0, 0);
-    bool ok = false;
-#pragma unroll
-    for (int k = 0; k < MAXRUN; ++k) {
-      if (v >= pre[k] && v < pre[k] + R.rl[k]) {
-        g = R.rg[k] + (v - pre[k]);
-        code = R.rc[k];
-        ok = true;
-      }
-    }
-    const bool own = (code >> 6) & 1;
-    const int thr = !ok ? -1 : (own ? g : 0x7fffffff);
-    half8_t ph, pl, pb;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      ph[k] = zero;
-      pl[k] = zero;
-      pb[k] = zero;
-    }
-    float beta = GRAM_NONE;
-    if (thr >= 0) {
-      const Rec b = A.rec[g];
-      const double xj = (b.x + code_shift(code & 3, G.sL[0])) - ox;
-      const double yj = (b.y + code_shift((code >> 2) & 3, G.sL[1])) - oy;
-      const double zj = (b.z + code_shift((code >> 4) & 3, G.sL[2])) - oz;
-      const float p[7] = {(float)xj, (float)yj, (float)zj, (float)b.vx, (float)b.vy, (float)b.vz,
-                          (float)b.r};
-#pragma unroll
-      for (int k = 0; k < 7; ++k) {
-        _Float16 hi, lo;
-        split_half(p[k], hi, lo);
-        ph[k] = hi;
-        pl[k] = lo;
-      }
-      beta = (float)(((xj * xj + yj * yj) + zj * zj) + dt2 * ((xj * b.vx + yj * b.vy) + zj * b.vz) -
-                     b.r * b.r);
-    }
-    ph[7] = one;
-    {
-      _Float16 hi, lo;
-      split_half(beta, hi, lo);
-      pl[7] = hi;
-      pb[7] = lo;
-    }
-    // one wave owns S: its LDS writes reach its later reads in order
-    S.hi[lane] = ph;
-    S.lo[lane] = pl;
-    S.bl[lane] = pb;
-    S.gj[lane] = g;
-    S.thr[lane] = thr;
-#pragma unroll 1
-    for (int t = 0; t < 4; ++t) {
-      const int c = 16 * t + (lane & 15);  // the candidate column this lane feeds and reads
-      const half8_t bfr = slice == 3 ? S.bl[c] : (slice == 2 ? S.lo[c] : S.hi[c]);
-#pragma unroll
-      for (int rt = 0; rt < 4; ++rt) {
-        if (rt < nrt) {
-          const float4_t z4 = {0.0f, 0.0f, 0.0f, 0.0f};
-          const float4_t d = __builtin_amdgcn_mfma_f32_16x16x32_f16(afr[rt], bfr, z4, 0, 0, 0);
-          const bool p0 = d[0] <= A.tolg, p1 = d[1] <= A.tolg, p2 = d[2] <= A.tolg,
-                     p3 = d[3] <= A.tolg;
-          if (__ballot(p0 || p1 || p2 || p3)) {  // rare: queue this tile's survivors
-            if (Q.n > Q.cap - 4 * WAVE) flush_survivors(A, G, Q);
-            const int gc = S.gj[c], tc = S.thr[c];
-            const int i0 = h0 + 16 * rt + 4 * slice;
-            (void)push_survivor(p0 && i0 < tc, i0, gc, Q);
-            (void)push_survivor(p1 && i0 + 1 < tc, i0 + 1, gc, Q);
-            (void)push_survivor(p2 && i0 + 2 < tc, i0 + 2, gc, Q);
-            (void)push_survivor(p3 && i0 + 3 < tc, i0 + 3, gc, Q);
-          }
-        }
-      }
-    }
-  }
-  flush_survivors(A, G, Q);
-}
-
-__global__ __launch_bounds__(WAVE) void k_detect_gram(DetectArgs A) {
-  __shared__ int2 survq[2 * QCAP];
-  __shared__ GramLds S;
-  SurvivorQueue Q{survq, 0, 0u, 2 * QCAP, 0ull};
-  detect_cell_gram(A, A.G, A.start, xcd_remap(blockIdx.x, gridDim.x), Q, S);
-  if (__lane_id() == 0) A.cellc[blockIdx.x] = CellCount{Q.tests, (unsigned long long)Q.pushed};
-}
-
-// The cells the Gram kernel queued as crowded, through the binary64 filter;
-// one wave per cell over the device-counted list.
-__global__ __launch_bounds__(WAVE) void k_detect_list(DetectArgs A) {
-  __shared__ int2 survq[QCAP];
-  SurvivorQueue Q{survq, 0, 0u, QCAP, 0ull};
-  __shared__ HomeQ hq[WAVE];
-  const int count = (int)A.ctr->n_crowd;
-  for (int w = blockIdx.x; w < count; w += gridDim.x)
-    detect_cell64(A, A.G, A.start, A.crowd[w], Q, hq);
-  flush_survivors(A, A.G, Q);
-  if (__lane_id() == 0 && Q.tests) atomicAdd(&A.ctr->shard[blockIdx.x % NSHARD].tests, Q.tests);
 }
 
 // Box of a global cell number: the last b with cell_base[b] <= c.
@@ -1229,7 +1018,7 @@ __global__ __launch_bounds__(256) void k_detect_batched(DetectArgs A, BatchDev B
   }
 }
 
-// Sum of the per-cell counts of k_detect_half / k_detect_gram (a few cells per
+// Sum of the per-cell counts of the k_detect_half kernels (a few cells per
 // thread, so the loads of a thread are few and in flight together; one atomic
 // per workgroup and counter, spread over the shards).
 __global__ __launch_bounds__(256) void k_cell_counts(const CellCount *c, int n,
@@ -1253,13 +1042,6 @@ hipError_t launch_cell_counts(hipStream_t s, const CellCount *c, int n, SweepCou
 
 hipError_t launch_detect_half(hipStream_t s, const DetectArgs &A) {
   if (A.G.ncell <= 0) return hipSuccess;
-  if (A.gram) {
-    hipLaunchKernelGGL(k_detect_gram, dim3(A.G.ncell), dim3(WAVE), 0, s, A);
-    // crowded cells: at most ncell, usually none (the kernel exits at once)
-    const int blocks = A.G.ncell < 1024 ? A.G.ncell : 1024;
-    hipLaunchKernelGGL(k_detect_list, dim3(blocks), dim3(WAVE), 0, s, A);
-    return hipGetLastError();
-  }
   const size_t lds = (size_t)A.cap * (A.fp32 ? sizeof(Rec32) : sizeof(Rec));
   if (A.cap > 0) {
     if (A.fp32)

@@ -84,5 +84,29 @@ def step(x, v, r, m, L, dt, e):
             active[i] = active[j] = False
 
 
+def earliest(box, active=None):
+    """Earliest partner (index or -1) and contact time (inf if none) of every active
+    sphere of a workloads.Box over the active set, all pairs, tiny N only."""
+    n = box.n
+    x = [(float(box.x[i]), float(box.y[i]), float(box.z[i])) for i in range(n)]
+    v = [(float(box.vx[i]), float(box.vy[i]), float(box.vz[i])) for i in range(n)]
+    act = [True] * n if active is None else [bool(a) for a in active]
+    partner, tmin = [-1] * n, [math.inf] * n
+    for i in range(n):
+        if not act[i]:
+            continue
+        best = None
+        for j in range(n):
+            if j == i or not act[j]:
+                continue
+            t = contact_time(x[i], v[i], box.r[i], x[j], v[j], box.r[j], box.L, box.dt)
+            if t is not None and (best is None or (t, j) < best):
+                best = (t, j)
+        if best is not None:
+            tmin[i], partner[i] = best
+    import numpy as np
+    return np.array(partner, dtype=np.int64), np.array(tmin)
+
+
 def kinetic_energy(m, vx, vy, vz):
     return 0.5 * math.fsum(m[i] * (vx[i] ** 2 + vy[i] ** 2 + vz[i] ** 2) for i in range(len(m)))

@@ -3,6 +3,7 @@ entry point declared in include/pcol.h (no compute calls here)."""
 import ctypes
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -64,3 +65,39 @@ def test_struct_layouts_match_header(lib):
     assert o.max_sweeps == 0 and o.filter == 0 and o.timing == 0
     assert ctypes.sizeof(pc.pcol_particles) == 8 + 8 * 8
     assert ctypes.sizeof(pc.pcol_box) == 24
+
+
+def _c_layouts(tmp_path, structs):
+    """sizeof and offsetof of every field of the named structs, as a C compiler lays
+    them out from include/pcol.h (gcc, host ABI)."""
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "pcol.h"', "int main(void) {"]
+    for name, fields in structs.items():
+        lines.append(f'  printf("{name} sizeof %zu\\n", sizeof({name}));')
+        for f in fields:
+            lines.append(f'  printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                           str(src), "-o", str(exe)])
+    out = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        name, field, value = line.split()
+        out[(name, field)] = int(value)
+    return out
+
+
+def test_every_struct_layout_matches_the_c_header(tmp_path):
+    """Each ctypes structure of the binding has the size and field offsets that the C
+    header gives a C compiler (pcol_opts, pcol_stats, pcol_batch_stats, pcol_particles,
+    pcol_box, pcol_state_grad)."""
+    import paper_2501_05340_amd as pc
+    structs = {"pcol_opts": pc.pcol_opts, "pcol_stats": pc.pcol_stats,
+               "pcol_batch_stats": pc.pcol_batch_stats, "pcol_particles": pc.pcol_particles,
+               "pcol_box": pc.pcol_box, "pcol_state_grad": pc.pcol_state_grad}
+    c = _c_layouts(tmp_path, {k: [f for f, _ in v._fields_] for k, v in structs.items()})
+    for name, cls in structs.items():
+        assert c[(name, "sizeof")] == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert c[(name, field)] == getattr(cls, field).offset, (name, field)

@@ -131,8 +131,8 @@ def test_16M_sampled_keys_and_step_properties(big):
     fp, _ = oracle.earliest_subset(box, probe, active=(~hit).astype(np.uint8))
     assert np.all(fp < 0)
 
-    # the binary32 and Gram filter forms give the same step bitwise
-    for flt in (1, 2):
+    # the binary32 filter form gives the same step bitwise
+    for flt in (1,):
         print(f"[gpu-test] 16M step, filter {flt}", flush=True)
         out32, partner32, tcoll32, st32 = _step(box, p0, flt)
         assert np.array_equal(partner32, partner)

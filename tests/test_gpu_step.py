@@ -253,12 +253,12 @@ def test_error_codes_leave_inputs_unchanged():
 # ---------------------------------------------------------------- FP32 filter + FP64 recheck form
 
 
-@pytest.mark.parametrize("flt", [1, 2])
+@pytest.mark.parametrize("flt", [1])
 @pytest.mark.parametrize("which", ["config1", "config2", "poly20k", "small"])
 def test_filter_forms_match_oracle(which, flt, cfg2, poly20k):
-    """The binary32 filter (1) and the Gram filter on the matrix cores (2) pass
-    every pair the binary64 rule can keep and the survivors are decided in
-    binary64, so pair sets, times and states equal the oracle's exactly."""
+    """The binary32 filter (1) passes every pair the binary64 rule can keep and
+    its survivors are decided in binary64, so pair sets, times and states equal
+    the oracle's exactly."""
     if which == "config1":
         box = workloads.config(1)
     elif which == "config2":
@@ -278,7 +278,7 @@ def test_filter_forms_match_oracle(which, flt, cfg2, poly20k):
             assert st["band"] >= 1e-4
 
 
-@pytest.mark.parametrize("flt", [1, 2])
+@pytest.mark.parametrize("flt", [1])
 @pytest.mark.parametrize("q", [0.0, 0.99])
 def test_filter_forms_equal_plain_form_bitwise(poly20k, flt, q):
     a = gpu_step(poly20k, split_quantile=q)
@@ -289,15 +289,20 @@ def test_filter_forms_equal_plain_form_bitwise(poly20k, flt, q):
     assert a[3]["contacts"] == b[3]["contacts"]
 
 
-def test_gram_filter_crowded_cells_fall_back(poly20k):
-    """Cells of more than 64 spheres (a coarse grid) take the binary64 filter
-    inside the Gram kernel; the step is unchanged."""
-    a = gpu_step(poly20k, cell_mult=2.5, split_quantile=0.0)
-    b = gpu_step(poly20k, cell_mult=2.5, split_quantile=0.0, filter=2)
-    assert b[3]["max_cell"] > 64
-    for f in FIELDS:
-        assert np.array_equal(a[0][f].view(np.uint64), b[0][f].view(np.uint64))
-    assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2], equal_nan=True)
+@pytest.mark.parametrize("flt", [0, 1])
+def test_home_cells_per_workgroup_invariance(poly20k, flt):
+    """opts.home_cells (consecutive home cells per workgroup of the pair test) does
+    not change any result bit, and pcol_stats reports the value used."""
+    a = gpu_step(poly20k, filter=flt)
+    ncell = a[3]["nc"][0] * a[3]["nc"][1] * a[3]["nc"][2]
+    assert a[3]["home_cells"] == (4 if poly20k.n < 24 * ncell else 1)  # automatic choice
+    for hc in (1, 2, 3, 8, 16):
+        b = gpu_step(poly20k, filter=flt, home_cells=hc)
+        assert b[3]["home_cells"] == hc
+        for f in FIELDS:
+            assert np.array_equal(a[0][f].view(np.uint64), b[0][f].view(np.uint64))
+        assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2], equal_nan=True)
+        assert a[3]["pair_tests"] == b[3]["pair_tests"]
 
 
 def _chain(n=40, lines=1):

@@ -54,7 +54,7 @@ def test_walls_match_oracle(poly20k, case, walls):
     assert compare_step(box, g, orc) == 0
 
 
-@pytest.mark.parametrize("opts", [{"filter": 1}, {"filter": 2}, {"contact_slots": 1},
+@pytest.mark.parametrize("opts", [{"filter": 1}, {"home_cells": 2}, {"contact_slots": 1},
                                   {"split_quantile": 0.9}, {"split_quantile": 0.0}])
 def test_walls_every_filter_and_search_path(poly20k, opts):
     walls = (1, 0, 1)
