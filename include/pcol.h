@@ -81,8 +81,10 @@ typedef enum {
   PCOL_E_NOMEM = 3,   /* device allocation failed */
   PCOL_E_HIP = 4,     /* a HIP runtime call failed; see pcol_last_error */
   PCOL_E_SWEEPS = 5,  /* opts.max_sweeps sweeps ran and the last still resolved pairs */
-  PCOL_E_STATE = 6    /* call order: pcol_detect / pcol_resolve before pcol_bin, or for a
+  PCOL_E_STATE = 6,   /* call order: pcol_detect / pcol_resolve before pcol_bin, or for a
                          different particle count than the last pcol_bin */
+  PCOL_E_SCRATCH = 7  /* pcol_deposit_noalloc: the input needs more than the library's
+                         fixed device scratch (PCOL_NOALLOC_SCRATCH_BYTES) */
 } pcol_status;
 
 /* The spheres.  x, y, z in [0, len_k); r > 0 (radius: the paper's diameter is 2r);
@@ -369,6 +371,33 @@ pcol_status pcol_step_backward(pcol_ctx *ctx, const pcol_particles *start, const
 pcol_status pcol_deposit(pcol_ctx *ctx, const double *x, const double *y, const double *z,
                          int64_t n, const double *a, int comp, const int32_t nc[3],
                          const double len[3], double *out);
+
+/* Size of the fixed device scratch of pcol_deposit_noalloc (per GPU). */
+#define PCOL_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* pcol_deposit for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same operation, kernels and results (bitwise equal to pcol_deposit on the
+ * same input, up to the order of more than 64 spheres in one element), without
+ * a context and without any allocation: no hipMalloc, hipFree, pinned host
+ * memory or other allocating call.  Its scratch is a fixed array of
+ * PCOL_NOALLOC_SCRATCH_BYTES in device memory, one per GPU, which the library
+ * holds from the first call on that GPU until the process ends.  The input must
+ * fit: with R = 16 ceil((4 + comp) / 2) bytes per record and ne = nc_0 nc_1
+ * nc_2 elements, each rounded up to 256 B, the scratch holds 4n + 4n + Rn +
+ * 4(ne + 1) + 4(ne + 1) + 4(ne / 4096 + 2) + 64 comp ne + 8,232 + 4 bytes
+ * (about 72n + 264ne for comp = 4); a larger input returns PCOL_E_SCRATCH before
+ * any work, out unchanged.
+ *   hip_stream: the hipStream_t to enqueue on (NULL: the default stream) on the
+ *   current device.  Other arguments, checks and errors as pcol_deposit; the
+ *   position check is read back into host memory, so the call synchronises with
+ *   the stream.  Every call on one GPU uses that GPU's one scratch array (the
+ *   counts it needs zeroed are cleared by each call): calls that overlap in time
+ *   on one GPU, from several threads or on several streams, race and must not
+ *   be made.  Returns PCOL_OK, PCOL_E_INVALID, PCOL_E_SCRATCH or PCOL_E_HIP. */
+pcol_status pcol_deposit_noalloc(const double *x, const double *y, const double *z, int64_t n,
+                                 const double *a, int comp, const int32_t nc[3],
+                                 const double len[3], double *out, void *hip_stream);
 
 #ifdef __cplusplus
 }

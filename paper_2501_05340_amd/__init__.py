@@ -22,9 +22,11 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpcol.so")
 
-PCOL_OK, PCOL_E_INVALID, PCOL_E_BOX, PCOL_E_NOMEM, PCOL_E_HIP, PCOL_E_SWEEPS, PCOL_E_STATE = range(7)
+(PCOL_OK, PCOL_E_INVALID, PCOL_E_BOX, PCOL_E_NOMEM, PCOL_E_HIP, PCOL_E_SWEEPS, PCOL_E_STATE,
+ PCOL_E_SCRATCH) = range(8)
 STATUS_NAMES = {0: "PCOL_OK", 1: "PCOL_E_INVALID", 2: "PCOL_E_BOX", 3: "PCOL_E_NOMEM",
-                4: "PCOL_E_HIP", 5: "PCOL_E_SWEEPS", 6: "PCOL_E_STATE"}
+                4: "PCOL_E_HIP", 5: "PCOL_E_SWEEPS", 6: "PCOL_E_STATE", 7: "PCOL_E_SCRATCH"}
+NOALLOC_SCRATCH_BYTES = 64 << 20  # PCOL_NOALLOC_SCRATCH_BYTES
 NO_KEY = -1  # UINT64_MAX seen as int64
 
 
@@ -130,6 +132,9 @@ def _load():
     lib.pcol_deposit.argtypes = [ctx_p, V, V, V, ctypes.c_int64, V, ctypes.c_int,
                                  P(ctypes.c_int32), P(ctypes.c_double), V]
     lib.pcol_deposit.restype = ctypes.c_int
+    lib.pcol_deposit_noalloc.argtypes = [V, V, V, ctypes.c_int64, V, ctypes.c_int,
+                                         P(ctypes.c_int32), P(ctypes.c_double), V, V]
+    lib.pcol_deposit_noalloc.restype = ctypes.c_int
     return lib
 
 
@@ -138,7 +143,7 @@ lib = _load()
 EXPORTED = ["pcol_default_opts", "pcol_create", "pcol_destroy", "pcol_last_error",
             "pcol_set_stream", "pcol_bin", "pcol_detect", "pcol_resolve", "pcol_advance",
             "pcol_step", "pcol_step_spin", "pcol_step_backward", "pcol_step_batched",
-            "pcol_deposit", "pcol_step_walls", "pcol_step_spin_walls"]
+            "pcol_deposit", "pcol_step_walls", "pcol_step_spin_walls", "pcol_deposit_noalloc"]
 
 
 class PcolError(RuntimeError):
@@ -459,6 +464,28 @@ def pcol_deposit(ctx: Context, x, y, z, a, nc, L, out=None):
     ctx.check(lib.pcol_deposit(ctx.handle, _ptr(x, torch.float64, n), _ptr(y, torch.float64, n),
                                _ptr(z, torch.float64, n), n, _ptr(a, torch.float64), comp, ncv,
                                Lv, _ptr(out, torch.float64)))
+    return out
+
+
+def pcol_deposit_noalloc(x, y, z, a, nc, L, out):
+    """pcol_deposit without a context or any allocation (the library's fixed device
+    scratch; see include/pcol.h).  out: float64 device tensor of nc2 nc1 nc0 comp
+    values, overwritten.  Raises PcolError (PCOL_E_SCRATCH when the input does not fit)."""
+    n = int(x.shape[0])
+    comp = int(a.shape[0])
+    if a.dim() != 2 or a.shape[1] != n:
+        raise ValueError("a must have shape (comp, n)")
+    ncs = [int(v) for v in nc]
+    Lb = (L, L, L) if isinstance(L, (int, float)) else L
+    if out.numel() != ncs[0] * ncs[1] * ncs[2] * comp:
+        raise ValueError("out has the wrong size")
+    ncv = (ctypes.c_int32 * 3)(*ncs)
+    Lv = (ctypes.c_double * 3)(*[float(v) for v in Lb])
+    st = lib.pcol_deposit_noalloc(_ptr(x, torch.float64, n), _ptr(y, torch.float64, n),
+                                  _ptr(z, torch.float64, n), n, _ptr(a, torch.float64), comp, ncv,
+                                  Lv, _ptr(out, torch.float64), ctypes.c_void_p(_stream()))
+    if st != PCOL_OK:
+        raise PcolError(st, "pcol_deposit_noalloc failed")
     return out
 
 

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <fstream>
+#include <mutex>
 #include <new>
 #include <sstream>
 #include <string>
@@ -80,13 +81,9 @@ struct pcol_ctx {
   const Spin *spin = nullptr;      // set by pcol_step_spin for the step: its spins are validated
   int walls = 0;                   // set by pcol_step_walls for the step: bit k = walls on axis k
   // pcol_deposit: position check flag, and the element sort's scratch with its capacities
-  unsigned int *dep_flag = nullptr, *dep_flag_h = nullptr;
-  int *dep_eid = nullptr, *dep_slot = nullptr, *dep_cnt = nullptr, *dep_start = nullptr,
-      *dep_bsum = nullptr;
-  unsigned char *dep_rec = nullptr;
-  double *dep_E = nullptr;
-  ReachOut *dep_ro = nullptr;
-  int64_t dep_cap_n = 0, dep_cap_rec = 0, dep_cap_el = 0, dep_cap_E = 0;
+  unsigned int *dep_flag_h = nullptr;
+  unsigned char *dep_buf = nullptr;  // carved by deposit_layout
+  int64_t dep_cap = 0;
   // bounds for the first layer's pair test: reach, speed and radius
   double reach_pass = 0.0, vmax_pass = 0.0, rmax_pass = 0.0;
   double band = 0.0;   // FP32 filter band in use (relative to r_i + r_j)
@@ -210,7 +207,131 @@ double ms_between(hipEvent_t a, hipEvent_t b) {
   return (double)ms;
 }
 
+// ---------------------------------------------------------------- deposition scratch
+
+// The deposition's scratch carved out of one buffer, each part on a 256-B
+// boundary: element id and slot per sphere, the element-sorted records, the
+// per-element counts, starts and scan block sums, the eight corner sums per
+// element and component, the scan's statistics word and the position flag.
+struct DepositLayout {
+  int64_t eid, slot, rec, cnt, start, bsum, E, ro, flag, bytes;
+};
+
+DepositLayout deposit_layout(int64_t n, int64_t ne, int comp) {
+  DepositLayout L{};
+  int64_t at = 0;
+  auto take = [&at](int64_t bytes) {
+    const int64_t here = at;
+    at += (bytes + 255) / 256 * 256;
+    return here;
+  };
+  L.eid = take(n * (int64_t)sizeof(int));
+  L.slot = take(n * (int64_t)sizeof(int));
+  L.rec = take(n * deposit_record_bytes(comp));
+  L.cnt = take((ne + 1) * (int64_t)sizeof(int));
+  L.start = take((ne + 1) * (int64_t)sizeof(int));
+  L.bsum = take((ne / 4096 + 2) * (int64_t)sizeof(int));
+  L.E = take(8 * (int64_t)comp * ne * (int64_t)sizeof(double));
+  L.ro = take((int64_t)sizeof(ReachOut));
+  L.flag = take((int64_t)sizeof(unsigned int));
+  L.bytes = at;
+  return L;
+}
+
+// Argument checks of the deposition (no device access); fills D but its
+// scratch pointers.
+pcol_status deposit_args(const double *x, const double *y, const double *z, int64_t n,
+                         const double *a, int comp, const int32_t nc[3], const double len[3],
+                         double *out, DepositArgs &D, const char *&why) {
+  if (n < 0 || n > INT32_MAX) return why = "n outside [0, 2^31 - 1]", PCOL_E_INVALID;
+  if (comp < 1 || comp > 8) return why = "comp outside [1, 8]", PCOL_E_INVALID;
+  if (!nc || !len || !out) return why = "null grid or output", PCOL_E_INVALID;
+  if (n > 0 && (!x || !y || !z || !a)) return why = "null array", PCOL_E_INVALID;
+  D.x = x;
+  D.y = y;
+  D.z = z;
+  D.a = a;
+  D.n = n;
+  D.comp = comp;
+  D.out = out;
+  D.nnode = 1;
+  for (int d = 0; d < 3; ++d) {
+    if (nc[d] < 1 || nc[d] > (1 << 20)) return why = "nc outside [1, 2^20]", PCOL_E_INVALID;
+    if (!(len[d] > 0.0) || !isfinite(len[d])) return why = "box side <= 0", PCOL_E_INVALID;
+    D.nc[d] = nc[d];
+    D.L[d] = len[d];
+    D.h[d] = len[d] / nc[d];
+    D.nnode *= nc[d];
+    if (D.nnode > INT32_MAX) return why = "more than 2^31 - 1 elements", PCOL_E_INVALID;
+  }
+  return PCOL_OK;
+}
+
+// The deposition on stream s with its scratch at base (laid out by Lo): the
+// count checks every position and is read back (into flag_h, host memory)
+// before anything of the caller's is written; st receives PCOL_E_INVALID for a
+// bad position, else PCOL_OK.  Counts and the flag are cleared by fill kernels.
+hipError_t deposit_run(DepositArgs &D, const DepositLayout &Lo, unsigned char *base, hipStream_t s,
+                       unsigned int *flag_h, pcol_status &st) {
+  st = PCOL_OK;
+  D.eid = (int *)(base + Lo.eid);
+  D.slot = (int *)(base + Lo.slot);
+  D.rec = base + Lo.rec;
+  D.cnt = (int *)(base + Lo.cnt);
+  D.start = (int *)(base + Lo.start);
+  D.E = (double *)(base + Lo.E);
+  unsigned int *flag = (unsigned int *)(base + Lo.flag);
+  hipError_t e = launch_fill_i32(s, D.cnt, 0, D.nnode);
+  if (e != hipSuccess) return e;
+  if (D.n > 0) {  // the count checks the positions; nothing of the caller's is written yet
+    if ((e = launch_fill_u32(s, flag, 0u, 1)) != hipSuccess) return e;
+    if ((e = launch_deposit_count(s, D, flag)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(flag_h, flag, sizeof(unsigned int), hipMemcpyDeviceToHost, s)) !=
+        hipSuccess)
+      return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    if (*flag_h) {
+      st = PCOL_E_INVALID;
+      return hipSuccess;
+    }
+  }
+  if ((e = launch_scan(s, D.cnt, (int)D.nnode, D.start, (int *)(base + Lo.bsum),
+                       (ReachOut *)(base + Lo.ro))) != hipSuccess)
+    return e;
+  return launch_deposit(s, D);
+}
+
 }  // namespace
+
+// ---------------------------------------------------------------- static scratch
+
+// Device scratch of pcol_deposit_noalloc: one copy per GPU, held until the
+// process ends.  Host code never passes `scratch` itself to a kernel (its host
+// name is a stand-in, not a device address): the device address of each GPU's
+// copy comes from hipGetSymbolAddress, taken once per device on the first call
+// with that device current.
+static __device__ __align__(256) unsigned char scratch[PCOL_NOALLOC_SCRATCH_BYTES];
+
+static constexpr int MAX_DEVICES = 64;
+static std::mutex scratch_mu;
+static unsigned char *scratch_ptr[MAX_DEVICES] = {};
+
+static hipError_t static_scratch(unsigned char **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_ptr[dev] = (unsigned char *)p;
+  }
+  *out = scratch_ptr[dev];
+  return hipSuccess;
+}
+
 
 extern "C" {
 
@@ -245,9 +366,7 @@ void pcol_destroy(pcol_ctx *ctx) {
                  ctx->count,  ctx->start,  ctx->blocksum, ctx->cnt,      ctx->slot_t,
                  ctx->slot_j, ctx->key_j,  ctx->key_t,  ctx->status,      ctx->out,
                  ctx->ovf,    ctx->partner_tmp, ctx->tcoll_tmp, ctx->list_a, ctx->keep_cnt, ctx->keep_off, ctx->keep_bs, ctx->epoch_d,
-                 ctx->reach_d, ctx->cellc, ctx->ctr_d, ctx->sflags, ctx->stotals, ctx->dep_flag,
-                 ctx->dep_eid, ctx->dep_slot, ctx->dep_cnt, ctx->dep_start, ctx->dep_bsum,
-                 ctx->dep_rec, ctx->dep_E, ctx->dep_ro};
+                 ctx->reach_d, ctx->cellc, ctx->ctr_d, ctx->sflags, ctx->stotals, ctx->dep_buf};
   for (void *p : dev)
     if (p) (void)hipFree(p);
   if (ctx->reach_h) (void)hipHostFree(ctx->reach_h);
@@ -989,70 +1108,44 @@ pcol_status pcol_deposit(pcol_ctx *ctx, const double *x, const double *y, const 
                          int64_t n, const double *a, int comp, const int32_t nc[3],
                          const double len[3], double *out) {
   if (!ctx) return PCOL_E_INVALID;
-  if (n < 0 || n > INT32_MAX) return fail(ctx, PCOL_E_INVALID, "n outside [0, 2^31 - 1]");
-  if (comp < 1 || comp > 8) return fail(ctx, PCOL_E_INVALID, "comp outside [1, 8]");
-  if (!nc || !len || !out) return fail(ctx, PCOL_E_INVALID, "null grid or output");
-  if (n > 0 && (!x || !y || !z || !a)) return fail(ctx, PCOL_E_INVALID, "null array");
   DepositArgs D{};
-  D.x = x;
-  D.y = y;
-  D.z = z;
-  D.a = a;
-  D.n = n;
-  D.comp = comp;
-  D.out = out;
-  D.nnode = 1;
-  for (int d = 0; d < 3; ++d) {
-    if (nc[d] < 1 || nc[d] > (1 << 20)) return fail(ctx, PCOL_E_INVALID, "nc outside [1, 2^20]");
-    if (!(len[d] > 0.0) || !isfinite(len[d])) return fail(ctx, PCOL_E_INVALID, "box side <= 0");
-    D.nc[d] = nc[d];
-    D.L[d] = len[d];
-    D.h[d] = len[d] / nc[d];
-    D.nnode *= nc[d];
-    if (D.nnode > INT32_MAX) return fail(ctx, PCOL_E_INVALID, "more than 2^31 - 1 elements");
-  }
+  const char *why = nullptr;
+  pcol_status st = deposit_args(x, y, z, n, a, comp, nc, len, out, D, why);
+  if (st != PCOL_OK) return fail(ctx, st, why);
   hipStream_t s = ctx->stream;
-  const int64_t ne = D.nnode;
-  int64_t cap_start = ctx->dep_cap_el, cap_bsum = ctx->dep_cap_el, cap_ro = ctx->dep_ro ? 1 : 0;
-  int64_t cap_slot = ctx->dep_cap_n, cap_flag = ctx->dep_flag ? 1 : 0;
-  if (ctx->dep_cap_n < n || ctx->dep_cap_rec < n * deposit_record_bytes(comp) ||
-      ctx->dep_cap_el < ne + 1 || ctx->dep_cap_E < 8 * comp * ne || !ctx->dep_ro ||
-      !ctx->dep_flag)
-    PCOL_HIP(hipStreamSynchronize(s));  // the frees below wait for nothing queued
-  hipError_t e = grow(&ctx->dep_eid, ctx->dep_cap_n, n);
-  if (e == hipSuccess) e = grow(&ctx->dep_slot, cap_slot, n);
-  if (e == hipSuccess) e = grow(&ctx->dep_rec, ctx->dep_cap_rec, n * deposit_record_bytes(comp));
-  if (e == hipSuccess) e = grow(&ctx->dep_cnt, ctx->dep_cap_el, ne + 1);
-  if (e == hipSuccess) e = grow(&ctx->dep_start, cap_start, ne + 1);
-  if (e == hipSuccess) e = grow(&ctx->dep_bsum, cap_bsum, ne + 1);
-  if (e == hipSuccess) e = grow(&ctx->dep_E, ctx->dep_cap_E, 8 * comp * ne);
-  if (e == hipSuccess) e = grow(&ctx->dep_ro, cap_ro, 1);
-  if (e == hipSuccess) e = grow(&ctx->dep_flag, cap_flag, 1);
-  if (e == hipSuccess && !ctx->dep_flag_h)
-    e = hipHostMalloc((void **)&ctx->dep_flag_h, sizeof(unsigned int));
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(ctx, e == hipErrorOutOfMemory ? PCOL_E_NOMEM : PCOL_E_HIP,
-                "deposition scratch allocation failed");
+  const DepositLayout Lo = deposit_layout(D.n, D.nnode, comp);
+  if (ctx->dep_cap < Lo.bytes || !ctx->dep_flag_h) {
+    PCOL_HIP(hipStreamSynchronize(s));  // the free below waits for nothing queued
+    hipError_t e = grow(&ctx->dep_buf, ctx->dep_cap, Lo.bytes);
+    if (e == hipSuccess && !ctx->dep_flag_h)
+      e = hipHostMalloc((void **)&ctx->dep_flag_h, sizeof(unsigned int));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ctx, e == hipErrorOutOfMemory ? PCOL_E_NOMEM : PCOL_E_HIP,
+                  "deposition scratch allocation failed");
+    }
   }
-  D.eid = ctx->dep_eid;
-  D.slot = ctx->dep_slot;
-  D.cnt = ctx->dep_cnt;
-  D.start = ctx->dep_start;
-  D.rec = ctx->dep_rec;
-  D.E = ctx->dep_E;
-  PCOL_HIP(hipMemsetAsync(ctx->dep_cnt, 0, (size_t)ne * sizeof(int), s));
-  if (n > 0) {  // the count checks the positions; nothing of the caller's is written yet
-    PCOL_HIP(hipMemsetAsync(ctx->dep_flag, 0, sizeof(unsigned int), s));
-    PCOL_HIP(launch_deposit_count(s, D, ctx->dep_flag));
-    PCOL_HIP(hipMemcpyAsync(ctx->dep_flag_h, ctx->dep_flag, sizeof(unsigned int),
-                            hipMemcpyDeviceToHost, s));
-    PCOL_HIP(hipStreamSynchronize(s));
-    if (*ctx->dep_flag_h) return fail(ctx, PCOL_E_INVALID, "position outside [0, L) or not finite");
-  }
-  PCOL_HIP(launch_scan(s, ctx->dep_cnt, (int)ne, ctx->dep_start, ctx->dep_bsum, ctx->dep_ro));
-  PCOL_HIP(launch_deposit(s, D));
+  hipError_t e = deposit_run(D, Lo, ctx->dep_buf, s, ctx->dep_flag_h, st);
+  if (e != hipSuccess) return hip_fail(ctx, e, "pcol_deposit");
+  if (st != PCOL_OK) return fail(ctx, st, "position outside [0, L) or not finite");
   return PCOL_OK;
+}
+
+pcol_status pcol_deposit_noalloc(const double *x, const double *y, const double *z, int64_t n,
+                                 const double *a, int comp, const int32_t nc[3],
+                                 const double len[3], double *out, void *hip_stream) {
+  DepositArgs D{};
+  const char *why = nullptr;
+  pcol_status st = deposit_args(x, y, z, n, a, comp, nc, len, out, D, why);
+  if (st != PCOL_OK) return st;
+  const DepositLayout Lo = deposit_layout(D.n, D.nnode, comp);
+  if (Lo.bytes > (int64_t)PCOL_NOALLOC_SCRATCH_BYTES) return PCOL_E_SCRATCH;
+  unsigned char *base = nullptr;
+  if (static_scratch(&base) != hipSuccess) return PCOL_E_HIP;
+  unsigned int flag_h = 0u;  // pageable host word: no pinned allocation
+  if (deposit_run(D, Lo, base, (hipStream_t)hip_stream, &flag_h, st) != hipSuccess)
+    return PCOL_E_HIP;
+  return st;
 }
 
 }  // extern "C"
