@@ -24,7 +24,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRCS = [os.path.join(_HERE, "pcol_oracle.c")]
-_LIB = os.path.join(_HERE, "libpcol_oracle.so")
+# PCOL_ORACLE_LIB: another build of pcol_oracle.c to load (the sanitizer test
+# loads an AddressSanitizer / UndefinedBehaviorSanitizer build this way)
+_LIB = os.environ.get("PCOL_ORACLE_LIB") or os.path.join(_HERE, "libpcol_oracle.so")
 _lib = None
 
 OK, E_INVALID, E_BOX, E_NOMEM, E_SWEEPS = 0, 1, 2, 3, 5
@@ -102,6 +104,8 @@ def _load():
         lib.orc_deposit.argtypes = [ctypes.c_int64, _D, _D, _D, _D, ctypes.c_int,
                                     ctypes.POINTER(ctypes.c_int), _D, _D]
         lib.orc_deposit.restype = ctypes.c_int
+        lib.orc_max_threads.argtypes = []
+        lib.orc_max_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -118,6 +122,11 @@ class OracleError(RuntimeError):
     def __init__(self, code: int):
         super().__init__(f"oracle status {code}")
         self.code = code
+
+
+def max_threads() -> int:
+    """Threads the oracle's parallel loops run on (OpenMP)."""
+    return int(_load().orc_max_threads())
 
 
 def pair_time(xi, vi, ri, xj, vj, rj, L, dt):

@@ -65,6 +65,7 @@
  * Every function below cites the passage it follows.  Pins: tests/test_oracle_*.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -78,6 +79,9 @@ enum {
   ORC_E_NOMEM = 3,
   ORC_E_SWEEPS = 5   /* sweep cap reached with mutual pairs still found */
 };
+
+/* threads the parallel loops below run on (reported beside timings) */
+int orc_max_threads(void) { return omp_get_max_threads(); }
 
 /* minimum-image component: the separation along one periodic axis is mapped
  * into [-L/2, L/2] by one subtraction or addition of L */
@@ -143,12 +147,16 @@ static double orc_reach(int64_t n, const double *vx, const double *vy, const dou
 
 /* a plain uniform cell grid with cell side >= reach * cell_mult (Sec. "Collision
  * Operator": particles are bucketed by host element, and only elements within the
- * halo distance hold candidates) */
+ * halo distance hold candidates).  Besides the particle indices bucketed by cell
+ * it keeps a copy of each particle's position, velocity and radius at its
+ * bucketed slot (sd[7 k .. 7 k + 6] for item[k]), so that the candidates of a cell
+ * are read from consecutive memory; the values are the caller's, unchanged. */
 typedef struct {
   int nc[3];
   double h[3];
   int64_t *start; /* ncell + 1 */
   int64_t *item;  /* particle indices bucketed by cell */
+  double *sd;     /* x, y, z, vx, vy, vz, r of item[k] at sd + 7 k */
   int nb[3];      /* number of distinct neighbour offsets per axis */
   int off[3][3];  /* the distinct offsets */
 } orc_grid;
@@ -161,7 +169,8 @@ static int orc_cell_of(double x, double h, int nc) {
 }
 
 static int orc_grid_build(orc_grid *G, int64_t n, const double *x, const double *y,
-                          const double *z, const double L[3], double cell) {
+                          const double *z, const double *vx, const double *vy, const double *vz,
+                          const double *r, const double L[3], double cell) {
   const double *p[3] = {x, y, z};
   for (int a = 0; a < 3; ++a) {
     int nc = (int)floor(L[a] / (cell * (1.0 + 1e-9)));
@@ -213,12 +222,38 @@ static int orc_grid_build(orc_grid *G, int64_t n, const double *x, const double 
   for (int64_t i = 0; i < n; ++i) G->item[fill[cid[i]]++] = i;
   free(fill);
   free(cid);
+  G->sd = (double *)malloc((size_t)(n > 0 ? n : 1) * 7 * sizeof(double));
+  if (!G->sd) {
+    free(G->start);
+    free(G->item);
+    return ORC_E_NOMEM;
+  }
+  for (int64_t k = 0; k < n; ++k) {
+    const int64_t i = G->item[k];
+    double *d = G->sd + 7 * k;
+    d[0] = x[i];
+    d[1] = y[i];
+    d[2] = z[i];
+    d[3] = vx[i];
+    d[4] = vy[i];
+    d[5] = vz[i];
+    d[6] = r[i];
+  }
   return ORC_OK;
 }
 
 static void orc_grid_free(orc_grid *G) {
   free(G->start);
   free(G->item);
+  free(G->sd);
+}
+
+/* cell number q of the neighbour (a0, a1, a2) of cell (c0, c1, c2), periodic */
+static int64_t orc_neighbour(const orc_grid *G, int c0, int c1, int c2, int a0, int a1, int a2) {
+  const int q0 = (c0 + G->off[0][a0] + G->nc[0]) % G->nc[0];
+  const int q1 = (c1 + G->off[1][a1] + G->nc[1]) % G->nc[1];
+  const int q2 = (c2 + G->off[2][a2] + G->nc[2]) % G->nc[2];
+  return ((int64_t)q2 * G->nc[1] + q1) * G->nc[0] + q0;
 }
 
 static int orc_check_inputs(int64_t n, const double *x, const double *y, const double *z,
@@ -279,38 +314,50 @@ int orc_earliest(int64_t n, const double *x, const double *y, const double *z, c
     }
   } else {
     orc_grid G;
-    rc = orc_grid_build(&G, n, x, y, z, L, reach * cell_mult);
+    rc = orc_grid_build(&G, n, x, y, z, vx, vy, vz, r, L, reach * cell_mult);
     if (rc) return rc;
-#pragma omp parallel for schedule(dynamic, 64) reduction(+ : tests2)
-    for (int64_t i = 0; i < n; ++i) {
-      partner[i] = -1;
-      tmin[i] = INFINITY;
-      if (active && !active[i]) continue;
-      const double xi[3] = {x[i], y[i], z[i]}, vi[3] = {vx[i], vy[i], vz[i]};
-      const int c0 = orc_cell_of(x[i], G.h[0], G.nc[0]);
-      const int c1 = orc_cell_of(y[i], G.h[1], G.nc[1]);
-      const int c2 = orc_cell_of(z[i], G.h[2], G.nc[2]);
-      for (int a2 = 0; a2 < G.nb[2]; ++a2)
-        for (int a1 = 0; a1 < G.nb[1]; ++a1)
-          for (int a0 = 0; a0 < G.nb[0]; ++a0) {
-            const int q0 = (c0 + G.off[0][a0] + G.nc[0]) % G.nc[0];
-            const int q1 = (c1 + G.off[1][a1] + G.nc[1]) % G.nc[1];
-            const int q2 = (c2 + G.off[2][a2] + G.nc[2]) % G.nc[2];
-            const int64_t q = ((int64_t)q2 * G.nc[1] + q1) * G.nc[0] + q0;
-            for (int64_t k = G.start[q]; k < G.start[q + 1]; ++k) {
-              const int64_t j = G.item[k];
-              if (j == i || (active && !active[j])) continue;
-              ++tests2;
-              const double xj[3] = {x[j], y[j], z[j]}, vj[3] = {vx[j], vy[j], vz[j]};
-              double t;
-              if (orc_pair_time(xi, vi, r[i], xj, vj, r[j], L, dt, &t) &&
-                  orc_before(t, j, tmin[i], partner[i] < 0 ? INT64_MAX : partner[i])) {
-                tmin[i] = t;
-                partner[i] = j;
+    /* the active flags at the bucketed slots (1 = active) */
+    uint8_t *sact = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
+    if (!sact) {
+      orc_grid_free(&G);
+      return ORC_E_NOMEM;
+    }
+    for (int64_t k = 0; k < n; ++k) sact[k] = !active || active[G.item[k]];
+    const int64_t ncell = (int64_t)G.nc[0] * G.nc[1] * G.nc[2];
+    /* the particles cell by cell: each one's candidates are the particles of its
+     * cell and the adjacent ones */
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : tests2)
+    for (int64_t c = 0; c < ncell; ++c) {
+      const int c0 = (int)(c % G.nc[0]), c1 = (int)((c / G.nc[0]) % G.nc[1]),
+                c2 = (int)(c / ((int64_t)G.nc[0] * G.nc[1]));
+      for (int64_t s = G.start[c]; s < G.start[c + 1]; ++s) {
+        const int64_t i = G.item[s];
+        partner[i] = -1;
+        tmin[i] = INFINITY;
+        if (!sact[s]) continue;
+        const double *di = G.sd + 7 * s;
+        const double xi[3] = {di[0], di[1], di[2]}, vi[3] = {di[3], di[4], di[5]};
+        for (int a2 = 0; a2 < G.nb[2]; ++a2)
+          for (int a1 = 0; a1 < G.nb[1]; ++a1)
+            for (int a0 = 0; a0 < G.nb[0]; ++a0) {
+              const int64_t q = orc_neighbour(&G, c0, c1, c2, a0, a1, a2);
+              for (int64_t k = G.start[q]; k < G.start[q + 1]; ++k) {
+                const int64_t j = G.item[k];
+                if (j == i || !sact[k]) continue;
+                ++tests2;
+                const double *dj = G.sd + 7 * k;
+                const double xj[3] = {dj[0], dj[1], dj[2]}, vj[3] = {dj[3], dj[4], dj[5]};
+                double t;
+                if (orc_pair_time(xi, vi, di[6], xj, vj, dj[6], L, dt, &t) &&
+                    orc_before(t, j, tmin[i], partner[i] < 0 ? INT64_MAX : partner[i])) {
+                  tmin[i] = t;
+                  partner[i] = j;
+                }
               }
             }
-          }
+      }
     }
+    free(sact);
     orc_grid_free(&G);
   }
   if (pair_tests) *pair_tests = tests2 / 2;
@@ -333,7 +380,7 @@ int orc_earliest_subset(int64_t n, const double *x, const double *y, const doubl
   for (int a = 0; a < 3; ++a)
     if (!(L[a] > 2.0 * reach)) return ORC_E_BOX;
   orc_grid G;
-  rc = orc_grid_build(&G, n, x, y, z, L, reach);
+  rc = orc_grid_build(&G, n, x, y, z, vx, vy, vz, r, L, reach);
   if (rc) return rc;
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t s = 0; s < nsub; ++s) {
@@ -348,16 +395,14 @@ int orc_earliest_subset(int64_t n, const double *x, const double *y, const doubl
     for (int a2 = 0; a2 < G.nb[2]; ++a2)
       for (int a1 = 0; a1 < G.nb[1]; ++a1)
         for (int a0 = 0; a0 < G.nb[0]; ++a0) {
-          const int q0 = (c0 + G.off[0][a0] + G.nc[0]) % G.nc[0];
-          const int q1 = (c1 + G.off[1][a1] + G.nc[1]) % G.nc[1];
-          const int q2 = (c2 + G.off[2][a2] + G.nc[2]) % G.nc[2];
-          const int64_t q = ((int64_t)q2 * G.nc[1] + q1) * G.nc[0] + q0;
+          const int64_t q = orc_neighbour(&G, c0, c1, c2, a0, a1, a2);
           for (int64_t k = G.start[q]; k < G.start[q + 1]; ++k) {
             const int64_t j = G.item[k];
             if (j == i || (active && !active[j])) continue;
-            const double xj[3] = {x[j], y[j], z[j]}, vj[3] = {vx[j], vy[j], vz[j]};
+            const double *dj = G.sd + 7 * k;
+            const double xj[3] = {dj[0], dj[1], dj[2]}, vj[3] = {dj[3], dj[4], dj[5]};
             double t;
-            if (orc_pair_time(xi, vi, r[i], xj, vj, r[j], L, dt, &t) &&
+            if (orc_pair_time(xi, vi, r[i], xj, vj, dj[6], L, dt, &t) &&
                 orc_before(t, j, tmin[s], partner[s] < 0 ? INT64_MAX : partner[s])) {
               tmin[s] = t;
               partner[s] = j;
@@ -875,7 +920,7 @@ int orc_step_sequential(int64_t n, const double *x, const double *y, const doubl
   for (int a = 0; a < 3; ++a)
     if (!(L[a] > 2.0 * reach)) return ORC_E_BOX;
   orc_grid G;
-  rc = orc_grid_build(&G, n, x, y, z, L, reach * cell_mult);
+  rc = orc_grid_build(&G, n, x, y, z, vx, vy, vz, r, L, reach * cell_mult);
   if (rc) return rc;
   const int64_t ncell = (int64_t)G.nc[0] * G.nc[1] * G.nc[2];
   orc_keyed *order = (orc_keyed *)malloc((size_t)(ncell > 0 ? ncell : 1) * sizeof(orc_keyed));
@@ -925,10 +970,11 @@ int orc_step_sequential(int64_t n, const double *x, const double *y, const doubl
         for (int64_t u = G.start[q]; u < G.start[q + 1]; ++u) {
           const int64_t j = G.item[u];
           if (j == i || hit[j]) continue;
-          const double xj[3] = {x[j], y[j], z[j]}, vj[3] = {vx[j], vy[j], vz[j]};
+          const double *dj = G.sd + 7 * u;
+          const double xj[3] = {dj[0], dj[1], dj[2]}, vj[3] = {dj[3], dj[4], dj[5]};
           double t;
           ++tests;
-          if (!orc_pair_time(xi, vi, r[i], xj, vj, r[j], L, dt, &t)) continue;
+          if (!orc_pair_time(xi, vi, r[i], xj, vj, dj[6], L, dt, &t)) continue;
           orc_resolve_pair(i, j, t, x, y, z, vx, vy, vz, r, m, L, dt, e, xo, yo, zo, vxo, vyo,
                            vzo);
           hit[i] = hit[j] = 1;
@@ -1102,7 +1148,7 @@ static int orc_step_walls_core(int64_t n, const double *x, const double *y, cons
   for (int a = 0; a < 3; ++a)
     if (!(L[a] > 2.0 * reach)) return ORC_E_BOX;
   orc_grid G;
-  rc = orc_grid_build(&G, n, x, y, z, L, reach);
+  rc = orc_grid_build(&G, n, x, y, z, vx, vy, vz, r, L, reach);
   if (rc) return rc;
   const size_t nn = (size_t)(n > 0 ? n : 1);
   uint8_t *hit = (uint8_t *)calloc(nn, 1);
@@ -1142,9 +1188,10 @@ static int orc_step_walls_core(int64_t n, const double *x, const double *y, cons
               const int64_t j = G.item[k];
               if (j == i || hit[j]) continue;
               ++tk;
-              const double xj[3] = {x[j], y[j], z[j]}, vj[3] = {vx[j], vy[j], vz[j]};
+              const double *dj = G.sd + 7 * k;
+              const double xj[3] = {dj[0], dj[1], dj[2]}, vj[3] = {dj[3], dj[4], dj[5]};
               double t;
-              if (orc_pair_time_walls(xi, vi, r[i], xj, vj, r[j], L, wall, dt, &t) &&
+              if (orc_pair_time_walls(xi, vi, r[i], xj, vj, dj[6], L, wall, dt, &t) &&
                   orc_before(t, j, pt[i], pj[i] < 0 ? INT64_MAX : pj[i])) {
                 pt[i] = t;
                 pj[i] = j;

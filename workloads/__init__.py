@@ -37,7 +37,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gen.c")
-_LIB = os.path.join(_HERE, "libwlgen.so")
+# PCOL_WLGEN_LIB: another build of gen.c to load (used by the sanitizer test)
+_LIB = os.environ.get("PCOL_WLGEN_LIB") or os.path.join(_HERE, "libwlgen.so")
 _lib = None
 
 # RNG stream ids (one independent xoshiro stream per purpose)
