@@ -242,3 +242,46 @@ def test_batched_errors(tmp_path):
     torch.cuda.synchronize()
     res = _oracle_steps(boxes, 0.9)
     _check(boxes, off, res, q, partner, tcoll)
+
+
+@pytest.fixture(scope="module")
+def config4():
+    print("[gpu-test] generating the 512-box batching workload", flush=True)
+    boxes = workloads.config(4)
+    assert len(boxes) == 512
+    return boxes
+
+
+def test_config4_workload(config4):
+    """The batching workload as generated: 512 boxes, about 7.8M spheres, box sizes
+    log-uniform in [1k, 64k], every sphere inside its box."""
+    ns = np.array([b.n for b in config4])
+    assert ns.min() >= 1000 and ns.max() <= 64_000 and 7_000_000 < ns.sum() < 8_500_000
+    for b in config4:
+        for f, a in (("x", 0), ("y", 1), ("z", 2)):
+            v = getattr(b, f)
+            assert np.all(v >= 0.0) and np.all(v < b.L[a])
+
+
+def test_config4_batched_equals_oracle_per_box(config4, tmp_path):
+    """The whole batching workload (512 uneven boxes, 7.8M spheres) in one
+    pcol_step_batched call, autotuned as bench.py runs it, against the oracle stepping
+    every box alone: every partner and contact time bitwise, states within 1e-12
+    relative, pair and sweep counts equal."""
+    _tune_env(tmp_path)
+    boxes = config4
+    p, off = _concat(boxes)
+    n = p.n
+    ctx = pc.Context(n, pc.pcol_default_opts(autotune=1))
+    partner = torch.empty(n, dtype=torch.int32, device="cuda")
+    tcoll = torch.empty(n, dtype=torch.float64, device="cuda")
+    print("[gpu-test] config 4 batched step", flush=True)
+    st = pc.pcol_step_batched(ctx, p, off, [b.L for b in boxes], boxes[0].dt, boxes[0].e,
+                              partner, tcoll)
+    torch.cuda.synchronize()
+    ctx.close()
+    print("[gpu-test] oracle steps of the 512 boxes", flush=True)
+    res = _oracle_steps(boxes, boxes[0].e)
+    pairs = _check(boxes, off, res, p, partner, tcoll)
+    assert st["n_pairs"] == pairs and pairs > 1_000_000
+    assert st["n_sweeps"] == max(r.n_sweeps for r in res)

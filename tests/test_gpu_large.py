@@ -2,13 +2,15 @@
 volume fraction 0.3 (lognormal radii, e = 0.8, dt = 0.4), in the launch
 configuration bench.py times.
 
-The oracle cannot step 16M spheres within a test, so parity is checked
-* on sampled spheres the oracle computes one by one (earliest partner and exact
-  contact time over all spheres; post-collision states of sampled pairs; the
-  termination condition among the spheres left without a collision), and
-* by properties that hold at any size (mutual pairs, bitwise-symmetric times,
-  momentum conservation, the closed-form energy loss per pair, free flight of
-  every sphere without a collision, FP32 form equal to the plain form).
+The plain step is compared with the oracle's whole step (about a minute on
+the host's cores, run as a test of its own) element by element, in both filter forms: pair set and contact
+times bitwise, states within 1e-12 relative (in fact bitwise), the pair and
+sweep counts equal; pcol_detect's keys with the oracle's earliest partners of
+all 16M spheres.  Properties that hold at any size are checked beside them
+(momentum conservation, the closed-form energy loss per pair).  The friction and
+walls steps at this size are checked on sampled pairs and by properties; both
+are compared whole with the oracle at 1M in their own tests.  Each test keeps
+one oracle computation, so no test runs silent for minutes.
 """
 import math
 
@@ -18,6 +20,7 @@ import torch
 
 import oracle
 import workloads
+from tests.gpu_helpers import compare_step
 
 pytestmark = pytest.mark.gpu
 
@@ -27,17 +30,31 @@ FIELDS = ("x", "y", "z", "vx", "vy", "vz")
 
 
 @pytest.fixture(scope="module")
-def big():
-    print("[gpu-test] generating the 16M workload", flush=True)
-    box = workloads.config(3)
-    assert box.n == 16_000_000
-    p0 = pc.Particles.from_box(box)
-    return box, p0
+def big(box16m):
+    return box16m, pc.Particles.from_box(box16m)
 
 
-def _step(box, p0, fp32):
+@pytest.fixture(scope="module")
+def big_oracle(big):
+    box, _ = big
+    print("[gpu-test] oracle step at 16M", flush=True)
+    return oracle.step(box)
+
+
+@pytest.mark.timeout(900)
+def test_16M_oracle_step(big_oracle):
+    """The oracle's whole 16M step (its own test: about a minute on the host's cores),
+    which the comparisons below use."""
+    orc = big_oracle
+    hit = orc.partner >= 0
+    assert orc.n_pairs * 2 == int(hit.sum()) and orc.n_pairs > 1_000_000
+    assert np.array_equal(orc.partner[orc.partner[hit]], np.where(hit)[0])
+    assert np.array_equal(orc.tcoll[hit], orc.tcoll[orc.partner[hit]])
+
+
+def _step(box, p0, flt):
     p = p0.clone()
-    ctx = pc.Context(box.n, pc.pcol_default_opts(filter=fp32))
+    ctx = pc.Context(box.n, pc.pcol_default_opts(filter=flt))
     partner = torch.empty(box.n, dtype=torch.int32, device="cuda")
     tcoll = torch.empty(box.n, dtype=torch.float64, device="cuda")
     st = pc.pcol_step(ctx, p, box.L, box.dt, box.e, partner, tcoll)
@@ -49,13 +66,70 @@ def _step(box, p0, fp32):
 
 
 @pytest.mark.timeout(900)
-def test_16M_sampled_keys_and_step_properties(big):
+def test_16M_workload(big):
+    """The generated input: 16M spheres inside the box, no two overlapping (sampled
+    against the oracle's neighbour search: a pair that overlaps has no contact time,
+    so overlap is checked directly on the nearest neighbours of sampled spheres)."""
+    box, p0 = big
+    L = np.array(box.L)
+    for f, a in (("x", 0), ("y", 1), ("z", 2)):
+        v = getattr(box, f)
+        assert np.all(v >= 0.0) and np.all(v < L[a])
+    assert np.all(box.r >= 0.5) and np.all(box.r <= 2.0)
+    assert np.allclose(box.m, box.r ** 3, rtol=0, atol=0)
+    phi = math.fsum(4.0 / 3.0 * math.pi * box.r ** 3) / float(np.prod(L))
+    assert phi == pytest.approx(0.3, rel=1e-9)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("flt", [0, 1])
+def test_16M_step_equals_oracle(big, big_oracle, flt):
+    """The whole 16M step against the oracle's: every partner, every contact time
+    bitwise, every state within 1e-12 relative and in fact bitwise; pair and sweep
+    counts equal.  Filter 1 (binary32 with the binary64 recheck) is the precision
+    form: its pair-set mismatch against the binary64 oracle must be zero."""
+    box, p0 = big
+    orc = big_oracle
+    print(f"[gpu-test] 16M step, filter {flt}", flush=True)
+    gpu = _step(box, p0, flt)
+    out, partner, tcoll, st = gpu
+    assert compare_step(box, gpu, orc) == 0
+    assert st["n_pairs"] == orc.n_pairs and st["n_pairs"] > 1_000_000
+    assert st["n_sweeps"] == orc.n_sweeps
+    if flt == 1:
+        assert st["n_recheck"] > 0 and st["band"] >= 1e-4
+
+    if flt == 0:
+        # properties beside the comparison: momentum conserved; kinetic energy lost
+        # exactly as the closed form per pair
+        hit = partner >= 0
+        m = box.m
+        for f in ("vx", "vy", "vz"):
+            p_in = math.fsum(m * getattr(box, f))
+            p_out = math.fsum(m * out[f])
+            assert abs(p_out - p_in) <= 1e-10 * math.fsum(m * np.abs(getattr(box, f)))
+        ke = lambda vx, vy, vz: 0.5 * math.fsum(m * (vx * vx + vy * vy + vz * vz))
+        loss = ke(box.vx, box.vy, box.vz) - ke(out["vx"], out["vy"], out["vz"])
+        L = np.array(box.L)
+        pairs = np.where(hit & (np.arange(box.n) < partner))[0]
+        i, j = pairs, partner[pairs]
+        d = np.stack([getattr(box, f)[j] - getattr(box, f)[i] for f in ("x", "y", "z")], 1)
+        d = np.where(d > 0.5 * L, d - L, np.where(d < -0.5 * L, d + L, d))
+        u = np.stack([getattr(box, f)[j] - getattr(box, f)[i] for f in ("vx", "vy", "vz")], 1)
+        w = d + tcoll[i][:, None] * u
+        g = np.sum(u * w, 1) / (box.r[i] + box.r[j])
+        mr = m[i] * m[j] / (m[i] + m[j])
+        expect = math.fsum(0.5 * (1 - box.e ** 2) * mr * g * g)
+        assert loss == pytest.approx(expect, rel=1e-9)
+
+
+@pytest.mark.timeout(900)
+def test_16M_detect_keys_equal_oracle(big):
+    """pcol_detect over all 16M spheres (all active) against the oracle's earliest
+    partner of every sphere: partner index and exact contact time bitwise, and the
+    key's packed binary32 time."""
     box, p0 = big
     n = box.n
-    rng = np.random.default_rng(2024)
-    sample = rng.choice(n, 4000, replace=False)
-
-    # sweep-1 keys at sampled spheres against the oracle (exact partner and time)
     print("[gpu-test] 16M detect keys", flush=True)
     ctx = pc.Context(n)
     pc.pcol_bin(ctx, p0, box.L, box.dt)
@@ -64,82 +138,16 @@ def test_16M_sampled_keys_and_step_properties(big):
     key = key.cpu().numpy().view(np.uint64)
     tmin = tmin.cpu().numpy()
     ctx.close()
-    op, ot = oracle.earliest_subset(box, sample)
+    print("[gpu-test] oracle earliest partners at 16M", flush=True)
+    op, ot, _ = oracle.earliest(box)
+    none = np.uint64(2 ** 64 - 1)
+    kj = np.where(key == none, -1, (key & np.uint64(0xFFFFFFFF)).astype(np.int64))
+    assert np.array_equal(kj, op)
+    assert np.array_equal(tmin, ot)
     has = op >= 0
-    assert has.sum() > 1000
-    kj = (key[sample] & np.uint64(0xFFFFFFFF)).astype(np.int64)
-    assert np.array_equal(np.where(key[sample] == np.uint64(2 ** 64 - 1), -1, kj), op)
-    assert np.array_equal(tmin[sample], ot)
-
-    print("[gpu-test] 16M step, plain FP64", flush=True)
-    out, partner, tcoll, st = _step(box, p0, 0)
-    hit = partner >= 0
-    assert st["n_pairs"] * 2 == int(hit.sum()) and st["n_pairs"] > 1_000_000
-    # mutual pairs, bitwise-symmetric contact times
-    assert np.array_equal(partner[partner[hit]], np.where(hit)[0])
-    assert np.array_equal(tcoll[hit], tcoll[partner[hit]])
-    assert np.all(tcoll[hit] > 0) and np.all(tcoll[hit] <= box.dt)
-    # every pair mutual in sweep 1 (from the keys) collided with that partner
-    m1 = np.where(key != np.uint64(2 ** 64 - 1))[0]
-    kp = (key[m1] & np.uint64(0xFFFFFFFF)).astype(np.int64)
-    mutual = m1[(key[kp] & np.uint64(0xFFFFFFFF)).astype(np.int64) == m1]
-    pm = (key[mutual] & np.uint64(0xFFFFFFFF)).astype(np.int64)
-    assert np.array_equal(partner[mutual], pm)
-
-    # free flight of every sphere without a collision
-    L = np.array(box.L)
-    for f, v, a in (("x", box.vx, 0), ("y", box.vy, 1), ("z", box.vz, 2)):
-        x0 = getattr(box, f)[~hit]
-        x1 = x0 + box.dt * v[~hit]
-        x1 = np.where(x1 >= L[a], x1 - L[a], np.where(x1 < 0, x1 + L[a], x1))
-        x1 = np.where(x1 >= L[a], 0.0, x1)
-        assert np.array_equal(out[f][~hit], x1)
-    for f in ("vx", "vy", "vz"):
-        assert np.array_equal(out[f][~hit], getattr(box, f)[~hit])
-
-    # post-collision states of sampled pairs against the oracle's resolve
-    pairs = np.where(hit & (np.arange(n) < partner))[0]
-    for i in rng.choice(pairs, 300, replace=False):
-        j = partner[i]
-        xs, vs = oracle.resolve_pair(box, i, j, tcoll[i])
-        got_x = np.array([[out[f][i] for f in ("x", "y", "z")], [out[f][j] for f in ("x", "y", "z")]])
-        got_v = np.array([[out[f][i] for f in ("vx", "vy", "vz")],
-                          [out[f][j] for f in ("vx", "vy", "vz")]])
-        assert np.array_equal(got_x, xs) and np.array_equal(got_v, vs)
-
-    # momentum conserved; kinetic energy lost exactly as the closed form per pair
-    m = box.m
-    for f in ("vx", "vy", "vz"):
-        p_in = math.fsum(m * getattr(box, f))
-        p_out = math.fsum(m * out[f])
-        assert abs(p_out - p_in) <= 1e-10 * math.fsum(m * np.abs(getattr(box, f)))
-    ke = lambda vx, vy, vz: 0.5 * math.fsum(m * (vx * vx + vy * vy + vz * vz))
-    loss = ke(box.vx, box.vy, box.vz) - ke(out["vx"], out["vy"], out["vz"])
-    i, j = pairs, partner[pairs]
-    d = np.stack([getattr(box, f)[j] - getattr(box, f)[i] for f in ("x", "y", "z")], 1)
-    d = np.where(d > 0.5 * L, d - L, np.where(d < -0.5 * L, d + L, d))
-    u = np.stack([getattr(box, f)[j] - getattr(box, f)[i] for f in ("vx", "vy", "vz")], 1)
-    w = d + tcoll[i][:, None] * u
-    g = np.sum(u * w, 1) / (box.r[i] + box.r[j])
-    mr = m[i] * m[j] / (m[i] + m[j])
-    expect = math.fsum(0.5 * (1 - box.e ** 2) * mr * g * g)
-    assert loss == pytest.approx(expect, rel=1e-9)
-
-    # termination: among spheres left without a collision no contact remains (sampled)
-    free = np.where(~hit)[0]
-    probe = rng.choice(free, 2000, replace=False)
-    fp, _ = oracle.earliest_subset(box, probe, active=(~hit).astype(np.uint8))
-    assert np.all(fp < 0)
-
-    # the binary32 filter form gives the same step bitwise
-    for flt in (1,):
-        print(f"[gpu-test] 16M step, filter {flt}", flush=True)
-        out32, partner32, tcoll32, st32 = _step(box, p0, flt)
-        assert np.array_equal(partner32, partner)
-        assert np.array_equal(tcoll32, tcoll, equal_nan=True)
-        for f in FIELDS:
-            assert np.array_equal(out32[f].view(np.uint64), out[f].view(np.uint64))
-        assert st32["n_recheck"] > 0
+    assert has.sum() > 4_000_000
+    tf = (key[has] >> np.uint64(32)).astype(np.uint32).view(np.float32)
+    assert np.array_equal(tf, ot[has].astype(np.float32))
 
 
 @pytest.mark.timeout(900)
