@@ -125,6 +125,25 @@ typedef struct {
                          grid's cells need only twice the quantile extent instead of the reach.
                          Used when that shrinks the cells by 15% or more.  Results do not
                          depend on it. */
+  int order;          /* which pairs collide (pcol_step only; pcol_detect, pcol_resolve and
+                         the other steps always use rule 2):
+                         0: rules 2-3 (each sphere's earliest partner, mutual pairs per sweep);
+                         1: the order of Sec. "Collision Operator" taken literally: elements
+                         along a space-filling curve, the particles of an element one after
+                         another, each still eligible particle taking the first eligible
+                         partner with a contact (rule 1) found in its candidate elements in
+                         curve order, both then leaving the eligible set.  The elements are
+                         the cells of the curve grid, cell side >= reach = 2 max r +
+                         2 max|v| dt (floor(L_k / (reach (1 + 1e-9))) cells per axis, between
+                         1 and 2048), a sphere's cell floor(x_k / h_k) (h_k = L_k / cells,
+                         clamped to the last cell); the curve is the Morton order (bits of
+                         the cell coordinates interleaved, x lowest); particles of a cell in
+                         caller-index order.  With rank(i) = (Morton code of i's cell,
+                         caller index), that pass is the greedy matching of the contact graph
+                         taking edges by (lower rank of the two ends, higher rank), computed
+                         here in parallel: every active sphere points at its active contact
+                         of smallest rank, mutual pairs collide (rule 4) and leave, sweep
+                         after sweep.  Default 0. */
 } pcol_opts;
 
 typedef struct {

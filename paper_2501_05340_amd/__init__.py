@@ -44,7 +44,7 @@ class pcol_opts(ctypes.Structure):
                 ("home_cells", ctypes.c_int), ("contact_slots", ctypes.c_int),
                 ("filter", ctypes.c_int), ("band_rel", ctypes.c_double),
                 ("timing", ctypes.c_int), ("autotune", ctypes.c_int),
-                ("split_quantile", ctypes.c_double)]
+                ("split_quantile", ctypes.c_double), ("order", ctypes.c_int)]
 
 
 class pcol_stats(ctypes.Structure):

@@ -49,8 +49,6 @@ struct pcol_ctx {
   int *list_a = nullptr;  // spheres still to act after sweep 1
   int *keep_cnt = nullptr, *keep_off = nullptr, *keep_bs = nullptr;  // its construction
   int *nlist_h = nullptr;  // pinned read-back of its length
-  unsigned int *epoch_d = nullptr;  // step counter stamped into output records
-  int64_t epochs = 0;               // steps since the stamps were last reset
   OutRec *out = nullptr;
   int *partner_tmp = nullptr;
   double *tcoll_tmp = nullptr;
@@ -92,6 +90,7 @@ struct pcol_ctx {
   bool small = false;  // some axis has fewer than 3 cells
   bool detect_timed = false;
   int cpw_used = 0;  // home cells per workgroup of the last sweep-1 detect (0: exact search)
+  unsigned long long *crank = nullptr;  // literal order (opts.order = 1): curve rank per sorted sphere
   struct BatchPlan *bp = nullptr;  // batched form (pcol_step_batched)
 };
 
@@ -347,6 +346,7 @@ void pcol_default_opts(pcol_opts *o) {
   o->timing = 0;
   o->autotune = 1;
   o->split_quantile = 0.999;
+  o->order = 0;
 }
 
 const char *pcol_last_error(const pcol_ctx *ctx) {
@@ -365,8 +365,9 @@ void pcol_destroy(pcol_ctx *ctx) {
   void *dev[] = {ctx->rec,    ctx->rec32,  ctx->rank,   ctx->cid,         ctx->slot,
                  ctx->count,  ctx->start,  ctx->blocksum, ctx->cnt,      ctx->slot_t,
                  ctx->slot_j, ctx->key_j,  ctx->key_t,  ctx->status,      ctx->out,
-                 ctx->ovf,    ctx->partner_tmp, ctx->tcoll_tmp, ctx->list_a, ctx->keep_cnt, ctx->keep_off, ctx->keep_bs, ctx->epoch_d,
-                 ctx->reach_d, ctx->cellc, ctx->ctr_d, ctx->sflags, ctx->stotals, ctx->dep_buf};
+                 ctx->ovf,    ctx->partner_tmp, ctx->tcoll_tmp, ctx->list_a, ctx->keep_cnt, ctx->keep_off, ctx->keep_bs,
+                 ctx->reach_d, ctx->cellc, ctx->ctr_d, ctx->sflags, ctx->stotals, ctx->dep_buf,
+                 ctx->crank};
   for (void *p : dev)
     if (p) (void)hipFree(p);
   if (ctx->reach_h) (void)hipHostFree(ctx->reach_h);
@@ -402,6 +403,7 @@ pcol_status pcol_create(pcol_ctx **out, int64_t n_max, void *hip_stream, const p
   if (!(ctx->opts.cell_mult >= 1.0) || !isfinite(ctx->opts.cell_mult) ||
       ctx->opts.max_sweeps < 0 || ctx->opts.contact_slots < 0 || ctx->opts.contact_slots > 64 ||
       ctx->opts.home_cells < 0 || ctx->opts.home_cells > 16 ||
+      ctx->opts.order < 0 || ctx->opts.order > 1 ||
       !(ctx->opts.band_rel >= 0.0) ||
       !(ctx->opts.split_quantile >= 0.0 && ctx->opts.split_quantile <= 1.0) ||
       ctx->opts.filter < 0 || ctx->opts.filter > 1) {
@@ -430,12 +432,12 @@ pcol_status pcol_create(pcol_ctx **out, int64_t n_max, void *hip_stream, const p
   A(dalloc(&ctx->out, n));
   A(dalloc(&ctx->ovf, n));
   A(dalloc(&ctx->list_a, n));
-  A(dalloc(&ctx->epoch_d, 1));
   A(dalloc(&ctx->keep_cnt, n / 256 + 2));
   A(dalloc(&ctx->keep_off, n / 256 + 3));
   A(dalloc(&ctx->keep_bs, n / 256 / 4096 + 2));
   A(dalloc(&ctx->partner_tmp, n));
   A(dalloc(&ctx->tcoll_tmp, n));
+  if (ctx->opts.order == 1) A(dalloc(&ctx->crank, n));
   A(dalloc(&ctx->reach_d, 1));
   A(dalloc(&ctx->ctr_d, 1));
   A(dalloc(&ctx->sflags, 16));
@@ -448,9 +450,6 @@ pcol_status pcol_create(pcol_ctx **out, int64_t n_max, void *hip_stream, const p
   if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->nlist_h, sizeof(int));
   for (hipEvent_t &ev : ctx->ev)
     if (e == hipSuccess) e = hipEventCreate(&ev);
-  // output-record stamps: every record stale, epoch 0
-  if (e == hipSuccess) e = launch_init_out(ctx->stream, ctx->out, (int64_t)n);
-  if (e == hipSuccess) e = launch_fill_u32(ctx->stream, ctx->epoch_d, 0u, 1);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) {
     pcol_destroy(ctx);
@@ -589,6 +588,20 @@ pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box
   PCOL_HIP(launch_scan(s, ctx->count, cells_all, ctx->start, ctx->blocksum, ctx->reach_d));
   PCOL_HIP(launch_scatter(s, P, G, ctx->cid, ctx->slot, ctx->start, ctx->rec,
                           ctx->opts.filter == 1 ? ctx->rec32 : nullptr, ctx->rank, nullptr));
+  if (ctx->opts.order == 1) {
+    // the literal order's ranks on the curve grid: cell side >= the reach
+    // (2 max r + 2 max|v| dt, whatever grid the pair tests use), at most 2048
+    // cells per axis
+    CurveGrid C{};
+    for (int a = 0; a < 3; ++a) {
+      double q3 = floor(box->len[a] / (reach * (1.0 + 1e-9)));
+      if (!(q3 >= 1.0)) q3 = 1.0;
+      if (q3 > 2048.0) q3 = 2048.0;
+      C.nc[a] = (int)q3;
+      C.h[a] = box->len[a] / C.nc[a];
+    }
+    PCOL_HIP(launch_curve_rank(s, ctx->rec, (int)p->n, C, ctx->crank));
+  }
   // the largest cell and the second layer's range are read back without a
   // wait: only the binary32 filter sizes a launch by them (its LDS staging);
   // the other paths read them after their next synchronisation (bin_readback)
@@ -682,8 +695,9 @@ static double gram64_tolerance(double h, double R, double V, double r, double Lm
   return 2.0 * (E0 + Epos + E);
 }
 
-// sweep 1: keys of all spheres (all active) into ctx->key_j / key_t (sorted order)
-static pcol_status detect_all(pcol_ctx *ctx, double dt) {
+// sweep 1: keys of all spheres (all active) into ctx->key_j / key_t (sorted
+// order); crank given: the literal order's partners instead of rule 2's
+static pcol_status detect_all(pcol_ctx *ctx, double dt, const unsigned long long *crank) {
   hipStream_t s = ctx->stream;
   const int n = (int)ctx->binned_n;
   if (!ctx->small) {
@@ -754,37 +768,14 @@ static pcol_status detect_all(pcol_ctx *ctx, double dt) {
     ctx->detect_timed = true;
     PCOL_HIP(launch_slot_min(s, n, 1, ctx->cnt, ctx->slot_t, ctx->slot_j, ctx->K, ctx->status,
                              ctx->rec, ctx->key_j, ctx->key_t, ctx->ovf, ctx->ctr_d,
-                             nullptr, nullptr, 0, &ctx->G));
+                             nullptr, nullptr, 0, &ctx->G, crank));
     PCOL_HIP(launch_gather_exact(s, ctx->ovf, 0, &ctx->ctr_d->n_overflow, -1, ctx->rec, ctx->start,
-                                 ctx->G, dt, ctx->status, ctx->key_j, ctx->key_t, nullptr));
+                                 ctx->G, dt, ctx->status, ctx->key_j, ctx->key_t, nullptr, crank));
   } else {
     // fewer than 3 cells on some axis: exact search for every sphere
     ctx->cpw_used = 0;
     PCOL_HIP(launch_gather_exact(s, nullptr, n, nullptr, -1, ctx->rec, ctx->start, ctx->G, dt,
-                                 ctx->status, ctx->key_j, ctx->key_t, nullptr));
-  }
-  return PCOL_OK;
-}
-
-// Advance the step epoch on the stream (every stamp is reset long before the
-// 32-bit counter could wrap).
-static pcol_status next_epoch(pcol_ctx *ctx, hipStream_t s) {
-  if (++ctx->epochs >= (int64_t)1 << 30) {
-    PCOL_HIP(launch_init_out(s, ctx->out, ctx->n_max));
-    PCOL_HIP(launch_fill_u32(s, ctx->epoch_d, 0u, 1));
-    ctx->epochs = 1;
-  }
-  PCOL_HIP(launch_epoch_next(s, ctx->epoch_d));
-  return PCOL_OK;
-}
-
-// Account for one replay of a captured step, which advances the device epoch
-// itself; resets the stamps (outside the graph) when the counter grows large.
-static pcol_status graph_epoch(pcol_ctx *ctx, hipStream_t s) {
-  if (++ctx->epochs >= (int64_t)1 << 30) {
-    PCOL_HIP(launch_init_out(s, ctx->out, ctx->n_max));
-    PCOL_HIP(launch_fill_u32(s, ctx->epoch_d, 0u, 1));
-    ctx->epochs = 1;
+                                 ctx->status, ctx->key_j, ctx->key_t, nullptr, crank));
   }
   return PCOL_OK;
 }
@@ -810,7 +801,7 @@ pcol_status pcol_detect(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *
   PCOL_HIP(hipMemsetAsync(ctx->ctr_d, 0, sizeof(SweepCounters), s));
   if (!active) {
     PCOL_HIP(launch_fill_u8(s, ctx->status, ST_ACTIVE, n));
-    if ((st = detect_all(ctx, dt)) != PCOL_OK) return st;
+    if ((st = detect_all(ctx, dt, nullptr)) != PCOL_OK) return st;
   } else {
     PCOL_HIP(launch_status_from_active(s, active, ctx->rec, n, ctx->status));
     PCOL_HIP(launch_fill_i32(s, ctx->key_j, -1, n));
@@ -853,6 +844,10 @@ static pcol_status step_impl(pcol_ctx *ctx, pcol_particles *p, const pcol_box *b
   pcol_status st = check_common(ctx, p, box, dt);
   if (st != PCOL_OK) return st;
   if (!(e >= 0.0 && e <= 1.0)) return fail(ctx, PCOL_E_INVALID, "e outside [0, 1]");
+  if (ctx->opts.order == 1 && (spin || ctx->walls))
+    return fail(ctx, PCOL_E_INVALID, "the literal order (opts.order = 1) is built for pcol_step only");
+  // the literal order's ranks (set by the binning), else rule 2
+  const unsigned long long *crank = ctx->opts.order == 1 ? ctx->crank : nullptr;
   hipStream_t s = ctx->stream;
   const bool timing = ctx->opts.timing != 0;
   if (timing) PCOL_HIP(hipEventRecord(ctx->ev[0], s));
@@ -866,18 +861,17 @@ static pcol_status step_impl(pcol_ctx *ctx, pcol_particles *p, const pcol_box *b
   unsigned long long contacts = 0ull, recheck = 0ull, tests = 0ull;
   double ms_detect = 0.0;
   if (n > 0) {
-    if ((st = next_epoch(ctx, s)) != PCOL_OK) return st;
     PCOL_HIP(launch_fill_u8(s, ctx->status, ST_ACTIVE, n));
     PCOL_HIP(hipMemsetAsync(ctx->ctr_d, 0, sizeof(SweepCounters), s));
     // sweep 1: every contact within dt, then the earliest partner of each sphere
     ctx->detect_timed = false;
-    if ((st = detect_all(ctx, dt)) != PCOL_OK) return st;
+    if ((st = detect_all(ctx, dt, crank)) != PCOL_OK) return st;
     if (timing) PCOL_HIP(hipEventRecord(ctx->ev[2], s));
     // sweep 1 over every sphere; later sweeps over the list of the spheres it
     // left ACTIVE or DIRTY (the others are done for the step; entries that
     // finish later are skipped by their status)
     PCOL_HIP(launch_resolve_sweep(s, n, ctx->rec, ctx->G, dt, e, P.m, ctx->key_j, ctx->key_t,
-                                  ctx->status, ctx->out, ctx->ctr_d, nullptr, ctx->epoch_d,
+                                  ctx->status, ctx->out, ctx->ctr_d, nullptr,
                                   nullptr, 0, spin));
     PCOL_HIP(launch_keep_list(s, ctx->status, n, ctx->keep_cnt, ctx->keep_off, ctx->keep_bs,
                               ctx->reach_d, ctx->list_a));
@@ -919,16 +913,17 @@ static pcol_status step_impl(pcol_ctx *ctx, pcol_particles *p, const pcol_box *b
       if (!ctx->small) {
         PCOL_HIP(launch_slot_min(s, n, 0, ctx->cnt, ctx->slot_t, ctx->slot_j, ctx->K,
                                  ctx->status, ctx->rec, ctx->key_j, ctx->key_t, ctx->ovf,
-                                 ctx->ctr_d, nullptr, lin, nlist, &ctx->G));
+                                 ctx->ctr_d, nullptr, lin, nlist, &ctx->G, crank));
         PCOL_HIP(launch_gather_exact(s, ctx->ovf, 0, &ctx->ctr_d->n_overflow, -1, ctx->rec,
                                      ctx->start, ctx->G, dt, ctx->status, ctx->key_j,
-                                     ctx->key_t, nullptr));
+                                     ctx->key_t, nullptr, crank));
       } else {
         PCOL_HIP(launch_gather_exact(s, lin, nlist, nullptr, ST_DIRTY, ctx->rec, ctx->start,
-                                     ctx->G, dt, ctx->status, ctx->key_j, ctx->key_t, nullptr));
+                                     ctx->G, dt, ctx->status, ctx->key_j, ctx->key_t, nullptr,
+                                     crank));
       }
       PCOL_HIP(launch_resolve_sweep(s, n, ctx->rec, ctx->G, dt, e, P.m, ctx->key_j, ctx->key_t,
-                                    ctx->status, ctx->out, ctx->ctr_d, nullptr, ctx->epoch_d,
+                                    ctx->status, ctx->out, ctx->ctr_d, nullptr,
                                     lin, nlist, spin));
       PCOL_HIP(hipMemcpyAsync(ctx->ctr_h, ctx->ctr_d, sizeof(SweepCounters),
                               hipMemcpyDeviceToHost, s));
@@ -956,21 +951,22 @@ static pcol_status step_impl(pcol_ctx *ctx, pcol_particles *p, const pcol_box *b
         if (!ctx->small) {
           PCOL_HIP(launch_slot_min(s, n, 0, ctx->cnt, ctx->slot_t, ctx->slot_j, ctx->K,
                                    ctx->status, ctx->rec, ctx->key_j, ctx->key_t, ctx->ovf,
-                                   ctx->ctr_d, ctx->sflags, lin, nlist, &ctx->G));
+                                   ctx->ctr_d, ctx->sflags, lin, nlist, &ctx->G, crank));
           PCOL_HIP(launch_gather_exact(s, ctx->ovf, 0, &ctx->ctr_d->n_overflow, -1, ctx->rec,
                                        ctx->start, ctx->G, dt, ctx->status, ctx->key_j,
-                                       ctx->key_t, &Bf));
+                                       ctx->key_t, &Bf, crank));
         } else {
           PCOL_HIP(launch_gather_exact(s, lin, nlist, nullptr, ST_DIRTY, ctx->rec, ctx->start,
-                                       ctx->G, dt, ctx->status, ctx->key_j, ctx->key_t, &Bf));
+                                       ctx->G, dt, ctx->status, ctx->key_j, ctx->key_t, &Bf,
+                                       crank));
         }
         PCOL_HIP(launch_resolve_sweep(s, n, ctx->rec, ctx->G, dt, e, P.m, ctx->key_j,
                                       ctx->key_t, ctx->status, ctx->out, ctx->ctr_d, &Bf,
-                                      ctx->epoch_d, lin, nlist, spin));
+                                      lin, nlist, spin));
         PCOL_HIP(launch_sweep_check(s, ctx->ctr_d, ctx->sflags, ctx->stotals, k == S - 1));
       }
       if (timing) PCOL_HIP(hipEventRecord(ctx->ev[3], s));
-      PCOL_HIP(launch_finish(s, P, ctx->rank, ctx->out, ctx->epoch_d, part, tc, dt, ctx->G,
+      PCOL_HIP(launch_finish(s, P, ctx->rank, ctx->out, ctx->status, part, tc, dt, ctx->G,
                              &Bf));
       PCOL_HIP(hipMemcpyAsync(ctx->sflags_h, ctx->sflags, 4 * sizeof(unsigned int),
                               hipMemcpyDeviceToHost, s));
@@ -989,7 +985,7 @@ static pcol_status step_impl(pcol_ctx *ctx, pcol_particles *p, const pcol_box *b
       ovf_total += (int64_t)ctx->stotals_h[2];
     } else {
       if (timing) PCOL_HIP(hipEventRecord(ctx->ev[3], s));
-      PCOL_HIP(launch_finish(s, P, ctx->rank, ctx->out, ctx->epoch_d, part, tc, dt, ctx->G,
+      PCOL_HIP(launch_finish(s, P, ctx->rank, ctx->out, ctx->status, part, tc, dt, ctx->G,
                              nullptr));
     }
     if (timing) {
@@ -1318,7 +1314,6 @@ static pcol_status batch_enqueue(pcol_ctx *ctx, hipStream_t s, const Particles &
   const int ncell = bp->total_cells;
   PCOL_HIP(launch_fill_u32(s, bp->flags, 0u, 16));
   PCOL_HIP(launch_fill_u32(s, (unsigned int *)bp->totals, 0u, 8));
-  PCOL_HIP(launch_epoch_next(s, ctx->epoch_d));  // one step per replay
   PCOL_HIP(launch_fill_u32(s, (unsigned int *)ctx->ctr_d, 0u, sizeof(SweepCounters) / 4));
   PCOL_HIP(launch_breach(s, P, B, dt, 1));
   PCOL_HIP(launch_fill_i32(s, ctx->count, 0, ncell));
@@ -1364,8 +1359,7 @@ static pcol_status batch_enqueue(pcol_ctx *ctx, hipStream_t s, const Particles &
                                ctx->G, dt, ctx->status, ctx->key_j, ctx->key_t, &B));
   for (int k = 0; k < kmax; ++k) {
     PCOL_HIP(launch_resolve_sweep(s, n, ctx->rec, ctx->G, dt, e, P.m, ctx->key_j, ctx->key_t,
-                                  ctx->status, ctx->out, ctx->ctr_d, &B,
-                                  ctx->epoch_d));
+                                  ctx->status, ctx->out, ctx->ctr_d, &B));
     PCOL_HIP(launch_sweep_check(s, ctx->ctr_d, bp->flags, bp->totals, k == kmax - 1));
     PCOL_HIP(launch_slot_min(s, n, 0, ctx->cnt, ctx->slot_t, ctx->slot_j, ctx->K, ctx->status,
                              ctx->rec, ctx->key_j, ctx->key_t, ctx->ovf, ctx->ctr_d, bp->flags));
@@ -1373,7 +1367,7 @@ static pcol_status batch_enqueue(pcol_ctx *ctx, hipStream_t s, const Particles &
                                  ctx->start, ctx->G, dt, ctx->status, ctx->key_j,
                                  ctx->key_t, &B));
   }
-  PCOL_HIP(launch_finish(s, P, ctx->rank, ctx->out, ctx->epoch_d, part, tc, dt, ctx->G,
+  PCOL_HIP(launch_finish(s, P, ctx->rank, ctx->out, ctx->status, part, tc, dt, ctx->G,
                          &B));
   return PCOL_OK;
 }
@@ -1408,8 +1402,7 @@ static pcol_status batch_finish(pcol_ctx *ctx, const Particles &P, int32_t *part
   for (;;) {
     PCOL_HIP(launch_fill_u32(s, (unsigned int *)ctx->ctr_d, 0u, sizeof(SweepCounters) / 4));
     PCOL_HIP(launch_resolve_sweep(s, n, ctx->rec, ctx->G, dt, e, P.m, ctx->key_j, ctx->key_t,
-                                  ctx->status, ctx->out, ctx->ctr_d, &B,
-                                  ctx->epoch_d));
+                                  ctx->status, ctx->out, ctx->ctr_d, &B));
     PCOL_HIP(hipMemcpyAsync(ctx->ctr_h, ctx->ctr_d, sizeof(SweepCounters), hipMemcpyDeviceToHost, s));
     PCOL_HIP(hipStreamSynchronize(s));
     unsigned long long sp, sc;
@@ -1425,7 +1418,7 @@ static pcol_status batch_finish(pcol_ctx *ctx, const Particles &P, int32_t *part
                                  ctx->key_t, &B));
   }
   PCOL_HIP(launch_fill_u32(s, bp->flags + FLAG_UNFINISHED, 0u, 1));
-  PCOL_HIP(launch_finish(s, P, ctx->rank, ctx->out, ctx->epoch_d, part, tc, dt, ctx->G,
+  PCOL_HIP(launch_finish(s, P, ctx->rank, ctx->out, ctx->status, part, tc, dt, ctx->G,
                          &B));
   return PCOL_OK;
 }
@@ -1520,7 +1513,6 @@ static pcol_status batch_autotune(pcol_ctx *ctx, int nbox, const int64_t *box_of
         for (int k = 0; k < 6; ++k)
           PCOL_HIP(hipMemcpyAsync(dst[k], src[k], n * sizeof(double), hipMemcpyDeviceToDevice, s));
         PCOL_HIP(hipEventRecord(ctx->ev[0], s));
-        if ((st = graph_epoch(ctx, s)) != PCOL_OK) return st;
         PCOL_HIP(hipGraphLaunch(ex, s));
         PCOL_HIP(hipEventRecord(ctx->ev[1], s));
         PCOL_HIP(hipEventSynchronize(ctx->ev[1]));
@@ -1547,6 +1539,8 @@ extern "C" pcol_status pcol_step_batched(pcol_ctx *ctx, int32_t nbox, const int6
                                          double e, int32_t *partner, double *tcoll,
                                          pcol_batch_stats *stats) {
   if (!ctx) return PCOL_E_INVALID;
+  if (ctx->opts.order == 1)
+    return fail(ctx, PCOL_E_INVALID, "the literal order (opts.order = 1) is built for pcol_step only");
   if (nbox < 1 || !box_off || !boxes || !p) return fail(ctx, PCOL_E_INVALID, "bad batch arguments");
   pcol_box any{{1.0, 1.0, 1.0}};
   pcol_status st = check_common(ctx, p, &any, dt);
@@ -1615,7 +1609,6 @@ extern "C" pcol_status pcol_step_batched(pcol_ctx *ctx, int32_t nbox, const int6
       bp->cap_tc = tc;
       for (int k = 0; k < 8; ++k) bp->cap_ptr[k] = ptrs[k];
     }
-    if ((st = graph_epoch(ctx, ctx->stream)) != PCOL_OK) return st;
     PCOL_HIP(hipGraphLaunch(bp->exec, ctx->stream));
     PCOL_HIP(batch_readback(ctx, bp));
     const unsigned int err = bp->flags_h[FLAG_ERR];

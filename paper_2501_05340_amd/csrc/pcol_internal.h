@@ -26,12 +26,12 @@ struct alignas(16) Rec {
 // must be recomputed; FREE has no contact left in the step; COLLIDED is done.
 enum : uint8_t { ST_ACTIVE = 0, ST_FREE = 1, ST_COLLIDED = 2, ST_DIRTY = 3 };
 
-// End-of-step state of one sphere in cell-sorted order (64 B), copied to the
-// caller's order by a final gather.
+// End-of-step state of one collided sphere in cell-sorted order (64 B), copied
+// to the caller's order by a final gather.
 struct alignas(16) OutRec {
   double x, y, z, vx, vy, vz, t;
-  int partner;          // caller index, -1 = none
-  unsigned int epoch;   // step that wrote the record (a stale record never matches)
+  int partner;          // caller index
+  unsigned int pad;
 };
 
 // Uniform grid over the periodic box.  Cells are numbered (cz * nc1 + cy) * nc0 + cx,
@@ -101,6 +101,13 @@ struct ReachOut {
   unsigned int bad;          // bit 0: non-finite / r <= 0 / m <= 0; bit 1: position outside [0, L)
   unsigned int maxcell;      // filled by the scan
   unsigned int hist[RHO_BINS];  // extents by rho_bin
+};
+
+// The grid of the literal order's space-filling curve: nc cells of side h =
+// L / nc per axis (nc <= 2048), independent of the pair-test grid.
+struct CurveGrid {
+  int nc[3];
+  double h[3];
 };
 
 // Per-sweep counters the host reads back.  Sums are spread over NSHARD
@@ -414,30 +421,30 @@ hipError_t launch_slot_min(hipStream_t s, int n, int first, const int *cnt, cons
                            const int *slot_j, int K, uint8_t *status, const Rec *rec, int *key_j,
                            double *key_t, int *ovf_list, SweepCounters *ctr,
                            const unsigned int *flags, const int *list = nullptr, int nlist = 0,
-                           const Grid *G = nullptr);  // G: walls of the single box (none: periodic)
+                           const Grid *G = nullptr,  // G: walls of the single box (none: periodic)
+                           const unsigned long long *crank = nullptr);  // literal order's ranks
 hipError_t launch_gather_exact(hipStream_t s, const int *list, int nlist, const unsigned int *nlist_dev,
                                int select, const Rec *rec, const int *start, const Grid &G,
                                double dt, uint8_t *status, int *key_j, double *key_t,
-                               const BatchDev *B);
+                               const BatchDev *B, const unsigned long long *crank = nullptr);
+hipError_t launch_curve_rank(hipStream_t s, const Rec *rec, int n, const CurveGrid &C,
+                             unsigned long long *crank);
 // spin (nullable): friction and spins (the pair's sphere of smaller sorted index
 // resolves both sides and writes both spins in place)
 hipError_t launch_resolve_sweep(hipStream_t s, int n, const Rec *rec, const Grid &G, double dt,
                                 double e, const double *mass, const int *key_j,
                                 const double *key_t, uint8_t *status, OutRec *out,
                                 SweepCounters *ctr,
-                                const BatchDev *B, const unsigned int *epoch,
+                                const BatchDev *B,
                                 const int *list = nullptr, int nlist = 0,
                                 const Spin *spin = nullptr);
-// next step's epoch (one thread); every OutRec epoch starts at 0xffffffff
-hipError_t launch_epoch_next(hipStream_t s, unsigned int *epoch);
-hipError_t launch_init_out(hipStream_t s, OutRec *out, int64_t n);
 // list (read back from off[(n + 255) / 256] entries) of the ACTIVE or
 // DIRTY spheres; count and off need (n + 255) / 256 + 1 entries, blocksum
 // ((n + 255) / 256) / 4096 + 2
 hipError_t launch_keep_list(hipStream_t s, const uint8_t *status, int n, int *count, int *off,
                             int *blocksum, ReachOut *scratch_out, int *list);
 hipError_t launch_finish(hipStream_t s, const Particles &P, const int *rank, const OutRec *out,
-                         const unsigned int *epoch, int *partner, double *tcoll, double dt,
+                         const uint8_t *status, int *partner, double *tcoll, double dt,
                          const Grid &G, const BatchDev *B);
 hipError_t launch_fill_box_of(hipStream_t s, int nbox, const int64_t *box_off, int *box_of);
 hipError_t launch_breach(hipStream_t s, const Particles &P, const BatchDev &B, double dt,

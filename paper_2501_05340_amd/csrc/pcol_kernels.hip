@@ -534,41 +534,55 @@ __device__ __forceinline__ bool push_survivor(bool pass, int i, int g, SurvivorQ
   return true;
 }
 
-// One home sphere (FP32 record in scalar registers) against the lane's
-// candidate: the same filter in binary32 with the contact distance inflated by
-// the band; survivors are decided by the binary64 rule (queued, or at once
-// from the full records).
-template <bool SHIFT, bool MASK>
-__device__ __forceinline__ void pair32(const DetectArgs &A, const Grid &G, int g, int thr, int code,
-                                       float bx, float by, float bz, float br, float bvx,
-                                       float bvy, float bvz, int i, float ax, float ay, float az,
-                                       float ar, float avx, float avy, float avz,
-                                       SurvivorQueue &Q) {
-  const float d0 = bx - ax, d1 = by - ay, d2 = bz - az;
-  const float u0 = bvx - avx, u1 = bvy - avy, u2 = bvz - avz;
-  const float sb = (ar + br) * A.kband;
+// Append the survivors of two home spheres i0 and i1 against the lane's
+// candidate g (pass flags p0 and p1) to the queue, which has room for two
+// wave's worth (the caller makes sure of it).  One wave-wide test when neither
+// passes anywhere, the common case.
+__device__ __forceinline__ void push_two(bool p0, bool p1, int i0, int i1, int g,
+                                         SurvivorQueue &Q) {
+  const unsigned long long m0 = __ballot(p0), m1 = __ballot(p1);
+  if (!(m0 | m1)) return;
+  const unsigned long long below = (1ull << __lane_id()) - 1ull;
+  const int c0 = __popcll(m0), c1 = __popcll(m1);
+  if (p0) Q.q[Q.n + __popcll(m0 & below)] = make_int2(i0, g);
+  if (p1) Q.q[Q.n + c0 + __popcll(m1 & below)] = make_int2(i1, g);
+  Q.n += c0 + c1;
+  Q.pushed += c0 + c1;
+}
+
+// One home sphere (FP32 record) against the lane's candidate: the same filter in
+// binary32 with the contact distance inflated by the band.  Survivors are
+// decided by the binary64 rule (flush_survivors).
+template <bool MASK>
+__device__ __forceinline__ bool pass32(const DetectArgs &A, int thr, float bx, float by, float bz,
+                                       float br, float bvx, float bvy, float bvz, int i,
+                                       const Rec32 &h) {
+  const float d0 = bx - h.x, d1 = by - h.y, d2 = bz - h.z;
+  const float u0 = bvx - h.vx, u1 = bvy - h.vy, u2 = bvz - h.vz;
+  const float sb = (h.r + br) * A.kband;
   const float bb = __builtin_fmaf(d0, u0, __builtin_fmaf(d1, u1, d2 * u2));
   const float q = __builtin_fmaf(d0, d0, __builtin_fmaf(d1, d1, d2 * d2));
   const float cc = __builtin_fmaf(-sb, sb, q);
-  const bool pass = (!MASK || i < thr) && __builtin_fmaf(bb, A.dt2f, cc) <= 0.0f;
-  if (!push_survivor(pass, i, g, Q) && pass) {
-    const crec_ptr hrec = (crec_ptr)A.rec;
-    const Rec b = A.rec[g];
-    const double xi = hrec[i].x, yi = hrec[i].y, zi = hrec[i].z, ri = hrec[i].r;
-    const double vxi = hrec[i].vx, vyi = hrec[i].vy, vzi = hrec[i].vz;
-    double e0 = b.x - xi, e1 = b.y - yi, e2 = b.z - zi;
-    if (SHIFT) {
-      e0 = e0 + code_shift(code & 3, G.sL[0]);
-      e1 = e1 + code_shift((code >> 2) & 3, G.sL[1]);
-      e2 = e2 + code_shift((code >> 4) & 3, G.sL[2]);
-    }
-    double t;
-    if (contact_time(e0, e1, e2, b.vx - vxi, b.vy - vyi, b.vz - vzi, ri + b.r, A.dt, t))
-      record_contact(A, i, g, t);
-  }
+  return (!MASK || i < thr) && __builtin_fmaf(bb, A.dt2f, cc) <= 0.0f;
 }
 
-template <bool SHIFT, bool MASK, typename HP>
+// A home's FP32 record from LDS or through the scalar cache (constant address
+// space), field by field.
+template <typename HP>
+__device__ __forceinline__ Rec32 home32(HP p, int k) {
+  Rec32 h;
+  h.x = p[k].x;
+  h.y = p[k].y;
+  h.z = p[k].z;
+  h.r = p[k].r;
+  h.vx = p[k].vx;
+  h.vy = p[k].vy;
+  h.vz = p[k].vz;
+  h.pad = 0.f;
+  return h;
+}
+
+template <bool MASK, typename HP>
 __device__ __forceinline__ void detect_chunk32(const DetectArgs &A, const Grid &G, HP p, int h0,
                                                int h1, int g, int thr, int code, double ox,
                                                double oy, double oz, SurvivorQueue &Q) {
@@ -589,15 +603,19 @@ __device__ __forceinline__ void detect_chunk32(const DetectArgs &A, const Grid &
     br = 0.f;
   }
   int i = h0;
-  for (; i + 1 < h1; i += 2, p += 2) {
-    pair32<SHIFT, MASK>(A, G, g, thr, code, bx, by, bz, br, bvx, bvy, bvz, i, p[0].x, p[0].y,
-                        p[0].z, p[0].r, p[0].vx, p[0].vy, p[0].vz, Q);
-    pair32<SHIFT, MASK>(A, G, g, thr, code, bx, by, bz, br, bvx, bvy, bvz, i + 1, p[1].x, p[1].y,
-                        p[1].z, p[1].r, p[1].vx, p[1].vy, p[1].vz, Q);
+  for (;;) {
+    // two homes per step while the queue has room for their survivors; a full
+    // queue (rare) is decided here, outside the loop
+    for (; i < h1 && Q.n <= Q.cap - 2 * WAVE; i += 2) {
+      const bool two = i + 1 < h1;  // an odd last home pairs with itself, never passing twice
+      const Rec32 ha = home32(p, i - h0), hb = home32(p, two ? i + 1 - h0 : i - h0);
+      const bool p0 = pass32<MASK>(A, thr, bx, by, bz, br, bvx, bvy, bvz, i, ha);
+      const bool p1 = two && pass32<MASK>(A, thr, bx, by, bz, br, bvx, bvy, bvz, i + 1, hb);
+      push_two(p0, p1, i, i + 1, g, Q);
+    }
+    if (i >= h1) break;
+    flush_survivors(A, G, Q);
   }
-  if (i < h1)
-    pair32<SHIFT, MASK>(A, G, g, thr, code, bx, by, bz, br, bvx, bvy, bvz, i, p[0].x, p[0].y,
-                        p[0].z, p[0].r, p[0].vx, p[0].vy, p[0].vz, Q);
 }
 
 // Pair tests of one home cell (see k_detect_half).  `start` points at the first
@@ -769,30 +787,16 @@ __device__ __forceinline__ void detect_cell(const DetectArgs &A, const Grid &G, 
       const double ox = (cx + 0.5) * G.h[0], oy = (cy + 0.5) * G.h[1], oz = (cz + 0.5) * G.h[2];
       if (LDSI) {
         const Rec32 *p = (const Rec32 *)lds_raw;
-        if (base < rl[0]) {
-          if (any_shift)
-            detect_chunk32<true, true>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, Q);
-          else
-            detect_chunk32<false, true>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, Q);
-        } else {
-          if (any_shift)
-            detect_chunk32<true, false>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, Q);
-          else
-            detect_chunk32<false, false>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, Q);
-        }
+        if (base < rl[0])
+          detect_chunk32<true>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, Q);
+        else
+          detect_chunk32<false>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, Q);
       } else {
         const crec32_ptr p = (crec32_ptr)A.rec32 + h0;
-        if (base < rl[0]) {
-          if (any_shift)
-            detect_chunk32<true, true>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, Q);
-          else
-            detect_chunk32<false, true>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, Q);
-        } else {
-          if (any_shift)
-            detect_chunk32<true, false>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, Q);
-          else
-            detect_chunk32<false, false>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, Q);
-        }
+        if (base < rl[0])
+          detect_chunk32<true>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, Q);
+        else
+          detect_chunk32<false>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, Q);
       }
     }
   }
@@ -958,7 +962,7 @@ __global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
 // cells: the survivor queue carries over between them and is decided a wave at
 // a time (a cell of 13 spheres leaves about 13 survivors, so deciding them
 // per cell runs the rule's square root and division on a fifth of the lanes).
-// Register-limited to 5 waves per SIMD (a few spills in the per-cell set-up).
+// Register-limited to 5 waves per SIMD (96 registers, no spills).
 __global__ __launch_bounds__(WAVE, 5) void k_detect_half64g(DetectArgs A) {
   __shared__ int2 survq[QCAP];
   __shared__ HomeQ hq[WAVE];
@@ -1065,9 +1069,11 @@ hipError_t launch_detect_half(hipStream_t s, const DetectArgs &A) {
 // ---------------------------------------------------------------- a5/a7: partner from contact slots
 
 // Earliest partner (rule 2: exact binary64 t, ties to the smaller caller index)
-// of each sphere among its recorded contacts whose partner has not collided.
-// The contact set of a sphere only shrinks over the sweeps of a step, so the
-// slots written by the sweep-1 detect are complete for every later sweep.
+// of each sphere among its recorded contacts whose partner has not collided;
+// with crank given (the literal order), the contact of smallest curve rank
+// instead (see k_curve_rank).  The contact set of a sphere only shrinks over
+// the sweeps of a step, so the slots written by the sweep-1 detect are
+// complete for every later sweep.
 // first = 1: every sphere (sweep 1); first = 0: only DIRTY spheres, which
 // become ACTIVE again.  Spheres with more contacts than slots are queued for
 // the exact search (rare; one atomic per wave that has one).  Slots are
@@ -1077,7 +1083,8 @@ __global__ __launch_bounds__(256) void k_slot_min(int n, int first, const int *c
                                                   uint8_t *status, const Rec *rec, int *key_j,
                                                   double *key_t, int *ovf_list,
                                                   SweepCounters *ctr, const unsigned int *flags,
-                                                  const int *list, int nlist, Grid G) {
+                                                  const int *list, int nlist, Grid G,
+                                                  const unsigned long long *crank) {
   if (flags && (flags[FLAG_ERR] || flags[FLAG_DONE])) return;
   const int t = blockIdx.x * 256 + threadIdx.x;
   const int i = list && t < nlist ? list[t] : t;
@@ -1095,6 +1102,7 @@ __global__ __launch_bounds__(256) void k_slot_min(int n, int first, const int *c
       } else {
         double bt = INFINITY;
         int bj = -1;
+        unsigned long long br = ~0ull;  // literal order: curve rank of the best contact
         // between walls a contact counts only before both centres reach a wall
         double ti = INFINITY;
         if (G.walls) {
@@ -1109,7 +1117,14 @@ __global__ __launch_bounds__(256) void k_slot_min(int n, int first, const int *c
             const Rec b = rec[j];
             if (!(t <= ti) || !(t <= time_to_wall(b.x, b.y, b.z, b.vx, b.vy, b.vz, G))) continue;
           }
-          if (t < bt || (bj >= 0 && t == bt && rec[j].o < rec[bj].o)) {
+          if (crank) {
+            const unsigned long long rj = crank[j];
+            if (rj < br) {
+              br = rj;
+              bt = t;
+              bj = j;
+            }
+          } else if (t < bt || (bj >= 0 && t == bt && rec[j].o < rec[bj].o)) {
             bt = t;
             bj = j;
           }
@@ -1129,13 +1144,59 @@ hipError_t launch_slot_min(hipStream_t s, int n, int first, const int *cnt, cons
                            const int *slot_j, int K, uint8_t *status, const Rec *rec, int *key_j,
                            double *key_t, int *ovf_list, SweepCounters *ctr,
                            const unsigned int *flags, const int *list, int nlist,
-                           const Grid *G) {
+                           const Grid *G, const unsigned long long *crank) {
   const int items = list ? nlist : n;
   if (items <= 0) return hipSuccess;
   const Grid none{};  // walls = 0: periodic
   hipLaunchKernelGGL(k_slot_min, dim3((items + 255) / 256), dim3(256), 0, s, n, first, cnt, slot_t,
                      slot_j, K, status, rec, key_j, key_t, ovf_list, ctr, flags, list, nlist,
-                     G ? *G : none);
+                     G ? *G : none, crank);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- the literal order's ranks
+
+// Morton (Z-order) code of a cell: the bits of cx, cy, cz (each below 2^11)
+// interleaved, x lowest.
+__device__ __forceinline__ unsigned long long morton3(unsigned int cx, unsigned int cy,
+                                                      unsigned int cz) {
+  unsigned long long k = 0ull;
+#pragma unroll
+  for (int b = 0; b < 11; ++b) {
+    k |= (unsigned long long)((cx >> b) & 1u) << (3 * b);
+    k |= (unsigned long long)((cy >> b) & 1u) << (3 * b + 1);
+    k |= (unsigned long long)((cz >> b) & 1u) << (3 * b + 2);
+  }
+  return k;
+}
+
+// Rank of every sphere in the order the paper's traversal visits it (Sec.
+// "Collision Operator": elements along a space-filling curve, particles of an
+// element one after another): the Morton code of its cell on the curve grid C
+// (nc cells of side h per axis) above its caller index,
+// crank = code << 31 | o, in cell-sorted order.  A sphere's cell is
+// floor(x / h) in binary64, clamped to nc - 1.
+__global__ __launch_bounds__(256) void k_curve_rank(const Rec *rec, int n, CurveGrid C,
+                                                    unsigned long long *crank) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const Rec a = rec[i];
+  const double p[3] = {a.x, a.y, a.z};
+  unsigned int c[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double q = floor(p[k] / C.h[k]);
+    if (q < 0.0) q = 0.0;
+    if (q > (double)(C.nc[k] - 1)) q = (double)(C.nc[k] - 1);
+    c[k] = (unsigned int)q;
+  }
+  crank[i] = morton3(c[0], c[1], c[2]) << 31 | (unsigned long long)(unsigned int)a.o;
+}
+
+hipError_t launch_curve_rank(hipStream_t s, const Rec *rec, int n, const CurveGrid &C,
+                             unsigned long long *crank) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_curve_rank, dim3((n + 255) / 256), dim3(256), 0, s, rec, n, C, crank);
   return hipGetLastError();
 }
 
@@ -1350,9 +1411,10 @@ hipError_t launch_detect_wide(hipStream_t s, const DetectArgs &A, const int *fir
   return hipGetLastError();
 }
 
-// Earliest partner (rule 2: exact binary64 t, ties to the smaller caller index)
-// by an exact search of the sphere's search box (the 27 surrounding cells, or
-// the wider box of a split grid, in both layers), minimum image by rule 1.
+// Earliest partner (rule 2: exact binary64 t, ties to the smaller caller index;
+// with crank given, the contact of smallest curve rank) by an exact search of
+// the sphere's search box (the 27 surrounding cells, or the wider box of a
+// split grid, in both layers), minimum image by rule 1.
 // One wave per sphere; lanes over candidates; the wave reduces (t, caller
 // index) exactly.  Spheres come from `list` (length nlist, or *nlist_dev when
 // given) or, with list NULL, are all i < nlist whose status is `select`
@@ -1364,7 +1426,8 @@ __global__ __launch_bounds__(256) void k_gather_exact(const int *list, int nlist
                                                       const unsigned int *nlist_dev, int select,
                                                       const Rec *rec, const int *start, Grid G0,
                                                       double dt, uint8_t *status, int *key_j,
-                                                      double *key_t, BatchDev B) {
+                                                      double *key_t, BatchDev B,
+                                                      const unsigned long long *crank) {
   if (B.flags && (B.flags[FLAG_ERR] || B.flags[FLAG_DONE])) return;
   const int lane = __lane_id();
   const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
@@ -1385,6 +1448,7 @@ __global__ __launch_bounds__(256) void k_gather_exact(const int *list, int nlist
     const int cz = cell_coord(a.z, G.inv_h[2], G.nc[2]);
     double bt = INFINITY;
     int bo = 0x7fffffff, bj = -1;
+    unsigned long long br = ~0ull;  // literal order: curve rank of the best contact
     for (int layer = 0; layer < (G.layer2 ? 2 : 1); ++layer) {
       search_box_runs(G, st, layer ? G.layer2 : 0, cx, cy, cz, k, [&](int s0, int s1) {
         for (int j = s0 + lane; j < s1; j += WAVE) {
@@ -1394,7 +1458,14 @@ __global__ __launch_bounds__(256) void k_gather_exact(const int *list, int nlist
           double t;
           if (pair_time_walls(a, b, G, dt, t)) {
             const int o = b.o;
-            if (t < bt || (t == bt && o < bo)) {
+            if (crank) {
+              const unsigned long long rj = crank[j];
+              if (rj < br) {
+                br = rj;
+                bt = t;
+                bj = j;
+              }
+            } else if (t < bt || (t == bt && o < bo)) {
               bt = t;
               bo = o;
               bj = j;
@@ -1407,10 +1478,12 @@ __global__ __launch_bounds__(256) void k_gather_exact(const int *list, int nlist
       const double t2 = __shfl_xor(bt, o);
       const int o2 = __shfl_xor(bo, o);
       const int j2 = __shfl_xor(bj, o);
-      if (t2 < bt || (t2 == bt && o2 < bo)) {
+      const unsigned long long r2 = __shfl_xor(br, o);
+      if (crank ? r2 < br : (t2 < bt || (t2 == bt && o2 < bo))) {
         bt = t2;
         bo = o2;
         bj = j2;
+        br = r2;
       }
     }
     if (lane == 0) {
@@ -1424,14 +1497,14 @@ __global__ __launch_bounds__(256) void k_gather_exact(const int *list, int nlist
 hipError_t launch_gather_exact(hipStream_t s, const int *list, int nlist, const unsigned int *nlist_dev,
                                int select, const Rec *rec, const int *start, const Grid &G,
                                double dt, uint8_t *status, int *key_j, double *key_t,
-                               const BatchDev *B) {
+                               const BatchDev *B, const unsigned long long *crank) {
   int64_t waves = nlist_dev ? 8192 : nlist;
   if (waves <= 0) return hipSuccess;
   if (waves > 8192) waves = 8192;
   const int blocks = (int)((waves + 3) / 4);
   BatchDev none{};
   hipLaunchKernelGGL(k_gather_exact, dim3(blocks), dim3(256), 0, s, list, nlist, nlist_dev, select,
-                     rec, start, G, dt, status, key_j, key_t, B ? *B : none);
+                     rec, start, G, dt, status, key_j, key_t, B ? *B : none, crank);
   return hipGetLastError();
 }
 
@@ -1451,7 +1524,7 @@ __global__ __launch_bounds__(256) void k_resolve_sweep(int n, const Rec *rec, Gr
                                                        const int *key_j, const double *key_t,
                                                        uint8_t *status, OutRec *out,
                                                        SweepCounters *ctr, BatchDev B,
-                                                       const unsigned int *epoch, const int *list,
+                                                       const int *list,
                                                        int nlist, Spin S) {
   if (B.flags && (B.flags[FLAG_ERR] || B.flags[FLAG_DONE])) return;
   const int ti = blockIdx.x * 256 + threadIdx.x;
@@ -1474,15 +1547,14 @@ __global__ __launch_bounds__(256) void k_resolve_sweep(int n, const Rec *rec, Gr
           const double ma = mass[a.o], mb = mass[b.o];
           const double wa[3] = {S.wx[a.o], S.wy[a.o], S.wz[a.o]};
           const double wb[3] = {S.wx[b.o], S.wy[b.o], S.wz[b.o]};
-          const unsigned int ep = *epoch;
           double xo[3], vo[3], wo[3];
           resolve_one_spin(a, b, ma, mb, wa, wb, G0, t, dt, e, S.mu, xo, vo, wo);
-          out[i] = OutRec{xo[0], xo[1], xo[2], vo[0], vo[1], vo[2], t, b.o, ep};
+          out[i] = OutRec{xo[0], xo[1], xo[2], vo[0], vo[1], vo[2], t, b.o, 0u};
           S.wx[a.o] = wo[0];
           S.wy[a.o] = wo[1];
           S.wz[a.o] = wo[2];
           resolve_one_spin(b, a, mb, ma, wb, wa, G0, t, dt, e, S.mu, xo, vo, wo);
-          out[p] = OutRec{xo[0], xo[1], xo[2], vo[0], vo[1], vo[2], t, a.o, ep};
+          out[p] = OutRec{xo[0], xo[1], xo[2], vo[0], vo[1], vo[2], t, a.o, 0u};
           S.wx[b.o] = wo[0];
           S.wy[b.o] = wo[1];
           S.wz[b.o] = wo[2];
@@ -1510,7 +1582,7 @@ __global__ __launch_bounds__(256) void k_resolve_sweep(int n, const Rec *rec, Gr
         o.vz = vo[2];
         o.t = t;
         o.partner = b.o;
-        o.epoch = *epoch;
+        o.pad = 0u;
         out[i] = o;
         status[i] = ST_COLLIDED;
         if (i < p) npair = 1ull;
@@ -1525,32 +1597,14 @@ __global__ __launch_bounds__(256) void k_resolve_sweep(int n, const Rec *rec, Gr
 hipError_t launch_resolve_sweep(hipStream_t s, int n, const Rec *rec, const Grid &G, double dt,
                                 double e, const double *mass, const int *key_j,
                                 const double *key_t, uint8_t *status, OutRec *out,
-                                SweepCounters *ctr, const BatchDev *B, const unsigned int *epoch,
+                                SweepCounters *ctr, const BatchDev *B,
                                 const int *list, int nlist, const Spin *spin) {
   const int items = list ? nlist : n;
   if (items <= 0) return hipSuccess;
   BatchDev none{};
   hipLaunchKernelGGL(k_resolve_sweep, dim3((items + 255) / 256), dim3(256), 0, s, n, rec, G, dt,
-                     e, mass, key_j, key_t, status, out, ctr, B ? *B : none, epoch, list, nlist,
+                     e, mass, key_j, key_t, status, out, ctr, B ? *B : none, list, nlist,
                      spin ? *spin : Spin{nullptr, nullptr, nullptr, 0.0});
-  return hipGetLastError();
-}
-
-__global__ void k_epoch_next(unsigned int *epoch) { *epoch += 1u; }
-
-hipError_t launch_epoch_next(hipStream_t s, unsigned int *epoch) {
-  hipLaunchKernelGGL(k_epoch_next, dim3(1), dim3(1), 0, s, epoch);
-  return hipGetLastError();
-}
-
-__global__ __launch_bounds__(256) void k_init_out(OutRec *out, int64_t n) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) out[i].epoch = 0xffffffffu;
-}
-
-hipError_t launch_init_out(hipStream_t s, OutRec *out, int64_t n) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_init_out, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, n);
   return hipGetLastError();
 }
 
@@ -1594,21 +1648,24 @@ hipError_t launch_keep_list(hipStream_t s, const uint8_t *status, int n, int *co
 }
 
 // a8 and the copy back: the end-of-step state of every sphere in the caller's
-// order (coalesced writes).  A sphere that collided takes the output record its
-// resolve wrote (stamped with this step's epoch); any other flies the whole
-// step from its start state, still in the caller's arrays (rule 5).
+// order (coalesced writes).  A sphere whose status (sorted order) says it
+// collided this step takes the output record its resolve wrote; any other
+// flies the whole step from its start state, still in the caller's arrays
+// (rule 5).  Only collided spheres read their 64-B output record; the others
+// read one status byte (a 1-B-per-sphere array that stays in the device's
+// last-level cache).
 __global__ __launch_bounds__(256) void k_finish(Particles P, const int *rank,
-                                                const OutRec *out, const unsigned int *epoch,
+                                                const OutRec *out, const uint8_t *status,
                                                 int *partner, double *tcoll, double dt, Grid G0,
                                                 BatchDev B) {
   if (B.flags && (B.flags[FLAG_ERR] || B.flags[FLAG_UNFINISHED])) return;
   const int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (o >= P.n) return;
-  const int q = rank[o];
   double x, y, z, vx, vy, vz, t;
   int pj;
-  const OutRec r = out[q];
-  if (r.epoch == *epoch) {  // written by this step's resolve: collided
+  const int q = rank[o];
+  if (status[q] == ST_COLLIDED) {
+    const OutRec r = out[q];
     x = r.x;
     y = r.y;
     z = r.z;
@@ -1640,12 +1697,12 @@ __global__ __launch_bounds__(256) void k_finish(Particles P, const int *rank,
 }
 
 hipError_t launch_finish(hipStream_t s, const Particles &P, const int *rank, const OutRec *out,
-                         const unsigned int *epoch, int *partner, double *tcoll, double dt,
+                         const uint8_t *status, int *partner, double *tcoll, double dt,
                          const Grid &G, const BatchDev *B) {
   if (P.n <= 0) return hipSuccess;
   BatchDev none{};
   hipLaunchKernelGGL(k_finish, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, s, P, rank, out,
-                     epoch, partner, tcoll, dt, G, B ? *B : none);
+                     status, partner, tcoll, dt, G, B ? *B : none);
   return hipGetLastError();
 }
 
