@@ -6,18 +6,24 @@ cube, N(0, 1) velocities, e = 0.8, dt = 0.4; seeded random sequential
 placement.  A step is the whole path: validation and reach, binning, the
 pair-test sweep, partner selection and resolve sweeps until none is left, free
 flight and wrap.  Every timed step starts from the configured input: the
-positions and velocities are restored from a device copy (inside the timed
-region) before each step, so each step processes the same batch.
+positions and velocities are restored from a device copy before each step,
+outside its timed interval (each interval is bracketed by device
+synchronisations), so each step processes the same batch.
 
-Prints one JSON line: particles stepped per second (value), pair tests per
-second of the detect kernel, the detect kernel's ALU roofline fraction, and the
-CPU oracle timed on a bounded sample of the same workload.  Beside the plain
-FP64 path it reports the binary32 filter form on the same input (it decides
-its survivors by the binary64 rule, so both compute the same step bitwise),
-the batched form
-(512 uneven boxes, about 8M spheres, one captured graph per step, against a
-loop of single-box steps) and the adjoint form (10-step rollout of 1M spheres,
-forward and backward).
+Prints one JSON line: particles stepped per second (value); pair tests per
+second on the reference grid (cell side L / floor(L / reach), the 27 cells
+around each sphere, unordered pairs, one full detection pass) for the GPU and
+for the CPU oracle; the detect kernel's FP64 issue fraction with its counted and
+algorithmic HBM fractions; every phase's time and fraction of the HBM peak on
+its algorithmic bytes; and the CPU oracle timed on a bounded sample of the same
+workload (median of 3, all host threads, with single-thread times).  Beside the
+plain FP64 path it reports the binary32 filter form on the same input (its
+survivors are decided by the binary64 rule, so both compute the same step
+bitwise) and both forms' pair-set mismatch against the oracle on the sample;
+the batched form (512 uneven boxes, about 8M spheres, one captured graph per
+step, against a loop of single-box steps); the literal collision order; the
+friction, walls and cell-ordered forms; the deposition; and the adjoint form
+(10-step rollout of 1M spheres, forward and backward).
 """
 from __future__ import annotations
 
@@ -41,17 +47,19 @@ FLOPS_PER_PAIR_TEST = 15
 # 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz: binary64 vector operations per
 # second (an FMA is one; the published 78.6 TFLOP/s counts it as two flops)
 PEAK_FP64_OPS = 256 * 4 * 16 * 2.4e9
+PEAK_HBM = 8e12  # bytes/s
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "step_poly16M_fp64_fp32.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "step_poly16M_counters.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2501_05340_amd", "csrc", f)
                   for f in ("pcol_kernels.hip", "pcol_internal.h")]
 
 
 def measured_traffic():
-    """HBM bytes per launch of the FP64 detect kernel from the committed counter
-    summary (FETCH_SIZE + WRITE_SIZE, scaled by the plain-copy calibration), or
-    None when the kernel sources changed since the counters were taken."""
+    """Counted HBM bytes from the committed counter summary of one 16M FP64 step
+    (FETCH_SIZE + WRITE_SIZE, scaled by the plain-copy calibration): the detect
+    kernel's bytes per launch and each phase's bytes per step, or None when the
+    kernel sources changed since the counters were taken."""
     import hashlib
     try:
         text = open(TRAFFIC_PROFILE).read()
@@ -59,13 +67,49 @@ def measured_traffic():
         sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)).hexdigest()
         if vals.get("kernel_sources_sha256", "").strip() != sha:
             return None
-        return float(vals["traffic_bytes_per_launch"])
+        return {"detect_launch": float(vals["traffic_bytes_per_launch"]),
+                "phases": {k.split(".", 1)[1]: float(v) for k, v in vals.items()
+                           if k.startswith("phase_counted_bytes.")}}
     except (OSError, KeyError, ValueError):
         return None
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def ref_grid_pair_tests(x, y, z, L, reach, active=None) -> int:
+    """Unordered candidate pairs among the active spheres in the 27-cell stencil of
+    the reference grid, cell side L_k / floor(L_k / reach) (at least 3 cells per
+    axis): the pairs a plain cell-list search with cells of the reach tests,
+    whatever grid a code actually uses, so that GPU and oracle are counted alike."""
+    import numpy as np
+    nc = [int(np.floor(L[a] / reach)) for a in range(3)]
+    assert min(nc) >= 3, "reference grid needs 3 cells per axis"
+    keep = slice(None) if active is None else np.asarray(active, dtype=bool)
+    c = [np.minimum(np.floor(np.asarray(p)[keep] / (L[a] / nc[a])).astype(np.int64), nc[a] - 1)
+         for a, p in enumerate((x, y, z))]
+    cnt = np.bincount((c[2] * nc[1] + c[1]) * nc[0] + c[0],
+                      minlength=nc[0] * nc[1] * nc[2]).reshape(nc[2], nc[1], nc[0])
+    total = int((cnt * (cnt - 1) // 2).sum())
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if (dz, dy, dx) <= (0, 0, 0):
+                    continue  # 13 forward neighbours: every unordered cell pair once
+                total += int((cnt * np.roll(cnt, (-dz, -dy, -dx), axis=(0, 1, 2))).sum())
+    return total
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 def make_workload(args):
@@ -77,24 +121,103 @@ def make_workload(args):
     return box
 
 
+SINGLE_THREAD = """
+import json, statistics, sys, time
+sys.path.insert(0, {root!r})
+import oracle, workloads
+out = {{}}
+for name, box in (("config1", workloads.config(1)), ("config2_recipe_50k", workloads.config(2, n=50000))):
+    ts = []
+    for k in range(3):
+        t0 = time.perf_counter()
+        r = oracle.step(box)
+        ts.append(time.perf_counter() - t0)
+    t = statistics.median(ts)
+    out[name] = {{"n": box.n, "seconds_median_of_3": t, "particles_per_s": box.n / t,
+                  "pairs": r.n_pairs, "threads": oracle.max_threads()}}
+print(json.dumps(out))
+"""
+
+
 def cpu_baseline(args):
     """The oracle (plain FP64 C, OpenMP) on a bounded sample: the same recipe at
-    1M spheres (same density and velocity law, so the per-sphere cost matches)."""
+    1M spheres (same density and velocity law, so the per-sphere cost matches),
+    the whole step and one full detection pass each timed as the median of 3 runs
+    on all host threads; single-thread times of configs 1 (2,000 spheres) and 2
+    (its recipe at 50,000 spheres) in a child process with one OpenMP thread."""
+    import subprocess
     import oracle
     import workloads
     n = args.cpu_sample
     box = workloads.make_box(n, seed=103, phi=0.3, lognormal=(1.0, 0.25, 0.5, 2.0), e=0.8)
-    t0 = time.perf_counter()
-    res = oracle.step(box)
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    times, res = [], None
+    for k in range(3):
+        t0 = time.perf_counter()
+        res = oracle.step(box)
+        times.append(time.perf_counter() - t0)
+    t_step = statistics.median(times)
+    dtimes = []
+    for k in range(3):
+        t0 = time.perf_counter()
+        _, _, tests = oracle.earliest(box)
+        dtimes.append(time.perf_counter() - t0)
+    t_det = statistics.median(dtimes)
+    ref = ref_grid_pair_tests(box.x, box.y, box.z, box.L, res.reach)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    single = None
+    try:
+        r = subprocess.run([sys.executable, "-c", SINGLE_THREAD.format(root=ROOT)],
+                           capture_output=True, text=True, env=env, timeout=300)
+        single = json.loads(r.stdout.strip().splitlines()[-1]) if r.returncode == 0 else None
+    except (subprocess.TimeoutExpired, ValueError, IndexError):
+        single = None
+    threads = oracle.max_threads()
     return {
-        "value": n / dt, "unit": "particles/s", "cores": cores, "kind": "oracle",
+        "value": n / t_step, "unit": "particles/s", "cores": threads, "kind": "oracle",
         "sample": f"one step of {n} spheres, same recipe (lognormal r, phi 0.3, e 0.8, dt 0.4), "
-                  f"seed 103; {dt:.2f} s; {res.n_pairs} pairs in {res.n_sweeps} sweeps",
-        "pair_tests_per_s": res.pair_tests / dt,
-        "seconds": dt,
+                  f"seed 103; median of 3 runs {t_step:.2f} s ({', '.join(f'{t:.2f}' for t in times)}); "
+                  f"{res.n_pairs} pairs in {res.n_sweeps} sweeps",
+        "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+        "seconds_median": t_step, "seconds_runs": times,
+        # one full detection pass (every sphere active) on the oracle's grid, which is
+        # the reference grid: its pair tests per second, as the GPU's below
+        "pair_tests_per_s": ref / t_det, "ref_grid_pair_tests_per_pass": ref,
+        "oracle_grid_pair_tests_per_pass": tests, "detect_pass_seconds_median": t_det,
+        # the whole step: pair tests of every sweep (each sweep re-tests the active set)
+        "step_pair_tests_all_sweeps": res.pair_tests,
+        "step_pair_tests_per_s": res.pair_tests / t_step,
+        "single_thread": single,
+        "_box": box, "_res": res,
     }
+
+
+def oracle_parity(pc, torch, cpu):
+    """Both filter forms on the CPU baseline's sample against the oracle's step:
+    spheres whose partner differs, contact times and states."""
+    import numpy as np
+    box, res = cpu["_box"], cpu["_res"]
+    p0 = pc.Particles.from_box(box)
+    out = {}
+    for name, flt in (("fp64", 0), ("fp32", 1)):
+        p = p0.clone()
+        ctx = pc.Context(box.n, pc.pcol_default_opts(filter=flt))
+        partner = torch.empty(box.n, dtype=torch.int32, device="cuda")
+        tcoll = torch.empty(box.n, dtype=torch.float64, device="cuda")
+        pc.pcol_step(ctx, p, box.L, box.dt, box.e, partner, tcoll)
+        torch.cuda.synchronize()
+        ctx.close()
+        part = partner.cpu().numpy().astype(np.int64)
+        tc = tcoll.cpu().numpy()
+        err, nonbit = 0.0, 0
+        for f in ("x", "y", "z", "vx", "vy", "vz"):
+            a, b = getattr(p, f).cpu().numpy(), getattr(res, f)
+            err = max(err, float(np.max(np.abs(a - b)) / max(1.0, float(np.max(np.abs(b))))))
+            nonbit += int(np.count_nonzero(a.view(np.uint64) != b.view(np.uint64)))
+        out[name] = {"pair_set_mismatch_vs_oracle": int(np.count_nonzero(part != res.partner)),
+                     "tcoll_bitwise_equal": bool(np.array_equal(tc, res.tcoll, equal_nan=True)),
+                     "max_rel_state_error_vs_oracle": err, "state_values_not_bitwise": nonbit,
+                     "n": box.n, "pairs": res.n_pairs}
+    return out
 
 
 def batched_leg(args, pc, torch):
@@ -283,6 +406,57 @@ def cell_order_leg(args, pc, torch, box, p0, ref):
     return out
 
 
+def literal_leg(args, pc, torch, box, p0, ref):
+    """The 16M step in the paper's collision order taken literally (opts.order = 1:
+    elements along the Morton curve, first eligible contact found), each step from
+    the configured input; against the earliest-partner step on the same input: pairs,
+    kinetic energy dissipated, spheres whose partner differs, mean contact time."""
+    p = p0.clone()
+    ctx = pc.Context(box.n, pc.pcol_default_opts(timing=1, order=1))
+    partner = torch.empty(box.n, dtype=torch.int32, device="cuda")
+    tcoll = torch.empty(box.n, dtype=torch.float64, device="cuda")
+
+    def restore():
+        for t, t_0 in zip(p.tensors()[:6], p0.tensors()[:6]):
+            t.copy_(t_0)
+
+    for k in range(args.warmup):
+        restore()
+        pc.pcol_step(ctx, p, box.L, box.dt, box.e, partner, tcoll)
+    stats, wall = [], 0.0
+    for k in range(args.steps):
+        restore()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats.append(pc.pcol_step(ctx, p, box.L, box.dt, box.e, partner, tcoll))
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+    ke = lambda q: 0.5 * float((q.m * (q.vx * q.vx + q.vy * q.vy + q.vz * q.vz)).sum().item())
+    ke0 = ke(p0)
+    lit = {"loss": ke0 - ke(p), "partner": partner.clone(), "tcoll": tcoll.clone()}
+    ctx.close()
+    # the earliest-partner step's result on the same input (the plain leg's last step)
+    rp, rt = ref["partner"], ref["tcoll"]
+    erl_loss = ke0 - ke(ref["p"])
+    hit_l, hit_e = lit["partner"] >= 0, rp >= 0
+    out = {
+        "value": box.n * args.steps / wall, "unit": "particles/s",
+        "ms_per_step": wall * 1e3 / args.steps,
+        "ms_per_step_over_plain": (wall / args.steps) / (ref["wall"] / args.steps),
+        "pairs_per_step": statistics.mean(st["n_pairs"] for st in stats),
+        "pairs_per_step_earliest_rule": statistics.mean(st["n_pairs"] for st in ref["stats"]),
+        "sweeps_per_step": statistics.mean(st["n_sweeps"] for st in stats),
+        "ke_dissipated": lit["loss"], "ke_dissipated_earliest_rule": erl_loss,
+        "colliding_spheres_with_other_partner": int(((lit["partner"] != rp) & hit_l & hit_e).sum().item()),
+        "colliding_spheres": int(hit_l.sum().item()),
+        "mean_contact_time": float(lit["tcoll"][hit_l].mean().item()),
+        "mean_contact_time_earliest_rule": float(rt[hit_e].mean().item()),
+    }
+    log(f"[literal] {out['ms_per_step']:.3f} ms per step, {out['pairs_per_step']:.0f} pairs "
+        f"({out['pairs_per_step_earliest_rule']:.0f} earliest rule), {out['sweeps_per_step']:.1f} sweeps")
+    return out
+
+
 def walls_leg(args, pc, torch, box, p0, ref):
     """The 16M step between reflective walls on all three axes (pcol_step_walls), each
     step from the configured input, restored outside the timed interval."""
@@ -436,6 +610,8 @@ def main():
     ap.add_argument("--no-friction", action="store_true", help="skip the friction-and-spin leg")
     ap.add_argument("--no-deposition", action="store_true", help="skip the deposition leg")
     ap.add_argument("--no-walls", action="store_true", help="skip the walls leg")
+    ap.add_argument("--no-literal", action="store_true",
+                    help="skip the leg in the paper's literal collision order")
     ap.add_argument("--no-cell-order", action="store_true",
                     help="skip the leg with the spheres stored in cell order")
     args = ap.parse_args()
@@ -490,7 +666,7 @@ def main():
             log(f"[{name}] step {k}: pairs {st['n_pairs']} sweeps {st['n_sweeps']} tests "
                 f"{st['pair_tests']} rechecks {st['n_recheck']} bin {st['ms_bin']:.3f} detect "
                 f"{st['ms_detect']:.3f} sweeps {st['ms_sweeps']:.3f} advance {st['ms_advance']:.3f} ms")
-        out = {"p": p, "partner": partner, "stats": stats, "wall": wall}
+        out = {"p": p, "partner": partner, "tcoll": tcoll, "stats": stats, "wall": wall}
         ctx.close()
         return out
 
@@ -508,6 +684,39 @@ def main():
     det_total = sum(det_ms) * 1e-3
     achieved = tests * OPS_PER_PAIR_TEST / det_total
     flops = tests * FLOPS_PER_PAIR_TEST / det_total
+    # the reference grid's pair tests of one full detection pass (every sphere
+    # active), the count the oracle's rate below uses too
+    ref_tests = ref_grid_pair_tests(box.x, box.y, box.z, box.L, stats[0]["reach"])
+    det_med = statistics.median(det_ms) * 1e-3
+    counted = measured_traffic() if main_form == "fp64" else None
+    traffic = counted["detect_launch"] if counted else None
+    contacts = statistics.mean(st["contacts"] for st in stats)
+    pairs = statistics.mean(st["n_pairs"] for st in stats)
+    med = lambda key: statistics.median(st[key] for st in stats) * 1e-3
+    # algorithmic HBM bytes of each phase (what its kernels must move):
+    #  bin: validation and reach read the 64-B state; the cell ids read 56 B and
+    #    write cell and slot (8 B); the scatter reads 56 + 8 B and writes the 64-B
+    #    record and the 4-B sorted position;
+    #  detect: each first-layer record read once (64 B), a contact count per sphere
+    #    (4 B), 12 B per contact side in the slots;
+    #  sweeps: per collided sphere its record and its partner's (128 B), two masses,
+    #    its key (12 B) and its 64-B output record;
+    #  advance: the sorted position (4 B), the output record (64 B), the 48-B start
+    #    state read; the 48-B state, partner and time (12 B) written.
+    n = box.n
+    phase_bytes = {"bin": n * (64 + 64 + 132), "detect": n * 68 + contacts * 2 * 12,
+                   "sweeps": 2 * pairs * (128 + 16 + 12 + 64), "advance": n * 176}
+    phase_ms = {"bin": med("ms_bin"), "detect": det_med, "sweeps": med("ms_sweeps"),
+                "advance": med("ms_advance")}
+    phases = {k: {"ms": phase_ms[k] * 1e3, "algorithmic_bytes": phase_bytes[k],
+                  "hbm_frac_algorithmic": phase_bytes[k] / phase_ms[k] / PEAK_HBM}
+              for k in phase_ms}
+    # the phase's kernels' counted bytes (one step, from the counter summary) over
+    # the phase's time measured here
+    for k, ph in phases.items():
+        cb = counted["phases"].get(k) if counted else None
+        ph["counted_bytes"] = cb
+        ph["hbm_frac_counted"] = cb / phase_ms[k] / PEAK_HBM if cb else None
     form_names = {"fp64": "plain_fp64 (binary64 Gram filter)", "fp32": "binary32 filter + binary64 rule"}
     out = {
         "metric": METRIC,
@@ -527,14 +736,24 @@ def main():
                    "n": box.n, "form": form_names[main_form],
                    "split_quantile": (specs[main_form][1] if specs[main_form][1] is not None
                                       else pc.pcol_default_opts().split_quantile)},
-        "pair_tests_per_s": tests / det_total,
+        # pair tests per second on the reference grid (one full pass per detect)
+        "pair_tests_per_s": ref_tests / det_med,
+        "ref_grid_pair_tests_per_pass": ref_tests,
+        # the pairs the kernels actually test (the extent split removes most)
+        "pair_tests_split_per_pass": tests / args.steps,
+        "pair_tests_split_per_s": tests / det_total,
         "detect_ms_median": statistics.median(det_ms),
+        "phases": phases,
         "pairs_per_step": statistics.mean(st["n_pairs"] for st in stats),
         "sweeps_per_step": statistics.mean(st["n_sweeps"] for st in stats),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_OPS / 1e12,
                      "unit": "TOP/s", "frac": achieved / PEAK_FP64_OPS,
-                     "traffic": measured_traffic() if main_form == "fp64" else None,
+                     "traffic": traffic,
                      "traffic_unit": "bytes per launch",
+                     # the same launch against the HBM peak: counted bytes (FETCH_SIZE +
+                     # WRITE_SIZE, copy-calibrated) and algorithmic bytes
+                     "hbm_frac_counted": (traffic / det_med / PEAK_HBM) if traffic else None,
+                     "hbm_frac_algorithmic": phase_bytes["detect"] / det_med / PEAK_HBM,
                      "kernel": "k_detect_half64g",
                      "note": f"FP64 vector operations (an FMA counts one): {OPS_PER_PAIR_TEST} per "
                              f"unordered pair test; as flops ({FLOPS_PER_PAIR_TEST} per test) "
@@ -564,8 +783,8 @@ def main():
             "detect_speedup_vs_" + main_form: statistics.median(det_ms) / statistics.median(dmb),
             "pair_tests_per_step": tb / args.steps,
             "pair_tests_per_s": tb / (sum(dmb) * 1e-3),
-            "pair_set_mismatch": mismatch,
-            "state_bitwise_equal": state_equal,
+            "pair_set_mismatch_vs_fp64_gpu": mismatch,
+            "state_bitwise_equal_to_fp64_gpu": state_equal,
             "max_rel_velocity_error": max(errs),
             "rechecks_per_step": statistics.mean(st["n_recheck"] for st in sb),
             "split_quantile": (specs[name][1] if specs[name][1] is not None
@@ -582,13 +801,21 @@ def main():
         out["cell_order_form"] = cell_order_leg(args, pc, torch, box, p0, forms["fp64"])
     if not args.no_walls and "fp64" in forms:
         out["walls_form"] = walls_leg(args, pc, torch, box, p0, forms["fp64"])
+    if not args.no_literal and "fp64" in forms:
+        out["literal_order_form"] = literal_leg(args, pc, torch, box, p0, forms["fp64"])
     if not args.no_deposition:
         out["deposition"] = deposition_leg(args, pc, torch, box, p0)
     if not args.no_adjoint:
         out["adjoint_form"] = adjoint_leg(args, pc, torch)
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on {args.cpu_sample} spheres")
-        out["cpu_baseline"] = cpu_baseline(args)
+        cpu = cpu_baseline(args)
+        log("both filter forms against the oracle on its sample")
+        par = oracle_parity(pc, torch, cpu)
+        out["parity_vs_oracle"] = par
+        if "fp32_form" in out:
+            out["fp32_form"]["pair_set_mismatch_vs_oracle"] = par["fp32"]["pair_set_mismatch_vs_oracle"]
+        out["cpu_baseline"] = {k: v for k, v in cpu.items() if not k.startswith("_")}
     print(json.dumps(out), flush=True)
 
 
