@@ -497,8 +497,8 @@ def deposition_leg(args, pc, torch, box, p0):
     """Deposition of four source components (momentum and energy; standard normal,
     seed 3) of the 16M spheres at their start positions onto the corner nodes of a
     160^3 periodic grid over the same box (3.9 spheres per element), pcol_deposit per
-    call: position check with its readback, counting sort by element, element corner
-    sums, node sums."""
+    call: position check with its readback, counting sort by element, then element
+    corner sums and node sums per tile of nodes."""
     import workloads
     comp, nc = 4, (160, 160, 160)
     a = torch.as_tensor(workloads.deposit_case(box.n, seed=3, L=box.L, comp=comp)[3]).cuda()
@@ -539,8 +539,7 @@ def deposition_leg(args, pc, torch, box, p0):
         # the whole call (sort and sums) against the HBM peak, on its algorithmic bytes
         "roofline": {"bound": "hbm", "achieved": alg / wall / 1e9, "peak": 8000.0,
                      "unit": "GB/s", "frac": alg / wall / 8e12, "traffic": None,
-                     "kernel": "pcol_deposit (k_dep_count, scan, k_dep_scatter, k_dep_elem, "
-                               "k_dep_node)"},
+                     "kernel": "pcol_deposit (k_dep_count, scan, k_dep_scatter, k_dep_tile)"},
         "element_sorted_ms_per_call": wall_sorted * 1e3,
         "element_sorted_max_abs_diff": sorted_diff,
         "conservation_rel_error": float(

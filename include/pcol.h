@@ -384,9 +384,9 @@ pcol_status pcol_step_backward(pcol_ctx *ctx, const pcol_particles *start, const
  * within 2 (k - 1) 2^-53 sum|w a| (k its number of terms), and a node with one
  * term is exact.  Positions are checked on the device first (one readback, so
  * the call synchronises with the stream); on PCOL_E_INVALID out is unchanged.
- * n = 0 gives zeros.  Scratch: about (72 + 8 comp) bytes per sphere and
- * (12 + 64 comp) bytes per element, held by the context and grown on demand
- * (independent of n_max); growing it synchronises with the stream. */
+ * n = 0 gives zeros.  Scratch: 8 + 16 ceil((4 + comp) / 2) bytes per sphere
+ * (72 for comp = 4) and 8 bytes per element, held by the context and grown on
+ * demand (independent of n_max); growing it synchronises with the stream. */
 pcol_status pcol_deposit(pcol_ctx *ctx, const double *x, const double *y, const double *z,
                          int64_t n, const double *a, int comp, const int32_t nc[3],
                          const double len[3], double *out);
@@ -404,9 +404,9 @@ pcol_status pcol_deposit(pcol_ctx *ctx, const double *x, const double *y, const 
  * holds from the first call on that GPU until the process ends.  The input must
  * fit: with R = 16 ceil((4 + comp) / 2) bytes per record and ne = nc_0 nc_1
  * nc_2 elements, each rounded up to 256 B, the scratch holds 4n + 4n + Rn +
- * 4(ne + 1) + 4(ne + 1) + 4(ne / 4096 + 2) + 64 comp ne + 8,232 + 4 bytes
- * (about 72n + 264ne for comp = 4); a larger input returns PCOL_E_SCRATCH before
- * any work, out unchanged.
+ * 4(ne + 1) + 4(ne + 1) + 4(ne / 4096 + 2) + 8,232 + 4 bytes (about 72n + 8ne
+ * for comp = 4: for example 500k spheres on 3M elements); a larger input
+ * returns PCOL_E_SCRATCH before any work, out unchanged.
  *   hip_stream: the hipStream_t to enqueue on (NULL: the default stream) on the
  *   current device.  Other arguments, checks and errors as pcol_deposit; the
  *   position check is read back into host memory, so the call synchronises with

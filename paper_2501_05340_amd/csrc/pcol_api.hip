@@ -53,6 +53,8 @@ struct pcol_ctx {
   int *partner_tmp = nullptr;
   double *tcoll_tmp = nullptr;
   ReachOut *reach_d = nullptr;
+  ReachPart *reach_parts = nullptr;     // REACH_BLOCKS partial results of the reach pass
+  unsigned int *reach_phist = nullptr;  // REACH_BLOCKS partial extent histograms
   SweepCounters *ctr_d = nullptr;
   ReachOut *reach_h = nullptr;
   SweepCounters *ctr_h = nullptr;
@@ -210,10 +212,10 @@ double ms_between(hipEvent_t a, hipEvent_t b) {
 
 // The deposition's scratch carved out of one buffer, each part on a 256-B
 // boundary: element id and slot per sphere, the element-sorted records, the
-// per-element counts, starts and scan block sums, the eight corner sums per
-// element and component, the scan's statistics word and the position flag.
+// per-element counts, starts and scan block sums, the scan's statistics word and
+// the position flag.
 struct DepositLayout {
-  int64_t eid, slot, rec, cnt, start, bsum, E, ro, flag, bytes;
+  int64_t eid, slot, rec, cnt, start, bsum, ro, flag, bytes;
 };
 
 DepositLayout deposit_layout(int64_t n, int64_t ne, int comp) {
@@ -230,7 +232,6 @@ DepositLayout deposit_layout(int64_t n, int64_t ne, int comp) {
   L.cnt = take((ne + 1) * (int64_t)sizeof(int));
   L.start = take((ne + 1) * (int64_t)sizeof(int));
   L.bsum = take((ne / 4096 + 2) * (int64_t)sizeof(int));
-  L.E = take(8 * (int64_t)comp * ne * (int64_t)sizeof(double));
   L.ro = take((int64_t)sizeof(ReachOut));
   L.flag = take((int64_t)sizeof(unsigned int));
   L.bytes = at;
@@ -278,7 +279,6 @@ hipError_t deposit_run(DepositArgs &D, const DepositLayout &Lo, unsigned char *b
   D.rec = base + Lo.rec;
   D.cnt = (int *)(base + Lo.cnt);
   D.start = (int *)(base + Lo.start);
-  D.E = (double *)(base + Lo.E);
   unsigned int *flag = (unsigned int *)(base + Lo.flag);
   hipError_t e = launch_fill_i32(s, D.cnt, 0, D.nnode);
   if (e != hipSuccess) return e;
@@ -367,7 +367,7 @@ void pcol_destroy(pcol_ctx *ctx) {
                  ctx->slot_j, ctx->key_j,  ctx->key_t,  ctx->status,      ctx->out,
                  ctx->ovf,    ctx->partner_tmp, ctx->tcoll_tmp, ctx->list_a, ctx->keep_cnt, ctx->keep_off, ctx->keep_bs,
                  ctx->reach_d, ctx->cellc, ctx->ctr_d, ctx->sflags, ctx->stotals, ctx->dep_buf,
-                 ctx->crank};
+                 ctx->crank, ctx->reach_parts, ctx->reach_phist};
   for (void *p : dev)
     if (p) (void)hipFree(p);
   if (ctx->reach_h) (void)hipHostFree(ctx->reach_h);
@@ -439,6 +439,8 @@ pcol_status pcol_create(pcol_ctx **out, int64_t n_max, void *hip_stream, const p
   A(dalloc(&ctx->tcoll_tmp, n));
   if (ctx->opts.order == 1) A(dalloc(&ctx->crank, n));
   A(dalloc(&ctx->reach_d, 1));
+  A(dalloc(&ctx->reach_parts, REACH_BLOCKS));
+  A(dalloc(&ctx->reach_phist, (int64_t)REACH_BLOCKS * RHO_BINS));
   A(dalloc(&ctx->ctr_d, 1));
   A(dalloc(&ctx->sflags, 16));
   A(dalloc(&ctx->stotals, 4));
@@ -481,13 +483,13 @@ pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box
     P.wz = ctx->spin->wz;
   }
   hipStream_t s = ctx->stream;
-  // a1: reach and data validity (one read-back)
+  // a1: reach and data validity (one read-back); the histogram is accumulated
+  // into zeros, the other fields are written by the reduction
   PCOL_HIP(hipMemsetAsync(ctx->reach_d, 0, sizeof(ReachOut), s));
-  PCOL_HIP(launch_fill_u32(s, (unsigned int *)&ctx->reach_d->rmin, 0u, 1));
-  PCOL_HIP(launch_fill_u32(s, (unsigned int *)&ctx->reach_d->rmin + 1, 0x7ff00000u, 1));
   // the extent histogram only picks the split extent: above 2^20 spheres it
   // samples one sphere in 16 (the quantile of a million samples is as good)
-  PCOL_HIP(launch_reach(s, P, box->len, dt, p->n >= (1 << 20) ? 4 : 0, ctx->reach_d));
+  PCOL_HIP(launch_reach(s, P, box->len, dt, p->n >= (1 << 20) ? 4 : 0, ctx->reach_d,
+                        ctx->reach_parts, ctx->reach_phist));
   PCOL_HIP(hipMemcpyAsync(ctx->reach_h, ctx->reach_d, sizeof(ReachOut), hipMemcpyDeviceToHost, s));
   PCOL_HIP(hipStreamSynchronize(s));
   const ReachOut ro = *ctx->reach_h;

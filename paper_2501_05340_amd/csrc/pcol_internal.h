@@ -103,6 +103,20 @@ struct ReachOut {
   unsigned int hist[RHO_BINS];  // extents by rho_bin
 };
 
+// One workgroup's share of the reach pass: the bits of its maxima (of
+// non-negative doubles, so they order as the values), of its smallest radius
+// (+inf if none) and its validity bits.
+constexpr int REACH_BLOCKS = 1024;
+struct ReachPart {
+  unsigned long long v2max, rmax, rmin, rhomax;
+  unsigned int bad, pad;
+};
+__host__ __device__ inline ReachPart reach_merge(const ReachPart &a, const ReachPart &b) {
+  return ReachPart{a.v2max > b.v2max ? a.v2max : b.v2max, a.rmax > b.rmax ? a.rmax : b.rmax,
+                   a.rmin < b.rmin ? a.rmin : b.rmin, a.rhomax > b.rhomax ? a.rhomax : b.rhomax,
+                   a.bad | b.bad, 0u};
+}
+
 // The grid of the literal order's space-filling curve: nc cells of side h =
 // L / nc per axis (nc <= 2048), independent of the pair-test grid.
 struct CurveGrid {
@@ -400,9 +414,11 @@ hipError_t launch_fill_u8(hipStream_t s, uint8_t *p, uint8_t v, int64_t n);
 hipError_t launch_fill_f64(hipStream_t s, double *p, double v, int64_t n);
 hipError_t launch_fill_i32(hipStream_t s, int *p, int v, int64_t n);
 // hist_shift: the extent histogram covers the spheres whose index is a multiple
-// of 2^hist_shift (the maxima and the validity cover all)
+// of 2^hist_shift (the maxima and the validity cover all).  parts and phist are
+// scratch of REACH_BLOCKS partial results and REACH_BLOCKS * RHO_BINS counts;
+// out->hist must be zero and out's other fields are overwritten.
 hipError_t launch_reach(hipStream_t s, const Particles &P, const double L[3], double dt,
-                        int hist_shift, ReachOut *out);
+                        int hist_shift, ReachOut *out, ReachPart *parts, unsigned int *phist);
 hipError_t launch_cell_hist(hipStream_t s, const Particles &P, const Grid &G, double dt,
                             double rho_c, int *cid, int *slot, int *count);
 // the spheres of the second layer, sorted positions [*first_dev, n)
@@ -470,8 +486,7 @@ hipError_t launch_step_backward(hipStream_t s, const Particles &P, const Grid &G
 // Cartesian grid: positions x, y, z (n), sources a[q * n + i] (comp <= 8),
 // nc cells of side h = L / nc per axis, out[node * comp + q] (nnode nodes,
 // one per element).  Scratch: eid, slot (n each), cnt (nnode, zeroed before the
-// count), start (nnode + 1), rec (n records of deposit_record_bytes(comp)), E
-// (8 comp nnode corner sums).
+// count), start (nnode + 1), rec (n records of deposit_record_bytes(comp)).
 struct DepositArgs {
   const double *x, *y, *z, *a;
   int64_t n;
@@ -482,13 +497,13 @@ struct DepositArgs {
   double *out;
   int *eid, *slot, *cnt, *start;
   void *rec;
-  double *E;
 };
 int64_t deposit_record_bytes(int comp);
 // element and slot of every sphere (cnt must be zero); positions outside
 // [0, L) or not finite set bit 0 of *flag and are skipped
 hipError_t launch_deposit_count(hipStream_t s, const DepositArgs &D, unsigned int *flag);
-// after the scan of cnt into start: scatter, element corner sums, node sums
+// after the scan of cnt into start: scatter, then element corner sums and node
+// sums over tiles of nodes
 hipError_t launch_deposit(hipStream_t s, const DepositArgs &D);
 hipError_t launch_resolve_public(hipStream_t s, int n, const Rec *rec, const int *rank,
                                  const Grid &G, double dt, double e, const uint64_t *key,

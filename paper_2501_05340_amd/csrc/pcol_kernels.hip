@@ -138,10 +138,13 @@ hipError_t launch_fill_f64(hipStream_t s, double *p, double v, int64_t n) {
 // every partner a sphere can reach within the step).  The maxima and the
 // validity cover every sphere; the histogram, which only picks the split
 // extent (a performance choice), covers the spheres whose index is a multiple
-// of 2^hist_shift.  Grid-stride; each workgroup histograms in LDS and adds its
-// non-empty bins once.
+// of 2^hist_shift.  Grid-stride over at most REACH_BLOCKS workgroups; each
+// histograms in LDS and stores its partial results (maxima and its whole
+// histogram) in parts, which k_reach_final reduces: no address takes an atomic
+// from every workgroup.
 __global__ __launch_bounds__(256) void k_reach(Particles P, double L0, double L1, double L2,
-                                               double dt, int hist_shift, ReachOut *out) {
+                                               double dt, int hist_shift, ReachPart *parts,
+                                               unsigned int *phist) {
   __shared__ unsigned int hist[RHO_BINS];
   for (int k = threadIdx.x; k < RHO_BINS; k += 256) hist[k] = 0u;
   __syncthreads();
@@ -216,25 +219,61 @@ __global__ __launch_bounds__(256) void k_reach(Particles P, double L0, double L1
     em = d > em ? d : em;
     bad |= __shfl_xor(bad, o);
   }
-  if (__lane_id() == 0) {
-    atomicMax(&out->v2max, dbits(v2));
-    atomicMax(&out->rmax, dbits(rm));
-    atomicMax(&out->rhomax, dbits(em));
-    if (rn > 0.0) atomicMin(&out->rmin, dbits(rn));
-    if (bad) atomicOr(&out->bad, bad);
-  }
+  __shared__ ReachPart wpart[256 / WAVE];
+  if (__lane_id() == 0)
+    wpart[threadIdx.x / WAVE] = ReachPart{dbits(v2), dbits(rm), dbits(rn), dbits(em), bad, 0u};
   __syncthreads();
+  if (threadIdx.x == 0) {
+    ReachPart p = wpart[0];
+    for (int w = 1; w < 256 / WAVE; ++w) p = reach_merge(p, wpart[w]);
+    parts[blockIdx.x] = p;
+  }
   for (int k = threadIdx.x; k < RHO_BINS; k += 256)
-    if (hist[k]) atomicAdd(&out->hist[k], hist[k]);
+    phist[(int64_t)blockIdx.x * RHO_BINS + k] = hist[k];
+}
+
+// Reduction of k_reach's nblocks partial results into out: the maxima, the
+// smallest radius and the validity bits by one workgroup, the histogram by
+// REACH_FINAL_Y workgroups per 256 bins, each summing a share of the partial
+// histograms and adding its non-zero sums (REACH_FINAL_Y adds per bin at most).
+constexpr int REACH_FINAL_Y = 32;
+
+__global__ __launch_bounds__(256) void k_reach_final(int nblocks, const ReachPart *parts,
+                                                     const unsigned int *phist, ReachOut *out) {
+  const int b = blockIdx.x * 256 + threadIdx.x;  // bin
+  const int per = (nblocks + REACH_FINAL_Y - 1) / REACH_FINAL_Y;
+  const int k0 = blockIdx.y * per, k1 = k0 + per < nblocks ? k0 + per : nblocks;
+  unsigned int s = 0u;
+  for (int k = k0; k < k1; ++k) s += phist[(int64_t)k * RHO_BINS + b];
+  if (s) atomicAdd(&out->hist[b], s);
+  if (blockIdx.x != 0 || blockIdx.y != 0) return;
+  __shared__ ReachPart red[256];
+  ReachPart p{0ull, 0ull, dbits(INFINITY), 0ull, 0u, 0u};
+  for (int k = threadIdx.x; k < nblocks; k += 256) p = reach_merge(p, parts[k]);
+  red[threadIdx.x] = p;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] = reach_merge(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out->v2max = red[0].v2max;
+    out->rmax = red[0].rmax;
+    out->rhomax = red[0].rhomax;
+    out->rmin = red[0].rmin;
+    out->bad = red[0].bad;
+  }
 }
 
 hipError_t launch_reach(hipStream_t s, const Particles &P, const double L[3], double dt,
-                        int hist_shift, ReachOut *out) {
+                        int hist_shift, ReachOut *out, ReachPart *parts, unsigned int *phist) {
   int64_t g = (P.n + 255) / 256;
-  if (g > 1024) g = 1024;
+  if (g > REACH_BLOCKS) g = REACH_BLOCKS;
   if (g < 1) g = 1;
   hipLaunchKernelGGL(k_reach, dim3((int)g), dim3(256), 0, s, P, L[0], L[1], L[2], dt, hist_shift,
-                     out);
+                     parts, phist);
+  hipLaunchKernelGGL(k_reach_final, dim3(RHO_BINS / 256, REACH_FINAL_Y), dim3(256), 0, s, (int)g,
+                     parts, phist, out);
   return hipGetLastError();
 }
 
@@ -2103,9 +2142,10 @@ hipError_t launch_sweep_check(hipStream_t s, SweepCounters *ctr, unsigned int *f
 // sphere would bound the operator at 0.7e9 spheres/s whatever the memory
 // order.  Instead the spheres are counted and scattered by element (a counting
 // sort, one integer atomic per sphere), each element sums its spheres' corner
-// contributions in caller-index order, and each node gathers the eight corner
-// sums that touch it in a fixed order: no floating-point atomics, and the
-// result is the same bit for bit on every run.  Nodes are stored node-major:
+// contributions in caller-index order, and each node adds the corner sums of
+// its eight elements in a fixed order, in the shared memory of the workgroup
+// that owns the node's tile: no floating-point atomics, and the result is the
+// same bit for bit on every run.  Nodes are stored node-major:
 // out[node * comp + q], node = (k nc1 + j) nc0 + i; element e has the node of
 // the same number as its corner (0, 0, 0).
 namespace pcol {
@@ -2183,18 +2223,14 @@ __global__ __launch_bounds__(256) void k_dep_scatter(DepositArgs D) {
   reinterpret_cast<DepRec<COMP> *>(D.rec)[D.start[D.eid[i]] + D.slot[i]] = r;
 }
 
-// One thread per element: the eight corner sums of its spheres, each a sum in
-// caller-index order of w_b a_q with the trilinear weight
+// The eight corner sums of element e's spheres, each a sum in caller-index
+// order of w_b a_q with the trilinear weight
 // w_b = ((b0 ? f0 : 1 - f0) (b1 ? f1 : 1 - f1)) (b2 ? f2 : 1 - f2).
-// E[(b COMP + q) nelem + e]: coalesced across the element threads.
 template <int COMP>
-__global__ __launch_bounds__(256) void k_dep_elem(DepositArgs D) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= D.nnode) return;
+__device__ __forceinline__ void elem_sums(const DepositArgs &D, int64_t e, double (&acc)[8][COMP]) {
   const DepRec<COMP> *R = reinterpret_cast<const DepRec<COMP> *>(D.rec);
   const int m0 = D.start[e], m1 = D.start[e + 1];
   const bool ordered = m1 - m0 <= DEP_SORT_MAX;
-  double acc[8][COMP];
 #pragma unroll
   for (int b = 0; b < 8; ++b)
 #pragma unroll
@@ -2247,44 +2283,75 @@ __global__ __launch_bounds__(256) void k_dep_elem(DepositArgs D) {
       add(R[k]);
     }
   }
-#pragma unroll
-  for (int b = 0; b < 8; ++b)
-#pragma unroll
-    for (int q = 0; q < COMP; ++q) D.E[(int64_t)(b * COMP + q) * D.nnode + e] = acc[b][q];
 }
 
-// One thread per node: node (i, j, k) is corner b of element (i - b0, j - b1,
-// k - b2) (periodic); the eight corner sums are added in the order b = 0..7.
+// Node sums over a tile of DEP_TN^3 nodes: node (i, j, k) is corner b of
+// element (i - b0, j - b1, k - b2) (periodic), and receives the eight corner
+// sums in the order b = 0..7.  One thread per element of the tile's
+// (DEP_TN + 1)^3 elements (the tile's own and one layer below it on each axis)
+// forms its element's eight corner sums; then, phase b after phase b, every
+// element adds its corner-b sum to the tile node it touches (within a phase no
+// two elements share a node), so each node's sum is formed in the order b =
+// 0..7 from zero, with no atomics and no corner-sum array in memory.  The
+// elements of the lower layer are summed by two to eight tiles.
+constexpr int DEP_TN = 7, DEP_TE = DEP_TN + 1, DEP_TILE_THREADS = DEP_TE * DEP_TE * DEP_TE;
+
 template <int COMP>
-__global__ __launch_bounds__(256) void k_dep_node(DepositArgs D) {
-  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= D.nnode) return;
-  const int i = (int)(n % D.nc[0]);
-  const int j = (int)((n / D.nc[0]) % D.nc[1]);
-  const int k = (int)(n / ((int64_t)D.nc[0] * D.nc[1]));
-  const int im = i == 0 ? D.nc[0] - 1 : i - 1;
-  const int jm = j == 0 ? D.nc[1] - 1 : j - 1;
-  const int km = k == 0 ? D.nc[2] - 1 : k - 1;
-  double s[COMP];
+__global__ __launch_bounds__(DEP_TILE_THREADS) void k_dep_tile(DepositArgs D, int ntx, int nty) {
+  __shared__ double nacc[DEP_TN * DEP_TN * DEP_TN * COMP];
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
+  const int i0 = tx * DEP_TN, j0 = ty * DEP_TN, k0 = tz * DEP_TN;
+  const int t = threadIdx.x;
+  const int ex = t % DEP_TE, ey = (t / DEP_TE) % DEP_TE, ez = t / (DEP_TE * DEP_TE);
+  // the element's global cell, one below the tile's first node on each axis
+  auto wrap = [](int c, int nc) { return c < 0 ? c + nc : (c >= nc ? c - nc : c); };
+  const int gi = wrap(i0 - 1 + ex, D.nc[0]), gj = wrap(j0 - 1 + ey, D.nc[1]),
+            gk = wrap(k0 - 1 + ez, D.nc[2]);
+  for (int u = t; u < DEP_TN * DEP_TN * DEP_TN * COMP; u += DEP_TILE_THREADS) nacc[u] = 0.0;
+  // every element of the tile's box touches a node of the tile, but past the
+  // grid's last cell (a partial tile) it has no node to serve
+  const bool live = i0 - 1 + ex < D.nc[0] && j0 - 1 + ey < D.nc[1] && k0 - 1 + ez < D.nc[2];
+  double acc[8][COMP];
+  if (live) {
+    elem_sums<COMP>(D, ((int64_t)gk * D.nc[1] + gj) * D.nc[0] + gi, acc);
+  } else {
 #pragma unroll
-  for (int q = 0; q < COMP; ++q) s[q] = 0.0;
+    for (int b = 0; b < 8; ++b)
+#pragma unroll
+      for (int q = 0; q < COMP; ++q) acc[b][q] = 0.0;
+  }
+  __syncthreads();
 #pragma unroll
   for (int b = 0; b < 8; ++b) {
-    const int64_t e = ((int64_t)((b & 4) ? km : k) * D.nc[1] + ((b & 2) ? jm : j)) * D.nc[0] +
-                      ((b & 1) ? im : i);
+    const int nx = ex - 1 + (b & 1), ny = ey - 1 + ((b >> 1) & 1), nz = ez - 1 + ((b >> 2) & 1);
+    const bool hit = live && nx >= 0 && nx < DEP_TN && ny >= 0 && ny < DEP_TN && nz >= 0 &&
+                     nz < DEP_TN && i0 + nx < D.nc[0] && j0 + ny < D.nc[1] && k0 + nz < D.nc[2];
+    if (hit) {
+      double *a = nacc + ((nz * DEP_TN + ny) * DEP_TN + nx) * COMP;
 #pragma unroll
-    for (int q = 0; q < COMP; ++q) s[q] += D.E[(int64_t)(b * COMP + q) * D.nnode + e];
+      for (int q = 0; q < COMP; ++q) a[q] += acc[b][q];
+    }
+    __syncthreads();
   }
+  if (t < DEP_TN * DEP_TN * DEP_TN) {
+    const int nx = t % DEP_TN, ny = (t / DEP_TN) % DEP_TN, nz = t / (DEP_TN * DEP_TN);
+    if (i0 + nx < D.nc[0] && j0 + ny < D.nc[1] && k0 + nz < D.nc[2]) {
+      const int64_t n = ((int64_t)(k0 + nz) * D.nc[1] + (j0 + ny)) * D.nc[0] + (i0 + nx);
 #pragma unroll
-  for (int q = 0; q < COMP; ++q) D.out[n * COMP + q] = s[q];
+      for (int q = 0; q < COMP; ++q) D.out[n * COMP + q] = nacc[t * COMP + q];
+    }
+  }
 }
 
 template <int COMP>
 hipError_t deposit_sorted(hipStream_t s, const DepositArgs &D) {
-  const unsigned gn = (unsigned)((D.n + 255) / 256), ge = (unsigned)((D.nnode + 255) / 256);
+  const unsigned gn = (unsigned)((D.n + 255) / 256);
   if (D.n > 0) hipLaunchKernelGGL(k_dep_scatter<COMP>, dim3(gn), dim3(256), 0, s, D);
-  hipLaunchKernelGGL(k_dep_elem<COMP>, dim3(ge), dim3(256), 0, s, D);
-  hipLaunchKernelGGL(k_dep_node<COMP>, dim3(ge), dim3(256), 0, s, D);
+  const int ntx = (D.nc[0] + DEP_TN - 1) / DEP_TN, nty = (D.nc[1] + DEP_TN - 1) / DEP_TN,
+            ntz = (D.nc[2] + DEP_TN - 1) / DEP_TN;
+  hipLaunchKernelGGL(k_dep_tile<COMP>, dim3((unsigned)(ntx * nty * ntz)), dim3(DEP_TILE_THREADS),
+                     0, s, D, ntx, nty);
   return hipGetLastError();
 }
 

@@ -95,7 +95,7 @@ def test_noalloc_on_a_side_stream_and_empty_input():
 
 def test_noalloc_refuses_what_does_not_fit_and_bad_positions():
     print("[gpu-test] pcol_deposit_noalloc: refused inputs", flush=True)
-    nc, comp = (64, 64, 64), 4  # 264 B per element alone: 69 MB > 64 MiB
+    nc, comp = (256, 256, 160), 4  # 8 B per element alone: 84 MB > 64 MiB
     args, host, L = _case(1000, 24, nc, comp)
     out = torch.full((nc[2], nc[1], nc[0], comp), 7.0, dtype=torch.float64, device="cuda")
     with pytest.raises(pc.PcolError) as ei:
