@@ -27,7 +27,6 @@ struct pcol_ctx {
 
   // cell-sorted state of the last pcol_bin
   Rec *rec = nullptr;
-  Rec32 *rec32 = nullptr;  // FP32 filter records (filter 1 only)
   int *rank = nullptr;  // caller index -> sorted position
   int *cid = nullptr;
   int *slot = nullptr;
@@ -362,7 +361,7 @@ pcol_status pcol_set_stream(pcol_ctx *ctx, void *hip_stream) {
 
 void pcol_destroy(pcol_ctx *ctx) {
   if (!ctx) return;
-  void *dev[] = {ctx->rec,    ctx->rec32,  ctx->rank,   ctx->cid,         ctx->slot,
+  void *dev[] = {ctx->rec,    ctx->rank,   ctx->cid,         ctx->slot,
                  ctx->count,  ctx->start,  ctx->blocksum, ctx->cnt,      ctx->slot_t,
                  ctx->slot_j, ctx->key_j,  ctx->key_t,  ctx->status,      ctx->out,
                  ctx->ovf,    ctx->partner_tmp, ctx->tcoll_tmp, ctx->list_a, ctx->keep_cnt, ctx->keep_off, ctx->keep_bs,
@@ -419,7 +418,6 @@ pcol_status pcol_create(pcol_ctx **out, int64_t n_max, void *hip_stream, const p
     if (e == hipSuccess && r != hipSuccess) e = r;
   };
   A(dalloc(&ctx->rec, n));
-  if (ctx->opts.filter == 1) A(dalloc(&ctx->rec32, n));
   A(dalloc(&ctx->rank, n));
   A(dalloc(&ctx->cid, n));
   A(dalloc(&ctx->slot, n));
@@ -588,8 +586,7 @@ pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box
   PCOL_HIP(launch_fill_i32(s, ctx->count, 0, cells_all));
   PCOL_HIP(launch_cell_hist(s, P, G, dt, rho_c, ctx->cid, ctx->slot, ctx->count));
   PCOL_HIP(launch_scan(s, ctx->count, cells_all, ctx->start, ctx->blocksum, ctx->reach_d));
-  PCOL_HIP(launch_scatter(s, P, G, ctx->cid, ctx->slot, ctx->start, ctx->rec,
-                          ctx->opts.filter == 1 ? ctx->rec32 : nullptr, ctx->rank, nullptr));
+  PCOL_HIP(launch_scatter(s, P, ctx->cid, ctx->slot, ctx->start, ctx->rec, ctx->rank, nullptr));
   if (ctx->opts.order == 1) {
     // the literal order's ranks on the curve grid: cell side >= the reach
     // (2 max r + 2 max|v| dt, whatever grid the pair tests use), at most 2048
@@ -605,8 +602,7 @@ pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box
     PCOL_HIP(launch_curve_rank(s, ctx->rec, (int)p->n, C, ctx->crank));
   }
   // the largest cell and the second layer's range are read back without a
-  // wait: only the binary32 filter sizes a launch by them (its LDS staging);
-  // the other paths read them after their next synchronisation (bin_readback)
+  // wait; they are read after the next synchronisation (bin_readback)
   PCOL_HIP(hipMemcpyAsync(&ctx->reach_h->maxcell, &ctx->reach_d->maxcell, sizeof(unsigned int),
                           hipMemcpyDeviceToHost, s));
   if (split)
@@ -628,10 +624,6 @@ pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box
   ctx->binned = true;
   ctx->binned_n = p->n;
   ctx->binned_x = p->x;
-  if (ctx->opts.filter == 1) {
-    PCOL_HIP(hipStreamSynchronize(s));
-    bin_readback(ctx);
-  }
   return PCOL_OK;
 }
 
@@ -746,14 +738,7 @@ static pcol_status detect_all(pcol_ctx *ctx, double dt, const unsigned long long
       A.rho_c = ctx->rho_c;
     }
     A.K = ctx->K;
-    A.rec32 = ctx->rec32;
     A.fp32 = ctx->opts.filter == 1;
-    // the FP32 filter reads its home records from an LDS copy of the home cell
-    // (when the largest cell fits in 20 KB); the FP64 filter reads them through
-    // the scalar cache, which measured faster for 64-B records
-    A.cap = A.fp32 && ctx->maxcell * (int)sizeof(Rec32) <= 20 * 1024
-                ? (ctx->maxcell > 0 ? ctx->maxcell : 1)
-                : 0;
     ctx->band = A.fp32 ? fp32_band(ctx, dt) : 0.0;
     // round the factor up so the float never shrinks the inflation
     const double kb = 1.0 + ctx->band;
@@ -1321,8 +1306,7 @@ static pcol_status batch_enqueue(pcol_ctx *ctx, hipStream_t s, const Particles &
   PCOL_HIP(launch_fill_i32(s, ctx->count, 0, ncell));
   PCOL_HIP(launch_cell_hist_b(s, P, B, ctx->cid, ctx->slot, ctx->count));
   PCOL_HIP(launch_scan(s, ctx->count, ncell, ctx->start, ctx->blocksum, ctx->reach_d));
-  PCOL_HIP(launch_scatter(s, P, ctx->G, ctx->cid, ctx->slot, ctx->start, ctx->rec, nullptr,
-                          ctx->rank, &B));
+  PCOL_HIP(launch_scatter(s, P, ctx->cid, ctx->slot, ctx->start, ctx->rec, ctx->rank, &B));
   PCOL_HIP(launch_fill_u8(s, ctx->status, ST_ACTIVE, n));
   PCOL_HIP(launch_fill_i32(s, ctx->cnt, 0, n));
   DetectArgs A{};
@@ -1351,7 +1335,6 @@ static pcol_status batch_enqueue(pcol_ctx *ctx, hipStream_t s, const Particles &
     A.tol64 = gram64_tolerance(hmax, hmax, hmax / (2.0 * dt), 0.5 * hmax, Lmax, A.dt2);
   }
   A.K = ctx->K;
-  A.cap = 0;
   A.fp32 = 0;
   int blocks = 256 * 8 * 4 / wpb;  // about 8 resident waves per SIMD
   PCOL_HIP(launch_detect_batched(s, A, B, blocks, wpb));

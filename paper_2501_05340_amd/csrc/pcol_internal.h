@@ -85,8 +85,9 @@ __device__ __forceinline__ int rho_bin(double v) {
   return k < 0 ? 0 : (k >= RHO_BINS ? RHO_BINS - 1 : (int)k);
 }
 
-// FP32 copy of a record for the pair filter: position relative to the centre
-// of the sphere's own cell, radius, velocity (32 B).
+// FP32 copy of a home sphere's record for the pair filter, staged in LDS by
+// the detect kernel: position relative to the centre of the home cell, radius,
+// velocity (32 B).
 struct alignas(16) Rec32 {
   float x, y, z, r;
   float vx, vy, vz, pad;
@@ -385,7 +386,6 @@ struct CellCount {
 // Everything the sweep-1 detect needs.
 struct DetectArgs {
   const Rec *rec;
-  const Rec32 *rec32; // FP32 filter records (fp32 form only)
   const int *start;   // ncell + 1
   int *cnt;           // per sorted sphere: contacts found
   double *slot_t;     // [n * K]
@@ -400,8 +400,6 @@ struct DetectArgs {
   double tol_wide;    // the same for pairs with a sphere above the split extent (full reach)
   double rho_c;       // split extent (first-layer spheres have extent <= rho_c)
   int K;
-  int cap;            // home spheres staged in LDS per cell (largest cell occupancy);
-                      // 0: read the home spheres through the scalar cache instead
   int fp32;           // FP32 filter + FP64 recheck
   float kband;        // FP32 filter: contact distance inflated to s * kband
   float dt2f;         // FP32 filter: 2 dt (1 + 2^-12)
@@ -425,9 +423,8 @@ hipError_t launch_cell_hist(hipStream_t s, const Particles &P, const Grid &G, do
 hipError_t launch_detect_wide(hipStream_t s, const DetectArgs &A, const int *first_dev, int n);
 hipError_t launch_scan(hipStream_t s, const int *count, int ncell, int *start, int *blocksum,
                        ReachOut *out);
-hipError_t launch_scatter(hipStream_t s, const Particles &P, const Grid &G, const int *cid,
-                          const int *slot, const int *start, Rec *rec, Rec32 *rec32, int *rank,
-                          const BatchDev *B);
+hipError_t launch_scatter(hipStream_t s, const Particles &P, const int *cid, const int *slot,
+                          const int *start, Rec *rec, int *rank, const BatchDev *B);
 hipError_t launch_detect_half(hipStream_t s, const DetectArgs &A);
 // workgroups of launch_detect_half, each writing one CellCount
 int detect_half_blocks(const DetectArgs &A);

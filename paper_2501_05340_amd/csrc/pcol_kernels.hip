@@ -417,12 +417,10 @@ hipError_t launch_scan(hipStream_t s, const int *count, int ncell, int *start, i
 
 // cell-sorted 64-B records of the start-of-step state; reads the caller's SoA
 // arrays coalesced and writes one record per sphere (its caller index and box
-// inside, so no other array is written in sorted order).  With rec32 given,
-// also the 32-B FP32 filter record (position relative to the cell centre).
-__global__ __launch_bounds__(256) void k_scatter(Particles P, Grid G, const int *cid,
-                                                 const int *slot, const int *start, Rec *rec,
-                                                 Rec32 *rec32, int *rank, const int *box_of,
-                                                 const unsigned int *flags) {
+// inside, so no other array is written in sorted order).
+__global__ __launch_bounds__(256) void k_scatter(Particles P, const int *cid, const int *slot,
+                                                 const int *start, Rec *rec, int *rank,
+                                                 const int *box_of, const unsigned int *flags) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= P.n || (flags && flags[FLAG_ERR])) return;
   const int c = cid[i];
@@ -439,29 +437,13 @@ __global__ __launch_bounds__(256) void k_scatter(Particles P, Grid G, const int 
   q.box = box_of ? box_of[i] : 0;
   rec[pos] = q;
   rank[i] = pos;
-  if (rec32) {
-    const int cl = c >= G.ncell ? c - G.ncell : c;  // cell within its layer
-    int cx, cy, cz;
-    cell_xyz(G, cl, cx, cy, cz);
-    Rec32 f;
-    f.x = (float)(q.x - (cx + 0.5) * G.h[0]);
-    f.y = (float)(q.y - (cy + 0.5) * G.h[1]);
-    f.z = (float)(q.z - (cz + 0.5) * G.h[2]);
-    f.r = (float)q.r;
-    f.vx = (float)q.vx;
-    f.vy = (float)q.vy;
-    f.vz = (float)q.vz;
-    f.pad = 0.f;
-    rec32[pos] = f;
-  }
 }
 
-hipError_t launch_scatter(hipStream_t s, const Particles &P, const Grid &G, const int *cid,
-                          const int *slot, const int *start, Rec *rec, Rec32 *rec32, int *rank,
-                          const BatchDev *B) {
+hipError_t launch_scatter(hipStream_t s, const Particles &P, const int *cid, const int *slot,
+                          const int *start, Rec *rec, int *rank, const BatchDev *B) {
   if (P.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scatter, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, s, P, G, cid,
-                     slot, start, rec, rec32, rank, B ? B->box_of : nullptr,
+  hipLaunchKernelGGL(k_scatter, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, s, P, cid,
+                     slot, start, rec, rank, B ? B->box_of : nullptr,
                      B ? (const unsigned int *)B->flags : nullptr);
   return hipGetLastError();
 }
@@ -486,12 +468,6 @@ hipError_t launch_scatter(hipStream_t s, const Particles &P, const Grid &G, cons
 // and the rule's exact operation order off the hot path; every pair it passes
 // is decided by the rule itself.
 constexpr int MAXRUN = 10;
-
-// records seen through the constant address space: wave-uniform reads of the
-// home spheres become scalar loads (the records are never written during the
-// detect)
-typedef __attribute__((address_space(4))) const Rec *crec_ptr;
-typedef __attribute__((address_space(4))) const Rec32 *crec32_ptr;
 
 // shift code of a run: per axis 0 = -L, 1 = none, 2 = +L (2 bits each), bit 6 = own cell
 __device__ __forceinline__ int run_code(int sx, int sy, int sz, int own) {
@@ -605,24 +581,9 @@ __device__ __forceinline__ bool pass32(const DetectArgs &A, int thr, float bx, f
   return (!MASK || i < thr) && __builtin_fmaf(bb, A.dt2f, cc) <= 0.0f;
 }
 
-// A home's FP32 record from LDS or through the scalar cache (constant address
-// space), field by field.
-template <typename HP>
-__device__ __forceinline__ Rec32 home32(HP p, int k) {
-  Rec32 h;
-  h.x = p[k].x;
-  h.y = p[k].y;
-  h.z = p[k].z;
-  h.r = p[k].r;
-  h.vx = p[k].vx;
-  h.vy = p[k].vy;
-  h.vz = p[k].vz;
-  h.pad = 0.f;
-  return h;
-}
-
-template <bool MASK, typename HP>
-__device__ __forceinline__ void detect_chunk32(const DetectArgs &A, const Grid &G, HP p, int h0,
+// One candidate chunk against the homes [h0, h1) staged in LDS at p.
+template <bool MASK>
+__device__ __forceinline__ void detect_chunk32(const DetectArgs &A, const Grid &G, const Rec32 *p, int h0,
                                                int h1, int g, int thr, int code, double ox,
                                                double oy, double oz, SurvivorQueue &Q) {
   float bx, by, bz, bvx, bvy, bvz, br;
@@ -647,7 +608,7 @@ __device__ __forceinline__ void detect_chunk32(const DetectArgs &A, const Grid &
     // queue (rare) is decided here, outside the loop
     for (; i < h1 && Q.n <= Q.cap - 2 * WAVE; i += 2) {
       const bool two = i + 1 < h1;  // an odd last home pairs with itself, never passing twice
-      const Rec32 ha = home32(p, i - h0), hb = home32(p, two ? i + 1 - h0 : i - h0);
+      const Rec32 ha = p[i - h0], hb = p[two ? i + 1 - h0 : i - h0];
       const bool p0 = pass32<MASK>(A, thr, bx, by, bz, br, bvx, bvy, bvz, i, ha);
       const bool p1 = two && pass32<MASK>(A, thr, bx, by, bz, br, bvx, bvy, bvz, i + 1, hb);
       push_two(p0, p1, i, i + 1, g, Q);
@@ -659,8 +620,7 @@ __device__ __forceinline__ void detect_chunk32(const DetectArgs &A, const Grid &
 
 // Pair tests of one home cell (see k_detect_half).  `start` points at the first
 // cell of the box whose grid is G (cell numbers below are local to that box;
-// sphere positions in start[] are global).  LDSI: lds_raw holds room for the
-// home cell and the workgroup is this single wave.
+// sphere positions in start[] are global).
 // Runs of consecutive cell-sorted records that make the half stencil of one
 // home cell: the own cell (pairs with j after i), the next cell along x, and 4
 // rows of 3 cells, a row split in two where it wraps along x; each with its
@@ -671,17 +631,16 @@ struct CellRuns {
   bool any_shift;
 };
 
-__device__ __forceinline__ bool cell_runs(const Grid &G, const int *start, int cell, CellRuns &R) {
+// The 20 cell starts the runs of cell_runs need, fetched by one vector load
+// (lane k loads slot k) instead of a chain of dependent scalar loads:
+  //   0, 1   the own cell [h0, h1)
+  //   2, 3   the next cell along x (cell 0 of the row where x wraps)
+//   4 + 4 row + {0, 1, 2, 3}: the row's first run and second run (the
+//          second is empty unless the row wraps along x)
+__device__ __forceinline__ int cell_starts(const Grid &G, const int *start, int cell) {
   const int nc0 = G.nc[0], nc1 = G.nc[1], nc2 = G.nc[2];
   int cx, cy, cz;
   cell_xyz(G, cell, cx, cy, cz);
-  const int dys[4] = {1, -1, 0, 1}, dzs[4] = {0, 1, 1, 1};
-  // The 20 cell starts the runs below need, fetched by one vector load (lane
-  // k loads slot k) instead of a chain of dependent scalar loads:
-  //   0, 1   the own cell [h0, h1)
-  //   2, 3   the next cell along x (cell 0 of the row where x wraps)
-  //   4 + 4 row + {0, 1, 2, 3}: the row's first run and second run (the
-  //          second is empty unless the row wraps along x)
   int v = 0;
   {
     // the lane index made opaque per call, so that the lane-constant selections
@@ -713,6 +672,15 @@ __device__ __forceinline__ bool cell_runs(const Grid &G, const int *start, int c
     }
     if (ln < 20) v = start[idx];
   }
+  return v;
+}
+
+// The runs of cell `cell` from its 20 starts v (cell_starts).
+__device__ __forceinline__ bool cell_runs_from(const Grid &G, int cell, int v, CellRuns &R) {
+  const int nc0 = G.nc[0], nc1 = G.nc[1], nc2 = G.nc[2];
+  int cx, cy, cz;
+  cell_xyz(G, cell, cx, cy, cz);
+  const int dys[4] = {1, -1, 0, 1}, dzs[4] = {0, 1, 1, 1};
   const int h0 = __builtin_amdgcn_readlane(v, 0), h1 = __builtin_amdgcn_readlane(v, 1);
   R.h0 = h0;
   R.h1 = h1;
@@ -758,6 +726,10 @@ __device__ __forceinline__ bool cell_runs(const Grid &G, const int *start, int c
   return true;
 }
 
+__device__ __forceinline__ bool cell_runs(const Grid &G, const int *start, int cell, CellRuns &R) {
+  return cell_runs_from(G, cell, cell_starts(G, start, cell), R);
+}
+
 // Candidate slot v of a cell's list (see cell_runs): its sorted index and run
 // code.  The run of v is the last run whose first slot is at most v (an empty
 // run shares its first slot with the next one, so it is never the last such
@@ -778,24 +750,19 @@ __device__ __forceinline__ void cand_of(const int pre[MAXRUN], const int off[MAX
   code = c;
 }
 
-template <bool FP32, bool LDSI>
-__device__ __forceinline__ void detect_cell(const DetectArgs &A, const Grid &G, const int *start,
-                                            int cell, SurvivorQueue &Q, double4 *lds_raw) {
+// Home spheres of the binary32 filter staged in LDS per batch.
+constexpr int HB32 = WAVE;
+
+// Pair tests of one home cell with the binary32 filter.  The home spheres are
+// staged in LDS (hl) HB32 at a time as binary32 records relative to the home
+// cell centre, converted from the binary64 records; candidates in chunks of 64
+// lanes, converted likewise with their run's image shift.
+__device__ __forceinline__ void detect_cell32(const DetectArgs &A, const Grid &G, const int *start,
+                                              int cell, SurvivorQueue &Q, Rec32 *hl) {
   CellRuns R;
   if (!cell_runs(G, start, cell, R)) return;
-  const int h0 = R.h0, h1 = R.h1, cx = R.cx, cy = R.cy, cz = R.cz;
+  const int h0 = R.h0, h1 = R.h1;
   const int *rg = R.rg, *rl = R.rl, *rc = R.rc;
-  const bool any_shift = R.any_shift;
-  if (LDSI) {  // stage the home cell (cap >= occupancy of every cell)
-    for (int k = threadIdx.x; k < h1 - h0; k += WAVE) {
-      if (FP32)
-        ((Rec32 *)lds_raw)[k] = A.rec32[h0 + k];
-      else
-        ((Rec *)lds_raw)[k] = A.rec[h0 + k];
-    }
-    __syncthreads();
-  }
-
   int total = 0;
   int pre[MAXRUN];
 #pragma unroll
@@ -806,38 +773,44 @@ __device__ __forceinline__ void detect_cell(const DetectArgs &A, const Grid &G, 
   // unordered pairs this cell tests: own cell pairs once, every home against the rest
   Q.tests += (unsigned long long)(h1 - h0) * (unsigned long long)(total - (h1 - h0)) +
              (unsigned long long)(h1 - h0) * (unsigned long long)(h1 - h0 - 1) / 2ull;
-
+  const double ox = (R.cx + 0.5) * G.h[0], oy = (R.cy + 0.5) * G.h[1], oz = (R.cz + 0.5) * G.h[2];
   const int lane = __lane_id();
-  for (int base = 0; base < total; base += WAVE) {
-    const int v = base + lane;
-    int g = 0, code = run_code(0, 0, 0, 0);
-    bool ok = false;
+  for (int hb = h0; hb < h1; hb += HB32) {
+    const int he = hb + HB32 < h1 ? hb + HB32 : h1;
+    if (hb + lane < he) {
+      const Rec q = A.rec[hb + lane];
+      Rec32 f;
+      f.x = (float)(q.x - ox);
+      f.y = (float)(q.y - oy);
+      f.z = (float)(q.z - oz);
+      f.r = (float)q.r;
+      f.vx = (float)q.vx;
+      f.vy = (float)q.vy;
+      f.vz = (float)q.vz;
+      f.pad = 0.f;
+      hl[lane] = f;
+    }
+    __syncthreads();  // the workgroup is this one wave
+    for (int base = 0; base < total; base += WAVE) {
+      const int v = base + lane;
+      int g = 0, code = run_code(0, 0, 0, 0);
+      bool ok = false;
 #pragma unroll
-    for (int k = 0; k < MAXRUN; ++k) {
-      if (v >= pre[k] && v < pre[k] + rl[k]) {
-        g = rg[k] + (v - pre[k]);
-        code = rc[k];
-        ok = true;
+      for (int k = 0; k < MAXRUN; ++k) {
+        if (v >= pre[k] && v < pre[k] + rl[k]) {
+          g = rg[k] + (v - pre[k]);
+          code = rc[k];
+          ok = true;
+        }
       }
+      const bool own = (code >> 6) & 1;
+      const int thr = !ok ? -1 : (own ? g : 0x7fffffff);
+      if (base < rl[0])
+        detect_chunk32<true>(A, G, (const Rec32 *)hl, hb, he, g, thr, code, ox, oy, oz, Q);
+      else
+        detect_chunk32<false>(A, G, (const Rec32 *)hl, hb, he, g, thr, code, ox, oy, oz, Q);
     }
-    const bool own = (code >> 6) & 1;
-    const int thr = !ok ? -1 : (own ? g : 0x7fffffff);
-    if (FP32) {
-      const double ox = (cx + 0.5) * G.h[0], oy = (cy + 0.5) * G.h[1], oz = (cz + 0.5) * G.h[2];
-      if (LDSI) {
-        const Rec32 *p = (const Rec32 *)lds_raw;
-        if (base < rl[0])
-          detect_chunk32<true>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, Q);
-        else
-          detect_chunk32<false>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, Q);
-      } else {
-        const crec32_ptr p = (crec32_ptr)A.rec32 + h0;
-        if (base < rl[0])
-          detect_chunk32<true>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, Q);
-        else
-          detect_chunk32<false>(A, G, p, h0, h1, g, thr, code, ox, oy, oz, Q);
-      }
-    }
+    __syncthreads();  // before the next batch overwrites hl
   }
   // the survivors left in Q are the caller's to decide
 }
@@ -903,10 +876,11 @@ __device__ __forceinline__ void detect_chunk64(const DetectArgs &A, const Grid &
 
 // Pair tests of one home cell with the binary64 Gram filter; homes in batches
 // of 64 (hq holds one batch), candidates in chunks of 64 lanes.
-__device__ __forceinline__ void detect_cell64(const DetectArgs &A, const Grid &G, const int *start,
+// v: the cell's 20 starts (cell_starts), loaded ahead by the caller.
+__device__ __forceinline__ void detect_cell64(const DetectArgs &A, const Grid &G, int v,
                                               int cell, SurvivorQueue &Q, HomeQ *hq) {
   CellRuns R;
-  if (!cell_runs(G, start, cell, R)) return;
+  if (!cell_runs_from(G, cell, v, R)) return;
   const int h0 = R.h0, h1 = R.h1, nh = h1 - h0;
   int total = 0;
   int pre[MAXRUN];
@@ -975,21 +949,22 @@ __device__ __forceinline__ void detect_cell64(const DetectArgs &A, const Grid &G
   // or after later cells of the same grid
 }
 
-template <bool FP32, bool LDSI>
+template <bool FP32>
 __global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
-  extern __shared__ double4 lds_raw[];  // LDSI: the home cell's FP32 records
   __shared__ int2 survq[QCAP];
   SurvivorQueue Q{survq, 0, 0u, QCAP, 0ull};
   if (FP32) {  // A.cpw consecutive cells per workgroup (see k_detect_half64g)
+    __shared__ Rec32 hl[HB32];
     const int c0 = xcd_remap(blockIdx.x, gridDim.x) * A.cpw;
     const int c1 = c0 + A.cpw < A.G.ncell ? c0 + A.cpw : A.G.ncell;
     for (int cell = c0; cell < c1; ++cell) {
-      detect_cell<true, LDSI>(A, A.G, A.start, cell, Q, lds_raw);
+      detect_cell32(A, A.G, A.start, cell, Q, hl);
       if (cell + 1 == c1 || Q.n >= WAVE) flush_survivors(A, A.G, Q);
     }
   } else {
     __shared__ HomeQ hq[WAVE];
-    detect_cell64(A, A.G, A.start, xcd_remap(blockIdx.x, gridDim.x), Q, hq);
+    const int cell = xcd_remap(blockIdx.x, gridDim.x);
+    detect_cell64(A, A.G, cell_starts(A.G, A.start, cell), cell, Q, hq);
     flush_survivors(A, A.G, Q);
   }
   // this cell's counts, summed by launch_cell_counts (a counter atomic per
@@ -1008,8 +983,12 @@ __global__ __launch_bounds__(WAVE, 5) void k_detect_half64g(DetectArgs A) {
   SurvivorQueue Q{survq, 0, 0u, QCAP, 0ull};
   const int c0 = xcd_remap(blockIdx.x, gridDim.x) * A.cpw;
   const int c1 = c0 + A.cpw < A.G.ncell ? c0 + A.cpw : A.G.ncell;
+  // the next cell's starts are loaded while this cell is tested
+  int v = c0 < c1 ? cell_starts(A.G, A.start, c0) : 0;
   for (int cell = c0; cell < c1; ++cell) {  // one flush site (register pressure)
-    detect_cell64(A, A.G, A.start, cell, Q, hq);
+    const int vc = v;
+    if (cell + 1 < c1) v = cell_starts(A.G, A.start, cell + 1);
+    detect_cell64(A, A.G, vc, cell, Q, hq);
     if (cell + 1 == c1 || Q.n >= WAVE) flush_survivors(A, A.G, Q);
   }
   if (__lane_id() == 0) A.cellc[blockIdx.x] = CellCount{Q.tests, 0ull};
@@ -1056,7 +1035,7 @@ __global__ __launch_bounds__(256) void k_detect_batched(DetectArgs A, BatchDev B
     const int b = box_of_cell(B.cell_base, B.nbox, item);
     const Grid G = B.gtab[b];
     const int base = B.cell_base[b];
-    detect_cell64(A, G, A.start + base, item - base, Q, hq[wave]);
+    detect_cell64(A, G, cell_starts(G, A.start + base, item - base), item - base, Q, hq[wave]);
     flush_survivors(A, G, Q);  // the next item may be another box's grid
   }
 }
@@ -1085,22 +1064,12 @@ hipError_t launch_cell_counts(hipStream_t s, const CellCount *c, int n, SweepCou
 
 hipError_t launch_detect_half(hipStream_t s, const DetectArgs &A) {
   if (A.G.ncell <= 0) return hipSuccess;
-  const size_t lds = (size_t)A.cap * (A.fp32 ? sizeof(Rec32) : sizeof(Rec));
-  if (A.cap > 0) {
-    if (A.fp32)
-      hipLaunchKernelGGL((k_detect_half<true, true>), dim3(detect_half_blocks(A)), dim3(WAVE), lds,
-                         s, A);
-    else
-      hipLaunchKernelGGL((k_detect_half<false, true>), dim3(A.G.ncell), dim3(WAVE), lds, s, A);
-  } else {
-    if (A.fp32)
-      hipLaunchKernelGGL((k_detect_half<true, false>), dim3(detect_half_blocks(A)), dim3(WAVE), 0,
-                         s, A);
-    else if (A.cpw > 1)
-      hipLaunchKernelGGL(k_detect_half64g, dim3(detect_half_blocks(A)), dim3(WAVE), 0, s, A);
-    else
-      hipLaunchKernelGGL((k_detect_half<false, false>), dim3(A.G.ncell), dim3(WAVE), 0, s, A);
-  }
+  if (A.fp32)
+    hipLaunchKernelGGL(k_detect_half<true>, dim3(detect_half_blocks(A)), dim3(WAVE), 0, s, A);
+  else if (A.cpw > 1)
+    hipLaunchKernelGGL(k_detect_half64g, dim3(detect_half_blocks(A)), dim3(WAVE), 0, s, A);
+  else
+    hipLaunchKernelGGL(k_detect_half<false>, dim3(A.G.ncell), dim3(WAVE), 0, s, A);
   return hipGetLastError();
 }
 
