@@ -252,7 +252,7 @@ def batched_leg(args, pc, torch):
     torch.cuda.synchronize()
     first_ms = (time.perf_counter() - t0) * 1e3
     log(f"[batched] first call {first_ms:.1f} ms (plan, tune={st0['tuned']}, capture): "
-        f"cell_mult {st0['cell_mult']} waves/block {st0['waves_per_block']}")
+        f"cell_mult {st0['cell_mult']} home cells/workgroup {st0['home_cells']}")
     for k in range(args.warmup):
         restore()
         pc.pcol_step_batched(ctx, p, off, Ls, dt, e, partner, None)
@@ -310,7 +310,7 @@ def batched_leg(args, pc, torch):
         "speedup_vs_box_loop": loop_wall * 1e3 / ms,
         "pair_set_mismatch_vs_box_loop": mismatch, "state_bitwise_equal_to_box_loop": same_state,
         "first_call_ms": first_ms, "tuned_on_first_call": bool(st0["tuned"]),
-        "cell_mult": st0["cell_mult"], "waves_per_block": st0["waves_per_block"],
+        "cell_mult": st0["cell_mult"], "home_cells": st0["home_cells"],
         "total_cells": st0["total_cells"],
         "pairs_per_step": statistics.mean(st["n_pairs"] for st in stats),
         "sweeps_per_step": statistics.mean(st["n_sweeps"] for st in stats),

@@ -118,8 +118,9 @@ typedef struct {
                          inflated by a band, survivors decided in binary64. */
   double band_rel;    /* FP32 filter safety band, relative to r_i + r_j (default 1e-4) */
   int timing;         /* 1: time kernels with HIP events; times land in pcol_stats */
-  int autotune;       /* pcol_step_batched: 1 = pick cell size and workgroup shape by timing
-                         candidates on the first call (cached, see pcol_step_batched) */
+  int autotune;       /* pcol_step_batched: 1 = pick cell size and home cells per workgroup
+                         by timing candidates on the first call (cached, see
+                         pcol_step_batched); 0 = opts.cell_mult and 4 cells */
   double split_quantile; /* extent split (default 0.999; 0 or 1 = off): the spheres whose extent
                          r + |v| dt lies above this quantile are searched separately, so the
                          grid's cells need only twice the quantile extent instead of the reach.
@@ -260,7 +261,7 @@ typedef struct {
   int32_t replanned;     /* 1 if this call (re)built the per-box grids and the graph */
   int32_t finished_on_host; /* 1 if the captured sweeps did not suffice and the host finished */
   int32_t tuned;         /* 1 if this call ran the autotuner */
-  int32_t waves_per_block; /* chosen workgroup shape of the pair-test launch */
+  int32_t home_cells;    /* chosen home cells per workgroup of the pair-test launch */
   double cell_mult;      /* chosen cell size factor */
 } pcol_batch_stats;
 
@@ -286,8 +287,8 @@ typedef struct {
  * sweeps captured in the graph (the host runs any beyond them); with 0 the
  * graph starts with 12 and is re-captured with more after a step that needed
  * more.
- * With opts.autotune, the first call times candidate cell sizes and workgroup
- * shapes on scratch copies of the input and keeps the fastest; choices are
+ * With opts.autotune, the first call times candidate cell sizes and home cells
+ * per workgroup on scratch copies of the input and keeps the fastest; choices are
  * cached in the text file named by the environment variable PCOL_TUNE_CACHE
  * (default $HOME/.cache/pcol_tune.txt), keyed by GPU and batch shape.
  * Synchronises once per call (plus planning and tuning calls). */

@@ -72,7 +72,7 @@ class pcol_batch_stats(ctypes.Structure):
                 ("contacts", ctypes.c_int64), ("n_overflow", ctypes.c_int64),
                 ("total_cells", ctypes.c_int64), ("replanned", ctypes.c_int32),
                 ("finished_on_host", ctypes.c_int32), ("tuned", ctypes.c_int32),
-                ("waves_per_block", ctypes.c_int32), ("cell_mult", ctypes.c_double)]
+                ("home_cells", ctypes.c_int32), ("cell_mult", ctypes.c_double)]
 
     as_dict = pcol_stats.as_dict
 

@@ -121,7 +121,7 @@ struct BatchPlan {
   bool tables = false;  // grids planned for the current layout
   // tuning choice
   double cell_mult = 1.0;
-  int wpb = 1;
+  int cpw = 4;           // home cells per workgroup of the pair-test launch
   bool tuned = false;
   int kmax = 12;        // sweeps captured in the graph
   // captured graph and its arguments
@@ -1151,12 +1151,13 @@ BatchDev batch_dev(const BatchPlan *bp) {
 
 // Grid of one box: cell side >= reach * mult * 1.05 per axis (the slack lets
 // the reach grow a little over later steps before a re-plan), no more cells
-// than max(27, 2 n_b) for a box of n_b spheres, and at least 3 cells per axis
-// (else the box is rejected).
+// than max(27, n_b / 8) for a box of n_b spheres (sparse boxes get cells of
+// about 8 spheres: the per-cell work of the pair tests outweighs the extra
+// pairs), and at least 3 cells per axis (else the box is rejected).
 bool box_grid(const double len[3], int64_t nb, double reach, double mult, Grid &G) {
   double cell = reach * mult * 1.05;
   const double vol = len[0] * len[1] * len[2];
-  const double most = (double)(nb > 13 ? 2 * nb : 27);
+  const double most = (double)nb / 8.0 > 27.0 ? (double)nb / 8.0 : 27.0;
   const double floor_side = cbrt(vol / most);
   if (!(cell >= floor_side)) cell = floor_side;
   for (int a = 0; a < 3; ++a) {
@@ -1294,7 +1295,7 @@ static pcol_status batch_plan(pcol_ctx *ctx, int nbox, const int64_t *box_off,
 
 // Enqueue the whole batched step on stream s (captured into a graph).
 static pcol_status batch_enqueue(pcol_ctx *ctx, hipStream_t s, const Particles &P, int32_t *part,
-                                 double *tc, double dt, double e, int kmax, int wpb) {
+                                 double *tc, double dt, double e, int kmax, int cpw) {
   BatchPlan *bp = ctx->bp;
   const BatchDev B = batch_dev(bp);
   const int n = (int)P.n;
@@ -1336,8 +1337,7 @@ static pcol_status batch_enqueue(pcol_ctx *ctx, hipStream_t s, const Particles &
   }
   A.K = ctx->K;
   A.fp32 = 0;
-  int blocks = 256 * 8 * 4 / wpb;  // about 8 resident waves per SIMD
-  PCOL_HIP(launch_detect_batched(s, A, B, blocks, wpb));
+  PCOL_HIP(launch_detect_batched(s, A, B, bp->total_cells, cpw));
   PCOL_HIP(launch_slot_min(s, n, 1, ctx->cnt, ctx->slot_t, ctx->slot_j, ctx->K, ctx->status,
                            ctx->rec, ctx->key_j, ctx->key_t, ctx->ovf, ctx->ctr_d, bp->flags));
   PCOL_HIP(launch_gather_exact(s, ctx->ovf, 0, &ctx->ctr_d->n_overflow, -1, ctx->rec, ctx->start,
@@ -1358,11 +1358,11 @@ static pcol_status batch_enqueue(pcol_ctx *ctx, hipStream_t s, const Particles &
 }
 
 static pcol_status batch_capture(pcol_ctx *ctx, const Particles &P, int32_t *part, double *tc,
-                                 double dt, double e, int kmax, int wpb, hipGraphExec_t *exec) {
+                                 double dt, double e, int kmax, int cpw, hipGraphExec_t *exec) {
   BatchPlan *bp = ctx->bp;
   if (!bp->gstream) PCOL_HIP(hipStreamCreateWithFlags(&bp->gstream, hipStreamNonBlocking));
   PCOL_HIP(hipStreamBeginCapture(bp->gstream, hipStreamCaptureModeRelaxed));
-  pcol_status st = batch_enqueue(ctx, bp->gstream, P, part, tc, dt, e, kmax, wpb);
+  pcol_status st = batch_enqueue(ctx, bp->gstream, P, part, tc, dt, e, kmax, cpw);
   hipGraph_t g = nullptr;
   hipError_t ee = hipStreamEndCapture(bp->gstream, &g);
   if (st != PCOL_OK) {
@@ -1417,7 +1417,7 @@ static std::string tune_key(int nbox, int64_t n, const int64_t *box_off, const p
   double vol = 0.0;
   for (int b = 0; b < nbox; ++b) vol += boxes[b].len[0] * boxes[b].len[1] * boxes[b].len[2];
   std::ostringstream k;
-  k << prop.gcnArchName << "|n" << (int)round(log2((double)(n > 0 ? n : 1))) << "|b"
+  k << "c" << prop.gcnArchName << "|n" << (int)round(log2((double)(n > 0 ? n : 1))) << "|b"
     << (int)round(log2((double)nbox)) << "|rho" << (int)round(4.0 * log2(n / vol + 1e-300))
     << "|dt" << dt;
   (void)box_off;
@@ -1434,7 +1434,7 @@ static std::string tune_path() {
   return std::string(h ? h : ".") + "/.cache/pcol_tune.txt";
 }
 
-static bool tune_lookup(const std::string &key, double &mult, int &wpb) {
+static bool tune_lookup(const std::string &key, double &mult, int &cpw) {
   std::ifstream f(tune_path());
   std::string k;
   double m;
@@ -1443,20 +1443,20 @@ static bool tune_lookup(const std::string &key, double &mult, int &wpb) {
   while (f >> k >> m >> w)
     if (k == key) {
       mult = m;
-      wpb = w;
+      cpw = w;
       found = true;
     }
   return found;
 }
 
-static void tune_store(const std::string &key, double mult, int wpb) {
+static void tune_store(const std::string &key, double mult, int cpw) {
   std::ofstream f(tune_path(), std::ios::app);
-  if (f) f << key << " " << mult << " " << wpb << "\n";
+  if (f) f << key << " " << mult << " " << cpw << "\n";
 }
 
-// Time candidate (cell size factor, workgroup shape) pairs on scratch copies of
-// the input; keep the fastest.  Every candidate computes the same step (the
-// result does not depend on the cell size or the launch shape).
+// Time candidate (cell size factor, home cells per workgroup) pairs on scratch
+// copies of the input; keep the fastest.  Every candidate computes the same
+// step (the result does not depend on the cell size or the launch shape).
 static pcol_status batch_autotune(pcol_ctx *ctx, int nbox, const int64_t *box_off,
                                   const pcol_box *boxes, const Particles &P, double dt,
                                   double e) {
@@ -1481,16 +1481,16 @@ static pcol_status batch_autotune(pcol_ctx *ctx, int nbox, const int64_t *box_of
   T.vy = dst[4];
   T.vz = dst[5];
   const double mults[3] = {1.0, 1.15, 1.3};
-  const int shapes[2] = {1, 4};
+  const int shapes[3] = {2, 4, 8};  // home cells per workgroup
   double best = 1e300, best_mult = 1.0;
-  int best_wpb = 1;
+  int best_cpw = 4;
   for (double mult : mults) {
     pcol_status st = batch_plan(ctx, nbox, box_off, boxes, P, dt, mult);
     if (st == PCOL_E_BOX) continue;  // this cell size leaves some box under 3 cells
     if (st != PCOL_OK) return st;
-    for (int wpb : shapes) {
+    for (int cpw : shapes) {
       hipGraphExec_t ex = nullptr;
-      if ((st = batch_capture(ctx, T, ctx->partner_tmp, ctx->tcoll_tmp, dt, e, bp->kmax, wpb,
+      if ((st = batch_capture(ctx, T, ctx->partner_tmp, ctx->tcoll_tmp, dt, e, bp->kmax, cpw,
                               &ex)) != PCOL_OK)
         return st;
       float times[3];
@@ -1508,12 +1508,12 @@ static pcol_status batch_autotune(pcol_ctx *ctx, int nbox, const int64_t *box_of
       if (times[1] < best) {
         best = times[1];
         best_mult = mult;
-        best_wpb = wpb;
+        best_cpw = cpw;
       }
     }
   }
   bp->cell_mult = best_mult;
-  bp->wpb = best_wpb;
+  bp->cpw = best_cpw;
   bp->tuned = true;
   bp->tables = false;
   return PCOL_OK;
@@ -1560,17 +1560,17 @@ extern "C" pcol_status pcol_step_batched(pcol_ctx *ctx, int32_t nbox, const int6
     int w;
     if (tune_lookup(key, m, w)) {
       bp->cell_mult = m;
-      bp->wpb = w;
+      bp->cpw = w;
       bp->tuned = true;
     } else {
       if ((st = batch_autotune(ctx, nbox, box_off, boxes, P, dt, e)) != PCOL_OK) return st;
-      tune_store(key, bp->cell_mult, bp->wpb);
+      tune_store(key, bp->cell_mult, bp->cpw);
       tuned = 1;
     }
   }
   if (!ctx->opts.autotune && !bp->tuned) {
     bp->cell_mult = ctx->opts.cell_mult;
-    bp->wpb = 1;
+    bp->cpw = 4;
   }
   for (int attempt = 0;; ++attempt) {
     if (!same_layout || !bp->tables) {
@@ -1585,7 +1585,7 @@ extern "C" pcol_status pcol_step_batched(pcol_ctx *ctx, int32_t nbox, const int6
     if (recapture) {
       if (bp->exec) (void)hipGraphExecDestroy(bp->exec);
       bp->exec = nullptr;
-      if ((st = batch_capture(ctx, P, part, tc, dt, e, bp->kmax, bp->wpb, &bp->exec)) != PCOL_OK)
+      if ((st = batch_capture(ctx, P, part, tc, dt, e, bp->kmax, bp->cpw, &bp->exec)) != PCOL_OK)
         return st;
       bp->captured = true;
       bp->cap_dt = dt;
@@ -1617,6 +1617,11 @@ extern "C" pcol_status pcol_step_batched(pcol_ctx *ctx, int32_t nbox, const int6
       bp->kmax = (int)sweeps + 4;
       bp->captured = false;
     }
+  } else if (ctx->opts.max_sweeps == 0 && bp->kmax > (int)sweeps + 4) {
+    // far more sweep slots than the step used: each empty slot still launches
+    // its kernels (early exits), so capture fewer next time
+    bp->kmax = (int)sweeps + 4;
+    bp->captured = false;
   }
   if (stats) {
     memset(stats, 0, sizeof(*stats));
@@ -1628,7 +1633,7 @@ extern "C" pcol_status pcol_step_batched(pcol_ctx *ctx, int32_t nbox, const int6
     stats->replanned = replanned;
     stats->finished_on_host = host_finish;
     stats->tuned = tuned;
-    stats->waves_per_block = bp->wpb;
+    stats->home_cells = bp->cpw;
     stats->cell_mult = bp->cell_mult;
   }
   return PCOL_OK;

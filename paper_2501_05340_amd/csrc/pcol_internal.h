@@ -464,8 +464,9 @@ hipError_t launch_breach(hipStream_t s, const Particles &P, const BatchDev &B, d
                          int check_plan);
 hipError_t launch_cell_hist_b(hipStream_t s, const Particles &P, const BatchDev &B, int *cid,
                               int *slot, int *count);
+// cpw consecutive global cells per workgroup (one wave) over total_cells
 hipError_t launch_detect_batched(hipStream_t s, const DetectArgs &A, const BatchDev &B,
-                                 int blocks, int waves_per_block);
+                                 int total_cells, int cpw);
 hipError_t launch_sweep_check(hipStream_t s, SweepCounters *ctr, unsigned int *flags,
                               unsigned long long *totals, int last);
 hipError_t launch_advance(hipStream_t s, const Particles &P, const int *partner, double dt,

@@ -1015,28 +1015,34 @@ __device__ __forceinline__ int box_of_cell(const int *cell_base, int nbox, int c
   return lo;
 }
 
-// Batched form: one persistent launch over the cells of all boxes.  Each wave
-// takes work items (global cell numbers) in a fixed interleaved order and runs
-// the single-box pair tests with its box's grid from the table.  Plain FP64
-// filter, home spheres through the scalar cache (no LDS, so a workgroup may
-// hold several independent waves).
-__global__ __launch_bounds__(256) void k_detect_batched(DetectArgs A, BatchDev B) {
+// Batched form: the cells of all boxes are numbered consecutively, box after
+// box, and each workgroup (one wave) takes cpw consecutive global cells, as
+// k_detect_half64g does in one box: the box of each cell comes from the
+// first-cell table, the pair tests run with that box's grid, and the survivor
+// queue carries over the cells, decided with the grid of the box its survivors
+// came from whenever the next cell lies in another box, when it holds a wave's
+// worth, and at the end.
+__global__ __launch_bounds__(WAVE) void k_detect_batched(DetectArgs A, BatchDev B, int cpw) {
   if (B.flags[FLAG_ERR]) return;
-  __shared__ int2 survq[4][QCAP];
-  __shared__ HomeQ hq[4][WAVE];
-  const int wpb = blockDim.x / WAVE;
-  // the wave's index, as a wave-uniform value (so are the items and their box,
-  // whose grid then sits in scalar registers)
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  __shared__ int2 survq[QCAP];
+  __shared__ HomeQ hq[WAVE];
+  SurvivorQueue Q{survq, 0, 0u, QCAP, 0ull};
   const int total = B.cell_base[B.nbox];
-  const int stride = gridDim.x * wpb;
-  SurvivorQueue Q{survq[wave], 0, 0u, QCAP, 0ull};
-  for (int item = blockIdx.x * wpb + wave; item < total; item += stride) {
-    const int b = box_of_cell(B.cell_base, B.nbox, item);
+  const int c0 = xcd_remap(blockIdx.x, gridDim.x) * cpw;
+  const int c1 = c0 + cpw < total ? c0 + cpw : total;
+  if (c0 >= c1) return;
+  int b = box_of_cell(B.cell_base, B.nbox, c0);
+  int qb = b;  // the box of the queued survivors
+  for (int item = c0; item < c1; ++item) {
+    while (item >= B.cell_base[b + 1]) ++b;  // boxes of no cells are passed over
+    if (b != qb) {
+      if (Q.n > 0) flush_survivors(A, B.gtab[qb], Q);
+      qb = b;
+    }
     const Grid G = B.gtab[b];
     const int base = B.cell_base[b];
-    detect_cell64(A, G, cell_starts(G, A.start + base, item - base), item - base, Q, hq[wave]);
-    flush_survivors(A, G, Q);  // the next item may be another box's grid
+    detect_cell64(A, G, cell_starts(G, A.start + base, item - base), item - base, Q, hq);
+    if (item + 1 == c1 || Q.n >= WAVE) flush_survivors(A, G, Q);
   }
 }
 
@@ -2059,9 +2065,10 @@ hipError_t launch_cell_hist_b(hipStream_t s, const Particles &P, const BatchDev 
 }
 
 hipError_t launch_detect_batched(hipStream_t s, const DetectArgs &A, const BatchDev &B,
-                                 int blocks, int waves_per_block) {
-  if (waves_per_block < 1 || waves_per_block > 4) return hipErrorInvalidValue;  // queue slices
-  hipLaunchKernelGGL(k_detect_batched, dim3(blocks), dim3(WAVE * waves_per_block), 0, s, A, B);
+                                 int total_cells, int cpw) {
+  if (cpw < 1 || total_cells <= 0) return cpw < 1 ? hipErrorInvalidValue : hipSuccess;
+  hipLaunchKernelGGL(k_detect_batched, dim3((unsigned)((total_cells + cpw - 1) / cpw)), dim3(WAVE),
+                     0, s, A, B, cpw);
   return hipGetLastError();
 }
 

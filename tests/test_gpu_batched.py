@@ -207,7 +207,7 @@ def test_batched_equals_single_box_steps_config_shape(tmp_path):
         ctx.close()
     assert results[0]["tuned"] == 1 and results[1]["tuned"] == 0
     assert results[0]["cell_mult"] == results[1]["cell_mult"]
-    assert results[0]["waves_per_block"] == results[1]["waves_per_block"]
+    assert results[0]["home_cells"] == results[1]["home_cells"]
     assert os.path.exists(os.environ["PCOL_TUNE_CACHE"])
 
 
