@@ -109,6 +109,12 @@ struct BatchPlan {
   int *box_of = nullptr;
   int64_t *box_off_d = nullptr;
   double *breach = nullptr;
+  int *chunk_box = nullptr;               // chunks of the reach pass (BREACH_CHUNK spheres)
+  int64_t *chunk_lo = nullptr;
+  BoxMax *bmax = nullptr;                 // [nbox], zero between passes
+  int nchunk = 0, cap_chunk = 0;
+  std::vector<int> chunk_box_h;
+  std::vector<int64_t> chunk_lo_h;
   unsigned int *flags = nullptr;          // FLAG_* words
   unsigned long long *totals = nullptr;   // pairs, contacts, overflow
   int cap_box = 0;
@@ -379,8 +385,9 @@ void pcol_destroy(pcol_ctx *ctx) {
   for (hipEvent_t &e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
   if (BatchPlan *bp = ctx->bp) {
-    void *bd[] = {bp->gtab, bp->cell_base, bp->box_of, bp->box_off_d,
-                  bp->breach, bp->flags, bp->totals, bp->tune_buf};
+    void *bd[] = {bp->gtab,    bp->cell_base, bp->box_of, bp->box_off_d, bp->breach,
+                  bp->chunk_box, bp->chunk_lo, bp->bmax,  bp->flags,     bp->totals,
+                  bp->tune_buf};
     for (void *q : bd)
       if (q) (void)hipFree(q);
     if (bp->flags_h) (void)hipHostFree(bp->flags_h);
@@ -1144,6 +1151,10 @@ BatchDev batch_dev(const BatchPlan *bp) {
   B.box_of = bp->box_of;
   B.box_off = bp->box_off_d;
   B.breach = bp->breach;
+  B.nchunk = bp->nchunk;
+  B.chunk_box = bp->chunk_box;
+  B.chunk_lo = bp->chunk_lo;
+  B.bmax = bp->bmax;
   B.flags = bp->flags;
   B.nbox = bp->nbox;
   return B;
@@ -1220,10 +1231,35 @@ static pcol_status batch_plan(pcol_ctx *ctx, int nbox, const int64_t *box_off,
     if ((e = regrow(&bp->gtab, nbox)) != hipSuccess ||
         (e = regrow(&bp->cell_base, nbox + 1)) != hipSuccess ||
         (e = regrow(&bp->box_off_d, nbox + 1)) != hipSuccess ||
-        (e = regrow(&bp->breach, nbox)) != hipSuccess)
+        (e = regrow(&bp->breach, nbox)) != hipSuccess ||
+        (e = regrow(&bp->bmax, nbox)) != hipSuccess)
       return fail(ctx, PCOL_E_NOMEM, "batched tables");
     bp->cap_box = nbox;
   }
+  // chunks of the reach pass: each box cut into pieces of BREACH_CHUNK spheres
+  std::vector<int> &cbox = bp->chunk_box_h;
+  std::vector<int64_t> &clo = bp->chunk_lo_h;
+  cbox.clear();
+  clo.clear();
+  for (int b = 0; b < nbox; ++b)
+    for (int64_t lo = box_off[b]; lo < box_off[b + 1]; lo += BREACH_CHUNK) {
+      cbox.push_back(b);
+      clo.push_back(lo);
+    }
+  if ((int)cbox.size() > bp->cap_chunk) {
+    if ((e = regrow(&bp->chunk_box, (int64_t)cbox.size())) != hipSuccess ||
+        (e = regrow(&bp->chunk_lo, (int64_t)cbox.size())) != hipSuccess)
+      return fail(ctx, PCOL_E_NOMEM, "batched tables");
+    bp->cap_chunk = (int)cbox.size();
+  }
+  bp->nchunk = (int)cbox.size();
+  if (!cbox.empty()) {
+    PCOL_HIP(hipMemcpyAsync(bp->chunk_box, cbox.data(), cbox.size() * sizeof(int),
+                            hipMemcpyHostToDevice, s));
+    PCOL_HIP(hipMemcpyAsync(bp->chunk_lo, clo.data(), clo.size() * sizeof(int64_t),
+                            hipMemcpyHostToDevice, s));
+  }
+  PCOL_HIP(hipMemsetAsync(bp->bmax, 0, (size_t)nbox * sizeof(BoxMax), s));
   if (P.n > bp->cap_n) {
     if ((e = regrow(&bp->box_of, P.n)) != hipSuccess)
       return fail(ctx, PCOL_E_NOMEM, "batched tables");

@@ -368,6 +368,15 @@ struct StateGrad {
 // let every kernel of a captured step skip its work.
 enum { FLAG_DONE = 0, FLAG_ERR = 1, FLAG_SWEEPS = 2, FLAG_UNFINISHED = 3 };
 enum : unsigned int { ERR_INVALID = 1u, ERR_REPLAN = 2u, ERR_BOX = 4u };
+// A box's maxima during the batched reach pass (bits of non-negative doubles)
+// and its validity bits; zero between passes.
+struct BoxMax {
+  unsigned long long v2, rm;
+  unsigned int bad, pad;
+};
+// Spheres per workgroup of the batched reach pass (a box spans one or more).
+constexpr int BREACH_CHUNK = 4096;
+
 struct BatchDev {
   const Grid *gtab;       // [nbox]
   const int *cell_base;   // [nbox + 1]
@@ -376,6 +385,10 @@ struct BatchDev {
   double *breach;         // [nbox] reach found by the last step
   unsigned int *flags;    // FLAG_* words
   int nbox;
+  int nchunk;             // chunks of the reach pass: box chunk_box[k], spheres from chunk_lo[k]
+  const int *chunk_box;
+  const int64_t *chunk_lo;
+  BoxMax *bmax;           // [nbox]
 };
 
 // Pair tests and filter survivors of one workgroup of the k_detect_half kernels.

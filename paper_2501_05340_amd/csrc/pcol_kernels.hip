@@ -1978,16 +1978,20 @@ hipError_t launch_fill_box_of(hipStream_t s, int nbox, const int64_t *box_off, i
   return hipGetLastError();
 }
 
-// a1 per box, one workgroup per box: data validity, reach = 2 max r + 2 max|v| dt
-// (stored), the box check L > 2 reach, and whether the planned cells are still
-// at least the reach wide (else the host re-plans before any state changes).
-__global__ __launch_bounds__(256) void k_breach(Particles P, BatchDev B, double dt,
-                                                int check_plan) {
-  const int b = blockIdx.x;
-  const Grid G = B.gtab[b];
+// a1 per box: data validity, reach = 2 max r + 2 max|v| dt (stored), the box
+// check L > 2 reach, and whether the planned cells are still at least the reach
+// wide (else the host re-plans before any state changes).  Boxes are cut into
+// chunks of at most BREACH_CHUNK spheres, one workgroup each, which merge their
+// maxima into the box's BoxMax; k_breach_fin then takes one box per thread
+// and clears its BoxMax for the next pass.
+__global__ __launch_bounds__(256) void k_breach(Particles P, BatchDev B) {
+  const int b = B.chunk_box[blockIdx.x];
+  const Grid &G = B.gtab[b];
+  const int64_t lo = B.chunk_lo[blockIdx.x];
+  const int64_t hi = lo + BREACH_CHUNK < B.box_off[b + 1] ? lo + BREACH_CHUNK : B.box_off[b + 1];
   double v2 = 0.0, rm = 0.0;
   unsigned int bad = 0u;
-  for (int64_t i = B.box_off[b] + threadIdx.x; i < B.box_off[b + 1]; i += 256) {
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
     const double x = P.x[i], y = P.y[i], z = P.z[i];
     const double vx = P.vx[i], vy = P.vy[i], vz = P.vz[i];
     const double r = P.r[i], m = P.m[i];
@@ -2023,20 +2027,35 @@ __global__ __launch_bounds__(256) void k_breach(Particles P, BatchDev B, double 
       rm = sr[k] > rm ? sr[k] : rm;
       bad |= sb[k];
     }
-    const double reach = 2.0 * rm + 2.0 * sqrt(v2) * dt;
-    B.breach[b] = reach;
-    for (int a = 0; a < 3; ++a) {
-      if (!(G.L[a] > 2.0 * reach)) bad |= ERR_BOX;
-      if (check_plan && !(reach * (1.0 + 1e-9) <= G.L[a] / G.nc[a])) bad |= ERR_REPLAN;
-    }
-    if (bad) atomicOr(&B.flags[FLAG_ERR], bad);
+    atomicMax(&B.bmax[b].v2, dbits(v2));
+    atomicMax(&B.bmax[b].rm, dbits(rm));
+    if (bad) atomicOr(&B.bmax[b].bad, bad);
   }
+}
+
+__global__ __launch_bounds__(256) void k_breach_fin(BatchDev B, double dt, int check_plan) {
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  if (b >= B.nbox) return;
+  const BoxMax mx = B.bmax[b];
+  B.bmax[b] = BoxMax{0ull, 0ull, 0u, 0u};
+  const double v2 = __longlong_as_double((long long)mx.v2);
+  const double rm = __longlong_as_double((long long)mx.rm);
+  unsigned int bad = mx.bad;
+  const Grid &G = B.gtab[b];
+  const double reach = 2.0 * rm + 2.0 * sqrt(v2) * dt;
+  B.breach[b] = reach;
+  for (int a = 0; a < 3; ++a) {
+    if (!(G.L[a] > 2.0 * reach)) bad |= ERR_BOX;
+    if (check_plan && !(reach * (1.0 + 1e-9) <= G.L[a] / G.nc[a])) bad |= ERR_REPLAN;
+  }
+  if (bad) atomicOr(&B.flags[FLAG_ERR], bad);
 }
 
 hipError_t launch_breach(hipStream_t s, const Particles &P, const BatchDev &B, double dt,
                          int check_plan) {
   if (B.nbox <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_breach, dim3(B.nbox), dim3(256), 0, s, P, B, dt, check_plan);
+  if (B.nchunk > 0) hipLaunchKernelGGL(k_breach, dim3(B.nchunk), dim3(256), 0, s, P, B);
+  hipLaunchKernelGGL(k_breach_fin, dim3((B.nbox + 255) / 256), dim3(256), 0, s, B, dt, check_plan);
   return hipGetLastError();
 }
 
