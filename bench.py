@@ -58,8 +58,9 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2501_05340_amd", "csrc", f)
 def measured_traffic():
     """Counted HBM bytes from the committed counter summary of one 16M FP64 step
     (FETCH_SIZE + WRITE_SIZE, scaled by the plain-copy calibration): the detect
-    kernel's bytes per launch and each phase's bytes per step, or None when the
-    kernel sources changed since the counters were taken."""
+    kernel's bytes per launch, each phase's bytes per step and the bytes of one
+    stored-order deposition call, or None when the kernel sources changed since
+    the counters were taken."""
     import hashlib
     try:
         text = open(TRAFFIC_PROFILE).read()
@@ -69,7 +70,8 @@ def measured_traffic():
             return None
         return {"detect_launch": float(vals["traffic_bytes_per_launch"]),
                 "phases": {k.split(".", 1)[1]: float(v) for k, v in vals.items()
-                           if k.startswith("phase_counted_bytes.")}}
+                           if k.startswith("phase_counted_bytes.")},
+                "deposition_call": float(vals["deposition_counted_bytes_per_call"])}
     except (OSError, KeyError, ValueError):
         return None
 
@@ -531,6 +533,8 @@ def deposition_leg(args, pc, torch, box, p0):
     # algorithmic bytes: positions and sources read once, the node array written once
     # (the operator's own traffic, whatever the scratch of the sort)
     alg = box.n * (24 + 8 * comp) + nnode * comp * 8
+    counted = measured_traffic()
+    traffic = counted["deposition_call"] if counted else None
     res = {
         "value": box.n / wall, "unit": "particles/s", "ms_per_call": wall * 1e3,
         "nc": list(nc), "comp": comp, "spheres_per_element": box.n / nnode,
@@ -538,7 +542,9 @@ def deposition_leg(args, pc, torch, box, p0):
         "algorithmic_bytes": alg, "algorithmic_GBps": alg / wall / 1e9,
         # the whole call (sort and sums) against the HBM peak, on its algorithmic bytes
         "roofline": {"bound": "hbm", "achieved": alg / wall / 1e9, "peak": 8000.0,
-                     "unit": "GB/s", "frac": alg / wall / 8e12, "traffic": None,
+                     "unit": "GB/s", "frac": alg / wall / 8e12, "traffic": traffic,
+                     "traffic_unit": "bytes per call",
+                     "hbm_frac_counted": traffic / wall / 8e12 if traffic else None,
                      "kernel": "pcol_deposit (k_dep_count, scan, k_dep_scatter, k_dep_tile)"},
         "element_sorted_ms_per_call": wall_sorted * 1e3,
         "element_sorted_max_abs_diff": sorted_diff,
