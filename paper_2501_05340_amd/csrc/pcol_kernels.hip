@@ -474,9 +474,9 @@ __device__ __forceinline__ int run_code(int sx, int sy, int sz, int own) {
   return (sx + 1) | ((sy + 1) << 2) | ((sz + 1) << 4) | (own << 6);
 }
 
-__device__ __forceinline__ double code_shift(int c, double L) {
-  return c == 0 ? -L : (c == 2 ? L : 0.0);
-}
+// -L, 0 or +L for c = 0, 1, 2: (c - 1) L is each of them exactly (one convert
+// and one multiply instead of a chain of selects).
+__device__ __forceinline__ double code_shift(int c, double L) { return (double)(c - 1) * L; }
 
 // Candidate slots past the end of the list hold this far-away sphere: its
 // separation squares to +inf and b stays finite, so it never passes the reject.
@@ -730,25 +730,6 @@ __device__ __forceinline__ bool cell_runs(const Grid &G, const int *start, int c
   return cell_runs_from(G, cell, cell_starts(G, start, cell), R);
 }
 
-// Candidate slot v of a cell's list (see cell_runs): its sorted index and run
-// code.  The run of v is the last run whose first slot is at most v (an empty
-// run shares its first slot with the next one, so it is never the last such
-// run for a slot inside the list); off[k] = rg[k] - pre[k] turns the slot into
-// the index.  ok: v is inside the list.
-__device__ __forceinline__ void cand_of(const int pre[MAXRUN], const int off[MAXRUN],
-                                        const int *rc, int total, int v, int &g, int &code,
-                                        bool &ok) {
-  int o = off[0], c = rc[0];
-#pragma unroll
-  for (int k = 1; k < MAXRUN; ++k) {
-    const bool in = v >= pre[k];
-    o = in ? off[k] : o;
-    c = in ? rc[k] : c;
-  }
-  ok = v < total;
-  g = o + v;
-  code = c;
-}
 
 // Home spheres of the binary32 filter staged in LDS per batch.
 constexpr int HB32 = WAVE;
@@ -756,13 +737,14 @@ constexpr int HB32 = WAVE;
 // Pair tests of one home cell with the binary32 filter.  The home spheres are
 // staged in LDS (hl) HB32 at a time as binary32 records relative to the home
 // cell centre, converted from the binary64 records; candidates in chunks of 64
-// lanes, converted likewise with their run's image shift.
+// lanes, converted likewise with their run's image shift.  rt: the wave's room
+// in LDS for the cell's run table (MAXRUN entries).
 __device__ __forceinline__ void detect_cell32(const DetectArgs &A, const Grid &G, const int *start,
-                                              int cell, SurvivorQueue &Q, Rec32 *hl) {
+                                              int cell, SurvivorQueue &Q, Rec32 *hl, int2 *rt) {
   CellRuns R;
   if (!cell_runs(G, start, cell, R)) return;
   const int h0 = R.h0, h1 = R.h1;
-  const int *rg = R.rg, *rl = R.rl, *rc = R.rc;
+  const int *rl = R.rl;
   int total = 0;
   int pre[MAXRUN];
 #pragma unroll
@@ -770,11 +752,15 @@ __device__ __forceinline__ void detect_cell32(const DetectArgs &A, const Grid &G
     pre[k] = total;
     total += rl[k];
   }
+  const int lane = __lane_id();
+  if (lane == 0) {  // the run table, as in detect_cell64
+#pragma unroll
+    for (int k = 0; k < MAXRUN; ++k) rt[k] = make_int2(R.rg[k] - pre[k], R.rc[k]);
+  }
   // unordered pairs this cell tests: own cell pairs once, every home against the rest
   Q.tests += (unsigned long long)(h1 - h0) * (unsigned long long)(total - (h1 - h0)) +
              (unsigned long long)(h1 - h0) * (unsigned long long)(h1 - h0 - 1) / 2ull;
   const double ox = (R.cx + 0.5) * G.h[0], oy = (R.cy + 0.5) * G.h[1], oz = (R.cz + 0.5) * G.h[2];
-  const int lane = __lane_id();
   for (int hb = h0; hb < h1; hb += HB32) {
     const int he = hb + HB32 < h1 ? hb + HB32 : h1;
     if (hb + lane < he) {
@@ -793,16 +779,12 @@ __device__ __forceinline__ void detect_cell32(const DetectArgs &A, const Grid &G
     __syncthreads();  // the workgroup is this one wave
     for (int base = 0; base < total; base += WAVE) {
       const int v = base + lane;
-      int g = 0, code = run_code(0, 0, 0, 0);
-      bool ok = false;
+      int r = 0;  // the run of list slot v (see detect_cell64)
 #pragma unroll
-      for (int k = 0; k < MAXRUN; ++k) {
-        if (v >= pre[k] && v < pre[k] + rl[k]) {
-          g = rg[k] + (v - pre[k]);
-          code = rc[k];
-          ok = true;
-        }
-      }
+      for (int k = 1; k < MAXRUN; ++k) r += v >= pre[k] ? 1 : 0;
+      const int2 run = rt[r];
+      const int g = run.x + v, code = run.y;
+      const bool ok = v < total;
       const bool own = (code >> 6) & 1;
       const int thr = !ok ? -1 : (own ? g : 0x7fffffff);
       if (base < rl[0])
@@ -876,9 +858,10 @@ __device__ __forceinline__ void detect_chunk64(const DetectArgs &A, const Grid &
 
 // Pair tests of one home cell with the binary64 Gram filter; homes in batches
 // of 64 (hq holds one batch), candidates in chunks of 64 lanes.
-// v: the cell's 20 starts (cell_starts), loaded ahead by the caller.
+// v: the cell's 20 starts (cell_starts), loaded ahead by the caller; rt: the
+// wave's room in LDS for the cell's run table (MAXRUN entries).
 __device__ __forceinline__ void detect_cell64(const DetectArgs &A, const Grid &G, int v,
-                                              int cell, SurvivorQueue &Q, HomeQ *hq) {
+                                              int cell, SurvivorQueue &Q, HomeQ *hq, int2 *rt) {
   CellRuns R;
   if (!cell_runs_from(G, cell, v, R)) return;
   const int h0 = R.h0, h1 = R.h1, nh = h1 - h0;
@@ -894,9 +877,12 @@ __device__ __forceinline__ void detect_cell64(const DetectArgs &A, const Grid &G
   const int lane = __lane_id();
   const double ox = (R.cx + 0.5) * G.h[0], oy = (R.cy + 0.5) * G.h[1], oz = (R.cz + 0.5) * G.h[2];
   const double dt2 = A.dt2;
-  int off[MAXRUN];
+  // the run table in LDS (the wave's own; its LDS operations stay in order):
+  // run k's offset from list slot to sorted index (rg[k] - pre[k]) and its code
+  if (lane == 0) {
 #pragma unroll
-  for (int k = 0; k < MAXRUN; ++k) off[k] = R.rg[k] - pre[k];
+    for (int k = 0; k < MAXRUN; ++k) rt[k] = make_int2(R.rg[k] - pre[k], R.rc[k]);
+  }
   for (int hb = 0; hb < nh; hb += WAVE) {
     const int nb = nh - hb < WAVE ? nh - hb : WAVE;
     if (lane < nb) {  // this batch's home terms (one wave owns hq: in-order LDS)
@@ -916,9 +902,16 @@ __device__ __forceinline__ void detect_cell64(const DetectArgs &A, const Grid &G
     }
     for (int base = 0; base < total; base += WAVE) {
       const int v = base + lane;
-      int g, code;
-      bool ok;
-      cand_of(pre, off, R.rc, total, v, g, code, ok);
+      // the run of list slot v: the last run whose first slot is at most v.  The
+      // first slots are non-decreasing, so it is the number of runs after the
+      // first that start at or before v (an empty run starts where the next
+      // does, so it is never the one counted last for a slot inside the list)
+      int r = 0;
+#pragma unroll
+      for (int k = 1; k < MAXRUN; ++k) r += v >= pre[k] ? 1 : 0;
+      const int2 run = rt[r];
+      const int g = run.x + v, code = run.y;
+      const bool ok = v < total;
       const bool own = (code >> 6) & 1;
       const int thr = !ok ? -1 : (own ? g : 0x7fffffff);
       double P[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -955,16 +948,18 @@ __global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
   SurvivorQueue Q{survq, 0, 0u, QCAP, 0ull};
   if (FP32) {  // A.cpw consecutive cells per workgroup (see k_detect_half64g)
     __shared__ Rec32 hl[HB32];
+    __shared__ int2 rt[MAXRUN];
     const int c0 = xcd_remap(blockIdx.x, gridDim.x) * A.cpw;
     const int c1 = c0 + A.cpw < A.G.ncell ? c0 + A.cpw : A.G.ncell;
     for (int cell = c0; cell < c1; ++cell) {
-      detect_cell32(A, A.G, A.start, cell, Q, hl);
+      detect_cell32(A, A.G, A.start, cell, Q, hl, rt);
       if (cell + 1 == c1 || Q.n >= WAVE) flush_survivors(A, A.G, Q);
     }
   } else {
     __shared__ HomeQ hq[WAVE];
+    __shared__ int2 rt[MAXRUN];
     const int cell = xcd_remap(blockIdx.x, gridDim.x);
-    detect_cell64(A, A.G, cell_starts(A.G, A.start, cell), cell, Q, hq);
+    detect_cell64(A, A.G, cell_starts(A.G, A.start, cell), cell, Q, hq, rt);
     flush_survivors(A, A.G, Q);
   }
   // this cell's counts, summed by launch_cell_counts (a counter atomic per
@@ -980,6 +975,7 @@ __global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
 __global__ __launch_bounds__(WAVE, 5) void k_detect_half64g(DetectArgs A) {
   __shared__ int2 survq[QCAP];
   __shared__ HomeQ hq[WAVE];
+  __shared__ int2 rt[MAXRUN];
   SurvivorQueue Q{survq, 0, 0u, QCAP, 0ull};
   const int c0 = xcd_remap(blockIdx.x, gridDim.x) * A.cpw;
   const int c1 = c0 + A.cpw < A.G.ncell ? c0 + A.cpw : A.G.ncell;
@@ -988,7 +984,7 @@ __global__ __launch_bounds__(WAVE, 5) void k_detect_half64g(DetectArgs A) {
   for (int cell = c0; cell < c1; ++cell) {  // one flush site (register pressure)
     const int vc = v;
     if (cell + 1 < c1) v = cell_starts(A.G, A.start, cell + 1);
-    detect_cell64(A, A.G, vc, cell, Q, hq);
+    detect_cell64(A, A.G, vc, cell, Q, hq, rt);
     if (cell + 1 == c1 || Q.n >= WAVE) flush_survivors(A, A.G, Q);
   }
   if (__lane_id() == 0) A.cellc[blockIdx.x] = CellCount{Q.tests, 0ull};
@@ -1026,6 +1022,7 @@ __global__ __launch_bounds__(WAVE) void k_detect_batched(DetectArgs A, BatchDev 
   if (B.flags[FLAG_ERR]) return;
   __shared__ int2 survq[QCAP];
   __shared__ HomeQ hq[WAVE];
+  __shared__ int2 rt[MAXRUN];
   SurvivorQueue Q{survq, 0, 0u, QCAP, 0ull};
   const int total = B.cell_base[B.nbox];
   const int c0 = xcd_remap(blockIdx.x, gridDim.x) * cpw;
@@ -1041,7 +1038,7 @@ __global__ __launch_bounds__(WAVE) void k_detect_batched(DetectArgs A, BatchDev 
     }
     const Grid G = B.gtab[b];
     const int base = B.cell_base[b];
-    detect_cell64(A, G, cell_starts(G, A.start + base, item - base), item - base, Q, hq);
+    detect_cell64(A, G, cell_starts(G, A.start + base, item - base), item - base, Q, hq, rt);
     if (item + 1 == c1 || Q.n >= WAVE) flush_survivors(A, G, Q);
   }
 }
