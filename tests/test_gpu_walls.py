@@ -45,8 +45,6 @@ def test_walls_match_oracle(poly20k, case, walls):
     box = {"config1": lambda: workloads.config(1), "poly20k": lambda: poly20k,
            "poly4097": lambda: box_slice(poly20k, 4097),
            "config2": lambda: workloads.config(2)}[case]()
-    if case == "config2" and walls != (1, 1, 1):
-        pytest.skip("one wall layout at 1M")
     _announce(f"walls {walls} {case} n={box.n}")
     g = gpu_step_walls(box, walls)
     orc = oracle.step_walls(box, walls)
