@@ -622,112 +622,87 @@ __device__ __forceinline__ void detect_chunk32(const DetectArgs &A, const Grid &
 // cell of the box whose grid is G (cell numbers below are local to that box;
 // sphere positions in start[] are global).
 // Runs of consecutive cell-sorted records that make the half stencil of one
-// home cell: the own cell (pairs with j after i), the next cell along x, and 4
-// rows of 3 cells, a row split in two where it wraps along x; each with its
-// periodic image shift code.  Returns false for an empty home cell.
-struct CellRuns {
-  int rg[MAXRUN], rl[MAXRUN], rc[MAXRUN];
-  int h0, h1, cx, cy, cz;
-  bool any_shift;
-};
+// home cell: run 0 the own cell (pairs with j after i), run 1 the next cell
+// along x, runs 2..9 the 4 rows of 3 cells, each row as two runs (the second
+// empty unless the row wraps along x); each with its periodic image code.
+// Run k's bounds are the starts of two cells, held in lanes 2k and 2k + 1 of
+// the wave, so that one vector load fetches all 20 and the runs are formed
+// lane by lane rather than in scalar code.
 
-// The 20 cell starts the runs of cell_runs need, fetched by one vector load
-// (lane k loads slot k) instead of a chain of dependent scalar loads:
-  //   0, 1   the own cell [h0, h1)
-  //   2, 3   the next cell along x (cell 0 of the row where x wraps)
-//   4 + 4 row + {0, 1, 2, 3}: the row's first run and second run (the
-//          second is empty unless the row wraps along x)
-__device__ __forceinline__ int cell_starts(const Grid &G, const int *start, int cell) {
+// Lane j < 20 of a home cell's stencil: the cell whose start it loads (lane
+// 2k the first cell of run k, lane 2k + 1 the cell one past its last) and run
+// k's image code (run_code).  Lanes from 20 on load nothing.
+__device__ __forceinline__ int cell_starts(const Grid &G, const int *start, int cell, int &code) {
   const int nc0 = G.nc[0], nc1 = G.nc[1], nc2 = G.nc[2];
   int cx, cy, cz;
   cell_xyz(G, cell, cx, cy, cz);
+  // the lane index made opaque per call, so that the lane-constant selections
+  // below are recomputed per cell rather than hoisted out of a cell loop
+  // (held across it they cost registers and, in the grouped kernel, spills)
+  int ln = (int)__lane_id();
+  asm volatile("" : "+v"(ln));
+  const int k = ln >> 1, end = ln & 1;
+  const bool lw = cx - 1 < 0, rw = cx + 1 >= nc0;  // the row wraps left / right
+  // rows (runs 2..9): offsets (dy, dz) = (1, 0), (-1, 1), (0, 1), (1, 1)
+  const int row = (k - 2) >> 1, second = (k - 2) & 1, w = 2 * second + end;
+  int y = cy + (row == 1 ? -1 : (row == 2 ? 0 : 1)), z = cz + (row == 0 ? 0 : 1);
+  const int sy = y >= nc1 ? 1 : (y < 0 ? -1 : 0), sz = z >= nc2 ? 1 : 0;
+  y -= sy * nc1;
+  z -= sz * nc2;
+  // the wrapped left cell then cells 0..1; cells cx-1..cx then the wrapped
+  // right cell 0; or cells cx-1..cx+1 and an empty second run
+  const int o = lw ? (w == 0 ? nc0 - 1 : (w == 1 ? nc0 : (w == 2 ? 0 : 2)))
+                   : (rw ? (w == 0 ? cx - 1 : (w == 1 ? cx + 1 : (w == 2 ? 0 : 1)))
+                         : (w == 0 ? cx - 1 : cx + 2));
+  const int sx_row = lw ? (second ? 0 : -1) : (rw ? second : 0);
+  // run 1: the next cell along x, cell 0 of the own row where x wraps
+  const int idx = k == 0 ? cell + end
+                         : (k == 1 ? (rw ? cell - cx : cell + 1) + end : (z * nc1 + y) * nc0 + o);
+  code = k == 0 ? run_code(0, 0, 0, 1)
+                : (k == 1 ? run_code(rw ? 1 : 0, 0, 0, 0) : run_code(sx_row, sy, sz, 0));
   int v = 0;
-  {
-    // the lane index made opaque per call, so that the lane-constant selections
-    // below are recomputed per cell rather than hoisted out of a cell loop
-    // (held across it they cost registers and, in the grouped kernel, spills)
-    int ln = (int)__lane_id();
-    asm volatile("" : "+v"(ln));
-    int idx = cell;
-    if (ln == 1) {
-      idx = cell + 1;
-    } else if (ln == 2 || ln == 3) {
-      const int own_row = (cz * nc1 + cy) * nc0;
-      idx = cx + 1 >= nc0 ? own_row + (ln - 2) : cell + ln - 1;
-    } else if (ln >= 4 && ln < 20) {
-      const int row = (ln - 4) >> 2, w = (ln - 4) & 3;
-      // row offsets (dy, dz) = (1, 0), (-1, 1), (0, 1), (1, 1), as dys / dzs
-      int y = cy + (row == 1 ? -1 : (row == 2 ? 0 : 1)), z = cz + (row == 0 ? 0 : 1);
-      y = y >= nc1 ? y - nc1 : (y < 0 ? y + nc1 : y);
-      z = z >= nc2 ? z - nc2 : z;
-      const int rb = (z * nc1 + y) * nc0;
-      int o;
-      if (cx - 1 < 0)  // the wrapped left cell, then cells 0..1
-        o = w == 0 ? nc0 - 1 : (w == 1 ? nc0 : (w == 2 ? 0 : 2));
-      else if (cx + 1 >= nc0)  // cells cx-1..cx, then the wrapped right cell 0
-        o = w == 0 ? cx - 1 : (w == 1 ? cx + 1 : (w == 2 ? 0 : 1));
-      else  // cells cx-1..cx+1; empty second run
-        o = w == 0 ? cx - 1 : cx + 2;
-      idx = rb + o;
-    }
-    if (ln < 20) v = start[idx];
-  }
+  if (ln < 20) v = start[idx];
   return v;
 }
 
-// The runs of cell `cell` from its 20 starts v (cell_starts).
-__device__ __forceinline__ bool cell_runs_from(const Grid &G, int cell, int v, CellRuns &R) {
-  const int nc0 = G.nc[0], nc1 = G.nc[1], nc2 = G.nc[2];
-  int cx, cy, cz;
-  cell_xyz(G, cell, cx, cy, cz);
-  const int dys[4] = {1, -1, 0, 1}, dzs[4] = {0, 1, 1, 1};
-  const int h0 = __builtin_amdgcn_readlane(v, 0), h1 = __builtin_amdgcn_readlane(v, 1);
-  R.h0 = h0;
-  R.h1 = h1;
-  R.cx = cx;
-  R.cy = cy;
-  R.cz = cz;
-  if (h1 <= h0) return false;
-  // runs of consecutive sorted records: global start, length, shift code
-  int *rg = R.rg, *rl = R.rl, *rc = R.rc;
-  bool any_shift = false;
-  // own cell first (pairs with j after i), then the next cell along x
-  rg[0] = h0;
-  rl[0] = h1 - h0;
-  rc[0] = run_code(0, 0, 0, 1);
-  rg[1] = __builtin_amdgcn_readlane(v, 2);
-  rl[1] = __builtin_amdgcn_readlane(v, 3) - rg[1];
-  rc[1] = run_code(cx + 1 >= nc0 ? 1 : 0, 0, 0, 0);
-  if (cx + 1 >= nc0) any_shift = true;
-#pragma unroll
-  for (int row = 0; row < 4; ++row) {
-    const int y = cy + dys[row], z = cz + dzs[row];
-    const int sy = y >= nc1 ? 1 : (y < 0 ? -1 : 0), sz = z >= nc2 ? 1 : 0;
-    const int k0 = 2 + 2 * row, k1 = 3 + 2 * row;
-    rg[k0] = __builtin_amdgcn_readlane(v, 4 + 4 * row);
-    rl[k0] = __builtin_amdgcn_readlane(v, 5 + 4 * row) - rg[k0];
-    rg[k1] = __builtin_amdgcn_readlane(v, 6 + 4 * row);
-    rl[k1] = __builtin_amdgcn_readlane(v, 7 + 4 * row) - rg[k1];
-    if (cx - 1 < 0) {
-      rc[k0] = run_code(-1, sy, sz, 0);
-      rc[k1] = run_code(0, sy, sz, 0);
-      any_shift = true;
-    } else if (cx + 1 >= nc0) {
-      rc[k0] = run_code(0, sy, sz, 0);
-      rc[k1] = run_code(1, sy, sz, 0);
-      any_shift = true;
-    } else {
-      rc[k0] = run_code(0, sy, sz, 0);
-      rc[k1] = run_code(0, sy, sz, 0);
-    }
-    if (sy != 0 || sz != 0) any_shift = true;
-  }
-  R.any_shift = any_shift;
-  return true;
-}
+// A home cell's runs as the candidate search needs them: its spheres [h0, h1),
+// the candidate list length, and the first list slot of each run (pre[0] = 0;
+// an empty run starts where the next does).
+struct CellSet {
+  int h0, h1, total;
+  int pre[MAXRUN];
+};
 
-__device__ __forceinline__ bool cell_runs(const Grid &G, const int *start, int cell, CellRuns &R) {
-  return cell_runs_from(G, cell, cell_starts(G, start, cell), R);
+// The runs of a home cell from its lanes' starts v and codes (cell_starts):
+// run lengths and their prefix sums formed across lanes 0..19 (DPP shifts
+// within rows of 16 lanes, then the carry of the first row), and the run table
+// rt (the wave's own room in LDS; its LDS operations stay in order) written by
+// lanes 2k: run k's offset from list slot to sorted index and its code.
+// Returns false for an empty home cell.
+__device__ __forceinline__ bool cell_setup(int v, int code, int2 *rt, CellSet &S) {
+  const int h0 = __builtin_amdgcn_readlane(v, 0), h1 = __builtin_amdgcn_readlane(v, 1);
+  S.h0 = h0;
+  S.h1 = h1;
+  if (h1 <= h0) return false;
+  const int ln = (int)__lane_id();
+  const bool first = ln < 20 && (ln & 1) == 0;
+  // lane 2k + 1's start beside lane 2k's (row_shl:1; a pair never straddles a row)
+  const int vn = __builtin_amdgcn_update_dpp(0, v, 0x101, 0xf, 0xf, true);
+  const int rl = first ? vn - v : 0;
+  int inc = rl;
+  inc += __builtin_amdgcn_update_dpp(0, inc, 0x111, 0xf, 0xf, true);  // row_shr:1
+  inc += __builtin_amdgcn_update_dpp(0, inc, 0x112, 0xf, 0xf, true);  // row_shr:2
+  inc += __builtin_amdgcn_update_dpp(0, inc, 0x114, 0xf, 0xf, true);  // row_shr:4
+  inc += __builtin_amdgcn_update_dpp(0, inc, 0x118, 0xf, 0xf, true);  // row_shr:8
+  const int carry = __builtin_amdgcn_readlane(inc, 15);
+  if (ln >= 16) inc += carry;
+  const int excl = inc - rl;
+  if (first) rt[ln >> 1] = make_int2(v - excl, code);
+  S.total = __builtin_amdgcn_readlane(inc, 19);
+  S.pre[0] = 0;
+#pragma unroll
+  for (int k = 1; k < MAXRUN; ++k) S.pre[k] = __builtin_amdgcn_readlane(excl, 2 * k);
+  return true;
 }
 
 
@@ -741,26 +716,19 @@ constexpr int HB32 = WAVE;
 // in LDS for the cell's run table (MAXRUN entries).
 __device__ __forceinline__ void detect_cell32(const DetectArgs &A, const Grid &G, const int *start,
                                               int cell, SurvivorQueue &Q, Rec32 *hl, int2 *rt) {
-  CellRuns R;
-  if (!cell_runs(G, start, cell, R)) return;
-  const int h0 = R.h0, h1 = R.h1;
-  const int *rl = R.rl;
-  int total = 0;
-  int pre[MAXRUN];
-#pragma unroll
-  for (int k = 0; k < MAXRUN; ++k) {
-    pre[k] = total;
-    total += rl[k];
-  }
+  int code;
+  const int vs = cell_starts(G, start, cell, code);
+  CellSet S;
+  if (!cell_setup(vs, code, rt, S)) return;
+  const int h0 = S.h0, h1 = S.h1, total = S.total;
+  const int *pre = S.pre;
   const int lane = __lane_id();
-  if (lane == 0) {  // the run table, as in detect_cell64
-#pragma unroll
-    for (int k = 0; k < MAXRUN; ++k) rt[k] = make_int2(R.rg[k] - pre[k], R.rc[k]);
-  }
   // unordered pairs this cell tests: own cell pairs once, every home against the rest
   Q.tests += (unsigned long long)(h1 - h0) * (unsigned long long)(total - (h1 - h0)) +
              (unsigned long long)(h1 - h0) * (unsigned long long)(h1 - h0 - 1) / 2ull;
-  const double ox = (R.cx + 0.5) * G.h[0], oy = (R.cy + 0.5) * G.h[1], oz = (R.cz + 0.5) * G.h[2];
+  int cx, cy, cz;
+  cell_xyz(G, cell, cx, cy, cz);
+  const double ox = (cx + 0.5) * G.h[0], oy = (cy + 0.5) * G.h[1], oz = (cz + 0.5) * G.h[2];
   for (int hb = h0; hb < h1; hb += HB32) {
     const int he = hb + HB32 < h1 ? hb + HB32 : h1;
     if (hb + lane < he) {
@@ -787,7 +755,7 @@ __device__ __forceinline__ void detect_cell32(const DetectArgs &A, const Grid &G
       const bool ok = v < total;
       const bool own = (code >> 6) & 1;
       const int thr = !ok ? -1 : (own ? g : 0x7fffffff);
-      if (base < rl[0])
+      if (base < h1 - h0)
         detect_chunk32<true>(A, G, (const Rec32 *)hl, hb, he, g, thr, code, ox, oy, oz, Q);
       else
         detect_chunk32<false>(A, G, (const Rec32 *)hl, hb, he, g, thr, code, ox, oy, oz, Q);
@@ -858,31 +826,23 @@ __device__ __forceinline__ void detect_chunk64(const DetectArgs &A, const Grid &
 
 // Pair tests of one home cell with the binary64 Gram filter; homes in batches
 // of 64 (hq holds one batch), candidates in chunks of 64 lanes.
-// v: the cell's 20 starts (cell_starts), loaded ahead by the caller; rt: the
-// wave's room in LDS for the cell's run table (MAXRUN entries).
-__device__ __forceinline__ void detect_cell64(const DetectArgs &A, const Grid &G, int v,
-                                              int cell, SurvivorQueue &Q, HomeQ *hq, int2 *rt) {
-  CellRuns R;
-  if (!cell_runs_from(G, cell, v, R)) return;
-  const int h0 = R.h0, h1 = R.h1, nh = h1 - h0;
-  int total = 0;
-  int pre[MAXRUN];
-#pragma unroll
-  for (int k = 0; k < MAXRUN; ++k) {
-    pre[k] = total;
-    total += R.rl[k];
-  }
+// vs, code: the cell's 20 starts and run codes (cell_starts), loaded ahead by
+// the caller; rt: the wave's room in LDS for the cell's run table (MAXRUN
+// entries).
+__device__ __forceinline__ void detect_cell64(const DetectArgs &A, const Grid &G, int vs,
+                                              int code, int cell, SurvivorQueue &Q, HomeQ *hq,
+                                              int2 *rt) {
+  CellSet S;
+  if (!cell_setup(vs, code, rt, S)) return;
+  const int h0 = S.h0, h1 = S.h1, nh = h1 - h0, total = S.total;
+  const int *pre = S.pre;
   Q.tests += (unsigned long long)nh * (unsigned long long)(total - nh) +
              (unsigned long long)nh * (unsigned long long)(nh - 1) / 2ull;
   const int lane = __lane_id();
-  const double ox = (R.cx + 0.5) * G.h[0], oy = (R.cy + 0.5) * G.h[1], oz = (R.cz + 0.5) * G.h[2];
+  int cx, cy, cz;
+  cell_xyz(G, cell, cx, cy, cz);
+  const double ox = (cx + 0.5) * G.h[0], oy = (cy + 0.5) * G.h[1], oz = (cz + 0.5) * G.h[2];
   const double dt2 = A.dt2;
-  // the run table in LDS (the wave's own; its LDS operations stay in order):
-  // run k's offset from list slot to sorted index (rg[k] - pre[k]) and its code
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < MAXRUN; ++k) rt[k] = make_int2(R.rg[k] - pre[k], R.rc[k]);
-  }
   for (int hb = 0; hb < nh; hb += WAVE) {
     const int nb = nh - hb < WAVE ? nh - hb : WAVE;
     if (lane < nb) {  // this batch's home terms (one wave owns hq: in-order LDS)
@@ -932,7 +892,7 @@ __device__ __forceinline__ void detect_cell64(const DetectArgs &A, const Grid &G
                b.r * b.r;
       }
       // own-cell candidates (the first rl[0] of the list): only j after i
-      if (base < R.rl[0])
+      if (base < nh)
         detect_chunk64<true>(A, G, hq, nb, h0 + hb, g, thr, P, beta, Q);
       else
         detect_chunk64<false>(A, G, hq, nb, h0 + hb, g, thr, P, beta, Q);
@@ -959,7 +919,9 @@ __global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
     __shared__ HomeQ hq[WAVE];
     __shared__ int2 rt[MAXRUN];
     const int cell = xcd_remap(blockIdx.x, gridDim.x);
-    detect_cell64(A, A.G, cell_starts(A.G, A.start, cell), cell, Q, hq, rt);
+    int code;
+    const int vs = cell_starts(A.G, A.start, cell, code);
+    detect_cell64(A, A.G, vs, code, cell, Q, hq, rt);
     flush_survivors(A, A.G, Q);
   }
   // this cell's counts, summed by launch_cell_counts (a counter atomic per
@@ -980,11 +942,13 @@ __global__ __launch_bounds__(WAVE, 5) void k_detect_half64g(DetectArgs A) {
   const int c0 = xcd_remap(blockIdx.x, gridDim.x) * A.cpw;
   const int c1 = c0 + A.cpw < A.G.ncell ? c0 + A.cpw : A.G.ncell;
   // the next cell's starts are loaded while this cell is tested
-  int v = c0 < c1 ? cell_starts(A.G, A.start, c0) : 0;
+  int code = 0;
+  int v = c0 < c1 ? cell_starts(A.G, A.start, c0, code) : 0;
   for (int cell = c0; cell < c1; ++cell) {  // one flush site (register pressure)
     const int vc = v;
-    if (cell + 1 < c1) v = cell_starts(A.G, A.start, cell + 1);
-    detect_cell64(A, A.G, vc, cell, Q, hq, rt);
+    const int cc = code;
+    if (cell + 1 < c1) v = cell_starts(A.G, A.start, cell + 1, code);
+    detect_cell64(A, A.G, vc, cc, cell, Q, hq, rt);
     if (cell + 1 == c1 || Q.n >= WAVE) flush_survivors(A, A.G, Q);
   }
   if (__lane_id() == 0) A.cellc[blockIdx.x] = CellCount{Q.tests, 0ull};
@@ -1038,7 +1002,9 @@ __global__ __launch_bounds__(WAVE) void k_detect_batched(DetectArgs A, BatchDev 
     }
     const Grid G = B.gtab[b];
     const int base = B.cell_base[b];
-    detect_cell64(A, G, cell_starts(G, A.start + base, item - base), item - base, Q, hq, rt);
+    int code;
+    const int vs = cell_starts(G, A.start + base, item - base, code);
+    detect_cell64(A, G, vs, code, item - base, Q, hq, rt);
     if (item + 1 == c1 || Q.n >= WAVE) flush_survivors(A, G, Q);
   }
 }
