@@ -644,22 +644,27 @@ __device__ __forceinline__ int cell_starts(const Grid &G, const int *start, int 
   const int k = ln >> 1, end = ln & 1;
   const bool lw = cx - 1 < 0, rw = cx + 1 >= nc0;  // the row wraps left / right
   // rows (runs 2..9): offsets (dy, dz) = (1, 0), (-1, 1), (0, 1), (1, 1)
-  const int row = (k - 2) >> 1, second = (k - 2) & 1, w = 2 * second + end;
+  const int row = (k - 2) >> 1, second = (k - 2) & 1;
   int y = cy + (row == 1 ? -1 : (row == 2 ? 0 : 1)), z = cz + (row == 0 ? 0 : 1);
   const int sy = y >= nc1 ? 1 : (y < 0 ? -1 : 0), sz = z >= nc2 ? 1 : 0;
   y -= sy * nc1;
   z -= sz * nc2;
-  // the wrapped left cell then cells 0..1; cells cx-1..cx then the wrapped
-  // right cell 0; or cells cx-1..cx+1 and an empty second run
-  const int o = lw ? (w == 0 ? nc0 - 1 : (w == 1 ? nc0 : (w == 2 ? 0 : 2)))
-                   : (rw ? (w == 0 ? cx - 1 : (w == 1 ? cx + 1 : (w == 2 ? 0 : 1)))
-                         : (w == 0 ? cx - 1 : cx + 2));
-  const int sx_row = lw ? (second ? 0 : -1) : (rw ? second : 0);
+  // a row's two runs, as cells [a0, a1) and [a2, a3) of the row: the wrapped
+  // left cell then cells 0..1; cells cx-1..cx then the wrapped right cell 0;
+  // or cells cx-1..cx+1 and an empty second run.  The four bounds are uniform
+  // and each lane selects one (simple selects, no divergent branches).
+  const int a0 = lw ? nc0 - 1 : cx - 1, a1 = lw ? nc0 : (rw ? cx + 1 : cx + 2);
+  const int a2 = lw || rw ? 0 : cx + 2, a3 = lw ? 2 : (rw ? 1 : cx + 2);
+  const int o01 = end ? a1 : a0, o23 = end ? a3 : a2;
+  const int o = second ? o23 : o01;
+  // image along x of a row's first / second run
+  const int sx0 = lw ? -1 : 0, sx1 = !lw && rw ? 1 : 0;
+  const int sx_row = second ? sx1 : sx0;
   // run 1: the next cell along x, cell 0 of the own row where x wraps
-  const int idx = k == 0 ? cell + end
-                         : (k == 1 ? (rw ? cell - cx : cell + 1) + end : (z * nc1 + y) * nc0 + o);
-  code = k == 0 ? run_code(0, 0, 0, 1)
-                : (k == 1 ? run_code(rw ? 1 : 0, 0, 0, 0) : run_code(sx_row, sy, sz, 0));
+  const int c01 = k == 0 ? cell : (rw ? cell - cx : cell + 1);
+  const int idx = k < 2 ? c01 + end : (z * nc1 + y) * nc0 + o;
+  const int code01 = k == 0 ? run_code(0, 0, 0, 1) : run_code(rw ? 1 : 0, 0, 0, 0);
+  code = k < 2 ? code01 : run_code(sx_row, sy, sz, 0);
   int v = 0;
   if (ln < 20) v = start[idx];
   return v;
