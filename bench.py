@@ -39,11 +39,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "pair tests/s + particles stepped/s at 16M; FP32+recheck vs FP64 at equal pair set"
 # FP64 vector operations of one pair test in the detect kernel's filter, the
-# Gram form F = alpha_i + beta_j + <P_j, Q_i>: one add and seven FMAs (the
-# compare excluded; per-sphere terms are formed once per sphere, not per
-# pair).  An FMA is one operation here (two flops): 8 operations, 15 flops.
-OPS_PER_PAIR_TEST = 8
-FLOPS_PER_PAIR_TEST = 15
+# Gram form alpha_i + <P_j, Q_i> <= tol - beta_j: seven FMAs from alpha_i (the
+# compare excluded; per-sphere terms and the candidate's threshold are formed
+# once per sphere or chunk, not per pair).  An FMA is one operation here (two
+# flops): 7 operations, 14 flops.
+OPS_PER_PAIR_TEST = 7
+FLOPS_PER_PAIR_TEST = 14
 # 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz: binary64 vector operations per
 # second (an FMA is one; the published 78.6 TFLOP/s counts it as two flops)
 PEAK_FP64_OPS = 256 * 4 * 16 * 2.4e9

@@ -670,18 +670,21 @@ static double fp32_band(const pcol_ctx *ctx, double dt) {  // returns the band
 }
 
 // Tolerance of the binary64 Gram filter (filter 0).  The filter evaluates
-// F = alpha_i + beta_j + <P_j, Q_i> from coordinates relative to the home cell
-// centre.  For a pair the rule keeps, the real F is at most E0 = 3 eps
-// ((reach^2 + (2 r_max)^2) + reach 2 v_max dt2) (the binary64 argument: the kept
-// root c / (-b + sqrt D) <= dt gives c <= 2 |b| dt (1 + 6 eps) < |b| dt2).  The
-// evaluation differs from the real F by
+// G = alpha_i + <P_j, Q_i> (seven FMAs from alpha_i) from coordinates relative
+// to the home cell centre and passes the pair when G <= fl(tol - beta_j); in
+// real numbers that is F = G + beta_j <= tol.  For a pair the rule keeps, the
+// real F is at most E0 = 3 eps ((reach^2 + (2 r_max)^2) + reach 2 v_max dt2)
+// (the binary64 argument: the kept root c / (-b + sqrt D) <= dt gives
+// c <= 2 |b| dt (1 + 6 eps) < |b| dt2).  The evaluation differs from the real F by
 //  * the relative coordinates: each is one or two roundings of values below
 //    L + h, so the separation d is off by at most delta = eps (2 (Lmax + h) + X_i +
 //    X_j), which moves F by at most delta (2 reach + 2 v_max dt2) + delta^2;
-//  * alpha, beta, Q, P (a few roundings each, <= 6 eps relative) and the eight
-//    operations of the sum (<= 8 eps of the sum of magnitudes): at most
+//  * alpha, beta, Q, P (a few roundings each, <= 6 eps relative) and the seven
+//    FMAs of the sum (<= 7 eps of the sum of magnitudes): at most
 //    16 eps (A_ + B_ + S) with A_, B_, S the bounds of |alpha|, |beta| and
-//    sum_k |P_k Q_k| for |x_i| <= X_i = (sqrt 3 / 2) h, |x_j| <= X_i + reach.
+//    sum_k |P_k Q_k| for |x_i| <= X_i = (sqrt 3 / 2) h, |x_j| <= X_i + reach;
+//  * the threshold's one rounding, at most eps (tol + |beta|): the eps tol part
+//    is covered by the factor two below, the eps B_ part by a 17th eps.
 // The tolerance is twice the sum.
 static double gram64_tolerance(double h, double R, double V, double r, double Lmax,
                                double dt2) {
@@ -692,7 +695,7 @@ static double gram64_tolerance(double h, double R, double V, double r, double Lm
   const double E0 = 3.0 * eps * ((R * R + 4.0 * r * r) + R * 2.0 * V * dt2);
   const double delta = eps * (2.0 * (Lmax + h) + Xi + Xj);
   const double Epos = delta * (2.0 * R + 2.0 * V * dt2) + delta * delta;
-  const double E = 16.0 * eps * (Ab + Bb + S);
+  const double E = 17.0 * eps * (Ab + Bb + S);
   return 2.0 * (E0 + Epos + E);
 }
 

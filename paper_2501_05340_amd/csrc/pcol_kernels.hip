@@ -777,12 +777,14 @@ __device__ __forceinline__ void detect_cell32(const DetectArgs &A, const Grid &G
 //   P_j = (x_j, v_j, r_j),  Q_i = (-2 x_i - dt2 v_i, -dt2 x_i, -2 r_i),
 //   alpha_i = |x_i|^2 + dt2 x_i.v_i - r_i^2,  beta_j = |x_j|^2 + dt2 x_j.v_j - r_j^2
 // (d = x_j - x_i, u = v_j - v_i, s = r_i + r_j).  Q_i and alpha_i are formed once
-// per home sphere into LDS, P_j and beta_j once per candidate and chunk (the
-// run's periodic shift applied), so a pair costs one add and seven FMAs.  A
-// pair passes iff F <= tol64, a bound on the rounding of this evaluation and of
-// the relative coordinates for pairs the rule can keep (host, gram64_tolerance);
-// survivors are decided by the rule (flush_survivors), so the result is exactly
-// the rule's.
+// per home sphere into LDS, P_j and the candidate's threshold tol64 - beta_j
+// once per candidate and chunk (the run's periodic shift applied), so a pair
+// costs seven FMAs (alpha_i + <P_j, Q_i>, alpha_i the first addend) and one
+// compare.  A pair passes iff alpha_i + <P_j, Q_i> <= tol64 - beta_j as
+// evaluated, tol64 a bound on the rounding of this evaluation, of the
+// threshold and of the relative coordinates for pairs the rule can keep (host,
+// gram64_tolerance); survivors are decided by the rule (flush_survivors), so
+// the result is exactly the rule's.
 struct alignas(16) HomeQ {
   double q[7];
   double alpha;
@@ -793,19 +795,19 @@ struct alignas(16) HomeQ {
 template <bool MASK>
 __device__ __forceinline__ void detect_chunk64(const DetectArgs &A, const Grid &G, const HomeQ *hq,
                                                int nb, int i0, int g, int thr, const double P[7],
-                                               double beta, SurvivorQueue &Q) {
+                                               double fthr, SurvivorQueue &Q) {
   int k = 0;
   for (; k + 1 < nb; k += 2) {
     const HomeQ a = hq[k], b = hq[k + 1];
-    double t0 = a.alpha + beta, t1 = b.alpha + beta;
+    double t0 = a.alpha, t1 = b.alpha;
 #pragma unroll
     for (int c = 0; c < 7; ++c) {
       t0 = __builtin_fma(P[c], a.q[c], t0);
       t1 = __builtin_fma(P[c], b.q[c], t1);
     }
     const int i = i0 + k;
-    const bool p0 = t0 <= A.tol64 && (!MASK || i < thr);
-    const bool p1 = t1 <= A.tol64 && (!MASK || i + 1 < thr);
+    const bool p0 = t0 <= fthr && (!MASK || i < thr);
+    const bool p1 = t1 <= fthr && (!MASK || i + 1 < thr);
     if (!push_survivor(p0, i, g, Q) && p0) {
       double t;
       if (pair_time(A.rec[i], A.rec[g], G, A.dt, t)) record_contact(A, i, g, t);
@@ -817,11 +819,11 @@ __device__ __forceinline__ void detect_chunk64(const DetectArgs &A, const Grid &
   }
   if (k < nb) {
     const HomeQ a = hq[k];
-    double t0 = a.alpha + beta;
+    double t0 = a.alpha;
 #pragma unroll
     for (int c = 0; c < 7; ++c) t0 = __builtin_fma(P[c], a.q[c], t0);
     const int i = i0 + k;
-    const bool p0 = t0 <= A.tol64 && (!MASK || i < thr);
+    const bool p0 = t0 <= fthr && (!MASK || i < thr);
     if (!push_survivor(p0, i, g, Q) && p0) {
       double t;
       if (pair_time(A.rec[i], A.rec[g], G, A.dt, t)) record_contact(A, i, g, t);
@@ -880,7 +882,7 @@ __device__ __forceinline__ void detect_cell64(const DetectArgs &A, const Grid &G
       const bool own = (code >> 6) & 1;
       const int thr = !ok ? -1 : (own ? g : 0x7fffffff);
       double P[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-      double beta = 1e300;  // no candidate: never passes
+      double beta = 1e300;  // no candidate: its threshold -1e300 is never met
       if (thr >= 0) {
         const Rec b = A.rec[g];
         const double xj = (b.x + code_shift(code & 3, G.sL[0])) - ox;
@@ -898,9 +900,9 @@ __device__ __forceinline__ void detect_cell64(const DetectArgs &A, const Grid &G
       }
       // own-cell candidates (the first rl[0] of the list): only j after i
       if (base < nh)
-        detect_chunk64<true>(A, G, hq, nb, h0 + hb, g, thr, P, beta, Q);
+        detect_chunk64<true>(A, G, hq, nb, h0 + hb, g, thr, P, A.tol64 - beta, Q);
       else
-        detect_chunk64<false>(A, G, hq, nb, h0 + hb, g, thr, P, beta, Q);
+        detect_chunk64<false>(A, G, hq, nb, h0 + hb, g, thr, P, A.tol64 - beta, Q);
     }
   }
   // the survivors left in Q are the caller's to decide (flush_survivors), now
