@@ -478,6 +478,14 @@ __device__ __forceinline__ int run_code(int sx, int sy, int sz, int own) {
 // and one multiply instead of a chain of selects).
 __device__ __forceinline__ double code_shift(int c, double L) { return (double)(c - 1) * L; }
 
+// One run of a home cell's candidate list in the wave's table in LDS: the
+// offset from list slot to sorted index, the image code (run_code; bit 6 the
+// own cell) and the image shift per axis, (c - 1) L (exact).
+struct alignas(16) RunT {
+  int off, code;
+  double sx, sy, sz;
+};
+
 // Candidate slots past the end of the list hold this far-away sphere: its
 // separation squares to +inf and b stays finite, so it never passes the reject.
 constexpr double FAR_AWAY = 1e300;
@@ -584,15 +592,15 @@ __device__ __forceinline__ bool pass32(const DetectArgs &A, int thr, float bx, f
 // One candidate chunk against the homes [h0, h1) staged in LDS at p.
 template <bool MASK>
 __device__ __forceinline__ void detect_chunk32(const DetectArgs &A, const Grid &G, const Rec32 *p, int h0,
-                                               int h1, int g, int thr, int code, double ox,
+                                               int h1, int g, int thr, const RunT &run, double ox,
                                                double oy, double oz, SurvivorQueue &Q) {
   float bx, by, bz, bvx, bvy, bvz, br;
   if (thr >= 0) {
     const Rec b = A.rec[g];
     // candidate relative to the home cell centre (ox, oy, oz), image shift applied
-    bx = (float)((b.x + code_shift(code & 3, G.sL[0])) - ox);
-    by = (float)((b.y + code_shift((code >> 2) & 3, G.sL[1])) - oy);
-    bz = (float)((b.z + code_shift((code >> 4) & 3, G.sL[2])) - oz);
+    bx = (float)((b.x + run.sx) - ox);
+    by = (float)((b.y + run.sy) - oy);
+    bz = (float)((b.z + run.sz) - oz);
     bvx = (float)b.vx;
     bvy = (float)b.vy;
     bvz = (float)b.vz;
@@ -682,14 +690,17 @@ struct CellSet {
 // run lengths and their prefix sums formed across lanes 0..19 (DPP shifts
 // within rows of 16 lanes, then the carry of the first row), and the run table
 // rt (the wave's own room in LDS; its LDS operations stay in order) written by
-// lanes 2k: run k's offset from list slot to sorted index and its code.
-// Returns false for an empty home cell.
-__device__ __forceinline__ bool cell_setup(int v, int code, int2 *rt, CellSet &S) {
+// lanes 2k: run k's offset from list slot to sorted index, its code and its
+// image shift on the grid G.  Returns false for an empty home cell.
+__device__ __forceinline__ bool cell_setup(const Grid &G, int v, int code, RunT *rt, CellSet &S) {
   const int h0 = __builtin_amdgcn_readlane(v, 0), h1 = __builtin_amdgcn_readlane(v, 1);
   S.h0 = h0;
   S.h1 = h1;
   if (h1 <= h0) return false;
-  const int ln = (int)__lane_id();
+  // the lane index opaque, so that the table addresses are formed here per
+  // cell and not held across the cell loop (registers)
+  int ln = (int)__lane_id();
+  asm volatile("" : "+v"(ln));
   const bool first = ln < 20 && (ln & 1) == 0;
   // lane 2k + 1's start beside lane 2k's (row_shl:1; a pair never straddles a row)
   const int vn = __builtin_amdgcn_update_dpp(0, v, 0x101, 0xf, 0xf, true);
@@ -702,7 +713,9 @@ __device__ __forceinline__ bool cell_setup(int v, int code, int2 *rt, CellSet &S
   const int carry = __builtin_amdgcn_readlane(inc, 15);
   if (ln >= 16) inc += carry;
   const int excl = inc - rl;
-  if (first) rt[ln >> 1] = make_int2(v - excl, code);
+  if (first)
+    rt[ln >> 1] = RunT{v - excl, code, code_shift(code & 3, G.sL[0]),
+                       code_shift((code >> 2) & 3, G.sL[1]), code_shift((code >> 4) & 3, G.sL[2])};
   S.total = __builtin_amdgcn_readlane(inc, 19);
   S.pre[0] = 0;
 #pragma unroll
@@ -720,11 +733,11 @@ constexpr int HB32 = WAVE;
 // lanes, converted likewise with their run's image shift.  rt: the wave's room
 // in LDS for the cell's run table (MAXRUN entries).
 __device__ __forceinline__ void detect_cell32(const DetectArgs &A, const Grid &G, const int *start,
-                                              int cell, SurvivorQueue &Q, Rec32 *hl, int2 *rt) {
+                                              int cell, SurvivorQueue &Q, Rec32 *hl, RunT *rt) {
   int code;
   const int vs = cell_starts(G, start, cell, code);
   CellSet S;
-  if (!cell_setup(vs, code, rt, S)) return;
+  if (!cell_setup(G, vs, code, rt, S)) return;
   const int h0 = S.h0, h1 = S.h1, total = S.total;
   const int *pre = S.pre;
   const int lane = __lane_id();
@@ -755,15 +768,16 @@ __device__ __forceinline__ void detect_cell32(const DetectArgs &A, const Grid &G
       int r = 0;  // the run of list slot v (see detect_cell64)
 #pragma unroll
       for (int k = 1; k < MAXRUN; ++k) r += v >= pre[k] ? 1 : 0;
-      const int2 run = rt[r];
-      const int g = run.x + v, code = run.y;
+      asm volatile("" : "+v"(r));  // the count apart from the table address
+      const RunT run = rt[r];
+      const int g = run.off + v;
       const bool ok = v < total;
-      const bool own = (code >> 6) & 1;
+      const bool own = (run.code >> 6) & 1;
       const int thr = !ok ? -1 : (own ? g : 0x7fffffff);
       if (base < h1 - h0)
-        detect_chunk32<true>(A, G, (const Rec32 *)hl, hb, he, g, thr, code, ox, oy, oz, Q);
+        detect_chunk32<true>(A, G, (const Rec32 *)hl, hb, he, g, thr, run, ox, oy, oz, Q);
       else
-        detect_chunk32<false>(A, G, (const Rec32 *)hl, hb, he, g, thr, code, ox, oy, oz, Q);
+        detect_chunk32<false>(A, G, (const Rec32 *)hl, hb, he, g, thr, run, ox, oy, oz, Q);
     }
     __syncthreads();  // before the next batch overwrites hl
   }
@@ -838,9 +852,9 @@ __device__ __forceinline__ void detect_chunk64(const DetectArgs &A, const Grid &
 // entries).
 __device__ __forceinline__ void detect_cell64(const DetectArgs &A, const Grid &G, int vs,
                                               int code, int cell, SurvivorQueue &Q, HomeQ *hq,
-                                              int2 *rt) {
+                                              RunT *rt) {
   CellSet S;
-  if (!cell_setup(vs, code, rt, S)) return;
+  if (!cell_setup(G, vs, code, rt, S)) return;
   const int h0 = S.h0, h1 = S.h1, nh = h1 - h0, total = S.total;
   const int *pre = S.pre;
   Q.tests += (unsigned long long)nh * (unsigned long long)(total - nh) +
@@ -876,18 +890,19 @@ __device__ __forceinline__ void detect_cell64(const DetectArgs &A, const Grid &G
       int r = 0;
 #pragma unroll
       for (int k = 1; k < MAXRUN; ++k) r += v >= pre[k] ? 1 : 0;
-      const int2 run = rt[r];
-      const int g = run.x + v, code = run.y;
+      asm volatile("" : "+v"(r));  // the count apart from the table address
+      const RunT run = rt[r];
+      const int g = run.off + v;
       const bool ok = v < total;
-      const bool own = (code >> 6) & 1;
+      const bool own = (run.code >> 6) & 1;
       const int thr = !ok ? -1 : (own ? g : 0x7fffffff);
       double P[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
       double beta = 1e300;  // no candidate: its threshold -1e300 is never met
       if (thr >= 0) {
         const Rec b = A.rec[g];
-        const double xj = (b.x + code_shift(code & 3, G.sL[0])) - ox;
-        const double yj = (b.y + code_shift((code >> 2) & 3, G.sL[1])) - oy;
-        const double zj = (b.z + code_shift((code >> 4) & 3, G.sL[2])) - oz;
+        const double xj = (b.x + run.sx) - ox;
+        const double yj = (b.y + run.sy) - oy;
+        const double zj = (b.z + run.sz) - oz;
         P[0] = xj;
         P[1] = yj;
         P[2] = zj;
@@ -915,7 +930,7 @@ __global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
   SurvivorQueue Q{survq, 0, 0u, QCAP, 0ull};
   if (FP32) {  // A.cpw consecutive cells per workgroup (see k_detect_half64g)
     __shared__ Rec32 hl[HB32];
-    __shared__ int2 rt[MAXRUN];
+    __shared__ RunT rt[MAXRUN];
     const int c0 = xcd_remap(blockIdx.x, gridDim.x) * A.cpw;
     const int c1 = c0 + A.cpw < A.G.ncell ? c0 + A.cpw : A.G.ncell;
     for (int cell = c0; cell < c1; ++cell) {
@@ -924,7 +939,7 @@ __global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
     }
   } else {
     __shared__ HomeQ hq[WAVE];
-    __shared__ int2 rt[MAXRUN];
+    __shared__ RunT rt[MAXRUN];
     const int cell = xcd_remap(blockIdx.x, gridDim.x);
     int code;
     const int vs = cell_starts(A.G, A.start, cell, code);
@@ -944,7 +959,7 @@ __global__ __launch_bounds__(WAVE) void k_detect_half(DetectArgs A) {
 __global__ __launch_bounds__(WAVE, 5) void k_detect_half64g(DetectArgs A) {
   __shared__ int2 survq[QCAP];
   __shared__ HomeQ hq[WAVE];
-  __shared__ int2 rt[MAXRUN];
+  __shared__ RunT rt[MAXRUN];
   SurvivorQueue Q{survq, 0, 0u, QCAP, 0ull};
   const int c0 = xcd_remap(blockIdx.x, gridDim.x) * A.cpw;
   const int c1 = c0 + A.cpw < A.G.ncell ? c0 + A.cpw : A.G.ncell;
@@ -993,7 +1008,7 @@ __global__ __launch_bounds__(WAVE) void k_detect_batched(DetectArgs A, BatchDev 
   if (B.flags[FLAG_ERR]) return;
   __shared__ int2 survq[QCAP];
   __shared__ HomeQ hq[WAVE];
-  __shared__ int2 rt[MAXRUN];
+  __shared__ RunT rt[MAXRUN];
   SurvivorQueue Q{survq, 0, 0u, QCAP, 0ull};
   const int total = B.cell_base[B.nbox];
   const int c0 = xcd_remap(blockIdx.x, gridDim.x) * cpw;
