@@ -89,6 +89,14 @@ struct pcol_ctx {
   double h[3] = {0, 0, 0};
   int maxcell = 0;
   bool small = false;  // some axis has fewer than 3 cells
+  // the last binning's grid, tried first by the next call of the same shape
+  // (sphere count, box, step, walls): its reach pass then bins on it as well
+  bool plan_valid = false;
+  int64_t plan_n = -1;
+  double plan_L[3] = {0, 0, 0}, plan_dt = 0.0;
+  int plan_walls = 0;
+  Grid plan_G{};
+  double plan_rho_c = INFINITY;
   bool detect_timed = false;
   int cpw_used = 0;  // home cells per workgroup of the last sweep-1 detect (0: exact search)
   unsigned long long *crank = nullptr;  // literal order (opts.order = 1): curve rank per sorted sphere
@@ -488,13 +496,34 @@ pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box
     P.wz = ctx->spin->wz;
   }
   hipStream_t s = ctx->stream;
+  // The grid of the last binning is tried first when this call has its shape
+  // (sphere count, box, step, walls): the reach pass then also takes every
+  // sphere's cell and slot on it (a2), and the plan is kept only if the reach
+  // now measured leads to the same grid and split extent; otherwise the counts
+  // are redone on the new grid below.  Either way the grid is the one the
+  // reach of this call determines.
+  const bool tried = ctx->plan_valid && ctx->plan_n == p->n && ctx->plan_dt == dt &&
+                     ctx->plan_walls == ctx->walls && ctx->plan_L[0] == box->len[0] &&
+                     ctx->plan_L[1] == box->len[1] && ctx->plan_L[2] == box->len[2] &&
+                     (int64_t)(ctx->plan_G.layer2 ? 2 * ctx->plan_G.ncell : ctx->plan_G.ncell) +
+                             2 <= ctx->cell_cap;
+  ctx->plan_valid = false;
   // a1: reach and data validity (one read-back); the histogram is accumulated
   // into zeros, the other fields are written by the reduction
   PCOL_HIP(hipMemsetAsync(ctx->reach_d, 0, sizeof(ReachOut), s));
   // the extent histogram only picks the split extent: above 2^20 spheres it
   // samples one sphere in 16 (the quantile of a million samples is as good)
-  PCOL_HIP(launch_reach(s, P, box->len, dt, p->n >= (1 << 20) ? 4 : 0, ctx->reach_d,
-                        ctx->reach_parts, ctx->reach_phist));
+  const int hist_shift = p->n >= (1 << 20) ? 4 : 0;
+  if (tried) {
+    const Grid &T = ctx->plan_G;
+    PCOL_HIP(launch_fill_i32(s, ctx->count, 0, T.layer2 ? 2 * T.ncell : T.ncell));
+    PCOL_HIP(launch_reach(s, P, box->len, dt, hist_shift, ctx->reach_d, ctx->reach_parts,
+                          ctx->reach_phist, &T, ctx->plan_rho_c, ctx->cid, ctx->slot,
+                          ctx->count));
+  } else {
+    PCOL_HIP(launch_reach(s, P, box->len, dt, hist_shift, ctx->reach_d, ctx->reach_parts,
+                          ctx->reach_phist));
+  }
   PCOL_HIP(hipMemcpyAsync(ctx->reach_h, ctx->reach_d, sizeof(ReachOut), hipMemcpyDeviceToHost, s));
   PCOL_HIP(hipStreamSynchronize(s));
   const ReachOut ro = *ctx->reach_h;
@@ -589,9 +618,16 @@ pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box
     if (e != hipSuccess) return fail(ctx, PCOL_E_NOMEM, "cell arrays");
     ctx->cell_cap = cap;
   }
-  // a2-a4: counting sort into cell-sorted records
-  PCOL_HIP(launch_fill_i32(s, ctx->count, 0, cells_all));
-  PCOL_HIP(launch_cell_hist(s, P, G, dt, rho_c, ctx->cid, ctx->slot, ctx->count));
+  // a2-a4: counting sort into cell-sorted records (the counts already taken by
+  // the reach pass when the tried grid is this one)
+  const bool binned_on_plan = tried && ctx->plan_G.nc[0] == G.nc[0] &&
+                              ctx->plan_G.nc[1] == G.nc[1] && ctx->plan_G.nc[2] == G.nc[2] &&
+                              ctx->plan_G.layer2 == G.layer2 &&
+                              (!split || ctx->plan_rho_c == rho_c);
+  if (!binned_on_plan) {
+    PCOL_HIP(launch_fill_i32(s, ctx->count, 0, cells_all));
+    PCOL_HIP(launch_cell_hist(s, P, G, dt, rho_c, ctx->cid, ctx->slot, ctx->count));
+  }
   PCOL_HIP(launch_scan(s, ctx->count, cells_all, ctx->start, ctx->blocksum, ctx->reach_d));
   PCOL_HIP(launch_scatter(s, P, ctx->cid, ctx->slot, ctx->start, ctx->rec, ctx->rank, nullptr));
   if (ctx->opts.order == 1) {
@@ -631,6 +667,13 @@ pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box
   ctx->binned = true;
   ctx->binned_n = p->n;
   ctx->binned_x = p->x;
+  ctx->plan_valid = true;
+  ctx->plan_n = p->n;
+  ctx->plan_dt = dt;
+  ctx->plan_walls = ctx->walls;
+  for (int a = 0; a < 3; ++a) ctx->plan_L[a] = box->len[a];
+  ctx->plan_G = G;
+  ctx->plan_rho_c = rho_c;
   return PCOL_OK;
 }
 

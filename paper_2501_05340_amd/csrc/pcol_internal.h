@@ -427,9 +427,13 @@ hipError_t launch_fill_i32(hipStream_t s, int *p, int v, int64_t n);
 // hist_shift: the extent histogram covers the spheres whose index is a multiple
 // of 2^hist_shift (the maxima and the validity cover all).  parts and phist are
 // scratch of REACH_BLOCKS partial results and REACH_BLOCKS * RHO_BINS counts;
-// out->hist must be zero and out's other fields are overwritten.
+// out->hist must be zero and out's other fields are overwritten.  G given: the
+// pass also bins the spheres on G with split extent rho_c into cid, slot and
+// count (zero on entry), as launch_cell_hist does.
 hipError_t launch_reach(hipStream_t s, const Particles &P, const double L[3], double dt,
-                        int hist_shift, ReachOut *out, ReachPart *parts, unsigned int *phist);
+                        int hist_shift, ReachOut *out, ReachPart *parts, unsigned int *phist,
+                        const Grid *G = nullptr, double rho_c = 0.0, int *cid = nullptr,
+                        int *slot = nullptr, int *count = nullptr);
 hipError_t launch_cell_hist(hipStream_t s, const Particles &P, const Grid &G, double dt,
                             double rho_c, int *cid, int *slot, int *count);
 // the spheres of the second layer, sorted positions [*first_dev, n)

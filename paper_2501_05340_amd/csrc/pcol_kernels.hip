@@ -142,9 +142,16 @@ hipError_t launch_fill_f64(hipStream_t s, double *p, double v, int64_t n) {
 // histograms in LDS and stores its partial results (maxima and its whole
 // histogram) in parts, which k_reach_final reduces: no address takes an atomic
 // from every workgroup.
+// BIN: the same pass also takes each sphere's cell and slot on the grid G with
+// split extent rho_c, exactly as k_cell_hist does (the binning of a step whose
+// grid is planned before its reach is known; the plan is checked against the
+// reach afterwards).  A sphere that fails the checks still gets a cell inside
+// the grid, and the caller discards the pass.
+template <bool BIN>
 __global__ __launch_bounds__(256) void k_reach(Particles P, double L0, double L1, double L2,
                                                double dt, int hist_shift, ReachPart *parts,
-                                               unsigned int *phist) {
+                                               unsigned int *phist, Grid G, double rho_c,
+                                               int *cid, int *slot, int *count) {
   __shared__ unsigned int hist[RHO_BINS];
   for (int k = threadIdx.x; k < RHO_BINS; k += 256) hist[k] = 0u;
   __syncthreads();
@@ -152,8 +159,13 @@ __global__ __launch_bounds__(256) void k_reach(Particles P, double L0, double L1
   unsigned int bad = 0u;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t hmask = ((int64_t)1 << hist_shift) - 1;
-  // four elements per thread per step: their loads are issued together
-  for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i0 < P.n; i0 += 4 * stride) {
+  // four elements per thread per step: their loads are issued together.  The
+  // loop runs while the wave's first element is in range, so that every lane
+  // of a wave takes each step (the binning's run_slot needs the whole wave);
+  // lanes past the end hold no element.
+  const int64_t wbase = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~(WAVE - 1));
+  for (int64_t w0 = wbase; w0 < P.n; w0 += 4 * stride) {
+    const int64_t i0 = w0 + (threadIdx.x & (WAVE - 1));
     double x[4], y[4], z[4], vx[4], vy[4], vz[4], r[4], m[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -196,6 +208,21 @@ __global__ __launch_bounds__(256) void k_reach(Particles P, double L0, double L1
             has = ((i0 + u * stride) & hmask) == 0;
             if (has) bin = rho_bin(ex);  // -1 (no lane's bin) for the others
           }
+        }
+      }
+      if (BIN) {  // the cell and slot (every lane of the wave takes part)
+        int c = -1;
+        if (in) {
+          const int cx = cell_coord(x[u], G.inv_h[0], G.nc[0]);
+          const int cy = cell_coord(y[u], G.inv_h[1], G.nc[1]);
+          const int cz = cell_coord(z[u], G.inv_h[2], G.nc[2]);
+          c = (cz * G.nc[1] + cy) * G.nc[0] + cx;
+          if (G.layer2 && !(extent(r[u], vx[u], vy[u], vz[u], dt) <= rho_c)) c += G.layer2;
+        }
+        const int sl = run_slot(c, count);
+        if (c >= 0) {
+          cid[i0 + u * stride] = c;
+          slot[i0 + u * stride] = sl;
         }
       }
       // histogram: one LDS atomic per distinct bin of the wave (lanes of one
@@ -266,12 +293,17 @@ __global__ __launch_bounds__(256) void k_reach_final(int nblocks, const ReachPar
 }
 
 hipError_t launch_reach(hipStream_t s, const Particles &P, const double L[3], double dt,
-                        int hist_shift, ReachOut *out, ReachPart *parts, unsigned int *phist) {
+                        int hist_shift, ReachOut *out, ReachPart *parts, unsigned int *phist,
+                        const Grid *G, double rho_c, int *cid, int *slot, int *count) {
   int64_t g = (P.n + 255) / 256;
   if (g > REACH_BLOCKS) g = REACH_BLOCKS;
   if (g < 1) g = 1;
-  hipLaunchKernelGGL(k_reach, dim3((int)g), dim3(256), 0, s, P, L[0], L[1], L[2], dt, hist_shift,
-                     parts, phist);
+  if (G)
+    hipLaunchKernelGGL(k_reach<true>, dim3((int)g), dim3(256), 0, s, P, L[0], L[1], L[2], dt,
+                       hist_shift, parts, phist, *G, rho_c, cid, slot, count);
+  else
+    hipLaunchKernelGGL(k_reach<false>, dim3((int)g), dim3(256), 0, s, P, L[0], L[1], L[2], dt,
+                       hist_shift, parts, phist, Grid{}, 0.0, nullptr, nullptr, nullptr);
   hipLaunchKernelGGL(k_reach_final, dim3(RHO_BINS / 256, REACH_FINAL_Y), dim3(256), 0, s, (int)g,
                      parts, phist, out);
   return hipGetLastError();

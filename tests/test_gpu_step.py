@@ -208,6 +208,31 @@ def test_determinism_rerun(cfg2):
     assert np.array_equal(a[1], b[1])
 
 
+def test_grid_of_the_last_call_reused_and_replaced(poly20k):
+    """A context tries the grid of its last binning first (its reach pass then bins on
+    it too) and keeps it only when this call's reach leads to the same grid and split
+    extent: repeated, changed and invalid inputs on one context all give the oracle's
+    step, and the grid follows the reach of each call."""
+    ctx = pc.Context(poly20k.n)
+    fast = poly20k.copy()
+    for f in ("vx", "vy", "vz"):
+        getattr(fast, f)[:] *= 2.0  # a larger reach: another grid
+    bad = poly20k.copy()
+    bad.x[5] = np.nan
+    grids = []
+    for k, b in enumerate([poly20k, poly20k, fast, fast, poly20k]):
+        _announce(f"grid reuse call {k} n={b.n}")
+        gpu = gpu_step(b, ctx)
+        compare_step(b, gpu, oracle.step(b))
+        grids.append((tuple(gpu[3]["nc"]), gpu[3]["rho_c"]))
+        if k == 1:  # an invalid input on the same context fails and leaves no plan behind
+            p = pc.Particles.from_box(bad)
+            with pytest.raises(pc.PcolError) as ei:
+                pc.pcol_step(ctx, p, bad.L, bad.dt, bad.e)
+            assert ei.value.code == pc.PCOL_E_INVALID
+    assert grids[0] == grids[1] == grids[4] and grids[2] == grids[3] and grids[0] != grids[2]
+
+
 def test_error_codes_leave_inputs_unchanged():
     box = workloads.config(1)
     ctx = pc.Context(box.n)
