@@ -700,9 +700,9 @@ def main():
     pairs = statistics.mean(st["n_pairs"] for st in stats)
     med = lambda key: statistics.median(st[key] for st in stats) * 1e-3
     # algorithmic HBM bytes of each phase (what its kernels must move):
-    #  bin: validation and reach read the 64-B state; the cell ids read 56 B and
-    #    write cell and slot (8 B); the scatter reads 56 + 8 B and writes the 64-B
-    #    record and the 4-B sorted position;
+    #  bin: validation, reach and cell ids (one pass on the grid of the last
+    #    step) read the 64-B state and write cell and slot (8 B); the scatter
+    #    reads 56 + 8 B and writes the 64-B record and the 4-B sorted position;
     #  detect: each first-layer record read once (64 B), a contact count per sphere
     #    (4 B), 12 B per contact side in the slots;
     #  sweeps: per collided sphere its record and its partner's (128 B), two masses,
@@ -710,7 +710,7 @@ def main():
     #  advance: the sorted position (4 B), the output record (64 B), the 48-B start
     #    state read; the 48-B state, partner and time (12 B) written.
     n = box.n
-    phase_bytes = {"bin": n * (64 + 64 + 132), "detect": n * 68 + contacts * 2 * 12,
+    phase_bytes = {"bin": n * (72 + 132), "detect": n * 68 + contacts * 2 * 12,
                    "sweeps": 2 * pairs * (128 + 16 + 12 + 64), "advance": n * 176}
     phase_ms = {"bin": med("ms_bin"), "detect": det_med, "sweeps": med("ms_sweeps"),
                 "advance": med("ms_advance")}
