@@ -192,7 +192,10 @@ pcol_status pcol_set_stream(pcol_ctx *ctx, void *hip_stream);
  * reach = 2 max r + 2 max|v| dt and a uniform grid of cell side >= reach *
  * cell_mult per axis, and keeps a cell-sorted copy of the start-of-step state
  * in the context.  Reads only.  Synchronises (reads back the reach and the
- * largest cell). */
+ * largest cell).  A call with the sphere count, box, dt and walls of the
+ * context's last binning counts the spheres into that binning's grid during
+ * the reach pass and keeps those counts when this call's reach gives the same
+ * grid (the grid is always the one this call's reach determines). */
 pcol_status pcol_bin(pcol_ctx *ctx, const pcol_particles *p, const pcol_box *box, double dt);
 
 /* Earliest partner of every active sphere over the active set (rule 1-2),
