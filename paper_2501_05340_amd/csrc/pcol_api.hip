@@ -1385,9 +1385,10 @@ static pcol_status batch_enqueue(pcol_ctx *ctx, hipStream_t s, const Particles &
   PCOL_HIP(launch_fill_u32(s, bp->flags, 0u, 16));
   PCOL_HIP(launch_fill_u32(s, (unsigned int *)bp->totals, 0u, 8));
   PCOL_HIP(launch_fill_u32(s, (unsigned int *)ctx->ctr_d, 0u, sizeof(SweepCounters) / 4));
-  PCOL_HIP(launch_breach(s, P, B, dt, 1));
+  // reach check and cell ids in one pass over the spheres (the counts are
+  // discarded with everything else if the check fails)
   PCOL_HIP(launch_fill_i32(s, ctx->count, 0, ncell));
-  PCOL_HIP(launch_cell_hist_b(s, P, B, ctx->cid, ctx->slot, ctx->count));
+  PCOL_HIP(launch_breach(s, P, B, dt, 1, ctx->cid, ctx->slot, ctx->count));
   PCOL_HIP(launch_scan(s, ctx->count, ncell, ctx->start, ctx->blocksum, ctx->reach_d));
   PCOL_HIP(launch_scatter(s, P, ctx->cid, ctx->slot, ctx->start, ctx->rec, ctx->rank, &B));
   PCOL_HIP(launch_fill_u8(s, ctx->status, ST_ACTIVE, n));
@@ -1701,8 +1702,9 @@ extern "C" pcol_status pcol_step_batched(pcol_ctx *ctx, int32_t nbox, const int6
     }
   } else if (ctx->opts.max_sweeps == 0 && bp->kmax > (int)sweeps + 4) {
     // far more sweep slots than the step used: each empty slot still launches
-    // its kernels (early exits), so capture fewer next time
-    bp->kmax = (int)sweeps + 4;
+    // its kernels (early exits, about 25 us a slot), so capture fewer next time,
+    // keeping room for two more sweeps than this step took
+    bp->kmax = (int)sweeps + 2;
     bp->captured = false;
   }
   if (stats) {

@@ -477,10 +477,12 @@ hipError_t launch_finish(hipStream_t s, const Particles &P, const int *rank, con
                          const uint8_t *status, int *partner, double *tcoll, double dt,
                          const Grid &G, const BatchDev *B);
 hipError_t launch_fill_box_of(hipStream_t s, int nbox, const int64_t *box_off, int *box_of);
+// count given (zero on entry): the pass also takes every sphere's global cell
+// (box's first cell + local cell on its planned grid) and its slot in that cell
+// into cid, slot and count
 hipError_t launch_breach(hipStream_t s, const Particles &P, const BatchDev &B, double dt,
-                         int check_plan);
-hipError_t launch_cell_hist_b(hipStream_t s, const Particles &P, const BatchDev &B, int *cid,
-                              int *slot, int *count);
+                         int check_plan, int *cid = nullptr, int *slot = nullptr,
+                         int *count = nullptr);
 // cpw consecutive global cells per workgroup (one wave) over total_cells
 hipError_t launch_detect_batched(hipStream_t s, const DetectArgs &A, const BatchDev &B,
                                  int total_cells, int cpw);

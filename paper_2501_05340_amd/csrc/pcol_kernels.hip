@@ -2001,7 +2001,14 @@ hipError_t launch_fill_box_of(hipStream_t s, int nbox, const int64_t *box_off, i
 // chunks of at most BREACH_CHUNK spheres, one workgroup each, which merge their
 // maxima into the box's BoxMax; k_breach_fin then takes one box per thread
 // and clears its BoxMax for the next pass.
-__global__ __launch_bounds__(256) void k_breach(Particles P, BatchDev B) {
+// BIN: the same pass also takes each sphere's global cell (the box's first
+// cell + its cell on the box's planned grid) and its slot in that cell, before
+// k_breach_fin has checked the data and the plan: cell coordinates are
+// clamped, so every count stays inside the plan's cells, and a failed check
+// stops every kernel after it.
+template <bool BIN>
+__global__ __launch_bounds__(256) void k_breach(Particles P, BatchDev B, int *cid, int *slot,
+                                                int *count) {
   const int b = B.chunk_box[blockIdx.x];
   const Grid &G = B.gtab[b];
   const int64_t lo = B.chunk_lo[blockIdx.x];
@@ -2021,6 +2028,14 @@ __global__ __launch_bounds__(256) void k_breach(Particles P, BatchDev B) {
     if (fin) {
       v2 = w > v2 ? w : v2;
       rm = r > rm ? r : rm;
+    }
+    if (BIN) {
+      const int cx = cell_coord(x, G.inv_h[0], G.nc[0]);
+      const int cy = cell_coord(y, G.inv_h[1], G.nc[1]);
+      const int cz = cell_coord(z, G.inv_h[2], G.nc[2]);
+      const int c = B.cell_base[b] + (cz * G.nc[1] + cy) * G.nc[0] + cx;
+      cid[i] = c;
+      slot[i] = atomicAdd(&count[c], 1);
     }
   }
   __shared__ double sv[4], sr[4];
@@ -2069,34 +2084,16 @@ __global__ __launch_bounds__(256) void k_breach_fin(BatchDev B, double dt, int c
 }
 
 hipError_t launch_breach(hipStream_t s, const Particles &P, const BatchDev &B, double dt,
-                         int check_plan) {
+                         int check_plan, int *cid, int *slot, int *count) {
   if (B.nbox <= 0) return hipSuccess;
-  if (B.nchunk > 0) hipLaunchKernelGGL(k_breach, dim3(B.nchunk), dim3(256), 0, s, P, B);
+  if (B.nchunk > 0) {
+    if (count)
+      hipLaunchKernelGGL(k_breach<true>, dim3(B.nchunk), dim3(256), 0, s, P, B, cid, slot, count);
+    else
+      hipLaunchKernelGGL(k_breach<false>, dim3(B.nchunk), dim3(256), 0, s, P, B, nullptr, nullptr,
+                         nullptr);
+  }
   hipLaunchKernelGGL(k_breach_fin, dim3((B.nbox + 255) / 256), dim3(256), 0, s, B, dt, check_plan);
-  return hipGetLastError();
-}
-
-// a2 for many boxes: global cell number = the box's first cell + its local cell
-__global__ __launch_bounds__(256) void k_cell_hist_b(Particles P, BatchDev B, int *cid, int *slot,
-                                                     int *count) {
-  if (B.flags[FLAG_ERR]) return;
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= P.n) return;
-  const int b = B.box_of[i];
-  const Grid G = B.gtab[b];
-  const int cx = cell_coord(P.x[i], G.inv_h[0], G.nc[0]);
-  const int cy = cell_coord(P.y[i], G.inv_h[1], G.nc[1]);
-  const int cz = cell_coord(P.z[i], G.inv_h[2], G.nc[2]);
-  const int c = B.cell_base[b] + (cz * G.nc[1] + cy) * G.nc[0] + cx;
-  cid[i] = c;
-  slot[i] = atomicAdd(&count[c], 1);
-}
-
-hipError_t launch_cell_hist_b(hipStream_t s, const Particles &P, const BatchDev &B, int *cid,
-                              int *slot, int *count) {
-  if (P.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cell_hist_b, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, s, P, B,
-                     cid, slot, count);
   return hipGetLastError();
 }
 
