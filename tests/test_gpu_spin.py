@@ -97,6 +97,36 @@ def test_spin_over_many_sweeps(lines):
     assert compare_spin(g, orc) == 0
 
 
+@pytest.mark.parametrize("walls", [None, (1, 1, 1)], ids=["periodic", "walls"])
+def test_spin_steps_in_lockstep_on_one_context(walls, poly20k):
+    """Eight friction steps of the polydisperse box on one context (each call's
+    binning tries the last call's grid), every step against the oracle's step from
+    the oracle's previous state, positions, velocities and spins bitwise."""
+    box, mu = poly20k, 0.4
+    w = _spins(box.n, 11, 1.0 / float(np.min(box.r)))
+    p = pc.Particles.from_box(box)
+    wt = [torch.as_tensor(np.ascontiguousarray(w[k]), dtype=torch.float64).cuda() for k in range(3)]
+    ctx = pc.Context(box.n)
+    partner = torch.empty(box.n, dtype=torch.int32, device="cuda")
+    tcoll = torch.empty(box.n, dtype=torch.float64, device="cuda")
+    b, wo = box, w
+    for k in range(8):
+        _announce(f"spin lockstep {walls} step {k} n={box.n}")
+        if walls is None:
+            st = pc.pcol_step_spin(ctx, p, wt, b.L, b.dt, b.e, mu, partner, tcoll)
+            orc = oracle.step_spin(b, wo, mu)
+        else:
+            st = pc.pcol_step_spin_walls(ctx, p, wt, b.L, walls, b.dt, b.e, mu, partner, tcoll)
+            orc = oracle.step_walls_spin(b, walls, wo, mu)
+        torch.cuda.synchronize()
+        g = (to_host(p), np.array([t.cpu().numpy() for t in wt]),
+             partner.cpu().numpy().astype(np.int64), tcoll.cpu().numpy(), st)
+        assert orc.n_pairs > 0 and st["n_pairs"] == orc.n_pairs
+        assert compare_spin(g, orc) == 0
+        b = workloads.Box(orc.x, orc.y, orc.z, orc.vx, orc.vy, orc.vz, b.r, b.m, b.L, b.dt, b.e)
+        wo = np.array([orc.wx, orc.wy, orc.wz])
+
+
 def test_spin_errors_leave_inputs_unchanged():
     box = workloads.config(1)
     ctx = pc.Context(box.n)

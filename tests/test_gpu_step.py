@@ -11,7 +11,7 @@ import torch
 
 import oracle
 import workloads
-from tests.gpu_helpers import FIELDS, box_slice, compare_step, gpu_step
+from tests.gpu_helpers import FIELDS, box_slice, compare_step, gpu_step, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -231,6 +231,27 @@ def test_grid_of_the_last_call_reused_and_replaced(poly20k):
                 pc.pcol_step(ctx, p, bad.L, bad.dt, bad.e)
             assert ei.value.code == pc.PCOL_E_INVALID
     assert grids[0] == grids[1] == grids[4] and grids[2] == grids[3] and grids[0] != grids[2]
+
+
+@pytest.mark.parametrize("opts", [{"filter": 1}, {"order": 1}], ids=["fp32", "literal"])
+def test_steps_in_lockstep_on_one_context(poly20k, opts):
+    """Six steps of the polydisperse box on one context (each call's binning tries the
+    last call's grid) through the binary32 filter and through the literal order, every
+    step against the oracle's step from the oracle's previous state, bitwise."""
+    ctx = pc.Context(poly20k.n, pc.pcol_default_opts(**opts))
+    p = pc.Particles.from_box(poly20k)
+    partner = torch.empty(poly20k.n, dtype=torch.int32, device="cuda")
+    tcoll = torch.empty(poly20k.n, dtype=torch.float64, device="cuda")
+    b = poly20k
+    for k in range(6):
+        _announce(f"lockstep {opts} step {k} n={b.n}")
+        st = pc.pcol_step(ctx, p, b.L, b.dt, b.e, partner, tcoll)
+        torch.cuda.synchronize()
+        orc = oracle.step_sequential(b) if opts.get("order") else oracle.step(b)
+        gpu = (to_host(p), partner.cpu().numpy().astype(np.int64), tcoll.cpu().numpy(), st)
+        assert orc.n_pairs > 0 and st["n_pairs"] == orc.n_pairs
+        assert compare_step(b, gpu, orc) == 0
+        b = workloads.Box(orc.x, orc.y, orc.z, orc.vx, orc.vy, orc.vz, b.r, b.m, b.L, b.dt, b.e)
 
 
 def test_error_codes_leave_inputs_unchanged():
