@@ -1550,6 +1550,9 @@ hipError_t launch_gather_exact(hipStream_t s, const int *list, int nlist, const 
 // thread writes only its own status, and reads only keys, so the sweep is a
 // pure function of the keys.  Partners are spatial neighbours, so the partner
 // reads stay within a few cells of the sorted order.
+// SPIN: the friction-and-spin resolve (S given); the plain kernel leaves it out
+// and needs half the registers, which the sweeps' random reads repay in waves.
+template <bool SPIN>
 __global__ __launch_bounds__(256) void k_resolve_sweep(int n, const Rec *rec, Grid G0, double dt,
                                                        double e, const double *mass,
                                                        const int *key_j, const double *key_t,
@@ -1568,7 +1571,7 @@ __global__ __launch_bounds__(256) void k_resolve_sweep(int n, const Rec *rec, Gr
       status[i] = ST_FREE;
     } else {
       const int q = key_j[p];
-      if (q == i && S.wx) {
+      if (SPIN && q == i) {
         // with spins, the thread of the smaller sorted index resolves both sides
         // and writes both spins in place (the partner's thread writes nothing,
         // so no thread reads a spin another one has already changed)
@@ -1633,9 +1636,14 @@ hipError_t launch_resolve_sweep(hipStream_t s, int n, const Rec *rec, const Grid
   const int items = list ? nlist : n;
   if (items <= 0) return hipSuccess;
   BatchDev none{};
-  hipLaunchKernelGGL(k_resolve_sweep, dim3((items + 255) / 256), dim3(256), 0, s, n, rec, G, dt,
-                     e, mass, key_j, key_t, status, out, ctr, B ? *B : none, list, nlist,
-                     spin ? *spin : Spin{nullptr, nullptr, nullptr, 0.0});
+  if (spin && spin->wx)
+    hipLaunchKernelGGL(k_resolve_sweep<true>, dim3((items + 255) / 256), dim3(256), 0, s, n, rec,
+                       G, dt, e, mass, key_j, key_t, status, out, ctr, B ? *B : none, list, nlist,
+                       *spin);
+  else
+    hipLaunchKernelGGL(k_resolve_sweep<false>, dim3((items + 255) / 256), dim3(256), 0, s, n, rec,
+                       G, dt, e, mass, key_j, key_t, status, out, ctr, B ? *B : none, list, nlist,
+                       Spin{nullptr, nullptr, nullptr, 0.0});
   return hipGetLastError();
 }
 
